@@ -1,0 +1,190 @@
+"""Seeded synthetic inputs: point clouds on surfaces and random fields.
+
+The paper evaluates RFD on mesh vertex clouds (Thingi10K meshes of a few
+thousand to 1.5M vertices, vertex normals and velocities with d=3, Sec. 3 and
+App. C; distributions with d=1 for the Wasserstein experiments, App. D). Those
+meshes are not available, so these generators stand in for them: points drawn
+area-uniformly on a sphere, a torus, an ellipsoid and a deformed torus, plus
+i.i.d. N(0,1) fields. Everything is drawn with numpy's PCG64 generator from a
+stated seed, in float64, and cast once to float32.
+
+This module holds no arithmetic of the integrator itself. Both the GPU path
+(through the tests and the benchmark) and the CPU oracle read their inputs
+from here.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field as _dc_field
+
+import numpy as np
+
+SURFACES = ("sphere", "torus", "ellipsoid")
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def sphere(n: int, seed: int, radius: float = 1.0) -> np.ndarray:
+    """Uniform on the sphere: normalised N(0, I3) draws."""
+    g = _rng(seed)
+    p = g.standard_normal((n, 3))
+    nrm = np.linalg.norm(p, axis=1, keepdims=True)
+    nrm[nrm == 0] = 1.0
+    return (radius * p / nrm).astype(np.float32)
+
+
+def torus(n: int, seed: int, R: float = 1.0, r: float = 0.3, jitter: float = 0.0,
+          deform: bool = False) -> np.ndarray:
+    """Area-uniform on the torus by rejection on the angle v.
+
+    The area element of the torus is r (R + r cos v) du dv, so (u, v) uniform
+    is accepted with probability (R + r cos v) / (R + r). With ``deform`` the
+    tube radius becomes r (1 + 0.25 sin 3u) and z is lifted by 0.2 sin 2u (the
+    sampling density is that of the undeformed torus). ``jitter`` adds
+    N(0, jitter^2) noise to each coordinate.
+    """
+    g = _rng(seed)
+    out = np.empty((0, 3))
+    while out.shape[0] < n:
+        k = max(2 * (n - out.shape[0]), 1024)
+        u = g.uniform(0.0, 2 * math.pi, k)
+        v = g.uniform(0.0, 2 * math.pi, k)
+        acc = g.uniform(0.0, 1.0, k) < (R + r * np.cos(v)) / (R + r)
+        u, v = u[acc], v[acc]
+        rr = r * (1.0 + 0.25 * np.sin(3 * u)) if deform else r
+        x = (R + rr * np.cos(v)) * np.cos(u)
+        y = (R + rr * np.cos(v)) * np.sin(u)
+        z = rr * np.sin(v) + (0.2 * np.sin(2 * u) if deform else 0.0)
+        out = np.concatenate([out, np.stack([x, y, z], axis=1)])
+    out = out[:n]
+    if jitter > 0:
+        out = out + g.normal(0.0, jitter, out.shape)
+    return out.astype(np.float32)
+
+
+def ellipsoid(n: int, seed: int, axes=(1.0, 0.6, 0.3)) -> np.ndarray:
+    """Area-uniform on the ellipsoid with semi-axes a >= b >= c.
+
+    Points p uniform on the unit sphere map to (a px, b py, c pz); the area
+    stretch of that map is sqrt((bc px)^2 + (ac py)^2 + (ab pz)^2), whose
+    maximum is ab, so p is accepted with probability stretch / (ab).
+    """
+    a, b, c = axes
+    g = _rng(seed)
+    out = np.empty((0, 3))
+    while out.shape[0] < n:
+        k = max(2 * (n - out.shape[0]), 1024)
+        p = g.standard_normal((k, 3))
+        p /= np.linalg.norm(p, axis=1, keepdims=True)
+        stretch = np.sqrt((b * c * p[:, 0]) ** 2 + (a * c * p[:, 1]) ** 2 + (a * b * p[:, 2]) ** 2)
+        acc = g.uniform(0.0, 1.0, k) < stretch / (a * b)
+        q = p[acc] * np.array([a, b, c])
+        out = np.concatenate([out, q])
+    return out[:n].astype(np.float32)
+
+
+def surface(kind: str, n: int, seed: int) -> np.ndarray:
+    if kind == "sphere":
+        return sphere(n, seed)
+    if kind == "torus":
+        return torus(n, seed)
+    if kind == "ellipsoid":
+        return ellipsoid(n, seed)
+    if kind == "deformed_torus":
+        return torus(n, seed, deform=True)
+    raise ValueError(f"unknown surface {kind!r}")
+
+
+def field(n: int, d: int, seed: int) -> np.ndarray:
+    """F in R^{n x d}, i.i.d. N(0, 1), drawn in float64 and cast to float32."""
+    return _rng(seed).standard_normal((n, d)).astype(np.float32)
+
+
+@dataclass
+class Cloud:
+    """One integration problem: points X (n x 3), field F (n x d) and the
+    integrator's parameters."""
+    X: np.ndarray
+    F: np.ndarray
+    eps: float
+    lam: float
+    m: int
+    seed: int
+    surface: str = ""
+    extra: dict = _dc_field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.X.shape[0])
+
+    @property
+    def d(self) -> int:
+        return int(self.F.shape[1])
+
+
+def plain_sphere(n: int = 2000, d: int = 3, m: int = 64, seed: int = 0) -> Cloud:
+    """N points uniform on the unit sphere, eps=0.1, lambda=-0.5, m=64, d=3."""
+    return Cloud(sphere(n, seed), field(n, d, seed + 1), eps=0.1, lam=-0.5, m=m, seed=seed,
+                 surface="sphere")
+
+
+def large_torus(n: int = 1_000_000, d: int = 16, m: int = 256, seed: int = 0) -> Cloud:
+    """One large cloud: torus R=1, r=0.3 plus N(0, 0.01^2) jitter; eps=0.02,
+    lambda=-1, m=256, d=16."""
+    return Cloud(torus(n, seed, jitter=0.01), field(n, d, seed + 1), eps=0.02, lam=-1.0, m=m,
+                 seed=seed, surface="torus")
+
+
+def batch_sizes(count: int = 512, lo: int = 1000, hi: int = 65536, seed: int = 0) -> np.ndarray:
+    """Cloud sizes N = floor(exp(U(ln lo, ln hi)))."""
+    g = _rng(seed)
+    return np.floor(np.exp(g.uniform(math.log(lo), math.log(hi), count))).astype(np.int64)
+
+
+def uneven_batch(count: int = 512, d: int = 3, m: int = 128, seed: int = 0,
+                 lo: int = 1000, hi: int = 65536) -> list[Cloud]:
+    """Many clouds of log-uniform size on sphere / torus / ellipsoid by index
+    mod 3; eps=0.05, lambda=-0.5, m=128, d=3."""
+    sizes = batch_sizes(count, lo, hi, seed)
+    out = []
+    for i, n in enumerate(sizes):
+        kind = SURFACES[i % 3]
+        s = seed * 100003 + 17 * i + 1
+        out.append(Cloud(surface(kind, int(n), s), field(int(n), d, s + 7), eps=0.05, lam=-0.5,
+                         m=m, seed=s, surface=kind))
+    return out
+
+
+def sinkhorn_pair(n: int = 100_000, d: int = 1, m: int = 128, seed: int = 0) -> list[Cloud]:
+    """Two clouds for repeated application: a sphere and a deformed torus of n
+    points each, eps=0.05, lambda=-0.5, m=128; F holds d start vectors."""
+    return [
+        Cloud(sphere(n, seed), field(n, d, seed + 1), eps=0.05, lam=-0.5, m=m, seed=seed,
+              surface="sphere"),
+        Cloud(torus(n, seed + 2, deform=True), field(n, d, seed + 3), eps=0.05, lam=-0.5, m=m,
+              seed=seed + 2, surface="deformed_torus"),
+    ]
+
+
+def scaling_vectors(n: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Two positive scaling vectors s0, s1 ~ U[0.9, 1.1] for the alternating
+    repeated-application loop."""
+    g = _rng(seed)
+    return (g.uniform(0.9, 1.1, n).astype(np.float32), g.uniform(0.9, 1.1, n).astype(np.float32))
+
+
+def poisson_requests(count: int, qps: float, seed: int, lo: int = 2000, hi: int = 200_000,
+                     ds=(3, 16, 64), ms=(64, 128, 256)) -> list[dict]:
+    """Request stream for the serving loop: exponential inter-arrival gaps at
+    the given rate, log-uniform N, a random surface, d and m drawn uniformly."""
+    g = _rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += g.exponential(1.0 / qps)
+        n = int(math.floor(math.exp(g.uniform(math.log(lo), math.log(hi)))))
+        out.append(dict(t=t, n=n, surface=SURFACES[int(g.integers(0, 3))], d=int(g.choice(ds)),
+                        m=int(g.choice(ms)), seed=int(g.integers(0, 2**31 - 1))))
+    return out

@@ -1,0 +1,432 @@
+"""Pins for the CPU oracle against things other than itself: published values,
+closed forms, library routines on the same mathematics, brute force on tiny
+inputs and the statistical law of the estimator (Lemma 2.5 proof, App. A.4).
+All CPU."""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.linalg as sl
+import scipy.optimize as so
+import scipy.stats as ss
+
+from oracle import rfd_oracle as o
+from paper_2302_00942_amd import workloads as wl
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_constants():
+    vals = {}
+    with open(os.path.join(GOLD, "constants.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    return vals
+
+
+# ---------------------------------------------------------------- sampler
+def test_splitmix64_published_outputs():
+    with open(os.path.join(GOLD, "splitmix64_seed0.txt")) as fh:
+        ref = [int(x, 16) for x in fh.read().split() if x.startswith("0x")]
+    g = o.splitmix64(0)
+    assert [next(g) for _ in range(3)] == ref
+
+
+def test_gaussian_stream_is_standard_normal():
+    g = o.gaussian_stream(12345)
+    z = np.array([next(g) for _ in range(100_000)])
+    assert abs(z.mean()) < 5 / math.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / z.size)
+    assert ss.kstest(z, "norm").pvalue > 1e-4
+    # successive pairs are uncorrelated (Box-Muller uses both outputs)
+    assert abs(np.corrcoef(z[0::2], z[1::2])[0, 1]) < 5 / math.sqrt(z.size / 2)
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.02])
+def test_ball_sampler_is_truncated_gaussian(eps):
+    sig, R = o.preset(eps)
+    om = o.sample_frequencies(4000, eps, seed=7).astype(np.float64)
+    r = np.linalg.norm(om, axis=1)
+    assert r.max() <= R * (1 + 1e-6)
+    # radial law: chi_3 scaled by sigma and truncated at R
+    cdf = lambda x: ss.chi(3).cdf(np.asarray(x) / sig) / ss.chi(3).cdf(R / sig)
+    assert ss.kstest(r, cdf).pvalue > 1e-4
+    # direction is isotropic: mean unit vector ~ 0
+    u = om / r[:, None]
+    assert np.linalg.norm(u.mean(axis=0)) < 5 / math.sqrt(len(r))
+
+
+def test_box_sampler_is_truncated_gaussian():
+    eps = 0.05
+    sig, R = o.preset(eps, o.BOX_LINF)
+    assert R == pytest.approx(0.5 / eps) and sig == pytest.approx(R / 3)
+    om = o.sample_frequencies(3000, eps, seed=3, shape=o.BOX_LINF).astype(np.float64)
+    assert np.abs(om).max() <= R * (1 + 1e-6)
+    tn = ss.truncnorm(-R / sig, R / sig, scale=sig)
+    for c in range(3):
+        assert ss.kstest(om[:, c], tn.cdf).pvalue > 1e-4
+
+
+def test_sampler_is_deterministic_and_seed_dependent():
+    a = o.sample_frequencies(64, 0.1, seed=5)
+    b = o.sample_frequencies(64, 0.1, seed=5)
+    c = o.sample_frequencies(64, 0.1, seed=6)
+    assert a.dtype == np.float32 and np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+# ---------------------------------------------------------------- weights
+def test_constants_match_their_definitions():
+    g = _golden_constants()
+    assert o.THETA13 == g["theta13"]
+    u0 = so.brentq(lambda u: math.sin(u) - u * math.cos(u), math.pi, 1.5 * math.pi, xtol=1e-15)
+    assert abs(u0 - g["u0"]) < 1e-12 and abs(o.U0 - u0) < 1e-12
+    # tau_ball vanishes at the truncation radius of the main-lobe preset
+    eps = 0.05
+    R = o.preset(eps)[1]
+    assert abs(o.tau_ball(np.array([[R, 0, 0]]), eps)[0]) < 1e-12 * o.tau_ball(np.zeros((1, 3)), eps)[0]
+
+
+def _tau_ball_quad(r, eps):
+    # radial Fourier transform of the ball indicator: int_0^eps 4 pi rho^2 j0(2 pi r rho) d rho
+    j0 = lambda rho: np.sinc(2.0 * r * rho)  # sin(2 pi r rho)/(2 pi r rho)
+    val, _ = si.quad(lambda rho: 4 * math.pi * rho * rho * j0(rho), 0.0, eps, epsabs=0, epsrel=1e-13, limit=200)
+    return val
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.02])
+def test_tau_ball_matches_radial_quadrature(eps):
+    vol = 4 * math.pi * eps ** 3 / 3
+    assert o.tau_ball(np.zeros((1, 3)), eps)[0] == pytest.approx(vol, rel=1e-15)
+    # both branches (series below u = 1e-2) and across the first zero
+    for u in [1e-6, 5e-3, 9.99e-3, 1.001e-2, 0.3, 1.0, 3.0, 4.4, 6.0, 9.0]:
+        r = u / (2 * math.pi * eps)
+        om = np.array([[r / math.sqrt(3)] * 3])
+        got = o.tau_ball(om, eps)[0]
+        ref = _tau_ball_quad(r, eps)
+        assert abs(got - ref) <= 1e-11 * vol, (u, got, ref)
+
+
+def test_tau_box_matches_product_of_1d_transforms():
+    eps = 0.05
+    assert o.tau_box(np.zeros((1, 3)), eps)[0] == pytest.approx((2 * eps) ** 3, rel=1e-15)
+    rng = np.random.default_rng(0)
+    for om in rng.uniform(-12, 12, (8, 3)):
+        ref = 1.0
+        for c in om:
+            v, _ = si.quad(lambda z: math.cos(2 * math.pi * c * z), -eps, eps, epsabs=0, epsrel=1e-13)
+            ref *= v
+        assert abs(o.tau_box(om[None], eps)[0] - ref) < 1e-13 * (2 * eps) ** 3
+
+
+def test_truncation_mass_and_pdf_normalisation():
+    for t in [0.5, 1.0, 3.0, 7.0]:
+        assert o.truncation_mass(t) == pytest.approx(ss.chi(3).cdf(t), rel=1e-13)
+        assert o.truncation_mass(t, o.BOX_LINF) == pytest.approx((2 * ss.norm.cdf(t) - 1) ** 3, rel=1e-13)
+    sig, R = 0.7, 2.0
+    tot, _ = si.quad(lambda r: o.pdf(np.array([[r, 0, 0]]), sig, R)[0] * 4 * math.pi * r * r, 0, R,
+                     epsabs=0, epsrel=1e-13)
+    assert tot == pytest.approx(1.0, abs=1e-12)
+
+
+def test_main_lobe_weights_positive_and_origin_value():
+    # w(0) = tau(0) / p(0) = (4 pi eps^3/3) (2 pi sigma^2)^{3/2} C(3), independent of eps
+    for eps in [0.1, 0.05, 0.02]:
+        sig, R = o.preset(eps)
+        w0 = o.weights(np.zeros((1, 3)), eps)[0]
+        ref = 4 * math.pi * eps ** 3 / 3 * (2 * math.pi * sig * sig) ** 1.5 * ss.chi(3).cdf(3.0)
+        assert w0 == pytest.approx(ref, rel=1e-13)
+        om, w = o.frequencies_and_weights(256, eps, seed=1)
+        assert np.all(w > 0)
+
+
+# ---------------------------------------------------------------- expm, phi1
+def test_pade13_coefficients_satisfy_the_pade_conditions():
+    # [13/13] Pade of e^x: q(x) e^x - p(x) = O(x^27), checked in exact rational
+    # arithmetic on the Taylor coefficients, with q(x) = p(-x) and p(0) = 1.
+    from fractions import Fraction
+    b = o.pade13_coefficients()
+    bf = [Fraction(x).limit_denominator(10 ** 30) for x in b]
+    p = bf + [Fraction(0)] * 14
+    q = [c * (-1) ** k for k, c in enumerate(bf)]
+    for k in range(27):
+        conv = sum(q[j] / math.factorial(k - j) for j in range(min(k, 13) + 1))
+        assert abs(float(conv - p[k])) < 1e-16 * max(1.0, float(abs(p[k]))), k
+    assert b[0] == 1.0 and b[1] == 0.5
+
+
+@pytest.mark.parametrize("scale", [1e-3, 0.1, 1.0, 5.0, 30.0, 300.0])
+@pytest.mark.parametrize("kind", ["general", "symmetric", "negdef"])
+def test_expm_matches_scipy(scale, kind):
+    if kind == "symmetric" and scale > 100:
+        pytest.skip("e^A overflows float64 for eigenvalues above ~709")
+    rng = np.random.default_rng(int(scale * 1000) + len(kind))
+    n = 40
+    A = rng.standard_normal((n, n)) / math.sqrt(n)
+    if kind == "symmetric":
+        A = (A + A.T) / 2
+    if kind == "negdef":
+        A = -A @ A.T
+    A = A * scale
+    ref = sl.expm(A)
+    err = np.linalg.norm(o.expm(A) - ref) / max(np.linalg.norm(ref), 1e-300)
+    assert err < 1e-11, err
+
+
+def test_expm_closed_forms():
+    d = np.array([-700.0, -3.0, 0.0, 1e-9, 2.5, 20.0])
+    assert np.allclose(np.diag(o.expm(np.diag(d))), np.exp(d), rtol=1e-13, atol=0)
+    t = 2.3
+    Rot = o.expm(np.array([[0.0, -t], [t, 0.0]]))
+    assert np.allclose(Rot, [[math.cos(t), -math.sin(t)], [math.sin(t), math.cos(t)]], atol=1e-14)
+    N = np.diag(np.ones(3), 1) * 1.7  # nilpotent
+    ref = np.eye(4) + N + N @ N / 2 + N @ N @ N / 6
+    assert np.allclose(o.expm(N), ref, rtol=1e-14, atol=1e-14)
+
+
+def test_phi1_diagonal_closed_form():
+    x = np.array([-12103.0, -3304.0, -50.0, -1.0, -1e-8, 0.0, 1e-8, 0.7, 9.0])
+    ref = np.where(x == 0, 1.0, np.expm1(x) / np.where(x == 0, 1, x))
+    got = np.diag(o.phi1(np.diag(x)))
+    # one spectrum spanning -12103..9 forces s = 12 squarings on every entry;
+    # scaling and squaring then loses about 2^s unit roundoffs on the small ones
+    s = o.scaling_power(np.diag(x))
+    assert s == 12
+    assert np.allclose(got, ref, rtol=2 ** s * 4 * np.finfo(float).eps, atol=0)
+    for xi, ri in zip(x, ref):  # one entry at a time: no overscaling
+        assert o.phi1(np.array([[xi]]))[0, 0] == pytest.approx(ri, rel=1e-14)
+    P, E = o.phi1_and_exp(np.diag(x))
+    assert np.allclose(np.diag(E), np.exp(x), rtol=1e-12, atol=1e-300)
+
+
+def test_phi1_matches_definition_and_series():
+    rng = np.random.default_rng(3)
+    n = 30
+    # well-conditioned nonsingular: phi1(Y) = (e^Y - I) Y^{-1}
+    Y = rng.standard_normal((n, n)) / math.sqrt(n) * 4 + 3 * np.eye(n)
+    ref = np.linalg.solve(Y.T, (sl.expm(Y) - np.eye(n)).T).T
+    assert np.linalg.norm(o.phi1(Y) - ref) / np.linalg.norm(ref) < 1e-12
+    # small norm: phi1(Y) = sum_k Y^k / (k+1)!
+    Y = rng.standard_normal((n, n)) / math.sqrt(n) * 0.05
+    ref = np.zeros((n, n))
+    Yk = np.eye(n)
+    for k in range(30):
+        ref += Yk / math.factorial(k + 1)
+        Yk = Yk @ Y
+    assert np.linalg.norm(o.phi1(Y) - ref) / np.linalg.norm(ref) < 1e-14
+    # non-normal, diagonalizable: V phi1(D) V^{-1}
+    V = np.eye(n) + 0.3 * rng.standard_normal((n, n)) / math.sqrt(n)
+    lam = -np.linspace(0.5, 400.0, n)
+    Y = V @ np.diag(lam) @ np.linalg.inv(V)
+    ref = V @ np.diag(np.expm1(lam) / lam) @ np.linalg.inv(V)
+    assert np.linalg.norm(o.phi1(Y) - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def test_phi1_singular_argument():
+    # rank-deficient argument: phi1 is defined where the inverse is not
+    rng = np.random.default_rng(4)
+    U = rng.standard_normal((20, 3))
+    Y = -U @ U.T
+    w, Q = np.linalg.eigh(Y)
+    ref = Q @ np.diag(np.where(np.abs(w) < 1e-12, 1.0, np.expm1(w) / np.where(np.abs(w) < 1e-12, 1, w))) @ Q.T
+    assert np.linalg.norm(o.phi1(Y) - ref) / np.linalg.norm(ref) < 1e-12
+
+
+# ---------------------------------------------------------------- low-rank identity
+@pytest.mark.parametrize("n,m,lam", [(300, 16, -0.3), (300, 64, 0.05), (20, 64, -0.5), (500, 40, -2.0)])
+def test_lowrank_identity_exact_on_rank_m(n, m, lam):
+    rng = np.random.default_rng(n + m)
+    A = rng.standard_normal((n, m)) / math.sqrt(m)
+    B = rng.standard_normal((n, m)) / math.sqrt(m)  # not equal to A: catches a transposed core
+    F = rng.standard_normal((n, 5))
+    ref = sl.expm(lam * (A @ B.T)) @ F
+    out, parts = o.lowrank_apply(A, B, F, lam)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-12
+    assert np.allclose(parts["M"], B.T @ A)
+
+
+def _what_loop(X, om, w):
+    # W_hat(i, j) = (1/f) sum_k w_k cos(2 pi omega_k . (x_i - x_j)), plain loops
+    n, f = len(X), len(om)
+    out = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            s = 0.0
+            for k in range(f):
+                ph = sum(float(om[k][c]) * (float(X[i][c]) - float(X[j][c])) for c in range(3))
+                s += w[k] * math.cos(2 * math.pi * ph)
+            out[i, j] = s / f
+    return out
+
+
+def test_features_reproduce_real_part_estimator():
+    X = wl.sphere(6, 1)
+    om, w = o.frequencies_and_weights(8, 0.3, seed=2)
+    assert np.allclose(o.what_hat(X, om, w), _what_loop(X, om, w), rtol=1e-12, atol=1e-14)
+    # signed weights: sign on A only, still the same estimator
+    om, w = o.frequencies_and_weights(8, 0.3, seed=2, sigma=1 / 0.3, radius=3 / 0.3)
+    assert np.any(w < 0)
+    assert np.allclose(o.what_hat(X, om, w), _what_loop(X, om, w), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_rfd_matches_dense_expm_of_feature_graph(signed):
+    c = wl.plain_sphere(n=400, d=3, m=64, seed=11)
+    kw = dict(sigma=1 / c.eps, radius=3 / c.eps) if signed else {}
+    lam = -0.01 if signed else c.lam
+    out, p = o.rfd_integrate(c.X, c.F, c.eps, lam, c.m, c.seed, return_parts=True, **kw)
+    if signed:
+        assert np.any(p["w"] < 0)
+    W = o.what_hat(c.X, p["omega"], p["w"])
+    ref = sl.expm(lam * W) @ c.F.astype(np.float64)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_single_point_closed_form():
+    X = np.array([[0.3, -0.2, 0.9]], dtype=np.float32)
+    F = np.array([[1.5, -2.0, 0.25, 4.0]], dtype=np.float32)
+    for lam in [-0.5, 0.3]:
+        out, p = o.rfd_integrate(X, F, 0.1, lam, 64, 9, return_parts=True)
+        what = p["w"].sum() / 32
+        assert np.allclose(out, math.exp(lam * what) * F.astype(np.float64), rtol=1e-14, atol=0)
+
+
+def test_identical_points_closed_form():
+    n = 1000
+    X = np.tile(np.array([[0.1, 0.2, -0.3]], dtype=np.float32), (n, 1))
+    F = wl.field(n, 3, 5)
+    lam = -0.5
+    out, p = o.rfd_integrate(X, F, 0.05, lam, 128, 4, return_parts=True)
+    what = p["w"].sum() / 64
+    ref = F + np.ones((n, 1)) * (math.expm1(lam * what * n) / n) * F.astype(np.float64).sum(0)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_lambda_zero_is_identity():
+    c = wl.plain_sphere(n=300)
+    out = o.rfd_integrate(c.X, c.F, c.eps, 0.0, c.m, c.seed)
+    assert np.array_equal(out, c.F.astype(np.float64))
+
+
+# ---------------------------------------------------------------- dense brute force
+def test_dense_adjacency_boundary_and_self_loops():
+    X = np.array([[0, 0, 0], [0.5, 0, 0], [0, 0.75, 0]], dtype=np.float32)
+    W = o.dense_adjacency(X, 0.5)
+    assert W.tolist() == [[1, 1, 0], [1, 1, 0], [0, 0, 1]]  # |x0 - x1| = eps exactly: inclusive
+    W0 = o.dense_adjacency(X, 0.5, self_loops=False)
+    assert np.array_equal(W0, W - np.eye(3))
+
+
+def test_dense_path_graph_closed_form():
+    # three points on a line: W = I + P3, P3 the path adjacency with eigenvalues 0, +-sqrt2
+    X = np.array([[0, 0, 0], [0.5, 0, 0], [1.0, 0, 0]], dtype=np.float32)
+    F = np.eye(3)
+    lam = -0.7
+    out = o.dense_integrate(X, F, 0.5, lam)
+    s2 = math.sqrt(2.0)
+    V = np.array([[0.5, 1 / s2, 0.5], [s2 / 2, 0, -s2 / 2], [0.5, -1 / s2, 0.5]])  # columns: +sqrt2, 0, -sqrt2
+    ref = math.exp(lam) * V @ np.diag(np.exp(lam * np.array([s2, 0, -s2]))) @ V.T
+    assert np.allclose(out, ref, rtol=1e-13, atol=1e-15)
+
+
+def test_self_loop_convention_is_a_scalar_factor():
+    c = wl.plain_sphere(n=300, seed=2)
+    a = o.dense_integrate(c.X, c.F, c.eps, c.lam, self_loops=True)
+    b = o.dense_integrate(c.X, c.F, c.eps, c.lam, self_loops=False)
+    assert np.linalg.norm(a - math.exp(c.lam) * b) / np.linalg.norm(a) < 1e-13
+
+
+# ---------------------------------------------------------------- estimator law (Lemma 2.5 proof)
+def _gl(R, n=4000):
+    x, wq = np.polynomial.legendre.leggauss(n)
+    return 0.5 * R * (x + 1), 0.5 * R * wq
+
+
+def _f_tilde(rho, eps, R):
+    # E[W_hat(z)] = int_{||w|| <= R} cos(2 pi w.z) tau(w) dw, radial form
+    r, wq = _gl(R)
+    tau = o.tau_ball(np.stack([r, 0 * r, 0 * r], 1), eps)
+    rho = np.atleast_1d(rho)
+    return (tau * 4 * math.pi * r * r * np.sinc(2 * np.outer(rho, r))) @ wq
+
+
+def _second_moment(rho, eps, R, sig):
+    # E[(tau/p)^2 cos^2(2 pi w.z)] = int tau^2/p * (1 + sinc(4 r rho))/2 * 4 pi r^2 dr
+    r, wq = _gl(R)
+    om = np.stack([r, 0 * r, 0 * r], 1)
+    g = o.tau_ball(om, eps) ** 2 / o.pdf(om, sig, R)
+    return float((g * 4 * math.pi * r * r * 0.5 * (1 + np.sinc(4 * r * rho))) @ wq)
+
+
+def test_estimator_mean_and_variance_law():
+    eps, f = 0.1, 256
+    sig, R = o.preset(eps)
+    rhos = [0.0, 0.5 * eps, eps, 2 * eps]
+    X = np.array([[0, 0, 0]] + [[r, 0, 0] for r in rhos[1:]], dtype=np.float32)
+    draws = []
+    for seed in range(300):
+        om, w = o.frequencies_and_weights(2 * f, eps, seed=1000 + seed)
+        draws.append(o.what_hat(X, om, w)[0])
+    draws = np.array(draws)  # seeds x 4: W_hat(x0, x_j)
+    for j, rho in enumerate(rhos):
+        mean_ref = _f_tilde(rho, eps, R)[0]
+        var_ref = (_second_moment(rho, eps, R, sig) - mean_ref ** 2) / f
+        se = math.sqrt(var_ref / len(draws))
+        assert abs(draws[:, j].mean() - mean_ref) < 5 * se + 1e-12, (rho, draws[:, j].mean(), mean_ref)
+        ratio = draws[:, j].var(ddof=1) / var_ref
+        assert 0.75 < ratio < 1.3, (rho, ratio)
+
+
+def test_kernel_error_decays_as_inverse_sqrt_m():
+    eps = 0.1
+    sig, R = o.preset(eps)
+    X = wl.sphere(60, 21)
+    D = np.linalg.norm(X[:, None, :].astype(np.float64) - X[None, :, :], axis=-1)
+    Wbar = _f_tilde(D.ravel(), eps, R).reshape(D.shape)
+    ms = [64, 256, 1024, 4096]
+    errs = []
+    for m in ms:
+        e = [np.linalg.norm(o.what_hat(X, *o.frequencies_and_weights(m, eps, seed=s)) - Wbar)
+             for s in range(20)]
+        errs.append(np.mean(e))
+    slope = np.polyfit(np.log(ms), np.log(errs), 1)[0]
+    assert -0.6 < slope < -0.4, slope
+
+
+@pytest.mark.slow
+def test_integrated_error_halves_per_4x_features():
+    eps, lam = 0.1, -0.5
+    sig, R = o.preset(eps)
+    X = wl.sphere(300, 31)
+    F = wl.field(300, 3, 32).astype(np.float64)
+    D = np.linalg.norm(X[:, None, :].astype(np.float64) - X[None, :, :], axis=-1)
+    Wbar = _f_tilde(D.ravel(), eps, R).reshape(D.shape)
+    ref = sl.expm(lam * Wbar) @ F
+    errs = []
+    for m in [1024, 4096, 16384]:
+        # m > N here, so the N x N route is the cheap one; the low-rank route
+        # equals it exactly (pinned above)
+        e = [o.relf(sl.expm(lam * o.what_hat(X, *o.frequencies_and_weights(m, eps, seed=s))) @ F, ref)
+             for s in range(12)]
+        errs.append(np.mean(e))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 1.6 < r1 < 2.5 and 1.6 < r2 < 2.5, (errs, r1, r2)
+
+
+def test_repeated_apply_matches_dense_composition():
+    n = 200
+    clouds = [wl.sphere(n, 1), wl.torus(n, 2, deform=True)]
+    om_w = [o.frequencies_and_weights(64, 0.2, seed=s) for s in (3, 4)]
+    s0, s1 = wl.scaling_vectors(n, 5)
+    v0 = wl.field(n, 2, 6)
+    lam = [-0.5, -0.3]
+    got = o.repeated_apply(clouds, v0, (s0, s1), lam, 3, [a for a, _ in om_w], [b for _, b in om_w])
+    K = [sl.expm(l * o.what_hat(X, om, w)) for X, (om, w), l in zip(clouds, om_w, lam)]
+    v = v0.astype(np.float64)
+    for t in range(3):
+        v = (s0, s1)[t % 2].astype(np.float64)[:, None] * (K[t % 2] @ v)
+    assert np.linalg.norm(got - v) / np.linalg.norm(v) < 1e-12
