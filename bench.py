@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Throughput of the RFD graph-field integrator on one MI355X.
+
+Workload: one cloud of N = 1,000,000 points on a torus (R = 1, r = 0.3,
+area-uniform, N(0, 0.01^2) jitter), eps = 0.02, lambda = -1, m = 256 random
+features, field F in R^{N x 16} ~ N(0, 1); synthetic, seeded.
+
+One step = one one-shot integration out = exp(lambda A B^T) F of that cloud:
+random features (recomputed in both passes), the Gram B^T A and B^T F in one
+pass, phi_1 of the 256 x 256 core in FP64, G = S H, and the expansion
+out = F + A G. Inputs are resident in HBM before the timed region; the
+frequencies are sampled once (they do not depend on the cloud).
+
+`value` is BF16 throughput in points*channels/s (features and the thin
+products in BF16 on the matrix cores, FP32 accumulation, FP64 phi_1), with
+its error against the FP64 CPU oracle checked at <= 2e-3; the FP32 path is
+timed beside it. Per-kernel durations come from hipEvents recorded on the
+launch stream by the library; the roofline object describes the kernel that
+takes the largest share of the step.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RFD integrated points·channels/s BF16 vs FP32 at rel err ≤2e-3; p50/p99 latency"
+PEAK = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "bf16_TFs": 2500.0,
+    "fp32_mfma_TFs": 157.3,
+    "fp64_TFs": 78.6,
+    # transcendental (sin/cos) rate: 256 CUs x 4 SIMDs x 16 lanes / 4 (quarter rate) x 2.4 GHz
+    "trans_Tops": 256 * 4 * 16 / 4 * 2.4e9 / 1e12,
+}
+KERNEL_SOURCES = {
+    "k_bta_gram": "paper_2302_00942_amd/csrc/k_stream.hip",
+    "k_bta": "paper_2302_00942_amd/csrc/k_stream.hip",
+    "k_expand": "paper_2302_00942_amd/csrc/k_stream.hip",
+    "k_reduce": "paper_2302_00942_amd/csrc/k_stream.hip",
+    "k_phi1": "paper_2302_00942_amd/csrc/k_phi1.hip",
+}
+
+
+def source_hash(path: str) -> str:
+    with open(os.path.join(ROOT, path), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/traffic.txt), or None when absent or when the kernel's
+    source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    want = source_hash(KERNEL_SOURCES.get(kernel, ""))
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
+            if parts.get("kernel") == kernel and parts.get("workload") == workload:
+                if parts.get("source_sha") != want:
+                    return None
+                return float(parts["bytes_per_launch"])
+    return None
+
+
+def phi1_flops(m: int, s: int) -> float:
+    # Pade 13 (6 products), LU with 2m right-hand sides (2/3 m^3 + 4 m^3), s squaring steps (2 products each)
+    return (6 + 2 * s) * 2.0 * m ** 3 + (2.0 / 3.0 + 4.0) * m ** 3
+
+
+def algorithmic(kernel: str, N: int, m: int, d: int, s: int, nparts: int):
+    """(bytes, flops, transcendentals) per launch, from the per-point figures:
+    pass 1 (Gram + B^T F) reads X (12 B) and F (4d B) and does m^2 + 2md flops
+    (Gram halved by symmetry) and m sin/cos; the expansion reads X and F and
+    writes out (12 + 8d B), 2md flops, m sin/cos."""
+    if kernel == "k_bta_gram":
+        return N * (12 + 4 * d), N * (m * m + 2.0 * m * d), N * m
+    if kernel == "k_bta":
+        return N * (12 + 4 * d), N * 2.0 * m * d, N * m
+    if kernel == "k_expand":
+        return N * (12 + 8 * d), N * 2.0 * m * d, N * m
+    if kernel == "k_phi1":
+        return 12 * m * m * 8, phi1_flops(m, s), 0
+    if kernel == "k_reduce":
+        floats = m * (m + 1) / 2 + m * d
+        return nparts * floats * 4, nparts * floats, 0
+    return 0, 0, 0
+
+
+def roofline(kernel: str, avg_ms: float, N: int, m: int, d: int, s: int, nparts: int, prec: str, workload: str):
+    B, Fl, T = algorithmic(kernel, N, m, d, s, nparts)
+    sec = avg_ms * 1e-3
+    cands = []
+    if B:
+        cands.append(("hbm", B / sec / 1e9, PEAK["hbm_GBs"], "GB/s", B))
+    if Fl:
+        if kernel == "k_phi1":
+            cands.append(("mfma", Fl / sec / 1e12, PEAK["fp64_TFs"], "TFLOP/s", Fl))
+        elif kernel != "k_reduce":
+            peak = PEAK["bf16_TFs"] if prec == "bf16" else PEAK["fp32_mfma_TFs"]
+            cands.append(("mfma", Fl / sec / 1e12, peak, "TFLOP/s", Fl))
+    if T:
+        cands.append(("alu", T / sec / 1e12, PEAK["trans_Tops"], "Tops/s (sin/cos)", T))
+    bound, ach, peak, unit, work = max(cands, key=lambda c: c[1] / c[2])
+    traffic = read_traffic(kernel, workload)
+    return {"kernel": kernel, "bound": bound, "achieved": round(ach, 3), "peak": round(peak, 3), "unit": unit,
+            "frac": round(ach / peak, 4), "traffic": traffic, "avg_us": round(avg_ms * 1e3, 2),
+            "all": {c[0]: round(c[1] / c[2], 4) for c in cands}}
+
+
+def time_steps(fn, steps: int, warmup: int, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(st)
+        fn()
+        b.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = sorted(a.elapsed_time(b) for a, b in evs)
+    p = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
+    return wall / steps * 1e3, p(0.5), p(0.99)
+
+
+def cpu_baseline(cloud):
+    from threadpoolctl import threadpool_info
+    from oracle import rfd_oracle as o
+    t0 = time.perf_counter()
+    out = o.rfd_integrate(cloud.X, cloud.F, cloud.eps, cloud.lam, cloud.m, cloud.seed)
+    t = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return out, t, threads
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (and the error check)")
+    ap.add_argument("--n", type=int, default=1_000_000, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one MI355X: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        return 2
+    import torch
+    from paper_2302_00942_amd import rfd, workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    rfd.lib()
+    cloud = wl.large_torus(n=args.n)
+    N, m, d = cloud.n, cloud.m, cloud.d
+    workload = f"torus N={N} m={m} d={d} eps={cloud.eps} lambda={cloud.lam} one-shot"
+    X = torch.from_numpy(cloud.X).cuda()
+    F = torch.from_numpy(cloud.F).cuda()
+    res = {}
+    outs = {}
+    for prec in ("fp32", "bf16"):
+        plan = rfd.Plan(m, cloud.eps, cloud.lam, cloud.seed, precision=prec)
+        out = torch.empty_like(F)
+        step = lambda: plan.oneshot(X, F, out=out)
+        ms, p50, p99 = time_steps(step, args.steps, args.warmup, torch)
+        st = plan.check()
+        if st != rfd.OK:
+            print(f"device reported {rfd.status_string(st)} for {prec}", file=sys.stderr)
+            return 1
+        outs[prec] = out.cpu().numpy()
+        # per-kernel durations: the same steps with hipEvents around every launch
+        rfd.profile_enable(True)
+        rfd.profile_read(reset=True)
+        for _ in range(args.steps):
+            step()
+        kern = rfd.profile_read(reset=True)
+        rfd.profile_enable(False)
+        _, _, s = plan.core()
+        # resident plan: integrate only (two passes over X and F)
+        plan.features(X)
+        rms, rp50, rp99 = time_steps(lambda: plan.integrate(F, out=out), args.steps, args.warmup, torch)
+        res[prec] = dict(ms=ms, p50=p50, p99=p99, kern=kern, s=s, resident_ms=rms)
+        plan.close()
+
+    line = {
+        "metric": METRIC,
+        "value": round(N * d / (res["bf16"]["ms"] * 1e-3), 1),
+        "unit": "points*channels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["bf16"]["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": workload, "N": N, "m": m, "d": d, "eps": cloud.eps, "lambda": cloud.lam,
+                   "surface": "torus R=1 r=0.3 + N(0,0.01^2) jitter", "step": "one-shot integration",
+                   "precision": "bf16 features and thin products, fp32 accumulation, fp64 phi_1"},
+        "latency_ms": {"p50": round(res["bf16"]["p50"], 4), "p99": round(res["bf16"]["p99"], 4)},
+        "fp32": {"value": round(N * d / (res["fp32"]["ms"] * 1e-3), 1), "ms_per_step": round(res["fp32"]["ms"], 4),
+                 "p50": round(res["fp32"]["p50"], 4), "p99": round(res["fp32"]["p99"], 4)},
+        "speedup_bf16_over_fp32": round(res["fp32"]["ms"] / res["bf16"]["ms"], 3),
+        "resident_plan_integrate": {p: {"value": round(N * d / (res[p]["resident_ms"] * 1e-3), 1),
+                                        "ms": round(res[p]["resident_ms"], 4)} for p in ("bf16", "fp32")},
+        "phi1_scaling_power": res["bf16"]["s"],
+    }
+    for prec in ("bf16", "fp32"):
+        kern = res[prec]["kern"]
+        line.setdefault("kernels_us", {})[prec] = {k: round(v[0] / v[1] * 1e3, 2) for k, v in kern.items()}
+    kern = res["bf16"]["kern"]
+    from paper_2302_00942_amd.rfd import lib  # noqa: F401
+    nparts = min(512, (N + 63) // 64)
+    dom = max(kern.items(), key=lambda kv: kv[1][0])[0]
+    line["roofline"] = roofline(dom, kern[dom][0] / kern[dom][1], N, m, d, res["bf16"]["s"], nparts, "bf16",
+                                workload)
+    line["roofline_all"] = {k: roofline(k, v[0] / v[1], N, m, d, res["bf16"]["s"], nparts, "bf16", workload)
+                            for k, v in kern.items() if k in KERNEL_SOURCES}
+    if not args.no_cpu_baseline:
+        from oracle import rfd_oracle as o
+        ref, t, threads = cpu_baseline(cloud)
+        Fd = cloud.F.astype(np.float64)
+        for prec in ("bf16", "fp32"):
+            key = "rel_err" if prec == "bf16" else None
+            e = o.relf(outs[prec], ref)
+            ec = o.relf(outs[prec] - Fd, ref - Fd)
+            if prec == "bf16":
+                line["rel_err"] = float(f"{e:.3e}")
+                line["rel_err_correction"] = float(f"{ec:.3e}")
+            else:
+                line["fp32"]["rel_err"] = float(f"{e:.3e}")
+                line["fp32"]["rel_err_correction"] = float(f"{ec:.3e}")
+        line["cpu_baseline"] = {"value": round(N * d / t, 1), "unit": "points*channels/s", "cores": threads,
+                                "kind": "oracle",
+                                "sample": f"one full one-shot integration of the same cloud ({workload}), "
+                                          f"numpy float64, {t:.2f} s"}
+        if line["rel_err"] > 2e-3 or line["fp32"]["rel_err"] > 1e-5:
+            print(json.dumps(line))
+            print("accuracy bar missed", file=sys.stderr)
+            return 1
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

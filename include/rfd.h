@@ -1,0 +1,216 @@
+/*
+ * rfd.h -- C ABI of the RFDiffusion (RFD) graph-field integrator on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * What it computes (Choromanski et al., "Efficient Graph Field Integrators
+ * Meet Point Clouds", ICML 2023, arXiv 2302.00942):
+ *
+ *   Graph-field integration (Sec. 1, Eq. 1): out(v) = sum_w K(w, v) F(w) for
+ *   every point v of a cloud X = {x_i} in R^3, with the graph diffusion kernel
+ *   K = exp(lambda W) (Sec. 2, Eq. 3) of the epsilon-NN graph
+ *   W(i, j) = 1[||x_i - x_j|| <= eps] (Sec. 2.4, Eq. "w").
+ *
+ *   W is never built. Random Fourier features give W ~= A B^T with
+ *   A, B in R^{N x m} (Sec. 2.4): f = m/2 frequencies omega_k drawn from a
+ *   truncated Gaussian with pdf p, importance weights w_k = tau(omega_k) /
+ *   p(omega_k) (tau = Fourier transform of the ball indicator), and real
+ *   features Phi(x) = [c_k cos(2 pi omega_k.x) || c_k sin(2 pi omega_k.x)],
+ *   c_k = sqrt(|w_k| / f); B = Phi, A = Phi diag(sgn w, sgn w). This is the
+ *   real-part estimator of the Lemma 2.5 proof (App. A.4).
+ *
+ *   The low-rank exponential (Sec. 2.4, the identity displayed after the
+ *   feature maps and the bracket order of the GFI formula that follows) is
+ *   applied in phi_1 form, which needs no inverse of B^T A:
+ *       out = F + A (lambda phi_1(lambda B^T A)) (B^T F),
+ *       phi_1(Y) = sum_{k>=0} Y^k / (k+1)!,
+ *   with phi_1 evaluated in FP64 by a [13/13] Pade approximant with scaling
+ *   and squaring.
+ *
+ * Memory: every X, F and out pointer is DEVICE memory owned by the caller.
+ * F and out are row-major N x d float32 arrays with leading dimensions
+ * ldF, ldO >= d (in elements). A plan owns its own device buffers (the
+ * frequencies, a copy of X, the m x m core and scratch), allocated with
+ * hipMalloc when created or when a cloud needs more room, and freed by
+ * rfd_plan_destroy. Nothing throws across this ABI: every call returns an
+ * rfd_status. Objects are thread-compatible (one thread at a time per plan),
+ * not thread-safe; the server object is thread-safe.
+ */
+#ifndef RFD_H
+#define RFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RFD_OK = 0,
+  RFD_ERR_INVALID_ARG = 1,   /* bad size, null pointer, m odd or <= 0, eps <= 0, ld < d ... */
+  RFD_ERR_RANGE = 2,         /* exp(lambda A B^T) could overflow FP64 (see rfd_plan_create) */
+  RFD_ERR_OUT_OF_BUDGET = 3, /* server: the request can never fit the HBM budget */
+  RFD_ERR_NONFINITE = 4,     /* NaN or Inf in X or F, or produced in the core */
+  RFD_ERR_DEVICE = 5,        /* a HIP runtime call failed */
+  RFD_ERR_NOT_READY = 6,     /* rfd_integrate before rfd_features; rfd_wait timed out */
+  RFD_ERR_SHUTDOWN = 7       /* server is shutting down */
+} rfd_status;
+
+/* Shape of the neighbourhood f(z) = 1[||z|| <= eps] (Sec. 2.4). */
+typedef enum {
+  RFD_BALL_L2 = 0,  /* Euclidean ball: tau = (sin u - u cos u)/(2 pi^2 r^3), u = 2 pi eps r */
+  RFD_BOX_LINF = 1  /* max-norm box: tau = prod_i sin(2 pi eps w_i)/(pi w_i) */
+} rfd_shape;
+
+/* Arithmetic of the two thin products and the Gram (features always come
+ * from FP32 phases; accumulation is FP32; phi_1 is FP64). */
+typedef enum {
+  RFD_FP32 = 0,  /* FP32 features, FP32 matrix cores (v_mfma_f32_*_f32) */
+  RFD_BF16 = 1   /* features and F rounded to BF16 (RNE) as MFMA operands */
+} rfd_precision;
+
+typedef struct {
+  int32_t m;          /* real feature columns, even, 2 <= m <= 256 (f = m/2 frequencies) */
+  int32_t shape;      /* rfd_shape */
+  int32_t precision;  /* rfd_precision */
+  int32_t reserved;   /* must be 0 */
+  double eps;         /* neighbourhood radius, > 0 */
+  double lambda;      /* diffusion strength in exp(lambda W); any sign */
+  double sigma;       /* Gaussian scale of the frequency law; 0 with radius 0 = preset */
+  double radius;      /* truncation radius R of the frequency law; 0 with sigma 0 = preset:
+                         ball R = 0.7151483/eps (first zero of tau), box R = 1/(2 eps);
+                         sigma = R/3. The preset keeps every weight >= 0. */
+  uint64_t seed;      /* SplitMix64 seed of the frequency stream */
+  const float* omega; /* optional HOST array of f x 3 frequencies (row-major); NULL = sample */
+} rfd_params;
+
+typedef struct rfd_plan_s* rfd_plan_t;
+typedef struct rfd_server_s* rfd_server_t;
+typedef void* rfd_stream_t; /* a hipStream_t; NULL = the default stream */
+
+/* ---------------------------------------------------------------- plans */
+
+/* Validates params, samples the f frequencies on the host (SplitMix64 ->
+ * 53-bit uniforms -> Box-Muller, both outputs in order -> times sigma ->
+ * rejected outside the ball/box of radius R, in FP64 -> rounded to FP32) or
+ * takes them from params->omega, computes the weights w = tau/p in FP64 and
+ * uploads the frequencies. Errors: RFD_ERR_INVALID_ARG. */
+rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan);
+
+/* Host only (no device memory, no GPU needed): the f frequencies and FP64
+ * weights that rfd_plan_create would produce for these params, written to
+ * caller-owned host arrays of f x 3 floats and f doubles. Errors:
+ * RFD_ERR_INVALID_ARG as for rfd_plan_create. */
+rfd_status rfd_params_frequencies(const rfd_params* params, float* omega_fx3, double* w_f);
+
+/* Copies the plan's FP32 frequencies (f x 3, row-major) and FP64 weights (f)
+ * to host arrays; either pointer may be NULL. */
+rfd_status rfd_plan_export(rfd_plan_t plan, float* omega_fx3, double* w_f);
+
+/* Features of a cloud: copies X (N x 3 float32, device, row-major) into the
+ * plan, computes M = B^T A (split over N, fixed-order reduction, FP64 result)
+ * and S = lambda phi_1(lambda M) in FP64 (Pade 13, scaling and squaring).
+ * Enqueued on `stream`; returns once enqueued. Errors found on the host are
+ * returned at once: RFD_ERR_INVALID_ARG (N < 0), RFD_ERR_RANGE when lambda
+ * and the weights allow growth (lambda * w > 0 for some k) and the exact
+ * bound |lambda| N sum|w|/f exceeds 700. Device-side findings (non-finite X
+ * or core) are reported by rfd_plan_check. N = 0 is valid: out = F. */
+rfd_status rfd_features(rfd_plan_t plan, const float* X_dev, int64_t N, rfd_stream_t stream);
+
+/* out = F + A (S (B^T F)) for the plan's cloud: K4 (split-N B^T F), K5
+ * (reduce, G = S H) and K6 (out = F + A G), enqueued on `stream`. out may
+ * alias F (each row of F is read before that row of out is written).
+ * d = 0 is a no-op. Errors: RFD_ERR_NOT_READY if rfd_features has not run;
+ * RFD_ERR_INVALID_ARG for ld < d, d < 0, d > 1024 or null pointers. */
+rfd_status rfd_integrate(rfd_plan_t plan, const float* F_dev, int64_t ldF, int32_t d,
+                         float* out_dev, int64_t ldO, rfd_stream_t stream);
+
+/* One-shot: rfd_features followed by rfd_integrate, with the Gram and B^T F
+ * computed in ONE pass over X and F (B^T [A | F]); two passes in total. */
+rfd_status rfd_integrate_oneshot(rfd_plan_t plan, const float* X_dev, int64_t N,
+                                 const float* F_dev, int64_t ldF, int32_t d,
+                                 float* out_dev, int64_t ldO, rfd_stream_t stream);
+
+/* Waits for `stream` and reports what the device found for this plan since
+ * the last check: RFD_OK or RFD_ERR_NONFINITE (clears the flag). */
+rfd_status rfd_plan_check(rfd_plan_t plan, rfd_stream_t stream);
+
+/* Copies the plan's M (m x m, FP64, row-major) and S = lambda phi_1(lambda M)
+ * (m x m, FP64, row-major) to host arrays after synchronising `stream`; also
+ * the scaling power s used for phi_1. Any pointer may be NULL. M here is
+ * B^T A in the feature scaling c_k (the same matrix the paper's core uses). */
+rfd_status rfd_plan_core(rfd_plan_t plan, double* M_mxm, double* S_mxm, int32_t* s_out,
+                         rfd_stream_t stream);
+
+void rfd_plan_destroy(rfd_plan_t plan);
+
+/* --------------------------------------------------------------- batches */
+
+/* One item of a batch: a plan whose rfd_features has run, and its field. */
+typedef struct {
+  rfd_plan_t plan;
+  const float* F;
+  int64_t ldF;
+  int32_t d;
+  int32_t reserved;
+  float* out;
+  int64_t ldO;
+} rfd_item;
+
+/* One-shot integration of many clouds with one launch per kernel stage over
+ * a flattened (cloud, chunk) list. Every plan must share m and precision;
+ * X of item i is given in Xs[i] with Ns[i] points. Results are bitwise equal
+ * to calling rfd_integrate_oneshot per cloud (the split of each cloud into
+ * chunks depends only on its own N, m, d and precision). */
+rfd_status rfd_integrate_batch(rfd_plan_t* plans, const float* const* Xs, const int64_t* Ns,
+                               const float* const* Fs, const int64_t* ldFs, const int32_t* ds,
+                               float* const* outs, const int64_t* ldOs, int32_t n,
+                               rfd_stream_t stream);
+
+/* ---------------------------------------------------------------- server */
+
+typedef struct {
+  const float* X;     /* device, N x 3; must stay valid until rfd_wait returns */
+  int64_t N;
+  const float* F;     /* device, N x d */
+  int64_t ldF;
+  int32_t d;
+  int32_t reserved;
+  float* out;         /* device, N x d */
+  int64_t ldO;
+  rfd_params params;
+  uint64_t cloud_key; /* reuse a resident plan for the same cloud; 0 = no reuse */
+} rfd_request;
+
+typedef struct {
+  rfd_status status;
+  int32_t reserved;
+  double t_submit, t_start, t_done; /* seconds on the host steady clock */
+} rfd_result;
+
+rfd_status rfd_server_create(size_t hbm_budget_bytes, int32_t max_inflight, rfd_server_t* out);
+rfd_status rfd_submit(rfd_server_t server, const rfd_request* req, uint64_t* ticket);
+rfd_status rfd_wait(rfd_server_t server, uint64_t ticket, double timeout_s, rfd_result* res);
+void rfd_server_destroy(rfd_server_t server);
+
+const char* rfd_status_string(rfd_status s);
+
+/* --------------------------------------------------------------- profiling */
+
+/* Turns per-kernel timing on (1) or off (0) for the whole process. While on,
+ * every kernel launch of the library is bracketed by two hipEvents recorded
+ * on the stream it is launched on (a few microseconds of overhead each). */
+void rfd_profile_enable(int on);
+
+/* Synchronises the device, then writes per-kernel total milliseconds and
+ * launch counts for the first n kernel ids (either array may be NULL) and
+ * returns the number of kernel ids; reset != 0 clears the totals. */
+int32_t rfd_profile_read(double* total_ms, int64_t* counts, int32_t n, int32_t reset);
+
+/* Name of kernel id i (a static string), "?" when out of range. */
+const char* rfd_profile_kernel_name(int32_t id);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RFD_H */

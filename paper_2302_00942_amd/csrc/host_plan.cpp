@@ -1,0 +1,448 @@
+// Host side of the RFD library: parameter validation, the frequency sampler,
+// importance weights, plan buffers and the single-cloud C ABI entry points.
+//
+// Built with -ffp-contract=off so that the sampler's float64 arithmetic is
+// evaluated exactly as written (no fused multiply-adds).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "rfd_internal.h"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+// First positive root of sin(u) - u cos(u): where the 3-D ball transform first
+// changes sign. Main-lobe truncation radius = kU0 / (2 pi eps).
+constexpr double kU0 = 4.493409457909064;
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): Weyl sequence with
+// increment 0x9E3779B97F4A7C15, then the variant-13 mixer.
+struct SplitMix64 {
+  uint64_t state;
+  uint64_t next() {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+};
+
+// Standard normals by Box-Muller on 53-bit uniforms: u1 in (0, 1],
+// u2 in [0, 1); both outputs r cos(2 pi u2), r sin(2 pi u2) are used, in order.
+struct Gaussian {
+  SplitMix64 g;
+  double spare = 0.0;
+  bool has_spare = false;
+  double next() {
+    if (has_spare) {
+      has_spare = false;
+      return spare;
+    }
+    const uint64_t a = g.next(), b = g.next();
+    const double u1 = (double)((a >> 11) + 1) * (1.0 / 9007199254740992.0);
+    const double u2 = (double)(b >> 11) * (1.0 / 9007199254740992.0);
+    const double r = sqrt(-2.0 * log(u1));
+    const double t = (2.0 * kPi) * u2;
+    spare = r * sin(t);
+    has_spare = true;
+    return r * cos(t);
+  }
+};
+
+void preset(const rfd_params& p, double* sigma, double* R) {
+  if (p.sigma > 0.0 && p.radius > 0.0) {
+    *sigma = p.sigma;
+    *R = p.radius;
+    return;
+  }
+  const double r0 = kU0 / (2.0 * kPi);
+  *R = (p.shape == RFD_BALL_L2) ? (r0 / p.eps) : (0.5 / p.eps);
+  *sigma = *R / 3.0;
+}
+
+// Fourier transform of the ball indicator 1[||z|| <= eps] in R^3 under
+// f(z) = int exp(2 pi i w.z) tau(w) dw: (sin u - u cos u) / (2 pi^2 r^3),
+// u = 2 pi eps r, with its Taylor series near the origin.
+double tau_ball(double x, double y, double z, double eps) {
+  const double r = sqrt(x * x + y * y + z * z);
+  const double u = 2.0 * kPi * eps * r;
+  const double vol = 4.0 * kPi * eps * eps * eps / 3.0;
+  if (u < 1e-2) return vol * (1.0 - u * u / 10.0 + u * u * u * u / 280.0);
+  return (sin(u) - u * cos(u)) / (2.0 * kPi * kPi * r * r * r);
+}
+
+// Transform of the box prod_i 1[|z_i| <= eps]: prod_i sin(2 pi eps w_i) / (pi w_i).
+double tau_box(double x, double y, double z, double eps) {
+  auto g = [eps](double w) {
+    const double a = 2.0 * kPi * eps * w;
+    if (fabs(a) < 1e-4) return 2.0 * eps * (1.0 - a * a / 6.0);
+    return sin(a) / (kPi * w);
+  };
+  return g(x) * g(y) * g(z);
+}
+
+// P(N(0, I3) in the radius-t ball) (chi_3 CDF) or box (erf^3).
+double trunc_mass(double t, int shape) {
+  if (shape == RFD_BALL_L2) return erf(t / sqrt(2.0)) - sqrt(2.0 / kPi) * t * exp(-0.5 * t * t);
+  const double e = erf(t / sqrt(2.0));
+  return e * e * e;
+}
+
+rfd_status check_params(const rfd_params* p) {
+  if (!p) return RFD_ERR_INVALID_ARG;
+  if (p->m < 2 || p->m > rfd::kMaxM || (p->m & 1)) return RFD_ERR_INVALID_ARG;
+  if (!(p->eps > 0.0) || !isfinite(p->eps)) return RFD_ERR_INVALID_ARG;
+  if (!isfinite(p->lambda)) return RFD_ERR_INVALID_ARG;
+  if (p->shape != RFD_BALL_L2 && p->shape != RFD_BOX_LINF) return RFD_ERR_INVALID_ARG;
+  if (p->precision != RFD_FP32 && p->precision != RFD_BF16) return RFD_ERR_INVALID_ARG;
+  if (p->reserved != 0) return RFD_ERR_INVALID_ARG;
+  const bool zs = p->sigma == 0.0, zr = p->radius == 0.0;
+  if (zs != zr) return RFD_ERR_INVALID_ARG;
+  if (!zs && !(p->sigma > 0.0 && p->radius > 0.0 && isfinite(p->sigma) && isfinite(p->radius)))
+    return RFD_ERR_INVALID_ARG;
+  return RFD_OK;
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return hipSuccess;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+void free_dev(rfd::PlanDev& d) {
+  void* ptrs[] = {d.om, d.cvec, d.svec, d.X, d.Mraw, d.H0, d.S64, d.T64, d.G32, d.Gt16,
+                  d.phi_ws, d.pivots, d.sdev, d.barrier, d.flag, d.partials};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  d = rfd::PlanDev{};
+}
+
+// Frequencies (sampled from the seed, or taken from params->omega) and the
+// weights w = tau / p at the float32 frequencies.
+rfd_status sample_features(const rfd_params& prm, double sigma, double radius, std::vector<float>& omega,
+                           std::vector<double>& w) {
+  const int f = prm.m / 2;
+  omega.resize((size_t)f * 3);
+  if (prm.omega) {
+    for (int i = 0; i < 3 * f; ++i) {
+      if (!isfinite(prm.omega[i])) return RFD_ERR_INVALID_ARG;
+      omega[i] = prm.omega[i];
+    }
+  } else {
+    Gaussian g{SplitMix64{prm.seed}};
+    const double R = radius, sig = sigma;
+    int k = 0;
+    while (k < f) {
+      const double w0 = sig * g.next();
+      const double w1 = sig * g.next();
+      const double w2 = sig * g.next();
+      bool ok;
+      if (prm.shape == RFD_BALL_L2) ok = (w0 * w0 + w1 * w1) + w2 * w2 <= R * R;
+      else ok = std::max(fabs(w0), std::max(fabs(w1), fabs(w2))) <= R;
+      if (ok) {
+        omega[3 * k] = (float)w0;
+        omega[3 * k + 1] = (float)w1;
+        omega[3 * k + 2] = (float)w2;
+        ++k;
+      }
+    }
+  }
+  w.resize(f);
+  const double C = trunc_mass(radius / sigma, prm.shape);
+  const double norm = pow(2.0 * kPi * sigma * sigma, -1.5) / C;
+  for (int k = 0; k < f; ++k) {
+    const double x = omega[3 * k], y = omega[3 * k + 1], z = omega[3 * k + 2];
+    const double tau = prm.shape == RFD_BALL_L2 ? tau_ball(x, y, z, prm.eps) : tau_box(x, y, z, prm.eps);
+    const double pd = norm * exp(-(x * x + y * y + z * z) / (2.0 * sigma * sigma));
+    w[k] = tau / pd;
+  }
+  return RFD_OK;
+}
+
+#define HIPCK(x)                           \
+  do {                                     \
+    if ((x) != hipSuccess) return RFD_ERR_DEVICE; \
+  } while (0)
+
+}  // namespace
+
+// ------------------------------------------------------------------ internal helpers shared with the batch code
+namespace rfd {
+
+rfd_status ensure_partials(rfd_plan_s* p, size_t floats, hipStream_t st) {
+  if (floats <= p->dev.partials_cap) return RFD_OK;
+  if (p->dev.partials) {
+    HIPCK(hipStreamSynchronize(st));
+    HIPCK(hipFree(p->dev.partials));
+    p->dev.partials = nullptr;
+    p->dev.partials_cap = 0;
+  }
+  HIPCK(dalloc(&p->dev.partials, floats));
+  p->dev.partials_cap = floats;
+  return RFD_OK;
+}
+
+rfd_status ensure_x(rfd_plan_s* p, int64_t N, hipStream_t st) {
+  if (N <= p->dev.Xcap) return RFD_OK;
+  if (p->dev.X) {
+    HIPCK(hipStreamSynchronize(st));
+    HIPCK(hipFree(p->dev.X));
+    p->dev.X = nullptr;
+    p->dev.Xcap = 0;
+  }
+  HIPCK(dalloc(&p->dev.X, (size_t)N * 3));
+  p->dev.Xcap = N;
+  return RFD_OK;
+}
+
+// Largest channel slice of one pass: fused Gram + B^T F keeps at most two
+// channel blocks when m = 256 (register budget); otherwise four.
+int slice_width(int dev_m, bool gram) { return (gram && dev_m == 256) ? 32 : 64; }
+
+rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_t st) {
+  if (N < 0 || (N > 0 && !X)) return RFD_ERR_INVALID_ARG;
+  p->N = N;
+  if (N == 0) return RFD_OK;
+  rfd_status s = ensure_x(p, N, st);
+  if (s != RFD_OK) return s;
+  HIPCK(hipMemcpyAsync(p->dev.X, X, (size_t)N * 3 * sizeof(float), hipMemcpyDeviceToDevice, st));
+  const int M = p->dev_m;
+  s = ensure_partials(p, (size_t)bta_partials(N, M, 0, true, p->params.precision) * bta_partial_floats(M, 0, true), st);
+  if (s != RFD_OK) return s;
+  HIPCK(launch_bta(p, p->dev.X, N, nullptr, 0, 0, true, st));
+  HIPCK(launch_reduce(p, N, 0, true, st));
+  HIPCK(launch_phi1(p, st));
+  return RFD_OK;
+}
+
+rfd_status integrate_enqueue(rfd_plan_s* p, const float* F, int64_t ldF, int d, float* out, int64_t ldO,
+                             hipStream_t st, int first_channel_done) {
+  const int M = p->dev_m;
+  const int64_t N = p->N;
+  const int W = slice_width(M, false);
+  for (int c0 = first_channel_done; c0 < d; c0 += W) {
+    const int dc = std::min(W, d - c0);
+    rfd_status s = ensure_partials(p, (size_t)bta_partials(N, M, dc, false, p->params.precision) *
+                                          bta_partial_floats(M, dc, false), st);
+    if (s != RFD_OK) return s;
+    HIPCK(launch_bta(p, p->dev.X, N, F + c0, ldF, dc, false, st));
+    HIPCK(launch_reduce(p, N, dc, false, st));
+    HIPCK(launch_gcore(p, dc, st));
+    HIPCK(launch_expand(p, p->dev.X, N, F + c0, ldF, dc, out + c0, ldO, st));
+  }
+  return RFD_OK;
+}
+
+rfd_status check_field_args(int64_t N, const float* F, int64_t ldF, int d, const float* out, int64_t ldO) {
+  if (d < 0 || d > kMaxD) return RFD_ERR_INVALID_ARG;
+  if (d == 0 || N == 0) return RFD_OK;
+  if (!F || !out || ldF < d || ldO < d) return RFD_ERR_INVALID_ARG;
+  return RFD_OK;
+}
+
+}  // namespace rfd
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* rfd_status_string(rfd_status s) {
+  switch (s) {
+    case RFD_OK: return "ok";
+    case RFD_ERR_INVALID_ARG: return "invalid argument";
+    case RFD_ERR_RANGE: return "exp(lambda W) overflows float64";
+    case RFD_ERR_OUT_OF_BUDGET: return "request does not fit the HBM budget";
+    case RFD_ERR_NONFINITE: return "non-finite value in the input or the core";
+    case RFD_ERR_DEVICE: return "HIP runtime error";
+    case RFD_ERR_NOT_READY: return "not ready";
+    case RFD_ERR_SHUTDOWN: return "server shut down";
+  }
+  return "unknown status";
+}
+
+rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan) {
+  if (!out_plan) return RFD_ERR_INVALID_ARG;
+  *out_plan = nullptr;
+  rfd_status st = check_params(params);
+  if (st != RFD_OK) return st;
+  rfd_plan_s* p = new (std::nothrow) rfd_plan_s();
+  if (!p) return RFD_ERR_DEVICE;
+  p->params = *params;
+  p->m = params->m;
+  p->f = params->m / 2;
+  preset(*params, &p->sigma, &p->radius);
+  const int f = p->f;
+  st = sample_features(*params, p->sigma, p->radius, p->omega, p->w);
+  if (st != RFD_OK) {
+    delete p;
+    return st;
+  }
+  p->wsum_abs = 0.0;
+  p->any_growth = false;
+  for (int k = 0; k < f; ++k) {
+    p->wsum_abs += fabs(p->w[k]);
+    if (params->lambda * p->w[k] > 0.0) p->any_growth = true;
+  }
+  // [13/13] Pade numerator of exp: b_k = (2q-k)! q! / ((2q)! k! (q-k)!), q = 13,
+  // by the ratio b_{k+1} / b_k = (q - k) / ((2q - k)(k + 1)).
+  p->pade_b[0] = 1.0;
+  for (int k = 0; k < 13; ++k) p->pade_b[k + 1] = p->pade_b[k] * (double)(13 - k) / ((double)(26 - k) * (double)(k + 1));
+
+  const int M = params->m <= 64 ? 64 : (params->m <= 128 ? 128 : 256);
+  p->dev_m = M;
+  const int fp = M / 2;
+  (void)hipGetDevice(&p->device);
+  rfd::PlanDev& d = p->dev;
+  const size_t mm = (size_t)M * M;
+  bool ok = dalloc(&d.om, fp) == hipSuccess && dalloc(&d.cvec, M) == hipSuccess && dalloc(&d.svec, M) == hipSuccess &&
+            dalloc(&d.Mraw, mm) == hipSuccess && dalloc(&d.H0, (size_t)M * 64) == hipSuccess &&
+            dalloc(&d.S64, mm) == hipSuccess && dalloc(&d.T64, mm) == hipSuccess &&
+            dalloc(&d.G32, (size_t)M * 64) == hipSuccess && dalloc(&d.Gt16, (size_t)2 * M * 64) == hipSuccess &&
+            dalloc(&d.phi_ws, 9 * mm) == hipSuccess && dalloc(&d.pivots, M) == hipSuccess &&
+            dalloc(&d.sdev, 1) == hipSuccess && dalloc(&d.barrier, 1) == hipSuccess && dalloc(&d.flag, 1) == hipSuccess;
+  if (!ok) {
+    free_dev(d);
+    delete p;
+    return RFD_ERR_DEVICE;
+  }
+  std::vector<float4> om(fp);
+  std::vector<double> cv(M, 0.0), sv(M, 1.0);
+  for (int k = 0; k < fp; ++k) {
+    if (k < f) {
+      om[k] = make_float4(p->omega[3 * k], p->omega[3 * k + 1], p->omega[3 * k + 2], 0.f);
+      const double c = sqrt(fabs(p->w[k]) / f);
+      cv[k] = c;
+      cv[fp + k] = c;
+      sv[k] = sv[fp + k] = p->w[k] < 0.0 ? -1.0 : 1.0;
+    } else {
+      om[k] = make_float4(0.f, 0.f, 0.f, 0.f);  // padding: zero-scaled columns
+    }
+  }
+  int zero = 0;
+  ok = hipMemcpy(d.om, om.data(), sizeof(float4) * fp, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(d.cvec, cv.data(), sizeof(double) * M, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(d.svec, sv.data(), sizeof(double) * M, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(d.flag, &zero, sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(d.sdev, &zero, sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    free_dev(d);
+    delete p;
+    return RFD_ERR_DEVICE;
+  }
+  *out_plan = p;
+  return RFD_OK;
+}
+
+rfd_status rfd_params_frequencies(const rfd_params* params, float* omega_fx3, double* w_f) {
+  rfd_status st = check_params(params);
+  if (st != RFD_OK) return st;
+  double sigma, R;
+  preset(*params, &sigma, &R);
+  std::vector<float> om;
+  std::vector<double> w;
+  st = sample_features(*params, sigma, R, om, w);
+  if (st != RFD_OK) return st;
+  if (omega_fx3) memcpy(omega_fx3, om.data(), sizeof(float) * om.size());
+  if (w_f) memcpy(w_f, w.data(), sizeof(double) * w.size());
+  return RFD_OK;
+}
+
+rfd_status rfd_plan_export(rfd_plan_t p, float* omega_fx3, double* w_f) {
+  if (!p) return RFD_ERR_INVALID_ARG;
+  if (omega_fx3) memcpy(omega_fx3, p->omega.data(), sizeof(float) * p->omega.size());
+  if (w_f) memcpy(w_f, p->w.data(), sizeof(double) * p->w.size());
+  return RFD_OK;
+}
+
+rfd_status rfd_features(rfd_plan_t p, const float* X_dev, int64_t N, rfd_stream_t stream) {
+  if (!p) return RFD_ERR_INVALID_ARG;
+  return rfd::features_enqueue(p, X_dev, N, (hipStream_t)stream);
+}
+
+rfd_status rfd_integrate(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, float* out, int64_t ldO,
+                         rfd_stream_t stream) {
+  if (!p) return RFD_ERR_INVALID_ARG;
+  if (p->N < 0) return RFD_ERR_NOT_READY;
+  rfd_status s = rfd::check_field_args(p->N, F, ldF, d, out, ldO);
+  if (s != RFD_OK || d == 0 || p->N == 0) return s;
+  return rfd::integrate_enqueue(p, F, ldF, d, out, ldO, (hipStream_t)stream, 0);
+}
+
+rfd_status rfd_integrate_oneshot(rfd_plan_t p, const float* X, int64_t N, const float* F, int64_t ldF, int32_t d,
+                                 float* out, int64_t ldO, rfd_stream_t stream) {
+  if (!p) return RFD_ERR_INVALID_ARG;
+  if (N < 0 || (N > 0 && !X)) return RFD_ERR_INVALID_ARG;
+  rfd_status s = rfd::check_field_args(N, F, ldF, d, out, ldO);
+  if (s != RFD_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (d == 0 || N == 0) return rfd::features_enqueue(p, X, N, st);
+  p->N = N;
+  s = rfd::ensure_x(p, N, st);
+  if (s != RFD_OK) return s;
+  HIPCK(hipMemcpyAsync(p->dev.X, X, (size_t)N * 3 * sizeof(float), hipMemcpyDeviceToDevice, st));
+  const int M = p->dev_m;
+  const int dc = std::min(rfd::slice_width(M, true), (int)d);
+  s = rfd::ensure_partials(p, (size_t)rfd::bta_partials(N, M, dc, true, p->params.precision) *
+                                  rfd::bta_partial_floats(M, dc, true), st);
+  if (s != RFD_OK) return s;
+  HIPCK(rfd::launch_bta(p, p->dev.X, N, F, ldF, dc, true, st));
+  HIPCK(rfd::launch_reduce(p, N, dc, true, st));
+  HIPCK(rfd::launch_phi1(p, st));
+  HIPCK(rfd::launch_gcore(p, dc, st));
+  HIPCK(rfd::launch_expand(p, p->dev.X, N, F, ldF, dc, out, ldO, st));
+  return rfd::integrate_enqueue(p, F, ldF, d, out, ldO, st, dc);
+}
+
+rfd_status rfd_plan_check(rfd_plan_t p, rfd_stream_t stream) {
+  if (!p) return RFD_ERR_INVALID_ARG;
+  HIPCK(hipStreamSynchronize((hipStream_t)stream));
+  int flag = 0, zero = 0;
+  HIPCK(hipMemcpy(&flag, p->dev.flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) HIPCK(hipMemcpy(p->dev.flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+  if (flag & 1) return RFD_ERR_NONFINITE;
+  if (flag & 2) return RFD_ERR_RANGE;
+  if (flag & 4) return RFD_ERR_DEVICE;
+  return RFD_OK;
+}
+
+rfd_status rfd_plan_core(rfd_plan_t p, double* M_out, double* S_out, int32_t* s_out, rfd_stream_t stream) {
+  if (!p) return RFD_ERR_INVALID_ARG;
+  if (p->N < 0) return RFD_ERR_NOT_READY;
+  HIPCK(hipStreamSynchronize((hipStream_t)stream));
+  const int M = p->dev_m, m = p->m, f = p->f, fp = M / 2;
+  const size_t mm = (size_t)M * M;
+  std::vector<double> raw(mm), S(mm);
+  HIPCK(hipMemcpy(raw.data(), p->dev.Mraw, sizeof(double) * mm, hipMemcpyDeviceToHost));
+  HIPCK(hipMemcpy(S.data(), p->dev.S64, sizeof(double) * mm, hipMemcpyDeviceToHost));
+  int sv = 0;
+  HIPCK(hipMemcpy(&sv, p->dev.sdev, sizeof(int), hipMemcpyDeviceToHost));
+  // padded canonical index of real canonical index i: cos_k -> k, sin_k -> fp + k
+  auto pidx = [&](int i) { return i < f ? i : fp + (i - f); };
+  for (int i = 0; i < m; ++i) {
+    const int wi = i < f ? i : i - f;
+    const double ci = sqrt(fabs(p->w[wi]) / f);
+    for (int j = 0; j < m; ++j) {
+      const int wj = j < f ? j : j - f;
+      const double cj = sqrt(fabs(p->w[wj]) / f), sj = p->w[wj] < 0.0 ? -1.0 : 1.0;
+      const size_t q = (size_t)pidx(i) * M + pidx(j);
+      if (M_out) M_out[(size_t)i * m + j] = p->N == 0 ? 0.0 : ci * raw[q] * cj * sj;
+      if (S_out) S_out[(size_t)i * m + j] = S[q];
+    }
+  }
+  if (s_out) *s_out = sv;
+  return RFD_OK;
+}
+
+void rfd_plan_destroy(rfd_plan_t p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  free_dev(p->dev);
+  delete p;
+}
+
+}  // extern "C"

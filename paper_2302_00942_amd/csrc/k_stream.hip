@@ -1,0 +1,591 @@
+// Split-N streaming kernels of the RFD integrator on gfx950.
+//
+//   k_bta     one pass over a cloud: recompute the random features of a chunk
+//             of points into LDS and accumulate, on the matrix cores, the
+//             Gram B^T A (upper triangle) and/or B^T F; one FP32 partial per
+//             workgroup (Sec. 2.4: B^T A and B^T x of the GFI formula).
+//   k_reduce  fixed-order FP64 sum of the partials -> M (canonical order) and
+//             H0 (device order); flags non-finite sums.
+//   k_gcore   G' = T H0 (FP64) with T = diag(c s) S diag(c), S = lambda phi_1(lambda M).
+//   k_expand  out = F + Phi G' with the features of each point computed in
+//             registers directly in the MFMA operand layout.
+//
+// Features are never stored in HBM: both passes evaluate cos/sin of the FP32
+// phase omega_k . x (in revolutions, reduced by fract) with the hardware
+// transcendental unit. Feature columns are kept unscaled on the device; the
+// scale c_k and sign s_k live in the m x m core.
+#include "rfd_internal.h"
+
+namespace rfd {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ void phase_sincos(float4 w, float x, float y, float z, float& s, float& c) {
+  float th = fmaf(w.z, z, fmaf(w.y, y, w.x * x));
+  float t = __builtin_amdgcn_fractf(th);  // exact: th - floor(th) in [0, 1)
+  s = __builtin_amdgcn_sinf(t);           // sin(2 pi t)
+  c = __builtin_amdgcn_cosf(t);           // cos(2 pi t)
+}
+
+__device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
+  __bf16 ha = (__bf16)a, hb = (__bf16)b;  // round to nearest even
+  unsigned short ua = __builtin_bit_cast(unsigned short, ha);
+  unsigned short ub = __builtin_bit_cast(unsigned short, hb);
+  return (unsigned)ua | ((unsigned)ub << 16);
+}
+
+// Upper-triangular tile enumeration of an NB x NB grid of 32 x 32 blocks, row-major.
+__host__ __device__ constexpr int tri_count(int NB) { return NB * (NB + 1) / 2; }
+__host__ __device__ constexpr int tri_I(int NB, int t) {
+  int I = 0;
+  while (t >= NB - I) { t -= NB - I; ++I; }
+  return I;
+}
+__host__ __device__ constexpr int tri_J(int NB, int t) {
+  int I = 0;
+  while (t >= NB - I) { t -= NB - I; ++I; }
+  return I + t;
+}
+
+template <int M, int PREC>
+struct BtaShape {
+  static constexpr int NB = M / 32;                 // 32-wide feature blocks
+  static constexpr int NT = tri_count(NB);          // Gram tiles
+  static constexpr int TPW = (NT + 3) / 4;          // Gram tiles per wave
+  static constexpr int RB = M / 16;                 // 16-row blocks for B^T F
+  static constexpr int RPW = RB / 4;                // row blocks per wave
+  // LDS row pitch (elements) of the feature and field tiles: conflict-free reads
+  static constexpr int PITCH = PREC ? (kChunk + 8) : (kChunk + 1);
+  using elem = typename std::conditional<PREC != 0, __bf16, float>::type;
+};
+
+// Channel blocks of a pass over d channels: 1, 2 or 4 blocks of 16. A Gram
+// pass without a field still carries one (all-zero) block: that variant
+// keeps the register allocation of the fused kernel.
+static int dblocks(int d) {
+  if (d <= 16) return 1;
+  if (d <= 32) return 2;
+  return 4;
+}
+
+size_t bta_partial_floats(int m, int d, bool gram) {
+  int NB = m / 32;
+  size_t g = gram ? (size_t)tri_count(NB) * 1024 : 0;
+  return g + (size_t)(m / 16) * dblocks(d) * 256;
+}
+
+// Number of workgroups (= partials) of a split-N pass: a function of the
+// cloud's own size only, so a cloud gives the same bits alone or in a batch.
+int bta_partials(int64_t N, int m, int d, bool gram, int prec) {
+  int64_t chunks = (N + kChunk - 1) / kChunk;
+  int64_t target = 512;  // two workgroups per CU
+  if (chunks < target) target = chunks;
+  if (target < 1) target = 1;
+  return (int)target;
+}
+
+// ------------------------------------------------------------------ k_bta
+// Accumulators: Gram tiles acc[i] (32x32 f32: 16 regs), B^T F tiles hacc[r][cb] (16x16: 4 regs).
+template <int M, int PREC, bool GRAM, int DB, int W>
+__device__ __forceinline__ void bta_mma(const typename BtaShape<M, PREC>::elem* __restrict__ phi,
+                                        const typename BtaShape<M, PREC>::elem* __restrict__ fs,
+                                        const typename BtaShape<M, PREC>::elem* __restrict__ fsl,
+                                        f32x16 (&acc)[BtaShape<M, PREC>::TPW],
+                                        f32x4 (&hacc)[BtaShape<M, PREC>::RPW][DB > 0 ? DB : 1], int lane) {
+  using S = BtaShape<M, PREC>;
+  constexpr int P = S::PITCH;
+  if constexpr (PREC) {
+    // BF16: Gram with 32x32x16, B^T F with 16x16x32.
+    if constexpr (GRAM) {
+#pragma unroll 1
+      for (int ks = 0; ks < kChunk / 16; ++ks) {
+        bf16x8 fr[S::NB];
+#pragma unroll
+        for (int J = 0; J < S::NB; ++J)
+          fr[J] = *(const bf16x8*)(phi + (J * 32 + (lane & 31)) * P + ks * 16 + 8 * (lane >> 5));
+#pragma unroll
+        for (int i = 0; i < S::TPW; ++i) {
+          const int t = W + 4 * i;
+          if (t < S::NT) {
+            acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fr[tri_I(S::NB, t)], fr[tri_J(S::NB, t)], acc[i], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if constexpr (DB > 0) {
+#pragma unroll
+      for (int ks = 0; ks < kChunk / 32; ++ks) {
+        // F enters as a hi + lo pair of BF16 values (F = hi + lo to ~16 bits)
+        bf16x8 fb[DB], fbl[DB];
+#pragma unroll
+        for (int cb = 0; cb < DB; ++cb) {
+          fb[cb] = *(const bf16x8*)(fs + (cb * 16 + (lane & 15)) * P + ks * 32 + 8 * (lane >> 4));
+          fbl[cb] = *(const bf16x8*)(fsl + (cb * 16 + (lane & 15)) * P + ks * 32 + 8 * (lane >> 4));
+        }
+#pragma unroll
+        for (int r = 0; r < S::RPW; ++r) {
+          const int R = W + 4 * r;
+          bf16x8 fa = *(const bf16x8*)(phi + (R * 16 + (lane & 15)) * P + ks * 32 + 8 * (lane >> 4));
+#pragma unroll
+          for (int cb = 0; cb < DB; ++cb) {
+            hacc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[cb], hacc[r][cb], 0, 0, 0);
+            hacc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fbl[cb], hacc[r][cb], 0, 0, 0);
+          }
+        }
+      }
+    }
+  } else {
+    // FP32: Gram with 32x32x2, B^T F with 16x16x4.
+    if constexpr (GRAM) {
+#pragma unroll 4
+      for (int ks = 0; ks < kChunk / 2; ++ks) {
+        float fr[S::NB];
+#pragma unroll
+        for (int J = 0; J < S::NB; ++J) fr[J] = phi[(J * 32 + (lane & 31)) * P + ks * 2 + (lane >> 5)];
+#pragma unroll
+        for (int i = 0; i < S::TPW; ++i) {
+          const int t = W + 4 * i;
+          if (t < S::NT)
+            acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[tri_I(S::NB, t)], fr[tri_J(S::NB, t)], acc[i], 0, 0, 0);
+        }
+      }
+    }
+    if constexpr (DB > 0) {
+#pragma unroll 4
+      for (int ks = 0; ks < kChunk / 4; ++ks) {
+        float fb[DB];
+#pragma unroll
+        for (int cb = 0; cb < DB; ++cb) fb[cb] = fs[(cb * 16 + (lane & 15)) * P + ks * 4 + (lane >> 4)];
+#pragma unroll
+        for (int r = 0; r < S::RPW; ++r) {
+          const int R = W + 4 * r;
+          float fa = phi[(R * 16 + (lane & 15)) * P + ks * 4 + (lane >> 4)];
+#pragma unroll
+          for (int cb = 0; cb < DB; ++cb)
+            hacc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, fb[cb], hacc[r][cb], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+template <int M, int PREC, bool GRAM, int DB, int W>
+__device__ __forceinline__ void bta_store(float* __restrict__ part, f32x16 (&acc)[BtaShape<M, PREC>::TPW],
+                                          f32x4 (&hacc)[BtaShape<M, PREC>::RPW][DB > 0 ? DB : 1], int lane) {
+  using S = BtaShape<M, PREC>;
+  if constexpr (GRAM) {
+#pragma unroll
+    for (int i = 0; i < S::TPW; ++i) {
+      const int t = W + 4 * i;
+      if (t < S::NT) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) part[(size_t)t * 1024 + r * 64 + lane] = acc[i][r];
+      }
+    }
+  }
+  if constexpr (DB > 0) {
+    float* hp = part + (GRAM ? (size_t)S::NT * 1024 : 0);
+#pragma unroll
+    for (int r = 0; r < S::RPW; ++r) {
+      const int R = W + 4 * r;
+#pragma unroll
+      for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hp[((size_t)R * DB + cb) * 256 + q * 64 + lane] = hacc[r][cb][q];
+    }
+  }
+}
+
+// grid: nparts workgroups of 256 threads; workgroup b handles chunks
+// [b*nchunks/nparts, (b+1)*nchunks/nparts) and writes partial b.
+template <int M, int PREC, bool GRAM, int DB>
+__global__ __launch_bounds__(256) void k_bta(const float* __restrict__ X, int64_t N,
+                                             const float4* __restrict__ om, const float* __restrict__ F,
+                                             int64_t ldF, int d, int64_t cpw, float* __restrict__ partials,
+                                             size_t part_stride) {
+  using S = BtaShape<M, PREC>;
+  using E = typename S::elem;
+  constexpr int P = S::PITCH;
+  constexpr int FQ = M / 2;
+  constexpr int DBS = DB > 0 ? DB : 1;
+  __shared__ float4 oms[FQ];
+  __shared__ __attribute__((aligned(16))) E phi[M * P];
+  __shared__ __attribute__((aligned(16))) E fs[DBS * 16 * P];
+  __shared__ __attribute__((aligned(16))) E fsl[PREC ? DBS * 16 * P : 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k = tid; k < FQ; k += 256) oms[k] = om[k];
+
+  f32x16 acc[S::TPW];
+  f32x4 hacc[S::RPW][DBS];
+#pragma unroll
+  for (int i = 0; i < S::TPW; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+#pragma unroll
+  for (int i = 0; i < S::RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < DBS; ++c) hacc[i][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nchunks = (N + kChunk - 1) / kChunk;
+  // even split of the chunks over the grid (depends only on N and the grid size)
+  const int64_t c0 = ((int64_t)blockIdx.x * nchunks) / gridDim.x;
+  const int64_t c1 = ((int64_t)(blockIdx.x + 1) * nchunks) / gridDim.x;
+  (void)cpw;
+
+  const int pp = tid & 31;   // point pair within the chunk
+  const int kq = tid >> 5;   // frequency phase 0..7
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    const int64_t base = ch * kChunk;
+    __syncthreads();  // previous chunk's MFMA reads are done (and oms is visible)
+    // ---- features of points base+2pp, base+2pp+1 into LDS (device order rows)
+    const int64_t pa = base + 2 * pp, pb = pa + 1;
+    const bool va = pa < N, vb = pb < N;
+    float xa = 0.f, ya = 0.f, za = 0.f, xb = 0.f, yb = 0.f, zb = 0.f;
+    if (va) { xa = X[pa * 3]; ya = X[pa * 3 + 1]; za = X[pa * 3 + 2]; }
+    if (vb) { xb = X[pb * 3]; yb = X[pb * 3 + 1]; zb = X[pb * 3 + 2]; }
+#pragma unroll 2
+    for (int k = kq; k < FQ; k += 8) {
+      const float4 w = oms[k];
+      float sa, ca, sb, cb;
+      phase_sincos(w, xa, ya, za, sa, ca);
+      phase_sincos(w, xb, yb, zb, sb, cb);
+      if (!va) { sa = 0.f; ca = 0.f; }
+      if (!vb) { sb = 0.f; cb = 0.f; }
+      if constexpr (PREC) {
+        *(unsigned*)(phi + (2 * k) * P + 2 * pp) = pack_bf16x2(ca, cb);
+        *(unsigned*)(phi + (2 * k + 1) * P + 2 * pp) = pack_bf16x2(sa, sb);
+      } else {
+        phi[(2 * k) * P + 2 * pp] = ca;
+        phi[(2 * k) * P + 2 * pp + 1] = cb;
+        phi[(2 * k + 1) * P + 2 * pp] = sa;
+        phi[(2 * k + 1) * P + 2 * pp + 1] = sb;
+      }
+    }
+    // ---- field chunk, transposed to [channel][point]
+    if constexpr (DB > 0) {
+      constexpr int DC = DB * 16;
+      for (int idx = tid; idx < kChunk * DC; idx += 256) {
+        const int p = idx / DC, c = idx - p * DC;
+        const int64_t gp = base + p;
+        float v = (gp < N && c < d) ? F[gp * ldF + c] : 0.f;
+        if constexpr (PREC) {
+          const __bf16 hi = (__bf16)v;
+          fs[c * P + p] = hi;
+          fsl[c * P + p] = (__bf16)(v - (float)hi);
+        } else {
+          fs[c * P + p] = v;
+        }
+      }
+    }
+    __syncthreads();
+    switch (wave) {
+      case 0: bta_mma<M, PREC, GRAM, DB, 0>(phi, fs, fsl, acc, hacc, lane); break;
+      case 1: bta_mma<M, PREC, GRAM, DB, 1>(phi, fs, fsl, acc, hacc, lane); break;
+      case 2: bta_mma<M, PREC, GRAM, DB, 2>(phi, fs, fsl, acc, hacc, lane); break;
+      default: bta_mma<M, PREC, GRAM, DB, 3>(phi, fs, fsl, acc, hacc, lane); break;
+    }
+  }
+  float* part = partials + (size_t)blockIdx.x * part_stride;
+  switch (wave) {
+    case 0: bta_store<M, PREC, GRAM, DB, 0>(part, acc, hacc, lane); break;
+    case 1: bta_store<M, PREC, GRAM, DB, 1>(part, acc, hacc, lane); break;
+    case 2: bta_store<M, PREC, GRAM, DB, 2>(part, acc, hacc, lane); break;
+    default: bta_store<M, PREC, GRAM, DB, 3>(part, acc, hacc, lane); break;
+  }
+}
+
+// ------------------------------------------------------------------ k_reduce
+// One thread per partial element: sum over the nparts partials in order, in
+// FP64, then scatter to its matrix position.
+__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partials, size_t stride, int nparts,
+                                                int m, int d, int DB, int gram, double* __restrict__ Mraw,
+                                                double* __restrict__ H0, int* __restrict__ flag) {
+  const int NB = m / 32;
+  const size_t ng = gram ? (size_t)tri_count(NB) * 1024 : 0;
+  const size_t nh = (size_t)(m / 16) * DB * 256;
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= ng + nh) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += (double)partials[(size_t)b * stride + e];
+  if (!isfinite(s)) __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int f = m / 2;
+  if (e < ng) {
+    const int t = (int)(e >> 10), r = (int)((e >> 6) & 15), l = (int)(e & 63);
+    int I = 0, tt = t;
+    while (tt >= NB - I) { tt -= NB - I; ++I; }
+    const int J = I + tt;
+    const int row = I * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+    const int col = J * 32 + (l & 31);
+    const int ci = dev_to_canon(row, f), cj = dev_to_canon(col, f);
+    Mraw[(size_t)ci * m + cj] = s;
+    Mraw[(size_t)cj * m + ci] = s;
+  } else {
+    const size_t eh = e - ng;
+    const int tile = (int)(eh >> 8), q = (int)((eh >> 6) & 3), l = (int)(eh & 63);
+    const int R = tile / DB, cb = tile - R * DB;
+    const int row = R * 16 + 4 * (l >> 4) + q;
+    const int ch = cb * 16 + (l & 15);
+    if (ch < d) H0[(size_t)row * d + ch] = s;
+  }
+}
+
+// ------------------------------------------------------------------ k_gcore
+// G'[j][c] = sum_i T[j][i] H0[i][c] (device order), FP64; stored as FP32
+// [j][c] and as a BF16 hi + lo pair, transposed [c][j] (lo at offset 64 m).
+__global__ __launch_bounds__(256) void k_gcore(const double* __restrict__ T, const double* __restrict__ H0, int m,
+                                               int d, float* __restrict__ G32, __bf16* __restrict__ Gt16) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= m * d) return;
+  const int j = e / d, c = e - j * d;
+  double s = 0.0;
+  for (int i = 0; i < m; ++i) s += T[(size_t)j * m + i] * H0[(size_t)i * d + c];
+  const float g = (float)s;
+  const __bf16 hi = (__bf16)g;
+  G32[(size_t)j * d + c] = g;
+  Gt16[(size_t)c * m + j] = hi;                                  // hi part, d x m
+  Gt16[(size_t)kMaxDBlocks * kDBlock * m + (size_t)c * m + j] = (__bf16)(g - (float)hi);  // lo part
+}
+
+// ------------------------------------------------------------------ k_expand
+// out = F + Phi G'. Each wave owns tiles of 16 points; lane l handles point
+// l%16 and the feature group g = l/16 of every K step. Point tiles are
+// distributed round-robin over the waves of the grid.
+template <int M, int PREC, int DB>
+__global__ __launch_bounds__(256) void k_expand(const float* __restrict__ X, int64_t N,
+                                                const float4* __restrict__ om, const float* __restrict__ G32,
+                                                const __bf16* __restrict__ Gt16, int d, const float* F,
+                                                int64_t ldF, float* out, int64_t ldO) {
+  constexpr int FQ = M / 2;
+  constexpr int GP = M + 8;  // BF16 row pitch of G'^T in LDS: conflict-free 16-byte reads
+  __shared__ float4 oms[FQ];
+  __shared__ float gs[PREC ? 1 : M * DB * 16];
+  __shared__ __attribute__((aligned(16))) __bf16 gth[PREC ? DB * 16 * GP : 8];
+  __shared__ __attribute__((aligned(16))) __bf16 gtl[PREC ? DB * 16 * GP : 8];
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int k = tid; k < FQ; k += 256) oms[k] = om[k];
+  if constexpr (PREC) {
+    for (int idx = tid; idx < DB * 16 * M; idx += 256) {
+      const int c = idx / M, j = idx - c * M;
+      const bool ok = c < d;
+      gth[c * GP + j] = ok ? Gt16[(size_t)c * M + j] : (__bf16)0.f;
+      gtl[c * GP + j] = ok ? Gt16[(size_t)kMaxDBlocks * kDBlock * M + (size_t)c * M + j] : (__bf16)0.f;
+    }
+  }
+  if constexpr (!PREC) {
+    for (int idx = tid; idx < M * DB * 16; idx += 256) {
+      const int j = idx / (DB * 16), c = idx - j * (DB * 16);
+      gs[idx] = c < d ? G32[(size_t)j * d + c] : 0.f;
+    }
+  }
+  __syncthreads();
+  const int g = lane >> 4, pl = lane & 15;
+  const int64_t ntiles = (N + 15) / 16;
+  const int64_t wstride = (int64_t)gridDim.x * 4;
+
+  if constexpr (PREC) {
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + (tid >> 6); tile < ntiles; tile += wstride) {
+      const int64_t p = tile * 16 + pl;
+      float x = 0.f, y = 0.f, z = 0.f;
+      if (p < N) { x = X[p * 3]; y = X[p * 3 + 1]; z = X[p * 3 + 2]; }
+      f32x4 acc[DB];
+#pragma unroll
+      for (int cb = 0; cb < DB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < M / 32; ++s) {
+        bf16x8 a;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float sn, cs;
+          phase_sincos(oms[16 * s + 4 * g + i], x, y, z, sn, cs);
+          a[2 * i] = (__bf16)cs;
+          a[2 * i + 1] = (__bf16)sn;
+        }
+#pragma unroll
+        for (int cb = 0; cb < DB; ++cb) {
+          const int off = (cb * 16 + pl) * GP + s * 32 + 8 * g;
+          const bf16x8 bh = *(const bf16x8*)(gth + off);
+          const bf16x8 bl = *(const bf16x8*)(gtl + off);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[cb], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < DB; ++cb) {
+        const int c = cb * 16 + pl;
+        if (c < d) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t pr = tile * 16 + 4 * g + q;
+            if (pr < N) out[pr * ldO + c] = F[pr * ldF + c] + acc[cb][q];
+          }
+        }
+      }
+    }
+  } else {
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + (tid >> 6); tile < ntiles; tile += wstride) {
+      const int64_t p = tile * 16 + pl;
+      float x = 0.f, y = 0.f, z = 0.f;
+      if (p < N) { x = X[p * 3]; y = X[p * 3 + 1]; z = X[p * 3 + 2]; }
+      f32x4 acc[DB];
+#pragma unroll
+      for (int cb = 0; cb < DB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      // K steps in pairs: lane group g uses frequency k = 4t + g, cos then sin.
+#pragma unroll 4
+      for (int t = 0; t < FQ / 4; ++t) {
+        const int k = 4 * t + g;
+        float sn, cs;
+        phase_sincos(oms[k], x, y, z, sn, cs);
+#pragma unroll
+        for (int cb = 0; cb < DB; ++cb) {
+          const float b0 = gs[(2 * k) * (DB * 16) + cb * 16 + pl];
+          const float b1 = gs[(2 * k + 1) * (DB * 16) + cb * 16 + pl];
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(cs, b0, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(sn, b1, acc[cb], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < DB; ++cb) {
+        const int c = cb * 16 + pl;
+        if (c < d) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t pr = tile * 16 + 4 * g + q;
+            if (pr < N) out[pr * ldO + c] = F[pr * ldF + c] + acc[cb][q];
+          }
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_copy_rows(const float* __restrict__ src, int64_t lds, float* __restrict__ dst, int64_t ldd,
+                            int64_t rows, int cols) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows * cols) return;
+  const int64_t r = i / cols, c = i - r * cols;
+  dst[r * ldd + c] = src[r * lds + c];
+}
+
+// ------------------------------------------------------------------ launchers
+template <int M, int PREC, bool GRAM>
+static hipError_t bta_dispatch_db(int DB, dim3 grid, const float* X, int64_t N, const float4* om, const float* F,
+                                  int64_t ldF, int d, int64_t cpw, float* parts, size_t stride, hipStream_t st) {
+  switch (DB) {
+    case 1:
+      hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 1>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, cpw, parts, stride);
+      return hipGetLastError();
+    case 2:
+      hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 2>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, cpw, parts, stride);
+      return hipGetLastError();
+    case 4:
+      if constexpr (!(GRAM && M == 256)) {
+        hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 4>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, cpw, parts, stride);
+        return hipGetLastError();
+      }
+      return hipErrorInvalidValue;
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bta(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF, int d, bool gram,
+                      hipStream_t st) {
+  const int M = p->dev_m, prec = p->params.precision;
+  const int DB = dblocks(d);
+  const int nparts = bta_partials(N, M, d, gram, prec);
+  const int64_t nchunks = (N + kChunk - 1) / kChunk;
+  const int64_t cpw = (nchunks + nparts - 1) / nparts;
+  const size_t stride = bta_partial_floats(M, d, gram);
+  dim3 grid(nparts);
+  const float4* om = p->dev.om;
+  float* parts = p->dev.partials;
+  ProfileScope prof(gram ? kKGram : kKBta, st);
+#define RFD_BTA(MM, PP)                                                                                     \
+  if (M == MM && prec == PP) {                                                                              \
+    return gram ? bta_dispatch_db<MM, PP, true>(DB, grid, X, N, om, F, ldF, d, cpw, parts, stride, st)      \
+                : bta_dispatch_db<MM, PP, false>(DB, grid, X, N, om, F, ldF, d, cpw, parts, stride, st);    \
+  }
+  RFD_BTA(64, 0)
+  RFD_BTA(64, 1)
+  RFD_BTA(128, 0)
+  RFD_BTA(128, 1)
+  RFD_BTA(256, 0)
+  RFD_BTA(256, 1)
+#undef RFD_BTA
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(rfd_plan_s* p, int64_t N, int d, bool gram, hipStream_t st) {
+  const int M = p->dev_m, prec = p->params.precision;
+  const int DB = dblocks(d);
+  const int nparts = bta_partials(N, M, d, gram, prec);
+  const size_t stride = bta_partial_floats(M, d, gram);
+  const size_t total = stride;
+  dim3 grid((unsigned)((total + 255) / 256));
+  ProfileScope prof(kKReduce, st);
+  hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, p->dev.partials, stride, nparts, M, d, DB, gram ? 1 : 0,
+                     p->dev.Mraw, p->dev.H0, p->dev.flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_gcore(rfd_plan_s* p, int d, hipStream_t st) {
+  const int M = p->dev_m;
+  dim3 grid((unsigned)((M * d + 255) / 256));
+  ProfileScope prof(kKGcore, st);
+  hipLaunchKernelGGL(k_gcore, grid, dim3(256), 0, st, p->dev.T64, p->dev.H0, M, d, p->dev.G32, p->dev.Gt16);
+  return hipGetLastError();
+}
+
+template <int M, int PREC>
+static hipError_t expand_dispatch(int DB, dim3 grid, const float* X, int64_t N, const float4* om, const float* G32,
+                                  const __bf16* Gt16, int d, const float* F, int64_t ldF, float* out, int64_t ldO,
+                                  hipStream_t st) {
+  switch (DB) {
+    case 1:
+      hipLaunchKernelGGL((k_expand<M, PREC, 1>), grid, dim3(256), 0, st, X, N, om, G32, Gt16, d, F, ldF, out, ldO);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_expand<M, PREC, 2>), grid, dim3(256), 0, st, X, N, om, G32, Gt16, d, F, ldF, out, ldO);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_expand<M, PREC, 4>), grid, dim3(256), 0, st, X, N, om, G32, Gt16, d, F, ldF, out, ldO);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF, int d, float* out,
+                         int64_t ldO, hipStream_t st) {
+  const int M = p->dev_m, prec = p->params.precision;
+  const int DB = dblocks(d);
+  const int64_t ntiles = (N + 15) / 16;
+  int64_t nwg = (ntiles + 3) / 4;
+  if (nwg > 2048) nwg = 2048;
+  if (nwg < 1) nwg = 1;
+  dim3 grid((unsigned)nwg);
+  const float4* om = p->dev.om;
+  ProfileScope prof(kKExpand, st);
+#define RFD_EXP(MM, PP) \
+  if (M == MM && prec == PP) return expand_dispatch<MM, PP>(DB, grid, X, N, om, p->dev.G32, p->dev.Gt16, d, F, ldF, out, ldO, st);
+  RFD_EXP(64, 0)
+  RFD_EXP(64, 1)
+  RFD_EXP(128, 0)
+  RFD_EXP(128, 1)
+  RFD_EXP(256, 0)
+  RFD_EXP(256, 1)
+#undef RFD_EXP
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_copy_rows(const float* src, int64_t ld_src, float* dst, int64_t ld_dst, int64_t rows, int cols,
+                            hipStream_t st) {
+  const int64_t n = rows * cols;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, ld_src, dst, ld_dst, rows,
+                     cols);
+  return hipGetLastError();
+}
+
+}  // namespace rfd

@@ -1,0 +1,109 @@
+// Internal declarations of the RFD library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <vector>
+
+#include "rfd.h"
+
+namespace rfd {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kMaxM = 256;        // largest supported number of feature columns
+constexpr int kMaxD = 1024;       // largest field width per call
+constexpr int kChunk = 64;        // points per chunk of the split-N passes
+constexpr int kDBlock = 16;       // channels per MFMA block of the field
+constexpr int kMaxDBlocks = 4;    // channel blocks handled by one pass (64 channels)
+
+// Device feature order: column 2k holds cos(2 pi omega_k . x), column 2k+1
+// holds sin(2 pi omega_k . x), both unscaled. The paper's order
+// [cos_0..cos_{f-1} | sin_0..sin_{f-1}] with the scale c_k is restored at the
+// host boundary (rfd_plan_core) and folded into the m x m core T.
+__host__ __device__ inline int dev_to_canon(int j, int f) { return (j & 1) ? f + (j >> 1) : (j >> 1); }
+
+// Scratch and resident buffers of one plan.
+struct PlanDev {
+  float4* om = nullptr;       // f x float4
+  double* cvec = nullptr;     // m: c_j in canonical order
+  double* svec = nullptr;     // m: sign_j in canonical order
+  float* X = nullptr;         // copy of the cloud
+  int64_t Xcap = 0;
+  double* Mraw = nullptr;     // m x m
+  double* H0 = nullptr;       // m x 64, device order: unscaled Phi^T F of one channel slice
+  double* S64 = nullptr;      // m x m, canonical order, lambda phi_1(lambda M)
+  double* T64 = nullptr;      // m x m, device order
+  float* G32 = nullptr;       // m x 64, device order: G' = T H0 of one channel slice
+  __bf16* Gt16 = nullptr;     // 2 x 64 x m: G'^T as BF16 hi, then BF16 lo
+  double* phi_ws = nullptr;   // 9 m^2 doubles of phi_1 workspace
+  int* pivots = nullptr;      // m
+  int* sdev = nullptr;        // scaling power s
+  unsigned* barrier = nullptr;// grid barrier counter
+  int* flag = nullptr;        // non-finite flag
+  float* partials = nullptr;  // split-N partial sums
+  size_t partials_cap = 0;    // in floats
+};
+
+}  // namespace rfd
+
+struct rfd_plan_s {
+  rfd_params params{};
+  int m = 0, f = 0;
+  double sigma = 0, radius = 0;
+  std::vector<float> omega;   // f x 3
+  std::vector<double> w;      // f
+  double wsum_abs = 0;        // sum |w_k|
+  bool any_growth = false;    // lambda * w_k > 0 for some k
+  int64_t N = -1;             // cloud size after rfd_features (-1: none)
+  int dev_m = 0;              // padded feature count used on the device: 64, 128 or 256
+  double pade_b[14] = {};     // [13/13] Pade numerator coefficients of exp
+  int device = 0;
+  rfd::PlanDev dev;
+};
+
+namespace rfd {
+
+// Kernel ids of the optional per-launch timing (profile.cpp).
+enum KernelId {
+  kKGram = 0, kKBta, kKReduce, kKPhi1, kKGcore, kKExpand, kKCopy, kKPhi1Batch, kKBtaBatch, kKExpandBatch,
+  kNumKernelIds
+};
+
+// Brackets one launch with hipEvents on its stream while profiling is on.
+class ProfileScope {
+ public:
+  ProfileScope(int id, hipStream_t st);
+  ~ProfileScope();
+  ProfileScope(const ProfileScope&) = delete;
+  ProfileScope& operator=(const ProfileScope&) = delete;
+
+ private:
+  int id_;
+  hipStream_t st_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+  bool active_ = false;
+};
+const char* kernel_name(int id);
+
+// Kernels and launchers (k_stream.hip, k_phi1.hip).
+hipError_t launch_bta(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF,
+                      int d, bool gram, hipStream_t st);
+hipError_t launch_reduce(rfd_plan_s* p, int64_t N, int d, bool gram, hipStream_t st);
+hipError_t launch_phi1(rfd_plan_s* p, hipStream_t st);
+hipError_t launch_phi1_batch(rfd_plan_s** plans, int n, void* dev_args, hipStream_t st);
+size_t phi1_args_bytes();
+hipError_t launch_gcore(rfd_plan_s* p, int d, hipStream_t st);
+hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF,
+                         int d, float* out, int64_t ldO, hipStream_t st);
+hipError_t launch_copy_rows(const float* src, int64_t ld_src, float* dst, int64_t ld_dst,
+                            int64_t rows, int cols, hipStream_t st);
+int bta_partials(int64_t N, int m, int d, bool gram, int prec);  // number of workgroups / partials
+size_t bta_partial_floats(int m, int d, bool gram);              // floats per partial
+
+}  // namespace rfd

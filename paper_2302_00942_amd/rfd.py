@@ -1,0 +1,239 @@
+"""Python binding of librfd.so (the C ABI declared in include/rfd.h).
+
+Argument marshalling only: every step of the integrator runs in the HIP
+kernels of the library. torch supplies device memory and streams. Loading
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librfd.so")
+
+OK, INVALID_ARG, RANGE, OUT_OF_BUDGET, NONFINITE, DEVICE, NOT_READY, SHUTDOWN = range(8)
+BALL_L2, BOX_LINF = 0, 1
+FP32, BF16 = 0, 1
+_PREC = {"fp32": FP32, "bf16": BF16, FP32: FP32, BF16: BF16}
+_SHAPE = {"ball": BALL_L2, "box": BOX_LINF, BALL_L2: BALL_L2, BOX_LINF: BOX_LINF}
+
+
+class RfdError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class Params(C.Structure):
+    _fields_ = [("m", C.c_int32), ("shape", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32),
+                ("eps", C.c_double), ("lam", C.c_double), ("sigma", C.c_double), ("radius", C.c_double),
+                ("seed", C.c_uint64), ("omega", C.POINTER(C.c_float))]
+
+
+class Request(C.Structure):
+    _fields_ = [("X", C.c_void_p), ("N", C.c_int64), ("F", C.c_void_p), ("ldF", C.c_int64), ("d", C.c_int32),
+                ("reserved", C.c_int32), ("out", C.c_void_p), ("ldO", C.c_int64), ("params", Params),
+                ("cloud_key", C.c_uint64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded librfd.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2302_00942_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+        sigs = {
+            "rfd_status_string": ([i32], C.c_char_p),
+            "rfd_plan_create": ([C.POINTER(Params), C.POINTER(vp)], i32),
+            "rfd_params_frequencies": ([C.POINTER(Params), vp, vp], i32),
+            "rfd_plan_export": ([vp, vp, vp], i32),
+            "rfd_features": ([vp, vp, i64, vp], i32),
+            "rfd_integrate": ([vp, vp, i64, i32, vp, i64, vp], i32),
+            "rfd_integrate_oneshot": ([vp, vp, i64, vp, i64, i32, vp, i64, vp], i32),
+            "rfd_plan_check": ([vp, vp], i32),
+            "rfd_plan_core": ([vp, vp, vp, vp, vp], i32),
+            "rfd_plan_destroy": ([vp], None),
+            "rfd_integrate_batch": ([vp, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
+            "rfd_server_create": ([C.c_size_t, i32, C.POINTER(vp)], i32),
+            "rfd_submit": ([vp, C.POINTER(Request), C.POINTER(u64)], i32),
+            "rfd_wait": ([vp, u64, dbl, C.POINTER(Result)], i32),
+            "rfd_server_destroy": ([vp], None),
+            "rfd_profile_enable": ([C.c_int], None),
+            "rfd_profile_read": ([vp, vp, i32, i32], i32),
+            "rfd_profile_kernel_name": ([i32], C.c_char_p),
+        }
+        for name, (args, res) in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().rfd_status_string(int(s)).decode()
+
+
+def _check(s: int, what: str) -> None:
+    if s != OK:
+        raise RfdError(s, what)
+
+
+def make_params(m: int, eps: float, lam: float, seed: int = 0, shape="ball", precision="fp32",
+                sigma: float = 0.0, radius: float = 0.0, omega: Optional[np.ndarray] = None):
+    p = Params()
+    p.m, p.shape, p.precision, p.reserved = int(m), _SHAPE[shape], _PREC[precision], 0
+    p.eps, p.lam, p.sigma, p.radius, p.seed = float(eps), float(lam), float(sigma), float(radius), int(seed)
+    keep = None
+    if omega is not None:
+        keep = np.ascontiguousarray(omega, dtype=np.float32)
+        p.omega = keep.ctypes.data_as(C.POINTER(C.c_float))
+    else:
+        p.omega = None
+    return p, keep
+
+
+def frequencies(m: int, eps: float, seed: int = 0, shape="ball", sigma: float = 0.0, radius: float = 0.0):
+    """(omega f x 3 float32, w f float64) as the library samples them (host only)."""
+    p, _ = make_params(m, eps, 0.0, seed, shape, "fp32", sigma, radius)
+    f = m // 2
+    om = np.zeros((f, 3), dtype=np.float32)
+    w = np.zeros(f, dtype=np.float64)
+    _check(lib().rfd_params_frequencies(C.byref(p), om.ctypes.data, w.ctypes.data), "rfd_params_frequencies")
+    return om, w
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _dev_f32(t, what: str, cols: Optional[int] = None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError(f"{what} must be a float32 CUDA tensor")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{what} must be 2-D with unit column stride")
+    if cols is not None and t.shape[1] != cols:
+        raise ValueError(f"{what} must have {cols} columns")
+    return t
+
+
+class Plan:
+    """An RFD plan: frequencies, weights and (after features) the m x m core."""
+
+    def __init__(self, m: int, eps: float, lam: float, seed: int = 0, shape="ball", precision="fp32",
+                 sigma: float = 0.0, radius: float = 0.0, omega: Optional[np.ndarray] = None):
+        p, keep = make_params(m, eps, lam, seed, shape, precision, sigma, radius, omega)
+        h = C.c_void_p()
+        _check(lib().rfd_plan_create(C.byref(p), C.byref(h)), "rfd_plan_create")
+        self._h = h
+        self.m, self.eps, self.lam, self.seed = m, eps, lam, seed
+        self.precision = _PREC[precision]
+        self.N = None
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    def export(self):
+        f = self.m // 2
+        om = np.zeros((f, 3), dtype=np.float32)
+        w = np.zeros(f, dtype=np.float64)
+        _check(lib().rfd_plan_export(self._h, om.ctypes.data, w.ctypes.data), "rfd_plan_export")
+        return om, w
+
+    def features(self, X, stream=None) -> None:
+        X = _dev_f32(X, "X", 3)
+        if X.stride(0) != 3:
+            raise ValueError("X must be contiguous N x 3")
+        _check(lib().rfd_features(self._h, X.data_ptr(), X.shape[0], _stream_handle(stream)), "rfd_features")
+        self.N = X.shape[0]
+
+    def integrate(self, F, out=None, stream=None):
+        import torch
+        F = _dev_f32(F, "F")
+        if out is None:
+            out = torch.empty_like(F)
+        out = _dev_f32(out, "out", F.shape[1])
+        _check(lib().rfd_integrate(self._h, F.data_ptr(), F.stride(0), F.shape[1], out.data_ptr(), out.stride(0),
+                                   _stream_handle(stream)), "rfd_integrate")
+        return out
+
+    def oneshot(self, X, F, out=None, stream=None):
+        import torch
+        X = _dev_f32(X, "X", 3)
+        if X.stride(0) != 3:
+            raise ValueError("X must be contiguous N x 3")
+        F = _dev_f32(F, "F")
+        if F.shape[0] != X.shape[0]:
+            raise ValueError("X and F must have the same number of rows")
+        if out is None:
+            out = torch.empty_like(F)
+        out = _dev_f32(out, "out", F.shape[1])
+        _check(lib().rfd_integrate_oneshot(self._h, X.data_ptr(), X.shape[0], F.data_ptr(), F.stride(0), F.shape[1],
+                                           out.data_ptr(), out.stride(0), _stream_handle(stream)),
+               "rfd_integrate_oneshot")
+        self.N = X.shape[0]
+        return out
+
+    def check(self, stream=None) -> int:
+        """Synchronises and returns the device status code (OK, NONFINITE, RANGE, DEVICE)."""
+        return int(lib().rfd_plan_check(self._h, _stream_handle(stream)))
+
+    def core(self, stream=None):
+        """(M, S, s): M = B^T A and S = lambda phi_1(lambda M), FP64 m x m, and the scaling power."""
+        M = np.zeros((self.m, self.m))
+        S = np.zeros((self.m, self.m))
+        s = C.c_int32()
+        _check(lib().rfd_plan_core(self._h, M.ctypes.data, S.ctypes.data, C.byref(s), _stream_handle(stream)),
+               "rfd_plan_core")
+        return M, S, int(s.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().rfd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def profile_enable(on: bool) -> None:
+    lib().rfd_profile_enable(1 if on else 0)
+
+
+def profile_read(reset: bool = True) -> dict:
+    """{kernel name: (total ms, launches)} since the last reset (synchronises the device)."""
+    n = 32
+    tot = np.zeros(n)
+    cnt = np.zeros(n, dtype=np.int64)
+    k = lib().rfd_profile_read(tot.ctypes.data, cnt.ctypes.data, n, 1 if reset else 0)
+    return {lib().rfd_profile_kernel_name(i).decode(): (float(tot[i]), int(cnt[i])) for i in range(k) if cnt[i]}
+
+
+def declared_symbols(header: Optional[str] = None) -> list[str]:
+    """Function names declared in include/rfd.h."""
+    import re
+    header = header or os.path.join(os.path.dirname(_HERE), "include", "rfd.h")
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rfd_[a-z_]+)\s*\(", text)))

@@ -1,0 +1,72 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+rejects bad parameters, and its host-side sampler and weights agree with the
+oracle's independent implementation. No compute call needs a GPU here."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle import rfd_oracle as o
+from paper_2302_00942_amd import rfd
+
+
+def test_library_exports_every_declared_symbol():
+    L = rfd.lib()
+    names = rfd.declared_symbols()
+    assert "rfd_plan_create" in names and "rfd_submit" in names and len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("m,eps,seed", [(64, 0.1, 0), (256, 0.02, 0), (128, 0.05, 12345), (30, 0.01, 7)])
+def test_sampler_matches_oracle_bitwise(m, eps, seed):
+    om, w = rfd.frequencies(m, eps, seed)
+    om_ref, w_ref = o.frequencies_and_weights(m, eps, seed)
+    assert om.dtype == np.float32 and np.array_equal(om, om_ref)
+    assert np.allclose(w, w_ref, rtol=1e-12, atol=0)
+
+
+def test_box_sampler_and_weights_match_oracle():
+    om, w = rfd.frequencies(64, 0.05, 3, shape="box")
+    om_ref, w_ref = o.frequencies_and_weights(64, 0.05, 3, shape=o.BOX_LINF)
+    assert np.array_equal(om, om_ref)
+    assert np.allclose(w, w_ref, rtol=1e-12, atol=0)
+
+
+def test_custom_sigma_radius_signed_weights_match_oracle():
+    om, w = rfd.frequencies(64, 0.1, 5, sigma=10.0, radius=30.0)
+    om_ref, w_ref = o.frequencies_and_weights(64, 0.1, 5, sigma=10.0, radius=30.0)
+    assert np.array_equal(om, om_ref)
+    assert np.any(w < 0)
+    assert np.allclose(w, w_ref, rtol=1e-11, atol=1e-14 * np.abs(w_ref).max())
+
+
+@pytest.mark.parametrize("kw", [dict(m=63), dict(m=0), dict(m=258), dict(eps=0.0), dict(eps=-1.0),
+                                dict(lam=float("nan")), dict(sigma=1.0), dict(radius=2.0), dict(shape=5),
+                                dict(precision=7)])
+def test_invalid_params_are_rejected_before_any_device_work(kw):
+    base = dict(m=64, eps=0.1, lam=-0.5, seed=0, shape="ball", precision="fp32", sigma=0.0, radius=0.0)
+    base.update(kw)
+    p, _ = rfd.make_params(base["m"], base["eps"], base["lam"], base["seed"], "ball", "fp32",
+                           base["sigma"], base["radius"])
+    if "shape" in kw:
+        p.shape = kw["shape"]
+    if "precision" in kw:
+        p.precision = kw["precision"]
+    f = max(base["m"], 2) // 2 + 1
+    om = np.zeros((f, 3), dtype=np.float32)
+    w = np.zeros(f)
+    assert rfd.lib().rfd_params_frequencies(C.byref(p), om.ctypes.data, w.ctypes.data) == rfd.INVALID_ARG
+    h = C.c_void_p()
+    assert rfd.lib().rfd_plan_create(C.byref(p), C.byref(h)) == rfd.INVALID_ARG
+    assert not h.value
+
+
+def test_null_arguments():
+    L = rfd.lib()
+    assert L.rfd_plan_create(None, None) == rfd.INVALID_ARG
+    assert L.rfd_features(None, None, 0, None) == rfd.INVALID_ARG
+    assert L.rfd_integrate(None, None, 0, 0, None, 0, None) == rfd.INVALID_ARG
+    assert L.rfd_plan_check(None, None) == rfd.INVALID_ARG
+    L.rfd_plan_destroy(None)
+    assert rfd.status_string(rfd.NONFINITE).startswith("non-finite")

@@ -1,0 +1,233 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle on
+the same seeded inputs (the oracle draws its own frequencies from the same
+seed with its own sampler).
+
+Bars: FP32 relative Frobenius error <= 1e-5 on out, BF16 <= 2e-3; the
+correction term out - F is reported (and loosely bounded) because it is only
+~sqrt(m/N) of out."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import rfd_oracle as o
+from paper_2302_00942_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16": 2e-3}
+# correction-term bound (diagnostic): the correction is much smaller than out
+CORR_TOL = {"fp32": 2e-3, "bf16": 5e-2}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2302_00942_amd import rfd
+    rfd.lib()
+    return torch
+
+
+def run_oneshot(torch, X, F, eps, lam, m, seed, prec, **kw):
+    from paper_2302_00942_amd import rfd
+    plan = rfd.Plan(m, eps, lam, seed, precision=prec, **kw)
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    Fd = torch.from_numpy(np.ascontiguousarray(F)).cuda()
+    out = plan.oneshot(Xd, Fd)
+    st = plan.check()
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), plan, st
+
+
+def compare(out, ref, F, prec, label=""):
+    relf = o.relf(out, ref)
+    corr = o.relf(out - F.astype(np.float64), ref - F.astype(np.float64))
+    rms = math.sqrt(np.mean(ref ** 2)) if ref.size else 1.0
+    emax = float(np.max(np.abs(out - ref))) / rms if ref.size else 0.0
+    print(f"[{label}] {prec}: relF(out)={relf:.3e} relF(corr)={corr:.3e} max|diff|/rms={emax:.3e}")
+    assert relf <= TOL[prec], (label, relf)
+    assert emax <= 20 * TOL[prec], (label, emax)
+    assert corr <= CORR_TOL[prec], (label, corr)
+    return relf, corr
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_plain_sphere_2000(torch_cuda, prec):
+    c = wl.plain_sphere()
+    ref = o.rfd_integrate(c.X, c.F, c.eps, c.lam, c.m, c.seed)
+    out, plan, st = run_oneshot(torch_cuda, c.X, c.F, c.eps, c.lam, c.m, c.seed, prec)
+    assert st == 0
+    compare(out, ref, c.F, prec, "sphere N=2000 m=64 d=3")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("m", [64, 128, 256])
+@pytest.mark.parametrize("n,d", [(5003, 16), (4097, 3), (1000, 40), (777, 64), (300, 100)])
+def test_shapes_and_ragged_tails(torch_cuda, prec, m, n, d):
+    X = wl.torus(n, 3 + m, jitter=0.005)
+    F = wl.field(n, d, 4 + n)
+    eps, lam, seed = 0.05, -0.7, 11 + m
+    ref = o.rfd_integrate(X, F, eps, lam, m, seed)
+    out, plan, st = run_oneshot(torch_cuda, X, F, eps, lam, m, seed, prec)
+    assert st == 0
+    compare(out, ref, F, prec, f"torus N={n} m={m} d={d}")
+
+
+@pytest.mark.parametrize("m", [2, 30, 96, 130])
+def test_non_power_of_two_feature_counts(torch_cuda, m):
+    X = wl.sphere(1500, 9)
+    F = wl.field(1500, 5, 10)
+    ref = o.rfd_integrate(X, F, 0.1, -0.5, m, 3)
+    out, plan, st = run_oneshot(torch_cuda, X, F, 0.1, -0.5, m, 3, "fp32")
+    assert st == 0
+    compare(out, ref, F, "fp32", f"m={m}")
+
+
+def test_core_matches_oracle(torch_cuda):
+    c = wl.plain_sphere(n=3000, m=128, seed=5)
+    out, parts = o.rfd_integrate(c.X, c.F, c.eps, c.lam, c.m, c.seed, return_parts=True)
+    _, plan, st = run_oneshot(torch_cuda, c.X, c.F, c.eps, c.lam, c.m, c.seed, "fp32")
+    M, S, s = plan.core()
+    eM = np.linalg.norm(M - parts["M"]) / np.linalg.norm(parts["M"])
+    eS = np.linalg.norm(S - parts["S"]) / np.linalg.norm(parts["S"])
+    print(f"core: s={s} (oracle {o.scaling_power(c.lam * parts['M'])}) relF(M)={eM:.3e} relF(S)={eS:.3e}")
+    assert abs(s - o.scaling_power(c.lam * parts["M"])) <= 1
+    assert eM < 1e-5 and eS < 1e-3
+
+
+def test_box_shape_and_signed_weights(torch_cuda):
+    X = wl.ellipsoid(2500, 2)
+    F = wl.field(2500, 3, 3)
+    ref = o.rfd_integrate(X, F, 0.08, -0.4, 64, 1, shape=o.BOX_LINF)
+    out, _, st = run_oneshot(torch_cuda, X, F, 0.08, -0.4, 64, 1, "fp32", shape="box")
+    assert st == 0
+    compare(out, ref, F, "fp32", "box")
+    # signed weights (wide frequency law) with a small |lambda| so exp stays bounded
+    ref = o.rfd_integrate(X, F, 0.08, -0.002, 64, 1, sigma=1 / 0.08, radius=3 / 0.08)
+    out, _, st = run_oneshot(torch_cuda, X, F, 0.08, -0.002, 64, 1, "fp32", sigma=1 / 0.08, radius=3 / 0.08)
+    assert st == 0
+    compare(out, ref, F, "fp32", "signed")
+
+
+def test_positive_lambda(torch_cuda):
+    # growth direction (the Wasserstein experiments use lambda > 0)
+    X = wl.sphere(2000, 4)
+    F = wl.field(2000, 2, 5)
+    ref = o.rfd_integrate(X, F, 0.05, 0.02, 64, 6)
+    out, _, st = run_oneshot(torch_cuda, X, F, 0.05, 0.02, 64, 6, "fp32")
+    assert st == 0
+    compare(out, ref, F, "fp32", "lambda>0")
+
+
+def test_single_point_closed_form(torch_cuda):
+    X = np.array([[0.3, -0.2, 0.9]], dtype=np.float32)
+    F = np.array([[1.5, -2.0, 0.25, 4.0]], dtype=np.float32)
+    out, plan, st = run_oneshot(torch_cuda, X, F, 0.1, -0.5, 64, 9, "fp32")
+    om, w = plan.export()
+    ref = math.exp(-0.5 * w.sum() / 32) * F.astype(np.float64)
+    assert o.relf(out, ref) < 1e-6
+
+
+def test_identical_points_closed_form_large(torch_cuda):
+    # all points equal: W_hat = w_hat 1 1^T, out = F + 1 ((e^{lam w_hat N} - 1)/N) 1^T F;
+    # exercises every split-N workgroup of a 1M-point pass
+    n = 1_000_000
+    X = np.tile(np.array([[0.1, 0.2, -0.3]], dtype=np.float32), (n, 1))
+    F = wl.field(n, 4, 8)
+    for prec in ("fp32", "bf16"):
+        out, plan, st = run_oneshot(torch_cuda, X, F, 0.05, -0.5, 128, 4, prec)
+        om, w = plan.export()
+        what = w.sum() / 64
+        ref = F.astype(np.float64) + (math.expm1(-0.5 * what * n) / n) * F.astype(np.float64).sum(0)
+        relf = o.relf(out, ref)
+        print(f"identical points N=1e6 {prec}: relF={relf:.3e}")
+        assert relf <= TOL[prec]
+
+
+def test_lambda_zero_is_identity_bitwise(torch_cuda):
+    c = wl.plain_sphere(n=1000)
+    for prec in ("fp32", "bf16"):
+        out, _, st = run_oneshot(torch_cuda, c.X, c.F, c.eps, 0.0, c.m, c.seed, prec)
+        assert np.array_equal(out, c.F)
+
+
+def test_resident_plan_equals_oneshot_bitwise(torch_cuda):
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    c = wl.plain_sphere(n=7000, d=16, m=128, seed=2)
+    for prec in ("fp32", "bf16"):
+        a, _, _ = run_oneshot(torch, c.X, c.F, c.eps, c.lam, c.m, c.seed, prec)
+        plan = rfd.Plan(c.m, c.eps, c.lam, c.seed, precision=prec)
+        plan.features(torch.from_numpy(c.X).cuda())
+        Fd = torch.from_numpy(c.F).cuda()
+        b1 = plan.integrate(Fd).cpu().numpy()
+        b2 = plan.integrate(Fd).cpu().numpy()  # resident plan reused
+        assert np.array_equal(a, b1) and np.array_equal(b1, b2)
+
+
+def test_inplace_and_strided(torch_cuda):
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    c = wl.plain_sphere(n=3001, d=5, m=64, seed=3)
+    ref, _, _ = run_oneshot(torch, c.X, c.F, c.eps, c.lam, c.m, c.seed, "fp32")
+    plan = rfd.Plan(c.m, c.eps, c.lam, c.seed)
+    plan.features(torch.from_numpy(c.X).cuda())
+    big = torch.zeros((3001, 12), device="cuda")
+    big[:, 2:7] = torch.from_numpy(c.F).cuda()
+    Fv = big[:, 2:7]
+    plan.integrate(Fv, out=Fv)  # in place, leading dimension 12
+    got = big[:, 2:7].cpu().numpy()
+    assert np.array_equal(got, ref)
+    assert torch.count_nonzero(big[:, :2]).item() == 0 and torch.count_nonzero(big[:, 7:]).item() == 0
+
+
+def test_repeatable_run_to_run(torch_cuda):
+    c = wl.plain_sphere(n=20000, d=16, m=256, seed=4)
+    for prec in ("fp32", "bf16"):
+        a, _, _ = run_oneshot(torch_cuda, c.X, c.F, c.eps, c.lam, c.m, c.seed, prec)
+        b, _, _ = run_oneshot(torch_cuda, c.X, c.F, c.eps, c.lam, c.m, c.seed, prec)
+        assert np.array_equal(a, b)
+
+
+def test_nonfinite_input_is_reported(torch_cuda):
+    c = wl.plain_sphere(n=500)
+    F = c.F.copy()
+    F[17, 1] = np.nan
+    _, _, st = run_oneshot(torch_cuda, c.X, F, c.eps, c.lam, c.m, c.seed, "fp32")
+    from paper_2302_00942_amd import rfd
+    assert st == rfd.NONFINITE
+
+
+def test_empty_and_zero_width(torch_cuda):
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    plan = rfd.Plan(64, 0.1, -0.5, 0)
+    X = torch.zeros((0, 3), device="cuda")
+    F = torch.zeros((0, 4), device="cuda")
+    out = plan.oneshot(X, F)
+    assert out.shape == (0, 4) and plan.check() == rfd.OK
+    c = wl.plain_sphere(n=100)
+    Xd = torch.from_numpy(c.X).cuda()
+    out = plan.oneshot(Xd, torch.zeros((100, 0), device="cuda"))
+    assert out.shape == (100, 0) and plan.check() == rfd.OK
+
+
+def test_not_ready_before_features(torch_cuda):
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    plan = rfd.Plan(64, 0.1, -0.5, 0)
+    with pytest.raises(rfd.RfdError) as e:
+        plan.integrate(torch.zeros((10, 3), device="cuda"))
+    assert e.value.status == rfd.NOT_READY
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_large_torus_full_size(torch_cuda, prec):
+    """The 1M-point torus at its full size, m=256, d=16, in the benchmark's
+    launch configuration, against the full oracle."""
+    c = wl.large_torus()
+    ref = o.rfd_integrate(c.X, c.F, c.eps, c.lam, c.m, c.seed)
+    out, plan, st = run_oneshot(torch_cuda, c.X, c.F, c.eps, c.lam, c.m, c.seed, prec)
+    assert st == 0
+    compare(out, ref, c.F, prec, "torus N=1e6 m=256 d=16")
