@@ -117,7 +117,7 @@ hipError_t dalloc(T** p, size_t count) {
 
 void free_dev(rfd::PlanDev& d) {
   void* ptrs[] = {d.om, d.cvec, d.svec, d.X, d.Mraw, d.H0, d.S64, d.T64, d.G32, d.Gt16,
-                  d.phi_ws, d.pivots, d.sdev, d.barrier, d.flag, d.partials};
+                  d.phi_ws, d.pivots, d.sdev, d.barrier, d.flag, d.lvl, d.partials};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   d = rfd::PlanDev{};
@@ -303,8 +303,9 @@ rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan) {
             dalloc(&d.Mraw, mm) == hipSuccess && dalloc(&d.H0, (size_t)M * 64) == hipSuccess &&
             dalloc(&d.S64, mm) == hipSuccess && dalloc(&d.T64, mm) == hipSuccess &&
             dalloc(&d.G32, (size_t)M * 64) == hipSuccess && dalloc(&d.Gt16, (size_t)2 * M * 64) == hipSuccess &&
-            dalloc(&d.phi_ws, 9 * mm) == hipSuccess && dalloc(&d.pivots, M) == hipSuccess &&
-            dalloc(&d.sdev, 1) == hipSuccess && dalloc(&d.barrier, 1) == hipSuccess && dalloc(&d.flag, 1) == hipSuccess;
+            dalloc(&d.phi_ws, rfd::phi1_ws_doubles(M)) == hipSuccess && dalloc(&d.pivots, M) == hipSuccess &&
+            dalloc(&d.sdev, 1) == hipSuccess && dalloc(&d.barrier, rfd::kBarrierWords) == hipSuccess && dalloc(&d.flag, 1) == hipSuccess &&
+            dalloc(&d.lvl, rfd::reduce_scratch_doubles(M)) == hipSuccess;
   if (!ok) {
     free_dev(d);
     delete p;

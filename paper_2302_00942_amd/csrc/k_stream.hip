@@ -4,8 +4,8 @@
 //             of points into LDS and accumulate, on the matrix cores, the
 //             Gram B^T A (upper triangle) and/or B^T F; one FP32 partial per
 //             workgroup (Sec. 2.4: B^T A and B^T x of the GFI formula).
-//   k_reduce  fixed-order FP64 sum of the partials -> M (canonical order) and
-//             H0 (device order); flags non-finite sums.
+//   k_reduce  two-level fixed-order FP64 sum of the partials -> M (canonical
+//             order) and H0 (device order); flags non-finite sums.
 //   k_gcore   G' = T H0 (FP64) with T = diag(c s) S diag(c), S = lambda phi_1(lambda M).
 //   k_expand  out = F + Phi G' with the features of each point computed in
 //             registers directly in the MFMA operand layout.
@@ -33,24 +33,76 @@ __device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
   return (unsigned)ua | ((unsigned)ub << 16);
 }
 
-// Upper-triangular tile enumeration of an NB x NB grid of 32 x 32 blocks, row-major.
-__host__ __device__ constexpr int tri_count(int NB) { return NB * (NB + 1) / 2; }
-__host__ __device__ constexpr int tri_I(int NB, int t) {
-  int I = 0;
-  while (t >= NB - I) { t -= NB - I; ++I; }
-  return I;
+// Gram tile schedule. The NB x NB grid of 32 x 32 blocks of the symmetric
+// Gram has NB (NB + 1) / 2 distinct tiles: one per vertex (diagonal) and one
+// per edge of the complete graph on the NB feature blocks. Orienting every
+// edge towards one endpoint K groups the tiles into stars that share the MFMA
+// operand F_K; with a near-regular orientation every wave gets the same static
+// shape: segments of SEG[g] slots, slot 0 of a segment being the diagonal tile
+// (K, K) (except for NB = 2) and the other slots tiles (K, J). A tile computed as (K, J) with
+// K > J is the transpose of the upper-triangle tile; the reduction writes both
+// mirror images, so orientation does not matter there.
+//   NB = 8: circulant tournament on blocks 0..6 (i -> i+1, i+2, i+3 mod 7),
+//           7 -> 0..3, 4..6 -> 7; waves pair an out-degree-4 block with an
+//           out-degree-3 block: 9 tiles each.
+//   NB = 4: 0 -> 1, 2; 1 -> 2, 3; 2 -> 3; 3 -> 0; the shorter stars repeat
+//           their diagonal tile in the spare slot (computed, not stored).
+//   NB = 2: waves 0, 1 the diagonal tiles, wave 2 the tile (0, 1).
+template <int NB>
+struct GramSched;
+template <>
+struct GramSched<8> {
+  static constexpr int NSEG = 2, SLOTS = 9;
+  static constexpr int SEG[2] = {5, 4};
+};
+template <>
+struct GramSched<4> {
+  static constexpr int NSEG = 1, SLOTS = 3;
+  static constexpr int SEG[1] = {3};
+};
+template <>
+struct GramSched<2> {
+  static constexpr int NSEG = 1, SLOTS = 1;
+  static constexpr int SEG[1] = {1};
+};
+
+// (K, J) of slot s of wave w; returns false for a spare slot (not stored).
+__host__ __device__ inline bool gram_slot(int NB, int w, int s, int& K, int& J) {
+  if (NB == 8) {
+    if (s < 5) {
+      const int k0[4] = {7, 4, 5, 6};
+      const int j0[4][4] = {{0, 1, 2, 3}, {5, 6, 0, 7}, {6, 0, 1, 7}, {0, 1, 2, 7}};
+      K = k0[w];
+      J = s == 0 ? K : j0[w][s - 1];
+    } else {
+      K = w;
+      J = s == 5 ? w : w + (s - 5);
+    }
+    return true;
+  }
+  if (NB == 4) {
+    const int j4[4][3] = {{0, 1, 2}, {1, 2, 3}, {2, 3, -1}, {3, 0, -1}};
+    K = w;
+    J = j4[w][s];
+    if (J < 0) {
+      J = K;
+      return false;
+    }
+    return true;
+  }
+  // NB == 2
+  const int k2[4] = {0, 1, 0, 0}, jj[4] = {0, 1, 1, 0};
+  K = k2[w];
+  J = jj[w];
+  return w < 3;
 }
-__host__ __device__ constexpr int tri_J(int NB, int t) {
-  int I = 0;
-  while (t >= NB - I) { t -= NB - I; ++I; }
-  return I + t;
-}
+
+__host__ __device__ constexpr int gram_slots(int NB) { return NB == 8 ? 9 : (NB == 4 ? 3 : 1); }
 
 template <int M, int PREC>
 struct BtaShape {
   static constexpr int NB = M / 32;                 // 32-wide feature blocks
-  static constexpr int NT = tri_count(NB);          // Gram tiles
-  static constexpr int TPW = (NT + 3) / 4;          // Gram tiles per wave
+  static constexpr int SLOTS = gram_slots(NB);      // Gram tiles per wave
   static constexpr int RB = M / 16;                 // 16-row blocks for B^T F
   static constexpr int RPW = RB / 4;                // row blocks per wave
   // LDS row pitch (elements) of the feature and field tiles: conflict-free reads
@@ -68,8 +120,8 @@ static int dblocks(int d) {
 }
 
 size_t bta_partial_floats(int m, int d, bool gram) {
-  int NB = m / 32;
-  size_t g = gram ? (size_t)tri_count(NB) * 1024 : 0;
+  const int NB = m / 32;
+  const size_t g = gram ? (size_t)4 * gram_slots(NB) * 1024 : 0;
   return g + (size_t)(m / 16) * dblocks(d) * 256;
 }
 
@@ -84,114 +136,131 @@ int bta_partials(int64_t N, int m, int d, bool gram, int prec) {
 }
 
 // ------------------------------------------------------------------ k_bta
-// Accumulators: Gram tiles acc[i] (32x32 f32: 16 regs), B^T F tiles hacc[r][cb] (16x16: 4 regs).
-template <int M, int PREC, bool GRAM, int DB, int W>
+// Accumulators: Gram slots acc[s] (32x32 f32: 16 regs), B^T F tiles hacc[r][cb]
+// (16x16: 4 regs). The wave index w only selects LDS rows and partial slots.
+template <int M, int PREC, bool GRAM, int DB>
 __device__ __forceinline__ void bta_mma(const typename BtaShape<M, PREC>::elem* __restrict__ phi,
                                         const typename BtaShape<M, PREC>::elem* __restrict__ fs,
                                         const typename BtaShape<M, PREC>::elem* __restrict__ fsl,
-                                        f32x16 (&acc)[BtaShape<M, PREC>::TPW],
-                                        f32x4 (&hacc)[BtaShape<M, PREC>::RPW][DB > 0 ? DB : 1], int lane) {
+                                        f32x16 (&acc)[BtaShape<M, PREC>::SLOTS],
+                                        f32x4 (&hacc)[BtaShape<M, PREC>::RPW][DB], int lane, int w) {
   using S = BtaShape<M, PREC>;
+  using G = GramSched<S::NB>;
   constexpr int P = S::PITCH;
   if constexpr (PREC) {
     // BF16: Gram with 32x32x16, B^T F with 16x16x32.
     if constexpr (GRAM) {
 #pragma unroll 1
       for (int ks = 0; ks < kChunk / 16; ++ks) {
-        bf16x8 fr[S::NB];
+        const __bf16* base = phi + (lane & 31) * P + ks * 16 + 8 * (lane >> 5);
+        int s0 = 0;
 #pragma unroll
-        for (int J = 0; J < S::NB; ++J)
-          fr[J] = *(const bf16x8*)(phi + (J * 32 + (lane & 31)) * P + ks * 16 + 8 * (lane >> 5));
-#pragma unroll
-        for (int i = 0; i < S::TPW; ++i) {
-          const int t = W + 4 * i;
-          if (t < S::NT) {
-            acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fr[tri_I(S::NB, t)], fr[tri_J(S::NB, t)], acc[i], 0, 0, 0);
+        for (int g = 0; g < G::NSEG; ++g) {
+          int K, J;
+          gram_slot(S::NB, w, s0, K, J);
+          const bf16x8 a = *(const bf16x8*)(base + K * 32 * P);
+          if constexpr (S::NB == 2) {  // slot 0 of wave 2 is the off-diagonal tile
+            const bf16x8 b0 = *(const bf16x8*)(base + J * 32 * P);
+            acc[s0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc[s0], 0, 0, 0);
+          } else {
+            acc[s0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, a, acc[s0], 0, 0, 0);
           }
+#pragma unroll
+          for (int q = 1; q < G::SEG[g]; ++q) {
+            gram_slot(S::NB, w, s0 + q, K, J);
+            const bf16x8 bj = *(const bf16x8*)(base + J * 32 * P);
+            acc[s0 + q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bj, acc[s0 + q], 0, 0, 0);
+          }
+          s0 += G::SEG[g];
         }
       }
     }
-    if constexpr (DB > 0) {
 #pragma unroll
-      for (int ks = 0; ks < kChunk / 32; ++ks) {
-        // F enters as a hi + lo pair of BF16 values (F = hi + lo to ~16 bits)
-        bf16x8 fb[DB], fbl[DB];
+    for (int ks = 0; ks < kChunk / 32; ++ks) {
+      // F enters as a hi + lo pair of BF16 values (F = hi + lo to ~16 bits)
+      bf16x8 fb[DB], fbl[DB];
+#pragma unroll
+      for (int cb = 0; cb < DB; ++cb) {
+        fb[cb] = *(const bf16x8*)(fs + (cb * 16 + (lane & 15)) * P + ks * 32 + 8 * (lane >> 4));
+        fbl[cb] = *(const bf16x8*)(fsl + (cb * 16 + (lane & 15)) * P + ks * 32 + 8 * (lane >> 4));
+      }
+#pragma unroll
+      for (int r = 0; r < S::RPW; ++r) {
+        const int R = w + 4 * r;
+        const bf16x8 fa = *(const bf16x8*)(phi + (R * 16 + (lane & 15)) * P + ks * 32 + 8 * (lane >> 4));
 #pragma unroll
         for (int cb = 0; cb < DB; ++cb) {
-          fb[cb] = *(const bf16x8*)(fs + (cb * 16 + (lane & 15)) * P + ks * 32 + 8 * (lane >> 4));
-          fbl[cb] = *(const bf16x8*)(fsl + (cb * 16 + (lane & 15)) * P + ks * 32 + 8 * (lane >> 4));
-        }
-#pragma unroll
-        for (int r = 0; r < S::RPW; ++r) {
-          const int R = W + 4 * r;
-          bf16x8 fa = *(const bf16x8*)(phi + (R * 16 + (lane & 15)) * P + ks * 32 + 8 * (lane >> 4));
-#pragma unroll
-          for (int cb = 0; cb < DB; ++cb) {
-            hacc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[cb], hacc[r][cb], 0, 0, 0);
-            hacc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fbl[cb], hacc[r][cb], 0, 0, 0);
-          }
+          hacc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[cb], hacc[r][cb], 0, 0, 0);
+          hacc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fbl[cb], hacc[r][cb], 0, 0, 0);
         }
       }
     }
   } else {
     // FP32: Gram with 32x32x2, B^T F with 16x16x4.
     if constexpr (GRAM) {
-#pragma unroll 4
+#pragma unroll 2
       for (int ks = 0; ks < kChunk / 2; ++ks) {
-        float fr[S::NB];
+        const float* base = phi + (lane & 31) * P + ks * 2 + (lane >> 5);
+        int s0 = 0;
 #pragma unroll
-        for (int J = 0; J < S::NB; ++J) fr[J] = phi[(J * 32 + (lane & 31)) * P + ks * 2 + (lane >> 5)];
+        for (int g = 0; g < G::NSEG; ++g) {
+          int K, J;
+          gram_slot(S::NB, w, s0, K, J);
+          const float a = base[K * 32 * P];
+          if constexpr (S::NB == 2) {  // slot 0 of wave 2 is the off-diagonal tile
+            acc[s0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, base[J * 32 * P], acc[s0], 0, 0, 0);
+          } else {
+            acc[s0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, a, acc[s0], 0, 0, 0);
+          }
 #pragma unroll
-        for (int i = 0; i < S::TPW; ++i) {
-          const int t = W + 4 * i;
-          if (t < S::NT)
-            acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[tri_I(S::NB, t)], fr[tri_J(S::NB, t)], acc[i], 0, 0, 0);
+          for (int q = 1; q < G::SEG[g]; ++q) {
+            gram_slot(S::NB, w, s0 + q, K, J);
+            acc[s0 + q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, base[J * 32 * P], acc[s0 + q], 0, 0, 0);
+          }
+          s0 += G::SEG[g];
         }
       }
     }
-    if constexpr (DB > 0) {
 #pragma unroll 4
-      for (int ks = 0; ks < kChunk / 4; ++ks) {
-        float fb[DB];
+    for (int ks = 0; ks < kChunk / 4; ++ks) {
+      float fb[DB];
 #pragma unroll
-        for (int cb = 0; cb < DB; ++cb) fb[cb] = fs[(cb * 16 + (lane & 15)) * P + ks * 4 + (lane >> 4)];
+      for (int cb = 0; cb < DB; ++cb) fb[cb] = fs[(cb * 16 + (lane & 15)) * P + ks * 4 + (lane >> 4)];
 #pragma unroll
-        for (int r = 0; r < S::RPW; ++r) {
-          const int R = W + 4 * r;
-          float fa = phi[(R * 16 + (lane & 15)) * P + ks * 4 + (lane >> 4)];
+      for (int r = 0; r < S::RPW; ++r) {
+        const int R = w + 4 * r;
+        const float fa = phi[(R * 16 + (lane & 15)) * P + ks * 4 + (lane >> 4)];
 #pragma unroll
-          for (int cb = 0; cb < DB; ++cb)
-            hacc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, fb[cb], hacc[r][cb], 0, 0, 0);
-        }
+        for (int cb = 0; cb < DB; ++cb)
+          hacc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, fb[cb], hacc[r][cb], 0, 0, 0);
       }
     }
   }
 }
 
-template <int M, int PREC, bool GRAM, int DB, int W>
-__device__ __forceinline__ void bta_store(float* __restrict__ part, f32x16 (&acc)[BtaShape<M, PREC>::TPW],
-                                          f32x4 (&hacc)[BtaShape<M, PREC>::RPW][DB > 0 ? DB : 1], int lane) {
+template <int M, int PREC, bool GRAM, int DB>
+__device__ __forceinline__ void bta_store(float* __restrict__ part, f32x16 (&acc)[BtaShape<M, PREC>::SLOTS],
+                                          f32x4 (&hacc)[BtaShape<M, PREC>::RPW][DB], int lane, int w) {
   using S = BtaShape<M, PREC>;
   if constexpr (GRAM) {
 #pragma unroll
-    for (int i = 0; i < S::TPW; ++i) {
-      const int t = W + 4 * i;
-      if (t < S::NT) {
+    for (int sl = 0; sl < S::SLOTS; ++sl) {
+      int K, J;
+      if (gram_slot(S::NB, w, sl, K, J)) {
+        float* tp = part + (size_t)(w * S::SLOTS + sl) * 1024;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) part[(size_t)t * 1024 + r * 64 + lane] = acc[i][r];
+        for (int r = 0; r < 16; ++r) tp[r * 64 + lane] = acc[sl][r];
       }
     }
   }
-  if constexpr (DB > 0) {
-    float* hp = part + (GRAM ? (size_t)S::NT * 1024 : 0);
+  float* hp = part + (GRAM ? (size_t)4 * S::SLOTS * 1024 : 0);
 #pragma unroll
-    for (int r = 0; r < S::RPW; ++r) {
-      const int R = W + 4 * r;
+  for (int r = 0; r < S::RPW; ++r) {
+    const int R = w + 4 * r;
 #pragma unroll
-      for (int cb = 0; cb < DB; ++cb)
+    for (int cb = 0; cb < DB; ++cb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) hp[((size_t)R * DB + cb) * 256 + q * 64 + lane] = hacc[r][cb][q];
-    }
+      for (int q = 0; q < 4; ++q) hp[((size_t)R * DB + cb) * 256 + q * 64 + lane] = hacc[r][cb][q];
   }
 }
 
@@ -206,25 +275,25 @@ __global__ __launch_bounds__(256) void k_bta(const float* __restrict__ X, int64_
   using E = typename S::elem;
   constexpr int P = S::PITCH;
   constexpr int FQ = M / 2;
-  constexpr int DBS = DB > 0 ? DB : 1;
   __shared__ float4 oms[FQ];
   __shared__ __attribute__((aligned(16))) E phi[M * P];
-  __shared__ __attribute__((aligned(16))) E fs[DBS * 16 * P];
-  __shared__ __attribute__((aligned(16))) E fsl[PREC ? DBS * 16 * P : 1];
+  __shared__ __attribute__((aligned(16))) E fs[DB * 16 * P];
+  __shared__ __attribute__((aligned(16))) E fsl[PREC ? DB * 16 * P : 1];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int k = tid; k < FQ; k += 256) oms[k] = om[k];
 
-  f32x16 acc[S::TPW];
-  f32x4 hacc[S::RPW][DBS];
+  f32x16 acc[S::SLOTS];
+  f32x4 hacc[S::RPW][DB];
 #pragma unroll
-  for (int i = 0; i < S::TPW; ++i)
+  for (int i = 0; i < S::SLOTS; ++i)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
 #pragma unroll
   for (int i = 0; i < S::RPW; ++i)
 #pragma unroll
-    for (int c = 0; c < DBS; ++c) hacc[i][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < DB; ++c) hacc[i][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int64_t nchunks = (N + kChunk - 1) / kChunk;
   // even split of the chunks over the grid (depends only on N and the grid size)
@@ -262,7 +331,7 @@ __global__ __launch_bounds__(256) void k_bta(const float* __restrict__ X, int64_
       }
     }
     // ---- field chunk, transposed to [channel][point]
-    if constexpr (DB > 0) {
+    {
       constexpr int DC = DB * 16;
       for (int idx = tid; idx < kChunk * DC; idx += 256) {
         const int p = idx / DC, c = idx - p * DC;
@@ -278,42 +347,66 @@ __global__ __launch_bounds__(256) void k_bta(const float* __restrict__ X, int64_
       }
     }
     __syncthreads();
-    switch (wave) {
-      case 0: bta_mma<M, PREC, GRAM, DB, 0>(phi, fs, fsl, acc, hacc, lane); break;
-      case 1: bta_mma<M, PREC, GRAM, DB, 1>(phi, fs, fsl, acc, hacc, lane); break;
-      case 2: bta_mma<M, PREC, GRAM, DB, 2>(phi, fs, fsl, acc, hacc, lane); break;
-      default: bta_mma<M, PREC, GRAM, DB, 3>(phi, fs, fsl, acc, hacc, lane); break;
-    }
+    bta_mma<M, PREC, GRAM, DB>(phi, fs, fsl, acc, hacc, lane, wave);
   }
   float* part = partials + (size_t)blockIdx.x * part_stride;
-  switch (wave) {
-    case 0: bta_store<M, PREC, GRAM, DB, 0>(part, acc, hacc, lane); break;
-    case 1: bta_store<M, PREC, GRAM, DB, 1>(part, acc, hacc, lane); break;
-    case 2: bta_store<M, PREC, GRAM, DB, 2>(part, acc, hacc, lane); break;
-    default: bta_store<M, PREC, GRAM, DB, 3>(part, acc, hacc, lane); break;
-  }
+  bta_store<M, PREC, GRAM, DB>(part, acc, hacc, lane, wave);
 }
 
 // ------------------------------------------------------------------ k_reduce
-// One thread per partial element: sum over the nparts partials in order, in
-// FP64, then scatter to its matrix position.
-__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partials, size_t stride, int nparts,
-                                                int m, int d, int DB, int gram, double* __restrict__ Mraw,
-                                                double* __restrict__ H0, int* __restrict__ flag) {
-  const int NB = m / 32;
-  const size_t ng = gram ? (size_t)tri_count(NB) * 1024 : 0;
-  const size_t nh = (size_t)(m / 16) * DB * 256;
+// Two-level fixed-order FP64 sum of the partials. Level 1: thread (e, g) adds
+// the partials of group g (contiguous, increasing order) for element e.
+// Level 2: thread e adds the group sums in order and scatters the result. The
+// grouping depends only on the number of partials, i.e. on N.
+constexpr int kReduceGroups = 16;
+
+__host__ __device__ inline size_t reduce_elems(int m, int DB, bool gram) {
+  return (gram ? (size_t)4 * gram_slots(m / 32) * 1024 : 0) + (size_t)(m / 16) * DB * 256;
+}
+
+__global__ __launch_bounds__(256) void k_reduce1(const float* __restrict__ partials, size_t stride, int nparts,
+                                                 size_t E, double* __restrict__ lvl) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= ng + nh) return;
+  const int g = blockIdx.y;
+  if (e >= E) return;
+  const int b0 = (int)(((int64_t)g * nparts) / kReduceGroups);
+  const int b1 = (int)(((int64_t)(g + 1) * nparts) / kReduceGroups);
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += (double)partials[(size_t)b * stride + e];
+  int b = b0;
+  for (; b + 4 <= b1; b += 4) {
+    const float v0 = partials[(size_t)b * stride + e];
+    const float v1 = partials[(size_t)(b + 1) * stride + e];
+    const float v2 = partials[(size_t)(b + 2) * stride + e];
+    const float v3 = partials[(size_t)(b + 3) * stride + e];
+    s += (double)v0;
+    s += (double)v1;
+    s += (double)v2;
+    s += (double)v3;
+  }
+  for (; b < b1; ++b) s += (double)partials[(size_t)b * stride + e];
+  lvl[(size_t)g * E + e] = s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ lvl, size_t E, int m, int d, int DB,
+                                                 int gram, double* __restrict__ Mraw, double* __restrict__ H0,
+                                                 int* __restrict__ flag) {
+  const int NB = m / 32;
+  const int slots = gram_slots(NB);
+  const size_t ng = gram ? (size_t)4 * slots * 1024 : 0;
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= E) return;
+  int I = 0, J = 0;
+  if (e < ng) {
+    const int t = (int)(e >> 10);
+    if (!gram_slot(NB, t / slots, t % slots, I, J)) return;  // spare slot: never written
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int g = 0; g < kReduceGroups; ++g) s += lvl[(size_t)g * E + e];
   if (!isfinite(s)) __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const int f = m / 2;
   if (e < ng) {
-    const int t = (int)(e >> 10), r = (int)((e >> 6) & 15), l = (int)(e & 63);
-    int I = 0, tt = t;
-    while (tt >= NB - I) { tt -= NB - I; ++I; }
-    const int J = I + tt;
+    const int r = (int)((e >> 6) & 15), l = (int)(e & 63);
     const int row = I * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
     const int col = J * 32 + (l & 31);
     const int ci = dev_to_canon(row, f), cj = dev_to_canon(col, f);
@@ -330,20 +423,34 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
 }
 
 // ------------------------------------------------------------------ k_gcore
-// G'[j][c] = sum_i T[j][i] H0[i][c] (device order), FP64; stored as FP32
+// G'[j][c] = sum_i T[j][i] H0[i][c] (device order), FP64, one workgroup per
+// 16 rows x 16 channels with both operands staged in LDS; stored as FP32
 // [j][c] and as a BF16 hi + lo pair, transposed [c][j] (lo at offset 64 m).
 __global__ __launch_bounds__(256) void k_gcore(const double* __restrict__ T, const double* __restrict__ H0, int m,
                                                int d, float* __restrict__ G32, __bf16* __restrict__ Gt16) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= m * d) return;
-  const int j = e / d, c = e - j * d;
+  __shared__ double ts[16 * (kMaxM + 1)];
+  __shared__ double hs[kMaxM * 16];
+  const int t = threadIdx.x;
+  const int j0 = blockIdx.x * 16, c0 = blockIdx.y * 16;
+  for (int e = t; e < 16 * m; e += 256) {
+    const int r = e / m, i = e - r * m;
+    ts[r * (kMaxM + 1) + i] = T[(size_t)(j0 + r) * m + i];
+  }
+  for (int e = t; e < m * 16; e += 256) {
+    const int i = e >> 4, c = e & 15;
+    hs[e] = (c0 + c < d) ? H0[(size_t)i * d + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int r = t >> 4, c = t & 15;
   double s = 0.0;
-  for (int i = 0; i < m; ++i) s += T[(size_t)j * m + i] * H0[(size_t)i * d + c];
+  for (int i = 0; i < m; ++i) s += ts[r * (kMaxM + 1) + i] * hs[i * 16 + c];
+  const int j = j0 + r, ch = c0 + c;
+  if (ch >= d) return;
   const float g = (float)s;
   const __bf16 hi = (__bf16)g;
-  G32[(size_t)j * d + c] = g;
-  Gt16[(size_t)c * m + j] = hi;                                  // hi part, d x m
-  Gt16[(size_t)kMaxDBlocks * kDBlock * m + (size_t)c * m + j] = (__bf16)(g - (float)hi);  // lo part
+  G32[(size_t)j * d + ch] = g;
+  Gt16[(size_t)ch * m + j] = hi;                                                         // hi part, d x m
+  Gt16[(size_t)kMaxDBlocks * kDBlock * m + (size_t)ch * m + j] = (__bf16)(g - (float)hi);  // lo part
 }
 
 // ------------------------------------------------------------------ k_expand
@@ -520,17 +627,22 @@ hipError_t launch_reduce(rfd_plan_s* p, int64_t N, int d, bool gram, hipStream_t
   const int DB = dblocks(d);
   const int nparts = bta_partials(N, M, d, gram, prec);
   const size_t stride = bta_partial_floats(M, d, gram);
-  const size_t total = stride;
-  dim3 grid((unsigned)((total + 255) / 256));
+  const size_t E = reduce_elems(M, DB, gram);
   ProfileScope prof(kKReduce, st);
-  hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, p->dev.partials, stride, nparts, M, d, DB, gram ? 1 : 0,
-                     p->dev.Mraw, p->dev.H0, p->dev.flag);
+  hipLaunchKernelGGL(k_reduce1, dim3((unsigned)((E + 255) / 256), kReduceGroups), dim3(256), 0, st, p->dev.partials,
+                     stride, nparts, E, p->dev.lvl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce2, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, st, p->dev.lvl, E, M, d, DB,
+                     gram ? 1 : 0, p->dev.Mraw, p->dev.H0, p->dev.flag);
   return hipGetLastError();
 }
 
+size_t reduce_scratch_doubles(int m) { return (size_t)kReduceGroups * reduce_elems(m, kMaxDBlocks, true); }
+
 hipError_t launch_gcore(rfd_plan_s* p, int d, hipStream_t st) {
   const int M = p->dev_m;
-  dim3 grid((unsigned)((M * d + 255) / 256));
+  dim3 grid((unsigned)(M / 16), (unsigned)((d + 15) / 16));
   ProfileScope prof(kKGcore, st);
   hipLaunchKernelGGL(k_gcore, grid, dim3(256), 0, st, p->dev.T64, p->dev.H0, M, d, p->dev.G32, p->dev.Gt16);
   return hipGetLastError();

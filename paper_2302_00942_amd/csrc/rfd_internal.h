@@ -21,6 +21,7 @@ constexpr int kMaxD = 1024;       // largest field width per call
 constexpr int kChunk = 64;        // points per chunk of the split-N passes
 constexpr int kDBlock = 16;       // channels per MFMA block of the field
 constexpr int kMaxDBlocks = 4;    // channel blocks handled by one pass (64 channels)
+constexpr int kBarrierWords = 1024; // words of the grid-barrier counters of a plan
 
 // Device feature order: column 2k holds cos(2 pi omega_k . x), column 2k+1
 // holds sin(2 pi omega_k . x), both unscaled. The paper's order
@@ -41,11 +42,12 @@ struct PlanDev {
   double* T64 = nullptr;      // m x m, device order
   float* G32 = nullptr;       // m x 64, device order: G' = T H0 of one channel slice
   __bf16* Gt16 = nullptr;     // 2 x 64 x m: G'^T as BF16 hi, then BF16 lo
-  double* phi_ws = nullptr;   // 9 m^2 doubles of phi_1 workspace
+  double* phi_ws = nullptr;   // phi_1 workspace (phi1_ws_doubles)
   int* pivots = nullptr;      // m
   int* sdev = nullptr;        // scaling power s
   unsigned* barrier = nullptr;// grid barrier counter
   int* flag = nullptr;        // non-finite flag
+  double* lvl = nullptr;      // level-1 sums of the partial reduction
   float* partials = nullptr;  // split-N partial sums
   size_t partials_cap = 0;    // in floats
 };
@@ -98,6 +100,7 @@ hipError_t launch_reduce(rfd_plan_s* p, int64_t N, int d, bool gram, hipStream_t
 hipError_t launch_phi1(rfd_plan_s* p, hipStream_t st);
 hipError_t launch_phi1_batch(rfd_plan_s** plans, int n, void* dev_args, hipStream_t st);
 size_t phi1_args_bytes();
+size_t phi1_ws_doubles(int m);
 hipError_t launch_gcore(rfd_plan_s* p, int d, hipStream_t st);
 hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF,
                          int d, float* out, int64_t ldO, hipStream_t st);
@@ -105,5 +108,6 @@ hipError_t launch_copy_rows(const float* src, int64_t ld_src, float* dst, int64_
                             int64_t rows, int cols, hipStream_t st);
 int bta_partials(int64_t N, int m, int d, bool gram, int prec);  // number of workgroups / partials
 size_t bta_partial_floats(int m, int d, bool gram);              // floats per partial
+size_t reduce_scratch_doubles(int m);                            // level-1 reduction buffer
 
 }  // namespace rfd
