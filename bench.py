@@ -69,7 +69,7 @@ def read_traffic(kernel: str, workload: str):
             if line.startswith("#") or not line.strip():
                 continue
             parts = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
-            if parts.get("kernel") == kernel and parts.get("workload") == workload:
+            if parts.get("kernel") == kernel and parts.get("workload") == workload.replace(" ", "_"):
                 if parts.get("source_sha") != want:
                     return None
                 return float(parts["bytes_per_launch"])
@@ -157,7 +157,17 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (and the error check)")
     ap.add_argument("--n", type=int, default=1_000_000, help=argparse.SUPPRESS)
+    ap.add_argument("--dump-inputs", metavar="DIR", help="write the cloud for paper_2302_00942_amd/rfd_run and exit")
     args = ap.parse_args()
+    if args.dump_inputs:
+        from paper_2302_00942_amd import workloads as wl
+        c = wl.large_torus(n=args.n)
+        os.makedirs(args.dump_inputs, exist_ok=True)
+        c.X.tofile(os.path.join(args.dump_inputs, "X.bin"))
+        c.F.tofile(os.path.join(args.dump_inputs, "F.bin"))
+        with open(os.path.join(args.dump_inputs, "meta.txt"), "w") as fh:
+            fh.write(f"{c.n} {c.d} {c.m} {c.eps!r} {c.lam!r} {c.seed}\n")
+        return 0
     if args.gpus != 1:
         print("bench.py measures one MI355X: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         return 2

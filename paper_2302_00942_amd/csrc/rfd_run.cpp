@@ -1,0 +1,122 @@
+// rfd_run: native driver of the C ABI for profiling runs.
+//
+//   rfd_run DIR STEPS [PREC]
+//   rfd_run copy MIB
+//
+// DIR holds X.bin (N x 3 float32), F.bin (N x d float32) and meta.txt
+// ("N d m eps lambda seed"), as written by `bench.py --dump-inputs DIR`.
+// Runs STEPS one-shot integrations (PREC: bf16 or fp32, default bf16) on the
+// default stream and prints the average milliseconds per step. The copy form
+// runs one device-to-device copy of MIB mebibytes (a reference kernel of
+// known traffic for calibrating hardware byte counters).
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "rfd.h"
+
+static bool read_file(const std::string& path, void* dst, size_t bytes) {
+  FILE* f = fopen(path.c_str(), "rb");
+  if (!f) return false;
+  const size_t got = fread(dst, 1, bytes, f);
+  fclose(f);
+  return got == bytes;
+}
+
+static int copy_mode(long long mib) {
+  const size_t bytes = (size_t)mib << 20;
+  void *a = nullptr, *b = nullptr;
+  if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) return 1;
+  if (hipMemset(a, 1, bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return 1;
+  if (hipMemcpy(b, a, bytes, hipMemcpyDeviceToDevice) != hipSuccess) return 1;
+  printf("rfd_run copy: %zu bytes\n", bytes);
+  fflush(stdout);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  return 0;
+}
+
+int main(int argc, char** argv) {
+  if (argc == 3 && strcmp(argv[1], "copy") == 0) return copy_mode(atoll(argv[2]));
+  if (argc < 3) {
+    fprintf(stderr, "usage: %s DIR STEPS [bf16|fp32]\n", argv[0]);
+    return 2;
+  }
+  const std::string dir = argv[1];
+  const int steps = atoi(argv[2]);
+  const int prec = (argc > 3 && strcmp(argv[3], "fp32") == 0) ? RFD_FP32 : RFD_BF16;
+  long long N = 0;
+  int d = 0, m = 0;
+  double eps = 0, lam = 0;
+  unsigned long long seed = 0;
+  FILE* mf = fopen((dir + "/meta.txt").c_str(), "r");
+  if (!mf || fscanf(mf, "%lld %d %d %lf %lf %llu", &N, &d, &m, &eps, &lam, &seed) != 6) {
+    fprintf(stderr, "cannot read %s/meta.txt\n", dir.c_str());
+    return 1;
+  }
+  fclose(mf);
+  if (N <= 0 || d <= 0 || steps <= 0) {
+    fprintf(stderr, "bad sizes\n");
+    return 1;
+  }
+  std::vector<float> X((size_t)N * 3), F((size_t)N * d);
+  if (!read_file(dir + "/X.bin", X.data(), X.size() * 4) || !read_file(dir + "/F.bin", F.data(), F.size() * 4)) {
+    fprintf(stderr, "cannot read X.bin / F.bin\n");
+    return 1;
+  }
+  float *dX = nullptr, *dF = nullptr, *dO = nullptr;
+  if (hipMalloc(&dX, X.size() * 4) != hipSuccess || hipMalloc(&dF, F.size() * 4) != hipSuccess ||
+      hipMalloc(&dO, F.size() * 4) != hipSuccess) {
+    fprintf(stderr, "hipMalloc failed\n");
+    return 1;
+  }
+  if (hipMemcpy(dX, X.data(), X.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dF, F.data(), F.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    fprintf(stderr, "hipMemcpy failed\n");
+    return 1;
+  }
+  rfd_params p;
+  memset(&p, 0, sizeof(p));
+  p.m = m;
+  p.shape = RFD_BALL_L2;
+  p.precision = prec;
+  p.eps = eps;
+  p.lambda = lam;
+  p.seed = seed;
+  rfd_plan_t plan = nullptr;
+  rfd_status st = rfd_plan_create(&p, &plan);
+  if (st != RFD_OK) {
+    fprintf(stderr, "rfd_plan_create: %s\n", rfd_status_string(st));
+    return 1;
+  }
+  // one untimed step (allocations), then the timed ones
+  st = rfd_integrate_oneshot(plan, dX, N, dF, d, d, dO, d, nullptr);
+  if (st == RFD_OK) st = rfd_plan_check(plan, nullptr);
+  if (st != RFD_OK) {
+    fprintf(stderr, "warm-up step: %s\n", rfd_status_string(st));
+    return 1;
+  }
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  (void)hipEventRecord(a, nullptr);
+  for (int i = 0; i < steps && st == RFD_OK; ++i) st = rfd_integrate_oneshot(plan, dX, N, dF, d, d, dO, d, nullptr);
+  (void)hipEventRecord(b, nullptr);
+  (void)hipEventSynchronize(b);
+  if (st == RFD_OK) st = rfd_plan_check(plan, nullptr);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  fflush(stderr);
+  printf("rfd_run N=%lld d=%d m=%d prec=%s steps=%d: %.4f ms/step (%s)\n", N, d, m, prec == RFD_BF16 ? "bf16" : "fp32",
+         steps, ms / steps, rfd_status_string(st));
+  fflush(stdout);
+  rfd_plan_destroy(plan);
+  (void)hipFree(dX);
+  (void)hipFree(dF);
+  (void)hipFree(dO);
+  return st == RFD_OK ? 0 : 1;
+}
