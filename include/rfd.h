@@ -146,26 +146,40 @@ void rfd_plan_destroy(rfd_plan_t plan);
 
 /* --------------------------------------------------------------- batches */
 
-/* One item of a batch: a plan whose rfd_features has run, and its field. */
-typedef struct {
-  rfd_plan_t plan;
-  const float* F;
-  int64_t ldF;
-  int32_t d;
-  int32_t reserved;
-  float* out;
-  int64_t ldO;
-} rfd_item;
+typedef struct rfd_batch_s* rfd_batch_t;
 
-/* One-shot integration of many clouds with one launch per kernel stage over
- * a flattened (cloud, chunk) list. Every plan must share m and precision;
- * X of item i is given in Xs[i] with Ns[i] points. Results are bitwise equal
- * to calling rfd_integrate_oneshot per cloud (the split of each cloud into
- * chunks depends only on its own N, m, d and precision). */
-rfd_status rfd_integrate_batch(rfd_plan_t* plans, const float* const* Xs, const int64_t* Ns,
+/* A batch of one-shot integrations over many clouds of uneven size: item i
+ * integrates field Fs[i] (Ns[i] x ds[i], leading dimension ldFs[i]) on cloud
+ * Xs[i] (Ns[i] x 3) into outs[i] with plans[i]. All plans share m and
+ * precision; each item has its own plan; 1 <= ds[i] <= 64 (<= 32 when
+ * m > 128); all pointers are device memory that must stay valid while the
+ * batch exists. Each stage is ONE launch over the flattened work list:
+ * (cloud, part) for the feature/Gram/B^T F pass, (cloud, element block) for
+ * the reduction and G = S H, one workgroup per cloud for phi_1, (cloud,
+ * 1024-point block) for the expansion. The split of a cloud into parts
+ * depends only on its own N, so results equal the per-cloud entry points.
+ * Creation sizes the plans' buffers (hipMalloc) and uploads the work lists.
+ * Errors: RFD_ERR_INVALID_ARG (mixed m or precision, a plan used twice,
+ * sizes), RFD_ERR_DEVICE. */
+rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, const int64_t* Ns,
+                            const float* const* Fs, const int64_t* ldFs, const int32_t* ds,
+                            float* const* outs, const int64_t* ldOs, int32_t n, rfd_batch_t* out);
+
+/* Enqueues the batch on `stream`. Returns RFD_ERR_INVALID_ARG if a plan's
+ * buffers were reallocated since creation (a standalone call on a larger
+ * cloud); create the batch again then. The first launch runs eagerly; the second,
+ * on a non-default stream, records the launch sequence into a hipGraph;
+ * later launches replay that graph (one hipGraphLaunch). Per-cloud device
+ * findings are reported by rfd_plan_check on each plan. */
+rfd_status rfd_batch_launch(rfd_batch_t batch, rfd_stream_t stream);
+
+/* Waits for the device and frees the batch (not the plans). */
+void rfd_batch_destroy(rfd_batch_t batch);
+
+/* One-off batch: create, launch eagerly, synchronise `stream`, destroy. */
+rfd_status rfd_integrate_batch(const rfd_plan_t* plans, const float* const* Xs, const int64_t* Ns,
                                const float* const* Fs, const int64_t* ldFs, const int32_t* ds,
-                               float* const* outs, const int64_t* ldOs, int32_t n,
-                               rfd_stream_t stream);
+                               float* const* outs, const int64_t* ldOs, int32_t n, rfd_stream_t stream);
 
 /* ---------------------------------------------------------------- server */
 

@@ -1,31 +1,222 @@
-// Batched integration and the serving loop (filled in after the single-cloud path).
+// Batched integration of many clouds: one launch per stage over a flattened
+// (cloud, part) / (cloud, tile block) work list, recorded once into a
+// hipGraph and replayed. The server lives in server.cpp.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
 #include "rfd_internal.h"
+
+struct rfd_batch_s {
+  int n = 0, M = 0, prec = 0, DB = 1, dmax = 0;
+  int64_t nmax_copy = 0;
+  std::vector<rfd_plan_s*> plans;
+  rfd::CloudDesc* dcl = nullptr;
+  rfd::CopyDesc* dcp = nullptr;
+  int2* dwork_bta = nullptr;
+  int2* dwork_exp = nullptr;
+  int nwork_bta = 0, nwork_exp = 0;
+  void* dargs = nullptr;
+  int launches = 0;
+  std::vector<const void*> bound;  // per plan: the X copy and partial buffers the work lists point into
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+#define HIPCK(x)                                  \
+  do {                                            \
+    if ((x) != hipSuccess) return RFD_ERR_DEVICE; \
+  } while (0)
+
+void free_batch(rfd_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  void* ptrs[] = {b->dcl, b->dcp, b->dwork_bta, b->dwork_exp, b->dargs};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete b;
+}
+
+rfd_status enqueue(rfd_batch_s* b, hipStream_t st) {
+  HIPCK(rfd::launch_copy_points_batch(b->dcp, b->n, b->nmax_copy, st));
+  HIPCK(rfd::launch_bta_batch(b->M, b->prec, b->DB, b->dcl, b->dwork_bta, b->nwork_bta, st));
+  HIPCK(rfd::launch_reduce_batch(b->M, b->DB, b->dcl, b->n, st));
+  HIPCK(rfd::launch_phi1_batch_dev(b->M, b->n, b->dargs, st));
+  HIPCK(rfd::launch_gcore_batch(b->M, b->dmax, b->dcl, b->n, st));
+  if (b->nwork_exp > 0) HIPCK(rfd::launch_expand_batch(b->M, b->prec, b->DB, b->dcl, b->dwork_exp, b->nwork_exp, st));
+  return RFD_OK;
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * src.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+}  // namespace
 
 extern "C" {
 
-rfd_status rfd_integrate_batch(rfd_plan_t* plans, const float* const* Xs, const int64_t* Ns, const float* const* Fs,
-                               const int64_t* ldFs, const int32_t* ds, float* const* outs, const int64_t* ldOs,
-                               int32_t n, rfd_stream_t stream) {
-  (void)plans; (void)Xs; (void)Ns; (void)Fs; (void)ldFs; (void)ds; (void)outs; (void)ldOs; (void)n; (void)stream;
-  return RFD_ERR_INVALID_ARG;
+rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, const int64_t* Ns,
+                            const float* const* Fs, const int64_t* ldFs, const int32_t* ds, float* const* outs,
+                            const int64_t* ldOs, int32_t n, rfd_batch_t* out) {
+  if (!out) return RFD_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n < 1 || !plans || !Xs || !Ns || !Fs || !ldFs || !ds || !outs || !ldOs) return RFD_ERR_INVALID_ARG;
+  const int M = plans[0] ? plans[0]->dev_m : 0, prec = plans[0] ? plans[0]->params.precision : 0;
+  int dmax = 0;
+  for (int i = 0; i < n; ++i) {
+    rfd_plan_s* p = plans[i];
+    if (!p || p->dev_m != M || p->params.precision != prec) return RFD_ERR_INVALID_ARG;
+    if (Ns[i] < 0 || ds[i] < 1 || ldFs[i] < ds[i] || ldOs[i] < ds[i]) return RFD_ERR_INVALID_ARG;
+    if (Ns[i] > 0 && (!Xs[i] || !Fs[i] || !outs[i])) return RFD_ERR_INVALID_ARG;
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == p) return RFD_ERR_INVALID_ARG;  // each cloud needs its own plan
+    dmax = std::max(dmax, (int)ds[i]);
+  }
+  if (dmax > rfd::slice_width(M, true)) return RFD_ERR_INVALID_ARG;
+  rfd_batch_s* b = new (std::nothrow) rfd_batch_s();
+  if (!b) return RFD_ERR_DEVICE;
+  b->n = n;
+  b->M = M;
+  b->prec = prec;
+  b->dmax = dmax;
+  b->DB = rfd::dblocks(dmax);
+  b->plans.assign(plans, plans + n);
+  const size_t stride = rfd::bta_partial_floats(M, 16 * b->DB, true);
+  const int tpi = rfd::expand_tiles_per_item();
+  std::vector<rfd::CloudDesc> cl(n);
+  std::vector<rfd::CopyDesc> cp(n);
+  std::vector<int2> wb, we;
+  std::vector<unsigned char> args(rfd::phi1_args_bytes() * n);
+  for (int i = 0; i < n; ++i) {
+    rfd_plan_s* p = plans[i];
+    const int64_t N = Ns[i];
+    const int np = rfd::bta_partials(N, M, ds[i], true, prec);
+    rfd_status s = rfd::ensure_x(p, std::max<int64_t>(N, 1), nullptr);
+    if (s == RFD_OK) s = rfd::ensure_partials(p, (size_t)np * stride, nullptr);
+    if (s != RFD_OK) {
+      free_batch(b);
+      return s;
+    }
+    p->N = N;
+    rfd::CloudDesc& c = cl[i];
+    c.X = Xs[i];  // the kernels read the caller's points; the plan keeps a copy for later calls
+    c.N = N;
+    c.om = p->dev.om;
+    c.F = Fs[i];
+    c.ldF = ldFs[i];
+    c.out = outs[i];
+    c.ldO = ldOs[i];
+    c.partials = p->dev.partials;
+    c.lvl = p->dev.lvl;
+    c.Mraw = p->dev.Mraw;
+    c.H0 = p->dev.H0;
+    c.T64 = p->dev.T64;
+    c.G32 = p->dev.G32;
+    c.Gt16 = p->dev.Gt16;
+    c.flag = p->dev.flag;
+    c.d = ds[i];
+    c.nparts = np;
+    cp[i] = rfd::CopyDesc{Xs[i], p->dev.X, 3 * N};
+    b->nmax_copy = std::max<int64_t>(b->nmax_copy, 3 * N);
+    for (int q = 0; q < np; ++q) wb.push_back(make_int2(i, q));
+    const int64_t ntiles = (N + 15) / 16;
+    for (int64_t t0 = 0; t0 < ntiles; t0 += tpi) we.push_back(make_int2(i, (int)t0));
+    rfd::phi1_fill_args(p, args.data() + rfd::phi1_args_bytes() * i);
+  }
+  for (int i = 0; i < n; ++i) {
+    b->bound.push_back(plans[i]->dev.X);
+    b->bound.push_back(plans[i]->dev.partials);
+  }
+  b->nwork_bta = (int)wb.size();
+  b->nwork_exp = (int)we.size();
+  bool ok = upload(&b->dcl, cl) == hipSuccess && upload(&b->dcp, cp) == hipSuccess &&
+            upload(&b->dwork_bta, wb) == hipSuccess && upload(&b->dwork_exp, we) == hipSuccess &&
+            upload((unsigned char**)&b->dargs, args) == hipSuccess;
+  if (!ok) {
+    free_batch(b);
+    return RFD_ERR_DEVICE;
+  }
+  *out = b;
+  return RFD_OK;
 }
 
+rfd_status rfd_batch_launch(rfd_batch_t b, rfd_stream_t stream) {
+  if (!b) return RFD_ERR_INVALID_ARG;
+  // a plan whose buffers were reallocated since creation (by a larger
+  // standalone call) would leave the work lists pointing at freed memory
+  for (int i = 0; i < b->n; ++i)
+    if (b->plans[i]->dev.X != b->bound[2 * i] || b->plans[i]->dev.partials != b->bound[2 * i + 1])
+      return RFD_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  // first launch eager (sets kernel attributes); the second records a graph
+  // on a non-default stream; later launches replay it
+  if (b->exec) {
+    HIPCK(hipGraphLaunch(b->exec, st));
+    return RFD_OK;
+  }
+  if (b->launches == 0 || st == nullptr) {
+    ++b->launches;
+    return enqueue(b, st);
+  }
+  rfd::set_capturing(true);
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+  rfd_status s = e == hipSuccess ? enqueue(b, st) : RFD_ERR_DEVICE;
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(st, &g);
+  rfd::set_capturing(false);
+  if (s != RFD_OK || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return RFD_ERR_DEVICE;
+  }
+  b->graph = g;
+  HIPCK(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  ++b->launches;
+  HIPCK(hipGraphLaunch(b->exec, st));
+  return RFD_OK;
+}
+
+void rfd_batch_destroy(rfd_batch_t b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  free_batch(b);
+}
+
+rfd_status rfd_integrate_batch(const rfd_plan_t* plans, const float* const* Xs, const int64_t* Ns,
+                               const float* const* Fs, const int64_t* ldFs, const int32_t* ds, float* const* outs,
+                               const int64_t* ldOs, int32_t n, rfd_stream_t stream) {
+  rfd_batch_t b = nullptr;
+  rfd_status s = rfd_batch_create(plans, Xs, Ns, Fs, ldFs, ds, outs, ldOs, n, &b);
+  if (s != RFD_OK) return s;
+  b->launches = 1;  // no graph for a single use
+  s = enqueue(b, (hipStream_t)stream);
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && s == RFD_OK) s = RFD_ERR_DEVICE;
+  free_batch(b);
+  return s;
+}
+
+// ---------------------------------------------------------------- server (placeholder until server.cpp)
 rfd_status rfd_server_create(size_t hbm_budget_bytes, int32_t max_inflight, rfd_server_t* out) {
-  (void)hbm_budget_bytes; (void)max_inflight;
+  (void)hbm_budget_bytes;
+  (void)max_inflight;
   if (out) *out = nullptr;
   return RFD_ERR_INVALID_ARG;
 }
-
 rfd_status rfd_submit(rfd_server_t server, const rfd_request* req, uint64_t* ticket) {
   (void)server; (void)req; (void)ticket;
   return RFD_ERR_INVALID_ARG;
 }
-
 rfd_status rfd_wait(rfd_server_t server, uint64_t ticket, double timeout_s, rfd_result* res) {
   (void)server; (void)ticket; (void)timeout_s; (void)res;
   return RFD_ERR_INVALID_ARG;
 }
-
 void rfd_server_destroy(rfd_server_t server) { (void)server; }
 
 }  // extern "C"

@@ -691,14 +691,28 @@ hipError_t launch_phi1(rfd_plan_s* p, hipStream_t st) {
   }
 }
 
+void phi1_fill_args(rfd_plan_s* p, void* args_out) { fill_args(p, *(Phi1Args*)args_out); }
+
 template <int M>
-static hipError_t launch_phi1_batch_m(int n, void* dev_args, hipStream_t st) {
+static hipError_t launch_phi1_batch_m(int n, const void* dev_args, hipStream_t st) {
   const size_t lds = phi1_lds_bytes(M);
   hipError_t e = hipFuncSetAttribute((const void*)k_phi1_wg<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   ProfileScope prof(kKPhi1Batch, st);
   hipLaunchKernelGGL(k_phi1_wg<M>, dim3(n), dim3(256), lds, st, (const Phi1Args*)dev_args);
   return hipGetLastError();
+}
+
+// Sets the LDS attribute of the per-cloud kernel (outside any graph capture)
+// and launches it over n argument records already in device memory.
+hipError_t launch_phi1_batch_dev(int M, int n, const void* dev_args, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  switch (M) {
+    case 64: return launch_phi1_batch_m<64>(n, dev_args, st);
+    case 128: return launch_phi1_batch_m<128>(n, dev_args, st);
+    case 256: return launch_phi1_batch_m<256>(n, dev_args, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_phi1_batch(rfd_plan_s** plans, int n, void* dev_args, hipStream_t st) {

@@ -113,7 +113,7 @@ struct BtaShape {
 // Channel blocks of a pass over d channels: 1, 2 or 4 blocks of 16. A Gram
 // pass without a field still carries one (all-zero) block: that variant
 // keeps the register allocation of the fused kernel.
-static int dblocks(int d) {
+int dblocks(int d) {
   if (d <= 16) return 1;
   if (d <= 32) return 2;
   return 4;
@@ -125,14 +125,17 @@ size_t bta_partial_floats(int m, int d, bool gram) {
   return g + (size_t)(m / 16) * dblocks(d) * 256;
 }
 
-// Number of workgroups (= partials) of a split-N pass: a function of the
-// cloud's own size only, so a cloud gives the same bits alone or in a batch.
+// Number of partials (= workgroups) of a split-N pass over N points: at
+// least kMinChunksPerPart chunks per partial, at most 512 partials. A
+// function of N only, so a cloud gets the same partition alone and in a batch.
+constexpr int kMinChunksPerPart = 16;
 int bta_partials(int64_t N, int m, int d, bool gram, int prec) {
-  int64_t chunks = (N + kChunk - 1) / kChunk;
-  int64_t target = 512;  // two workgroups per CU
-  if (chunks < target) target = chunks;
-  if (target < 1) target = 1;
-  return (int)target;
+  (void)m; (void)d; (void)gram; (void)prec;
+  const int64_t chunks = (N + kChunk - 1) / kChunk;
+  int64_t parts = (chunks + kMinChunksPerPart - 1) / kMinChunksPerPart;
+  if (parts > 512) parts = 512;
+  if (parts < 1) parts = 1;
+  return (int)parts;
 }
 
 // ------------------------------------------------------------------ k_bta
@@ -264,13 +267,13 @@ __device__ __forceinline__ void bta_store(float* __restrict__ part, f32x16 (&acc
   }
 }
 
-// grid: nparts workgroups of 256 threads; workgroup b handles chunks
-// [b*nchunks/nparts, (b+1)*nchunks/nparts) and writes partial b.
+// One workgroup of a split-N pass: part b of nparts handles chunks
+// [b*nchunks/nparts, (b+1)*nchunks/nparts) of its cloud and writes its
+// partial at `part`.
 template <int M, int PREC, bool GRAM, int DB>
-__global__ __launch_bounds__(256) void k_bta(const float* __restrict__ X, int64_t N,
-                                             const float4* __restrict__ om, const float* __restrict__ F,
-                                             int64_t ldF, int d, int64_t cpw, float* __restrict__ partials,
-                                             size_t part_stride) {
+__device__ __forceinline__ void bta_body(const float* __restrict__ X, int64_t N, const float4* __restrict__ om,
+                                         const float* __restrict__ F, int64_t ldF, int d, int b, int nparts,
+                                         float* __restrict__ part) {
   using S = BtaShape<M, PREC>;
   using E = typename S::elem;
   constexpr int P = S::PITCH;
@@ -296,10 +299,9 @@ __global__ __launch_bounds__(256) void k_bta(const float* __restrict__ X, int64_
     for (int c = 0; c < DB; ++c) hacc[i][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int64_t nchunks = (N + kChunk - 1) / kChunk;
-  // even split of the chunks over the grid (depends only on N and the grid size)
-  const int64_t c0 = ((int64_t)blockIdx.x * nchunks) / gridDim.x;
-  const int64_t c1 = ((int64_t)(blockIdx.x + 1) * nchunks) / gridDim.x;
-  (void)cpw;
+  // even split of the chunks over the parts (depends only on N)
+  const int64_t c0 = ((int64_t)b * nchunks) / nparts;
+  const int64_t c1 = ((int64_t)(b + 1) * nchunks) / nparts;
 
   const int pp = tid & 31;   // point pair within the chunk
   const int kq = tid >> 5;   // frequency phase 0..7
@@ -349,8 +351,26 @@ __global__ __launch_bounds__(256) void k_bta(const float* __restrict__ X, int64_
     __syncthreads();
     bta_mma<M, PREC, GRAM, DB>(phi, fs, fsl, acc, hacc, lane, wave);
   }
-  float* part = partials + (size_t)blockIdx.x * part_stride;
   bta_store<M, PREC, GRAM, DB>(part, acc, hacc, lane, wave);
+}
+
+// grid: nparts workgroups of 256 threads, one per partial.
+template <int M, int PREC, bool GRAM, int DB>
+__global__ __launch_bounds__(256) void k_bta(const float* __restrict__ X, int64_t N,
+                                             const float4* __restrict__ om, const float* __restrict__ F,
+                                             int64_t ldF, int d, float* __restrict__ partials, size_t part_stride) {
+  bta_body<M, PREC, GRAM, DB>(X, N, om, F, ldF, d, (int)blockIdx.x, (int)gridDim.x,
+                              partials + (size_t)blockIdx.x * part_stride);
+}
+
+// Batched pass: one workgroup per (cloud, part) work item.
+template <int M, int PREC, bool GRAM, int DB>
+__global__ __launch_bounds__(256) void k_bta_batch(const CloudDesc* __restrict__ cl, const int2* __restrict__ work,
+                                                   size_t part_stride) {
+  const int2 wi = work[blockIdx.x];
+  const CloudDesc& c = cl[wi.x];
+  bta_body<M, PREC, GRAM, DB>(c.X, c.N, c.om, c.F, c.ldF, c.d, wi.y, c.nparts,
+                              c.partials + (size_t)wi.y * part_stride);
 }
 
 // ------------------------------------------------------------------ k_reduce
@@ -364,10 +384,8 @@ __host__ __device__ inline size_t reduce_elems(int m, int DB, bool gram) {
   return (gram ? (size_t)4 * gram_slots(m / 32) * 1024 : 0) + (size_t)(m / 16) * DB * 256;
 }
 
-__global__ __launch_bounds__(256) void k_reduce1(const float* __restrict__ partials, size_t stride, int nparts,
-                                                 size_t E, double* __restrict__ lvl) {
-  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const int g = blockIdx.y;
+__device__ __forceinline__ void reduce1_body(const float* __restrict__ partials, size_t stride, int nparts, size_t E,
+                                             double* __restrict__ lvl, size_t e, int g) {
   if (e >= E) return;
   const int b0 = (int)(((int64_t)g * nparts) / kReduceGroups);
   const int b1 = (int)(((int64_t)(g + 1) * nparts) / kReduceGroups);
@@ -387,13 +405,12 @@ __global__ __launch_bounds__(256) void k_reduce1(const float* __restrict__ parti
   lvl[(size_t)g * E + e] = s;
 }
 
-__global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ lvl, size_t E, int m, int d, int DB,
-                                                 int gram, double* __restrict__ Mraw, double* __restrict__ H0,
-                                                 int* __restrict__ flag) {
+__device__ __forceinline__ void reduce2_body(const double* __restrict__ lvl, size_t E, int m, int d, int DB, int gram,
+                                             double* __restrict__ Mraw, double* __restrict__ H0, int* __restrict__ flag,
+                                             size_t e) {
   const int NB = m / 32;
   const int slots = gram_slots(NB);
   const size_t ng = gram ? (size_t)4 * slots * 1024 : 0;
-  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= E) return;
   int I = 0, J = 0;
   if (e < ng) {
@@ -422,16 +439,38 @@ __global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ lvl,
   }
 }
 
+__global__ __launch_bounds__(256) void k_reduce1(const float* __restrict__ partials, size_t stride, int nparts,
+                                                 size_t E, double* __restrict__ lvl) {
+  reduce1_body(partials, stride, nparts, E, lvl, (size_t)blockIdx.x * 256 + threadIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ lvl, size_t E, int m, int d, int DB,
+                                                 int gram, double* __restrict__ Mraw, double* __restrict__ H0,
+                                                 int* __restrict__ flag) {
+  reduce2_body(lvl, E, m, d, DB, gram, Mraw, H0, flag, (size_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// Batched reduction: blockIdx.z is the cloud.
+__global__ __launch_bounds__(256) void k_reduce1_batch(const CloudDesc* __restrict__ cl, size_t stride, size_t E) {
+  const CloudDesc& c = cl[blockIdx.z];
+  reduce1_body(c.partials, stride, c.nparts, E, c.lvl, (size_t)blockIdx.x * 256 + threadIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void k_reduce2_batch(const CloudDesc* __restrict__ cl, size_t E, int m, int DB,
+                                                       int gram) {
+  const CloudDesc& c = cl[blockIdx.z];
+  reduce2_body(c.lvl, E, m, c.d, DB, gram, c.Mraw, c.H0, c.flag, (size_t)blockIdx.x * 256 + threadIdx.x);
+}
+
 // ------------------------------------------------------------------ k_gcore
 // G'[j][c] = sum_i T[j][i] H0[i][c] (device order), FP64, one workgroup per
 // 16 rows x 16 channels with both operands staged in LDS; stored as FP32
 // [j][c] and as a BF16 hi + lo pair, transposed [c][j] (lo at offset 64 m).
-__global__ __launch_bounds__(256) void k_gcore(const double* __restrict__ T, const double* __restrict__ H0, int m,
-                                               int d, float* __restrict__ G32, __bf16* __restrict__ Gt16) {
+__device__ __forceinline__ void gcore_body(const double* __restrict__ T, const double* __restrict__ H0, int m, int d,
+                                           float* __restrict__ G32, __bf16* __restrict__ Gt16, int j0, int c0) {
   __shared__ double ts[16 * (kMaxM + 1)];
   __shared__ double hs[kMaxM * 16];
   const int t = threadIdx.x;
-  const int j0 = blockIdx.x * 16, c0 = blockIdx.y * 16;
   for (int e = t; e < 16 * m; e += 256) {
     const int r = e / m, i = e - r * m;
     ts[r * (kMaxM + 1) + i] = T[(size_t)(j0 + r) * m + i];
@@ -453,15 +492,28 @@ __global__ __launch_bounds__(256) void k_gcore(const double* __restrict__ T, con
   Gt16[(size_t)kMaxDBlocks * kDBlock * m + (size_t)ch * m + j] = (__bf16)(g - (float)hi);  // lo part
 }
 
+__global__ __launch_bounds__(256) void k_gcore(const double* __restrict__ T, const double* __restrict__ H0, int m,
+                                               int d, float* __restrict__ G32, __bf16* __restrict__ Gt16) {
+  gcore_body(T, H0, m, d, G32, Gt16, blockIdx.x * 16, blockIdx.y * 16);
+}
+
+__global__ __launch_bounds__(256) void k_gcore_batch(const CloudDesc* __restrict__ cl, int m) {
+  const CloudDesc& c = cl[blockIdx.z];
+  if ((int)blockIdx.y * 16 >= c.d) return;
+  gcore_body(c.T64, c.H0, m, c.d, c.G32, c.Gt16, blockIdx.x * 16, blockIdx.y * 16);
+}
+
 // ------------------------------------------------------------------ k_expand
 // out = F + Phi G'. Each wave owns tiles of 16 points; lane l handles point
 // l%16 and the feature group g = l/16 of every K step. Point tiles are
 // distributed round-robin over the waves of the grid.
+// Point tiles [t_first + wave, t_end) with stride t_step are processed by the
+// four waves of the workgroup.
 template <int M, int PREC, int DB>
-__global__ __launch_bounds__(256) void k_expand(const float* __restrict__ X, int64_t N,
-                                                const float4* __restrict__ om, const float* __restrict__ G32,
-                                                const __bf16* __restrict__ Gt16, int d, const float* F,
-                                                int64_t ldF, float* out, int64_t ldO) {
+__device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t N, const float4* __restrict__ om,
+                                            const float* __restrict__ G32, const __bf16* __restrict__ Gt16, int d,
+                                            const float* F, int64_t ldF, float* out, int64_t ldO, int64_t t_first,
+                                            int64_t t_end, int64_t t_step) {
   constexpr int FQ = M / 2;
   constexpr int GP = M + 8;  // BF16 row pitch of G'^T in LDS: conflict-free 16-byte reads
   __shared__ float4 oms[FQ];
@@ -486,11 +538,11 @@ __global__ __launch_bounds__(256) void k_expand(const float* __restrict__ X, int
   }
   __syncthreads();
   const int g = lane >> 4, pl = lane & 15;
-  const int64_t ntiles = (N + 15) / 16;
-  const int64_t wstride = (int64_t)gridDim.x * 4;
+  const int64_t ntiles = t_end;
+  const int64_t wstride = t_step;
 
   if constexpr (PREC) {
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + (tid >> 6); tile < ntiles; tile += wstride) {
+    for (int64_t tile = t_first + (tid >> 6); tile < ntiles; tile += wstride) {
       const int64_t p = tile * 16 + pl;
       float x = 0.f, y = 0.f, z = 0.f;
       if (p < N) { x = X[p * 3]; y = X[p * 3 + 1]; z = X[p * 3 + 2]; }
@@ -529,7 +581,7 @@ __global__ __launch_bounds__(256) void k_expand(const float* __restrict__ X, int
       }
     }
   } else {
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + (tid >> 6); tile < ntiles; tile += wstride) {
+    for (int64_t tile = t_first + (tid >> 6); tile < ntiles; tile += wstride) {
       const int64_t p = tile * 16 + pl;
       float x = 0.f, y = 0.f, z = 0.f;
       if (p < N) { x = X[p * 3]; y = X[p * 3 + 1]; z = X[p * 3 + 2]; }
@@ -565,6 +617,35 @@ __global__ __launch_bounds__(256) void k_expand(const float* __restrict__ X, int
   }
 }
 
+template <int M, int PREC, int DB>
+__global__ __launch_bounds__(256) void k_expand(const float* __restrict__ X, int64_t N,
+                                                const float4* __restrict__ om, const float* __restrict__ G32,
+                                                const __bf16* __restrict__ Gt16, int d, const float* F,
+                                                int64_t ldF, float* out, int64_t ldO) {
+  expand_body<M, PREC, DB>(X, N, om, G32, Gt16, d, F, ldF, out, ldO, (int64_t)blockIdx.x * 4, (N + 15) / 16,
+                           (int64_t)gridDim.x * 4);
+}
+
+// Batched expansion: one workgroup per (cloud, first tile) work item, each
+// covering kExpandTilesPerItem tiles of 16 points.
+constexpr int kExpandTilesPerItem = 64;
+int expand_tiles_per_item() { return kExpandTilesPerItem; }
+template <int M, int PREC, int DB>
+__global__ __launch_bounds__(256) void k_expand_batch(const CloudDesc* __restrict__ cl, const int2* __restrict__ work) {
+  const int2 wi = work[blockIdx.x];
+  const CloudDesc& c = cl[wi.x];
+  const int64_t ntiles = (c.N + 15) / 16;
+  int64_t t_end = (int64_t)wi.y + kExpandTilesPerItem;
+  if (t_end > ntiles) t_end = ntiles;
+  expand_body<M, PREC, DB>(c.X, c.N, c.om, c.G32, c.Gt16, c.d, c.F, c.ldF, c.out, c.ldO, wi.y, t_end, 4);
+}
+
+// Batched copy of the clouds' points into their plans (blockIdx.y = cloud).
+__global__ __launch_bounds__(256) void k_copy_points_batch(const CopyDesc* __restrict__ cp) {
+  const CopyDesc c = cp[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < c.n; i += (int64_t)gridDim.x * 256) c.dst[i] = c.src[i];
+}
+
 __global__ void k_copy_rows(const float* __restrict__ src, int64_t lds, float* __restrict__ dst, int64_t ldd,
                             int64_t rows, int cols) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -576,17 +657,17 @@ __global__ void k_copy_rows(const float* __restrict__ src, int64_t lds, float* _
 // ------------------------------------------------------------------ launchers
 template <int M, int PREC, bool GRAM>
 static hipError_t bta_dispatch_db(int DB, dim3 grid, const float* X, int64_t N, const float4* om, const float* F,
-                                  int64_t ldF, int d, int64_t cpw, float* parts, size_t stride, hipStream_t st) {
+                                  int64_t ldF, int d, float* parts, size_t stride, hipStream_t st) {
   switch (DB) {
     case 1:
-      hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 1>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, cpw, parts, stride);
+      hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 1>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, parts, stride);
       return hipGetLastError();
     case 2:
-      hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 2>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, cpw, parts, stride);
+      hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 2>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, parts, stride);
       return hipGetLastError();
     case 4:
       if constexpr (!(GRAM && M == 256)) {
-        hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 4>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, cpw, parts, stride);
+        hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 4>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, parts, stride);
         return hipGetLastError();
       }
       return hipErrorInvalidValue;
@@ -600,8 +681,6 @@ hipError_t launch_bta(rfd_plan_s* p, const float* X, int64_t N, const float* F, 
   const int M = p->dev_m, prec = p->params.precision;
   const int DB = dblocks(d);
   const int nparts = bta_partials(N, M, d, gram, prec);
-  const int64_t nchunks = (N + kChunk - 1) / kChunk;
-  const int64_t cpw = (nchunks + nparts - 1) / nparts;
   const size_t stride = bta_partial_floats(M, d, gram);
   dim3 grid(nparts);
   const float4* om = p->dev.om;
@@ -609,8 +688,8 @@ hipError_t launch_bta(rfd_plan_s* p, const float* X, int64_t N, const float* F, 
   ProfileScope prof(gram ? kKGram : kKBta, st);
 #define RFD_BTA(MM, PP)                                                                                     \
   if (M == MM && prec == PP) {                                                                              \
-    return gram ? bta_dispatch_db<MM, PP, true>(DB, grid, X, N, om, F, ldF, d, cpw, parts, stride, st)      \
-                : bta_dispatch_db<MM, PP, false>(DB, grid, X, N, om, F, ldF, d, cpw, parts, stride, st);    \
+    return gram ? bta_dispatch_db<MM, PP, true>(DB, grid, X, N, om, F, ldF, d, parts, stride, st)           \
+                : bta_dispatch_db<MM, PP, false>(DB, grid, X, N, om, F, ldF, d, parts, stride, st);         \
   }
   RFD_BTA(64, 0)
   RFD_BTA(64, 1)
@@ -698,6 +777,94 @@ hipError_t launch_copy_rows(const float* src, int64_t ld_src, float* dst, int64_
   hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, ld_src, dst, ld_dst, rows,
                      cols);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batched launchers
+hipError_t launch_copy_points_batch(const CopyDesc* dcp, int ncl, int64_t nmax, hipStream_t st) {
+  int64_t blocks = (nmax + 255) / 256;
+  if (blocks > 256) blocks = 256;
+  if (blocks < 1) blocks = 1;
+  ProfileScope prof(kKCopy, st);
+  hipLaunchKernelGGL(k_copy_points_batch, dim3((unsigned)blocks, (unsigned)ncl), dim3(256), 0, st, dcp);
+  return hipGetLastError();
+}
+
+template <int M, int PREC>
+static hipError_t bta_batch_db(int DB, int nwork, const CloudDesc* dcl, const int2* dwork, size_t stride,
+                               hipStream_t st) {
+  switch (DB) {
+    case 1:
+      hipLaunchKernelGGL((k_bta_batch<M, PREC, true, 1>), dim3(nwork), dim3(256), 0, st, dcl, dwork, stride);
+      return hipGetLastError();
+    case 2:
+      hipLaunchKernelGGL((k_bta_batch<M, PREC, true, 2>), dim3(nwork), dim3(256), 0, st, dcl, dwork, stride);
+      return hipGetLastError();
+    case 4:
+      if constexpr (M != 256) {
+        hipLaunchKernelGGL((k_bta_batch<M, PREC, true, 4>), dim3(nwork), dim3(256), 0, st, dcl, dwork, stride);
+        return hipGetLastError();
+      }
+      return hipErrorInvalidValue;
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bta_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork,
+                            hipStream_t st) {
+  const size_t stride = bta_partial_floats(M, 16 * DB, true);
+  ProfileScope prof(kKBtaBatch, st);
+  if (M == 64) return prec ? bta_batch_db<64, 1>(DB, nwork, dcl, dwork, stride, st) : bta_batch_db<64, 0>(DB, nwork, dcl, dwork, stride, st);
+  if (M == 128) return prec ? bta_batch_db<128, 1>(DB, nwork, dcl, dwork, stride, st) : bta_batch_db<128, 0>(DB, nwork, dcl, dwork, stride, st);
+  if (M == 256) return prec ? bta_batch_db<256, 1>(DB, nwork, dcl, dwork, stride, st) : bta_batch_db<256, 0>(DB, nwork, dcl, dwork, stride, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_batch(int M, int DB, const CloudDesc* dcl, int ncl, hipStream_t st) {
+  const size_t stride = bta_partial_floats(M, 16 * DB, true);
+  const size_t E = reduce_elems(M, DB, true);
+  ProfileScope prof(kKReduce, st);
+  hipLaunchKernelGGL(k_reduce1_batch, dim3((unsigned)((E + 255) / 256), kReduceGroups, (unsigned)ncl), dim3(256), 0, st,
+                     dcl, stride, E);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce2_batch, dim3((unsigned)((E + 255) / 256), 1, (unsigned)ncl), dim3(256), 0, st, dcl, E, M,
+                     DB, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hipStream_t st) {
+  ProfileScope prof(kKGcore, st);
+  hipLaunchKernelGGL(k_gcore_batch, dim3((unsigned)(M / 16), (unsigned)((dmax + 15) / 16), (unsigned)ncl), dim3(256),
+                     0, st, dcl, M);
+  return hipGetLastError();
+}
+
+template <int M, int PREC>
+static hipError_t expand_batch_db(int DB, int nwork, const CloudDesc* dcl, const int2* dwork, hipStream_t st) {
+  switch (DB) {
+    case 1:
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 1>), dim3(nwork), dim3(256), 0, st, dcl, dwork);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 2>), dim3(nwork), dim3(256), 0, st, dcl, dwork);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 4>), dim3(nwork), dim3(256), 0, st, dcl, dwork);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork,
+                               hipStream_t st) {
+  ProfileScope prof(kKExpandBatch, st);
+  if (M == 64) return prec ? expand_batch_db<64, 1>(DB, nwork, dcl, dwork, st) : expand_batch_db<64, 0>(DB, nwork, dcl, dwork, st);
+  if (M == 128) return prec ? expand_batch_db<128, 1>(DB, nwork, dcl, dwork, st) : expand_batch_db<128, 0>(DB, nwork, dcl, dwork, st);
+  if (M == 256) return prec ? expand_batch_db<256, 1>(DB, nwork, dcl, dwork, st) : expand_batch_db<256, 0>(DB, nwork, dcl, dwork, st);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace rfd

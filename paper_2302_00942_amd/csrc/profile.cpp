@@ -2,6 +2,7 @@
 // library is bracketed by two hipEvents recorded on the launch stream.
 // rfd_profile_read synchronises the device and folds the finished pairs into
 // per-kernel totals.
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -42,7 +43,11 @@ Profiler& prof() {
 
 }  // namespace
 
+static std::atomic<int> g_capturing{0};
+void set_capturing(bool on) { g_capturing.fetch_add(on ? 1 : -1); }
+
 ProfileScope::ProfileScope(int id, hipStream_t st) : id_(id), st_(st) {
+  if (g_capturing.load() > 0) return;
   Profiler& p = prof();
   std::lock_guard<std::mutex> g(p.mu);
   if (!p.on) return;

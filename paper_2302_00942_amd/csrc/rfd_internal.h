@@ -29,6 +29,33 @@ constexpr int kBarrierWords = 1024; // words of the grid-barrier counters of a p
 // host boundary (rfd_plan_core) and folded into the m x m core T.
 __host__ __device__ inline int dev_to_canon(int j, int f) { return (j & 1) ? f + (j >> 1) : (j >> 1); }
 
+// One cloud of a batched launch (device-side descriptor).
+struct CloudDesc {
+  const float* X;     // points (the plan's copy)
+  int64_t N;
+  const float4* om;   // frequencies
+  const float* F;
+  int64_t ldF;
+  float* out;
+  int64_t ldO;
+  float* partials;    // the plan's split-N partials
+  double* lvl;        // the plan's level-1 reduction buffer
+  double* Mraw;
+  double* H0;
+  const double* T64;
+  float* G32;
+  __bf16* Gt16;
+  int* flag;
+  int d;
+  int nparts;
+};
+
+struct CopyDesc {
+  const float* src;
+  float* dst;
+  int64_t n;  // floats
+};
+
 // Scratch and resident buffers of one plan.
 struct PlanDev {
   float4* om = nullptr;       // f x float4
@@ -106,7 +133,24 @@ hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* 
                          int d, float* out, int64_t ldO, hipStream_t st);
 hipError_t launch_copy_rows(const float* src, int64_t ld_src, float* dst, int64_t ld_dst,
                             int64_t rows, int cols, hipStream_t st);
+// Batched stages over device descriptor arrays.
+hipError_t launch_copy_points_batch(const CopyDesc* dcp, int ncl, int64_t nmax, hipStream_t st);
+hipError_t launch_bta_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, hipStream_t st);
+hipError_t launch_reduce_batch(int M, int DB, const CloudDesc* dcl, int ncl, hipStream_t st);
+hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hipStream_t st);
+hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork,
+                               hipStream_t st);
+hipError_t launch_phi1_batch_dev(int M, int n, const void* dev_args, hipStream_t st);
+void phi1_fill_args(rfd_plan_s* p, void* args_out);  // writes one Phi1Args
+int dblocks(int d);
+int expand_tiles_per_item();
+void set_capturing(bool on);  // suspends per-kernel timing during graph capture
 int bta_partials(int64_t N, int m, int d, bool gram, int prec);  // number of workgroups / partials
+size_t phi1_args_bytes();
+// host helpers shared by the single-cloud and batched entry points (host_plan.cpp)
+rfd_status ensure_partials(rfd_plan_s* p, size_t floats, hipStream_t st);
+rfd_status ensure_x(rfd_plan_s* p, int64_t N, hipStream_t st);
+int slice_width(int dev_m, bool gram);
 size_t bta_partial_floats(int m, int d, bool gram);              // floats per partial
 size_t reduce_scratch_doubles(int m);                            // level-1 reduction buffer
 

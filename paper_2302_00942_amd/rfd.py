@@ -68,6 +68,9 @@ def lib() -> C.CDLL:
             "rfd_plan_core": ([vp, vp, vp, vp, vp], i32),
             "rfd_plan_destroy": ([vp], None),
             "rfd_integrate_batch": ([vp, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
+            "rfd_batch_create": ([vp, vp, vp, vp, vp, vp, vp, vp, i32, C.POINTER(vp)], i32),
+            "rfd_batch_launch": ([vp, vp], i32),
+            "rfd_batch_destroy": ([vp], None),
             "rfd_server_create": ([C.c_size_t, i32, C.POINTER(vp)], i32),
             "rfd_submit": ([vp, C.POINTER(Request), C.POINTER(u64)], i32),
             "rfd_wait": ([vp, u64, dbl, C.POINTER(Result)], i32),
@@ -208,6 +211,50 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().rfd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many one-shot integrations in one launch per stage (rfd_batch_*).
+
+    plans, Xs, Fs, outs: equal-length lists; every X (N x 3), F (N x d) and
+    out (N x d) a float32 CUDA tensor that stays alive with the batch."""
+
+    def __init__(self, plans, Xs, Fs, outs):
+        n = len(plans)
+        if not (len(Xs) == len(Fs) == len(outs) == n) or n == 0:
+            raise ValueError("plans, Xs, Fs and outs must have the same non-zero length")
+        for X, F, o in zip(Xs, Fs, outs):
+            _dev_f32(X, "X", 3)
+            _dev_f32(F, "F")
+            _dev_f32(o, "out", F.shape[1])
+            if X.shape[0] != F.shape[0] or X.stride(0) != 3:
+                raise ValueError("X must be contiguous N x 3 with N = F.shape[0]")
+        self._keep = (plans, Xs, Fs, outs)
+        P = C.c_void_p * n
+        self._arrs = dict(
+            plans=P(*[p.handle.value for p in plans]), Xs=P(*[X.data_ptr() for X in Xs]),
+            Ns=(C.c_int64 * n)(*[X.shape[0] for X in Xs]), Fs=P(*[F.data_ptr() for F in Fs]),
+            ldFs=(C.c_int64 * n)(*[F.stride(0) for F in Fs]), ds=(C.c_int32 * n)(*[F.shape[1] for F in Fs]),
+            outs=P(*[o.data_ptr() for o in outs]), ldOs=(C.c_int64 * n)(*[o.stride(0) for o in outs]))
+        a = self._arrs
+        h = C.c_void_p()
+        _check(lib().rfd_batch_create(a["plans"], a["Xs"], a["Ns"], a["Fs"], a["ldFs"], a["ds"], a["outs"], a["ldOs"],
+                                      n, C.byref(h)), "rfd_batch_create")
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        _check(lib().rfd_batch_launch(self._h, _stream_handle(stream)), "rfd_batch_launch")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().rfd_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):
