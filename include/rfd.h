@@ -48,7 +48,7 @@ extern "C" {
 typedef enum {
   RFD_OK = 0,
   RFD_ERR_INVALID_ARG = 1,   /* bad size, null pointer, m odd or <= 0, eps <= 0, ld < d ... */
-  RFD_ERR_RANGE = 2,         /* exp(lambda A B^T) could overflow FP64 (see rfd_plan_create) */
+  RFD_ERR_RANGE = 2,         /* exp(lambda A B^T) could overflow FP64 (see rfd_features) */
   RFD_ERR_OUT_OF_BUDGET = 3, /* server: the request can never fit the HBM budget */
   RFD_ERR_NONFINITE = 4,     /* NaN or Inf in X or F, or produced in the core */
   RFD_ERR_DEVICE = 5,        /* a HIP runtime call failed */
@@ -125,8 +125,18 @@ rfd_status rfd_features(rfd_plan_t plan, const float* X_dev, int64_t N, rfd_stre
 rfd_status rfd_integrate(rfd_plan_t plan, const float* F_dev, int64_t ldF, int32_t d,
                          float* out_dev, int64_t ldO, rfd_stream_t stream);
 
+/* out = diag(scale) (F + A (S (B^T F))): rfd_integrate with each output row i
+ * multiplied by scale[i] (device, N float32; NULL = no scaling) in the
+ * expansion's store. This is one step of a scaling loop such as the
+ * Wasserstein-barycenter iteration (App. D, Alg. 1). Same errors and aliasing
+ * rules as rfd_integrate. */
+rfd_status rfd_integrate_scaled(rfd_plan_t plan, const float* F_dev, int64_t ldF, int32_t d,
+                                float* out_dev, int64_t ldO, const float* scale_dev,
+                                rfd_stream_t stream);
+
 /* One-shot: rfd_features followed by rfd_integrate, with the Gram and B^T F
- * computed in ONE pass over X and F (B^T [A | F]); two passes in total. */
+ * computed in ONE pass over X and F (B^T [A | F]); two passes in total.
+ * Errors: those of rfd_features and rfd_integrate. */
 rfd_status rfd_integrate_oneshot(rfd_plan_t plan, const float* X_dev, int64_t N,
                                  const float* F_dev, int64_t ldF, int32_t d,
                                  float* out_dev, int64_t ldO, rfd_stream_t stream);
@@ -180,6 +190,29 @@ void rfd_batch_destroy(rfd_batch_t batch);
 rfd_status rfd_integrate_batch(const rfd_plan_t* plans, const float* const* Xs, const int64_t* Ns,
                                const float* const* Fs, const int64_t* ldFs, const int32_t* ds,
                                float* const* outs, const int64_t* ldOs, int32_t n, rfd_stream_t stream);
+
+/* ------------------------------------------------------ repeated application */
+
+typedef struct rfd_loop_s* rfd_loop_t;
+
+/* A loop of `iterations` in-place steps on the vector block v (N x d,
+ * leading dimension ldv, device): step t applies plan k = t mod nplans,
+ *     v <- diag(scales[k]) exp(lambda_k A_k B_k^T) v,
+ * with every plan's features already computed (rfd_features) on clouds of the
+ * same N; scales may be NULL or hold NULL entries (no scaling). Creation sizes
+ * the plans' buffers so that no launch allocates. Errors: RFD_ERR_INVALID_ARG
+ * (sizes, unequal N, more than 16 plans), RFD_ERR_NOT_READY. */
+rfd_status rfd_loop_create(const rfd_plan_t* plans, const float* const* scales, int32_t nplans,
+                           float* v, int64_t ldv, int32_t d, int32_t iterations, rfd_loop_t* out);
+
+/* Enqueues the whole loop on `stream`. The first launch runs eagerly; the
+ * second, on a non-default stream, records the iterations into a hipGraph;
+ * later launches replay it (one hipGraphLaunch). Returns RFD_ERR_INVALID_ARG
+ * if a plan's buffers or cloud size changed since creation. */
+rfd_status rfd_loop_launch(rfd_loop_t loop, rfd_stream_t stream);
+
+/* Waits for the device and frees the loop (not the plans). */
+void rfd_loop_destroy(rfd_loop_t loop);
 
 /* ---------------------------------------------------------------- server */
 

@@ -80,6 +80,8 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
       if (plans[j] == p) return RFD_ERR_INVALID_ARG;  // each cloud needs its own plan
     dmax = std::max(dmax, (int)ds[i]);
   }
+  for (int i = 0; i < n; ++i)
+    if (rfd::range_exceeded(plans[i], Ns[i])) return RFD_ERR_RANGE;
   if (dmax > rfd::slice_width(M, true)) return RFD_ERR_INVALID_ARG;
   rfd_batch_s* b = new (std::nothrow) rfd_batch_s();
   if (!b) return RFD_ERR_DEVICE;

@@ -205,15 +205,26 @@ rfd_status ensure_x(rfd_plan_s* p, int64_t N, hipStream_t st) {
 // channel blocks when m = 256 (register budget); otherwise four.
 int slice_width(int dev_m, bool gram) { return (gram && dev_m == 256) ? 32 : 64; }
 
+bool range_exceeded(const rfd_plan_s* p, int64_t N) {
+  // ||lambda M||_2 <= |lambda| trace(|M|) = |lambda| N sum_k |w_k| / f, since
+  // every feature pair contributes c_k^2 (cos^2 + sin^2) = |w_k| / f per point.
+  return p->any_growth && fabs(p->params.lambda) * (double)N * p->wsum_abs / p->f > 700.0;
+}
+
+size_t partial_floats_needed(const rfd_plan_s* p, int64_t N, int d, bool gram) {
+  const int M = p->dev_m;
+  return (size_t)bta_partials(N, M, d, gram, p->params.precision) * bta_partial_floats(M, d, gram);
+}
+
 rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_t st) {
   if (N < 0 || (N > 0 && !X)) return RFD_ERR_INVALID_ARG;
+  if (range_exceeded(p, N)) return RFD_ERR_RANGE;
   p->N = N;
   if (N == 0) return RFD_OK;
   rfd_status s = ensure_x(p, N, st);
   if (s != RFD_OK) return s;
   HIPCK(hipMemcpyAsync(p->dev.X, X, (size_t)N * 3 * sizeof(float), hipMemcpyDeviceToDevice, st));
-  const int M = p->dev_m;
-  s = ensure_partials(p, (size_t)bta_partials(N, M, 0, true, p->params.precision) * bta_partial_floats(M, 0, true), st);
+  s = ensure_partials(p, partial_floats_needed(p, N, 0, true), st);
   if (s != RFD_OK) return s;
   HIPCK(launch_bta(p, p->dev.X, N, nullptr, 0, 0, true, st));
   HIPCK(launch_reduce(p, N, 0, true, st));
@@ -222,21 +233,43 @@ rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_
 }
 
 rfd_status integrate_enqueue(rfd_plan_s* p, const float* F, int64_t ldF, int d, float* out, int64_t ldO,
-                             hipStream_t st, int first_channel_done) {
+                             hipStream_t st, int first_channel_done, const float* rowscale) {
   const int M = p->dev_m;
   const int64_t N = p->N;
   const int W = slice_width(M, false);
   for (int c0 = first_channel_done; c0 < d; c0 += W) {
     const int dc = std::min(W, d - c0);
-    rfd_status s = ensure_partials(p, (size_t)bta_partials(N, M, dc, false, p->params.precision) *
-                                          bta_partial_floats(M, dc, false), st);
+    rfd_status s = ensure_partials(p, partial_floats_needed(p, N, dc, false), st);
     if (s != RFD_OK) return s;
     HIPCK(launch_bta(p, p->dev.X, N, F + c0, ldF, dc, false, st));
     HIPCK(launch_reduce(p, N, dc, false, st));
     HIPCK(launch_gcore(p, dc, st));
-    HIPCK(launch_expand(p, p->dev.X, N, F + c0, ldF, dc, out + c0, ldO, st));
+    HIPCK(launch_expand(p, p->dev.X, N, F + c0, ldF, dc, out + c0, ldO, rowscale, st));
   }
   return RFD_OK;
+}
+
+rfd_status oneshot_enqueue(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF, int d,
+                           float* out, int64_t ldO, hipStream_t st) {
+  if (N < 0 || (N > 0 && !X)) return RFD_ERR_INVALID_ARG;
+  rfd_status s = check_field_args(N, F, ldF, d, out, ldO);
+  if (s != RFD_OK) return s;
+  if (d == 0 || N == 0) return features_enqueue(p, X, N, st);
+  if (range_exceeded(p, N)) return RFD_ERR_RANGE;
+  p->N = N;
+  s = ensure_x(p, N, st);
+  if (s != RFD_OK) return s;
+  HIPCK(hipMemcpyAsync(p->dev.X, X, (size_t)N * 3 * sizeof(float), hipMemcpyDeviceToDevice, st));
+  const int dc = std::min(slice_width(p->dev_m, true), d);
+  s = ensure_partials(p, partial_floats_needed(p, N, dc, true), st);
+  if (s != RFD_OK) return s;
+  // pass 1 carries the Gram and the first channel slice of B^T F
+  HIPCK(launch_bta(p, p->dev.X, N, F, ldF, dc, true, st));
+  HIPCK(launch_reduce(p, N, dc, true, st));
+  HIPCK(launch_phi1(p, st));
+  HIPCK(launch_gcore(p, dc, st));
+  HIPCK(launch_expand(p, p->dev.X, N, F, ldF, dc, out, ldO, nullptr, st));
+  return integrate_enqueue(p, F, ldF, d, out, ldO, st, dc, nullptr);
 }
 
 rfd_status check_field_args(int64_t N, const float* F, int64_t ldF, int d, const float* out, int64_t ldO) {
@@ -367,36 +400,22 @@ rfd_status rfd_features(rfd_plan_t p, const float* X_dev, int64_t N, rfd_stream_
 
 rfd_status rfd_integrate(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, float* out, int64_t ldO,
                          rfd_stream_t stream) {
+  return rfd_integrate_scaled(p, F, ldF, d, out, ldO, nullptr, stream);
+}
+
+rfd_status rfd_integrate_scaled(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, float* out, int64_t ldO,
+                                const float* scale, rfd_stream_t stream) {
   if (!p) return RFD_ERR_INVALID_ARG;
   if (p->N < 0) return RFD_ERR_NOT_READY;
   rfd_status s = rfd::check_field_args(p->N, F, ldF, d, out, ldO);
   if (s != RFD_OK || d == 0 || p->N == 0) return s;
-  return rfd::integrate_enqueue(p, F, ldF, d, out, ldO, (hipStream_t)stream, 0);
+  return rfd::integrate_enqueue(p, F, ldF, d, out, ldO, (hipStream_t)stream, 0, scale);
 }
 
 rfd_status rfd_integrate_oneshot(rfd_plan_t p, const float* X, int64_t N, const float* F, int64_t ldF, int32_t d,
                                  float* out, int64_t ldO, rfd_stream_t stream) {
   if (!p) return RFD_ERR_INVALID_ARG;
-  if (N < 0 || (N > 0 && !X)) return RFD_ERR_INVALID_ARG;
-  rfd_status s = rfd::check_field_args(N, F, ldF, d, out, ldO);
-  if (s != RFD_OK) return s;
-  hipStream_t st = (hipStream_t)stream;
-  if (d == 0 || N == 0) return rfd::features_enqueue(p, X, N, st);
-  p->N = N;
-  s = rfd::ensure_x(p, N, st);
-  if (s != RFD_OK) return s;
-  HIPCK(hipMemcpyAsync(p->dev.X, X, (size_t)N * 3 * sizeof(float), hipMemcpyDeviceToDevice, st));
-  const int M = p->dev_m;
-  const int dc = std::min(rfd::slice_width(M, true), (int)d);
-  s = rfd::ensure_partials(p, (size_t)rfd::bta_partials(N, M, dc, true, p->params.precision) *
-                                  rfd::bta_partial_floats(M, dc, true), st);
-  if (s != RFD_OK) return s;
-  HIPCK(rfd::launch_bta(p, p->dev.X, N, F, ldF, dc, true, st));
-  HIPCK(rfd::launch_reduce(p, N, dc, true, st));
-  HIPCK(rfd::launch_phi1(p, st));
-  HIPCK(rfd::launch_gcore(p, dc, st));
-  HIPCK(rfd::launch_expand(p, p->dev.X, N, F, ldF, dc, out, ldO, st));
-  return rfd::integrate_enqueue(p, F, ldF, d, out, ldO, st, dc);
+  return rfd::oneshot_enqueue(p, X, N, F, ldF, d, out, ldO, (hipStream_t)stream);
 }
 
 rfd_status rfd_plan_check(rfd_plan_t p, rfd_stream_t stream) {

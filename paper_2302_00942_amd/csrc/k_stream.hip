@@ -512,8 +512,9 @@ __global__ __launch_bounds__(256) void k_gcore_batch(const CloudDesc* __restrict
 template <int M, int PREC, int DB>
 __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t N, const float4* __restrict__ om,
                                             const float* __restrict__ G32, const __bf16* __restrict__ Gt16, int d,
-                                            const float* F, int64_t ldF, float* out, int64_t ldO, int64_t t_first,
-                                            int64_t t_end, int64_t t_step) {
+                                            const float* F, int64_t ldF, float* out, int64_t ldO,
+                                            const float* __restrict__ rowscale, int64_t t_first, int64_t t_end,
+                                            int64_t t_step) {
   constexpr int FQ = M / 2;
   constexpr int GP = M + 8;  // BF16 row pitch of G'^T in LDS: conflict-free 16-byte reads
   __shared__ float4 oms[FQ];
@@ -575,7 +576,10 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int64_t pr = tile * 16 + 4 * g + q;
-            if (pr < N) out[pr * ldO + c] = F[pr * ldF + c] + acc[cb][q];
+            if (pr < N) {
+              const float v = F[pr * ldF + c] + acc[cb][q];
+              out[pr * ldO + c] = rowscale ? rowscale[pr] * v : v;
+            }
           }
         }
       }
@@ -609,7 +613,10 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int64_t pr = tile * 16 + 4 * g + q;
-            if (pr < N) out[pr * ldO + c] = F[pr * ldF + c] + acc[cb][q];
+            if (pr < N) {
+              const float v = F[pr * ldF + c] + acc[cb][q];
+              out[pr * ldO + c] = rowscale ? rowscale[pr] * v : v;
+            }
           }
         }
       }
@@ -621,9 +628,10 @@ template <int M, int PREC, int DB>
 __global__ __launch_bounds__(256) void k_expand(const float* __restrict__ X, int64_t N,
                                                 const float4* __restrict__ om, const float* __restrict__ G32,
                                                 const __bf16* __restrict__ Gt16, int d, const float* F,
-                                                int64_t ldF, float* out, int64_t ldO) {
-  expand_body<M, PREC, DB>(X, N, om, G32, Gt16, d, F, ldF, out, ldO, (int64_t)blockIdx.x * 4, (N + 15) / 16,
-                           (int64_t)gridDim.x * 4);
+                                                int64_t ldF, float* out, int64_t ldO,
+                                                const float* __restrict__ rowscale) {
+  expand_body<M, PREC, DB>(X, N, om, G32, Gt16, d, F, ldF, out, ldO, rowscale, (int64_t)blockIdx.x * 4,
+                           (N + 15) / 16, (int64_t)gridDim.x * 4);
 }
 
 // Batched expansion: one workgroup per (cloud, first tile) work item, each
@@ -637,7 +645,7 @@ __global__ __launch_bounds__(256) void k_expand_batch(const CloudDesc* __restric
   const int64_t ntiles = (c.N + 15) / 16;
   int64_t t_end = (int64_t)wi.y + kExpandTilesPerItem;
   if (t_end > ntiles) t_end = ntiles;
-  expand_body<M, PREC, DB>(c.X, c.N, c.om, c.G32, c.Gt16, c.d, c.F, c.ldF, c.out, c.ldO, wi.y, t_end, 4);
+  expand_body<M, PREC, DB>(c.X, c.N, c.om, c.G32, c.Gt16, c.d, c.F, c.ldF, c.out, c.ldO, nullptr, wi.y, t_end, 4);
 }
 
 // Batched copy of the clouds' points into their plans (blockIdx.y = cloud).
@@ -730,16 +738,16 @@ hipError_t launch_gcore(rfd_plan_s* p, int d, hipStream_t st) {
 template <int M, int PREC>
 static hipError_t expand_dispatch(int DB, dim3 grid, const float* X, int64_t N, const float4* om, const float* G32,
                                   const __bf16* Gt16, int d, const float* F, int64_t ldF, float* out, int64_t ldO,
-                                  hipStream_t st) {
+                                  const float* rowscale, hipStream_t st) {
   switch (DB) {
     case 1:
-      hipLaunchKernelGGL((k_expand<M, PREC, 1>), grid, dim3(256), 0, st, X, N, om, G32, Gt16, d, F, ldF, out, ldO);
+      hipLaunchKernelGGL((k_expand<M, PREC, 1>), grid, dim3(256), 0, st, X, N, om, G32, Gt16, d, F, ldF, out, ldO, rowscale);
       break;
     case 2:
-      hipLaunchKernelGGL((k_expand<M, PREC, 2>), grid, dim3(256), 0, st, X, N, om, G32, Gt16, d, F, ldF, out, ldO);
+      hipLaunchKernelGGL((k_expand<M, PREC, 2>), grid, dim3(256), 0, st, X, N, om, G32, Gt16, d, F, ldF, out, ldO, rowscale);
       break;
     case 4:
-      hipLaunchKernelGGL((k_expand<M, PREC, 4>), grid, dim3(256), 0, st, X, N, om, G32, Gt16, d, F, ldF, out, ldO);
+      hipLaunchKernelGGL((k_expand<M, PREC, 4>), grid, dim3(256), 0, st, X, N, om, G32, Gt16, d, F, ldF, out, ldO, rowscale);
       break;
     default:
       return hipErrorInvalidValue;
@@ -748,7 +756,7 @@ static hipError_t expand_dispatch(int DB, dim3 grid, const float* X, int64_t N, 
 }
 
 hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF, int d, float* out,
-                         int64_t ldO, hipStream_t st) {
+                         int64_t ldO, const float* rowscale, hipStream_t st) {
   const int M = p->dev_m, prec = p->params.precision;
   const int DB = dblocks(d);
   const int64_t ntiles = (N + 15) / 16;
@@ -759,7 +767,7 @@ hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* 
   const float4* om = p->dev.om;
   ProfileScope prof(kKExpand, st);
 #define RFD_EXP(MM, PP) \
-  if (M == MM && prec == PP) return expand_dispatch<MM, PP>(DB, grid, X, N, om, p->dev.G32, p->dev.Gt16, d, F, ldF, out, ldO, st);
+  if (M == MM && prec == PP) return expand_dispatch<MM, PP>(DB, grid, X, N, om, p->dev.G32, p->dev.Gt16, d, F, ldF, out, ldO, rowscale, st);
   RFD_EXP(64, 0)
   RFD_EXP(64, 1)
   RFD_EXP(128, 0)

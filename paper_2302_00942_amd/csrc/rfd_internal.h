@@ -130,7 +130,7 @@ size_t phi1_args_bytes();
 size_t phi1_ws_doubles(int m);
 hipError_t launch_gcore(rfd_plan_s* p, int d, hipStream_t st);
 hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF,
-                         int d, float* out, int64_t ldO, hipStream_t st);
+                         int d, float* out, int64_t ldO, const float* rowscale, hipStream_t st);
 hipError_t launch_copy_rows(const float* src, int64_t ld_src, float* dst, int64_t ld_dst,
                             int64_t rows, int cols, hipStream_t st);
 // Batched stages over device descriptor arrays.
@@ -151,6 +151,18 @@ size_t phi1_args_bytes();
 rfd_status ensure_partials(rfd_plan_s* p, size_t floats, hipStream_t st);
 rfd_status ensure_x(rfd_plan_s* p, int64_t N, hipStream_t st);
 int slice_width(int dev_m, bool gram);
+// Host overflow guard of the core (exact bound |lambda| N sum|w| / f on the
+// spectral norm of lambda M, checked when some lambda w_k > 0).
+bool range_exceeded(const rfd_plan_s* p, int64_t N);
+rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_t st);
+// Channels [first_channel_done, d) of out = rowscale . (F + A S B^T F) (rowscale may be null).
+rfd_status integrate_enqueue(rfd_plan_s* p, const float* F, int64_t ldF, int d, float* out, int64_t ldO,
+                             hipStream_t st, int first_channel_done, const float* rowscale);
+rfd_status oneshot_enqueue(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF, int d,
+                           float* out, int64_t ldO, hipStream_t st);
+rfd_status check_field_args(int64_t N, const float* F, int64_t ldF, int d, const float* out, int64_t ldO);
+// Partial-buffer floats a pass over N points with d channels needs.
+size_t partial_floats_needed(const rfd_plan_s* p, int64_t N, int d, bool gram);
 size_t bta_partial_floats(int m, int d, bool gram);              // floats per partial
 size_t reduce_scratch_doubles(int m);                            // level-1 reduction buffer
 

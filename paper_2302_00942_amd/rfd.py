@@ -63,7 +63,11 @@ def lib() -> C.CDLL:
             "rfd_plan_export": ([vp, vp, vp], i32),
             "rfd_features": ([vp, vp, i64, vp], i32),
             "rfd_integrate": ([vp, vp, i64, i32, vp, i64, vp], i32),
+            "rfd_integrate_scaled": ([vp, vp, i64, i32, vp, i64, vp, vp], i32),
             "rfd_integrate_oneshot": ([vp, vp, i64, vp, i64, i32, vp, i64, vp], i32),
+            "rfd_loop_create": ([vp, vp, i32, vp, i64, i32, i32, C.POINTER(vp)], i32),
+            "rfd_loop_launch": ([vp, vp], i32),
+            "rfd_loop_destroy": ([vp], None),
             "rfd_plan_check": ([vp, vp], i32),
             "rfd_plan_core": ([vp, vp, vp, vp, vp], i32),
             "rfd_plan_destroy": ([vp], None),
@@ -178,6 +182,23 @@ class Plan:
                                    _stream_handle(stream)), "rfd_integrate")
         return out
 
+    def integrate_scaled(self, F, scale, out=None, stream=None):
+        """out = diag(scale) (F + A S B^T F); scale a float32 CUDA vector of N entries or None."""
+        import torch
+        F = _dev_f32(F, "F")
+        if out is None:
+            out = torch.empty_like(F)
+        out = _dev_f32(out, "out", F.shape[1])
+        sp = 0
+        if scale is not None:
+            if not (isinstance(scale, torch.Tensor) and scale.is_cuda and scale.dtype == torch.float32
+                    and scale.is_contiguous() and scale.numel() == F.shape[0]):
+                raise ValueError("scale must be a contiguous float32 CUDA vector with one entry per row")
+            sp = scale.data_ptr()
+        _check(lib().rfd_integrate_scaled(self._h, F.data_ptr(), F.stride(0), F.shape[1], out.data_ptr(),
+                                          out.stride(0), sp or None, _stream_handle(stream)), "rfd_integrate_scaled")
+        return out
+
     def oneshot(self, X, F, out=None, stream=None):
         import torch
         X = _dev_f32(X, "X", 3)
@@ -255,6 +276,47 @@ class Batch:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().rfd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Loop:
+    """`iterations` in-place steps v <- diag(s_k) exp(lambda_k A_k B_k^T) v,
+    k = t mod len(plans) (rfd_loop_*). Every plan has its features computed on
+    a cloud of v.shape[0] points; scales holds float32 CUDA vectors or None."""
+
+    def __init__(self, plans, scales, v, iterations: int):
+        import torch
+        _dev_f32(v, "v")
+        n = len(plans)
+        if scales is None:
+            scales = [None] * n
+        if len(scales) != n or n == 0:
+            raise ValueError("one scale (or None) per plan")
+        for s in scales:
+            if s is not None and not (isinstance(s, torch.Tensor) and s.is_cuda and s.dtype == torch.float32
+                                      and s.is_contiguous() and s.numel() == v.shape[0]):
+                raise ValueError("each scale must be a contiguous float32 CUDA vector with one entry per row")
+        self._keep = (plans, scales, v)
+        P = C.c_void_p * n
+        self._plans = P(*[p.handle.value for p in plans])
+        self._scales = P(*[(s.data_ptr() if s is not None else None) for s in scales])
+        h = C.c_void_p()
+        _check(lib().rfd_loop_create(self._plans, self._scales, n, v.data_ptr(), v.stride(0), v.shape[1],
+                                     int(iterations), C.byref(h)), "rfd_loop_create")
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        _check(lib().rfd_loop_launch(self._h, _stream_handle(stream)), "rfd_loop_launch")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().rfd_loop_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -231,3 +231,25 @@ def test_large_torus_full_size(torch_cuda, prec):
     out, plan, st = run_oneshot(torch_cuda, c.X, c.F, c.eps, c.lam, c.m, c.seed, prec)
     assert st == 0
     compare(out, ref, c.F, prec, "torus N=1e6 m=256 d=16")
+
+
+def test_range_guard_on_growth(torch_cuda):
+    """lambda > 0 with nonnegative weights: the host bound |lambda| N sum|w|/f
+    on ||lambda M||_2 exceeds 700, so the call is refused before any launch."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    c = wl.plain_sphere(n=4000)
+    plan = rfd.Plan(c.m, c.eps, 1.0, c.seed)
+    om, w = plan.export()
+    assert abs(w).sum() / (c.m // 2) * 4000 > 700
+    X = torch.from_numpy(c.X).cuda()
+    with pytest.raises(rfd.RfdError) as e:
+        plan.oneshot(X, torch.from_numpy(c.F).cuda())
+    assert e.value.status == rfd.RANGE
+    with pytest.raises(rfd.RfdError) as e:
+        plan.features(X)
+    assert e.value.status == rfd.RANGE
+    # the same cloud at lambda < 0 cannot overflow and runs
+    plan2 = rfd.Plan(c.m, c.eps, -1.0, c.seed)
+    plan2.oneshot(X, torch.from_numpy(c.F).cuda())
+    assert plan2.check() == rfd.OK
