@@ -216,28 +216,75 @@ void rfd_loop_destroy(rfd_loop_t loop);
 
 /* ---------------------------------------------------------------- server */
 
+/* The server admits integration requests of mixed N, d and m and runs them
+ * with continuous batching: a worker thread admits queued requests (FIFO)
+ * whenever one of `max_inflight` slots is free and the device memory of the
+ * request's plan fits the HBM budget, evicting idle cached plans (least
+ * recently used first) to make room; admitted requests run on a pool of
+ * streams, so requests that arrive while others run are admitted as slots and
+ * memory free up, and their kernels overlap on the device. Plans stay
+ * resident between requests, cached by their parameters: a request whose
+ * cloud_key names a cloud whose features a cached plan holds runs the
+ * integrate passes only; otherwise the one-shot path runs on an idle plan
+ * with the same parameters (no allocation) or on a new plan. Each request's
+ * result equals rfd_integrate_oneshot (or rfd_integrate on the resident
+ * features) of the same inputs, bitwise, whatever else runs beside it. The
+ * budget counts the plans' own device memory (frequencies, core, workspaces,
+ * the copy of X, partial sums), not the callers' F and out. All functions
+ * are thread-safe. */
+
 typedef struct {
-  const float* X;     /* device, N x 3; must stay valid until rfd_wait returns */
+  const float* X;     /* device, N x 3; read before the request completes */
   int64_t N;
-  const float* F;     /* device, N x d */
+  const float* F;     /* device, N x d; must stay valid until the request completes */
   int64_t ldF;
   int32_t d;
   int32_t reserved;
-  float* out;         /* device, N x d */
+  float* out;         /* device, N x d; written by the time the request completes */
   int64_t ldO;
-  rfd_params params;
-  uint64_t cloud_key; /* reuse a resident plan for the same cloud; 0 = no reuse */
+  rfd_params params;  /* params.omega must be NULL (frequencies come from the seed) */
+  uint64_t cloud_key; /* nonzero: the caller's name for this cloud (same key = same X and N),
+                         so later requests on it reuse the resident features; 0 = no reuse */
 } rfd_request;
 
 typedef struct {
-  rfd_status status;
+  rfd_status status;  /* the request's outcome */
   int32_t reserved;
-  double t_submit, t_start, t_done; /* seconds on the host steady clock */
+  double t_submit, t_start, t_done; /* seconds on the host steady clock: submitted, admitted
+                                       (work enqueued), completion seen by the worker */
 } rfd_result;
 
+/* Starts a server on the current device: hbm_budget_bytes > 0 bounds the
+ * device memory of its resident plans; 1 <= max_inflight <= 64 requests run
+ * at once. Errors: RFD_ERR_INVALID_ARG, RFD_ERR_DEVICE. */
 rfd_status rfd_server_create(size_t hbm_budget_bytes, int32_t max_inflight, rfd_server_t* out);
+
+/* Queues one request and returns at once with its ticket. The server runs
+ * the request on its own non-blocking streams, which are not ordered after
+ * the caller's streams: X, F and out must be ready (the work producing them
+ * complete) when rfd_submit is called. Once rfd_wait has returned the
+ * request's status, out is complete on the device. Errors (nothing is
+ * queued): RFD_ERR_INVALID_ARG as for rfd_integrate_oneshot or a non-NULL
+ * params.omega; RFD_ERR_OUT_OF_BUDGET when the request alone can never fit
+ * the budget; RFD_ERR_SHUTDOWN. N = 0 or d = 0 completes at once. */
 rfd_status rfd_submit(rfd_server_t server, const rfd_request* req, uint64_t* ticket);
+
+/* Waits up to timeout_s seconds (< 0: without limit) for a ticket. Returns
+ * RFD_ERR_NOT_READY on timeout (the ticket stays valid) and
+ * RFD_ERR_INVALID_ARG for an unknown or already collected ticket; otherwise
+ * fills *res (may be NULL), forgets the ticket and returns the request's
+ * status: RFD_OK, RFD_ERR_RANGE, RFD_ERR_NONFINITE, RFD_ERR_DEVICE, or
+ * RFD_ERR_SHUTDOWN for a request still queued when the server was destroyed. */
 rfd_status rfd_wait(rfd_server_t server, uint64_t ticket, double timeout_s, rfd_result* res);
+
+/* Current device bytes of the resident plans, number of plans, queued and
+ * in-flight requests (any pointer may be NULL). */
+rfd_status rfd_server_stats(rfd_server_t server, size_t* device_bytes, int32_t* plans,
+                            int32_t* queued, int32_t* inflight);
+
+/* Finishes the in-flight requests, completes the queued ones with
+ * RFD_ERR_SHUTDOWN, frees every plan and the server. Call it only after every
+ * thread's rfd_wait on this server has returned. */
 void rfd_server_destroy(rfd_server_t server);
 
 const char* rfd_status_string(rfd_status s);

@@ -1,6 +1,6 @@
 // Batched integration of many clouds: one launch per stage over a flattened
 // (cloud, part) / (cloud, tile block) work list, recorded once into a
-// hipGraph and replayed. The server lives in server.cpp.
+// hipGraph and replayed.
 #include <string.h>
 
 #include <algorithm>
@@ -203,22 +203,5 @@ rfd_status rfd_integrate_batch(const rfd_plan_t* plans, const float* const* Xs, 
   free_batch(b);
   return s;
 }
-
-// ---------------------------------------------------------------- server (placeholder until server.cpp)
-rfd_status rfd_server_create(size_t hbm_budget_bytes, int32_t max_inflight, rfd_server_t* out) {
-  (void)hbm_budget_bytes;
-  (void)max_inflight;
-  if (out) *out = nullptr;
-  return RFD_ERR_INVALID_ARG;
-}
-rfd_status rfd_submit(rfd_server_t server, const rfd_request* req, uint64_t* ticket) {
-  (void)server; (void)req; (void)ticket;
-  return RFD_ERR_INVALID_ARG;
-}
-rfd_status rfd_wait(rfd_server_t server, uint64_t ticket, double timeout_s, rfd_result* res) {
-  (void)server; (void)ticket; (void)timeout_s; (void)res;
-  return RFD_ERR_INVALID_ARG;
-}
-void rfd_server_destroy(rfd_server_t server) { (void)server; }
 
 }  // extern "C"

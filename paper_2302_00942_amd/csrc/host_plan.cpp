@@ -212,11 +212,63 @@ bool range_exceeded(const rfd_plan_s* p, int64_t N) {
 }
 
 size_t partial_floats_needed(const rfd_plan_s* p, int64_t N, int d, bool gram) {
-  const int M = p->dev_m;
-  return (size_t)bta_partials(N, M, d, gram, p->params.precision) * bta_partial_floats(M, d, gram);
+  return partial_floats_for(p->dev_m, p->params.precision, N, d, gram);
 }
 
-rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_t st) {
+size_t partial_floats_for(int M, int prec, int64_t N, int d, bool gram) {
+  return (size_t)bta_partials(N, M, d, gram, prec) * bta_partial_floats(M, d, gram);
+}
+
+size_t request_partial_floats(int M, int prec, int64_t N, int d, bool oneshot) {
+  size_t need = 0;
+  int c0 = 0;
+  if (oneshot) {
+    c0 = std::min(slice_width(M, true), d);
+    need = partial_floats_for(M, prec, N, c0, true);
+  }
+  const int W = slice_width(M, false);
+  for (; c0 < d; c0 += W) need = std::max(need, partial_floats_for(M, prec, N, std::min(W, d - c0), false));
+  return need;
+}
+
+int padded_m(int m) { return m <= 64 ? 64 : (m <= 128 ? 128 : 256); }
+
+rfd_status check_params(const rfd_params* p) { return ::check_params(p); }
+
+void free_plan_device(rfd_plan_s* p) {
+  free_dev(p->dev);
+  delete p;
+}
+
+size_t plan_fixed_bytes(int M) {
+  const size_t mm = (size_t)M * M;
+  return sizeof(float4) * (M / 2) + 2 * sizeof(double) * M + 3 * sizeof(double) * mm +
+         sizeof(double) * M * 64 + sizeof(float) * M * 64 + 2 * sizeof(__bf16) * M * 64 +
+         sizeof(double) * phi1_ws_doubles(M) + sizeof(int) * M + 2 * sizeof(int) +
+         sizeof(unsigned) * kBarrierWords + sizeof(double) * reduce_scratch_doubles(M);
+}
+
+size_t plan_device_bytes(const rfd_plan_s* p) {
+  return plan_fixed_bytes(p->dev_m) + sizeof(float) * 3 * (size_t)p->dev.Xcap + sizeof(float) * p->dev.partials_cap;
+}
+
+// phi_1 either on the launch stream or, when `lane` is given, on the lane's
+// stream between two event waits (the lane serialises the cooperative
+// launches of concurrent requests).
+static rfd_status enqueue_phi1(rfd_plan_s* p, hipStream_t st, const PhiLane* lane) {
+  if (!lane) {
+    HIPCK(launch_phi1(p, st));
+    return RFD_OK;
+  }
+  HIPCK(hipEventRecord(lane->before, st));
+  HIPCK(hipStreamWaitEvent(lane->st, lane->before, 0));
+  HIPCK(launch_phi1(p, lane->st));
+  HIPCK(hipEventRecord(lane->after, lane->st));
+  HIPCK(hipStreamWaitEvent(st, lane->after, 0));
+  return RFD_OK;
+}
+
+rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_t st, const PhiLane* lane) {
   if (N < 0 || (N > 0 && !X)) return RFD_ERR_INVALID_ARG;
   if (range_exceeded(p, N)) return RFD_ERR_RANGE;
   p->N = N;
@@ -228,8 +280,7 @@ rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_
   if (s != RFD_OK) return s;
   HIPCK(launch_bta(p, p->dev.X, N, nullptr, 0, 0, true, st));
   HIPCK(launch_reduce(p, N, 0, true, st));
-  HIPCK(launch_phi1(p, st));
-  return RFD_OK;
+  return enqueue_phi1(p, st, lane);
 }
 
 rfd_status integrate_enqueue(rfd_plan_s* p, const float* F, int64_t ldF, int d, float* out, int64_t ldO,
@@ -250,11 +301,11 @@ rfd_status integrate_enqueue(rfd_plan_s* p, const float* F, int64_t ldF, int d, 
 }
 
 rfd_status oneshot_enqueue(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF, int d,
-                           float* out, int64_t ldO, hipStream_t st) {
+                           float* out, int64_t ldO, hipStream_t st, const PhiLane* lane) {
   if (N < 0 || (N > 0 && !X)) return RFD_ERR_INVALID_ARG;
   rfd_status s = check_field_args(N, F, ldF, d, out, ldO);
   if (s != RFD_OK) return s;
-  if (d == 0 || N == 0) return features_enqueue(p, X, N, st);
+  if (d == 0 || N == 0) return features_enqueue(p, X, N, st, lane);
   if (range_exceeded(p, N)) return RFD_ERR_RANGE;
   p->N = N;
   s = ensure_x(p, N, st);
@@ -266,7 +317,8 @@ rfd_status oneshot_enqueue(rfd_plan_s* p, const float* X, int64_t N, const float
   // pass 1 carries the Gram and the first channel slice of B^T F
   HIPCK(launch_bta(p, p->dev.X, N, F, ldF, dc, true, st));
   HIPCK(launch_reduce(p, N, dc, true, st));
-  HIPCK(launch_phi1(p, st));
+  s = enqueue_phi1(p, st, lane);
+  if (s != RFD_OK) return s;
   HIPCK(launch_gcore(p, dc, st));
   HIPCK(launch_expand(p, p->dev.X, N, F, ldF, dc, out, ldO, nullptr, st));
   return integrate_enqueue(p, F, ldF, d, out, ldO, st, dc, nullptr);
@@ -326,7 +378,7 @@ rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan) {
   p->pade_b[0] = 1.0;
   for (int k = 0; k < 13; ++k) p->pade_b[k + 1] = p->pade_b[k] * (double)(13 - k) / ((double)(26 - k) * (double)(k + 1));
 
-  const int M = params->m <= 64 ? 64 : (params->m <= 128 ? 128 : 256);
+  const int M = rfd::padded_m(params->m);
   p->dev_m = M;
   const int fp = M / 2;
   (void)hipGetDevice(&p->device);
@@ -395,7 +447,7 @@ rfd_status rfd_plan_export(rfd_plan_t p, float* omega_fx3, double* w_f) {
 
 rfd_status rfd_features(rfd_plan_t p, const float* X_dev, int64_t N, rfd_stream_t stream) {
   if (!p) return RFD_ERR_INVALID_ARG;
-  return rfd::features_enqueue(p, X_dev, N, (hipStream_t)stream);
+  return rfd::features_enqueue(p, X_dev, N, (hipStream_t)stream, nullptr);
 }
 
 rfd_status rfd_integrate(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, float* out, int64_t ldO,
@@ -415,7 +467,7 @@ rfd_status rfd_integrate_scaled(rfd_plan_t p, const float* F, int64_t ldF, int32
 rfd_status rfd_integrate_oneshot(rfd_plan_t p, const float* X, int64_t N, const float* F, int64_t ldF, int32_t d,
                                  float* out, int64_t ldO, rfd_stream_t stream) {
   if (!p) return RFD_ERR_INVALID_ARG;
-  return rfd::oneshot_enqueue(p, X, N, F, ldF, d, out, ldO, (hipStream_t)stream);
+  return rfd::oneshot_enqueue(p, X, N, F, ldF, d, out, ldO, (hipStream_t)stream, nullptr);
 }
 
 rfd_status rfd_plan_check(rfd_plan_t p, rfd_stream_t stream) {

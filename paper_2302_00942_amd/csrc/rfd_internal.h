@@ -154,15 +154,28 @@ int slice_width(int dev_m, bool gram);
 // Host overflow guard of the core (exact bound |lambda| N sum|w| / f on the
 // spectral norm of lambda M, checked when some lambda w_k > 0).
 bool range_exceeded(const rfd_plan_s* p, int64_t N);
-rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_t st);
+// A side stream on which phi_1 runs between two events (see enqueue_phi1).
+struct PhiLane {
+  hipStream_t st;
+  hipEvent_t before, after;
+};
+rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_t st, const PhiLane* lane);
 // Channels [first_channel_done, d) of out = rowscale . (F + A S B^T F) (rowscale may be null).
 rfd_status integrate_enqueue(rfd_plan_s* p, const float* F, int64_t ldF, int d, float* out, int64_t ldO,
                              hipStream_t st, int first_channel_done, const float* rowscale);
 rfd_status oneshot_enqueue(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF, int d,
-                           float* out, int64_t ldO, hipStream_t st);
+                           float* out, int64_t ldO, hipStream_t st, const PhiLane* lane);
 rfd_status check_field_args(int64_t N, const float* F, int64_t ldF, int d, const float* out, int64_t ldO);
 // Partial-buffer floats a pass over N points with d channels needs.
 size_t partial_floats_needed(const rfd_plan_s* p, int64_t N, int d, bool gram);
+size_t partial_floats_for(int M, int prec, int64_t N, int d, bool gram);
+// Largest partial buffer (floats) over the channel slices of one request.
+size_t request_partial_floats(int M, int prec, int64_t N, int d, bool oneshot);
+int padded_m(int m);                       // device feature count: 64, 128 or 256
+size_t plan_fixed_bytes(int M);            // device bytes of a plan before any cloud
+size_t plan_device_bytes(const rfd_plan_s* p);
+rfd_status check_params(const rfd_params* p);
+void free_plan_device(rfd_plan_s* p);      // frees the plan and its buffers without a device-wide wait
 size_t bta_partial_floats(int m, int d, bool gram);              // floats per partial
 size_t reduce_scratch_doubles(int m);                            // level-1 reduction buffer
 

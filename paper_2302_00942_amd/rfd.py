@@ -78,6 +78,7 @@ def lib() -> C.CDLL:
             "rfd_server_create": ([C.c_size_t, i32, C.POINTER(vp)], i32),
             "rfd_submit": ([vp, C.POINTER(Request), C.POINTER(u64)], i32),
             "rfd_wait": ([vp, u64, dbl, C.POINTER(Result)], i32),
+            "rfd_server_stats": ([vp, vp, vp, vp, vp], i32),
             "rfd_server_destroy": ([vp], None),
             "rfd_profile_enable": ([C.c_int], None),
             "rfd_profile_read": ([vp, vp, i32, i32], i32),
@@ -318,6 +319,68 @@ class Loop:
         if getattr(self, "_h", None):
             lib().rfd_loop_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server (rfd_server_*): submit() waits for
+    torch's current stream (the server's streams are not ordered after it),
+    queues a request and returns its ticket; wait() returns (status,
+    t_submit, t_start, t_done). The tensors of a request are kept alive until
+    it has been waited for."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 8):
+        h = C.c_void_p()
+        _check(lib().rfd_server_create(int(hbm_budget_bytes), int(max_inflight), C.byref(h)), "rfd_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, X, F, out, m: int, eps: float, lam: float, seed: int = 0, precision="fp32", shape="ball",
+               cloud_key: int = 0, sigma: float = 0.0, radius: float = 0.0) -> int:
+        X = _dev_f32(X, "X", 3)
+        F = _dev_f32(F, "F")
+        out = _dev_f32(out, "out", F.shape[1])
+        if X.stride(0) != 3 or X.shape[0] != F.shape[0] or out.shape[0] != F.shape[0]:
+            raise ValueError("X must be contiguous N x 3 and F, out N x d")
+        r = Request()
+        r.X, r.N, r.F, r.ldF, r.d, r.reserved = X.data_ptr(), X.shape[0], F.data_ptr(), F.stride(0), F.shape[1], 0
+        r.out, r.ldO = out.data_ptr(), out.stride(0)
+        r.params, _ = make_params(m, eps, lam, seed, shape, precision, sigma, radius)
+        r.cloud_key = int(cloud_key)
+        # the server's streams do not wait for torch's: the inputs must be complete now
+        import torch
+        torch.cuda.current_stream().synchronize()
+        t = C.c_uint64()
+        _check(lib().rfd_submit(self._h, C.byref(r), C.byref(t)), "rfd_submit")
+        self._keep[t.value] = (X, F, out)
+        return t.value
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        res = Result()
+        s = lib().rfd_wait(self._h, C.c_uint64(ticket), float(timeout), C.byref(res))
+        if s == NOT_READY:
+            return NOT_READY, None, None, None
+        if s == INVALID_ARG:  # unknown or already collected ticket
+            raise RfdError(s, "rfd_wait")
+        self._keep.pop(ticket, None)
+        return int(s), res.t_submit, res.t_start, res.t_done
+
+    def stats(self) -> dict:
+        b = C.c_size_t()
+        p, q, i = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().rfd_server_stats(self._h, C.byref(b), C.byref(p), C.byref(q), C.byref(i)), "rfd_server_stats")
+        return {"device_bytes": b.value, "plans": p.value, "queued": q.value, "inflight": i.value}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().rfd_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

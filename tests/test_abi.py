@@ -70,3 +70,23 @@ def test_null_arguments():
     assert L.rfd_plan_check(None, None) == rfd.INVALID_ARG
     L.rfd_plan_destroy(None)
     assert rfd.status_string(rfd.NONFINITE).startswith("non-finite")
+
+
+def test_server_loop_and_batch_argument_checks():
+    """Argument checks that return before any device call."""
+    L = rfd.lib()
+    h = C.c_void_p()
+    assert L.rfd_server_create(0, 4, C.byref(h)) == rfd.INVALID_ARG
+    assert L.rfd_server_create(1 << 30, 0, C.byref(h)) == rfd.INVALID_ARG
+    assert L.rfd_server_create(1 << 30, 65, C.byref(h)) == rfd.INVALID_ARG
+    assert L.rfd_server_create(1 << 30, 4, None) == rfd.INVALID_ARG
+    assert L.rfd_submit(None, None, None) == rfd.INVALID_ARG
+    assert L.rfd_wait(None, 1, 0.0, None) == rfd.INVALID_ARG
+    assert L.rfd_server_stats(None, None, None, None, None) == rfd.INVALID_ARG
+    L.rfd_server_destroy(None)
+    assert L.rfd_loop_create(None, None, 1, None, 1, 1, 1, C.byref(h)) == rfd.INVALID_ARG
+    assert L.rfd_loop_launch(None, None) == rfd.INVALID_ARG
+    L.rfd_loop_destroy(None)
+    assert L.rfd_batch_create(None, None, None, None, None, None, None, None, 0, C.byref(h)) == rfd.INVALID_ARG
+    assert L.rfd_batch_launch(None, None) == rfd.INVALID_ARG
+    assert L.rfd_integrate_scaled(None, None, 0, 0, None, 0, None, None) == rfd.INVALID_ARG
