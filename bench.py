@@ -140,6 +140,193 @@ def time_steps(fn, steps: int, warmup: int, torch):
     return wall / steps * 1e3, p(0.5), p(0.99)
 
 
+def n_partials(N: int) -> int:
+    """Split-N partition of a pass (a function of N only): chunks of 64 points,
+    at least 16 chunks per partial, at most 512 partials."""
+    chunks = (N + 63) // 64
+    return max(1, min(512, (chunks + 15) // 16))
+
+
+def replay_ms(launch, reps: int, torch, st):
+    """Average milliseconds of `launch(st)` over `reps` replays, timed with
+    events on the launch stream (after one eager launch and one capture)."""
+    with torch.cuda.stream(st):
+        launch(st)
+        launch(st)
+    st.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        launch(st)
+    b.record(st)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def bench_batch(torch, rfd, wl, reps: int):
+    """The 512 uneven clouds (N log-uniform in [1000, 65536], m = 128, d = 3,
+    BF16) as one batch replayed from its hipGraph, against the plain path: one
+    one-shot launch sequence per cloud, no batching, no graph."""
+    clouds = wl.uneven_batch()
+    res = {}
+    for prec in ("bf16", "fp32"):
+        plans = [rfd.Plan(c.m, c.eps, c.lam, c.seed, precision=prec) for c in clouds]
+        Xs = [torch.from_numpy(c.X).cuda() for c in clouds]
+        Fs = [torch.from_numpy(c.F).cuda() for c in clouds]
+        outs = [torch.empty_like(F) for F in Fs]
+        st = torch.cuda.Stream()
+        batch = rfd.Batch(plans, Xs, Fs, outs)
+        ms = replay_ms(lambda s: batch.launch(s), reps, torch, st)
+        bad = [p for p in plans if p.check() != rfd.OK]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            for p, X, F, o in zip(plans, Xs, Fs, outs):
+                p.oneshot(X, F, out=o)
+        torch.cuda.synchronize()
+        loop_ms = (time.perf_counter() - t0) / 2 * 1e3
+        pc = sum(c.n * c.d for c in clouds)
+        res[prec] = {"ms": round(ms, 4), "value": round(pc / (ms * 1e-3), 1),
+                     "per_cloud_loop_ms": round(loop_ms, 4), "speedup_vs_per_cloud_loop": round(loop_ms / ms, 3),
+                     "device_errors": len(bad)}
+        batch.close()
+        for p in plans:
+            p.close()
+    return {"workload": "512 clouds, N log-uniform in [1000, 65536] (sum %d), sphere/torus/ellipsoid, "
+                        "eps=0.05, lambda=-0.5, m=128, d=3; one-shot, graph replay" % sum(c.n for c in clouds),
+            "unit": "points*channels/s", **res}
+
+
+def bench_loop(torch, rfd, wl, reps: int):
+    """Repeated application: sphere and deformed torus of 100,000 points, m=128,
+    100 alternating scaled applications, graph-replayed; d = 1 and 32."""
+    n, iters = 100_000, 100
+    out = {}
+    for d in (32, 1):
+        clouds = wl.sinkhorn_pair(n=n, d=d, m=128, seed=0)
+        s0, s1 = wl.scaling_vectors(n, 1)
+        sd = [torch.from_numpy(s0).cuda(), torch.from_numpy(s1).cuda()]
+        for prec in ("bf16", "fp32"):
+            plans = [rfd.Plan(c.m, c.eps, c.lam, c.seed, precision=prec) for c in clouds]
+            for p, c in zip(plans, clouds):
+                p.features(torch.from_numpy(c.X).cuda())
+            v = torch.from_numpy(clouds[0].F).cuda()
+            loop = rfd.Loop(plans, sd, v, iters)
+            st = torch.cuda.Stream()
+            ms = replay_ms(lambda s: loop.launch(s), reps, torch, st)
+            it_us = ms * 1e3 / iters
+            # per iteration: X twice (24 B), v read twice and written once (12 d B), the scale (4 B)
+            gbs = (28 + 12 * d) * n / (it_us * 1e-6) / 1e9
+            out[f"d{d}_{prec}"] = {"us_per_iteration": round(it_us, 3),
+                                   "value": round(n * d / (it_us * 1e-6), 1),
+                                   "hbm_GBs_algorithmic": round(gbs, 1),
+                                   "hbm_frac": round(gbs / PEAK["hbm_GBs"], 4)}
+            loop.close()
+            for p in plans:
+                p.close()
+    return {"workload": "sphere + deformed torus, N=100000 each, eps=0.05, lambda=-0.5, m=128, "
+                        "100 alternating scaled applications in one hipGraph",
+            "unit": "points*channels/s", **out}
+
+
+def bench_serving(torch, rfd, wl, count: int, warm: int, pool: int = 64):
+    """Serving: a pool of clouds (N log-uniform in [2000, 200000], random
+    surface, m in {64, 128, 256}); each request integrates a fresh field of a
+    random width d in {3, 16, 64} on a random pool cloud (its cloud_key), so
+    plans and features stay resident once a cloud was seen. The saturation
+    rate is measured with a burst; then Poisson arrivals at 0.7 x that rate."""
+    import threading
+    g = np.random.default_rng(12345)
+    reqs = wl.poisson_requests(pool, 1.0, 777)
+    clouds = [(torch.from_numpy(wl.surface(q["surface"], q["n"], q["seed"])).cuda(), q["m"]) for q in reqs]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    fields = {}
+    for ci, (X, m) in enumerate(clouds):
+        for d in (3, 16, 64):
+            fields[ci, d] = torch.randn((X.shape[0], d), device="cuda", generator=gen)
+    ring = 64
+    outbuf = [torch.empty(200_000 * 64, device="cuda") for _ in range(ring)]
+    total = warm + 2 * count
+    picks = [(int(g.integers(0, pool)), int(g.choice((3, 16, 64)))) for _ in range(total)]
+    gaps = g.exponential(1.0, total)
+    res = {}
+    for prec in ("bf16", "fp32"):
+        srv = rfd.Server(32 << 30, 16)
+        done = [None] * total
+        cv = threading.Condition()
+        tickets = [None] * total
+        state = {"collected": 0}
+
+        def collector():
+            for i in range(total):
+                with cv:
+                    while tickets[i] is None:
+                        cv.wait()
+                    t = tickets[i]
+                done[i] = srv.wait(t)
+                with cv:
+                    state["collected"] = i + 1
+                    cv.notify_all()
+
+        th = threading.Thread(target=collector)
+        th.start()
+
+        def submit(i):
+            ci, d = picks[i]
+            with cv:
+                while state["collected"] < i - ring + 1:
+                    cv.wait()
+            X, m = clouds[ci]
+            F = fields[ci, d]
+            o = outbuf[i % ring][: X.shape[0] * d].view(X.shape[0], d)
+            t = srv.submit(X, F, o, m, 0.05, -0.5, seed=m, precision=prec, cloud_key=ci + 1)
+            with cv:
+                tickets[i] = t
+                cv.notify_all()
+
+        torch.cuda.synchronize()
+        for i in range(warm):  # every pool cloud's plan and features become resident
+            submit(i)
+        with cv:
+            while state["collected"] < warm:
+                cv.wait()
+        # saturation: a burst of `count` requests
+        for i in range(warm, warm + count):
+            submit(i)
+        with cv:
+            while state["collected"] < warm + count:
+                cv.wait()
+        burst = done[warm:warm + count]
+        sat = count / (max(r[3] for r in burst) - min(r[1] for r in burst))
+        qps = 0.7 * sat
+        # Poisson arrivals at 0.7 x saturation
+        t0 = time.perf_counter()
+        t_arr = t0
+        for k, i in enumerate(range(warm + count, total)):
+            t_arr += gaps[i] / qps
+            while time.perf_counter() < t_arr:
+                pass
+            submit(i)
+        th.join()
+        meas = done[warm + count:]
+        assert all(r[0] == rfd.OK for r in done), "a served request failed"
+        lat = sorted((r[3] - r[1]) * 1e3 for r in meas)
+        q = lambda f: lat[min(len(lat) - 1, int(math.ceil(f * len(lat))) - 1)]
+        span = max(r[3] for r in meas) - min(r[1] for r in meas)
+        pc = sum(clouds[picks[i][0]][0].shape[0] * picks[i][1] for i in range(warm + count, total))
+        st = srv.stats()
+        res[prec] = {"saturation_rps": round(sat, 1), "offered_qps": round(qps, 1),
+                     "achieved_rps": round(len(meas) / span, 1), "value": round(pc / span, 1),
+                     "p50_ms": round(q(0.5), 4), "p99_ms": round(q(0.99), 4),
+                     "resident_plans": st["plans"], "device_bytes": st["device_bytes"]}
+        srv.close()
+    return {"workload": f"{pool} pool clouds N log-uniform [2000, 200000], random surface, m in {{64,128,256}}, "
+                        f"d in {{3,16,64}}, eps=0.05, lambda=-0.5; {warm} warm-up, {count}-request burst for "
+                        f"saturation, {count} Poisson requests at 0.7 x saturation; 16 in flight, 32 GiB budget",
+            "unit": "points*channels/s", **res}
+
+
 def cpu_baseline(cloud):
     from threadpoolctl import threadpool_info
     from oracle import rfd_oracle as o
@@ -156,6 +343,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (and the error check)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched, repeated-application and serving measurements")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests of the serving leg")
     ap.add_argument("--n", type=int, default=1_000_000, help=argparse.SUPPRESS)
     ap.add_argument("--dump-inputs", metavar="DIR", help="write the cloud for paper_2302_00942_amd/rfd_run and exit")
     args = ap.parse_args()
@@ -238,12 +428,16 @@ def main() -> int:
         line.setdefault("kernels_us", {})[prec] = {k: round(v[0] / v[1] * 1e3, 2) for k, v in kern.items()}
     kern = res["bf16"]["kern"]
     from paper_2302_00942_amd.rfd import lib  # noqa: F401
-    nparts = min(512, (N + 63) // 64)
+    nparts = n_partials(N)
     dom = max(kern.items(), key=lambda kv: kv[1][0])[0]
     line["roofline"] = roofline(dom, kern[dom][0] / kern[dom][1], N, m, d, res["bf16"]["s"], nparts, "bf16",
                                 workload)
     line["roofline_all"] = {k: roofline(k, v[0] / v[1], N, m, d, res["bf16"]["s"], nparts, "bf16", workload)
                             for k, v in kern.items() if k in KERNEL_SOURCES}
+    if not args.no_extras:
+        line["batched"] = bench_batch(torch, rfd, wl, max(5, args.steps))
+        line["repeated_application"] = bench_loop(torch, rfd, wl, max(5, args.steps // 2))
+        line["serving"] = bench_serving(torch, rfd, wl, args.serve_requests, 500)
     if not args.no_cpu_baseline:
         from oracle import rfd_oracle as o
         ref, t, threads = cpu_baseline(cloud)

@@ -183,6 +183,20 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
  * findings are reported by rfd_plan_check on each plan. */
 rfd_status rfd_batch_launch(rfd_batch_t batch, rfd_stream_t stream);
 
+/* Autotunes the batch's expansion geometry (tiles of 16 points per
+ * workgroup: 8 ... 256): runs the batch once eagerly, then times `reps`
+ * expansion launches per candidate with hipEvents on `stream`, keeps the
+ * fastest for this batch and records it in the process-wide tuning table
+ * (key: m, precision, channel blocks, log2 of the batch's total points) for
+ * batches created later. The geometry never changes results. The outputs
+ * hold the batch's result on return; the next launch records a new graph.
+ * Errors: RFD_ERR_INVALID_ARG (reps < 1, an out aliasing its F, stale plan
+ * buffers), RFD_ERR_DEVICE. */
+rfd_status rfd_batch_tune(rfd_batch_t batch, int32_t reps, rfd_stream_t stream);
+
+/* The batch's current expansion tiles per workgroup. */
+int32_t rfd_batch_tiles_per_item(rfd_batch_t batch);
+
 /* Waits for the device and frees the batch (not the plans). */
 void rfd_batch_destroy(rfd_batch_t batch);
 
@@ -190,6 +204,32 @@ void rfd_batch_destroy(rfd_batch_t batch);
 rfd_status rfd_integrate_batch(const rfd_plan_t* plans, const float* const* Xs, const int64_t* Ns,
                                const float* const* Fs, const int64_t* ldFs, const int32_t* ds,
                                float* const* outs, const int64_t* ldOs, int32_t n, rfd_stream_t stream);
+
+/* --------------------------------------------------------------- autotuning */
+
+/* Autotunes the expansion geometry (tiles of 16 points per wave: 1 ... 16) of
+ * rfd_integrate for this plan's cloud and field width: computes G for the
+ * first channel slice, times `reps` expansion launches per candidate with
+ * hipEvents on `stream`, and records the fastest in the process-wide tuning
+ * table (key: m, precision, channel blocks, log2 N), which every later
+ * launch of that key uses (graphs already recorded keep their geometry).
+ * The geometry never changes results. On return (enqueued) out holds
+ * rfd_integrate(F). Errors: those of rfd_integrate; RFD_ERR_INVALID_ARG for
+ * reps < 1 or out == F. */
+rfd_status rfd_autotune(rfd_plan_t plan, const float* F_dev, int64_t ldF, int32_t d,
+                        float* out_dev, int64_t ldO, int32_t reps, rfd_stream_t stream);
+
+/* Writes the tuning table as text, one entry per line
+ * "knob m precision channel_blocks log2N value", into buf (with a final NUL)
+ * when cap is large enough; returns the bytes needed. */
+int32_t rfd_tune_export(char* buf, int32_t cap);
+
+/* Merges entries in the export format into the table; the whole text is
+ * validated first (RFD_ERR_INVALID_ARG leaves the table unchanged). */
+rfd_status rfd_tune_import(const char* text);
+
+/* Clears the tuning table (defaults apply again). */
+void rfd_tune_reset(void);
 
 /* ------------------------------------------------------ repeated application */
 

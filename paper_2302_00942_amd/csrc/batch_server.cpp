@@ -9,7 +9,11 @@
 #include "rfd_internal.h"
 
 struct rfd_batch_s {
-  int n = 0, M = 0, prec = 0, DB = 1, dmax = 0;
+  int n = 0, M = 0, prec = 0, DB = 1, dmax = 0, tpi = 64;
+  bool aliased = false;  // some out aliases its F (the batch is then not re-runnable)
+  int64_t total_n = 0;
+  std::vector<int64_t> Ns;
+  int exp_cap = 0;  // capacity of dwork_exp in items
   int64_t nmax_copy = 0;
   std::vector<rfd_plan_s*> plans;
   rfd::CloudDesc* dcl = nullptr;
@@ -31,6 +35,16 @@ namespace {
     if ((x) != hipSuccess) return RFD_ERR_DEVICE; \
   } while (0)
 
+// Expansion work items: (cloud, first tile) every `tpi` tiles of 16 points.
+std::vector<int2> expand_work(const std::vector<int64_t>& Ns, int tpi) {
+  std::vector<int2> we;
+  for (int i = 0; i < (int)Ns.size(); ++i) {
+    const int64_t ntiles = (Ns[i] + 15) / 16;
+    for (int64_t t0 = 0; t0 < ntiles; t0 += tpi) we.push_back(make_int2(i, (int)t0));
+  }
+  return we;
+}
+
 void free_batch(rfd_batch_s* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -46,7 +60,8 @@ rfd_status enqueue(rfd_batch_s* b, hipStream_t st) {
   HIPCK(rfd::launch_reduce_batch(b->M, b->DB, b->dcl, b->n, st));
   HIPCK(rfd::launch_phi1_batch_dev(b->M, b->n, b->dargs, st));
   HIPCK(rfd::launch_gcore_batch(b->M, b->dmax, b->dcl, b->n, st));
-  if (b->nwork_exp > 0) HIPCK(rfd::launch_expand_batch(b->M, b->prec, b->DB, b->dcl, b->dwork_exp, b->nwork_exp, st));
+  if (b->nwork_exp > 0)
+    HIPCK(rfd::launch_expand_batch(b->M, b->prec, b->DB, b->dcl, b->dwork_exp, b->nwork_exp, b->tpi, st));
   return RFD_OK;
 }
 
@@ -92,10 +107,16 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
   b->DB = rfd::dblocks(dmax);
   b->plans.assign(plans, plans + n);
   const size_t stride = rfd::bta_partial_floats(M, 16 * b->DB, true);
-  const int tpi = rfd::expand_tiles_per_item();
+  for (int i = 0; i < n; ++i) {
+    b->Ns.push_back(Ns[i]);
+    b->total_n += Ns[i];
+    if ((const float*)outs[i] == Fs[i]) b->aliased = true;
+  }
+  b->tpi = rfd::tuned(rfd::kTuneBatchExpandTilesPerItem, M, prec, b->DB, b->total_n,
+                      rfd::default_batch_tiles_per_item());
   std::vector<rfd::CloudDesc> cl(n);
   std::vector<rfd::CopyDesc> cp(n);
-  std::vector<int2> wb, we;
+  std::vector<int2> wb;
   std::vector<unsigned char> args(rfd::phi1_args_bytes() * n);
   for (int i = 0; i < n; ++i) {
     rfd_plan_s* p = plans[i];
@@ -129,16 +150,16 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
     cp[i] = rfd::CopyDesc{Xs[i], p->dev.X, 3 * N};
     b->nmax_copy = std::max<int64_t>(b->nmax_copy, 3 * N);
     for (int q = 0; q < np; ++q) wb.push_back(make_int2(i, q));
-    const int64_t ntiles = (N + 15) / 16;
-    for (int64_t t0 = 0; t0 < ntiles; t0 += tpi) we.push_back(make_int2(i, (int)t0));
     rfd::phi1_fill_args(p, args.data() + rfd::phi1_args_bytes() * i);
   }
   for (int i = 0; i < n; ++i) {
     b->bound.push_back(plans[i]->dev.X);
     b->bound.push_back(plans[i]->dev.partials);
   }
+  const std::vector<int2> we = expand_work(b->Ns, b->tpi);
   b->nwork_bta = (int)wb.size();
   b->nwork_exp = (int)we.size();
+  b->exp_cap = b->nwork_exp;
   bool ok = upload(&b->dcl, cl) == hipSuccess && upload(&b->dcp, cp) == hipSuccess &&
             upload(&b->dwork_bta, wb) == hipSuccess && upload(&b->dwork_exp, we) == hipSuccess &&
             upload((unsigned char**)&b->dargs, args) == hipSuccess;
@@ -184,6 +205,71 @@ rfd_status rfd_batch_launch(rfd_batch_t b, rfd_stream_t stream) {
   HIPCK(hipGraphLaunch(b->exec, st));
   return RFD_OK;
 }
+
+rfd_status rfd_batch_tune(rfd_batch_t b, int32_t reps, rfd_stream_t stream) {
+  if (!b || reps < 1 || b->aliased) return RFD_ERR_INVALID_ARG;
+  for (int i = 0; i < b->n; ++i)
+    if (b->plans[i]->dev.X != b->bound[2 * i] || b->plans[i]->dev.partials != b->bound[2 * i + 1])
+      return RFD_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  // one full eager pass leaves every cloud's G in place; the expansion is
+  // then re-run with each candidate geometry (it rewrites the same outputs)
+  rfd_status s = enqueue(b, st);
+  if (s != RFD_OK || b->nwork_exp == 0) return s;
+  static const int cands[] = {8, 16, 32, 64, 128, 256};
+  const std::vector<int2> most = expand_work(b->Ns, cands[0]);
+  int2* dw = nullptr;
+  HIPCK(hipMalloc((void**)&dw, sizeof(int2) * most.size()));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = b->tpi;
+  float best_ms = 1e30f;
+  bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  for (int c = 0; ok && c < (int)(sizeof(cands) / sizeof(cands[0])); ++c) {
+    const std::vector<int2> we = expand_work(b->Ns, cands[c]);
+    // (the previous candidate's launches have finished: its end event was waited on)
+    ok = hipMemcpyAsync(dw, we.data(), sizeof(int2) * we.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+         hipStreamSynchronize(st) == hipSuccess &&
+         rfd::launch_expand_batch(b->M, b->prec, b->DB, b->dcl, dw, (int)we.size(), cands[c], st) == hipSuccess &&
+         hipEventRecord(e0, st) == hipSuccess;
+    for (int r = 0; ok && r < reps; ++r)
+      ok = rfd::launch_expand_batch(b->M, b->prec, b->DB, b->dcl, dw, (int)we.size(), cands[c], st) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ok && ms < best_ms) {
+      best_ms = ms;
+      best = cands[c];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(dw);
+  if (!ok) return RFD_ERR_DEVICE;
+  rfd::set_tuned(rfd::kTuneBatchExpandTilesPerItem, b->M, b->prec, b->DB, b->total_n, best);
+  if (best != b->tpi) {
+    const std::vector<int2> we = expand_work(b->Ns, best);
+    if ((int)we.size() > b->exp_cap) {
+      (void)hipFree(b->dwork_exp);
+      b->dwork_exp = nullptr;
+      HIPCK(hipMalloc((void**)&b->dwork_exp, sizeof(int2) * we.size()));
+      b->exp_cap = (int)we.size();
+    }
+    HIPCK(hipMemcpy(b->dwork_exp, we.data(), sizeof(int2) * we.size(), hipMemcpyHostToDevice));
+    b->nwork_exp = (int)we.size();
+    b->tpi = best;
+    // the recorded graph holds the old geometry: record again on the next launch
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->launches = 1;
+  }
+  // the outputs hold the batch's result (every candidate rewrote them from the same G)
+  return RFD_OK;
+}
+
+int32_t rfd_batch_tiles_per_item(rfd_batch_t b) { return b ? b->tpi : 0; }
 
 void rfd_batch_destroy(rfd_batch_t b) {
   if (!b) return;

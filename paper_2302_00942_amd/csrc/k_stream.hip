@@ -126,13 +126,17 @@ size_t bta_partial_floats(int m, int d, bool gram) {
 }
 
 // Number of partials (= workgroups) of a split-N pass over N points: at
-// least kMinChunksPerPart chunks per partial, at most 512 partials. A
-// function of N only, so a cloud gets the same partition alone and in a batch.
-constexpr int kMinChunksPerPart = 16;
+// least 16 chunks per partial when the pass carries the Gram (its partials
+// are m(m+1)/2 floats, so fewer of them), 2 otherwise; at most 512 partials.
+// A function of N and the pass kind only, so a cloud gets the same partition
+// alone and in a batch.
+constexpr int kMinChunksPerPartGram = 16;
+constexpr int kMinChunksPerPart = 2;
 int bta_partials(int64_t N, int m, int d, bool gram, int prec) {
-  (void)m; (void)d; (void)gram; (void)prec;
+  (void)m; (void)d; (void)prec;
   const int64_t chunks = (N + kChunk - 1) / kChunk;
-  int64_t parts = (chunks + kMinChunksPerPart - 1) / kMinChunksPerPart;
+  const int per = gram ? kMinChunksPerPartGram : kMinChunksPerPart;
+  int64_t parts = (chunks + per - 1) / per;
   if (parts > 512) parts = 512;
   if (parts < 1) parts = 1;
   return (int)parts;
@@ -635,15 +639,15 @@ __global__ __launch_bounds__(256) void k_expand(const float* __restrict__ X, int
 }
 
 // Batched expansion: one workgroup per (cloud, first tile) work item, each
-// covering kExpandTilesPerItem tiles of 16 points.
-constexpr int kExpandTilesPerItem = 64;
-int expand_tiles_per_item() { return kExpandTilesPerItem; }
+// covering `tpi` tiles of 16 points (a launch-geometry choice: any tpi gives
+// the same result).
 template <int M, int PREC, int DB>
-__global__ __launch_bounds__(256) void k_expand_batch(const CloudDesc* __restrict__ cl, const int2* __restrict__ work) {
+__global__ __launch_bounds__(256) void k_expand_batch(const CloudDesc* __restrict__ cl, const int2* __restrict__ work,
+                                                      int tpi) {
   const int2 wi = work[blockIdx.x];
   const CloudDesc& c = cl[wi.x];
   const int64_t ntiles = (c.N + 15) / 16;
-  int64_t t_end = (int64_t)wi.y + kExpandTilesPerItem;
+  int64_t t_end = (int64_t)wi.y + tpi;
   if (t_end > ntiles) t_end = ntiles;
   expand_body<M, PREC, DB>(c.X, c.N, c.om, c.G32, c.Gt16, c.d, c.F, c.ldF, c.out, c.ldO, nullptr, wi.y, t_end, 4);
 }
@@ -760,7 +764,9 @@ hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* 
   const int M = p->dev_m, prec = p->params.precision;
   const int DB = dblocks(d);
   const int64_t ntiles = (N + 15) / 16;
-  int64_t nwg = (ntiles + 3) / 4;
+  // tiles of 16 points per wave: launch geometry only (results do not depend on it)
+  const int tpw = tuned(kTuneExpandTilesPerWave, M, prec, DB, N, default_expand_tiles_per_wave(N));
+  int64_t nwg = (ntiles + 4 * tpw - 1) / (4 * tpw);
   if (nwg > 2048) nwg = 2048;
   if (nwg < 1) nwg = 1;
   dim3 grid((unsigned)nwg);
@@ -849,16 +855,17 @@ hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hi
 }
 
 template <int M, int PREC>
-static hipError_t expand_batch_db(int DB, int nwork, const CloudDesc* dcl, const int2* dwork, hipStream_t st) {
+static hipError_t expand_batch_db(int DB, int nwork, const CloudDesc* dcl, const int2* dwork, int tpi,
+                                  hipStream_t st) {
   switch (DB) {
     case 1:
-      hipLaunchKernelGGL((k_expand_batch<M, PREC, 1>), dim3(nwork), dim3(256), 0, st, dcl, dwork);
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 1>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
       break;
     case 2:
-      hipLaunchKernelGGL((k_expand_batch<M, PREC, 2>), dim3(nwork), dim3(256), 0, st, dcl, dwork);
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 2>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
       break;
     case 4:
-      hipLaunchKernelGGL((k_expand_batch<M, PREC, 4>), dim3(nwork), dim3(256), 0, st, dcl, dwork);
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 4>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
       break;
     default:
       return hipErrorInvalidValue;
@@ -866,12 +873,12 @@ static hipError_t expand_batch_db(int DB, int nwork, const CloudDesc* dcl, const
   return hipGetLastError();
 }
 
-hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork,
+hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, int tpi,
                                hipStream_t st) {
   ProfileScope prof(kKExpandBatch, st);
-  if (M == 64) return prec ? expand_batch_db<64, 1>(DB, nwork, dcl, dwork, st) : expand_batch_db<64, 0>(DB, nwork, dcl, dwork, st);
-  if (M == 128) return prec ? expand_batch_db<128, 1>(DB, nwork, dcl, dwork, st) : expand_batch_db<128, 0>(DB, nwork, dcl, dwork, st);
-  if (M == 256) return prec ? expand_batch_db<256, 1>(DB, nwork, dcl, dwork, st) : expand_batch_db<256, 0>(DB, nwork, dcl, dwork, st);
+  if (M == 64) return prec ? expand_batch_db<64, 1>(DB, nwork, dcl, dwork, tpi, st) : expand_batch_db<64, 0>(DB, nwork, dcl, dwork, tpi, st);
+  if (M == 128) return prec ? expand_batch_db<128, 1>(DB, nwork, dcl, dwork, tpi, st) : expand_batch_db<128, 0>(DB, nwork, dcl, dwork, tpi, st);
+  if (M == 256) return prec ? expand_batch_db<256, 1>(DB, nwork, dcl, dwork, tpi, st) : expand_batch_db<256, 0>(DB, nwork, dcl, dwork, tpi, st);
   return hipErrorInvalidValue;
 }
 

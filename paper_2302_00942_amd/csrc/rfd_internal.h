@@ -138,12 +138,17 @@ hipError_t launch_copy_points_batch(const CopyDesc* dcp, int ncl, int64_t nmax, 
 hipError_t launch_bta_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, hipStream_t st);
 hipError_t launch_reduce_batch(int M, int DB, const CloudDesc* dcl, int ncl, hipStream_t st);
 hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hipStream_t st);
-hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork,
+hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, int tpi,
                                hipStream_t st);
 hipError_t launch_phi1_batch_dev(int M, int n, const void* dev_args, hipStream_t st);
 void phi1_fill_args(rfd_plan_s* p, void* args_out);  // writes one Phi1Args
 int dblocks(int d);
-int expand_tiles_per_item();
+// Launch-geometry tuning (autotune.cpp): knobs that change speed, never results.
+enum TuneKnob { kTuneExpandTilesPerWave = 0, kTuneBatchExpandTilesPerItem = 1, kNumTuneKnobs };
+int tuned(int knob, int M, int prec, int DB, int64_t N, int fallback);
+void set_tuned(int knob, int M, int prec, int DB, int64_t N, int value);
+int default_expand_tiles_per_wave(int64_t N);
+int default_batch_tiles_per_item();
 void set_capturing(bool on);  // suspends per-kernel timing during graph capture
 int bta_partials(int64_t N, int m, int d, bool gram, int prec);  // number of workgroups / partials
 size_t phi1_args_bytes();

@@ -166,12 +166,19 @@ bool admit_head(rfd_server_s* S) {
         resident = true;
         break;
       }
-  if (!e)
-    for (Entry* c : S->entries)
-      if (c->busy == 0 && same_params(c->plan->params, r.params) && (!e || c->last_use < e->last_use)) e = c;
   const size_t pf = rfd::request_partial_floats(M, prec, r.N, r.d, !resident);
-  size_t need = e ? grow_bytes(e->plan, r.N, pf, !resident)
-                  : rfd::plan_fixed_bytes(M) + sizeof(float) * 3 * (size_t)r.N + sizeof(float) * pf;
+  const size_t need_new = rfd::plan_fixed_bytes(M) + sizeof(float) * 3 * (size_t)r.N + sizeof(float) * pf;
+  // a new cloud takes an idle plan with the same parameters that holds no
+  // features worth keeping; else a new plan while the budget allows; else
+  // the least recently used idle plan with the same parameters
+  for (int pass = 0; !e && pass < 2; ++pass) {
+    if (pass == 1 && S->bytes + need_new <= S->budget) break;
+    for (Entry* c : S->entries)
+      if (c->busy == 0 && same_params(c->plan->params, r.params) && (pass == 1 || c->cloud_key == 0) &&
+          (!e || c->last_use < e->last_use))
+        e = c;
+  }
+  size_t need = e ? grow_bytes(e->plan, r.N, pf, !resident) : need_new;
   if (e && need > 0 && e->busy) return false;  // a busy plan grows only once idle
   while (S->bytes + need > S->budget) {
     Entry* victim = nullptr;

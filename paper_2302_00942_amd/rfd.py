@@ -75,6 +75,12 @@ def lib() -> C.CDLL:
             "rfd_batch_create": ([vp, vp, vp, vp, vp, vp, vp, vp, i32, C.POINTER(vp)], i32),
             "rfd_batch_launch": ([vp, vp], i32),
             "rfd_batch_destroy": ([vp], None),
+            "rfd_batch_tune": ([vp, i32, vp], i32),
+            "rfd_batch_tiles_per_item": ([vp], i32),
+            "rfd_autotune": ([vp, vp, i64, i32, vp, i64, i32, vp], i32),
+            "rfd_tune_export": ([vp, i32], i32),
+            "rfd_tune_import": ([C.c_char_p], i32),
+            "rfd_tune_reset": ([], None),
             "rfd_server_create": ([C.c_size_t, i32, C.POINTER(vp)], i32),
             "rfd_submit": ([vp, C.POINTER(Request), C.POINTER(u64)], i32),
             "rfd_wait": ([vp, u64, dbl, C.POINTER(Result)], i32),
@@ -217,6 +223,14 @@ class Plan:
         self.N = X.shape[0]
         return out
 
+    def autotune(self, F, out, reps: int = 10, stream=None):
+        """Tunes the expansion geometry for this cloud and F's width; out gets integrate(F)."""
+        F = _dev_f32(F, "F")
+        out = _dev_f32(out, "out", F.shape[1])
+        _check(lib().rfd_autotune(self._h, F.data_ptr(), F.stride(0), F.shape[1], out.data_ptr(), out.stride(0),
+                                  int(reps), _stream_handle(stream)), "rfd_autotune")
+        return out
+
     def check(self, stream=None) -> int:
         """Synchronises and returns the device status code (OK, NONFINITE, RANGE, DEVICE)."""
         return int(lib().rfd_plan_check(self._h, _stream_handle(stream)))
@@ -273,6 +287,11 @@ class Batch:
 
     def launch(self, stream=None) -> None:
         _check(lib().rfd_batch_launch(self._h, _stream_handle(stream)), "rfd_batch_launch")
+
+    def tune(self, reps: int = 5, stream=None) -> int:
+        """Autotunes the expansion tiles per workgroup; returns the chosen value."""
+        _check(lib().rfd_batch_tune(self._h, int(reps), _stream_handle(stream)), "rfd_batch_tune")
+        return int(lib().rfd_batch_tiles_per_item(self._h))
 
     def close(self) -> None:
         if getattr(self, "_h", None):
@@ -387,6 +406,21 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def tune_export() -> str:
+    n = lib().rfd_tune_export(None, 0)
+    buf = C.create_string_buffer(n)
+    lib().rfd_tune_export(buf, n)
+    return buf.value.decode()
+
+
+def tune_import(text: str) -> None:
+    _check(lib().rfd_tune_import(text.encode()), "rfd_tune_import")
+
+
+def tune_reset() -> None:
+    lib().rfd_tune_reset()
 
 
 def profile_enable(on: bool) -> None:

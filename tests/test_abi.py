@@ -90,3 +90,23 @@ def test_server_loop_and_batch_argument_checks():
     assert L.rfd_batch_create(None, None, None, None, None, None, None, None, 0, C.byref(h)) == rfd.INVALID_ARG
     assert L.rfd_batch_launch(None, None) == rfd.INVALID_ARG
     assert L.rfd_integrate_scaled(None, None, 0, 0, None, 0, None, None) == rfd.INVALID_ARG
+
+
+def test_tuning_table_text_round_trip():
+    """The launch-geometry table (host only): import validates the whole text,
+    export lists the entries, reset clears them."""
+    rfd.tune_reset()
+    assert rfd.tune_export() == ""
+    rfd.tune_import("0 256 1 1 20 8\n1 128 1 1 23 32\n")
+    txt = rfd.tune_export()
+    assert txt.splitlines() == ["0 256 1 1 20 8", "1 128 1 1 23 32"]
+    for bad in ("0 256 1 1 20\n", "9 256 1 1 20 8\n", "0 100 1 1 20 8\n", "0 256 1 3 20 8\n",
+                "0 256 1 1 20 0\n", "0 256 1 1 20 8\nxyz\n"):
+        with pytest.raises(rfd.RfdError) as e:
+            rfd.tune_import(bad)
+        assert e.value.status == rfd.INVALID_ARG
+    assert rfd.tune_export() == txt  # rejected imports change nothing
+    rfd.tune_import(txt.replace(" 8\n", " 4\n"))
+    assert rfd.tune_export().splitlines()[0] == "0 256 1 1 20 4"
+    rfd.tune_reset()
+    assert rfd.tune_export() == ""

@@ -136,3 +136,39 @@ def test_uneven_batch_512_clouds(torch_cuda):
         print(f"512-batch cloud {i} N={c.n}: relF={e:.3e}")
         assert e <= 2e-3
     b.close()
+
+
+def test_batch_tune_keeps_results(torch_cuda):
+    """Tuning the batched expansion geometry changes no bit of the outputs;
+    the graph recorded after tuning replays the same results."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    rfd.tune_reset()
+    clouds = wl.uneven_batch(count=40, seed=4)
+    plans = [rfd.Plan(c.m, c.eps, c.lam, c.seed, precision="bf16") for c in clouds]
+    Xs = [torch.from_numpy(c.X).cuda() for c in clouds]
+    Fs = [torch.from_numpy(c.F).cuda() for c in clouds]
+    outs = [torch.empty_like(F) for F in Fs]
+    b = rfd.Batch(plans, Xs, Fs, outs)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        b.launch(st)
+    st.synchronize()
+    ref = [o_.cpu().numpy() for o_ in outs]
+    for o_ in outs:
+        o_.fill_(float("nan"))
+    torch.cuda.synchronize()
+    tpi = b.tune(reps=2, stream=st)
+    st.synchronize()
+    print(f"tuned tiles per item: {tpi}")
+    assert all(np.array_equal(r, o_.cpu().numpy()) for r, o_ in zip(ref, outs))
+    for _ in range(3):  # record after tuning, then replays
+        for o_ in outs:
+            o_.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(st):
+            b.launch(st)
+        st.synchronize()
+        assert all(np.array_equal(r, o_.cpu().numpy()) for r, o_ in zip(ref, outs))
+    b.close()
+    rfd.tune_reset()

@@ -101,15 +101,30 @@ def test_resident_features_are_reused(torch_cuda):
     assert srv.wait(t1)[0] == rfd.OK and srv.wait(t2)[0] == rfd.OK
     assert srv.stats()["plans"] == 1
     plan = rfd.Plan(c.m, c.eps, c.lam, c.seed, precision="bf16")
-    assert np.array_equal(plan.oneshot(X, F1).cpu().numpy(), o1.cpu().numpy())
-    assert np.array_equal(plan.oneshot(X, F2).cpu().numpy(), o2.cpu().numpy())
-    # the same parameters on another cloud reuse the idle plan's buffers
+    assert np.array_equal(plan.oneshot(X, F1).cpu().numpy(), o1.cpu().numpy())  # first request: one-shot
+    res = rfd.Plan(c.m, c.eps, c.lam, c.seed, precision="bf16")
+    res.features(X)
+    assert np.array_equal(res.integrate(F2).cpu().numpy(), o2.cpu().numpy())  # resident: integrate only
+    # another cloud without a key gets its own plan while the budget allows
+    # (the resident features of cloud 42 are kept) ...
     Y = torch.from_numpy(wl.torus(20000, 5)).cuda()
     G = torch.from_numpy(wl.field(20000, 3, 6)).cuda()
     o3 = torch.empty_like(G)
     assert srv.wait(srv.submit(Y, G, o3, c.m, c.eps, c.lam, c.seed, "bf16"))[0] == rfd.OK
-    assert srv.stats()["plans"] == 1
+    assert srv.stats()["plans"] == 2
     assert np.array_equal(plan.oneshot(Y, G).cpu().numpy(), o3.cpu().numpy())
+    # ... and a further keyless cloud reuses that idle keyless plan's buffers
+    Z = torch.from_numpy(wl.ellipsoid(15000, 7)).cuda()
+    H = torch.from_numpy(wl.field(15000, 5, 8)).cuda()
+    o4 = torch.empty_like(H)
+    assert srv.wait(srv.submit(Z, H, o4, c.m, c.eps, c.lam, c.seed, "bf16"))[0] == rfd.OK
+    assert srv.stats()["plans"] == 2
+    assert np.array_equal(plan.oneshot(Z, H).cpu().numpy(), o4.cpu().numpy())
+    # cloud 42 is still resident: a third field on it runs the integrate passes only
+    o5 = torch.empty_like(F1)
+    assert srv.wait(srv.submit(X, F1, o5, c.m, c.eps, c.lam, c.seed, "bf16", cloud_key=42))[0] == rfd.OK
+    assert srv.stats()["plans"] == 2
+    assert np.array_equal(res.integrate(F1).cpu().numpy(), o5.cpu().numpy())
     srv.close()
 
 
