@@ -176,6 +176,7 @@ def bench_batch(torch, rfd, wl, reps: int):
         outs = [torch.empty_like(F) for F in Fs]
         st = torch.cuda.Stream()
         batch = rfd.Batch(plans, Xs, Fs, outs)
+        tpi = batch.tune(reps=3, stream=st)
         ms = replay_ms(lambda s: batch.launch(s), reps, torch, st)
         bad = [p for p in plans if p.check() != rfd.OK]
         torch.cuda.synchronize()
@@ -186,7 +187,7 @@ def bench_batch(torch, rfd, wl, reps: int):
         torch.cuda.synchronize()
         loop_ms = (time.perf_counter() - t0) / 2 * 1e3
         pc = sum(c.n * c.d for c in clouds)
-        res[prec] = {"ms": round(ms, 4), "value": round(pc / (ms * 1e-3), 1),
+        res[prec] = {"ms": round(ms, 4), "value": round(pc / (ms * 1e-3), 1), "tuned_tiles_per_item": tpi,
                      "per_cloud_loop_ms": round(loop_ms, 4), "speedup_vs_per_cloud_loop": round(loop_ms / ms, 3),
                      "device_errors": len(bad)}
         batch.close()
@@ -208,9 +209,11 @@ def bench_loop(torch, rfd, wl, reps: int):
         sd = [torch.from_numpy(s0).cuda(), torch.from_numpy(s1).cuda()]
         for prec in ("bf16", "fp32"):
             plans = [rfd.Plan(c.m, c.eps, c.lam, c.seed, precision=prec) for c in clouds]
+            v = torch.from_numpy(clouds[0].F).cuda()
+            tmp = torch.empty_like(v)
             for p, c in zip(plans, clouds):
                 p.features(torch.from_numpy(c.X).cuda())
-            v = torch.from_numpy(clouds[0].F).cuda()
+                p.autotune(v, tmp, reps=5)  # before the loop's graph records the geometry
             loop = rfd.Loop(plans, sd, v, iters)
             st = torch.cuda.Stream()
             ms = replay_ms(lambda s: loop.launch(s), reps, torch, st)
@@ -378,6 +381,9 @@ def main() -> int:
     for prec in ("fp32", "bf16"):
         plan = rfd.Plan(m, cloud.eps, cloud.lam, cloud.seed, precision=prec)
         out = torch.empty_like(F)
+        # untimed set-up: features once, then the autotuner picks the expansion geometry
+        plan.features(X)
+        plan.autotune(F, out, reps=5)
         step = lambda: plan.oneshot(X, F, out=out)
         ms, p50, p99 = time_steps(step, args.steps, args.warmup, torch)
         st = plan.check()
@@ -438,6 +444,7 @@ def main() -> int:
         line["batched"] = bench_batch(torch, rfd, wl, max(5, args.steps))
         line["repeated_application"] = bench_loop(torch, rfd, wl, max(5, args.steps // 2))
         line["serving"] = bench_serving(torch, rfd, wl, args.serve_requests, 500)
+        line["tuning_table"] = rfd.tune_export().strip().splitlines()
     if not args.no_cpu_baseline:
         from oracle import rfd_oracle as o
         ref, t, threads = cpu_baseline(cloud)

@@ -133,8 +133,8 @@ def test_budget_eviction_and_out_of_budget(torch_cuda):
     from paper_2302_00942_amd import rfd
     reqs = to_dev(torch, request_set(10, 11, lo=2000, hi=20000))
     for q in reqs:
-        q["m"] = 256  # large fixed plan footprint (~7 MB each)
-    budget = 24 << 20  # room for about three such plans
+        q["m"] = 256  # large fixed plan footprint (about 15 MB each)
+    budget = 48 << 20  # room for about three such plans
     srv = rfd.Server(budget, 4)
     outs = [torch.empty_like(q["Fd"]) for q in reqs]
     tickets = [srv.submit(q["Xd"], q["Fd"], o_, 256, 0.05, -0.5, 1000 + i, q["prec"])
