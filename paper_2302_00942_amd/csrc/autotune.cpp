@@ -54,9 +54,13 @@ void set_tuned(int knob, int M, int prec, int DB, int64_t N, int value) {
   t.v[Key{knob, M, prec, DB, log2_bucket(N)}] = value;
 }
 
-// One tile per wave for clouds below ~64k points (fill the chip), else up to
-// eight (fewer workgroups staging G into LDS).
-int default_expand_tiles_per_wave(int64_t N) { return N < (int64_t)1 << 16 ? 1 : (N < (int64_t)1 << 19 ? 2 : 8); }
+// Defaults from tuning runs on MI355X: FP32 is fastest with one tile per wave
+// at every size; BF16 (whose workgroups stage twice the G bytes) prefers
+// fewer workgroups as N grows.
+int default_expand_tiles_per_wave(int64_t N, int prec) {
+  if (!prec || N < (int64_t)1 << 16) return 1;
+  return N < (int64_t)1 << 19 ? 4 : 16;
+}
 int default_batch_tiles_per_item() { return 64; }
 
 }  // namespace rfd
@@ -87,7 +91,7 @@ rfd_status rfd_autotune(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, fl
   HIPCK(rfd::launch_reduce(p, N, dc, false, st));
   HIPCK(rfd::launch_gcore(p, dc, st));
   const int DB = rfd::dblocks(dc);
-  const int prev = rfd::tuned(rfd::kTuneExpandTilesPerWave, M, prec, DB, N, rfd::default_expand_tiles_per_wave(N));
+  const int prev = rfd::tuned(rfd::kTuneExpandTilesPerWave, M, prec, DB, N, rfd::default_expand_tiles_per_wave(N, prec));
   static const int cands[] = {1, 2, 4, 8, 16};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCK(hipEventCreate(&e0));

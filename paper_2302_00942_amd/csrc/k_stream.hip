@@ -765,7 +765,7 @@ hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* 
   const int DB = dblocks(d);
   const int64_t ntiles = (N + 15) / 16;
   // tiles of 16 points per wave: launch geometry only (results do not depend on it)
-  const int tpw = tuned(kTuneExpandTilesPerWave, M, prec, DB, N, default_expand_tiles_per_wave(N));
+  const int tpw = tuned(kTuneExpandTilesPerWave, M, prec, DB, N, default_expand_tiles_per_wave(N, prec));
   int64_t nwg = (ntiles + 4 * tpw - 1) / (4 * tpw);
   if (nwg > 2048) nwg = 2048;
   if (nwg < 1) nwg = 1;

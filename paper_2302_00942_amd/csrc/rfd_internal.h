@@ -147,7 +147,7 @@ int dblocks(int d);
 enum TuneKnob { kTuneExpandTilesPerWave = 0, kTuneBatchExpandTilesPerItem = 1, kNumTuneKnobs };
 int tuned(int knob, int M, int prec, int DB, int64_t N, int fallback);
 void set_tuned(int knob, int M, int prec, int DB, int64_t N, int value);
-int default_expand_tiles_per_wave(int64_t N);
+int default_expand_tiles_per_wave(int64_t N, int prec);
 int default_batch_tiles_per_item();
 void set_capturing(bool on);  // suspends per-kernel timing during graph capture
 int bta_partials(int64_t N, int m, int d, bool gram, int prec);  // number of workgroups / partials
