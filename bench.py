@@ -77,8 +77,10 @@ def read_traffic(kernel: str, workload: str):
 
 
 def phi1_flops(m: int, s: int) -> float:
-    # Pade 13 (6 products), LU with 2m right-hand sides (2/3 m^3 + 4 m^3), s squaring steps (2 products each)
-    return (6 + 2 * s) * 2.0 * m ** 3 + (2.0 / 3.0 + 4.0) * m ** 3
+    # degree-23 Taylor of phi_1 and exp by Paterson-Stockmeyer: Y^2, then Y^3 and Y^4,
+    # then five Horner steps for each of the two series (13 products), and s squaring
+    # steps of two products each
+    return (13 + 2 * s) * 2.0 * m ** 3
 
 
 def algorithmic(kernel: str, N: int, m: int, d: int, s: int, nparts: int):

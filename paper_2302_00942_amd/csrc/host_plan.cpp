@@ -117,7 +117,7 @@ hipError_t dalloc(T** p, size_t count) {
 
 void free_dev(rfd::PlanDev& d) {
   void* ptrs[] = {d.om, d.cvec, d.svec, d.X, d.Mraw, d.H0, d.S64, d.T64, d.G32, d.Gt16,
-                  d.phi_ws, d.pivots, d.sdev, d.barrier, d.flag, d.lvl, d.partials};
+                  d.phi_ws, d.sdev, d.barrier, d.flag, d.lvl, d.partials};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   d = rfd::PlanDev{};
@@ -244,7 +244,7 @@ size_t plan_fixed_bytes(int M) {
   const size_t mm = (size_t)M * M;
   return sizeof(float4) * (M / 2) + 2 * sizeof(double) * M + 3 * sizeof(double) * mm +
          sizeof(double) * M * 64 + sizeof(float) * M * 64 + 2 * sizeof(__bf16) * M * 64 +
-         sizeof(double) * phi1_ws_doubles(M) + sizeof(int) * M + 2 * sizeof(int) +
+         sizeof(double) * phi1_ws_doubles(M) + 2 * sizeof(int) +
          sizeof(unsigned) * kBarrierWords + sizeof(double) * reduce_scratch_doubles(M);
 }
 
@@ -373,10 +373,6 @@ rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan) {
     p->wsum_abs += fabs(p->w[k]);
     if (params->lambda * p->w[k] > 0.0) p->any_growth = true;
   }
-  // [13/13] Pade numerator of exp: b_k = (2q-k)! q! / ((2q)! k! (q-k)!), q = 13,
-  // by the ratio b_{k+1} / b_k = (q - k) / ((2q - k)(k + 1)).
-  p->pade_b[0] = 1.0;
-  for (int k = 0; k < 13; ++k) p->pade_b[k + 1] = p->pade_b[k] * (double)(13 - k) / ((double)(26 - k) * (double)(k + 1));
 
   const int M = rfd::padded_m(params->m);
   p->dev_m = M;
@@ -388,7 +384,7 @@ rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan) {
             dalloc(&d.Mraw, mm) == hipSuccess && dalloc(&d.H0, (size_t)M * 64) == hipSuccess &&
             dalloc(&d.S64, mm) == hipSuccess && dalloc(&d.T64, mm) == hipSuccess &&
             dalloc(&d.G32, (size_t)M * 64) == hipSuccess && dalloc(&d.Gt16, (size_t)2 * M * 64) == hipSuccess &&
-            dalloc(&d.phi_ws, rfd::phi1_ws_doubles(M)) == hipSuccess && dalloc(&d.pivots, M) == hipSuccess &&
+            dalloc(&d.phi_ws, rfd::phi1_ws_doubles(M)) == hipSuccess &&
             dalloc(&d.sdev, 1) == hipSuccess && dalloc(&d.barrier, rfd::kBarrierWords) == hipSuccess && dalloc(&d.flag, 1) == hipSuccess &&
             dalloc(&d.lvl, rfd::reduce_scratch_doubles(M)) == hipSuccess;
   if (!ok) {

@@ -1,28 +1,23 @@
 // FP64 phi_1 of the m x m RFD core on gfx950.
 //
 // S = lambda phi_1(lambda M), M = B^T A = diag(c) Mraw diag(c) diag(s), by
-// scaling and squaring with the [13/13] Pade approximant of exp (Higham 2005,
-// "The scaling and squaring method for the matrix exponential revisited"):
+// scaling and squaring with truncated Taylor series evaluated by the
+// Paterson-Stockmeyer scheme (no linear solve):
 //
-//   X = lambda M, s = max(0, ceil(log2(||X||_1 / theta_13))), Y = X / 2^s
-//   U0 = b13 Y^12 + b11 Y^10 + ... + b3 Y^2 + b1 I,   U = Y U0   (odd part)
-//   V  = b12 Y^12 + ... + b2 Y^2 + b0 I                         (even part)
-//   Q = V - U,   P = Q^{-1} (2 U0),   E = I + Y P
+//   X = lambda M, s = max(0, ceil(log2(||X||_1 / theta_23))), Y = X / 2^s
+//   P = sum_{k<=23} Y^k / (k+1)!  (phi_1(Y)),   E = sum_{k<=23} Y^k / k!  (e^Y)
 //
-// P is phi_1(Y) to Pade accuracy: the [13/13] approximant applied to the
-// augmented matrix [[Y, I], [0, 0]] has top-right block Q^{-1} (p~(Y) - q~(Y))
-// with p~, q~ the Pade polynomials shifted down one power, and p~ - q~ = 2 U0
-// because q(x) = p(-x) (Al-Mohy & Higham 2011 use this augmentation for phi
-// functions). E = Q^{-1}(V + U) = I + Y P because Q^{-1} commutes with Y. The
-// scaling is undone with phi_1(2Y) = phi_1(Y) (e^Y + I) / 2 and
+// Both series are written as sum_j Y4^j B_j with B_j = sum_{i<4} c_{4j+i} Y^i
+// and evaluated by Horner's rule in Y4 = Y^4 (five products each, the two
+// chains side by side in the same phases). theta_23 = 2.014710780944616 is the
+// largest 1-norm for which the backward error of the degree-23 Taylor
+// approximant of exp stays below 2^-53: with T(Y) = e^{Y + h(Y)},
+// ||h(Y)|| / ||Y|| <= sum_n |h_n| theta^{n-1} for the power series
+// h(x) = log(e^{-x} T(x)) (the backward-error bound of Al-Mohy & Higham,
+// SIAM J. Matrix Anal. Appl. 31(3), 2009, applied to Taylor polynomials).
+// The scaling is undone with phi_1(2Y) = phi_1(Y) (e^Y + I) / 2 and
 // e^{2Y} = e^Y e^Y, s times. Powers are formed from the unscaled X with the
 // exact power-of-two factors 2^{-ks} applied in the products.
-//
-// The solve is a right-looking blocked LU with partial pivoting (32-column
-// panels, the next panel factored in the same phase as the trailing update);
-// the m right-hand-side columns ride along as trailing columns, so forward
-// elimination needs no separate pass, and back substitution runs per
-// 32-column strip without cross-workgroup sync.
 //
 // One body serves two schedules: k_phi1_wg (one workgroup per cloud, for
 // batches) and k_phi1_grid (one cloud over a cooperative grid, with a
@@ -35,12 +30,10 @@ struct Phi1Args {
   int m;               // padded size, a multiple of 64, <= 256
   int reserved;
   double lambda;
-  double b[14];        // Pade [13/13] numerator coefficients
   const double* Mraw;  // m x m, canonical order (symmetric)
   const double* cvec;  // m, canonical order
   const double* svec;  // m, canonical order
   double* ws;          // phi1_ws_doubles(m)
-  int* piv;            // m
   int* sdev;           // s
   double* S64;         // m x m canonical: lambda phi_1(lambda M)
   double* T64;         // m x m device order: diag(c s) S diag(c)
@@ -94,19 +87,6 @@ struct GridBarrier {
     __syncthreads();
   }
 };
-
-// Largest 32-bit key over the 64 lanes of a wave (DPP: swaps within quads,
-// half-row and row mirrors, then the two row broadcasts; lane 63 ends with the
-// maximum, which is read back into a uniform value).
-__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
-  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
-}
 
 // ------------------------------------------------------------------ GEMM tile
 // 32 x 32 tile (ti, tj) of alpha A B for row-major m x m A and B. Each wave
@@ -174,325 +154,80 @@ __device__ __forceinline__ void gemm_tile(int ti, int tj, const double* __restri
   }
 }
 
-// ------------------------------------------------------------------ LU pieces
-// Matrix QR: m rows, row pitch ld = 2m; columns [0, m) hold Q, [m, 2m) the
-// right-hand sides. Panel k: rows r0..m-1, columns r0..r0+31, factored with
-// partial pivoting; thread t holds panel row t in registers, the column steps
-// are unrolled at compile time so every register index is static.
-//
-// Pivot choice: the 32-bit key of row t is the FP32 bit pattern of |a_tj|
-// with its 8 low mantissa bits replaced by 255 - t; the largest key wins. The
-// chosen pivot is within a factor 1 + 2^-15 of the column maximum (ties go to
-// the smallest row), a deterministic partial-pivoting rule.
-struct PanelCtx {
-  double* rows;  // LDS: 2 x 2 x 32 doubles: [buffer][pivot row, displaced row]
-  unsigned* red; // LDS: 2 x 4 per-wave maximum keys
-  int* piv;      // global pivot vector
-  int* flag;
-  int r0, nr, t;
+// ------------------------------------------------------------------ body
+constexpr double kTheta23 = 2.014710780944616;
+
+// 1/k! as a compile-time constant.
+constexpr double inv_factorial(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= (double)i;
+  return 1.0 / f;
+}
+
+// Coefficient block j of the two series: B_j = sum_{i<4} c_{4j+i} Y^i, with
+// c_k = 1/(k+1)! for phi_1 (chain 0) and 1/k! for exp (chain 1).
+template <int J, int CHAIN>
+__device__ __forceinline__ double coef_block(double id, double y, double y2, double y3) {
+  constexpr int o = CHAIN == 0 ? 1 : 0;
+  constexpr double c0 = inv_factorial(4 * J + o), c1 = inv_factorial(4 * J + 1 + o);
+  constexpr double c2 = inv_factorial(4 * J + 2 + o), c3 = inv_factorial(4 * J + 3 + o);
+  return ((c0 * id + c1 * y) + c2 * y2) + c3 * y3;
+}
+
+struct TaylorWs {
+  const double* X0;  // lambda M (unscaled)
+  double* Y2;
+  double* Y3;
+  double* Y4;
+  double* R[2][2];   // [chain][ping-pong]
+  double sc1;        // 2^-s
 };
 
-template <int J>
-__device__ __forceinline__ void panel_step(double (&r)[32], const PanelCtx& c) {
-  if constexpr (J < 32) {
-    const int t = c.t, w = t >> 6;
-    double* prow = c.rows + (J & 1) * 64;
-    double* srow = prow + 32;
-    unsigned* red = c.red + (J & 1) * 4;
-    const bool cand = t < c.nr && t >= J;
-    const unsigned key = cand ? ((__float_as_uint(fabsf((float)r[J])) & ~0xFFu) | (unsigned)(255 - t)) : 0u;
-    const unsigned wm = wave_max_u32(key);
-    if ((t & 63) == 0) red[w] = wm;
-    __syncthreads();
-    const unsigned best = max(max(red[0], red[1]), max(red[2], red[3]));
-    const int p = best == 0u ? J : 255 - (int)(best & 0xFFu);
-    if (t == p) {
-#pragma unroll
-      for (int k = J; k < 32; ++k) prow[k] = r[k];
+// Horner step J (J = 4 ... 0): R_chain <- Y4 R_chain + B_J, both chains.
+template <int m, int J, class BAR>
+__device__ __forceinline__ void horner_phase(const TaylorWs& w, int worker, int nw, double* lds, BAR& bar) {
+  constexpr int nb = m / 32, nt = nb * nb;
+  constexpr int src = (J + 1) & 1, dst = J & 1;
+  for (int tile = worker; tile < 2 * nt; tile += nw) {
+    const int tt = tile % nt;
+    const auto form = [&](int i, int j, double& id, double& y, double& y2, double& y3) {
+      const size_t e = (size_t)i * m + j;
+      id = i == j ? 1.0 : 0.0;
+      y = w.X0[e] * w.sc1;
+      y2 = w.Y2[e];
+      y3 = w.Y3[e];
+    };
+    if (tile < nt) {
+      gemm_tile<m>(tt / nb, tt % nb, w.Y4, w.R[0][src], 1.0, lds, [&](int i, int j, double v) {
+        double id, y, y2, y3;
+        form(i, j, id, y, y2, y3);
+        w.R[0][dst][(size_t)i * m + j] = v + coef_block<J, 0>(id, y, y2, y3);
+      });
+    } else {
+      gemm_tile<m>(tt / nb, tt % nb, w.Y4, w.R[1][src], 1.0, lds, [&](int i, int j, double v) {
+        double id, y, y2, y3;
+        form(i, j, id, y, y2, y3);
+        w.R[1][dst][(size_t)i * m + j] = v + coef_block<J, 1>(id, y, y2, y3);
+      });
     }
-    if (t == J && p != J) {
-#pragma unroll
-      for (int k = J; k < 32; ++k) srow[k] = r[k];
-    }
-    if (t == 0) c.piv[c.r0 + J] = c.r0 + p;
-    __syncthreads();
-    if (p != J) {
-      if (t == J) {
-#pragma unroll
-        for (int k = J; k < 32; ++k) r[k] = prow[k];
-      } else if (t == p) {
-#pragma unroll
-        for (int k = J; k < 32; ++k) r[k] = srow[k];
-      }
-    }
-    double dv = prow[J];
-    if (dv == 0.0) {
-      if (t == 0) __hip_atomic_fetch_or(c.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      dv = 1.0;
-    }
-    if (t < c.nr && t > J) {
-      const double lf = r[J] / dv;
-      r[J] = lf;
-#pragma unroll
-      for (int k = J + 1; k < 32; ++k) r[k] -= lf * prow[k];
-    }
-    // no barrier here: the next step writes the other LDS buffer, and this
-    // one is written again only after the next step's two barriers
-    panel_step<J + 1>(r, c);
   }
+  bar.sync();
 }
 
-template <int m>
-__device__ __forceinline__ void lu_panel(int k, double* QR, int* piv, int* flag, double* lds) {
-  const int r0 = 32 * k, nr = m - r0;
-  const size_t ld = 2 * (size_t)m;
-  const int t = threadIdx.x;
-  double* Pn = lds;  // nr x 33 staging for coalesced loads and stores
-  PanelCtx c{lds + 256 * 33, (unsigned*)(lds + 256 * 33 + 128), piv, flag, r0, nr, t};
-  __syncthreads();
-  {
-    constexpr int NL = m / 8;
-    double vp[NL];
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = t + 256 * q, i = e >> 5;
-      if (i < nr) vp[q] = QR[(r0 + i) * ld + r0 + (e & 31)];
-    }
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = t + 256 * q, i = e >> 5;
-      if (i < nr) Pn[i * 33 + (e & 31)] = vp[q];
-    }
-  }
-  __syncthreads();
-  double r[32];
-  const bool act = t < nr;
-#pragma unroll
-  for (int q = 0; q < 32; ++q) r[q] = act ? Pn[t * 33 + q] : 0.0;
-  panel_step<0>(r, c);
-  __syncthreads();
-  if (act) {
-#pragma unroll
-    for (int q = 0; q < 32; ++q) Pn[t * 33 + q] = r[q];
-  }
-  __syncthreads();
-  {
-    constexpr int NL = m / 8;
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = t + 256 * q, i = e >> 5;
-      if (i < nr) QR[(r0 + i) * ld + r0 + (e & 31)] = Pn[i * 33 + (e & 31)];
-    }
-  }
-}
-
-// Inverse of the upper triangular diagonal block U_kk (rows and columns
-// 32k..32k+31 of QR, final once panel k is factored) into Ui (32 x 32,
-// row-major): thread c < 32 solves U x = e_c in registers.
-template <int m>
-__device__ __forceinline__ void upper_inverse(int k, const double* QR, double* Ui, double* lds) {
-  const int r0 = 32 * k;
-  const size_t ld = 2 * (size_t)m;
-  const int t = threadIdx.x;
-  double* Ub = lds;  // 32 x 33
-  __syncthreads();
-  for (int e = t; e < 32 * 32; e += 256) Ub[(e >> 5) * 33 + (e & 31)] = QR[(r0 + (e >> 5)) * ld + r0 + (e & 31)];
-  __syncthreads();
-  if (t < 32) {
-    double x[32];
-#pragma unroll
-    for (int i = 31; i >= 0; --i) {
-      double v = (i == t) ? 1.0 : 0.0;
-#pragma unroll
-      for (int j = i + 1; j < 32; ++j) v -= Ub[i * 33 + j] * x[j];
-      x[i] = v / Ub[i * 33 + i];
-    }
-#pragma unroll
-    for (int i = 0; i < 32; ++i) Ui[i * 32 + t] = x[i];
-  }
-}
-
-// Trailing update of one 32-column strip (columns cs..cs+31, cs >= r0 + 32)
-// after panel k: apply the panel's row swaps, U12 = L11^{-1} A12, A22 -= L21 U12.
-template <int m>
-__device__ __forceinline__ void lu_strip(int k, int cs, double* QR, const int* piv, double* lds) {
-  const int r0 = 32 * k, nr = m - r0;
-  const size_t ld = 2 * (size_t)m;
-  const int t = threadIdx.x;
-  double* Sx = lds;             // nr x 33
-  double* Lp = lds + nr * 33;   // nr x 33 (L11 over L21)
-  __syncthreads();
-  {
-    constexpr int NL = m / 8;  // upper bound of nr * 32 / 256
-    double v[NL];
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = t + 256 * q, i = e >> 5, c = e & 31;
-      if (i < nr) v[q] = QR[(r0 + i) * ld + cs + c];
-    }
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = t + 256 * q, i = e >> 5, c = e & 31;
-      if (i < nr) Sx[i * 33 + c] = v[q];
-    }
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = t + 256 * q, i = e >> 5, c = e & 31;
-      if (i < nr) v[q] = QR[(r0 + i) * ld + r0 + c];
-    }
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = t + 256 * q, i = e >> 5, c = e & 31;
-      if (i < nr) Lp[i * 33 + c] = v[q];
-    }
-  }
-  __syncthreads();
-  if (t < 32) {
-    // row swaps, in order, then the unit lower triangular solve, on column t
-    for (int j = 0; j < 32; ++j) {
-      const int p = piv[r0 + j] - r0;
-      if (p != j) {
-        const double a = Sx[j * 33 + t];
-        Sx[j * 33 + t] = Sx[p * 33 + t];
-        Sx[p * 33 + t] = a;
-      }
-    }
-    double x[32];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) x[i] = Sx[i * 33 + t];
-#pragma unroll
-    for (int i = 1; i < 32; ++i) {
-      double v = x[i];
-#pragma unroll
-      for (int j = 0; j < i; ++j) v -= Lp[i * 33 + j] * x[j];
-      x[i] = v;
-    }
-#pragma unroll
-    for (int i = 0; i < 32; ++i) Sx[i * 33 + t] = x[i];
-  }
-  __syncthreads();
-  // A22 -= L21 U12 on the matrix cores: tiles of 16 rows x 16 columns
-  const int w = t >> 6, l = t & 63;
-  const int ntile = ((nr - 32) / 16) * 2;
-  for (int tile = w; tile < ntile; tile += 4) {
-    const int i0 = 32 + (tile >> 1) * 16, c0 = (tile & 1) * 16;
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Lp[(i0 + (l & 15)) * 33 + 4 * s + (l >> 4)],
-                                                 Sx[(4 * s + (l >> 4)) * 33 + c0 + (l & 15)], acc, 0, 0, 0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = i0 + 4 * r + (l >> 4), c = c0 + (l & 15);
-      Sx[i * 33 + c] -= acc[r];
-    }
-  }
-  __syncthreads();
-  for (int e = t; e < nr * 32; e += 256) {
-    const int i = e >> 5, c = e & 31;
-    QR[(r0 + i) * ld + cs + c] = Sx[i * 33 + c];
-  }
-}
-
-// Back substitution U X = R for one 32-column strip of the right-hand side
-// (columns m + cs .. of QR) with the inverted diagonal blocks Uinv (nb blocks
-// of 32 x 32): per block, X_k = Uinv_k R_k and R_{<k} -= U_{<k,k} X_k, both on
-// the matrix cores. X goes to dst (m x m, columns cs ..).
-template <int m>
-__device__ __forceinline__ void back_strip(int cs, const double* QR, const double* Uinv, double* dst, double* lds) {
-  const size_t ld = 2 * (size_t)m;
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  double* Rx = lds;               // m x 33
-  double* Ub = lds + m * 33;      // m x 33: U[0..r0-1][r0..r0+31], then Uinv_k in rows r0..r0+31
-  __syncthreads();
-  {
-    constexpr int NL = m / 8;
-    double vr[NL];
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = t + 256 * q;
-      vr[q] = QR[(e >> 5) * ld + m + cs + (e & 31)];
-    }
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = t + 256 * q;
-      Rx[(e >> 5) * 33 + (e & 31)] = vr[q];
-    }
-  }
-  for (int k = m / 32 - 1; k >= 0; --k) {
-    const int r0 = 32 * k;
-    __syncthreads();
-    {
-      constexpr int NL = m / 8;
-      double vu[NL];
-#pragma unroll
-      for (int q = 0; q < NL; ++q) {
-        const int e = t + 256 * q, i = e >> 5;
-        if (i < r0) vu[q] = QR[i * ld + r0 + (e & 31)];
-        else if (i < r0 + 32) vu[q] = Uinv[(size_t)k * 1024 + (i - r0) * 32 + (e & 31)];
-      }
-#pragma unroll
-      for (int q = 0; q < NL; ++q) {
-        const int e = t + 256 * q, i = e >> 5;
-        if (i < r0 + 32) Ub[i * 33 + (e & 31)] = vu[q];
-      }
-    }
-    __syncthreads();
-    // X_k = Uinv_k R_k: waves 0..3 take the four 16 x 16 quadrants
-    {
-      const int i0 = (w >> 1) * 16, c0 = (w & 1) * 16;
-      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < 8; ++s)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ub[(r0 + i0 + (l & 15)) * 33 + 4 * s + (l >> 4)],
-                                                   Rx[(r0 + 4 * s + (l >> 4)) * 33 + c0 + (l & 15)], acc, 0, 0, 0);
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Rx[(r0 + i0 + 4 * r + (l >> 4)) * 33 + c0 + (l & 15)] = acc[r];
-    }
-    __syncthreads();
-    const int ntile = (r0 / 16) * 2;
-    for (int tile = w; tile < ntile; tile += 4) {
-      const int i0 = (tile >> 1) * 16, c0 = (tile & 1) * 16;
-      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < 8; ++s)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ub[(i0 + (l & 15)) * 33 + 4 * s + (l >> 4)],
-                                                   Rx[(r0 + 4 * s + (l >> 4)) * 33 + c0 + (l & 15)], acc, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + 4 * r + (l >> 4), c = c0 + (l & 15);
-        Rx[i * 33 + c] -= acc[r];
-      }
-    }
-  }
-  __syncthreads();
-  for (int e = t; e < m * 32; e += 256) {
-    const int i = e >> 5, c = e & 31;
-    dst[(size_t)i * m + cs + c] = Rx[i * 33 + c];
-  }
-}
-
-// ------------------------------------------------------------------ body
 template <int m, class BAR>
 __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw, double* lds, BAR& bar) {
   constexpr int nb = m / 32, nt = nb * nb;
   const size_t mm = (size_t)m * m;
   double* X0 = a.ws;        // lambda M
   double* Y2 = X0 + mm;
-  double* Y4 = Y2 + mm;
-  double* Y6 = Y4 + mm;
-  double* W1 = Y6 + mm;
-  double* Z1 = W1 + mm;
-  double* C1 = Z1 + mm;
-  double* C2 = C1 + mm;
-  double* U0 = C2 + mm;
-  double* V = U0 + mm;
-  double* QR = V + mm;      // m x 2m
-  double* colsum = QR + 2 * mm;
-  double* Uinv = colsum + m;  // nb blocks of 32 x 32
+  double* Y3 = Y2 + mm;
+  double* Y4 = Y3 + mm;
+  double* R00 = Y4 + mm;    // phi_1 chain, two buffers
+  double* R01 = R00 + mm;
+  double* R10 = R01 + mm;   // exp chain, two buffers
+  double* R11 = R10 + mm;
+  double* colsum = R11 + mm;
   const int t = threadIdx.x;
-  const double* b = a.b;
 
   // ---- P0: X0 = lambda M, and column sums of |X0| (M is symmetric, so the
   // column sum of |X0| over rows is a row sum of |Mraw| scaled by c)
@@ -517,77 +252,42 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   for (int j = 0; j < m; ++j) nrm = fmax(nrm, colsum[j]);
   int s = 0;
   if (!(nrm <= 1e300)) s = 0;  // non-finite input: flagged by the reduction already
-  else if (nrm > 5.371920351148152) s = (int)ceil(log2(nrm / 5.371920351148152));
+  else if (nrm > kTheta23) s = (int)ceil(log2(nrm / kTheta23));
   if (s > 1000) s = 1000;
   if (worker == 0 && t == 0) *a.sdev = s;
   const double sc1 = ldexp(1.0, -s), sc2 = ldexp(1.0, -2 * s);
 
-  // ---- P1..P3: even powers of Y = X0 / 2^s; the last epilogue forms the
-  // Pade combinations W1, Z1 (B operands) and C1, C2 (additive terms)
+  // ---- P1: Y2 = X0 X0 / 4^s
   for (int tile = worker; tile < nt; tile += nw)
     gemm_tile<m>(tile / nb, tile % nb, X0, X0, sc2, lds, [&](int i, int j, double v) { Y2[(size_t)i * m + j] = v; });
   bar.sync();
-  for (int tile = worker; tile < nt; tile += nw)
-    gemm_tile<m>(tile / nb, tile % nb, Y2, Y2, 1.0, lds, [&](int i, int j, double v) { Y4[(size_t)i * m + j] = v; });
-  bar.sync();
-  for (int tile = worker; tile < nt; tile += nw)
-    gemm_tile<m>(tile / nb, tile % nb, Y4, Y2, 1.0, lds, [&](int i, int j, double y6) {
-      const size_t e = (size_t)i * m + j;
-      const double y4 = Y4[e], y2 = Y2[e], id = i == j ? 1.0 : 0.0;
-      Y6[e] = y6;
-      W1[e] = b[13] * y6 + b[11] * y4 + b[9] * y2;
-      Z1[e] = b[12] * y6 + b[10] * y4 + b[8] * y2;
-      C1[e] = b[7] * y6 + b[5] * y4 + b[3] * y2 + b[1] * id;
-      C2[e] = b[6] * y6 + b[4] * y4 + b[2] * y2 + b[0] * id;
-    });
-  bar.sync();
-  // ---- P4: U0 = Y6 W1 + C1,  V = Y6 Z1 + C2
+  // ---- P2: Y3 = Y2 X0 / 2^s (its epilogue also forms B_5 of both chains) and Y4 = Y2 Y2
   for (int tile = worker; tile < 2 * nt; tile += nw) {
     const int tt = tile % nt;
     if (tile < nt)
-      gemm_tile<m>(tt / nb, tt % nb, Y6, W1, 1.0, lds,
-                [&](int i, int j, double v) { const size_t e = (size_t)i * m + j; U0[e] = v + C1[e]; });
+      gemm_tile<m>(tt / nb, tt % nb, Y2, X0, sc1, lds, [&](int i, int j, double y3) {
+        const size_t e = (size_t)i * m + j;
+        const double id = i == j ? 1.0 : 0.0, y = X0[e] * sc1, y2 = Y2[e];
+        Y3[e] = y3;
+        R01[e] = coef_block<5, 0>(id, y, y2, y3);
+        R11[e] = coef_block<5, 1>(id, y, y2, y3);
+      });
     else
-      gemm_tile<m>(tt / nb, tt % nb, Y6, Z1, 1.0, lds,
-                [&](int i, int j, double v) { const size_t e = (size_t)i * m + j; V[e] = v + C2[e]; });
+      gemm_tile<m>(tt / nb, tt % nb, Y2, Y2, 1.0, lds, [&](int i, int j, double v) { Y4[(size_t)i * m + j] = v; });
   }
   bar.sync();
-  // ---- P5: U = Y U0; system Q = V - U with right-hand side 2 U0
-  for (int tile = worker; tile < nt; tile += nw)
-    gemm_tile<m>(tile / nb, tile % nb, X0, U0, sc1, lds, [&](int i, int j, double u) {
-      const size_t e = (size_t)i * m + j;
-      QR[(size_t)i * 2 * m + j] = V[e] - u;
-      QR[(size_t)i * 2 * m + m + j] = 2.0 * U0[e];
-    });
-  bar.sync();
-  // ---- P6: blocked LU with partial pivoting, next panel factored in the
-  // same phase as the trailing update (by the worker owning its strip)
-  // The inverse of each diagonal U block is taken, off the critical path, by
-  // the worker after the last strip owner in the phase following its panel.
-  if (worker == 0) lu_panel<m>(0, QR, a.piv, a.flag, lds);
-  bar.sync();
-  for (int k = 0; k < nb; ++k) {
-    const int nstrip = 2 * nb - k - 1;
-    for (int st = worker; st < nstrip; st += nw) {
-      lu_strip<m>(k, 32 * (k + 1 + st), QR, a.piv, lds);
-      if (st == 0 && k + 1 < nb) lu_panel<m>(k + 1, QR, a.piv, a.flag, lds);
-    }
-    if (worker == nstrip % nw) upper_inverse<m>(k, QR, Uinv + (size_t)k * 1024, lds);
-    bar.sync();
-  }
-  // ---- P7: back substitution per right-hand-side strip: P -> Y2
-  double* Pc = Y2;
-  for (int st = worker; st < nb; st += nw) back_strip<m>(32 * st, QR, Uinv, Pc, lds);
-  bar.sync();
-  // ---- P8: E = I + Y P -> Y4
-  double* Ec = Y4;
-  for (int tile = worker; tile < nt; tile += nw)
-    gemm_tile<m>(tile / nb, tile % nb, X0, Pc, sc1, lds,
-              [&](int i, int j, double v) { Ec[(size_t)i * m + j] = v + (i == j ? 1.0 : 0.0); });
-  bar.sync();
-  // ---- P9: undo the scaling: P <- P (E + I) / 2, E <- E E
-  double* En = Y6;
-  double* Pn = W1;
+  // ---- P3..P7: Horner steps J = 4 ... 0 (J odd reads buffer 0, writes 1 ... ends in buffer 0)
+  const TaylorWs w{X0, Y2, Y3, Y4, {{R00, R01}, {R10, R11}}, sc1};
+  horner_phase<m, 4>(w, worker, nw, lds, bar);
+  horner_phase<m, 3>(w, worker, nw, lds, bar);
+  horner_phase<m, 2>(w, worker, nw, lds, bar);
+  horner_phase<m, 1>(w, worker, nw, lds, bar);
+  horner_phase<m, 0>(w, worker, nw, lds, bar);
+  // ---- undo the scaling: P <- P (E + I) / 2, E <- E E
+  double* Pc = R00;
+  double* Ec = R10;
+  double* Pn = R01;
+  double* En = R11;
   for (int it = 0; it < s; ++it) {
     for (int tile = worker; tile < 2 * nt; tile += nw) {
       const int tt = tile % nt;
@@ -603,7 +303,7 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
     double* x = Ec; Ec = En; En = x;
     x = Pc; Pc = Pn; Pn = x;
   }
-  // ---- P10: S = lambda P (canonical), T = diag(c s) S diag(c) in device order
+  // ---- S = lambda P (canonical), T = diag(c s) S diag(c) in device order
   const int fq = m / 2;
   for (size_t e = (size_t)worker * 256 + t; e < mm; e += (size_t)nw * 256) {
     const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
@@ -637,26 +337,18 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 }
 
 // LDS bytes of the phi_1 kernels for padded size m.
-static size_t phi1_lds_bytes(int m) {
-  const size_t gemm = (size_t)(32 * (m + 1) + m * 33) * 8;
-  const size_t strip = (size_t)(2 * m * 33) * 8;
-  const size_t panel = (size_t)(256 * 33 + 128 + 8) * 8;
-  size_t x = gemm > strip ? gemm : strip;
-  return x > panel ? x : panel;
-}
+static size_t phi1_lds_bytes(int m) { return (size_t)(32 * (m + 1) + m * 33) * 8; }
 
-size_t phi1_ws_doubles(int m) { return 12 * (size_t)m * m + m + (size_t)(m / 32) * 1024; }
+size_t phi1_ws_doubles(int m) { return 8 * (size_t)m * m + m; }
 
 static void fill_args(rfd_plan_s* p, Phi1Args& a) {
   a.m = p->dev_m;
   a.reserved = 0;
   a.lambda = p->params.lambda;
-  for (int k = 0; k < 14; ++k) a.b[k] = p->pade_b[k];
   a.Mraw = p->dev.Mraw;
   a.cvec = p->dev.cvec;
   a.svec = p->dev.svec;
   a.ws = p->dev.phi_ws;
-  a.piv = p->dev.pivots;
   a.sdev = p->dev.sdev;
   a.S64 = p->dev.S64;
   a.T64 = p->dev.T64;

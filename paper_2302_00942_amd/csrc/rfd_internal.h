@@ -70,7 +70,6 @@ struct PlanDev {
   float* G32 = nullptr;       // m x 64, device order: G' = T H0 of one channel slice
   __bf16* Gt16 = nullptr;     // 2 x 64 x m: G'^T as BF16 hi, then BF16 lo
   double* phi_ws = nullptr;   // phi_1 workspace (phi1_ws_doubles)
-  int* pivots = nullptr;      // m
   int* sdev = nullptr;        // scaling power s
   unsigned* barrier = nullptr;// grid barrier counter
   int* flag = nullptr;        // non-finite flag
@@ -91,7 +90,6 @@ struct rfd_plan_s {
   bool any_growth = false;    // lambda * w_k > 0 for some k
   int64_t N = -1;             // cloud size after rfd_features (-1: none)
   int dev_m = 0;              // padded feature count used on the device: 64, 128 or 256
-  double pade_b[14] = {};     // [13/13] Pade numerator coefficients of exp
   int device = 0;
   rfd::PlanDev dev;
 };

@@ -110,3 +110,43 @@ def test_tuning_table_text_round_trip():
     assert rfd.tune_export().splitlines()[0] == "0 256 1 1 20 4"
     rfd.tune_reset()
     assert rfd.tune_export() == ""
+
+
+def _taylor_theta(q: int, nmax: int = 120) -> float:
+    """Largest theta with sum_n |h_n| theta^(n-1) <= 2^-53, where
+    h(x) = log(e^{-x} T_q(x)) = sum_{n>q} h_n x^n is the backward-error series
+    of the degree-q Taylor polynomial T_q of exp (exact rationals)."""
+    import math
+    from fractions import Fraction as Fr
+    em = [Fr((-1) ** k, math.factorial(k)) for k in range(nmax + 1)]
+    r = [sum(em[i] * Fr(1, math.factorial(n - i)) for i in range(n + 1) if n - i <= q) for n in range(nmax + 1)]
+    r[0] -= 1  # r = e^{-x} T_q(x) - 1, starts at x^{q+1}
+    h = [Fr(0)] * (nmax + 1)
+    rp, k = r[:], 1
+    while any(rp) and k <= nmax // (q + 1) + 1:  # log(1 + r) = r - r^2/2 + ...
+        for n in range(nmax + 1):
+            h[n] += Fr((-1) ** (k + 1), k) * rp[n]
+        nxt = [Fr(0)] * (nmax + 1)
+        for i, a in enumerate(rp):
+            if a:
+                for j in range(nmax + 1 - i):
+                    if r[j]:
+                        nxt[i + j] += a * r[j]
+        rp, k = nxt, k + 1
+    ht = [abs(float(v)) for v in h]
+    f = lambda th: sum(c * th ** n for n, c in enumerate(ht)) / th
+    lo, hi = 1e-3, 20.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if f(mid) <= 2.0 ** -53 else (lo, mid)
+    return lo
+
+
+def test_taylor_scaling_threshold():
+    """The phi_1 kernel picks s from ||lambda M||_1 / theta_23 with
+    theta_23 = 2.014710780944616 (its degree-23 Taylor evaluation). Pinned by
+    recomputing the threshold from the backward-error series, and the method
+    itself by reproducing the published degree-18 value theta_18 = 1.09
+    (Al-Mohy & Higham's Taylor thresholds for double precision)."""
+    assert abs(_taylor_theta(23) - 2.014710780944616) < 1e-9
+    assert abs(_taylor_theta(18) - 1.09) < 5e-3

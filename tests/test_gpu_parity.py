@@ -91,8 +91,12 @@ def test_core_matches_oracle(torch_cuda):
     M, S, s = plan.core()
     eM = np.linalg.norm(M - parts["M"]) / np.linalg.norm(parts["M"])
     eS = np.linalg.norm(S - parts["S"]) / np.linalg.norm(parts["S"])
-    print(f"core: s={s} (oracle {o.scaling_power(c.lam * parts['M'])}) relF(M)={eM:.3e} relF(S)={eS:.3e}")
-    assert abs(s - o.scaling_power(c.lam * parts["M"])) <= 1
+    # the device evaluates phi_1 by degree-23 Taylor: s from the 1-norm over theta_23
+    nrm = np.abs(c.lam * parts["M"]).sum(axis=0).max()
+    s_dev = max(0, math.ceil(math.log2(nrm / 2.014710780944616)))
+    print(f"core: s={s} (expected {s_dev}; oracle Pade {o.scaling_power(c.lam * parts['M'])}) "
+          f"relF(M)={eM:.3e} relF(S)={eS:.3e}")
+    assert abs(s - s_dev) <= 1
     assert eM < 1e-5 and eS < 1e-3
 
 
