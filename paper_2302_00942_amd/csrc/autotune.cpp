@@ -124,6 +124,41 @@ rfd_status rfd_autotune(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, fl
   return rfd::integrate_enqueue(p, F, ldF, d, out, ldO, st, 0, nullptr);
 }
 
+rfd_status rfd_autotune_phi1(rfd_plan_t p, int32_t reps, rfd_stream_t stream) {
+  if (!p || reps < 1) return RFD_ERR_INVALID_ARG;
+  if (p->N < 0) return RFD_ERR_NOT_READY;
+  if (p->N == 0) return RFD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int M = p->dev_m, nt2 = 2 * (M / 32) * (M / 32);
+  const int prev = rfd::tuned(rfd::kTunePhi1Workgroups, M, 0, 1, 0, nt2 > 128 ? 128 : nt2);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return RFD_ERR_DEVICE;
+  }
+  int best = 0;
+  float best_ms = 1e30f;
+  bool ok = true;
+  // phi_1 reads the plan's core and rewrites S and T with the same values
+  for (int nw = nt2 < 128 ? nt2 : 128; ok && nw >= 8 && nw * 8 >= nt2; nw /= 2) {
+    rfd::set_tuned(rfd::kTunePhi1Workgroups, M, 0, 1, 0, nw);
+    ok = rfd::launch_phi1(p, st) == hipSuccess && hipEventRecord(e0, st) == hipSuccess;
+    for (int r = 0; ok && r < reps; ++r) ok = rfd::launch_phi1(p, st) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ok && ms < best_ms) {
+      best_ms = ms;
+      best = nw;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  rfd::set_tuned(rfd::kTunePhi1Workgroups, M, 0, 1, 0, ok && best ? best : prev);
+  return ok && best ? RFD_OK : RFD_ERR_DEVICE;
+}
+
 int32_t rfd_tune_export(char* buf, int32_t cap) {
   rfd::Table& t = rfd::table();
   std::string txt;

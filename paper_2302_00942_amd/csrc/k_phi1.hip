@@ -362,8 +362,12 @@ static hipError_t launch_phi1_m(Phi1Args& a, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)k_phi1_grid<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   constexpr int nb = M / 32;
-  int nw = 2 * nb * nb;  // the widest phases (U0 and V, the squarings) have 2 nb^2 tiles
-  if (nw > 128) nw = 128;
+  // workgroups: the widest phases (Horner steps, squarings) have 2 nb^2 tiles;
+  // fewer workgroups make the barrier cheaper and give each more tiles (the
+  // count never changes results: each tile is computed the same way)
+  int nw = tuned(kTunePhi1Workgroups, M, 0, 1, 0, 2 * nb * nb > 128 ? 128 : 2 * nb * nb);
+  if (nw < 1) nw = 1;
+  if (nw > 2 * nb * nb) nw = 2 * nb * nb;
   hipLaunchKernelGGL(k_zero_u32, dim3((kBarWords + 255) / 256), dim3(256), 0, st, a.barrier, kBarWords);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -14,6 +14,8 @@
 // phase omega_k . x (in revolutions, reduced by fract) with the hardware
 // transcendental unit. Feature columns are kept unscaled on the device; the
 // scale c_k and sign s_k live in the m x m core.
+#include <type_traits>
+
 #include "rfd_internal.h"
 
 namespace rfd {
@@ -26,11 +28,15 @@ __device__ __forceinline__ void phase_sincos(float4 w, float x, float y, float z
   c = __builtin_amdgcn_cosf(t);           // cos(2 pi t)
 }
 
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+
+// Two floats rounded to BF16 (nearest even) in one word, a in the low half:
+// a single v_cvt_pk_bf16_f32.
 __device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
-  __bf16 ha = (__bf16)a, hb = (__bf16)b;  // round to nearest even
-  unsigned short ua = __builtin_bit_cast(unsigned short, ha);
-  unsigned short ub = __builtin_bit_cast(unsigned short, hb);
-  return (unsigned)ua | ((unsigned)ub << 16);
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
 }
 
 // Gram tile schedule. The NB x NB grid of 32 x 32 blocks of the symmetric
@@ -309,23 +315,20 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, int64_t N,
 
   const int pp = tid & 31;   // point pair within the chunk
   const int kq = tid >> 5;   // frequency phase 0..7
-  for (int64_t ch = c0; ch < c1; ++ch) {
-    const int64_t base = ch * kChunk;
-    __syncthreads();  // previous chunk's MFMA reads are done (and oms is visible)
-    // ---- features of points base+2pp, base+2pp+1 into LDS (device order rows)
-    const int64_t pa = base + 2 * pp, pb = pa + 1;
-    const bool va = pa < N, vb = pb < N;
-    float xa = 0.f, ya = 0.f, za = 0.f, xb = 0.f, yb = 0.f, zb = 0.f;
-    if (va) { xa = X[pa * 3]; ya = X[pa * 3 + 1]; za = X[pa * 3 + 2]; }
-    if (vb) { xb = X[pb * 3]; yb = X[pb * 3 + 1]; zb = X[pb * 3 + 2]; }
+  // features of points pa, pa + 1 into LDS (device order rows); points past
+  // N (only in a cloud's last chunk) get zero features
+  const auto features = [&](int64_t pa, bool va, bool vb, float xa, float ya, float za, float xb, float yb,
+                            float zb, auto masked) {
 #pragma unroll 2
     for (int k = kq; k < FQ; k += 8) {
       const float4 w = oms[k];
       float sa, ca, sb, cb;
       phase_sincos(w, xa, ya, za, sa, ca);
       phase_sincos(w, xb, yb, zb, sb, cb);
-      if (!va) { sa = 0.f; ca = 0.f; }
-      if (!vb) { sb = 0.f; cb = 0.f; }
+      if constexpr (decltype(masked)::value) {
+        if (!va) { sa = 0.f; ca = 0.f; }
+        if (!vb) { sb = 0.f; cb = 0.f; }
+      }
       if constexpr (PREC) {
         *(unsigned*)(phi + (2 * k) * P + 2 * pp) = pack_bf16x2(ca, cb);
         *(unsigned*)(phi + (2 * k + 1) * P + 2 * pp) = pack_bf16x2(sa, sb);
@@ -335,6 +338,21 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, int64_t N,
         phi[(2 * k + 1) * P + 2 * pp] = sa;
         phi[(2 * k + 1) * P + 2 * pp + 1] = sb;
       }
+    }
+  };
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    const int64_t base = ch * kChunk;
+    __syncthreads();  // previous chunk's MFMA reads are done (and oms is visible)
+    const int64_t pa = base + 2 * pp, pb = pa + 1;
+    if (base + kChunk <= N) {  // full chunk (uniform branch): no masking
+      features(pa, true, true, X[pa * 3], X[pa * 3 + 1], X[pa * 3 + 2], X[pb * 3], X[pb * 3 + 1], X[pb * 3 + 2],
+               std::false_type{});
+    } else {
+      const bool va = pa < N, vb = pb < N;
+      float xa = 0.f, ya = 0.f, za = 0.f, xb = 0.f, yb = 0.f, zb = 0.f;
+      if (va) { xa = X[pa * 3]; ya = X[pa * 3 + 1]; za = X[pa * 3 + 2]; }
+      if (vb) { xb = X[pb * 3]; yb = X[pb * 3 + 1]; zb = X[pb * 3 + 2]; }
+      features(pa, va, vb, xa, ya, za, xb, yb, zb, std::true_type{});
     }
     // ---- field chunk, transposed to [channel][point]
     {
@@ -556,14 +574,14 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
       for (int cb = 0; cb < DB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < M / 32; ++s) {
-        bf16x8 a;
+        u32x4_t aw;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           float sn, cs;
           phase_sincos(oms[16 * s + 4 * g + i], x, y, z, sn, cs);
-          a[2 * i] = (__bf16)cs;
-          a[2 * i + 1] = (__bf16)sn;
+          aw[i] = pack_bf16x2(cs, sn);
         }
+        const bf16x8 a = __builtin_bit_cast(bf16x8, aw);
 #pragma unroll
         for (int cb = 0; cb < DB; ++cb) {
           const int off = (cb * 16 + pl) * GP + s * 32 + 8 * g;

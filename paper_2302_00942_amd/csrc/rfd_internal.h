@@ -142,7 +142,8 @@ hipError_t launch_phi1_batch_dev(int M, int n, const void* dev_args, hipStream_t
 void phi1_fill_args(rfd_plan_s* p, void* args_out);  // writes one Phi1Args
 int dblocks(int d);
 // Launch-geometry tuning (autotune.cpp): knobs that change speed, never results.
-enum TuneKnob { kTuneExpandTilesPerWave = 0, kTuneBatchExpandTilesPerItem = 1, kNumTuneKnobs };
+enum TuneKnob { kTuneExpandTilesPerWave = 0, kTuneBatchExpandTilesPerItem = 1, kTunePhi1Workgroups = 2,
+                kNumTuneKnobs };
 int tuned(int knob, int M, int prec, int DB, int64_t N, int fallback);
 void set_tuned(int knob, int M, int prec, int DB, int64_t N, int value);
 int default_expand_tiles_per_wave(int64_t N, int prec);

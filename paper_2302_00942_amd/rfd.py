@@ -78,6 +78,7 @@ def lib() -> C.CDLL:
             "rfd_batch_tune": ([vp, i32, vp], i32),
             "rfd_batch_tiles_per_item": ([vp], i32),
             "rfd_autotune": ([vp, vp, i64, i32, vp, i64, i32, vp], i32),
+            "rfd_autotune_phi1": ([vp, i32, vp], i32),
             "rfd_tune_export": ([vp, i32], i32),
             "rfd_tune_import": ([C.c_char_p], i32),
             "rfd_tune_reset": ([], None),
@@ -230,6 +231,10 @@ class Plan:
         _check(lib().rfd_autotune(self._h, F.data_ptr(), F.stride(0), F.shape[1], out.data_ptr(), out.stride(0),
                                   int(reps), _stream_handle(stream)), "rfd_autotune")
         return out
+
+    def autotune_phi1(self, reps: int = 5, stream=None) -> None:
+        """Tunes the workgroup count of the phi_1 kernel (needs features)."""
+        _check(lib().rfd_autotune_phi1(self._h, int(reps), _stream_handle(stream)), "rfd_autotune_phi1")
 
     def check(self, stream=None) -> int:
         """Synchronises and returns the device status code (OK, NONFINITE, RANGE, DEVICE)."""
