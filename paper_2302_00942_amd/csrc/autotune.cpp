@@ -54,12 +54,12 @@ void set_tuned(int knob, int M, int prec, int DB, int64_t N, int value) {
   t.v[Key{knob, M, prec, DB, log2_bucket(N)}] = value;
 }
 
-// Defaults from tuning runs on MI355X: FP32 is fastest with one tile per wave
-// at every size; BF16 (whose workgroups stage twice the G bytes) prefers
-// fewer workgroups as N grows.
+// Default from tuning runs on MI355X: one tile per wave at every size and
+// precision (the expansion keeps 8 waves per SIMD resident).
 int default_expand_tiles_per_wave(int64_t N, int prec) {
-  if (!prec || N < (int64_t)1 << 16) return 1;
-  return N < (int64_t)1 << 19 ? 4 : 16;
+  (void)N;
+  (void)prec;
+  return 1;
 }
 int default_batch_tiles_per_item() { return 64; }
 

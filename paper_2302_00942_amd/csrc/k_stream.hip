@@ -315,10 +315,33 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, int64_t N,
 
   const int pp = tid & 31;   // point pair within the chunk
   const int kq = tid >> 5;   // frequency phase 0..7
+  constexpr int DC = DB * 16;
+  constexpr int FPT = kChunk * DC / 256;  // field values per thread per chunk
+  // registers of one chunk: the coordinates of points pa, pa + 1 and FPT field
+  // values; the next chunk's are loaded while the current one is multiplied
+  float xa = 0.f, ya = 0.f, za = 0.f, xb = 0.f, yb = 0.f, zb = 0.f;
+  float fv[FPT];
+  const auto load_chunk = [&](int64_t base) {
+    const int64_t pa = base + 2 * pp, pb = pa + 1;
+    if (base + kChunk <= N) {
+      xa = X[pa * 3]; ya = X[pa * 3 + 1]; za = X[pa * 3 + 2];
+      xb = X[pb * 3]; yb = X[pb * 3 + 1]; zb = X[pb * 3 + 2];
+    } else {
+      xa = ya = za = xb = yb = zb = 0.f;
+      if (pa < N) { xa = X[pa * 3]; ya = X[pa * 3 + 1]; za = X[pa * 3 + 2]; }
+      if (pb < N) { xb = X[pb * 3]; yb = X[pb * 3 + 1]; zb = X[pb * 3 + 2]; }
+    }
+#pragma unroll
+    for (int q = 0; q < FPT; ++q) {
+      const int idx = tid + 256 * q;
+      const int p = idx / DC, c = idx - p * DC;
+      const int64_t gp = base + p;
+      fv[q] = (gp < N && c < d) ? F[gp * ldF + c] : 0.f;
+    }
+  };
   // features of points pa, pa + 1 into LDS (device order rows); points past
   // N (only in a cloud's last chunk) get zero features
-  const auto features = [&](int64_t pa, bool va, bool vb, float xa, float ya, float za, float xb, float yb,
-                            float zb, auto masked) {
+  const auto features = [&](int64_t pa, bool va, bool vb, auto masked) {
 #pragma unroll 2
     for (int k = kq; k < FQ; k += 8) {
       const float4 w = oms[k];
@@ -340,36 +363,30 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, int64_t N,
       }
     }
   };
+  if (c0 < c1) load_chunk(c0 * kChunk);
   for (int64_t ch = c0; ch < c1; ++ch) {
     const int64_t base = ch * kChunk;
     __syncthreads();  // previous chunk's MFMA reads are done (and oms is visible)
-    const int64_t pa = base + 2 * pp, pb = pa + 1;
-    if (base + kChunk <= N) {  // full chunk (uniform branch): no masking
-      features(pa, true, true, X[pa * 3], X[pa * 3 + 1], X[pa * 3 + 2], X[pb * 3], X[pb * 3 + 1], X[pb * 3 + 2],
-               std::false_type{});
-    } else {
-      const bool va = pa < N, vb = pb < N;
-      float xa = 0.f, ya = 0.f, za = 0.f, xb = 0.f, yb = 0.f, zb = 0.f;
-      if (va) { xa = X[pa * 3]; ya = X[pa * 3 + 1]; za = X[pa * 3 + 2]; }
-      if (vb) { xb = X[pb * 3]; yb = X[pb * 3 + 1]; zb = X[pb * 3 + 2]; }
-      features(pa, va, vb, xa, ya, za, xb, yb, zb, std::true_type{});
-    }
+    const int64_t pa = base + 2 * pp;
+    if (base + kChunk <= N)  // full chunk (uniform branch): no masking
+      features(pa, true, true, std::false_type{});
+    else
+      features(pa, pa < N, pa + 1 < N, std::true_type{});
     // ---- field chunk, transposed to [channel][point]
-    {
-      constexpr int DC = DB * 16;
-      for (int idx = tid; idx < kChunk * DC; idx += 256) {
-        const int p = idx / DC, c = idx - p * DC;
-        const int64_t gp = base + p;
-        float v = (gp < N && c < d) ? F[gp * ldF + c] : 0.f;
-        if constexpr (PREC) {
-          const __bf16 hi = (__bf16)v;
-          fs[c * P + p] = hi;
-          fsl[c * P + p] = (__bf16)(v - (float)hi);
-        } else {
-          fs[c * P + p] = v;
-        }
+#pragma unroll
+    for (int q = 0; q < FPT; ++q) {
+      const int idx = tid + 256 * q;
+      const int p = idx / DC, c = idx - p * DC;
+      const float v = fv[q];
+      if constexpr (PREC) {
+        const __bf16 hi = (__bf16)v;
+        fs[c * P + p] = hi;
+        fsl[c * P + p] = (__bf16)(v - (float)hi);
+      } else {
+        fs[c * P + p] = v;
       }
     }
+    if (ch + 1 < c1) load_chunk(base + kChunk);  // in flight during the products below
     __syncthreads();
     bta_mma<M, PREC, GRAM, DB>(phi, fs, fsl, acc, hacc, lane, wave);
   }
@@ -526,6 +543,42 @@ __global__ __launch_bounds__(256) void k_gcore_batch(const CloudDesc* __restrict
 }
 
 // ------------------------------------------------------------------ k_expand
+// The F values a lane adds to its outputs: rows tile*16 + 4g + q, column
+// cb*16 + pl (the MFMA output layout), zero outside the cloud and the field.
+template <int DB>
+__device__ __forceinline__ void load_residual(const float* F, int64_t ldF, int d, int64_t N, int64_t tile, int g,
+                                              int pl, float (&fres)[DB][4]) {
+#pragma unroll
+  for (int cb = 0; cb < DB; ++cb) {
+    const int c = cb * 16 + pl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t pr = tile * 16 + 4 * g + q;
+      fres[cb][q] = (c < d && pr < N) ? F[pr * ldF + c] : 0.f;
+    }
+  }
+}
+
+template <int DB>
+__device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* __restrict__ rowscale, int d,
+                                          int64_t N, int64_t tile, int g, int pl, const float (&fres)[DB][4],
+                                          const f32x4 (&acc)[DB]) {
+#pragma unroll
+  for (int cb = 0; cb < DB; ++cb) {
+    const int c = cb * 16 + pl;
+    if (c < d) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t pr = tile * 16 + 4 * g + q;
+        if (pr < N) {
+          const float v = fres[cb][q] + acc[cb][q];
+          out[pr * ldO + c] = rowscale ? rowscale[pr] * v : v;
+        }
+      }
+    }
+  }
+}
+
 // out = F + Phi G'. Each wave owns tiles of 16 points; lane l handles point
 // l%16 and the feature group g = l/16 of every K step. Point tiles are
 // distributed round-robin over the waves of the grid.
@@ -569,10 +622,12 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
       const int64_t p = tile * 16 + pl;
       float x = 0.f, y = 0.f, z = 0.f;
       if (p < N) { x = X[p * 3]; y = X[p * 3 + 1]; z = X[p * 3 + 2]; }
+      float fres[DB][4];  // the residual F values of this lane's outputs, loaded ahead of the products
+      load_residual(F, ldF, d, N, tile, g, pl, fres);
       f32x4 acc[DB];
 #pragma unroll
       for (int cb = 0; cb < DB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
+#pragma unroll 2
       for (int s = 0; s < M / 32; ++s) {
         u32x4_t aw;
 #pragma unroll
@@ -591,26 +646,15 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
           acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[cb], 0, 0, 0);
         }
       }
-#pragma unroll
-      for (int cb = 0; cb < DB; ++cb) {
-        const int c = cb * 16 + pl;
-        if (c < d) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int64_t pr = tile * 16 + 4 * g + q;
-            if (pr < N) {
-              const float v = F[pr * ldF + c] + acc[cb][q];
-              out[pr * ldO + c] = rowscale ? rowscale[pr] * v : v;
-            }
-          }
-        }
-      }
+      store_out(out, ldO, rowscale, d, N, tile, g, pl, fres, acc);
     }
   } else {
     for (int64_t tile = t_first + (tid >> 6); tile < ntiles; tile += wstride) {
       const int64_t p = tile * 16 + pl;
       float x = 0.f, y = 0.f, z = 0.f;
       if (p < N) { x = X[p * 3]; y = X[p * 3 + 1]; z = X[p * 3 + 2]; }
+      float fres[DB][4];
+      load_residual(F, ldF, d, N, tile, g, pl, fres);
       f32x4 acc[DB];
 #pragma unroll
       for (int cb = 0; cb < DB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -628,20 +672,7 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
           acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(sn, b1, acc[cb], 0, 0, 0);
         }
       }
-#pragma unroll
-      for (int cb = 0; cb < DB; ++cb) {
-        const int c = cb * 16 + pl;
-        if (c < d) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int64_t pr = tile * 16 + 4 * g + q;
-            if (pr < N) {
-              const float v = F[pr * ldF + c] + acc[cb][q];
-              out[pr * ldO + c] = rowscale ? rowscale[pr] * v : v;
-            }
-          }
-        }
-      }
+      store_out(out, ldO, rowscale, d, N, tile, g, pl, fres, acc);
     }
   }
 }
