@@ -220,8 +220,7 @@ rfd_status rfd_autotune(rfd_plan_t plan, const float* F_dev, int64_t ldF, int32_
                         float* out_dev, int64_t ldO, int32_t reps, rfd_stream_t stream);
 
 /* Autotunes the number of workgroups of the cooperative phi_1 kernel for the
- * plan's padded m (candidates: 2 (m/32)^2 capped at 128, halved down to 8 or
- * to a quarter of that): re-runs phi_1 on the plan's core `reps` times per
+ * plan's padded m (candidates: (m/32)^2, its half and its quarter): re-runs phi_1 on the plan's core `reps` times per
  * candidate, timed with hipEvents on `stream`, and records the fastest in the
  * tuning table (key: m). The count never changes results. Requires features
  * (rfd_features or a one-shot call). Errors: RFD_ERR_INVALID_ARG,

@@ -129,8 +129,8 @@ rfd_status rfd_autotune_phi1(rfd_plan_t p, int32_t reps, rfd_stream_t stream) {
   if (p->N < 0) return RFD_ERR_NOT_READY;
   if (p->N == 0) return RFD_OK;
   hipStream_t st = (hipStream_t)stream;
-  const int M = p->dev_m, nt2 = 2 * (M / 32) * (M / 32);
-  const int prev = rfd::tuned(rfd::kTunePhi1Workgroups, M, 0, 1, 0, nt2 > 128 ? 128 : nt2);
+  const int M = p->dev_m, nt = (M / 32) * (M / 32);
+  const int prev = rfd::tuned(rfd::kTunePhi1Workgroups, M, 0, 1, 0, nt);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -141,7 +141,7 @@ rfd_status rfd_autotune_phi1(rfd_plan_t p, int32_t reps, rfd_stream_t stream) {
   float best_ms = 1e30f;
   bool ok = true;
   // phi_1 reads the plan's core and rewrites S and T with the same values
-  for (int nw = nt2 < 128 ? nt2 : 128; ok && nw >= 8 && nw * 8 >= nt2; nw /= 2) {
+  for (int nw = nt; ok && nw >= 2 && nw * 4 >= nt; nw /= 2) {
     rfd::set_tuned(rfd::kTunePhi1Workgroups, M, 0, 1, 0, nw);
     ok = rfd::launch_phi1(p, st) == hipSuccess && hipEventRecord(e0, st) == hipSuccess;
     for (int r = 0; ok && r < reps; ++r) ok = rfd::launch_phi1(p, st) == hipSuccess;

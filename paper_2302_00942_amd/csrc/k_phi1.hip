@@ -88,69 +88,153 @@ struct GridBarrier {
   }
 };
 
-// ------------------------------------------------------------------ GEMM tile
-// 32 x 32 tile (ti, tj) of alpha A B for row-major m x m A and B. Each wave
-// computes one 16 x 16 quadrant with four independent MFMA chains (k-steps
-// taken round-robin, summed in a fixed order); the caller's epilogue gets
-// (i, j, value) for the four values each lane holds.
-template <int m, class EPI>
-__device__ __forceinline__ void gemm_tile(int ti, int tj, const double* __restrict__ A,
-                                          const double* __restrict__ B, double alpha, double* lds, EPI epi) {
-  double* As = lds;                 // 32 x (m + 1)
-  double* Bs = lds + 32 * (m + 1);  // m x 33
+// ------------------------------------------------------------------ GEMM tiles
+// One workgroup computes the 32 x 32 tile (ti, tj) of C1 = alpha1 A1 B1 and,
+// with NP = 2, of C2 = alpha2 A2 B2, for row-major m x m operands. The two
+// products of a phase share a panel: SHARE == kShareA (A2 is A1: the row
+// panel of A is loaded once) or kShareB (B2 is B1). K runs in blocks of KB
+// through LDS. With ALL, every block's panels are loaded into registers up
+// front (one memory round trip per tile) and staged through one LDS buffer;
+// otherwise two LDS buffers alternate and the next block's panels are loaded
+// while the current block is multiplied. Each wave computes one 16 x 16
+// quadrant of each tile with four MFMA chains over the k steps (k = 4c mod 16
+// in chain c, increasing k within a chain), summed in a fixed order. The NS
+// side matrices the epilogue reads elementwise are loaded with the panels
+// (ALL) or after the products; the epilogue gets (i, j, c1, c2, side values at (i, j)) for the four
+// values each lane holds.
+constexpr int kShareA = 0, kShareB = 1;
+// doubles per LDS panel: A panels are 32 x KB (row pitch KB + 1), B panels
+// KB x 32 (row pitch 33)
+constexpr int panel_doubles(int KB) { return 32 * (KB + 1) > KB * 33 ? 32 * (KB + 1) : KB * 33; }
+constexpr int gemm_lds_doubles(int KB, bool all) { return (all ? 1 : 2) * 3 * panel_doubles(KB); }
+
+template <int NS>
+struct Side {
+  double v[NS > 0 ? NS : 1];
+};
+
+template <int m, int KB, bool ALL, int NP, int SHARE, int NS = 0, class EPI>
+__device__ __forceinline__ void gemm_tiles(int ti, int tj, const double* __restrict__ A1,
+                                           const double* __restrict__ B1, const double* __restrict__ A2,
+                                           const double* __restrict__ B2, double alpha1, double alpha2,
+                                           double* lds, EPI epi, const double* S0 = nullptr,
+                                           const double* S1 = nullptr, const double* S2 = nullptr) {
+  constexpr int NA = (NP == 2 && SHARE == kShareB) ? 2 : 1;  // A row panels per block
+  constexpr int NBP = (NP == 2 && SHARE == kShareA) ? 2 : 1; // B column panels per block
+  constexpr int NB_K = m / KB;
+  constexpr int PD = panel_doubles(KB);
+  constexpr int AP = KB + 1;         // A panel row pitch
+  constexpr int LQ = 32 * KB / 512;  // double2 per thread per panel
+  constexpr int AH = KB / 2;         // double2 per A panel row
+  constexpr int NR = ALL ? NB_K : 1; // blocks held in registers
   const int tid = threadIdx.x;
-  constexpr int NL = 16 * m / 256;  // double2 loads per thread and operand
-  __syncthreads();
-  // each operand's loads are all issued before its first LDS store
-  {
-    const double2* A2 = (const double2*)(A + (size_t)ti * 32 * m);
-    double2 va[NL];
+  const double* Ag[2] = {A1, A2};
+  const double* Bg[2] = {B1, B2};
+  double2 ra[NR][NA][LQ], rb[NR][NBP][LQ];
+  // A panel element e = tid + 256 q: row e / AH, double2 column e % AH;
+  // B panel element e: row e / 16, double2 column e % 16
+  const auto load = [&](int kb, int slot) {
 #pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = tid + 256 * q;  // 32 rows x m/2 double2
-      va[q] = A2[(size_t)(e / (m / 2)) * (m / 2) + (e % (m / 2))];
-    }
+    for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = tid + 256 * q;
-      const int i = e / (m / 2), k2 = e % (m / 2);
-      As[i * (m + 1) + 2 * k2] = va[q].x;
-      As[i * (m + 1) + 2 * k2 + 1] = va[q].y;
-    }
-  }
-  {
-    double2 vb[NL];
+      for (int q = 0; q < LQ; ++q) {
+        const int e = tid + 256 * q, r = e / AH, c2 = e % AH;
+        ra[slot][a][q] = *(const double2*)(Ag[a] + (size_t)(ti * 32 + r) * m + kb * KB + 2 * c2);
+      }
 #pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = tid + 256 * q;  // m rows x 16 double2
-      vb[q] = *(const double2*)(B + (size_t)(e >> 4) * m + tj * 32 + 2 * (e & 15));
-    }
+    for (int b = 0; b < NBP; ++b)
 #pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = tid + 256 * q;
-      const int k = e >> 4, j2 = e & 15;
-      Bs[k * 33 + 2 * j2] = vb[q].x;
-      Bs[k * 33 + 2 * j2 + 1] = vb[q].y;
-    }
-  }
-  __syncthreads();
+      for (int q = 0; q < LQ; ++q) {
+        const int e = tid + 256 * q, r = e >> 4, c2 = e & 15;
+        rb[slot][b][q] = *(const double2*)(Bg[b] + (size_t)(kb * KB + r) * m + tj * 32 + 2 * c2);
+      }
+  };
+  const auto store = [&](int slot, double* buf) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int q = 0; q < LQ; ++q) {
+        const int e = tid + 256 * q, r = e / AH, c2 = e % AH;
+        buf[a * PD + r * AP + 2 * c2] = ra[slot][a][q].x;
+        buf[a * PD + r * AP + 2 * c2 + 1] = ra[slot][a][q].y;
+      }
+#pragma unroll
+    for (int b = 0; b < NBP; ++b)
+#pragma unroll
+      for (int q = 0; q < LQ; ++q) {
+        const int e = tid + 256 * q, r = e >> 4, c2 = e & 15;
+        buf[(NA + b) * PD + r * 33 + 2 * c2] = rb[slot][b][q].x;
+        buf[(NA + b) * PD + r * 33 + 2 * c2 + 1] = rb[slot][b][q].y;
+      }
+  };
   const int w = tid >> 6, l = tid & 63, qi = w >> 1, qj = w & 1;
-  f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
-  const double* ap = As + (qi * 16 + (l & 15)) * (m + 1) + (l >> 4);
-  const double* bp = Bs + (l >> 4) * 33 + qj * 16 + (l & 15);
-#pragma unroll 4
-  for (int s = 0; s < m / 4; s += 4) {
-    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[4 * s], bp[4 * s * 33], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[4 * s + 4], bp[(4 * s + 4) * 33], acc1, 0, 0, 0);
-    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[4 * s + 8], bp[(4 * s + 8) * 33], acc2, 0, 0, 0);
-    acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[4 * s + 12], bp[(4 * s + 12) * 33], acc3, 0, 0, 0);
+  // output element r of this lane: row ti*32 + qi*16 + 4r + l/16, column tj*32 + qj*16 + l%16
+  const auto out_index = [&](int r) {
+    return (size_t)(ti * 32 + qi * 16 + 4 * r + (l >> 4)) * m + tj * 32 + qj * 16 + (l & 15);
+  };
+  Side<NS> side[4];
+  const auto load_side = [&]() {
+    const double* sp[3] = {S0, S1, S2};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < NS; ++q) side[r].v[q] = sp[q][out_index(r)];
+  };
+  f64x4 acc[NP][4];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[p][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const auto multiply = [&](const double* buf) {
+    const int ao = (qi * 16 + (l & 15)) * AP + (l >> 4);
+    const int bo = (l >> 4) * 33 + qj * 16 + (l & 15);
+#pragma unroll
+    for (int s = 0; s < KB / 4; s += 4) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k = 4 * (s + c);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const int pa = (NA == 2) ? p : 0, pb = (NBP == 2) ? p : 0;
+          acc[p][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(buf[pa * PD + ao + k], buf[(NA + pb) * PD + bo + k * 33],
+                                                           acc[p][c], 0, 0, 0);
+        }
+      }
+    }
+  };
+  if constexpr (ALL) {
+#pragma unroll
+    for (int kb = 0; kb < NB_K; ++kb) load(kb, kb);  // every load in flight at once
+    load_side();
+#pragma unroll
+    for (int kb = 0; kb < NB_K; ++kb) {
+      __syncthreads();  // the buffer's previous readers are done
+      store(kb, lds);
+      __syncthreads();
+      multiply(lds);
+    }
+  } else {
+    __syncthreads();  // the buffers' previous readers are done
+    load(0, 0);
+    store(0, lds);
+    __syncthreads();
+#pragma unroll 1
+    for (int kb = 0; kb < NB_K; ++kb) {
+      if (kb + 1 < NB_K) load(kb + 1, 0);  // in flight during this block's products
+      multiply(lds + (kb & 1) * 3 * PD);
+      if (kb + 1 < NB_K) store(0, lds + ((kb + 1) & 1) * 3 * PD);
+      __syncthreads();
+    }
+    load_side();  // after the loop: no registers held across it
   }
   // f64 16x16x4 output layout: register r holds row 4 r + l/16, column l%16
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = ti * 32 + qi * 16 + 4 * r + (l >> 4);
     const int j = tj * 32 + qj * 16 + (l & 15);
-    epi(i, j, alpha * ((acc0[r] + acc1[r]) + (acc2[r] + acc3[r])));
+    const double v1 = alpha1 * ((acc[0][0][r] + acc[0][1][r]) + (acc[0][2][r] + acc[0][3][r]));
+    const double v2 = NP == 2 ? alpha2 * ((acc[NP - 1][0][r] + acc[NP - 1][1][r]) + (acc[NP - 1][2][r] + acc[NP - 1][3][r])) : 0.0;
+    epi(i, j, v1, v2, side[r]);
   }
 }
 
@@ -183,38 +267,26 @@ struct TaylorWs {
   double sc1;        // 2^-s
 };
 
-// Horner step J (J = 4 ... 0): R_chain <- Y4 R_chain + B_J, both chains.
-template <int m, int J, class BAR>
+// Horner step J (J = 4 ... 0): R_chain <- Y4 R_chain + B_J, both chains (one
+// workgroup per tile, the Y4 row panel shared by the two products).
+template <int m, int KB, bool ALL, int J, class BAR>
 __device__ __forceinline__ void horner_phase(const TaylorWs& w, int worker, int nw, double* lds, BAR& bar) {
   constexpr int nb = m / 32, nt = nb * nb;
   constexpr int src = (J + 1) & 1, dst = J & 1;
-  for (int tile = worker; tile < 2 * nt; tile += nw) {
-    const int tt = tile % nt;
-    const auto form = [&](int i, int j, double& id, double& y, double& y2, double& y3) {
-      const size_t e = (size_t)i * m + j;
-      id = i == j ? 1.0 : 0.0;
-      y = w.X0[e] * w.sc1;
-      y2 = w.Y2[e];
-      y3 = w.Y3[e];
-    };
-    if (tile < nt) {
-      gemm_tile<m>(tt / nb, tt % nb, w.Y4, w.R[0][src], 1.0, lds, [&](int i, int j, double v) {
-        double id, y, y2, y3;
-        form(i, j, id, y, y2, y3);
-        w.R[0][dst][(size_t)i * m + j] = v + coef_block<J, 0>(id, y, y2, y3);
-      });
-    } else {
-      gemm_tile<m>(tt / nb, tt % nb, w.Y4, w.R[1][src], 1.0, lds, [&](int i, int j, double v) {
-        double id, y, y2, y3;
-        form(i, j, id, y, y2, y3);
-        w.R[1][dst][(size_t)i * m + j] = v + coef_block<J, 1>(id, y, y2, y3);
-      });
-    }
-  }
+  for (int tile = worker; tile < nt; tile += nw)
+    gemm_tiles<m, KB, ALL, 2, kShareA, 3>(
+        tile / nb, tile % nb, w.Y4, w.R[0][src], w.Y4, w.R[1][src], 1.0, 1.0, lds,
+        [&](int i, int j, double v0, double v1, const Side<3>& sd) {
+          const size_t e = (size_t)i * m + j;
+          const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * w.sc1, y2 = sd.v[1], y3 = sd.v[2];
+          w.R[0][dst][e] = v0 + coef_block<J, 0>(id, y, y2, y3);
+          w.R[1][dst][e] = v1 + coef_block<J, 1>(id, y, y2, y3);
+        },
+        w.X0, w.Y2, w.Y3);
   bar.sync();
 }
 
-template <int m, class BAR>
+template <int m, int KB, bool ALL, class BAR>
 __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw, double* lds, BAR& bar) {
   constexpr int nb = m / 32, nt = nb * nb;
   const size_t mm = (size_t)m * m;
@@ -259,46 +331,47 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
 
   // ---- P1: Y2 = X0 X0 / 4^s
   for (int tile = worker; tile < nt; tile += nw)
-    gemm_tile<m>(tile / nb, tile % nb, X0, X0, sc2, lds, [&](int i, int j, double v) { Y2[(size_t)i * m + j] = v; });
+    gemm_tiles<m, KB, ALL, 1, kShareA>(tile / nb, tile % nb, X0, X0, X0, X0, sc2, 0.0, lds,
+                                       [&](int i, int j, double v, double, const Side<0>&) {
+                                         Y2[(size_t)i * m + j] = v;
+                                       });
   bar.sync();
   // ---- P2: Y3 = Y2 X0 / 2^s (its epilogue also forms B_5 of both chains) and Y4 = Y2 Y2
-  for (int tile = worker; tile < 2 * nt; tile += nw) {
-    const int tt = tile % nt;
-    if (tile < nt)
-      gemm_tile<m>(tt / nb, tt % nb, Y2, X0, sc1, lds, [&](int i, int j, double y3) {
-        const size_t e = (size_t)i * m + j;
-        const double id = i == j ? 1.0 : 0.0, y = X0[e] * sc1, y2 = Y2[e];
-        Y3[e] = y3;
-        R01[e] = coef_block<5, 0>(id, y, y2, y3);
-        R11[e] = coef_block<5, 1>(id, y, y2, y3);
-      });
-    else
-      gemm_tile<m>(tt / nb, tt % nb, Y2, Y2, 1.0, lds, [&](int i, int j, double v) { Y4[(size_t)i * m + j] = v; });
-  }
+  for (int tile = worker; tile < nt; tile += nw)
+    gemm_tiles<m, KB, ALL, 2, kShareA, 2>(
+        tile / nb, tile % nb, Y2, X0, Y2, Y2, sc1, 1.0, lds,
+        [&](int i, int j, double y3, double y4, const Side<2>& sd) {
+          const size_t e = (size_t)i * m + j;
+          const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * sc1, y2 = sd.v[1];
+          Y3[e] = y3;
+          Y4[e] = y4;
+          R01[e] = coef_block<5, 0>(id, y, y2, y3);
+          R11[e] = coef_block<5, 1>(id, y, y2, y3);
+        },
+        X0, Y2);
   bar.sync();
   // ---- P3..P7: Horner steps J = 4 ... 0 (J odd reads buffer 0, writes 1 ... ends in buffer 0)
   const TaylorWs w{X0, Y2, Y3, Y4, {{R00, R01}, {R10, R11}}, sc1};
-  horner_phase<m, 4>(w, worker, nw, lds, bar);
-  horner_phase<m, 3>(w, worker, nw, lds, bar);
-  horner_phase<m, 2>(w, worker, nw, lds, bar);
-  horner_phase<m, 1>(w, worker, nw, lds, bar);
-  horner_phase<m, 0>(w, worker, nw, lds, bar);
+  horner_phase<m, KB, ALL, 4>(w, worker, nw, lds, bar);
+  horner_phase<m, KB, ALL, 3>(w, worker, nw, lds, bar);
+  horner_phase<m, KB, ALL, 2>(w, worker, nw, lds, bar);
+  horner_phase<m, KB, ALL, 1>(w, worker, nw, lds, bar);
+  horner_phase<m, KB, ALL, 0>(w, worker, nw, lds, bar);
   // ---- undo the scaling: P <- P (E + I) / 2, E <- E E
   double* Pc = R00;
   double* Ec = R10;
   double* Pn = R01;
   double* En = R11;
   for (int it = 0; it < s; ++it) {
-    for (int tile = worker; tile < 2 * nt; tile += nw) {
-      const int tt = tile % nt;
-      if (tile < nt)
-        gemm_tile<m>(tt / nb, tt % nb, Ec, Ec, 1.0, lds, [&](int i, int j, double v) { En[(size_t)i * m + j] = v; });
-      else
-        gemm_tile<m>(tt / nb, tt % nb, Pc, Ec, 0.5, lds, [&](int i, int j, double v) {
-          const size_t e = (size_t)i * m + j;
-          Pn[e] = v + 0.5 * Pc[e];
-        });
-    }
+    for (int tile = worker; tile < nt; tile += nw)
+      gemm_tiles<m, KB, ALL, 2, kShareB, 1>(
+          tile / nb, tile % nb, Ec, Ec, Pc, Ec, 1.0, 0.5, lds,
+          [&](int i, int j, double e2, double pe, const Side<1>& sd) {
+            const size_t e = (size_t)i * m + j;
+            En[e] = e2;
+            Pn[e] = pe + 0.5 * sd.v[0];
+          },
+          Pc);
     bar.sync();
     double* x = Ec; Ec = En; En = x;
     x = Pc; Pc = Pn; Pn = x;
@@ -316,19 +389,25 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   }
 }
 
+// K blocks: the one-workgroup-per-cloud kernel keeps LDS small (three
+// workgroups per CU) and pipelines 32-wide blocks; the cooperative kernel
+// (one workgroup per CU) issues all of a tile's loads at once and stages
+// 128-wide blocks, one memory round trip per tile.
+constexpr int kWgKB = 32, kGridKB = 128;
+
 template <int M>
 __global__ __launch_bounds__(256) void k_phi1_wg(const Phi1Args* __restrict__ args) {
   extern __shared__ double lds[];
   const Phi1Args a = args[blockIdx.x];
   WgBarrier bar;
-  phi1_body<M>(a, 0, 1, lds, bar);
+  phi1_body<M, kWgKB, false>(a, 0, 1, lds, bar);
 }
 
 template <int M>
 __global__ __launch_bounds__(256) void k_phi1_grid(Phi1Args a) {
   extern __shared__ double lds[];
   GridBarrier bar{a.barrier, gridDim.x, 0u, a.flag};
-  phi1_body<M>(a, (int)blockIdx.x, (int)gridDim.x, lds, bar);
+  phi1_body<M, (M < kGridKB ? M : kGridKB), true>(a, (int)blockIdx.x, (int)gridDim.x, lds, bar);
 }
 
 __global__ void k_zero_u32(unsigned* p, int n) {
@@ -337,7 +416,7 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 }
 
 // LDS bytes of the phi_1 kernels for padded size m.
-static size_t phi1_lds_bytes(int m) { return (size_t)(32 * (m + 1) + m * 33) * 8; }
+static size_t phi1_lds_bytes(int KB, bool all) { return (size_t)gemm_lds_doubles(KB, all) * sizeof(double); }
 
 size_t phi1_ws_doubles(int m) { return 8 * (size_t)m * m + m; }
 
@@ -358,16 +437,16 @@ static void fill_args(rfd_plan_s* p, Phi1Args& a) {
 
 template <int M>
 static hipError_t launch_phi1_m(Phi1Args& a, hipStream_t st) {
-  const size_t lds = phi1_lds_bytes(M);
+  const size_t lds = phi1_lds_bytes(M < kGridKB ? M : kGridKB, true);
   hipError_t e = hipFuncSetAttribute((const void*)k_phi1_grid<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   constexpr int nb = M / 32;
-  // workgroups: the widest phases (Horner steps, squarings) have 2 nb^2 tiles;
-  // fewer workgroups make the barrier cheaper and give each more tiles (the
-  // count never changes results: each tile is computed the same way)
-  int nw = tuned(kTunePhi1Workgroups, M, 0, 1, 0, 2 * nb * nb > 128 ? 128 : 2 * nb * nb);
+  // workgroups: every phase has nb^2 tiles (pairs of products); fewer
+  // workgroups make the barrier cheaper and give each more tiles (the count
+  // never changes results: each tile is computed the same way)
+  int nw = tuned(kTunePhi1Workgroups, M, 0, 1, 0, nb * nb);
   if (nw < 1) nw = 1;
-  if (nw > 2 * nb * nb) nw = 2 * nb * nb;
+  if (nw > nb * nb) nw = nb * nb;
   hipLaunchKernelGGL(k_zero_u32, dim3((kBarWords + 255) / 256), dim3(256), 0, st, a.barrier, kBarWords);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -391,7 +470,7 @@ void phi1_fill_args(rfd_plan_s* p, void* args_out) { fill_args(p, *(Phi1Args*)ar
 
 template <int M>
 static hipError_t launch_phi1_batch_m(int n, const void* dev_args, hipStream_t st) {
-  const size_t lds = phi1_lds_bytes(M);
+  const size_t lds = phi1_lds_bytes(kWgKB, false);
   hipError_t e = hipFuncSetAttribute((const void*)k_phi1_wg<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   ProfileScope prof(kKPhi1Batch, st);
