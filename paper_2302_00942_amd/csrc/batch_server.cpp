@@ -14,6 +14,7 @@ struct rfd_batch_s {
   int64_t total_n = 0;
   std::vector<int64_t> Ns;
   int exp_cap = 0;  // capacity of dwork_exp in items
+  int max_parts = 0;  // largest split-N partition of the batch
   int64_t nmax_copy = 0;
   std::vector<rfd_plan_s*> plans;
   rfd::CloudDesc* dcl = nullptr;
@@ -57,7 +58,7 @@ void free_batch(rfd_batch_s* b) {
 rfd_status enqueue(rfd_batch_s* b, hipStream_t st) {
   HIPCK(rfd::launch_copy_points_batch(b->dcp, b->n, b->nmax_copy, st));
   HIPCK(rfd::launch_bta_batch(b->M, b->prec, b->DB, b->dcl, b->dwork_bta, b->nwork_bta, st));
-  HIPCK(rfd::launch_reduce_batch(b->M, b->DB, b->dcl, b->n, st));
+  HIPCK(rfd::launch_reduce_batch(b->M, b->DB, b->dcl, b->n, b->max_parts, st));
   HIPCK(rfd::launch_phi1_batch_dev(b->M, b->n, b->dargs, st));
   HIPCK(rfd::launch_gcore_batch(b->M, b->dmax, b->dcl, b->n, st));
   if (b->nwork_exp > 0)
@@ -122,6 +123,7 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
     rfd_plan_s* p = plans[i];
     const int64_t N = Ns[i];
     const int np = rfd::bta_partials(N, M, ds[i], true, prec);
+    b->max_parts = std::max(b->max_parts, np);
     rfd_status s = rfd::ensure_x(p, std::max<int64_t>(N, 1), nullptr);
     if (s == RFD_OK) s = rfd::ensure_partials(p, (size_t)np * stride, nullptr);
     if (s != RFD_OK) {

@@ -444,21 +444,18 @@ __device__ __forceinline__ void reduce1_body(const float* __restrict__ partials,
   lvl[(size_t)g * E + e] = s;
 }
 
-__device__ __forceinline__ void reduce2_body(const double* __restrict__ lvl, size_t E, int m, int d, int DB, int gram,
-                                             double* __restrict__ Mraw, double* __restrict__ H0, int* __restrict__ flag,
-                                             size_t e) {
-  const int NB = m / 32;
-  const int slots = gram_slots(NB);
-  const size_t ng = gram ? (size_t)4 * slots * 1024 : 0;
-  if (e >= E) return;
-  int I = 0, J = 0;
-  if (e < ng) {
-    const int t = (int)(e >> 10);
-    if (!gram_slot(NB, t / slots, t % slots, I, J)) return;  // spare slot: never written
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int g = 0; g < kReduceGroups; ++g) s += lvl[(size_t)g * E + e];
+// Gram slot (I, J) of element e of a Gram partial, false for a spare slot.
+__device__ __forceinline__ bool reduce_slot(size_t e, size_t ng, int NB, int slots, int& I, int& J) {
+  if (e >= ng) return true;
+  const int t = (int)(e >> 10);
+  return gram_slot(NB, t / slots, t % slots, I, J);
+}
+
+// Writes the reduced element e (Gram tile element or B^T F element) into
+// Mraw (both triangles, canonical order) or H0, flagging non-finite sums.
+__device__ __forceinline__ void reduce_scatter(double s, size_t e, size_t ng, int I, int J, int m, int d, int DB,
+                                               double* __restrict__ Mraw, double* __restrict__ H0,
+                                               int* __restrict__ flag) {
   if (!isfinite(s)) __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const int f = m / 2;
   if (e < ng) {
@@ -476,6 +473,44 @@ __device__ __forceinline__ void reduce2_body(const double* __restrict__ lvl, siz
     const int ch = cb * 16 + (l & 15);
     if (ch < d) H0[(size_t)row * d + ch] = s;
   }
+}
+
+__device__ __forceinline__ void reduce2_body(const double* __restrict__ lvl, size_t E, int m, int d, int DB, int gram,
+                                             double* __restrict__ Mraw, double* __restrict__ H0, int* __restrict__ flag,
+                                             size_t e) {
+  const int NB = m / 32;
+  const int slots = gram_slots(NB);
+  const size_t ng = gram ? (size_t)4 * slots * 1024 : 0;
+  if (e >= E) return;
+  int I = 0, J = 0;
+  if (!reduce_slot(e, ng, NB, slots, I, J)) return;  // spare slot: never written
+  double s = 0.0;
+#pragma unroll
+  for (int g = 0; g < kReduceGroups; ++g) s += lvl[(size_t)g * E + e];
+  reduce_scatter(s, e, ng, I, J, m, d, DB, Mraw, H0, flag);
+}
+
+// Both levels in one thread: the same group sums, added in the same order,
+// so the result is bitwise that of reduce1 + reduce2 (for few partials).
+constexpr int kFusedReduceMaxParts = 64;
+__device__ __forceinline__ void reduce_fused_body(const float* __restrict__ partials, size_t stride, int nparts,
+                                                  size_t E, int m, int d, int DB, int gram, double* __restrict__ Mraw,
+                                                  double* __restrict__ H0, int* __restrict__ flag, size_t e) {
+  const int NB = m / 32;
+  const int slots = gram_slots(NB);
+  const size_t ng = gram ? (size_t)4 * slots * 1024 : 0;
+  if (e >= E) return;
+  int I = 0, J = 0;
+  if (!reduce_slot(e, ng, NB, slots, I, J)) return;
+  double s = 0.0;
+  for (int g = 0; g < kReduceGroups; ++g) {
+    const int b0 = (int)(((int64_t)g * nparts) / kReduceGroups);
+    const int b1 = (int)(((int64_t)(g + 1) * nparts) / kReduceGroups);
+    double sg = 0.0;
+    for (int b = b0; b < b1; ++b) sg += (double)partials[(size_t)b * stride + e];
+    s += sg;
+  }
+  reduce_scatter(s, e, ng, I, J, m, d, DB, Mraw, H0, flag);
 }
 
 __global__ __launch_bounds__(256) void k_reduce1(const float* __restrict__ partials, size_t stride, int nparts,
@@ -499,6 +534,21 @@ __global__ __launch_bounds__(256) void k_reduce2_batch(const CloudDesc* __restri
                                                        int gram) {
   const CloudDesc& c = cl[blockIdx.z];
   reduce2_body(c.lvl, E, m, c.d, DB, gram, c.Mraw, c.H0, c.flag, (size_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_fused(const float* __restrict__ partials, size_t stride, int nparts,
+                                                      size_t E, int m, int d, int DB, int gram,
+                                                      double* __restrict__ Mraw, double* __restrict__ H0,
+                                                      int* __restrict__ flag) {
+  reduce_fused_body(partials, stride, nparts, E, m, d, DB, gram, Mraw, H0, flag,
+                    (size_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_fused_batch(const CloudDesc* __restrict__ cl, size_t stride, size_t E,
+                                                            int m, int DB, int gram) {
+  const CloudDesc& c = cl[blockIdx.y];
+  reduce_fused_body(c.partials, stride, c.nparts, E, m, c.d, DB, gram, c.Mraw, c.H0, c.flag,
+                    (size_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 // ------------------------------------------------------------------ k_gcore
@@ -769,6 +819,11 @@ hipError_t launch_reduce(rfd_plan_s* p, int64_t N, int d, bool gram, hipStream_t
   const size_t stride = bta_partial_floats(M, d, gram);
   const size_t E = reduce_elems(M, DB, gram);
   ProfileScope prof(kKReduce, st);
+  if (nparts <= kFusedReduceMaxParts) {
+    hipLaunchKernelGGL(k_reduce_fused, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, st, p->dev.partials, stride,
+                       nparts, E, M, d, DB, gram ? 1 : 0, p->dev.Mraw, p->dev.H0, p->dev.flag);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_reduce1, dim3((unsigned)((E + 255) / 256), kReduceGroups), dim3(256), 0, st, p->dev.partials,
                      stride, nparts, E, p->dev.lvl);
   hipError_t e = hipGetLastError();
@@ -883,10 +938,15 @@ hipError_t launch_bta_batch(int M, int prec, int DB, const CloudDesc* dcl, const
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce_batch(int M, int DB, const CloudDesc* dcl, int ncl, hipStream_t st) {
+hipError_t launch_reduce_batch(int M, int DB, const CloudDesc* dcl, int ncl, int max_parts, hipStream_t st) {
   const size_t stride = bta_partial_floats(M, 16 * DB, true);
   const size_t E = reduce_elems(M, DB, true);
   ProfileScope prof(kKReduce, st);
+  if (max_parts <= kFusedReduceMaxParts) {
+    hipLaunchKernelGGL(k_reduce_fused_batch, dim3((unsigned)((E + 255) / 256), (unsigned)ncl), dim3(256), 0, st, dcl,
+                       stride, E, M, DB, 1);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_reduce1_batch, dim3((unsigned)((E + 255) / 256), kReduceGroups, (unsigned)ncl), dim3(256), 0, st,
                      dcl, stride, E);
   hipError_t e = hipGetLastError();

@@ -134,7 +134,7 @@ hipError_t launch_copy_rows(const float* src, int64_t ld_src, float* dst, int64_
 // Batched stages over device descriptor arrays.
 hipError_t launch_copy_points_batch(const CopyDesc* dcp, int ncl, int64_t nmax, hipStream_t st);
 hipError_t launch_bta_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, hipStream_t st);
-hipError_t launch_reduce_batch(int M, int DB, const CloudDesc* dcl, int ncl, hipStream_t st);
+hipError_t launch_reduce_batch(int M, int DB, const CloudDesc* dcl, int ncl, int max_parts, hipStream_t st);
 hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hipStream_t st);
 hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, int tpi,
                                hipStream_t st);
