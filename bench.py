@@ -48,6 +48,7 @@ KERNEL_SOURCES = {
     "k_expand": "paper_2302_00942_amd/csrc/k_stream.hip",
     "k_reduce": "paper_2302_00942_amd/csrc/k_stream.hip",
     "k_phi1": "paper_2302_00942_amd/csrc/k_phi1.hip",
+    "k_phi1_apply": "paper_2302_00942_amd/csrc/k_phi1.hip",
 }
 
 
@@ -83,6 +84,13 @@ def phi1_flops(m: int, s: int) -> float:
     return (13 + 2 * s) * 2.0 * m ** 3
 
 
+def phi1_apply_flops(m: int, s: int) -> float:
+    # the same series in action form: the exp chain keeps its m x m products (Y^2,
+    # Y^3 and Y^4, five Horner steps, s - 1 squarings); the phi_1 chain runs on an
+    # m x 32 block (Y v, Y^2 v, Y^3 v, five Horner steps, s squaring updates)
+    return (8 + s - 1) * 2.0 * m ** 3 + (8 + s) * 2.0 * m * m * 32
+
+
 def algorithmic(kernel: str, N: int, m: int, d: int, s: int, nparts: int):
     """(bytes, flops, transcendentals) per launch, from the per-point figures:
     pass 1 (Gram + B^T F) reads X (12 B) and F (4d B) and does m^2 + 2md flops
@@ -96,6 +104,8 @@ def algorithmic(kernel: str, N: int, m: int, d: int, s: int, nparts: int):
         return N * (12 + 8 * d), N * 2.0 * m * d, N * m
     if kernel == "k_phi1":
         return 12 * m * m * 8, phi1_flops(m, s), 0
+    if kernel == "k_phi1_apply":
+        return 8 * m * m * 8, phi1_apply_flops(m, s), 0
     if kernel == "k_reduce":
         floats = m * (m + 1) / 2 + m * d
         return nparts * floats * 4, nparts * floats, 0
@@ -109,7 +119,7 @@ def roofline(kernel: str, avg_ms: float, N: int, m: int, d: int, s: int, nparts:
     if B:
         cands.append(("hbm", B / sec / 1e9, PEAK["hbm_GBs"], "GB/s", B))
     if Fl:
-        if kernel == "k_phi1":
+        if kernel in ("k_phi1", "k_phi1_apply"):
             cands.append(("mfma", Fl / sec / 1e12, PEAK["fp64_TFs"], "TFLOP/s", Fl))
         elif kernel != "k_reduce":
             peak = PEAK["bf16_TFs"] if prec == "bf16" else PEAK["fp32_mfma_TFs"]

@@ -81,6 +81,8 @@ rfd_status rfd_autotune(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, fl
   if (d == 0 || p->N == 0) return RFD_OK;
   if ((const float*)out == F) return RFD_ERR_INVALID_ARG;  // the expansion is re-run: out must not alias F
   hipStream_t st = (hipStream_t)stream;
+  s = rfd::ensure_core(p, st);
+  if (s != RFD_OK) return s;
   const int M = p->dev_m, prec = p->params.precision;
   const int64_t N = p->N;
   // G of the first channel slice, then each candidate expansion of that slice
@@ -156,6 +158,7 @@ rfd_status rfd_autotune_phi1(rfd_plan_t p, int32_t reps, rfd_stream_t stream) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   rfd::set_tuned(rfd::kTunePhi1Workgroups, M, 0, 1, 0, ok && best ? best : prev);
+  if (ok) p->core_ready = true;  // the runs formed S and T
   return ok && best ? RFD_OK : RFD_ERR_DEVICE;
 }
 

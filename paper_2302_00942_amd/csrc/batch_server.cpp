@@ -181,6 +181,7 @@ rfd_status rfd_batch_launch(rfd_batch_t b, rfd_stream_t stream) {
     if (b->plans[i]->dev.X != b->bound[2 * i] || b->plans[i]->dev.partials != b->bound[2 * i + 1])
       return RFD_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
+  for (rfd_plan_s* p : b->plans) p->core_ready = true;  // the batch forms every plan's S and T
   // first launch eager (sets kernel attributes); the second records a graph
   // on a non-default stream; later launches replay it
   if (b->exec) {
@@ -217,6 +218,7 @@ rfd_status rfd_batch_tune(rfd_batch_t b, int32_t reps, rfd_stream_t stream) {
   // one full eager pass leaves every cloud's G in place; the expansion is
   // then re-run with each candidate geometry (it rewrites the same outputs)
   rfd_status s = enqueue(b, st);
+  for (rfd_plan_s* p : b->plans) p->core_ready = true;
   if (s != RFD_OK || b->nwork_exp == 0) return s;
   static const int cands[] = {8, 16, 32, 64, 128, 256};
   const std::vector<int2> most = expand_work(b->Ns, cands[0]);
@@ -287,6 +289,7 @@ rfd_status rfd_integrate_batch(const rfd_plan_t* plans, const float* const* Xs, 
   if (s != RFD_OK) return s;
   b->launches = 1;  // no graph for a single use
   s = enqueue(b, (hipStream_t)stream);
+  for (rfd_plan_s* p : b->plans) p->core_ready = true;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && s == RFD_OK) s = RFD_ERR_DEVICE;
   free_batch(b);
   return s;

@@ -256,6 +256,7 @@ size_t plan_device_bytes(const rfd_plan_s* p) {
 // stream between two event waits (the lane serialises the cooperative
 // launches of concurrent requests).
 static rfd_status enqueue_phi1(rfd_plan_s* p, hipStream_t st, const PhiLane* lane) {
+  p->core_ready = true;
   if (!lane) {
     HIPCK(launch_phi1(p, st));
     return RFD_OK;
@@ -266,6 +267,11 @@ static rfd_status enqueue_phi1(rfd_plan_s* p, hipStream_t st, const PhiLane* lan
   HIPCK(hipEventRecord(lane->after, lane->st));
   HIPCK(hipStreamWaitEvent(st, lane->after, 0));
   return RFD_OK;
+}
+
+rfd_status ensure_core(rfd_plan_s* p, hipStream_t st) {
+  if (p->core_ready || p->N <= 0) return RFD_OK;
+  return enqueue_phi1(p, st, nullptr);
 }
 
 rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_t st, const PhiLane* lane) {
@@ -317,9 +323,15 @@ rfd_status oneshot_enqueue(rfd_plan_s* p, const float* X, int64_t N, const float
   // pass 1 carries the Gram and the first channel slice of B^T F
   HIPCK(launch_bta(p, p->dev.X, N, F, ldF, dc, true, st));
   HIPCK(launch_reduce(p, N, dc, true, st));
-  s = enqueue_phi1(p, st, lane);
-  if (s != RFD_OK) return s;
-  HIPCK(launch_gcore(p, dc, st));
+  if (!lane && dc == d && d <= phi1_apply_max_width()) {
+    // the whole field in one block: phi_1 in action form gives G directly
+    HIPCK(launch_phi1_apply(p, d, st));
+    p->core_ready = false;
+  } else {
+    s = enqueue_phi1(p, st, lane);
+    if (s != RFD_OK) return s;
+    HIPCK(launch_gcore(p, dc, st));
+  }
   HIPCK(launch_expand(p, p->dev.X, N, F, ldF, dc, out, ldO, nullptr, st));
   return integrate_enqueue(p, F, ldF, d, out, ldO, st, dc, nullptr);
 }
@@ -457,6 +469,8 @@ rfd_status rfd_integrate_scaled(rfd_plan_t p, const float* F, int64_t ldF, int32
   if (p->N < 0) return RFD_ERR_NOT_READY;
   rfd_status s = rfd::check_field_args(p->N, F, ldF, d, out, ldO);
   if (s != RFD_OK || d == 0 || p->N == 0) return s;
+  s = rfd::ensure_core(p, (hipStream_t)stream);
+  if (s != RFD_OK) return s;
   return rfd::integrate_enqueue(p, F, ldF, d, out, ldO, (hipStream_t)stream, 0, scale);
 }
 
@@ -481,6 +495,8 @@ rfd_status rfd_plan_check(rfd_plan_t p, rfd_stream_t stream) {
 rfd_status rfd_plan_core(rfd_plan_t p, double* M_out, double* S_out, int32_t* s_out, rfd_stream_t stream) {
   if (!p) return RFD_ERR_INVALID_ARG;
   if (p->N < 0) return RFD_ERR_NOT_READY;
+  rfd_status st = rfd::ensure_core(p, (hipStream_t)stream);
+  if (st != RFD_OK) return st;
   HIPCK(hipStreamSynchronize((hipStream_t)stream));
   const int M = p->dev_m, m = p->m, f = p->f, fp = M / 2;
   const size_t mm = (size_t)M * M;

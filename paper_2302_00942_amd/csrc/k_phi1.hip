@@ -41,6 +41,16 @@ struct Phi1Args {
   unsigned* barrier;   // grid barrier counter (zeroed before launch)
 };
 
+// The action form: G' = diag(c s) S diag(c) H0 for one channel block, without S.
+struct ApplyArgs {
+  const double* H0;  // m x d, device order: B^T F of the block
+  int d;             // channels, <= kThinWidth
+  int reserved;
+  float* G32;        // m x d, device order
+  __bf16* Gt16;      // BF16 hi (d x m), then lo at offset 64 m
+};
+constexpr int kThinWidth = 32;
+
 struct WgBarrier {
   __device__ __forceinline__ void sync() { __syncthreads(); }
 };
@@ -113,12 +123,15 @@ struct Side {
   double v[NS > 0 ? NS : 1];
 };
 
-template <int m, int KB, bool ALL, int NP, int SHARE, int NS = 0, class EPI>
+// LDB and LDC are the row pitches of the B operands and of the output/side
+// matrices (m for m x m operands; the width of a thin operand block).
+template <int m, int KB, bool ALL, int NP, int SHARE, int NS = 0, int LDB = m, int LDC = m, class EPI>
 __device__ __forceinline__ void gemm_tiles(int ti, int tj, const double* __restrict__ A1,
                                            const double* __restrict__ B1, const double* __restrict__ A2,
                                            const double* __restrict__ B2, double alpha1, double alpha2,
                                            double* lds, EPI epi, const double* S0 = nullptr,
-                                           const double* S1 = nullptr, const double* S2 = nullptr) {
+                                           const double* S1 = nullptr, const double* S2 = nullptr,
+                                           const double* S3 = nullptr) {
   constexpr int NA = (NP == 2 && SHARE == kShareB) ? 2 : 1;  // A row panels per block
   constexpr int NBP = (NP == 2 && SHARE == kShareA) ? 2 : 1; // B column panels per block
   constexpr int NB_K = m / KB;
@@ -146,7 +159,7 @@ __device__ __forceinline__ void gemm_tiles(int ti, int tj, const double* __restr
 #pragma unroll
       for (int q = 0; q < LQ; ++q) {
         const int e = tid + 256 * q, r = e >> 4, c2 = e & 15;
-        rb[slot][b][q] = *(const double2*)(Bg[b] + (size_t)(kb * KB + r) * m + tj * 32 + 2 * c2);
+        rb[slot][b][q] = *(const double2*)(Bg[b] + (size_t)(kb * KB + r) * LDB + tj * 32 + 2 * c2);
       }
   };
   const auto store = [&](int slot, double* buf) {
@@ -170,11 +183,11 @@ __device__ __forceinline__ void gemm_tiles(int ti, int tj, const double* __restr
   const int w = tid >> 6, l = tid & 63, qi = w >> 1, qj = w & 1;
   // output element r of this lane: row ti*32 + qi*16 + 4r + l/16, column tj*32 + qj*16 + l%16
   const auto out_index = [&](int r) {
-    return (size_t)(ti * 32 + qi * 16 + 4 * r + (l >> 4)) * m + tj * 32 + qj * 16 + (l & 15);
+    return (size_t)(ti * 32 + qi * 16 + 4 * r + (l >> 4)) * LDC + tj * 32 + qj * 16 + (l & 15);
   };
   Side<NS> side[4];
   const auto load_side = [&]() {
-    const double* sp[3] = {S0, S1, S2};
+    const double* sp[4] = {S0, S1, S2, S3};
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -389,6 +402,180 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   }
 }
 
+// ------------------------------------------------------------------ action form
+// phi_1 applied to a thin block v = diag(c) H0 (m x 32, canonical order) with
+// the same Taylor degree and scaling: since every factor is a polynomial in Y
+// they commute, so
+//   phi_1(2^s Y) v = prod_{k<s} (E_k + I)/2 . phi_1(Y) v,   E_k = e^{2^k Y},
+// and only the exp chain needs m x m products (Horner steps, then squarings);
+// phi_1(Y) v takes thin Horner steps on Y v, Y^2 v, Y^3 v, and each squaring
+// phase applies (E_k + I)/2 to the thin block. The result leaves as G' in
+// device order (FP32 and a BF16 hi + lo pair), as the core product writes it.
+
+// Horner step J of both chains: E <- Y4 E + B_J (full tiles) and
+// W <- Y4 W + B_J v (thin tiles, B_J v from v, Y v, Y^2 v, Y^3 v).
+template <int m, int KB, bool ALL, int J, class BAR>
+__device__ __forceinline__ void apply_horner(const TaylorWs& w, double* const (&E)[2], const double* V,
+                                             const double* U1, const double* U2, const double* U3,
+                                             double* const (&W)[2], int worker, int nw, double* lds, BAR& bar) {
+  constexpr int nb = m / 32, nt = nb * nb, TW = kThinWidth;
+  constexpr int src = (J + 1) & 1, dst = J & 1;
+  for (int tile = worker; tile < nt + nb; tile += nw) {
+    if (tile < nt)
+      gemm_tiles<m, KB, ALL, 1, kShareA, 3>(
+          tile / nb, tile % nb, w.Y4, E[src], w.Y4, E[src], 1.0, 0.0, lds,
+          [&](int i, int j, double v, double, const Side<3>& sd) {
+            const double id = i == j ? 1.0 : 0.0;
+            E[dst][(size_t)i * m + j] = v + coef_block<J, 1>(id, sd.v[0] * w.sc1, sd.v[1], sd.v[2]);
+          },
+          w.X0, w.Y2, w.Y3);
+    else
+      gemm_tiles<m, KB, ALL, 1, kShareA, 4, TW, TW>(
+          tile - nt, 0, w.Y4, W[src], w.Y4, W[src], 1.0, 0.0, lds,
+          [&](int i, int j, double v, double, const Side<4>& sd) {
+            W[dst][(size_t)i * TW + j] = v + coef_block<J, 0>(sd.v[0], sd.v[1], sd.v[2], sd.v[3]);
+          },
+          V, U1, U2, U3);
+  }
+  bar.sync();
+}
+
+template <int m, int KB, bool ALL, class BAR>
+__device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& ap, int worker, int nw, double* lds,
+                                           BAR& bar) {
+  constexpr int nb = m / 32, nt = nb * nb, TW = kThinWidth;
+  const size_t mm = (size_t)m * m, mt = (size_t)m * TW;
+  double* X0 = a.ws;
+  double* Y2 = X0 + mm;
+  double* Y3 = Y2 + mm;
+  double* Y4 = Y3 + mm;
+  double* E0 = Y4 + mm;  // exp chain, two buffers
+  double* E1 = E0 + mm;
+  double* colsum = a.ws + 8 * mm;
+  double* V = colsum + m;  // thin blocks, m x TW each
+  double* U1 = V + mt;
+  double* U2 = U1 + mt;
+  double* U3 = U2 + mt;
+  double* W0 = U3 + mt;
+  double* W1 = W0 + mt;
+  const int t = threadIdx.x, f = m / 2, d = ap.d;
+
+  // ---- P0: X0 = lambda M, column sums of |X0|, and v = diag(c) H0 (canonical, zero past d)
+  for (size_t e = (size_t)worker * 256 + t; e < mm; e += (size_t)nw * 256) {
+    const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
+    X0[e] = a.lambda * a.cvec[i] * a.Mraw[e] * a.cvec[j] * a.svec[j];
+  }
+  for (size_t e = (size_t)worker * 256 + t; e < mt; e += (size_t)nw * 256) {
+    const int i = (int)(e / TW), c = (int)(e - (size_t)i * TW);
+    const int di = i < f ? 2 * i : 2 * (i - f) + 1;
+    V[e] = c < d ? a.cvec[i] * ap.H0[(size_t)di * d + c] : 0.0;
+  }
+  for (int j = worker; j < m; j += nw) {
+    __syncthreads();
+    lds[t] = t < m ? a.cvec[t] * fabs(a.Mraw[(size_t)j * m + t]) : 0.0;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+      if (t < o) lds[t] = lds[t] + lds[t + o];
+      __syncthreads();
+    }
+    if (t == 0) colsum[j] = fabs(a.lambda) * a.cvec[j] * lds[0];
+  }
+  bar.sync();
+  double nrm = 0.0;
+  for (int j = 0; j < m; ++j) nrm = fmax(nrm, colsum[j]);
+  int s = 0;
+  if (!(nrm <= 1e300)) s = 0;
+  else if (nrm > kTheta23) s = (int)ceil(log2(nrm / kTheta23));
+  if (s > 1000) s = 1000;
+  if (worker == 0 && t == 0) *a.sdev = s;
+  const double sc1 = ldexp(1.0, -s), sc2 = ldexp(1.0, -2 * s);
+
+  // ---- P1: Y2 = X0 X0 / 4^s; U1 = Y v
+  for (int tile = worker; tile < nt + nb; tile += nw) {
+    if (tile < nt)
+      gemm_tiles<m, KB, ALL, 1, kShareA>(tile / nb, tile % nb, X0, X0, X0, X0, sc2, 0.0, lds,
+                                         [&](int i, int j, double v, double, const Side<0>&) {
+                                           Y2[(size_t)i * m + j] = v;
+                                         });
+    else
+      gemm_tiles<m, KB, ALL, 1, kShareA, 0, TW, TW>(tile - nt, 0, X0, V, X0, V, sc1, 0.0, lds,
+                                                    [&](int i, int j, double v, double, const Side<0>&) {
+                                                      U1[(size_t)i * TW + j] = v;
+                                                    });
+  }
+  bar.sync();
+  // ---- P2: Y3 = Y2 Y, Y4 = Y2 Y2 (with B_5 of the exp chain); U2 = Y2 v, U3 = Y2 U1 (with B_5 v)
+  for (int tile = worker; tile < nt + nb; tile += nw) {
+    if (tile < nt)
+      gemm_tiles<m, KB, ALL, 2, kShareA, 2>(
+          tile / nb, tile % nb, Y2, X0, Y2, Y2, sc1, 1.0, lds,
+          [&](int i, int j, double y3, double y4, const Side<2>& sd) {
+            const size_t e = (size_t)i * m + j;
+            const double id = i == j ? 1.0 : 0.0;
+            Y3[e] = y3;
+            Y4[e] = y4;
+            E1[e] = coef_block<5, 1>(id, sd.v[0] * sc1, sd.v[1], y3);
+          },
+          X0, Y2);
+    else
+      gemm_tiles<m, KB, ALL, 2, kShareA, 2, TW, TW>(
+          tile - nt, 0, Y2, V, Y2, U1, 1.0, 1.0, lds,
+          [&](int i, int j, double u2, double u3, const Side<2>& sd) {
+            const size_t e = (size_t)i * TW + j;
+            U2[e] = u2;
+            U3[e] = u3;
+            W1[e] = coef_block<5, 0>(sd.v[0], sd.v[1], u2, u3);
+          },
+          V, U1);
+  }
+  bar.sync();
+  // ---- Horner steps J = 4 ... 0 (results in E0 and W0)
+  const TaylorWs w{X0, Y2, Y3, Y4, {{nullptr, nullptr}, {nullptr, nullptr}}, sc1};
+  double* const E[2] = {E0, E1};
+  double* const W[2] = {W0, W1};
+  apply_horner<m, KB, ALL, 4>(w, E, V, U1, U2, U3, W, worker, nw, lds, bar);
+  apply_horner<m, KB, ALL, 3>(w, E, V, U1, U2, U3, W, worker, nw, lds, bar);
+  apply_horner<m, KB, ALL, 2>(w, E, V, U1, U2, U3, W, worker, nw, lds, bar);
+  apply_horner<m, KB, ALL, 1>(w, E, V, U1, U2, U3, W, worker, nw, lds, bar);
+  apply_horner<m, KB, ALL, 0>(w, E, V, U1, U2, U3, W, worker, nw, lds, bar);
+  // ---- squaring: W <- (E W + W) / 2, E <- E E (the last E is not needed)
+  double* Ec = E0;
+  double* En = E1;
+  double* Wc = W0;
+  double* Wn = W1;
+  for (int it = 0; it < s; ++it) {
+    for (int tile = worker; tile < nt + nb; tile += nw) {
+      if (tile < nt) {
+        if (it + 1 < s)
+          gemm_tiles<m, KB, ALL, 1, kShareA>(tile / nb, tile % nb, Ec, Ec, Ec, Ec, 1.0, 0.0, lds,
+                                             [&](int i, int j, double v, double, const Side<0>&) {
+                                               En[(size_t)i * m + j] = v;
+                                             });
+      } else {
+        gemm_tiles<m, KB, ALL, 1, kShareA, 1, TW, TW>(
+            tile - nt, 0, Ec, Wc, Ec, Wc, 0.5, 0.0, lds,
+            [&](int i, int j, double v, double, const Side<1>& sd) { Wn[(size_t)i * TW + j] = v + 0.5 * sd.v[0]; },
+            Wc);
+      }
+    }
+    bar.sync();
+    double* x = Ec; Ec = En; En = x;
+    x = Wc; Wc = Wn; Wn = x;
+  }
+  // ---- G' = diag(c s) lambda w in device order, as FP32 and a BF16 hi + lo pair
+  for (size_t e = (size_t)worker * 256 + t; e < (size_t)m * d; e += (size_t)nw * 256) {
+    const int i = (int)(e / d), c = (int)(e - (size_t)i * d);
+    const double sv = a.lambda * Wc[(size_t)i * TW + c];
+    if (!isfinite(sv)) __hip_atomic_fetch_or(a.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int di = i < f ? 2 * i : 2 * (i - f) + 1;
+    const float g = (float)(a.cvec[i] * a.svec[i] * sv);
+    const __bf16 hi = (__bf16)g;
+    ap.G32[(size_t)di * d + c] = g;
+    ap.Gt16[(size_t)c * m + di] = hi;
+    ap.Gt16[(size_t)kMaxDBlocks * kDBlock * m + (size_t)c * m + di] = (__bf16)(g - (float)hi);
+  }
+}
+
 // K blocks: the one-workgroup-per-cloud kernel keeps LDS small (three
 // workgroups per CU) and pipelines 32-wide blocks; the cooperative kernel
 // (one workgroup per CU) issues all of a tile's loads at once and stages
@@ -410,6 +597,13 @@ __global__ __launch_bounds__(256) void k_phi1_grid(Phi1Args a) {
   phi1_body<M, (M < kGridKB ? M : kGridKB), true>(a, (int)blockIdx.x, (int)gridDim.x, lds, bar);
 }
 
+template <int M>
+__global__ __launch_bounds__(256) void k_phi1_apply_grid(Phi1Args a, ApplyArgs ap) {
+  extern __shared__ double lds[];
+  GridBarrier bar{a.barrier, gridDim.x, 0u, a.flag};
+  apply_body<M, (M < kGridKB ? M : kGridKB), true>(a, ap, (int)blockIdx.x, (int)gridDim.x, lds, bar);
+}
+
 __global__ void k_zero_u32(unsigned* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -418,7 +612,7 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 // LDS bytes of the phi_1 kernels for padded size m.
 static size_t phi1_lds_bytes(int KB, bool all) { return (size_t)gemm_lds_doubles(KB, all) * sizeof(double); }
 
-size_t phi1_ws_doubles(int m) { return 8 * (size_t)m * m + m; }
+size_t phi1_ws_doubles(int m) { return 8 * (size_t)m * m + m + 6 * (size_t)m * kThinWidth; }
 
 static void fill_args(rfd_plan_s* p, Phi1Args& a) {
   a.m = p->dev_m;
@@ -465,6 +659,37 @@ hipError_t launch_phi1(rfd_plan_s* p, hipStream_t st) {
     default: return hipErrorInvalidValue;
   }
 }
+
+template <int M>
+static hipError_t launch_apply_m(Phi1Args& a, ApplyArgs& ap, hipStream_t st) {
+  const size_t lds = phi1_lds_bytes(M < kGridKB ? M : kGridKB, true);
+  hipError_t e =
+      hipFuncSetAttribute((const void*)k_phi1_apply_grid<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  constexpr int nb = M / 32;
+  const int nw = nb * nb + nb;  // full tiles plus thin row tiles
+  hipLaunchKernelGGL(k_zero_u32, dim3((kBarWords + 255) / 256), dim3(256), 0, st, a.barrier, kBarWords);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  void* kargs[] = {&a, &ap};
+  ProfileScope prof(kKPhi1Apply, st);
+  return hipLaunchCooperativeKernel((const void*)k_phi1_apply_grid<M>, dim3(nw), dim3(256), kargs, (unsigned)lds, st);
+}
+
+hipError_t launch_phi1_apply(rfd_plan_s* p, int d, hipStream_t st) {
+  if (d < 1 || d > kThinWidth) return hipErrorInvalidValue;
+  Phi1Args a;
+  fill_args(p, a);
+  ApplyArgs ap{p->dev.H0, d, 0, p->dev.G32, p->dev.Gt16};
+  switch (a.m) {
+    case 64: return launch_apply_m<64>(a, ap, st);
+    case 128: return launch_apply_m<128>(a, ap, st);
+    case 256: return launch_apply_m<256>(a, ap, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int phi1_apply_max_width() { return kThinWidth; }
 
 void phi1_fill_args(rfd_plan_s* p, void* args_out) { fill_args(p, *(Phi1Args*)args_out); }
 

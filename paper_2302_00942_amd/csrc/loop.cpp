@@ -82,6 +82,16 @@ rfd_status rfd_loop_create(const rfd_plan_t* plans, const float* const* scales, 
   L->iters = iterations;
   for (int i = 0; i < nplans; ++i) {
     rfd_plan_s* p = plans[i];
+    // S and T must exist before any launch is recorded; this call has no
+    // stream, so the device is idle around the phi_1 launch
+    if (!p->core_ready) {
+      rfd_status cs = hipDeviceSynchronize() == hipSuccess ? rfd::ensure_core(p, nullptr) : RFD_ERR_DEVICE;
+      if (cs == RFD_OK && hipDeviceSynchronize() != hipSuccess) cs = RFD_ERR_DEVICE;
+      if (cs != RFD_OK) {
+        free_loop(L);
+        return cs;
+      }
+    }
     // size the partial buffer for the widest channel slice now, so that no
     // launch of the loop allocates
     const int W = rfd::slice_width(p->dev_m, false);

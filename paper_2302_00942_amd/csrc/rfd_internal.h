@@ -89,6 +89,7 @@ struct rfd_plan_s {
   double wsum_abs = 0;        // sum |w_k|
   bool any_growth = false;    // lambda * w_k > 0 for some k
   int64_t N = -1;             // cloud size after rfd_features (-1: none)
+  bool core_ready = false;    // S and T hold phi_1 of the current cloud's core
   int dev_m = 0;              // padded feature count used on the device: 64, 128 or 256
   int device = 0;
   rfd::PlanDev dev;
@@ -99,7 +100,7 @@ namespace rfd {
 // Kernel ids of the optional per-launch timing (profile.cpp).
 enum KernelId {
   kKGram = 0, kKBta, kKReduce, kKPhi1, kKGcore, kKExpand, kKCopy, kKPhi1Batch, kKBtaBatch, kKExpandBatch,
-  kNumKernelIds
+  kKPhi1Apply, kNumKernelIds
 };
 
 // Brackets one launch with hipEvents on its stream while profiling is on.
@@ -124,6 +125,12 @@ hipError_t launch_bta(rfd_plan_s* p, const float* X, int64_t N, const float* F, 
 hipError_t launch_reduce(rfd_plan_s* p, int64_t N, int d, bool gram, hipStream_t st);
 hipError_t launch_phi1(rfd_plan_s* p, hipStream_t st);
 hipError_t launch_phi1_batch(rfd_plan_s** plans, int n, void* dev_args, hipStream_t st);
+// G' of one block of d <= phi1_apply_max_width() channels straight from H0,
+// without forming S (the plan's S and T are then stale: see ensure_core).
+hipError_t launch_phi1_apply(rfd_plan_s* p, int d, hipStream_t st);
+int phi1_apply_max_width();
+// Forms S and T (phi_1 kernel) if the last core computation used the action form.
+rfd_status ensure_core(rfd_plan_s* p, hipStream_t st);
 size_t phi1_args_bytes();
 size_t phi1_ws_doubles(int m);
 hipError_t launch_gcore(rfd_plan_s* p, int d, hipStream_t st);

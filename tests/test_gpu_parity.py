@@ -292,3 +292,32 @@ def test_autotune_never_changes_results(torch_cuda):
     with pytest.raises(rfd.RfdError):
         plan.autotune(Fd, Fd)  # out aliasing F is refused
     rfd.tune_reset()
+
+
+@pytest.mark.parametrize("m", [64, 128, 256])
+def test_action_form_matches_full_core(torch_cuda, m):
+    """A one-shot call on a field of <= 32 channels takes phi_1 in action form
+    (G straight from B^T F, no S); a 33-channel call on the same cloud forms S
+    first. Their first channels agree to FP32 rounding, both meet the oracle
+    bar, and a resident integrate after the action-form call (which forms S on
+    demand) equals features + integrate on a fresh plan bitwise."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    n = 9001
+    X = wl.torus(n, 31, jitter=0.005)
+    F = wl.field(n, 33, 32)
+    eps, lam, seed = 0.05, -0.6, 77
+    for prec in ("fp32", "bf16"):
+        a, pa, st = run_oneshot(torch, X, F[:, :16], eps, lam, m, seed, prec)  # action form
+        b, _, _ = run_oneshot(torch, X, F, eps, lam, m, seed, prec)            # full core
+        e = o.relf(a, b[:, :16])
+        print(f"m={m} {prec}: action vs full relF={e:.3e}")
+        assert st == rfd.OK and e <= TOL[prec] / 10
+        ref = o.rfd_integrate(X, F[:, :16], eps, lam, m, seed)
+        compare(a, ref, F[:, :16].astype(np.float64), prec, f"action m={m}")
+        F2 = torch.from_numpy(wl.field(n, 5, 33)).cuda()
+        r1 = pa.integrate(F2).cpu().numpy()  # forms S on demand
+        fresh = rfd.Plan(m, eps, lam, seed, precision=prec)
+        fresh.features(torch.from_numpy(X).cuda())
+        r2 = fresh.integrate(F2).cpu().numpy()
+        assert np.array_equal(r1, r2)
