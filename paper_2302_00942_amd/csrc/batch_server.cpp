@@ -15,6 +15,13 @@ struct rfd_batch_s {
   std::vector<int64_t> Ns;
   int exp_cap = 0;  // capacity of dwork_exp in items
   int max_parts = 0;  // largest split-N partition of the batch
+  // phi_1 per cloud as the one-shot entry point takes it: in action form for
+  // fields of at most phi1_apply_max_width() channels (no S), else S and G = S H
+  int n_apply = 0, n_full = 0, dmax_full = 0;
+  void* dargs_apply = nullptr;   // Phi1Args of the action-form clouds
+  void* daargs = nullptr;        // their apply records
+  rfd::CloudDesc* dcl_full = nullptr;  // descriptors of the other clouds (for G = S H)
+  std::vector<bool> applied;     // per plan
   int64_t nmax_copy = 0;
   std::vector<rfd_plan_s*> plans;
   rfd::CloudDesc* dcl = nullptr;
@@ -49,7 +56,7 @@ std::vector<int2> expand_work(const std::vector<int64_t>& Ns, int tpi) {
 void free_batch(rfd_batch_s* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  void* ptrs[] = {b->dcl, b->dcp, b->dwork_bta, b->dwork_exp, b->dargs};
+  void* ptrs[] = {b->dcl, b->dcp, b->dwork_bta, b->dwork_exp, b->dargs, b->dargs_apply, b->daargs, b->dcl_full};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete b;
@@ -59,8 +66,11 @@ rfd_status enqueue(rfd_batch_s* b, hipStream_t st) {
   HIPCK(rfd::launch_copy_points_batch(b->dcp, b->n, b->nmax_copy, st));
   HIPCK(rfd::launch_bta_batch(b->M, b->prec, b->DB, b->dcl, b->dwork_bta, b->nwork_bta, st));
   HIPCK(rfd::launch_reduce_batch(b->M, b->DB, b->dcl, b->n, b->max_parts, st));
-  HIPCK(rfd::launch_phi1_batch_dev(b->M, b->n, b->dargs, st));
-  HIPCK(rfd::launch_gcore_batch(b->M, b->dmax, b->dcl, b->n, st));
+  if (b->n_apply > 0) HIPCK(rfd::launch_phi1_apply_batch_dev(b->M, b->n_apply, b->dargs_apply, b->daargs, st));
+  if (b->n_full > 0) {
+    HIPCK(rfd::launch_phi1_batch_dev(b->M, b->n_full, b->dargs, st));
+    HIPCK(rfd::launch_gcore_batch(b->M, b->dmax_full, b->dcl_full, b->n_full, st));
+  }
   if (b->nwork_exp > 0)
     HIPCK(rfd::launch_expand_batch(b->M, b->prec, b->DB, b->dcl, b->dwork_exp, b->nwork_exp, b->tpi, st));
   return RFD_OK;
@@ -118,7 +128,9 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
   std::vector<rfd::CloudDesc> cl(n);
   std::vector<rfd::CopyDesc> cp(n);
   std::vector<int2> wb;
-  std::vector<unsigned char> args(rfd::phi1_args_bytes() * n);
+  std::vector<unsigned char> args, args_apply, aargs;
+  std::vector<rfd::CloudDesc> cl_full;
+  const size_t PA = rfd::phi1_args_bytes(), AA = rfd::phi1_apply_args_bytes();
   for (int i = 0; i < n; ++i) {
     rfd_plan_s* p = plans[i];
     const int64_t N = Ns[i];
@@ -152,7 +164,21 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
     cp[i] = rfd::CopyDesc{Xs[i], p->dev.X, 3 * N};
     b->nmax_copy = std::max<int64_t>(b->nmax_copy, 3 * N);
     for (int q = 0; q < np; ++q) wb.push_back(make_int2(i, q));
-    rfd::phi1_fill_args(p, args.data() + rfd::phi1_args_bytes() * i);
+    const bool ap = ds[i] <= rfd::phi1_apply_max_width();
+    b->applied.push_back(ap);
+    if (ap) {
+      args_apply.resize(args_apply.size() + PA);
+      aargs.resize(aargs.size() + AA);
+      rfd::phi1_fill_args(p, args_apply.data() + args_apply.size() - PA);
+      rfd::phi1_fill_apply_args(p, ds[i], aargs.data() + aargs.size() - AA);
+      ++b->n_apply;
+    } else {
+      args.resize(args.size() + PA);
+      rfd::phi1_fill_args(p, args.data() + args.size() - PA);
+      cl_full.push_back(c);
+      b->dmax_full = std::max(b->dmax_full, (int)ds[i]);
+      ++b->n_full;
+    }
   }
   for (int i = 0; i < n; ++i) {
     b->bound.push_back(plans[i]->dev.X);
@@ -164,7 +190,9 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
   b->exp_cap = b->nwork_exp;
   bool ok = upload(&b->dcl, cl) == hipSuccess && upload(&b->dcp, cp) == hipSuccess &&
             upload(&b->dwork_bta, wb) == hipSuccess && upload(&b->dwork_exp, we) == hipSuccess &&
-            upload((unsigned char**)&b->dargs, args) == hipSuccess;
+            upload((unsigned char**)&b->dargs, args) == hipSuccess &&
+            upload((unsigned char**)&b->dargs_apply, args_apply) == hipSuccess &&
+            upload((unsigned char**)&b->daargs, aargs) == hipSuccess && upload(&b->dcl_full, cl_full) == hipSuccess;
   if (!ok) {
     free_batch(b);
     return RFD_ERR_DEVICE;
@@ -181,7 +209,7 @@ rfd_status rfd_batch_launch(rfd_batch_t b, rfd_stream_t stream) {
     if (b->plans[i]->dev.X != b->bound[2 * i] || b->plans[i]->dev.partials != b->bound[2 * i + 1])
       return RFD_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
-  for (rfd_plan_s* p : b->plans) p->core_ready = true;  // the batch forms every plan's S and T
+  for (int i = 0; i < b->n; ++i) b->plans[i]->core_ready = !b->applied[i];  // S and T unless in action form
   // first launch eager (sets kernel attributes); the second records a graph
   // on a non-default stream; later launches replay it
   if (b->exec) {
@@ -218,7 +246,7 @@ rfd_status rfd_batch_tune(rfd_batch_t b, int32_t reps, rfd_stream_t stream) {
   // one full eager pass leaves every cloud's G in place; the expansion is
   // then re-run with each candidate geometry (it rewrites the same outputs)
   rfd_status s = enqueue(b, st);
-  for (rfd_plan_s* p : b->plans) p->core_ready = true;
+  for (int i = 0; i < b->n; ++i) b->plans[i]->core_ready = !b->applied[i];
   if (s != RFD_OK || b->nwork_exp == 0) return s;
   static const int cands[] = {8, 16, 32, 64, 128, 256};
   const std::vector<int2> most = expand_work(b->Ns, cands[0]);
@@ -289,7 +317,7 @@ rfd_status rfd_integrate_batch(const rfd_plan_t* plans, const float* const* Xs, 
   if (s != RFD_OK) return s;
   b->launches = 1;  // no graph for a single use
   s = enqueue(b, (hipStream_t)stream);
-  for (rfd_plan_s* p : b->plans) p->core_ready = true;
+  for (int i = 0; i < b->n; ++i) b->plans[i]->core_ready = !b->applied[i];
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && s == RFD_OK) s = RFD_ERR_DEVICE;
   free_batch(b);
   return s;

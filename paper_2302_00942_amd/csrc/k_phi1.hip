@@ -604,6 +604,16 @@ __global__ __launch_bounds__(256) void k_phi1_apply_grid(Phi1Args a, ApplyArgs a
   apply_body<M, (M < kGridKB ? M : kGridKB), true>(a, ap, (int)blockIdx.x, (int)gridDim.x, lds, bar);
 }
 
+template <int M>
+__global__ __launch_bounds__(256) void k_phi1_apply_wg(const Phi1Args* __restrict__ args,
+                                                      const ApplyArgs* __restrict__ aargs) {
+  extern __shared__ double lds[];
+  const Phi1Args a = args[blockIdx.x];
+  const ApplyArgs ap = aargs[blockIdx.x];
+  WgBarrier bar;
+  apply_body<M, kWgKB, false>(a, ap, 0, 1, lds, bar);
+}
+
 __global__ void k_zero_u32(unsigned* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -690,6 +700,34 @@ hipError_t launch_phi1_apply(rfd_plan_s* p, int d, hipStream_t st) {
 }
 
 int phi1_apply_max_width() { return kThinWidth; }
+
+void phi1_fill_apply_args(rfd_plan_s* p, int d, void* out) {
+  *(ApplyArgs*)out = ApplyArgs{p->dev.H0, d, 0, p->dev.G32, p->dev.Gt16};
+}
+
+size_t phi1_apply_args_bytes() { return sizeof(ApplyArgs); }
+
+template <int M>
+static hipError_t launch_apply_batch_m(int n, const void* dev_args, const void* dev_aargs, hipStream_t st) {
+  const size_t lds = phi1_lds_bytes(kWgKB, false);
+  hipError_t e =
+      hipFuncSetAttribute((const void*)k_phi1_apply_wg<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  ProfileScope prof(kKPhi1Batch, st);
+  hipLaunchKernelGGL(k_phi1_apply_wg<M>, dim3(n), dim3(256), lds, st, (const Phi1Args*)dev_args,
+                     (const ApplyArgs*)dev_aargs);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi1_apply_batch_dev(int M, int n, const void* dev_args, const void* dev_aargs, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  switch (M) {
+    case 64: return launch_apply_batch_m<64>(n, dev_args, dev_aargs, st);
+    case 128: return launch_apply_batch_m<128>(n, dev_args, dev_aargs, st);
+    case 256: return launch_apply_batch_m<256>(n, dev_args, dev_aargs, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 void phi1_fill_args(rfd_plan_s* p, void* args_out) { fill_args(p, *(Phi1Args*)args_out); }
 

@@ -129,6 +129,10 @@ hipError_t launch_phi1_batch(rfd_plan_s** plans, int n, void* dev_args, hipStrea
 // without forming S (the plan's S and T are then stale: see ensure_core).
 hipError_t launch_phi1_apply(rfd_plan_s* p, int d, hipStream_t st);
 int phi1_apply_max_width();
+// Batched action form: one workgroup per cloud over Phi1Args / apply records.
+hipError_t launch_phi1_apply_batch_dev(int M, int n, const void* dev_args, const void* dev_aargs, hipStream_t st);
+void phi1_fill_apply_args(rfd_plan_s* p, int d, void* out);  // writes one apply record
+size_t phi1_apply_args_bytes();
 // Forms S and T (phi_1 kernel) if the last core computation used the action form.
 rfd_status ensure_core(rfd_plan_s* p, hipStream_t st);
 size_t phi1_args_bytes();

@@ -172,3 +172,29 @@ def test_batch_tune_keeps_results(torch_cuda):
         assert all(np.array_equal(r, o_.cpu().numpy()) for r, o_ in zip(ref, outs))
     b.close()
     rfd.tune_reset()
+
+
+def test_batch_mixed_widths_bitwise_equal_alone(torch_cuda):
+    """A batch whose fields straddle the action-form width (<= 32 channels:
+    phi_1 applied to the field block; wider: S and G = S H) takes, cloud by
+    cloud, the same path as the one-shot entry point: bitwise equal alone."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    clouds = _clouds(5, 3, 128, 21)
+    widths = [3, 40, 32, 33, 1]
+    Fs_np = [wl.field(c.n, dd, 200 + i) for i, (c, dd) in enumerate(zip(clouds, widths))]
+    for prec in ("fp32", "bf16"):
+        plans = [rfd.Plan(c.m, c.eps, c.lam, c.seed, precision=prec) for c in clouds]
+        Xs = [torch.from_numpy(c.X).cuda() for c in clouds]
+        Fs = [torch.from_numpy(F).cuda() for F in Fs_np]
+        outs = [torch.empty_like(F) for F in Fs]
+        rfd.Batch(plans, Xs, Fs, outs).launch()
+        torch.cuda.synchronize()
+        for c, X, F, out in zip(clouds, Xs, Fs, outs):
+            alone = rfd.Plan(c.m, c.eps, c.lam, c.seed, precision=prec).oneshot(X, F)
+            assert np.array_equal(alone.cpu().numpy(), out.cpu().numpy()), (prec, F.shape[1])
+        # resident use after the batch forms S where the batch did not
+        F2 = torch.from_numpy(wl.field(clouds[0].n, 4, 9)).cuda()
+        fresh = rfd.Plan(clouds[0].m, clouds[0].eps, clouds[0].lam, clouds[0].seed, precision=prec)
+        fresh.features(Xs[0])
+        assert np.array_equal(plans[0].integrate(F2).cpu().numpy(), fresh.integrate(F2).cpu().numpy())
