@@ -22,10 +22,8 @@ struct rfd_batch_s {
   void* daargs = nullptr;        // their apply records
   rfd::CloudDesc* dcl_full = nullptr;  // descriptors of the other clouds (for G = S H)
   std::vector<bool> applied;     // per plan
-  int64_t nmax_copy = 0;
   std::vector<rfd_plan_s*> plans;
   rfd::CloudDesc* dcl = nullptr;
-  rfd::CopyDesc* dcp = nullptr;
   int2* dwork_bta = nullptr;
   int2* dwork_exp = nullptr;
   int nwork_bta = 0, nwork_exp = 0;
@@ -56,14 +54,13 @@ std::vector<int2> expand_work(const std::vector<int64_t>& Ns, int tpi) {
 void free_batch(rfd_batch_s* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  void* ptrs[] = {b->dcl, b->dcp, b->dwork_bta, b->dwork_exp, b->dargs, b->dargs_apply, b->daargs, b->dcl_full};
+  void* ptrs[] = {b->dcl, b->dwork_bta, b->dwork_exp, b->dargs, b->dargs_apply, b->daargs, b->dcl_full};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete b;
 }
 
 rfd_status enqueue(rfd_batch_s* b, hipStream_t st) {
-  HIPCK(rfd::launch_copy_points_batch(b->dcp, b->n, b->nmax_copy, st));
   HIPCK(rfd::launch_bta_batch(b->M, b->prec, b->DB, b->dcl, b->dwork_bta, b->nwork_bta, st));
   HIPCK(rfd::launch_reduce_batch(b->M, b->DB, b->dcl, b->n, b->max_parts, st));
   if (b->n_apply > 0) HIPCK(rfd::launch_phi1_apply_batch_dev(b->M, b->n_apply, b->dargs_apply, b->daargs, st));
@@ -126,7 +123,6 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
   b->tpi = rfd::tuned(rfd::kTuneBatchExpandTilesPerItem, M, prec, b->DB, b->total_n,
                       rfd::default_batch_tiles_per_item());
   std::vector<rfd::CloudDesc> cl(n);
-  std::vector<rfd::CopyDesc> cp(n);
   std::vector<int2> wb;
   std::vector<unsigned char> args, args_apply, aargs;
   std::vector<rfd::CloudDesc> cl_full;
@@ -144,7 +140,8 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
     }
     p->N = N;
     rfd::CloudDesc& c = cl[i];
-    c.X = Xs[i];  // the kernels read the caller's points; the plan keeps a copy for later calls
+    c.X = Xs[i];  // the kernels read the caller's points; the split-N pass copies them into the plan
+    c.Xcopy = p->dev.X;
     c.N = N;
     c.om = p->dev.om;
     c.F = Fs[i];
@@ -161,8 +158,6 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
     c.flag = p->dev.flag;
     c.d = ds[i];
     c.nparts = np;
-    cp[i] = rfd::CopyDesc{Xs[i], p->dev.X, 3 * N};
-    b->nmax_copy = std::max<int64_t>(b->nmax_copy, 3 * N);
     for (int q = 0; q < np; ++q) wb.push_back(make_int2(i, q));
     const bool ap = ds[i] <= rfd::phi1_apply_max_width();
     b->applied.push_back(ap);
@@ -188,7 +183,7 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
   b->nwork_bta = (int)wb.size();
   b->nwork_exp = (int)we.size();
   b->exp_cap = b->nwork_exp;
-  bool ok = upload(&b->dcl, cl) == hipSuccess && upload(&b->dcp, cp) == hipSuccess &&
+  bool ok = upload(&b->dcl, cl) == hipSuccess &&
             upload(&b->dwork_bta, wb) == hipSuccess && upload(&b->dwork_exp, we) == hipSuccess &&
             upload((unsigned char**)&b->dargs, args) == hipSuccess &&
             upload((unsigned char**)&b->dargs_apply, args_apply) == hipSuccess &&

@@ -281,10 +281,9 @@ rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_
   if (N == 0) return RFD_OK;
   rfd_status s = ensure_x(p, N, st);
   if (s != RFD_OK) return s;
-  HIPCK(hipMemcpyAsync(p->dev.X, X, (size_t)N * 3 * sizeof(float), hipMemcpyDeviceToDevice, st));
   s = ensure_partials(p, partial_floats_needed(p, N, 0, true), st);
   if (s != RFD_OK) return s;
-  HIPCK(launch_bta(p, p->dev.X, N, nullptr, 0, 0, true, st));
+  HIPCK(launch_bta(p, X, N, nullptr, 0, 0, true, st, p->dev.X));  // also copies X into the plan
   HIPCK(launch_reduce(p, N, 0, true, st));
   return enqueue_phi1(p, st, lane);
 }
@@ -316,12 +315,11 @@ rfd_status oneshot_enqueue(rfd_plan_s* p, const float* X, int64_t N, const float
   p->N = N;
   s = ensure_x(p, N, st);
   if (s != RFD_OK) return s;
-  HIPCK(hipMemcpyAsync(p->dev.X, X, (size_t)N * 3 * sizeof(float), hipMemcpyDeviceToDevice, st));
   const int dc = std::min(slice_width(p->dev_m, true), d);
   s = ensure_partials(p, partial_floats_needed(p, N, dc, true), st);
   if (s != RFD_OK) return s;
   // pass 1 carries the Gram and the first channel slice of B^T F
-  HIPCK(launch_bta(p, p->dev.X, N, F, ldF, dc, true, st));
+  HIPCK(launch_bta(p, X, N, F, ldF, dc, true, st, p->dev.X));  // also copies X into the plan
   HIPCK(launch_reduce(p, N, dc, true, st));
   if (!lane && dc == d && d <= phi1_apply_max_width()) {
     // the whole field in one block: phi_1 in action form gives G directly

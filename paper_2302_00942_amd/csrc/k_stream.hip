@@ -279,9 +279,11 @@ __device__ __forceinline__ void bta_store(float* __restrict__ part, f32x16 (&acc
 
 // One workgroup of a split-N pass: part b of nparts handles chunks
 // [b*nchunks/nparts, (b+1)*nchunks/nparts) of its cloud and writes its
-// partial at `part`.
+// partial at `part`. With Xcopy, the points it reads are also written there
+// (the plan's resident copy of the cloud), so no separate copy pass is needed.
 template <int M, int PREC, bool GRAM, int DB>
-__device__ __forceinline__ void bta_body(const float* __restrict__ X, int64_t N, const float4* __restrict__ om,
+__device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __restrict__ Xcopy, int64_t N,
+                                         const float4* __restrict__ om,
                                          const float* __restrict__ F, int64_t ldF, int d, int b, int nparts,
                                          float* __restrict__ part) {
   using S = BtaShape<M, PREC>;
@@ -326,10 +328,20 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, int64_t N,
     if (base + kChunk <= N) {
       xa = X[pa * 3]; ya = X[pa * 3 + 1]; za = X[pa * 3 + 2];
       xb = X[pb * 3]; yb = X[pb * 3 + 1]; zb = X[pb * 3 + 2];
+      if (Xcopy && kq == 0) {
+        Xcopy[pa * 3] = xa; Xcopy[pa * 3 + 1] = ya; Xcopy[pa * 3 + 2] = za;
+        Xcopy[pb * 3] = xb; Xcopy[pb * 3 + 1] = yb; Xcopy[pb * 3 + 2] = zb;
+      }
     } else {
       xa = ya = za = xb = yb = zb = 0.f;
-      if (pa < N) { xa = X[pa * 3]; ya = X[pa * 3 + 1]; za = X[pa * 3 + 2]; }
-      if (pb < N) { xb = X[pb * 3]; yb = X[pb * 3 + 1]; zb = X[pb * 3 + 2]; }
+      if (pa < N) {
+        xa = X[pa * 3]; ya = X[pa * 3 + 1]; za = X[pa * 3 + 2];
+        if (Xcopy && kq == 0) { Xcopy[pa * 3] = xa; Xcopy[pa * 3 + 1] = ya; Xcopy[pa * 3 + 2] = za; }
+      }
+      if (pb < N) {
+        xb = X[pb * 3]; yb = X[pb * 3 + 1]; zb = X[pb * 3 + 2];
+        if (Xcopy && kq == 0) { Xcopy[pb * 3] = xb; Xcopy[pb * 3 + 1] = yb; Xcopy[pb * 3 + 2] = zb; }
+      }
     }
 #pragma unroll
     for (int q = 0; q < FPT; ++q) {
@@ -395,10 +407,10 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, int64_t N,
 
 // grid: nparts workgroups of 256 threads, one per partial.
 template <int M, int PREC, bool GRAM, int DB>
-__global__ __launch_bounds__(256) void k_bta(const float* __restrict__ X, int64_t N,
+__global__ __launch_bounds__(256) void k_bta(const float* __restrict__ X, float* __restrict__ Xcopy, int64_t N,
                                              const float4* __restrict__ om, const float* __restrict__ F,
                                              int64_t ldF, int d, float* __restrict__ partials, size_t part_stride) {
-  bta_body<M, PREC, GRAM, DB>(X, N, om, F, ldF, d, (int)blockIdx.x, (int)gridDim.x,
+  bta_body<M, PREC, GRAM, DB>(X, Xcopy, N, om, F, ldF, d, (int)blockIdx.x, (int)gridDim.x,
                               partials + (size_t)blockIdx.x * part_stride);
 }
 
@@ -408,7 +420,7 @@ __global__ __launch_bounds__(256) void k_bta_batch(const CloudDesc* __restrict__
                                                    size_t part_stride) {
   const int2 wi = work[blockIdx.x];
   const CloudDesc& c = cl[wi.x];
-  bta_body<M, PREC, GRAM, DB>(c.X, c.N, c.om, c.F, c.ldF, c.d, wi.y, c.nparts,
+  bta_body<M, PREC, GRAM, DB>(c.X, c.Xcopy, c.N, c.om, c.F, c.ldF, c.d, wi.y, c.nparts,
                               c.partials + (size_t)wi.y * part_stride);
 }
 
@@ -751,34 +763,20 @@ __global__ __launch_bounds__(256) void k_expand_batch(const CloudDesc* __restric
   expand_body<M, PREC, DB>(c.X, c.N, c.om, c.G32, c.Gt16, c.d, c.F, c.ldF, c.out, c.ldO, nullptr, wi.y, t_end, 4);
 }
 
-// Batched copy of the clouds' points into their plans (blockIdx.y = cloud).
-__global__ __launch_bounds__(256) void k_copy_points_batch(const CopyDesc* __restrict__ cp) {
-  const CopyDesc c = cp[blockIdx.y];
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < c.n; i += (int64_t)gridDim.x * 256) c.dst[i] = c.src[i];
-}
-
-__global__ void k_copy_rows(const float* __restrict__ src, int64_t lds, float* __restrict__ dst, int64_t ldd,
-                            int64_t rows, int cols) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= rows * cols) return;
-  const int64_t r = i / cols, c = i - r * cols;
-  dst[r * ldd + c] = src[r * lds + c];
-}
-
 // ------------------------------------------------------------------ launchers
 template <int M, int PREC, bool GRAM>
-static hipError_t bta_dispatch_db(int DB, dim3 grid, const float* X, int64_t N, const float4* om, const float* F,
-                                  int64_t ldF, int d, float* parts, size_t stride, hipStream_t st) {
+static hipError_t bta_dispatch_db(int DB, dim3 grid, const float* X, float* Xcopy, int64_t N, const float4* om,
+                                  const float* F, int64_t ldF, int d, float* parts, size_t stride, hipStream_t st) {
   switch (DB) {
     case 1:
-      hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 1>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, parts, stride);
+      hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 1>), grid, dim3(256), 0, st, X, Xcopy, N, om, F, ldF, d, parts, stride);
       return hipGetLastError();
     case 2:
-      hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 2>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, parts, stride);
+      hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 2>), grid, dim3(256), 0, st, X, Xcopy, N, om, F, ldF, d, parts, stride);
       return hipGetLastError();
     case 4:
       if constexpr (!(GRAM && M == 256)) {
-        hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 4>), grid, dim3(256), 0, st, X, N, om, F, ldF, d, parts, stride);
+        hipLaunchKernelGGL((k_bta<M, PREC, GRAM, 4>), grid, dim3(256), 0, st, X, Xcopy, N, om, F, ldF, d, parts, stride);
         return hipGetLastError();
       }
       return hipErrorInvalidValue;
@@ -788,7 +786,7 @@ static hipError_t bta_dispatch_db(int DB, dim3 grid, const float* X, int64_t N, 
 }
 
 hipError_t launch_bta(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF, int d, bool gram,
-                      hipStream_t st) {
+                      hipStream_t st, float* xcopy) {
   const int M = p->dev_m, prec = p->params.precision;
   const int DB = dblocks(d);
   const int nparts = bta_partials(N, M, d, gram, prec);
@@ -799,8 +797,8 @@ hipError_t launch_bta(rfd_plan_s* p, const float* X, int64_t N, const float* F, 
   ProfileScope prof(gram ? kKGram : kKBta, st);
 #define RFD_BTA(MM, PP)                                                                                     \
   if (M == MM && prec == PP) {                                                                              \
-    return gram ? bta_dispatch_db<MM, PP, true>(DB, grid, X, N, om, F, ldF, d, parts, stride, st)           \
-                : bta_dispatch_db<MM, PP, false>(DB, grid, X, N, om, F, ldF, d, parts, stride, st);         \
+    return gram ? bta_dispatch_db<MM, PP, true>(DB, grid, X, xcopy, N, om, F, ldF, d, parts, stride, st)    \
+                : bta_dispatch_db<MM, PP, false>(DB, grid, X, xcopy, N, om, F, ldF, d, parts, stride, st);  \
   }
   RFD_BTA(64, 0)
   RFD_BTA(64, 1)
@@ -888,25 +886,7 @@ hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_copy_rows(const float* src, int64_t ld_src, float* dst, int64_t ld_dst, int64_t rows, int cols,
-                            hipStream_t st) {
-  const int64_t n = rows * cols;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, ld_src, dst, ld_dst, rows,
-                     cols);
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------------------ batched launchers
-hipError_t launch_copy_points_batch(const CopyDesc* dcp, int ncl, int64_t nmax, hipStream_t st) {
-  int64_t blocks = (nmax + 255) / 256;
-  if (blocks > 256) blocks = 256;
-  if (blocks < 1) blocks = 1;
-  ProfileScope prof(kKCopy, st);
-  hipLaunchKernelGGL(k_copy_points_batch, dim3((unsigned)blocks, (unsigned)ncl), dim3(256), 0, st, dcp);
-  return hipGetLastError();
-}
-
 template <int M, int PREC>
 static hipError_t bta_batch_db(int DB, int nwork, const CloudDesc* dcl, const int2* dwork, size_t stride,
                                hipStream_t st) {

@@ -65,7 +65,7 @@ ProfileScope::~ProfileScope() {
 
 const char* kernel_name(int id) {
   static const char* names[kNumKernelIds] = {"k_bta_gram", "k_bta", "k_reduce", "k_phi1", "k_gcore", "k_expand",
-                                             "k_copy_rows", "k_phi1_batch", "k_bta_batch", "k_expand_batch",
+                                             "k_phi1_batch", "k_bta_batch", "k_expand_batch",
                                              "k_phi1_apply"};
   return (id >= 0 && id < kNumKernelIds) ? names[id] : "?";
 }

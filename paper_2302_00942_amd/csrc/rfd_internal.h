@@ -31,7 +31,8 @@ __host__ __device__ inline int dev_to_canon(int j, int f) { return (j & 1) ? f +
 
 // One cloud of a batched launch (device-side descriptor).
 struct CloudDesc {
-  const float* X;     // points (the plan's copy)
+  const float* X;     // points (the caller's)
+  float* Xcopy;       // the plan's resident copy, written by the split-N pass
   int64_t N;
   const float4* om;   // frequencies
   const float* F;
@@ -48,12 +49,6 @@ struct CloudDesc {
   int* flag;
   int d;
   int nparts;
-};
-
-struct CopyDesc {
-  const float* src;
-  float* dst;
-  int64_t n;  // floats
 };
 
 // Scratch and resident buffers of one plan.
@@ -99,7 +94,7 @@ namespace rfd {
 
 // Kernel ids of the optional per-launch timing (profile.cpp).
 enum KernelId {
-  kKGram = 0, kKBta, kKReduce, kKPhi1, kKGcore, kKExpand, kKCopy, kKPhi1Batch, kKBtaBatch, kKExpandBatch,
+  kKGram = 0, kKBta, kKReduce, kKPhi1, kKGcore, kKExpand, kKPhi1Batch, kKBtaBatch, kKExpandBatch,
   kKPhi1Apply, kNumKernelIds
 };
 
@@ -120,8 +115,9 @@ class ProfileScope {
 const char* kernel_name(int id);
 
 // Kernels and launchers (k_stream.hip, k_phi1.hip).
+// xcopy (may be null): where the pass also writes the points it reads.
 hipError_t launch_bta(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF,
-                      int d, bool gram, hipStream_t st);
+                      int d, bool gram, hipStream_t st, float* xcopy = nullptr);
 hipError_t launch_reduce(rfd_plan_s* p, int64_t N, int d, bool gram, hipStream_t st);
 hipError_t launch_phi1(rfd_plan_s* p, hipStream_t st);
 hipError_t launch_phi1_batch(rfd_plan_s** plans, int n, void* dev_args, hipStream_t st);
@@ -140,10 +136,7 @@ size_t phi1_ws_doubles(int m);
 hipError_t launch_gcore(rfd_plan_s* p, int d, hipStream_t st);
 hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF,
                          int d, float* out, int64_t ldO, const float* rowscale, hipStream_t st);
-hipError_t launch_copy_rows(const float* src, int64_t ld_src, float* dst, int64_t ld_dst,
-                            int64_t rows, int cols, hipStream_t st);
 // Batched stages over device descriptor arrays.
-hipError_t launch_copy_points_batch(const CopyDesc* dcp, int ncl, int64_t nmax, hipStream_t st);
 hipError_t launch_bta_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, hipStream_t st);
 hipError_t launch_reduce_batch(int M, int DB, const CloudDesc* dcl, int ncl, int max_parts, hipStream_t st);
 hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hipStream_t st);
