@@ -244,6 +244,32 @@ def bench_loop(torch, rfd, wl, reps: int):
             "unit": "points*channels/s", **out}
 
 
+def bench_resident_wide(torch, rfd, wl, reps: int):
+    """The HBM-bound regime: resident integrate of wide fields (m = 64 and 128,
+    d = 64) on the 1M-point torus. Algorithmic bytes per point: X read twice
+    (24 B), F read twice and out written once (12 d B)."""
+    n, d = 1_000_000, 64
+    c = wl.large_torus(n=n)
+    X = torch.from_numpy(c.X).cuda()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    F = torch.randn((n, d), device="cuda", generator=gen)
+    out = torch.empty_like(F)
+    res = {}
+    for m in (64, 128):
+        for prec in ("bf16", "fp32"):
+            p = rfd.Plan(m, c.eps, c.lam, c.seed, precision=prec)
+            p.features(X)
+            p.autotune(F, out, reps=3)
+            ms, _, _ = time_steps(lambda: p.integrate(F, out=out), reps, 3, torch)
+            gbs = (24 + 12 * d) * n / (ms * 1e-3) / 1e9
+            res[f"m{m}_{prec}"] = {"ms": round(ms, 4), "value": round(n * d / (ms * 1e-3), 1),
+                                   "hbm_GBs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / PEAK["hbm_GBs"], 4)}
+            p.close()
+    return {"workload": f"torus N={n}, eps={c.eps}, lambda={c.lam}, d={d}, resident plan (features once), "
+                        "integrate only", "unit": "points*channels/s", **res}
+
+
 def bench_serving(torch, rfd, wl, count: int, warm: int, pool: int = 64):
     """Serving: a pool of clouds (N log-uniform in [2000, 200000], random
     surface, m in {64, 128, 256}); each request integrates a fresh field of a
@@ -455,6 +481,7 @@ def main() -> int:
     if not args.no_extras:
         line["batched"] = bench_batch(torch, rfd, wl, max(5, args.steps))
         line["repeated_application"] = bench_loop(torch, rfd, wl, max(5, args.steps // 2))
+        line["resident_wide_fields"] = bench_resident_wide(torch, rfd, wl, max(5, args.steps))
         line["serving"] = bench_serving(torch, rfd, wl, args.serve_requests, 500)
         line["tuning_table"] = rfd.tune_export().strip().splitlines()
     if not args.no_cpu_baseline:

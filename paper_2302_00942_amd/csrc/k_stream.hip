@@ -323,6 +323,14 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __r
   // values; the next chunk's are loaded while the current one is multiplied
   float xa = 0.f, ya = 0.f, za = 0.f, xb = 0.f, yb = 0.f, zb = 0.f;
   float fv[FPT];
+  // BF16 staging item q of this thread: channel c, point pair pp2. A wave
+  // covers 16 channels x 4 point pairs, so its 32-bit LDS writes at word
+  // c * P/2 + pp2 (P/2 = 36) hit 64 distinct banks.
+  const auto field_pair = [&](int q, int& c, int& pp2) {
+    const int b = (tid >> 6) + 4 * q;  // block: 8 point-pair blocks per 16-channel block
+    c = (b >> 3) * 16 + (tid & 15);
+    pp2 = (b & 7) * 4 + ((tid >> 4) & 3);
+  };
   const auto load_chunk = [&](int64_t base) {
     const int64_t pa = base + 2 * pp, pb = pa + 1;
     if (base + kChunk <= N) {
@@ -343,12 +351,25 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __r
         if (Xcopy && kq == 0) { Xcopy[pb * 3] = xb; Xcopy[pb * 3 + 1] = yb; Xcopy[pb * 3 + 2] = zb; }
       }
     }
+    if constexpr (PREC) {
+      // lane: channel tid % 16 of a 16-channel block, point pair (tid / 16) % 4
+      // of a 4-pair block; the wave and q pick the blocks (see field_pair)
 #pragma unroll
-    for (int q = 0; q < FPT; ++q) {
-      const int idx = tid + 256 * q;
-      const int p = idx / DC, c = idx - p * DC;
-      const int64_t gp = base + p;
-      fv[q] = (gp < N && c < d) ? F[gp * ldF + c] : 0.f;
+      for (int q = 0; q < FPT / 2; ++q) {
+        int c, pp2;
+        field_pair(q, c, pp2);
+        const int64_t g0 = base + 2 * pp2;
+        fv[2 * q] = (g0 < N && c < d) ? F[g0 * ldF + c] : 0.f;
+        fv[2 * q + 1] = (g0 + 1 < N && c < d) ? F[(g0 + 1) * ldF + c] : 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < FPT; ++q) {
+        const int idx = tid + 256 * q;
+        const int p = idx / DC, c = idx - p * DC;
+        const int64_t gp = base + p;
+        fv[q] = (gp < N && c < d) ? F[gp * ldF + c] : 0.f;
+      }
     }
   };
   // features of points pa, pa + 1 into LDS (device order rows); points past
@@ -384,18 +405,24 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __r
       features(pa, true, true, std::false_type{});
     else
       features(pa, pa < N, pa + 1 < N, std::true_type{});
-    // ---- field chunk, transposed to [channel][point]
+    // ---- field chunk, transposed to [channel][point] (BF16: hi and lo parts)
+    if constexpr (PREC) {
 #pragma unroll
-    for (int q = 0; q < FPT; ++q) {
-      const int idx = tid + 256 * q;
-      const int p = idx / DC, c = idx - p * DC;
-      const float v = fv[q];
-      if constexpr (PREC) {
-        const __bf16 hi = (__bf16)v;
-        fs[c * P + p] = hi;
-        fsl[c * P + p] = (__bf16)(v - (float)hi);
-      } else {
-        fs[c * P + p] = v;
+      for (int q = 0; q < FPT / 2; ++q) {
+        int c, pp2;
+        field_pair(q, c, pp2);
+        const float v0 = fv[2 * q], v1 = fv[2 * q + 1];
+        const unsigned hi = pack_bf16x2(v0, v1);
+        const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xffff0000u);
+        *(unsigned*)(fs + c * P + 2 * pp2) = hi;
+        *(unsigned*)(fsl + c * P + 2 * pp2) = pack_bf16x2(v0 - h0, v1 - h1);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < FPT; ++q) {
+        const int idx = tid + 256 * q;
+        const int p = idx / DC, c = idx - p * DC;
+        fs[c * P + p] = fv[q];
       }
     }
     if (ch + 1 < c1) load_chunk(base + kChunk);  // in flight during the products below
