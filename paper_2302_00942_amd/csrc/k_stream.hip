@@ -688,17 +688,25 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
   const int tid = threadIdx.x, lane = tid & 63;
   for (int k = tid; k < FQ; k += 256) oms[k] = om[k];
   if constexpr (PREC) {
-    for (int idx = tid; idx < DB * 16 * M; idx += 256) {
-      const int c = idx / M, j = idx - c * M;
+    // 16-byte pieces of the G'^T rows (hi and lo); rows past d are zero
+    const uint4* gh = (const uint4*)Gt16;
+    const uint4* gl = (const uint4*)(Gt16 + (size_t)kMaxDBlocks * kDBlock * M);
+    for (int idx = tid; idx < DB * 16 * (M / 8); idx += 256) {
+      const int c = idx / (M / 8), j8 = idx - c * (M / 8);
       const bool ok = c < d;
-      gth[c * GP + j] = ok ? Gt16[(size_t)c * M + j] : (__bf16)0.f;
-      gtl[c * GP + j] = ok ? Gt16[(size_t)kMaxDBlocks * kDBlock * M + (size_t)c * M + j] : (__bf16)0.f;
+      const uint4 z = {0u, 0u, 0u, 0u};
+      *(uint4*)(gth + c * GP + 8 * j8) = ok ? gh[(size_t)c * (M / 8) + j8] : z;
+      *(uint4*)(gtl + c * GP + 8 * j8) = ok ? gl[(size_t)c * (M / 8) + j8] : z;
     }
   }
   if constexpr (!PREC) {
-    for (int idx = tid; idx < M * DB * 16; idx += 256) {
-      const int j = idx / (DB * 16), c = idx - j * (DB * 16);
-      gs[idx] = c < d ? G32[(size_t)j * d + c] : 0.f;
+    if (d == DB * 16) {  // G' rows fill the channel blocks: a straight copy
+      for (int idx = tid; idx < M * DB * 4; idx += 256) ((float4*)gs)[idx] = ((const float4*)G32)[idx];
+    } else {
+      for (int idx = tid; idx < M * DB * 16; idx += 256) {
+        const int j = idx / (DB * 16), c = idx - j * (DB * 16);
+        gs[idx] = c < d ? G32[(size_t)j * d + c] : 0.f;
+      }
     }
   }
   __syncthreads();
@@ -706,13 +714,27 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
   const int64_t ntiles = t_end;
   const int64_t wstride = t_step;
 
+  // a wave's next tile (its point and residual F values) is loaded while the
+  // current one is computed
+  float xn = 0.f, yn = 0.f, zn = 0.f;
+  float fn[DB][4];
+  const auto load_tile = [&](int64_t tile) {
+    const int64_t p = tile * 16 + pl;
+    xn = yn = zn = 0.f;
+    if (p < N) { xn = X[p * 3]; yn = X[p * 3 + 1]; zn = X[p * 3 + 2]; }
+    load_residual(F, ldF, d, N, tile, g, pl, fn);
+  };
+  if (t_first + (tid >> 6) < ntiles) load_tile(t_first + (tid >> 6));
+
   if constexpr (PREC) {
     for (int64_t tile = t_first + (tid >> 6); tile < ntiles; tile += wstride) {
-      const int64_t p = tile * 16 + pl;
-      float x = 0.f, y = 0.f, z = 0.f;
-      if (p < N) { x = X[p * 3]; y = X[p * 3 + 1]; z = X[p * 3 + 2]; }
-      float fres[DB][4];  // the residual F values of this lane's outputs, loaded ahead of the products
-      load_residual(F, ldF, d, N, tile, g, pl, fres);
+      const float x = xn, y = yn, z = zn;
+      float fres[DB][4];
+#pragma unroll
+      for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fres[cb][q] = fn[cb][q];
+      if (tile + wstride < ntiles) load_tile(tile + wstride);
       f32x4 acc[DB];
 #pragma unroll
       for (int cb = 0; cb < DB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -739,11 +761,13 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
     }
   } else {
     for (int64_t tile = t_first + (tid >> 6); tile < ntiles; tile += wstride) {
-      const int64_t p = tile * 16 + pl;
-      float x = 0.f, y = 0.f, z = 0.f;
-      if (p < N) { x = X[p * 3]; y = X[p * 3 + 1]; z = X[p * 3 + 2]; }
+      const float x = xn, y = yn, z = zn;
       float fres[DB][4];
-      load_residual(F, ldF, d, N, tile, g, pl, fres);
+#pragma unroll
+      for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fres[cb][q] = fn[cb][q];
+      if (tile + wstride < ntiles) load_tile(tile + wstride);
       f32x4 acc[DB];
 #pragma unroll
       for (int cb = 0; cb < DB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
