@@ -321,3 +321,20 @@ def test_action_form_matches_full_core(torch_cuda, m):
         fresh.features(torch.from_numpy(X).cuda())
         r2 = fresh.integrate(F2).cpu().numpy()
         assert np.array_equal(r1, r2)
+
+
+def test_plain_sphere_dense_ground_truth(torch_cuda):
+    """The 2,000-point sphere with the dense brute force exp(lambda W_eps) F
+    (W_eps the 0.1-ball adjacency with self-loops, the oracle's own Pade
+    expm): the distance of RFD at m = 64 to it is reported, not bounded (it
+    is the estimator's bias, ~0.5 at this m), and the GPU result must sit at
+    the oracle's distance."""
+    c = wl.plain_sphere()
+    dense = o.dense_integrate(c.X, c.F, c.eps, c.lam)
+    ref = o.rfd_integrate(c.X, c.F, c.eps, c.lam, c.m, c.seed)
+    out, _, st = run_oneshot(torch_cuda, c.X, c.F, c.eps, c.lam, c.m, c.seed, "fp32")
+    e_gpu, e_ref = o.relf(out, dense), o.relf(ref, dense)
+    deg = (o.dense_adjacency(c.X, c.eps) > 0).sum(1).mean()
+    print(f"sphere N=2000 m=64: mean eps-degree {deg:.2f}; relF(RFD - dense): GPU {e_gpu:.4f}, oracle {e_ref:.4f}; "
+          f"relF(dense - F) {o.relf(dense, c.F.astype(np.float64)):.3f}")
+    assert st == 0 and abs(e_gpu - e_ref) < 1e-5
