@@ -59,9 +59,14 @@ struct WgBarrier {
 // counter of their group of kBarGroup (128-byte apart lines); the last arrival
 // of a group (seen from the returned count) bumps the top counter, which every
 // workgroup polls. Counters only grow: round r waits for r * groups top
-// arrivals. Arrivals are acquire-release, the poll is relaxed and followed by
-// one acquire fence. The wait is bounded: on timeout the flag gets bit 2 and
-// the workgroup proceeds, so every wave always exits.
+// arrivals. Ordering comes from fences around relaxed counter operations:
+// each arrival is preceded by an agent-scope release fence; the last arrival
+// of a group takes an acquire-release fence before it bumps the top counter
+// (so the group's writes reach every poller through it); the poll is relaxed
+// and followed by one acquire fence. On gfx950 that is one L2 write-back
+// before the arrival and one invalidate after the wait. The wait is bounded:
+// on timeout the flag gets bit 2 and the workgroup proceeds, so every wave
+// always exits.
 constexpr int kBarGroup = 16;
 constexpr int kBarStride = 32;        // unsigned words between counters (128 bytes)
 constexpr int kBarWords = kBarStride * (1 + 256 / kBarGroup);
@@ -79,10 +84,13 @@ struct GridBarrier {
       const unsigned g = blockIdx.x / kBarGroup;
       const unsigned groups = (nblocks + kBarGroup - 1) / kBarGroup;
       const unsigned gsz = (g + 1 < groups) ? kBarGroup : nblocks - g * kBarGroup;
-      __threadfence();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned old =
-          __hip_atomic_fetch_add(ctr + kBarStride * (1 + g), 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (old + 1 == round * gsz) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(ctr + kBarStride * (1 + g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (old + 1 == round * gsz) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       const unsigned target = round * groups;
       unsigned spins = 0;
       while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -92,7 +100,7 @@ struct GridBarrier {
           break;
         }
       }
-      __threadfence();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
   }

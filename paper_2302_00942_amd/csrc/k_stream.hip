@@ -632,44 +632,59 @@ __global__ __launch_bounds__(256) void k_gcore_batch(const CloudDesc* __restrict
 }
 
 // ------------------------------------------------------------------ k_expand
-// The F values a lane adds to its outputs: rows tile*16 + 4g + q, column
-// cb*16 + pl (the MFMA output layout), zero outside the cloud and the field.
+// The products are formed as (Phi G')^T = G'^T Phi^T: with G'^T the MFMA A
+// operand and the features the B operand, lane (g, pl) holds channels
+// cb*16 + 4g + q (q = 0..3) of point tile*16 + pl, four consecutive floats of
+// one output row. The residual F values are loaded, and the outputs stored,
+// as one 16-byte access per lane when rows and bases allow it (VEC), so that
+// every store instruction writes whole rows.
 template <int DB>
 __device__ __forceinline__ void load_residual(const float* F, int64_t ldF, int d, int64_t N, int64_t tile, int g,
-                                              int pl, float (&fres)[DB][4]) {
+                                              int pl, bool vec, float (&fres)[DB][4]) {
+  const int64_t pr = tile * 16 + pl;
 #pragma unroll
   for (int cb = 0; cb < DB; ++cb) {
-    const int c = cb * 16 + pl;
+    const int c = cb * 16 + 4 * g;
+    if (vec) {
+      float4 v = {0.f, 0.f, 0.f, 0.f};
+      if (c < d && pr < N) v = *(const float4*)(F + pr * ldF + c);
+      fres[cb][0] = v.x; fres[cb][1] = v.y; fres[cb][2] = v.z; fres[cb][3] = v.w;
+    } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t pr = tile * 16 + 4 * g + q;
-      fres[cb][q] = (c < d && pr < N) ? F[pr * ldF + c] : 0.f;
+      for (int q = 0; q < 4; ++q) fres[cb][q] = (c + q < d && pr < N) ? F[pr * ldF + c + q] : 0.f;
     }
   }
 }
 
 template <int DB>
 __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* __restrict__ rowscale, int d,
-                                          int64_t N, int64_t tile, int g, int pl, const float (&fres)[DB][4],
-                                          const f32x4 (&acc)[DB]) {
+                                          int64_t N, int64_t tile, int g, int pl, bool vec,
+                                          const float (&fres)[DB][4], const f32x4 (&acc)[DB]) {
+  const int64_t pr = tile * 16 + pl;
+  if (pr >= N) return;
+  const float sc = rowscale ? rowscale[pr] : 1.f;
 #pragma unroll
   for (int cb = 0; cb < DB; ++cb) {
-    const int c = cb * 16 + pl;
-    if (c < d) {
+    const int c = cb * 16 + 4 * g;
+    float v[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t pr = tile * 16 + 4 * g + q;
-        if (pr < N) {
-          const float v = fres[cb][q] + acc[cb][q];
-          out[pr * ldO + c] = rowscale ? rowscale[pr] * v : v;
-        }
-      }
+    for (int q = 0; q < 4; ++q) {
+      v[q] = fres[cb][q] + acc[cb][q];
+      if (rowscale) v[q] = sc * v[q];
+    }
+    if (vec) {
+      if (c < d) *(float4*)(out + pr * ldO + c) = float4{v[0], v[1], v[2], v[3]};
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (c + q < d) out[pr * ldO + c + q] = v[q];
     }
   }
 }
 
 // out = F + Phi G'. Each wave owns tiles of 16 points; lane l handles point
-// l%16 and the feature group g = l/16 of every K step. Point tiles are
+// l%16 and the feature group g = l/16 of every K step, and after the products
+// channels 4g..4g+3 of each channel block of its point. Point tiles are
 // distributed round-robin over the waves of the grid.
 // Point tiles [t_first + wave, t_end) with stride t_step are processed by the
 // four waves of the workgroup.
@@ -711,6 +726,8 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
   }
   __syncthreads();
   const int g = lane >> 4, pl = lane & 15;
+  // 16-byte residual loads and output stores: every row starts 16-byte aligned
+  const bool vec = ((d | ldF | ldO) & 3) == 0 && (((uintptr_t)F | (uintptr_t)out) & 15) == 0;
   const int64_t ntiles = t_end;
   const int64_t wstride = t_step;
 
@@ -722,7 +739,7 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
     const int64_t p = tile * 16 + pl;
     xn = yn = zn = 0.f;
     if (p < N) { xn = X[p * 3]; yn = X[p * 3 + 1]; zn = X[p * 3 + 2]; }
-    load_residual(F, ldF, d, N, tile, g, pl, fn);
+    load_residual(F, ldF, d, N, tile, g, pl, vec, fn);
   };
   if (t_first + (tid >> 6) < ntiles) load_tile(t_first + (tid >> 6));
 
@@ -753,11 +770,11 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
           const int off = (cb * 16 + pl) * GP + s * 32 + 8 * g;
           const bf16x8 bh = *(const bf16x8*)(gth + off);
           const bf16x8 bl = *(const bf16x8*)(gtl + off);
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc[cb], 0, 0, 0);
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, a, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, a, acc[cb], 0, 0, 0);
         }
       }
-      store_out(out, ldO, rowscale, d, N, tile, g, pl, fres, acc);
+      store_out(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc);
     }
   } else {
     for (int64_t tile = t_first + (tid >> 6); tile < ntiles; tile += wstride) {
@@ -781,11 +798,11 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
         for (int cb = 0; cb < DB; ++cb) {
           const float b0 = gs[(2 * k) * (DB * 16) + cb * 16 + pl];
           const float b1 = gs[(2 * k + 1) * (DB * 16) + cb * 16 + pl];
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(cs, b0, acc[cb], 0, 0, 0);
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(sn, b1, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b0, cs, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, sn, acc[cb], 0, 0, 0);
         }
       }
-      store_out(out, ldO, rowscale, d, N, tile, g, pl, fres, acc);
+      store_out(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc);
     }
   }
 }
