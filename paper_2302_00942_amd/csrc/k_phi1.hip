@@ -262,6 +262,42 @@ __device__ __forceinline__ void gemm_tiles(int ti, int tj, const double* __restr
 // ------------------------------------------------------------------ body
 constexpr double kTheta23 = 2.014710780944616;
 
+// Column sums of |lambda diag(c) M diag(c s)| (the matrix whose 1-norm sets
+// the scaling): column j has entries lambda c_i M_ij c_j s_j, so its absolute
+// sum is |lambda| c_j sum_i c_i |M_ij|, read along row j of the symmetric M.
+// One wave per column: lane l adds rows l, l + 64, ... in order, then a fixed
+// butterfly combines the lanes and lane 0 keeps the total.
+template <int m>
+__device__ __forceinline__ void column_abs_sums(const Phi1Args& a, int worker, int nw, double* colsum) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int j = worker * 4 + w; j < m; j += nw * 4) {
+    double v = 0.0;
+    for (int i = l; i < m; i += 64) v += a.cvec[i] * fabs(a.Mraw[(size_t)j * m + i]);
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if (l == 0) colsum[j] = fabs(a.lambda) * a.cvec[j] * v;
+  }
+}
+
+// s = max(0, ceil(log2(||lambda M||_1 / theta_23))) from the column sums: a
+// max over the threads' values, then over the four waves through LDS (a max
+// is exact, so every workgroup gets the same s). Non-finite sums give s = 0;
+// the non-finite input is flagged where M is formed.
+template <int m>
+__device__ __forceinline__ int scaling_power(const double* colsum, double* lds) {
+  const int t = threadIdx.x;
+  double v = t < m ? colsum[t] : 0.0;
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  __syncthreads();  // earlier readers of lds are done
+  if ((t & 63) == 0) lds[t >> 6] = v;
+  __syncthreads();
+  const double nrm = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+  __syncthreads();  // lds is free again
+  int s = 0;
+  if (!(nrm <= 1e300)) s = 0;
+  else if (nrm > kTheta23) s = (int)ceil(log2(nrm / kTheta23));
+  return s > 1000 ? 1000 : s;
+}
+
 // 1/k! as a compile-time constant.
 constexpr double inv_factorial(int k) {
   double f = 1.0;
@@ -328,25 +364,11 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
     const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
     X0[e] = a.lambda * a.cvec[i] * a.Mraw[e] * a.cvec[j] * a.svec[j];
   }
-  for (int j = worker; j < m; j += nw) {
-    __syncthreads();
-    lds[t] = t < m ? a.cvec[t] * fabs(a.Mraw[(size_t)j * m + t]) : 0.0;
-    __syncthreads();
-    for (int o = 128; o >= 1; o >>= 1) {
-      if (t < o) lds[t] = lds[t] + lds[t + o];
-      __syncthreads();
-    }
-    if (t == 0) colsum[j] = fabs(a.lambda) * a.cvec[j] * lds[0];
-  }
+  column_abs_sums<m>(a, worker, nw, colsum);
   bar.sync();
 
-  // ---- s from the 1-norm (every worker, same arithmetic)
-  double nrm = 0.0;
-  for (int j = 0; j < m; ++j) nrm = fmax(nrm, colsum[j]);
-  int s = 0;
-  if (!(nrm <= 1e300)) s = 0;  // non-finite input: flagged by the reduction already
-  else if (nrm > kTheta23) s = (int)ceil(log2(nrm / kTheta23));
-  if (s > 1000) s = 1000;
+  // ---- s from the 1-norm (every worker, same value)
+  const int s = scaling_power<m>(colsum, lds);
   if (worker == 0 && t == 0) *a.sdev = s;
   const double sc1 = ldexp(1.0, -s), sc2 = ldexp(1.0, -2 * s);
 
@@ -478,23 +500,9 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
     const int di = i < f ? 2 * i : 2 * (i - f) + 1;
     V[e] = c < d ? a.cvec[i] * ap.H0[(size_t)di * d + c] : 0.0;
   }
-  for (int j = worker; j < m; j += nw) {
-    __syncthreads();
-    lds[t] = t < m ? a.cvec[t] * fabs(a.Mraw[(size_t)j * m + t]) : 0.0;
-    __syncthreads();
-    for (int o = 128; o >= 1; o >>= 1) {
-      if (t < o) lds[t] = lds[t] + lds[t + o];
-      __syncthreads();
-    }
-    if (t == 0) colsum[j] = fabs(a.lambda) * a.cvec[j] * lds[0];
-  }
+  column_abs_sums<m>(a, worker, nw, colsum);
   bar.sync();
-  double nrm = 0.0;
-  for (int j = 0; j < m; ++j) nrm = fmax(nrm, colsum[j]);
-  int s = 0;
-  if (!(nrm <= 1e300)) s = 0;
-  else if (nrm > kTheta23) s = (int)ceil(log2(nrm / kTheta23));
-  if (s > 1000) s = 1000;
+  const int s = scaling_power<m>(colsum, lds);
   if (worker == 0 && t == 0) *a.sdev = s;
   const double sc1 = ldexp(1.0, -s), sc2 = ldexp(1.0, -2 * s);
 
