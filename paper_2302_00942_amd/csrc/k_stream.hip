@@ -632,26 +632,41 @@ __global__ __launch_bounds__(256) void k_gcore_batch(const CloudDesc* __restrict
 }
 
 // ------------------------------------------------------------------ k_expand
-// The products are formed as (Phi G')^T = G'^T Phi^T: with G'^T the MFMA A
-// operand and the features the B operand, lane (g, pl) holds channels
-// cb*16 + 4g + q (q = 0..3) of point tile*16 + pl, four consecutive floats of
-// one output row. The residual F values are loaded, and the outputs stored,
-// as one 16-byte access per lane when rows and bases allow it (VEC), so that
-// every store instruction writes whole rows.
+// Output layout of the products, chosen by the number of channel blocks.
+// One block (d <= 16): the products are formed as (Phi G')^T = G'^T Phi^T
+// (G'^T the MFMA A operand), so lane (g, pl) holds channels 4g .. 4g+3 of
+// point tile*16 + pl, and the residual loads and output stores are one
+// 16-byte access per lane covering whole 64-byte rows (VEC, when rows and
+// bases allow it). Wider fields: the direct form, lane (g, pl) holding
+// channel cb*16 + pl of points tile*16 + 4g + q (q = 0..3), four rows per
+// access; a 16-byte piece per lane there would spread every access over 16
+// rows 64 * DB bytes apart, which measured slower for DB >= 2.
+template <int DB>
+constexpr bool kRowPieces = DB == 1;
+
 template <int DB>
 __device__ __forceinline__ void load_residual(const float* F, int64_t ldF, int d, int64_t N, int64_t tile, int g,
                                               int pl, bool vec, float (&fres)[DB][4]) {
-  const int64_t pr = tile * 16 + pl;
-#pragma unroll
-  for (int cb = 0; cb < DB; ++cb) {
-    const int c = cb * 16 + 4 * g;
+  if constexpr (kRowPieces<DB>) {
+    const int64_t pr = tile * 16 + pl;
+    const int c = 4 * g;
     if (vec) {
       float4 v = {0.f, 0.f, 0.f, 0.f};
       if (c < d && pr < N) v = *(const float4*)(F + pr * ldF + c);
-      fres[cb][0] = v.x; fres[cb][1] = v.y; fres[cb][2] = v.z; fres[cb][3] = v.w;
+      fres[0][0] = v.x; fres[0][1] = v.y; fres[0][2] = v.z; fres[0][3] = v.w;
     } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) fres[cb][q] = (c + q < d && pr < N) ? F[pr * ldF + c + q] : 0.f;
+      for (int q = 0; q < 4; ++q) fres[0][q] = (c + q < d && pr < N) ? F[pr * ldF + c + q] : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int cb = 0; cb < DB; ++cb) {
+      const int c = cb * 16 + pl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t pr = tile * 16 + 4 * g + q;
+        fres[cb][q] = (c < d && pr < N) ? F[pr * ldF + c] : 0.f;
+      }
     }
   }
 }
@@ -660,16 +675,15 @@ template <int DB>
 __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* __restrict__ rowscale, int d,
                                           int64_t N, int64_t tile, int g, int pl, bool vec,
                                           const float (&fres)[DB][4], const f32x4 (&acc)[DB]) {
-  const int64_t pr = tile * 16 + pl;
-  if (pr >= N) return;
-  const float sc = rowscale ? rowscale[pr] : 1.f;
-#pragma unroll
-  for (int cb = 0; cb < DB; ++cb) {
-    const int c = cb * 16 + 4 * g;
+  if constexpr (kRowPieces<DB>) {
+    const int64_t pr = tile * 16 + pl;
+    if (pr >= N) return;
+    const int c = 4 * g;
+    const float sc = rowscale ? rowscale[pr] : 1.f;
     float v[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      v[q] = fres[cb][q] + acc[cb][q];
+      v[q] = fres[0][q] + acc[0][q];
       if (rowscale) v[q] = sc * v[q];
     }
     if (vec) {
@@ -679,13 +693,28 @@ __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* 
       for (int q = 0; q < 4; ++q)
         if (c + q < d) out[pr * ldO + c + q] = v[q];
     }
+  } else {
+#pragma unroll
+    for (int cb = 0; cb < DB; ++cb) {
+      const int c = cb * 16 + pl;
+      if (c < d) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t pr = tile * 16 + 4 * g + q;
+          if (pr < N) {
+            const float v = fres[cb][q] + acc[cb][q];
+            out[pr * ldO + c] = rowscale ? rowscale[pr] * v : v;
+          }
+        }
+      }
+    }
   }
 }
 
 // out = F + Phi G'. Each wave owns tiles of 16 points; lane l handles point
-// l%16 and the feature group g = l/16 of every K step, and after the products
-// channels 4g..4g+3 of each channel block of its point. Point tiles are
-// distributed round-robin over the waves of the grid.
+// l%16 and the feature group g = l/16 of every K step (the outputs it then
+// holds follow the layout above). Point tiles are distributed round-robin
+// over the waves of the grid.
 // Point tiles [t_first + wave, t_end) with stride t_step are processed by the
 // four waves of the workgroup.
 template <int M, int PREC, int DB>
@@ -726,7 +755,8 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
   }
   __syncthreads();
   const int g = lane >> 4, pl = lane & 15;
-  // 16-byte residual loads and output stores: every row starts 16-byte aligned
+  // 16-byte residual loads and output stores (one-block layout): every row
+  // starts 16-byte aligned
   const bool vec = ((d | ldF | ldO) & 3) == 0 && (((uintptr_t)F | (uintptr_t)out) & 15) == 0;
   const int64_t ntiles = t_end;
   const int64_t wstride = t_step;
@@ -770,8 +800,13 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
           const int off = (cb * 16 + pl) * GP + s * 32 + 8 * g;
           const bf16x8 bh = *(const bf16x8*)(gth + off);
           const bf16x8 bl = *(const bf16x8*)(gtl + off);
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, a, acc[cb], 0, 0, 0);
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, a, acc[cb], 0, 0, 0);
+          if constexpr (kRowPieces<DB>) {
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, a, acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, a, acc[cb], 0, 0, 0);
+          } else {
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[cb], 0, 0, 0);
+          }
         }
       }
       store_out(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc);
@@ -798,8 +833,13 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
         for (int cb = 0; cb < DB; ++cb) {
           const float b0 = gs[(2 * k) * (DB * 16) + cb * 16 + pl];
           const float b1 = gs[(2 * k + 1) * (DB * 16) + cb * 16 + pl];
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b0, cs, acc[cb], 0, 0, 0);
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, sn, acc[cb], 0, 0, 0);
+          if constexpr (kRowPieces<DB>) {
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b0, cs, acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, sn, acc[cb], 0, 0, 0);
+          } else {
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(cs, b0, acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(sn, b1, acc[cb], 0, 0, 0);
+          }
         }
       }
       store_out(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc);
