@@ -469,6 +469,14 @@ __device__ __forceinline__ void reduce1_body(const float* __restrict__ partials,
   const int b1 = (int)(((int64_t)(g + 1) * nparts) / kReduceGroups);
   double s = 0.0;
   int b = b0;
+  // 16 loads in flight per step, added in increasing b
+  for (; b + 16 <= b1; b += 16) {
+    float v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = partials[(size_t)(b + u) * stride + e];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += (double)v[u];
+  }
   for (; b + 4 <= b1; b += 4) {
     const float v0 = partials[(size_t)b * stride + e];
     const float v1 = partials[(size_t)(b + 1) * stride + e];
@@ -541,14 +549,28 @@ __device__ __forceinline__ void reduce_fused_body(const float* __restrict__ part
   if (e >= E) return;
   int I = 0, J = 0;
   if (!reduce_slot(e, ng, NB, slots, I, J)) return;
-  double s = 0.0;
-  for (int g = 0; g < kReduceGroups; ++g) {
-    const int b0 = (int)(((int64_t)g * nparts) / kReduceGroups);
-    const int b1 = (int)(((int64_t)(g + 1) * nparts) / kReduceGroups);
-    double sg = 0.0;
-    for (int b = b0; b < b1; ++b) sg += (double)partials[(size_t)b * stride + e];
-    s += sg;
+  // every partial in flight at once, then the group sums in the order of
+  // reduce1 + reduce2: group g covers [g n / 16, (g + 1) n / 16); an empty
+  // group adds +0.0, which changes no sum here (neither sum is ever -0.0)
+  float v[kFusedReduceMaxParts];
+#pragma unroll
+  for (int b = 0; b < kFusedReduceMaxParts; ++b) v[b] = b < nparts ? partials[(size_t)b * stride + e] : 0.f;
+  double s = 0.0, sg = 0.0;
+  int g = 0;
+  int bend = (int)((int64_t)nparts / kReduceGroups);  // end of group 0
+#pragma unroll
+  for (int b = 0; b < kFusedReduceMaxParts; ++b) {
+    if (b < nparts) {
+      while (b >= bend) {
+        s += sg;
+        sg = 0.0;
+        ++g;
+        bend = (int)(((int64_t)(g + 1) * nparts) / kReduceGroups);
+      }
+      sg += (double)v[b];
+    }
   }
+  s += sg;
   reduce_scatter(s, e, ng, I, J, m, d, DB, Mraw, H0, flag);
 }
 
@@ -599,13 +621,30 @@ __device__ __forceinline__ void gcore_body(const double* __restrict__ T, const d
   __shared__ double ts[16 * (kMaxM + 1)];
   __shared__ double hs[kMaxM * 16];
   const int t = threadIdx.x;
-  for (int e = t; e < 16 * m; e += 256) {
-    const int r = e / m, i = e - r * m;
-    ts[r * (kMaxM + 1) + i] = T[(size_t)(j0 + r) * m + i];
+  // every load of the two operand tiles in flight at once (16 m elements
+  // each, m <= 256: at most 16 per thread), then staged into LDS
+  constexpr int Q = 16 * kMaxM / 256;
+  double tv[Q], hv[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = t + 256 * q;
+    tv[q] = 0.0;
+    hv[q] = 0.0;
+    if (e < 16 * m) {
+      const int r = e / m, i = e - r * m;
+      tv[q] = T[(size_t)(j0 + r) * m + i];
+      const int ih = e >> 4, c = e & 15;
+      if (c0 + c < d) hv[q] = H0[(size_t)ih * d + c0 + c];
+    }
   }
-  for (int e = t; e < m * 16; e += 256) {
-    const int i = e >> 4, c = e & 15;
-    hs[e] = (c0 + c < d) ? H0[(size_t)i * d + c0 + c] : 0.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = t + 256 * q;
+    if (e < 16 * m) {
+      const int r = e / m, i = e - r * m;
+      ts[r * (kMaxM + 1) + i] = tv[q];
+      hs[e] = hv[q];
+    }
   }
   __syncthreads();
   const int r = t >> 4, c = t & 15;
