@@ -549,28 +549,14 @@ __device__ __forceinline__ void reduce_fused_body(const float* __restrict__ part
   if (e >= E) return;
   int I = 0, J = 0;
   if (!reduce_slot(e, ng, NB, slots, I, J)) return;
-  // every partial in flight at once, then the group sums in the order of
-  // reduce1 + reduce2: group g covers [g n / 16, (g + 1) n / 16); an empty
-  // group adds +0.0, which changes no sum here (neither sum is ever -0.0)
-  float v[kFusedReduceMaxParts];
-#pragma unroll
-  for (int b = 0; b < kFusedReduceMaxParts; ++b) v[b] = b < nparts ? partials[(size_t)b * stride + e] : 0.f;
-  double s = 0.0, sg = 0.0;
-  int g = 0;
-  int bend = (int)((int64_t)nparts / kReduceGroups);  // end of group 0
-#pragma unroll
-  for (int b = 0; b < kFusedReduceMaxParts; ++b) {
-    if (b < nparts) {
-      while (b >= bend) {
-        s += sg;
-        sg = 0.0;
-        ++g;
-        bend = (int)(((int64_t)(g + 1) * nparts) / kReduceGroups);
-      }
-      sg += (double)v[b];
-    }
+  double s = 0.0;
+  for (int g = 0; g < kReduceGroups; ++g) {
+    const int b0 = (int)(((int64_t)g * nparts) / kReduceGroups);
+    const int b1 = (int)(((int64_t)(g + 1) * nparts) / kReduceGroups);
+    double sg = 0.0;
+    for (int b = b0; b < b1; ++b) sg += (double)partials[(size_t)b * stride + e];
+    s += sg;
   }
-  s += sg;
   reduce_scatter(s, e, ng, I, J, m, d, DB, Mraw, H0, flag);
 }
 
