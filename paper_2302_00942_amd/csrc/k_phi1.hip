@@ -106,6 +106,21 @@ struct GridBarrier {
   }
 };
 
+// Global-typed accesses. The per-cloud kernels read their pointers from
+// argument records in device memory, which the compiler cannot place in an
+// address space, so plain accesses become flat ones; flat accesses also
+// count against the LDS wait counter, so every LDS wait before a barrier
+// would drain the loads in flight as well. All these buffers are global.
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) f64x2_t gf64x2;
+__device__ __forceinline__ double gld(const double* p) { return *(const gdouble*)p; }
+__device__ __forceinline__ double2 gld2(const double* p) {
+  const f64x2_t v = *(const gf64x2*)p;
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(double* p, double v) { *(gdouble*)p = v; }
+
 // ------------------------------------------------------------------ GEMM tiles
 // One workgroup computes the 32 x 32 tile (ti, tj) of C1 = alpha1 A1 B1 and,
 // with NP = 2, of C2 = alpha2 A2 B2, for row-major m x m operands. The two
@@ -133,8 +148,16 @@ struct Side {
 
 // LDB and LDC are the row pitches of the B operands and of the output/side
 // matrices (m for m x m operands; the width of a thin operand block).
-template <int m, int KB, bool ALL, int NP, int SHARE, int NS = 0, int LDB = m, int LDC = m, class EPI>
-__device__ __forceinline__ void gemm_tiles(int ti, int tj, const double* __restrict__ A1,
+//
+// gemm_range runs the tiles of virtual indices first, first + step, ... <
+// end, map(idx, ti, tj) giving each tile. With ALL and a single K block
+// (KB == m) the tiles are streamed: as soon as one tile's panels sit in LDS,
+// the next tile's panel and side loads are issued, so they arrive while the
+// current tile is multiplied. Every tile's arithmetic is that of a lone tile
+// (the same products, summed in the same order), so results do not depend on
+// how tiles are grouped into runs.
+template <int m, int KB, bool ALL, int NP, int SHARE, int NS = 0, int LDB = m, int LDC = m, class MAP, class EPI>
+__device__ __forceinline__ void gemm_range(int first, int end, int step, MAP map, const double* __restrict__ A1,
                                            const double* __restrict__ B1, const double* __restrict__ A2,
                                            const double* __restrict__ B2, double alpha1, double alpha2,
                                            double* lds, EPI epi, const double* S0 = nullptr,
@@ -152,6 +175,7 @@ __device__ __forceinline__ void gemm_tiles(int ti, int tj, const double* __restr
   const double* Ag[2] = {A1, A2};
   const double* Bg[2] = {B1, B2};
   double2 ra[NR][NA][LQ], rb[NR][NBP][LQ];
+  int ti = 0, tj = 0;  // the tile whose panels are being loaded
   // A panel element e = tid + 256 q: row e / AH, double2 column e % AH;
   // B panel element e: row e / 16, double2 column e % 16
   const auto load = [&](int kb, int slot) {
@@ -160,14 +184,14 @@ __device__ __forceinline__ void gemm_tiles(int ti, int tj, const double* __restr
 #pragma unroll
       for (int q = 0; q < LQ; ++q) {
         const int e = tid + 256 * q, r = e / AH, c2 = e % AH;
-        ra[slot][a][q] = *(const double2*)(Ag[a] + (size_t)(ti * 32 + r) * m + kb * KB + 2 * c2);
+        ra[slot][a][q] = gld2(Ag[a] + (size_t)(ti * 32 + r) * m + kb * KB + 2 * c2);
       }
 #pragma unroll
     for (int b = 0; b < NBP; ++b)
 #pragma unroll
       for (int q = 0; q < LQ; ++q) {
         const int e = tid + 256 * q, r = e >> 4, c2 = e & 15;
-        rb[slot][b][q] = *(const double2*)(Bg[b] + (size_t)(kb * KB + r) * LDB + tj * 32 + 2 * c2);
+        rb[slot][b][q] = gld2(Bg[b] + (size_t)(kb * KB + r) * LDB + tj * 32 + 2 * c2);
       }
   };
   const auto store = [&](int slot, double* buf) {
@@ -189,24 +213,19 @@ __device__ __forceinline__ void gemm_tiles(int ti, int tj, const double* __restr
       }
   };
   const int w = tid >> 6, l = tid & 63, qi = w >> 1, qj = w & 1;
-  // output element r of this lane: row ti*32 + qi*16 + 4r + l/16, column tj*32 + qj*16 + l%16
-  const auto out_index = [&](int r) {
-    return (size_t)(ti * 32 + qi * 16 + 4 * r + (l >> 4)) * LDC + tj * 32 + qj * 16 + (l & 15);
+  // output element r of this lane in tile (i0, j0): row i0*32 + qi*16 + 4r + l/16,
+  // column j0*32 + qj*16 + l%16
+  const auto out_index = [&](int i0, int j0, int r) {
+    return (size_t)(i0 * 32 + qi * 16 + 4 * r + (l >> 4)) * LDC + j0 * 32 + qj * 16 + (l & 15);
   };
-  Side<NS> side[4];
-  const auto load_side = [&]() {
+  const auto load_side = [&](Side<NS> (&side)[4]) {
     const double* sp[4] = {S0, S1, S2, S3};
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int q = 0; q < NS; ++q) side[r].v[q] = sp[q][out_index(r)];
+      for (int q = 0; q < NS; ++q) side[r].v[q] = gld(sp[q] + out_index(ti, tj, r));
   };
-  f64x4 acc[NP][4];
-#pragma unroll
-  for (int p = 0; p < NP; ++p)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[p][c] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const auto multiply = [&](const double* buf) {
+  const auto multiply = [&](const double* buf, f64x4 (&acc)[NP][4]) {
     const int ao = (qi * 16 + (l & 15)) * AP + (l >> 4);
     const int bo = (l >> 4) * 33 + qj * 16 + (l & 15);
 #pragma unroll
@@ -223,41 +242,99 @@ __device__ __forceinline__ void gemm_tiles(int ti, int tj, const double* __restr
       }
     }
   };
-  if constexpr (ALL) {
+  const auto zero = [&](f64x4 (&acc)[NP][4]) {
 #pragma unroll
-    for (int kb = 0; kb < NB_K; ++kb) load(kb, kb);  // every load in flight at once
-    load_side();
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int kb = 0; kb < NB_K; ++kb) {
+      for (int c = 0; c < 4; ++c) acc[p][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+  };
+  // f64 16x16x4 output layout: register r holds row 4 r + l/16, column l%16
+  const auto epilogue = [&](int i0, int j0, const f64x4 (&acc)[NP][4], const Side<NS> (&side)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 * 32 + qi * 16 + 4 * r + (l >> 4);
+      const int j = j0 * 32 + qj * 16 + (l & 15);
+      const double v1 = alpha1 * ((acc[0][0][r] + acc[0][1][r]) + (acc[0][2][r] + acc[0][3][r]));
+      const double v2 =
+          NP == 2 ? alpha2 * ((acc[NP - 1][0][r] + acc[NP - 1][1][r]) + (acc[NP - 1][2][r] + acc[NP - 1][3][r]))
+                  : 0.0;
+      epi(i, j, v1, v2, side[r]);
+    }
+  };
+  if constexpr (ALL && NB_K == 1) {
+    if (first >= end) return;
+    Side<NS> side[4], cur[4];
+    map(first, ti, tj);
+    load(0, 0);
+    load_side(side);
+    for (int idx = first; idx < end; idx += step) {
+      const int ci = ti, cj = tj;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cur[r] = side[r];
       __syncthreads();  // the buffer's previous readers are done
-      store(kb, lds);
+      store(0, lds);
+      if (idx + step < end) {  // the next tile's loads fly during this tile's products
+        map(idx + step, ti, tj);
+        load(0, 0);
+        load_side(side);
+      }
       __syncthreads();
-      multiply(lds);
+      f64x4 acc[NP][4];
+      zero(acc);
+      multiply(lds, acc);
+      epilogue(ci, cj, acc, cur);
     }
   } else {
-    __syncthreads();  // the buffers' previous readers are done
-    load(0, 0);
-    store(0, lds);
-    __syncthreads();
-#pragma unroll 1
-    for (int kb = 0; kb < NB_K; ++kb) {
-      if (kb + 1 < NB_K) load(kb + 1, 0);  // in flight during this block's products
-      multiply(lds + (kb & 1) * 3 * PD);
-      if (kb + 1 < NB_K) store(0, lds + ((kb + 1) & 1) * 3 * PD);
-      __syncthreads();
-    }
-    load_side();  // after the loop: no registers held across it
-  }
-  // f64 16x16x4 output layout: register r holds row 4 r + l/16, column l%16
+    for (int idx = first; idx < end; idx += step) {
+      map(idx, ti, tj);
+      Side<NS> side[4];
+      f64x4 acc[NP][4];
+      zero(acc);
+      if constexpr (ALL) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = ti * 32 + qi * 16 + 4 * r + (l >> 4);
-    const int j = tj * 32 + qj * 16 + (l & 15);
-    const double v1 = alpha1 * ((acc[0][0][r] + acc[0][1][r]) + (acc[0][2][r] + acc[0][3][r]));
-    const double v2 = NP == 2 ? alpha2 * ((acc[NP - 1][0][r] + acc[NP - 1][1][r]) + (acc[NP - 1][2][r] + acc[NP - 1][3][r])) : 0.0;
-    epi(i, j, v1, v2, side[r]);
+        for (int kb = 0; kb < NB_K; ++kb) load(kb, kb);  // every load in flight at once
+        load_side(side);
+#pragma unroll
+        for (int kb = 0; kb < NB_K; ++kb) {
+          __syncthreads();  // the buffer's previous readers are done
+          store(kb, lds);
+          __syncthreads();
+          multiply(lds, acc);
+        }
+      } else {
+        __syncthreads();  // the buffers' previous readers are done
+        load(0, 0);
+        store(0, lds);
+        __syncthreads();
+#pragma unroll 1
+        for (int kb = 0; kb < NB_K; ++kb) {
+          if (kb + 1 < NB_K) load(kb + 1, 0);  // in flight during this block's products
+          multiply(lds + (kb & 1) * 3 * PD, acc);
+          if (kb + 1 < NB_K) store(0, lds + ((kb + 1) & 1) * 3 * PD);
+          __syncthreads();
+        }
+        load_side(side);  // after the loop: no registers held across it
+      }
+      epilogue(ti, tj, acc, side);
+    }
   }
 }
+
+// The tiles of one phase owned by worker `worker` of nw: full tiles t < nt
+// (tile (t / nb, t % nb) of an m x m product) come first, then the thin row
+// blocks t = nt .. nt + nthin - 1 (tile (t - nt, 0)), as in the loop
+// for (t = worker; t < nt + nthin; t += nw).
+struct PhaseTiles {
+  int first_full, end_full, first_thin, end_thin, step, nb, nt;
+  __device__ PhaseTiles(int worker, int nw, int nb_, int nthin) : step(nw), nb(nb_), nt(nb_ * nb_) {
+    first_full = worker;
+    end_full = nt;
+    first_thin = worker >= nt ? worker : worker + ((nt - worker + nw - 1) / nw) * nw;
+    end_thin = nt + nthin;
+  }
+  __device__ void full(int t, int& ti, int& tj) const { ti = t / nb; tj = t - (t / nb) * nb; }
+  __device__ void thin(int t, int& ti, int& tj) const { ti = t - nt; tj = 0; }
+};
 
 // ------------------------------------------------------------------ body
 constexpr double kTheta23 = 2.014710780944616;
@@ -330,16 +407,18 @@ template <int m, int KB, bool ALL, int J, class BAR>
 __device__ __forceinline__ void horner_phase(const TaylorWs& w, int worker, int nw, double* lds, BAR& bar) {
   constexpr int nb = m / 32, nt = nb * nb;
   constexpr int src = (J + 1) & 1, dst = J & 1;
-  for (int tile = worker; tile < nt; tile += nw)
-    gemm_tiles<m, KB, ALL, 2, kShareA, 3>(
-        tile / nb, tile % nb, w.Y4, w.R[0][src], w.Y4, w.R[1][src], 1.0, 1.0, lds,
+  {
+    const PhaseTiles pt(worker, nw, nb, 0);
+    gemm_range<m, KB, ALL, 2, kShareA, 3>(
+        pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, w.Y4, w.R[0][src], w.Y4, w.R[1][src], 1.0, 1.0, lds,
         [&](int i, int j, double v0, double v1, const Side<3>& sd) {
           const size_t e = (size_t)i * m + j;
           const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * w.sc1, y2 = sd.v[1], y3 = sd.v[2];
-          w.R[0][dst][e] = v0 + coef_block<J, 0>(id, y, y2, y3);
-          w.R[1][dst][e] = v1 + coef_block<J, 1>(id, y, y2, y3);
+          gst(w.R[0][dst] + e, v0 + coef_block<J, 0>(id, y, y2, y3));
+          gst(w.R[1][dst] + e, v1 + coef_block<J, 1>(id, y, y2, y3));
         },
         w.X0, w.Y2, w.Y3);
+  }
   bar.sync();
 }
 
@@ -373,25 +452,29 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   const double sc1 = ldexp(1.0, -s), sc2 = ldexp(1.0, -2 * s);
 
   // ---- P1: Y2 = X0 X0 / 4^s
-  for (int tile = worker; tile < nt; tile += nw)
-    gemm_tiles<m, KB, ALL, 1, kShareA>(tile / nb, tile % nb, X0, X0, X0, X0, sc2, 0.0, lds,
+  {
+    const PhaseTiles pt(worker, nw, nb, 0);
+    gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, X0, X0, X0, X0, sc2, 0.0, lds,
                                        [&](int i, int j, double v, double, const Side<0>&) {
-                                         Y2[(size_t)i * m + j] = v;
+                                         gst(Y2 + (size_t)i * m + j, v);
                                        });
+  }
   bar.sync();
   // ---- P2: Y3 = Y2 X0 / 2^s (its epilogue also forms B_5 of both chains) and Y4 = Y2 Y2
-  for (int tile = worker; tile < nt; tile += nw)
-    gemm_tiles<m, KB, ALL, 2, kShareA, 2>(
-        tile / nb, tile % nb, Y2, X0, Y2, Y2, sc1, 1.0, lds,
+  {
+    const PhaseTiles pt(worker, nw, nb, 0);
+    gemm_range<m, KB, ALL, 2, kShareA, 2>(
+        pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, Y2, X0, Y2, Y2, sc1, 1.0, lds,
         [&](int i, int j, double y3, double y4, const Side<2>& sd) {
           const size_t e = (size_t)i * m + j;
           const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * sc1, y2 = sd.v[1];
-          Y3[e] = y3;
-          Y4[e] = y4;
-          R01[e] = coef_block<5, 0>(id, y, y2, y3);
-          R11[e] = coef_block<5, 1>(id, y, y2, y3);
+          gst(Y3 + e, y3);
+          gst(Y4 + e, y4);
+          gst(R01 + e, coef_block<5, 0>(id, y, y2, y3));
+          gst(R11 + e, coef_block<5, 1>(id, y, y2, y3));
         },
         X0, Y2);
+  }
   bar.sync();
   // ---- P3..P7: Horner steps J = 4 ... 0 (J odd reads buffer 0, writes 1 ... ends in buffer 0)
   const TaylorWs w{X0, Y2, Y3, Y4, {{R00, R01}, {R10, R11}}, sc1};
@@ -406,15 +489,17 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   double* Pn = R01;
   double* En = R11;
   for (int it = 0; it < s; ++it) {
-    for (int tile = worker; tile < nt; tile += nw)
-      gemm_tiles<m, KB, ALL, 2, kShareB, 1>(
-          tile / nb, tile % nb, Ec, Ec, Pc, Ec, 1.0, 0.5, lds,
+    {
+      const PhaseTiles pt(worker, nw, nb, 0);
+      gemm_range<m, KB, ALL, 2, kShareB, 1>(
+          pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, Ec, Ec, Pc, Ec, 1.0, 0.5, lds,
           [&](int i, int j, double e2, double pe, const Side<1>& sd) {
             const size_t e = (size_t)i * m + j;
-            En[e] = e2;
-            Pn[e] = pe + 0.5 * sd.v[0];
+            gst(En + e, e2);
+            gst(Pn + e, pe + 0.5 * sd.v[0]);
           },
           Pc);
+    }
     bar.sync();
     double* x = Ec; Ec = En; En = x;
     x = Pc; Pc = Pn; Pn = x;
@@ -450,20 +535,19 @@ __device__ __forceinline__ void apply_horner(const TaylorWs& w, double* const (&
                                              double* const (&W)[2], int worker, int nw, double* lds, BAR& bar) {
   constexpr int nb = m / 32, nt = nb * nb, TW = kThinWidth;
   constexpr int src = (J + 1) & 1, dst = J & 1;
-  for (int tile = worker; tile < nt + nb; tile += nw) {
-    if (tile < nt)
-      gemm_tiles<m, KB, ALL, 1, kShareA, 3>(
-          tile / nb, tile % nb, w.Y4, E[src], w.Y4, E[src], 1.0, 0.0, lds,
+  {
+    const PhaseTiles pt(worker, nw, nb, nb);
+      gemm_range<m, KB, ALL, 1, kShareA, 3>(
+          pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, w.Y4, E[src], w.Y4, E[src], 1.0, 0.0, lds,
           [&](int i, int j, double v, double, const Side<3>& sd) {
             const double id = i == j ? 1.0 : 0.0;
-            E[dst][(size_t)i * m + j] = v + coef_block<J, 1>(id, sd.v[0] * w.sc1, sd.v[1], sd.v[2]);
+            gst(E[dst] + (size_t)i * m + j, v + coef_block<J, 1>(id, sd.v[0] * w.sc1, sd.v[1], sd.v[2]));
           },
           w.X0, w.Y2, w.Y3);
-    else
-      gemm_tiles<m, KB, ALL, 1, kShareA, 4, TW, TW>(
-          tile - nt, 0, w.Y4, W[src], w.Y4, W[src], 1.0, 0.0, lds,
+      gemm_range<m, KB, ALL, 1, kShareA, 4, TW, TW>(
+          pt.first_thin, pt.end_thin, pt.step, [&](int t, int& ti_, int& tj_) { pt.thin(t, ti_, tj_); }, w.Y4, W[src], w.Y4, W[src], 1.0, 0.0, lds,
           [&](int i, int j, double v, double, const Side<4>& sd) {
-            W[dst][(size_t)i * TW + j] = v + coef_block<J, 0>(sd.v[0], sd.v[1], sd.v[2], sd.v[3]);
+            gst(W[dst] + (size_t)i * TW + j, v + coef_block<J, 0>(sd.v[0], sd.v[1], sd.v[2], sd.v[3]));
           },
           V, U1, U2, U3);
   }
@@ -507,40 +591,38 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
   const double sc1 = ldexp(1.0, -s), sc2 = ldexp(1.0, -2 * s);
 
   // ---- P1: Y2 = X0 X0 / 4^s; U1 = Y v
-  for (int tile = worker; tile < nt + nb; tile += nw) {
-    if (tile < nt)
-      gemm_tiles<m, KB, ALL, 1, kShareA>(tile / nb, tile % nb, X0, X0, X0, X0, sc2, 0.0, lds,
+  {
+    const PhaseTiles pt(worker, nw, nb, nb);
+      gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, X0, X0, X0, X0, sc2, 0.0, lds,
                                          [&](int i, int j, double v, double, const Side<0>&) {
-                                           Y2[(size_t)i * m + j] = v;
+                                           gst(Y2 + (size_t)i * m + j, v);
                                          });
-    else
-      gemm_tiles<m, KB, ALL, 1, kShareA, 0, TW, TW>(tile - nt, 0, X0, V, X0, V, sc1, 0.0, lds,
+      gemm_range<m, KB, ALL, 1, kShareA, 0, TW, TW>(pt.first_thin, pt.end_thin, pt.step, [&](int t, int& ti_, int& tj_) { pt.thin(t, ti_, tj_); }, X0, V, X0, V, sc1, 0.0, lds,
                                                     [&](int i, int j, double v, double, const Side<0>&) {
-                                                      U1[(size_t)i * TW + j] = v;
+                                                      gst(U1 + (size_t)i * TW + j, v);
                                                     });
   }
   bar.sync();
   // ---- P2: Y3 = Y2 Y, Y4 = Y2 Y2 (with B_5 of the exp chain); U2 = Y2 v, U3 = Y2 U1 (with B_5 v)
-  for (int tile = worker; tile < nt + nb; tile += nw) {
-    if (tile < nt)
-      gemm_tiles<m, KB, ALL, 2, kShareA, 2>(
-          tile / nb, tile % nb, Y2, X0, Y2, Y2, sc1, 1.0, lds,
+  {
+    const PhaseTiles pt(worker, nw, nb, nb);
+      gemm_range<m, KB, ALL, 2, kShareA, 2>(
+          pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, Y2, X0, Y2, Y2, sc1, 1.0, lds,
           [&](int i, int j, double y3, double y4, const Side<2>& sd) {
             const size_t e = (size_t)i * m + j;
             const double id = i == j ? 1.0 : 0.0;
-            Y3[e] = y3;
-            Y4[e] = y4;
-            E1[e] = coef_block<5, 1>(id, sd.v[0] * sc1, sd.v[1], y3);
+            gst(Y3 + e, y3);
+            gst(Y4 + e, y4);
+            gst(E1 + e, coef_block<5, 1>(id, sd.v[0] * sc1, sd.v[1], y3));
           },
           X0, Y2);
-    else
-      gemm_tiles<m, KB, ALL, 2, kShareA, 2, TW, TW>(
-          tile - nt, 0, Y2, V, Y2, U1, 1.0, 1.0, lds,
+      gemm_range<m, KB, ALL, 2, kShareA, 2, TW, TW>(
+          pt.first_thin, pt.end_thin, pt.step, [&](int t, int& ti_, int& tj_) { pt.thin(t, ti_, tj_); }, Y2, V, Y2, U1, 1.0, 1.0, lds,
           [&](int i, int j, double u2, double u3, const Side<2>& sd) {
             const size_t e = (size_t)i * TW + j;
-            U2[e] = u2;
-            U3[e] = u3;
-            W1[e] = coef_block<5, 0>(sd.v[0], sd.v[1], u2, u3);
+            gst(U2 + e, u2);
+            gst(U3 + e, u3);
+            gst(W1 + e, coef_block<5, 0>(sd.v[0], sd.v[1], u2, u3));
           },
           V, U1);
   }
@@ -560,19 +642,17 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
   double* Wc = W0;
   double* Wn = W1;
   for (int it = 0; it < s; ++it) {
-    for (int tile = worker; tile < nt + nb; tile += nw) {
-      if (tile < nt) {
-        if (it + 1 < s)
-          gemm_tiles<m, KB, ALL, 1, kShareA>(tile / nb, tile % nb, Ec, Ec, Ec, Ec, 1.0, 0.0, lds,
-                                             [&](int i, int j, double v, double, const Side<0>&) {
-                                               En[(size_t)i * m + j] = v;
-                                             });
-      } else {
-        gemm_tiles<m, KB, ALL, 1, kShareA, 1, TW, TW>(
-            tile - nt, 0, Ec, Wc, Ec, Wc, 0.5, 0.0, lds,
-            [&](int i, int j, double v, double, const Side<1>& sd) { Wn[(size_t)i * TW + j] = v + 0.5 * sd.v[0]; },
-            Wc);
-      }
+    {
+      const PhaseTiles pt(worker, nw, nb, nb);
+      if (it + 1 < s)
+        gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, Ec, Ec, Ec, Ec, 1.0, 0.0,
+                                           lds, [&](int i, int j, double v, double, const Side<0>&) {
+                                             gst(En + (size_t)i * m + j, v);
+                                           });
+      gemm_range<m, KB, ALL, 1, kShareA, 1, TW, TW>(
+          pt.first_thin, pt.end_thin, pt.step, [&](int t, int& ti_, int& tj_) { pt.thin(t, ti_, tj_); }, Ec, Wc, Ec, Wc, 0.5, 0.0, lds,
+          [&](int i, int j, double v, double, const Side<1>& sd) { gst(Wn + (size_t)i * TW + j, v + 0.5 * sd.v[0]); },
+          Wc);
     }
     bar.sync();
     double* x = Ec; Ec = En; En = x;
@@ -592,18 +672,24 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
   }
 }
 
-// K blocks: the one-workgroup-per-cloud kernel keeps LDS small (three
-// workgroups per CU) and pipelines 32-wide blocks; the cooperative kernel
-// (one workgroup per CU) issues all of a tile's loads at once and stages
-// 128-wide blocks, one memory round trip per tile.
+// K blocks: the cooperative kernel (one workgroup per CU) issues all of a
+// tile's loads at once and stages 128-wide blocks, one memory round trip per
+// tile. The one-workgroup-per-cloud kernel takes a whole tile as one block
+// when m <= 128 and streams its tiles (the next tile's loads fly during the
+// current tile's products); at m = 256 it pipelines 32-wide blocks, which
+// keeps its LDS small.
 constexpr int kWgKB = 32, kGridKB = 128;
+template <int M>
+constexpr int wg_kb() { return M <= kGridKB ? M : kWgKB; }
+template <int M>
+constexpr bool wg_all() { return M <= kGridKB; }
 
 template <int M>
 __global__ __launch_bounds__(256) void k_phi1_wg(const Phi1Args* __restrict__ args) {
   extern __shared__ double lds[];
   const Phi1Args a = args[blockIdx.x];
   WgBarrier bar;
-  phi1_body<M, kWgKB, false>(a, 0, 1, lds, bar);
+  phi1_body<M, wg_kb<M>(), wg_all<M>()>(a, 0, 1, lds, bar);
 }
 
 template <int M>
@@ -627,7 +713,7 @@ __global__ __launch_bounds__(256) void k_phi1_apply_wg(const Phi1Args* __restric
   const Phi1Args a = args[blockIdx.x];
   const ApplyArgs ap = aargs[blockIdx.x];
   WgBarrier bar;
-  apply_body<M, kWgKB, false>(a, ap, 0, 1, lds, bar);
+  apply_body<M, wg_kb<M>(), wg_all<M>()>(a, ap, 0, 1, lds, bar);
 }
 
 __global__ void k_zero_u32(unsigned* p, int n) {
@@ -725,7 +811,7 @@ size_t phi1_apply_args_bytes() { return sizeof(ApplyArgs); }
 
 template <int M>
 static hipError_t launch_apply_batch_m(int n, const void* dev_args, const void* dev_aargs, hipStream_t st) {
-  const size_t lds = phi1_lds_bytes(kWgKB, false);
+  const size_t lds = phi1_lds_bytes(wg_kb<M>(), wg_all<M>());
   hipError_t e =
       hipFuncSetAttribute((const void*)k_phi1_apply_wg<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -749,7 +835,7 @@ void phi1_fill_args(rfd_plan_s* p, void* args_out) { fill_args(p, *(Phi1Args*)ar
 
 template <int M>
 static hipError_t launch_phi1_batch_m(int n, const void* dev_args, hipStream_t st) {
-  const size_t lds = phi1_lds_bytes(kWgKB, false);
+  const size_t lds = phi1_lds_bytes(wg_kb<M>(), wg_all<M>());
   hipError_t e = hipFuncSetAttribute((const void*)k_phi1_wg<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   ProfileScope prof(kKPhi1Batch, st);
