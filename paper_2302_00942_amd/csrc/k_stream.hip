@@ -39,6 +39,32 @@ __device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
   return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
 }
 
+// Global-typed accesses. The batched kernels read their pointers from cloud
+// records in device memory, which the compiler cannot place in an address
+// space, so plain accesses become flat ones; flat accesses also count
+// against the LDS wait counter, so the LDS wait before every barrier would
+// drain the next chunk's or tile's loads in flight as well. Every buffer
+// these kernels touch is global memory.
+typedef float f32x4v_t __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4v_t __attribute__((ext_vector_type(4)));
+#define RFD_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ float gldf(const float* p) { return *(const RFD_GLOBAL float*)p; }
+__device__ __forceinline__ double gldd(const double* p) { return *(const RFD_GLOBAL double*)p; }
+__device__ __forceinline__ float4 gld4(const float* p) {
+  const f32x4v_t v = *(const RFD_GLOBAL f32x4v_t*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint4 gldu4(const void* p) {
+  const u32x4v_t v = *(const RFD_GLOBAL u32x4v_t*)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstf(float* p, float v) { *(RFD_GLOBAL float*)p = v; }
+__device__ __forceinline__ void gstd(double* p, double v) { *(RFD_GLOBAL double*)p = v; }
+__device__ __forceinline__ void gsth(__bf16* p, __bf16 v) { *(RFD_GLOBAL __bf16*)p = v; }
+__device__ __forceinline__ void gst4(float* p, float4 v) {
+  *(RFD_GLOBAL f32x4v_t*)p = f32x4v_t{v.x, v.y, v.z, v.w};
+}
+
 // Gram tile schedule. The NB x NB grid of 32 x 32 blocks of the symmetric
 // Gram has NB (NB + 1) / 2 distinct tiles: one per vertex (diagonal) and one
 // per edge of the complete graph on the NB feature blocks. Orienting every
@@ -262,7 +288,7 @@ __device__ __forceinline__ void bta_store(float* __restrict__ part, f32x16 (&acc
       if (gram_slot(S::NB, w, sl, K, J)) {
         float* tp = part + (size_t)(w * S::SLOTS + sl) * 1024;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) tp[r * 64 + lane] = acc[sl][r];
+        for (int r = 0; r < 16; ++r) gstf(tp + r * 64 + lane, acc[sl][r]);
       }
     }
   }
@@ -273,7 +299,7 @@ __device__ __forceinline__ void bta_store(float* __restrict__ part, f32x16 (&acc
 #pragma unroll
     for (int cb = 0; cb < DB; ++cb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) hp[((size_t)R * DB + cb) * 256 + q * 64 + lane] = hacc[r][cb][q];
+      for (int q = 0; q < 4; ++q) gstf(hp + ((size_t)R * DB + cb) * 256 + q * 64 + lane, hacc[r][cb][q]);
   }
 }
 
@@ -297,7 +323,7 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __r
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  for (int k = tid; k < FQ; k += 256) oms[k] = om[k];
+  for (int k = tid; k < FQ; k += 256) oms[k] = gld4((const float*)(om + k));
 
   f32x16 acc[S::SLOTS];
   f32x4 hacc[S::RPW][DB];
@@ -334,21 +360,21 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __r
   const auto load_chunk = [&](int64_t base) {
     const int64_t pa = base + 2 * pp, pb = pa + 1;
     if (base + kChunk <= N) {
-      xa = X[pa * 3]; ya = X[pa * 3 + 1]; za = X[pa * 3 + 2];
-      xb = X[pb * 3]; yb = X[pb * 3 + 1]; zb = X[pb * 3 + 2];
+      xa = gldf(X + pa * 3); ya = gldf(X + pa * 3 + 1); za = gldf(X + pa * 3 + 2);
+      xb = gldf(X + pb * 3); yb = gldf(X + pb * 3 + 1); zb = gldf(X + pb * 3 + 2);
       if (Xcopy && kq == 0) {
-        Xcopy[pa * 3] = xa; Xcopy[pa * 3 + 1] = ya; Xcopy[pa * 3 + 2] = za;
-        Xcopy[pb * 3] = xb; Xcopy[pb * 3 + 1] = yb; Xcopy[pb * 3 + 2] = zb;
+        gstf(Xcopy + pa * 3, xa); gstf(Xcopy + pa * 3 + 1, ya); gstf(Xcopy + pa * 3 + 2, za);
+        gstf(Xcopy + pb * 3, xb); gstf(Xcopy + pb * 3 + 1, yb); gstf(Xcopy + pb * 3 + 2, zb);
       }
     } else {
       xa = ya = za = xb = yb = zb = 0.f;
       if (pa < N) {
-        xa = X[pa * 3]; ya = X[pa * 3 + 1]; za = X[pa * 3 + 2];
-        if (Xcopy && kq == 0) { Xcopy[pa * 3] = xa; Xcopy[pa * 3 + 1] = ya; Xcopy[pa * 3 + 2] = za; }
+        xa = gldf(X + pa * 3); ya = gldf(X + pa * 3 + 1); za = gldf(X + pa * 3 + 2);
+        if (Xcopy && kq == 0) { gstf(Xcopy + pa * 3, xa); gstf(Xcopy + pa * 3 + 1, ya); gstf(Xcopy + pa * 3 + 2, za); }
       }
       if (pb < N) {
-        xb = X[pb * 3]; yb = X[pb * 3 + 1]; zb = X[pb * 3 + 2];
-        if (Xcopy && kq == 0) { Xcopy[pb * 3] = xb; Xcopy[pb * 3 + 1] = yb; Xcopy[pb * 3 + 2] = zb; }
+        xb = gldf(X + pb * 3); yb = gldf(X + pb * 3 + 1); zb = gldf(X + pb * 3 + 2);
+        if (Xcopy && kq == 0) { gstf(Xcopy + pb * 3, xb); gstf(Xcopy + pb * 3 + 1, yb); gstf(Xcopy + pb * 3 + 2, zb); }
       }
     }
     if constexpr (PREC) {
@@ -359,8 +385,8 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __r
         int c, pp2;
         field_pair(q, c, pp2);
         const int64_t g0 = base + 2 * pp2;
-        fv[2 * q] = (g0 < N && c < d) ? F[g0 * ldF + c] : 0.f;
-        fv[2 * q + 1] = (g0 + 1 < N && c < d) ? F[(g0 + 1) * ldF + c] : 0.f;
+        fv[2 * q] = (g0 < N && c < d) ? gldf(F + g0 * ldF + c) : 0.f;
+        fv[2 * q + 1] = (g0 + 1 < N && c < d) ? gldf(F + (g0 + 1) * ldF + c) : 0.f;
       }
     } else {
 #pragma unroll
@@ -368,7 +394,7 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __r
         const int idx = tid + 256 * q;
         const int p = idx / DC, c = idx - p * DC;
         const int64_t gp = base + p;
-        fv[q] = (gp < N && c < d) ? F[gp * ldF + c] : 0.f;
+        fv[q] = (gp < N && c < d) ? gldf(F + gp * ldF + c) : 0.f;
       }
     }
   };
@@ -473,22 +499,22 @@ __device__ __forceinline__ void reduce1_body(const float* __restrict__ partials,
   for (; b + 16 <= b1; b += 16) {
     float v[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = partials[(size_t)(b + u) * stride + e];
+    for (int u = 0; u < 16; ++u) v[u] = gldf(partials + (size_t)(b + u) * stride + e);
 #pragma unroll
     for (int u = 0; u < 16; ++u) s += (double)v[u];
   }
   for (; b + 4 <= b1; b += 4) {
-    const float v0 = partials[(size_t)b * stride + e];
-    const float v1 = partials[(size_t)(b + 1) * stride + e];
-    const float v2 = partials[(size_t)(b + 2) * stride + e];
-    const float v3 = partials[(size_t)(b + 3) * stride + e];
+    const float v0 = gldf(partials + (size_t)b * stride + e);
+    const float v1 = gldf(partials + (size_t)(b + 1) * stride + e);
+    const float v2 = gldf(partials + (size_t)(b + 2) * stride + e);
+    const float v3 = gldf(partials + (size_t)(b + 3) * stride + e);
     s += (double)v0;
     s += (double)v1;
     s += (double)v2;
     s += (double)v3;
   }
-  for (; b < b1; ++b) s += (double)partials[(size_t)b * stride + e];
-  lvl[(size_t)g * E + e] = s;
+  for (; b < b1; ++b) s += (double)gldf(partials + (size_t)b * stride + e);
+  gstd(lvl + (size_t)g * E + e, s);
 }
 
 // Gram slot (I, J) of element e of a Gram partial, false for a spare slot.
@@ -510,15 +536,15 @@ __device__ __forceinline__ void reduce_scatter(double s, size_t e, size_t ng, in
     const int row = I * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
     const int col = J * 32 + (l & 31);
     const int ci = dev_to_canon(row, f), cj = dev_to_canon(col, f);
-    Mraw[(size_t)ci * m + cj] = s;
-    Mraw[(size_t)cj * m + ci] = s;
+    gstd(Mraw + (size_t)ci * m + cj, s);
+    gstd(Mraw + (size_t)cj * m + ci, s);
   } else {
     const size_t eh = e - ng;
     const int tile = (int)(eh >> 8), q = (int)((eh >> 6) & 3), l = (int)(eh & 63);
     const int R = tile / DB, cb = tile - R * DB;
     const int row = R * 16 + 4 * (l >> 4) + q;
     const int ch = cb * 16 + (l & 15);
-    if (ch < d) H0[(size_t)row * d + ch] = s;
+    if (ch < d) gstd(H0 + (size_t)row * d + ch, s);
   }
 }
 
@@ -533,7 +559,7 @@ __device__ __forceinline__ void reduce2_body(const double* __restrict__ lvl, siz
   if (!reduce_slot(e, ng, NB, slots, I, J)) return;  // spare slot: never written
   double s = 0.0;
 #pragma unroll
-  for (int g = 0; g < kReduceGroups; ++g) s += lvl[(size_t)g * E + e];
+  for (int g = 0; g < kReduceGroups; ++g) s += gldd(lvl + (size_t)g * E + e);
   reduce_scatter(s, e, ng, I, J, m, d, DB, Mraw, H0, flag);
 }
 
@@ -554,7 +580,7 @@ __device__ __forceinline__ void reduce_fused_body(const float* __restrict__ part
     const int b0 = (int)(((int64_t)g * nparts) / kReduceGroups);
     const int b1 = (int)(((int64_t)(g + 1) * nparts) / kReduceGroups);
     double sg = 0.0;
-    for (int b = b0; b < b1; ++b) sg += (double)partials[(size_t)b * stride + e];
+    for (int b = b0; b < b1; ++b) sg += (double)gldf(partials + (size_t)b * stride + e);
     s += sg;
   }
   reduce_scatter(s, e, ng, I, J, m, d, DB, Mraw, H0, flag);
@@ -618,9 +644,9 @@ __device__ __forceinline__ void gcore_body(const double* __restrict__ T, const d
     hv[q] = 0.0;
     if (e < 16 * m) {
       const int r = e / m, i = e - r * m;
-      tv[q] = T[(size_t)(j0 + r) * m + i];
+      tv[q] = gldd(T + (size_t)(j0 + r) * m + i);
       const int ih = e >> 4, c = e & 15;
-      if (c0 + c < d) hv[q] = H0[(size_t)ih * d + c0 + c];
+      if (c0 + c < d) hv[q] = gldd(H0 + (size_t)ih * d + c0 + c);
     }
   }
 #pragma unroll
@@ -640,9 +666,9 @@ __device__ __forceinline__ void gcore_body(const double* __restrict__ T, const d
   if (ch >= d) return;
   const float g = (float)s;
   const __bf16 hi = (__bf16)g;
-  G32[(size_t)j * d + ch] = g;
-  Gt16[(size_t)ch * m + j] = hi;                                                         // hi part, d x m
-  Gt16[(size_t)kMaxDBlocks * kDBlock * m + (size_t)ch * m + j] = (__bf16)(g - (float)hi);  // lo part
+  gstf(G32 + (size_t)j * d + ch, g);
+  gsth(Gt16 + (size_t)ch * m + j, hi);                                                         // hi part, d x m
+  gsth(Gt16 + (size_t)kMaxDBlocks * kDBlock * m + (size_t)ch * m + j, (__bf16)(g - (float)hi));  // lo part
 }
 
 __global__ __launch_bounds__(256) void k_gcore(const double* __restrict__ T, const double* __restrict__ H0, int m,
@@ -677,11 +703,11 @@ __device__ __forceinline__ void load_residual(const float* F, int64_t ldF, int d
     const int c = 4 * g;
     if (vec) {
       float4 v = {0.f, 0.f, 0.f, 0.f};
-      if (c < d && pr < N) v = *(const float4*)(F + pr * ldF + c);
+      if (c < d && pr < N) v = gld4(F + pr * ldF + c);
       fres[0][0] = v.x; fres[0][1] = v.y; fres[0][2] = v.z; fres[0][3] = v.w;
     } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) fres[0][q] = (c + q < d && pr < N) ? F[pr * ldF + c + q] : 0.f;
+      for (int q = 0; q < 4; ++q) fres[0][q] = (c + q < d && pr < N) ? gldf(F + pr * ldF + c + q) : 0.f;
     }
   } else {
 #pragma unroll
@@ -690,7 +716,7 @@ __device__ __forceinline__ void load_residual(const float* F, int64_t ldF, int d
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t pr = tile * 16 + 4 * g + q;
-        fres[cb][q] = (c < d && pr < N) ? F[pr * ldF + c] : 0.f;
+        fres[cb][q] = (c < d && pr < N) ? gldf(F + pr * ldF + c) : 0.f;
       }
     }
   }
@@ -704,7 +730,7 @@ __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* 
     const int64_t pr = tile * 16 + pl;
     if (pr >= N) return;
     const int c = 4 * g;
-    const float sc = rowscale ? rowscale[pr] : 1.f;
+    const float sc = rowscale ? gldf(rowscale + pr) : 1.f;
     float v[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -712,11 +738,11 @@ __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* 
       if (rowscale) v[q] = sc * v[q];
     }
     if (vec) {
-      if (c < d) *(float4*)(out + pr * ldO + c) = float4{v[0], v[1], v[2], v[3]};
+      if (c < d) gst4(out + pr * ldO + c, float4{v[0], v[1], v[2], v[3]});
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (c + q < d) out[pr * ldO + c + q] = v[q];
+        if (c + q < d) gstf(out + pr * ldO + c + q, v[q]);
     }
   } else {
 #pragma unroll
@@ -728,7 +754,7 @@ __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* 
           const int64_t pr = tile * 16 + 4 * g + q;
           if (pr < N) {
             const float v = fres[cb][q] + acc[cb][q];
-            out[pr * ldO + c] = rowscale ? rowscale[pr] * v : v;
+            gstf(out + pr * ldO + c, rowscale ? gldf(rowscale + pr) * v : v);
           }
         }
       }
@@ -755,7 +781,7 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
   __shared__ __attribute__((aligned(16))) __bf16 gth[PREC ? DB * 16 * GP : 8];
   __shared__ __attribute__((aligned(16))) __bf16 gtl[PREC ? DB * 16 * GP : 8];
   const int tid = threadIdx.x, lane = tid & 63;
-  for (int k = tid; k < FQ; k += 256) oms[k] = om[k];
+  for (int k = tid; k < FQ; k += 256) oms[k] = gld4((const float*)(om + k));
   if constexpr (PREC) {
     // 16-byte pieces of the G'^T rows (hi and lo); rows past d are zero
     const uint4* gh = (const uint4*)Gt16;
@@ -764,17 +790,17 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
       const int c = idx / (M / 8), j8 = idx - c * (M / 8);
       const bool ok = c < d;
       const uint4 z = {0u, 0u, 0u, 0u};
-      *(uint4*)(gth + c * GP + 8 * j8) = ok ? gh[(size_t)c * (M / 8) + j8] : z;
-      *(uint4*)(gtl + c * GP + 8 * j8) = ok ? gl[(size_t)c * (M / 8) + j8] : z;
+      *(uint4*)(gth + c * GP + 8 * j8) = ok ? gldu4(gh + (size_t)c * (M / 8) + j8) : z;
+      *(uint4*)(gtl + c * GP + 8 * j8) = ok ? gldu4(gl + (size_t)c * (M / 8) + j8) : z;
     }
   }
   if constexpr (!PREC) {
     if (d == DB * 16) {  // G' rows fill the channel blocks: a straight copy
-      for (int idx = tid; idx < M * DB * 4; idx += 256) ((float4*)gs)[idx] = ((const float4*)G32)[idx];
+      for (int idx = tid; idx < M * DB * 4; idx += 256) ((float4*)gs)[idx] = gld4(G32 + 4 * (size_t)idx);
     } else {
       for (int idx = tid; idx < M * DB * 16; idx += 256) {
         const int j = idx / (DB * 16), c = idx - j * (DB * 16);
-        gs[idx] = c < d ? G32[(size_t)j * d + c] : 0.f;
+        gs[idx] = c < d ? gldf(G32 + (size_t)j * d + c) : 0.f;
       }
     }
   }
@@ -793,7 +819,7 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
   const auto load_tile = [&](int64_t tile) {
     const int64_t p = tile * 16 + pl;
     xn = yn = zn = 0.f;
-    if (p < N) { xn = X[p * 3]; yn = X[p * 3 + 1]; zn = X[p * 3 + 2]; }
+    if (p < N) { xn = gldf(X + p * 3); yn = gldf(X + p * 3 + 1); zn = gldf(X + p * 3 + 2); }
     load_residual(F, ldF, d, N, tile, g, pl, vec, fn);
   };
   if (t_first + (tid >> 6) < ntiles) load_tile(t_first + (tid >> 6));
