@@ -198,3 +198,33 @@ def test_batch_mixed_widths_bitwise_equal_alone(torch_cuda):
         fresh = rfd.Plan(clouds[0].m, clouds[0].eps, clouds[0].lam, clouds[0].seed, precision=prec)
         fresh.features(Xs[0])
         assert np.array_equal(plans[0].integrate(F2).cpu().numpy(), fresh.integrate(F2).cpu().numpy())
+
+
+@pytest.mark.parametrize("m", [64, 256])
+def test_batch_schedules_bitwise_equal_alone(torch_cuda, m):
+    """The per-cloud phi_1 kernel stages its tiles differently by m (one K
+    block per tile, streamed, for m <= 128; 32-wide pipelined blocks at
+    m = 256) and the single-cloud kernel differently again (128-wide blocks);
+    the products are summed in one fixed order, so every cloud of a batch
+    equals its one-shot result bitwise, in action form (d <= 32) and with
+    the full core (d > 32; a batch at m = 256 takes fields of at most 32
+    channels, the width of its fused first pass)."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    clouds = _clouds(6, 3, m, 41, lo=1500, hi=12000)
+    widths = [3, 40, 16, 33, 1, 64] if m <= 128 else [3, 32, 16, 20, 1, 31]
+    Fs_np = [wl.field(c.n, dd, 300 + i) for i, (c, dd) in enumerate(zip(clouds, widths))]
+    for prec in ("fp32", "bf16"):
+        plans = [rfd.Plan(c.m, c.eps, c.lam, c.seed, precision=prec) for c in clouds]
+        Xs = [torch.from_numpy(c.X).cuda() for c in clouds]
+        Fs = [torch.from_numpy(F).cuda() for F in Fs_np]
+        outs = [torch.empty_like(F) for F in Fs]
+        rfd.Batch(plans, Xs, Fs, outs).launch()
+        torch.cuda.synchronize()
+        assert all(p.check() == rfd.OK for p in plans)
+        for c, X, F, out in zip(clouds, Xs, Fs, outs):
+            alone = rfd.Plan(c.m, c.eps, c.lam, c.seed, precision=prec).oneshot(X, F)
+            assert np.array_equal(alone.cpu().numpy(), out.cpu().numpy()), (m, prec, F.shape[1])
+        c, F = clouds[1], Fs_np[1]
+        e = o.relf(outs[1].cpu().numpy(), o.rfd_integrate(c.X, F, c.eps, c.lam, c.m, c.seed))
+        assert e <= {"fp32": 1e-5, "bf16": 2e-3}[prec], e
