@@ -324,16 +324,30 @@ __device__ __forceinline__ void gemm_range(int first, int end, int step, MAP map
 // (tile (t / nb, t % nb) of an m x m product) come first, then the thin row
 // blocks t = nt .. nt + nthin - 1 (tile (t - nt, 0)), as in the loop
 // for (t = worker; t < nt + nthin; t += nw).
+struct FullTileMap {
+  int nb;
+  __device__ void operator()(int t, int& ti, int& tj) const {
+    ti = t / nb;
+    tj = t - ti * nb;
+  }
+};
+struct ThinTileMap {
+  int nt;
+  __device__ void operator()(int t, int& ti, int& tj) const {
+    ti = t - nt;
+    tj = 0;
+  }
+};
 struct PhaseTiles {
-  int first_full, end_full, first_thin, end_thin, step, nb, nt;
-  __device__ PhaseTiles(int worker, int nw, int nb_, int nthin) : step(nw), nb(nb_), nt(nb_ * nb_) {
-    first_full = worker;
-    end_full = nt;
+  int first_full, end_full, first_thin, end_thin, step;
+  FullTileMap full;
+  ThinTileMap thin;
+  __device__ PhaseTiles(int worker, int nw, int nb, int nthin)
+      : first_full(worker), end_full(nb * nb), step(nw), full{nb}, thin{nb * nb} {
+    const int nt = nb * nb;
     first_thin = worker >= nt ? worker : worker + ((nt - worker + nw - 1) / nw) * nw;
     end_thin = nt + nthin;
   }
-  __device__ void full(int t, int& ti, int& tj) const { ti = t / nb; tj = t - (t / nb) * nb; }
-  __device__ void thin(int t, int& ti, int& tj) const { ti = t - nt; tj = 0; }
 };
 
 // ------------------------------------------------------------------ body
@@ -410,7 +424,7 @@ __device__ __forceinline__ void horner_phase(const TaylorWs& w, int worker, int 
   {
     const PhaseTiles pt(worker, nw, nb, 0);
     gemm_range<m, KB, ALL, 2, kShareA, 3>(
-        pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, w.Y4, w.R[0][src], w.Y4, w.R[1][src], 1.0, 1.0, lds,
+        pt.first_full, pt.end_full, pt.step, pt.full, w.Y4, w.R[0][src], w.Y4, w.R[1][src], 1.0, 1.0, lds,
         [&](int i, int j, double v0, double v1, const Side<3>& sd) {
           const size_t e = (size_t)i * m + j;
           const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * w.sc1, y2 = sd.v[1], y3 = sd.v[2];
@@ -454,7 +468,7 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   // ---- P1: Y2 = X0 X0 / 4^s
   {
     const PhaseTiles pt(worker, nw, nb, 0);
-    gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, X0, X0, X0, X0, sc2, 0.0, lds,
+    gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, pt.full, X0, X0, X0, X0, sc2, 0.0, lds,
                                        [&](int i, int j, double v, double, const Side<0>&) {
                                          gst(Y2 + (size_t)i * m + j, v);
                                        });
@@ -464,7 +478,7 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   {
     const PhaseTiles pt(worker, nw, nb, 0);
     gemm_range<m, KB, ALL, 2, kShareA, 2>(
-        pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, Y2, X0, Y2, Y2, sc1, 1.0, lds,
+        pt.first_full, pt.end_full, pt.step, pt.full, Y2, X0, Y2, Y2, sc1, 1.0, lds,
         [&](int i, int j, double y3, double y4, const Side<2>& sd) {
           const size_t e = (size_t)i * m + j;
           const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * sc1, y2 = sd.v[1];
@@ -492,7 +506,7 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
     {
       const PhaseTiles pt(worker, nw, nb, 0);
       gemm_range<m, KB, ALL, 2, kShareB, 1>(
-          pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, Ec, Ec, Pc, Ec, 1.0, 0.5, lds,
+          pt.first_full, pt.end_full, pt.step, pt.full, Ec, Ec, Pc, Ec, 1.0, 0.5, lds,
           [&](int i, int j, double e2, double pe, const Side<1>& sd) {
             const size_t e = (size_t)i * m + j;
             gst(En + e, e2);
@@ -537,19 +551,19 @@ __device__ __forceinline__ void apply_horner(const TaylorWs& w, double* const (&
   constexpr int src = (J + 1) & 1, dst = J & 1;
   {
     const PhaseTiles pt(worker, nw, nb, nb);
-      gemm_range<m, KB, ALL, 1, kShareA, 3>(
-          pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, w.Y4, E[src], w.Y4, E[src], 1.0, 0.0, lds,
-          [&](int i, int j, double v, double, const Side<3>& sd) {
-            const double id = i == j ? 1.0 : 0.0;
-            gst(E[dst] + (size_t)i * m + j, v + coef_block<J, 1>(id, sd.v[0] * w.sc1, sd.v[1], sd.v[2]));
-          },
-          w.X0, w.Y2, w.Y3);
-      gemm_range<m, KB, ALL, 1, kShareA, 4, TW, TW>(
-          pt.first_thin, pt.end_thin, pt.step, [&](int t, int& ti_, int& tj_) { pt.thin(t, ti_, tj_); }, w.Y4, W[src], w.Y4, W[src], 1.0, 0.0, lds,
-          [&](int i, int j, double v, double, const Side<4>& sd) {
-            gst(W[dst] + (size_t)i * TW + j, v + coef_block<J, 0>(sd.v[0], sd.v[1], sd.v[2], sd.v[3]));
-          },
-          V, U1, U2, U3);
+    gemm_range<m, KB, ALL, 1, kShareA, 3>(
+        pt.first_full, pt.end_full, pt.step, pt.full, w.Y4, E[src], w.Y4, E[src], 1.0, 0.0, lds,
+        [&](int i, int j, double v, double, const Side<3>& sd) {
+          const double id = i == j ? 1.0 : 0.0;
+          gst(E[dst] + (size_t)i * m + j, v + coef_block<J, 1>(id, sd.v[0] * w.sc1, sd.v[1], sd.v[2]));
+        },
+        w.X0, w.Y2, w.Y3);
+    gemm_range<m, KB, ALL, 1, kShareA, 4, TW, TW>(
+        pt.first_thin, pt.end_thin, pt.step, pt.thin, w.Y4, W[src], w.Y4, W[src], 1.0, 0.0, lds,
+        [&](int i, int j, double v, double, const Side<4>& sd) {
+          gst(W[dst] + (size_t)i * TW + j, v + coef_block<J, 0>(sd.v[0], sd.v[1], sd.v[2], sd.v[3]));
+        },
+        V, U1, U2, U3);
   }
   bar.sync();
 }
@@ -593,38 +607,38 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
   // ---- P1: Y2 = X0 X0 / 4^s; U1 = Y v
   {
     const PhaseTiles pt(worker, nw, nb, nb);
-      gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, X0, X0, X0, X0, sc2, 0.0, lds,
-                                         [&](int i, int j, double v, double, const Side<0>&) {
-                                           gst(Y2 + (size_t)i * m + j, v);
-                                         });
-      gemm_range<m, KB, ALL, 1, kShareA, 0, TW, TW>(pt.first_thin, pt.end_thin, pt.step, [&](int t, int& ti_, int& tj_) { pt.thin(t, ti_, tj_); }, X0, V, X0, V, sc1, 0.0, lds,
-                                                    [&](int i, int j, double v, double, const Side<0>&) {
-                                                      gst(U1 + (size_t)i * TW + j, v);
-                                                    });
+    gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, pt.full, X0, X0, X0, X0, sc2, 0.0, lds,
+                                       [&](int i, int j, double v, double, const Side<0>&) {
+                                         gst(Y2 + (size_t)i * m + j, v);
+                                       });
+    gemm_range<m, KB, ALL, 1, kShareA, 0, TW, TW>(pt.first_thin, pt.end_thin, pt.step, pt.thin, X0, V, X0, V, sc1,
+                                                  0.0, lds, [&](int i, int j, double v, double, const Side<0>&) {
+                                                    gst(U1 + (size_t)i * TW + j, v);
+                                                  });
   }
   bar.sync();
   // ---- P2: Y3 = Y2 Y, Y4 = Y2 Y2 (with B_5 of the exp chain); U2 = Y2 v, U3 = Y2 U1 (with B_5 v)
   {
     const PhaseTiles pt(worker, nw, nb, nb);
-      gemm_range<m, KB, ALL, 2, kShareA, 2>(
-          pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, Y2, X0, Y2, Y2, sc1, 1.0, lds,
-          [&](int i, int j, double y3, double y4, const Side<2>& sd) {
-            const size_t e = (size_t)i * m + j;
-            const double id = i == j ? 1.0 : 0.0;
-            gst(Y3 + e, y3);
-            gst(Y4 + e, y4);
-            gst(E1 + e, coef_block<5, 1>(id, sd.v[0] * sc1, sd.v[1], y3));
-          },
-          X0, Y2);
-      gemm_range<m, KB, ALL, 2, kShareA, 2, TW, TW>(
-          pt.first_thin, pt.end_thin, pt.step, [&](int t, int& ti_, int& tj_) { pt.thin(t, ti_, tj_); }, Y2, V, Y2, U1, 1.0, 1.0, lds,
-          [&](int i, int j, double u2, double u3, const Side<2>& sd) {
-            const size_t e = (size_t)i * TW + j;
-            gst(U2 + e, u2);
-            gst(U3 + e, u3);
-            gst(W1 + e, coef_block<5, 0>(sd.v[0], sd.v[1], u2, u3));
-          },
-          V, U1);
+    gemm_range<m, KB, ALL, 2, kShareA, 2>(
+        pt.first_full, pt.end_full, pt.step, pt.full, Y2, X0, Y2, Y2, sc1, 1.0, lds,
+        [&](int i, int j, double y3, double y4, const Side<2>& sd) {
+          const size_t e = (size_t)i * m + j;
+          const double id = i == j ? 1.0 : 0.0;
+          gst(Y3 + e, y3);
+          gst(Y4 + e, y4);
+          gst(E1 + e, coef_block<5, 1>(id, sd.v[0] * sc1, sd.v[1], y3));
+        },
+        X0, Y2);
+    gemm_range<m, KB, ALL, 2, kShareA, 2, TW, TW>(
+        pt.first_thin, pt.end_thin, pt.step, pt.thin, Y2, V, Y2, U1, 1.0, 1.0, lds,
+        [&](int i, int j, double u2, double u3, const Side<2>& sd) {
+          const size_t e = (size_t)i * TW + j;
+          gst(U2 + e, u2);
+          gst(U3 + e, u3);
+          gst(W1 + e, coef_block<5, 0>(sd.v[0], sd.v[1], u2, u3));
+        },
+        V, U1);
   }
   bar.sync();
   // ---- Horner steps J = 4 ... 0 (results in E0 and W0)
@@ -645,12 +659,12 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
     {
       const PhaseTiles pt(worker, nw, nb, nb);
       if (it + 1 < s)
-        gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, [&](int t, int& ti_, int& tj_) { pt.full(t, ti_, tj_); }, Ec, Ec, Ec, Ec, 1.0, 0.0,
+        gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, pt.full, Ec, Ec, Ec, Ec, 1.0, 0.0,
                                            lds, [&](int i, int j, double v, double, const Side<0>&) {
                                              gst(En + (size_t)i * m + j, v);
                                            });
       gemm_range<m, KB, ALL, 1, kShareA, 1, TW, TW>(
-          pt.first_thin, pt.end_thin, pt.step, [&](int t, int& ti_, int& tj_) { pt.thin(t, ti_, tj_); }, Ec, Wc, Ec, Wc, 0.5, 0.0, lds,
+          pt.first_thin, pt.end_thin, pt.step, pt.thin, Ec, Wc, Ec, Wc, 0.5, 0.0, lds,
           [&](int i, int j, double v, double, const Side<1>& sd) { gst(Wn + (size_t)i * TW + j, v + 0.5 * sd.v[0]); },
           Wc);
     }
