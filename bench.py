@@ -128,9 +128,15 @@ def roofline(kernel: str, avg_ms: float, N: int, m: int, d: int, s: int, nparts:
         cands.append(("alu", T / sec / 1e12, PEAK["trans_Tops"], "Tops/s (sin/cos)", T))
     bound, ach, peak, unit, work = max(cands, key=lambda c: c[1] / c[2])
     traffic = read_traffic(kernel, workload)
-    return {"kernel": kernel, "bound": bound, "achieved": round(ach, 3), "peak": round(peak, 3), "unit": unit,
-            "frac": round(ach / peak, 4), "traffic": traffic, "avg_us": round(avg_ms * 1e3, 2),
-            "all": {c[0]: round(c[1] / c[2], 4) for c in cands}}
+    out = {"kernel": kernel, "bound": bound, "achieved": round(ach, 3), "peak": round(peak, 3), "unit": unit,
+           "frac": round(ach / peak, 4), "traffic": traffic, "avg_us": round(avg_ms * 1e3, 2),
+           "all": {c[0]: round(c[1] / c[2], 4) for c in cands}}
+    if kernel in ("k_phi1", "k_phi1_apply"):
+        # grid barriers in one call: set-up, Y^2, (Y^3, Y^4), five Horner steps, s squarings
+        phases = 8 + s
+        out["dependent_phases"] = phases
+        out["us_per_phase"] = round(avg_ms * 1e3 / phases, 2)
+    return out
 
 
 def time_steps(fn, steps: int, warmup: int, torch):
