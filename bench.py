@@ -39,8 +39,9 @@ PEAK = {  # MI355X published peaks
     "bf16_TFs": 2500.0,
     "fp32_mfma_TFs": 157.3,
     "fp64_TFs": 78.6,
-    # transcendental (sin/cos) rate: 256 CUs x 4 SIMDs x 16 lanes / 4 (quarter rate) x 2.4 GHz
-    "trans_Tops": 256 * 4 * 16 / 4 * 2.4e9 / 1e12,
+    # transcendental (sin/cos) rate: a quarter of the FP32 vector lane rate behind the published
+    # 157.3 TFLOP/s (256 CUs x 4 SIMDs x 32 lanes x 2 flops x 2.4 GHz)
+    "trans_Tops": 256 * 4 * 32 / 4 * 2.4e9 / 1e12,
 }
 KERNEL_SOURCES = {
     "k_bta_gram": "paper_2302_00942_amd/csrc/k_stream.hip",
