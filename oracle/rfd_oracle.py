@@ -362,6 +362,39 @@ def repeated_apply(clouds, v0, scales, lam_list, iters: int, omegas, ws):
     return v
 
 
+def rfd_operator(X, eps: float, lam: float, m: int, seed: int, shape: int = BALL_L2):
+    """x -> exp(lam A B^T) x on the cloud X with the frequencies of `seed`,
+    by the low-rank identity (Sec. 2.4): x + A (lam phi_1(lam B^T A)) (B^T x)."""
+    om, w = frequencies_and_weights(m, eps, seed, shape)
+    Phi, sg = features(X, om, w)
+    A = Phi * sg
+    S = lam * phi1(lam * (Phi.T @ A))
+
+    def apply(x):
+        x = np.asarray(x, dtype=np.float64)
+        return x + A @ (S @ (Phi.T @ x))
+
+    return apply
+
+
+def gw_loss(apply_C, apply_D, T):
+    """Loss matrix of the Gromov-Wasserstein iterations for the Euclidean loss
+    (App. "Fast Computation of Tensor Products", Alg. 2): with p = T 1 and
+    q = T^T 1,
+        L = (C^2 p) 1^T + 1 (D^2 q)^T - 2 C T D^T,
+    where C^2 p (the Hadamard square of C applied to p) is taken as
+    diag(C (C diag(p))^T) and D likewise, and C T D^T as (D (C T)^T)^T; C and D
+    enter only through their actions (apply_C on n-row, apply_D on m-row
+    blocks)."""
+    T = np.asarray(T, dtype=np.float64)
+    p = T.sum(axis=1)
+    q = T.sum(axis=0)
+    v1 = np.diag(apply_C(apply_C(np.diag(p)).T)).copy()
+    v2 = np.diag(apply_D(apply_D(np.diag(q)).T)).copy()
+    w3 = apply_D(apply_C(T).T).T
+    return v1[:, None] + v2[None, :] - 2.0 * w3
+
+
 def relf(a, b) -> float:
     """Relative Frobenius error ||a - b|| / ||b||."""
     a = np.asarray(a, dtype=np.float64)

@@ -430,3 +430,44 @@ def test_repeated_apply_matches_dense_composition():
     for t in range(3):
         v = (s0, s1)[t % 2].astype(np.float64)[:, None] * (K[t % 2] @ v)
     assert np.linalg.norm(got - v) / np.linalg.norm(v) < 1e-12
+
+
+# ---- Gromov-Wasserstein loss matrix (App. "Fast Computation of Tensor Products", Alg. 2)
+
+
+def _gw_case(seed=0, n=40, m=30):
+    Xc = wl.sphere(n, seed + 1)
+    Xd = wl.torus(m, seed + 2)
+    aC = o.rfd_operator(Xc, 0.3, -0.4, 32, 5)
+    aD = o.rfd_operator(Xd, 0.3, -0.6, 32, 6)
+    g = np.random.default_rng(seed)
+    T = g.uniform(0, 1, (n, m))
+    return aC, aD, T / T.sum()
+
+
+def test_gw_loss_matches_brute_force():
+    """L_kl = sum_ij (C_ik - D_jl)^2 T_ij, summed directly over all i, j for
+    every (k, l) with the explicit matrices C = K_C I and D = K_D I, equals the
+    decomposed form (the operators are symmetric with the default preset)."""
+    aC, aD, T = _gw_case()
+    n, m = T.shape
+    C = aC(np.eye(n))
+    D = aD(np.eye(m))
+    assert np.abs(C - C.T).max() < 1e-12 and np.abs(D - D.T).max() < 1e-12
+    Lb = np.empty((n, m))
+    for k in range(n):
+        for l in range(m):
+            Lb[k, l] = np.sum((C[:, k][:, None] - D[:, l][None, :]) ** 2 * T)
+    L = o.gw_loss(aC, aD, T)
+    assert o.relf(L, Lb) < 1e-12
+    assert L.min() > -1e-12  # a T-weighted sum of squares
+
+
+def test_gw_hadamard_square_action():
+    """diag(C (C diag(p))^T) = C^(o2) p (the element-wise square of C applied
+    to p) for a symmetric C."""
+    aC, _, T = _gw_case(3)
+    n = T.shape[0]
+    C = aC(np.eye(n))
+    p = T.sum(axis=1)
+    assert o.relf(np.diag(aC(aC(np.diag(p)).T)), (C * C) @ p) < 1e-13
