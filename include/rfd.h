@@ -23,8 +23,8 @@
  *   applied in phi_1 form, which needs no inverse of B^T A:
  *       out = F + A (lambda phi_1(lambda B^T A)) (B^T F),
  *       phi_1(Y) = sum_{k>=0} Y^k / (k+1)!,
- *   with phi_1 evaluated in FP64 by a [13/13] Pade approximant with scaling
- *   and squaring.
+ *   with phi_1 evaluated in FP64 by the degree-23 Taylor series
+ *   (Paterson-Stockmeyer) with scaling and squaring.
  *
  * Memory: every X, F and out pointer is DEVICE memory owned by the caller.
  * F and out are row-major N x d float32 arrays with leading dimensions
@@ -109,7 +109,7 @@ rfd_status rfd_plan_export(rfd_plan_t plan, float* omega_fx3, double* w_f);
 
 /* Features of a cloud: copies X (N x 3 float32, device, row-major) into the
  * plan, computes M = B^T A (split over N, fixed-order reduction, FP64 result)
- * and S = lambda phi_1(lambda M) in FP64 (Pade 13, scaling and squaring).
+ * and S = lambda phi_1(lambda M) in FP64 (Taylor 23, scaling and squaring).
  * Enqueued on `stream`; returns once enqueued. Errors found on the host are
  * returned at once: RFD_ERR_INVALID_ARG (N < 0), RFD_ERR_RANGE when lambda
  * and the weights allow growth (lambda * w > 0 for some k) and the exact
@@ -261,6 +261,51 @@ rfd_status rfd_loop_launch(rfd_loop_t loop, rfd_stream_t stream);
 
 /* Waits for the device and frees the loop (not the plans). */
 void rfd_loop_destroy(rfd_loop_t loop);
+
+/* ------------------------------------------- Gromov-Wasserstein loss matrix */
+
+typedef struct rfd_gw_s* rfd_gw_t;
+
+/* Workspace for the loss matrix of the Gromov-Wasserstein iterations with the
+ * Euclidean loss (App. "Fast Computation of Tensor Products", Alg. 2), where
+ * the cost matrices are the RFD operators of two clouds: C = exp(lambda A B^T)
+ * of plan pc (source cloud, n points) and D likewise of plan pd (target
+ * cloud, m points), both with rfd_features already run on their clouds.
+ * C and D enter only through their actions (resident integrations). The
+ * identity behind Alg. 2 assumes symmetric costs, which holds for RFD
+ * operators whose weights are all positive (the default main-lobe sampling).
+ * Allocates two max(n, m)^2 float buffers and sizes both plans' buffers (S,
+ * partial sums) so that rfd_gw_loss allocates nothing. The plans must outlive
+ * the workspace and keep their cloud sizes. Errors: RFD_ERR_INVALID_ARG (null
+ * or identical plans, n or m < 1 or > 32768), RFD_ERR_NOT_READY (no
+ * features), RFD_ERR_DEVICE. */
+rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out);
+
+/* L = v1 1^T + 1 v2^T - 2 C T D^T for the coupling T (n x m float32,
+ * row-major, leading dimension ldT >= m, device), written to L (n x m,
+ * ldL >= m, device; must not overlap T), with p = T 1, q = T^T 1,
+ * v1 = diag(C (C diag p)^T) = C^{o2} p and v2 = D^{o2} q, each Hadamard-square
+ * action taken as two operator actions (the subsection "Estimating the Action
+ * of Hadamard Square of Matrices on Vectors"), and C T D^T as
+ * (D (C T)^T)^T (Alg. 2, step 3). The marginals are summed in FP64 in a fixed
+ * order; the operator actions follow the plans' precision. Enqueued on
+ * `stream`. Errors: RFD_ERR_INVALID_ARG (null pointers, ld < m, a plan's
+ * cloud size changed since rfd_gw_create). A non-finite T is reported by
+ * rfd_plan_check on the plans. */
+rfd_status rfd_gw_loss(rfd_gw_t gw, const float* T_dev, int64_t ldT, float* L_dev, int64_t ldL,
+                       rfd_stream_t stream);
+
+/* The three terms of the same loss separately, as the line search of the
+ * fused GW iterations uses them (App. "Gromov Wasserstein Distance", the
+ * cost c_{C,D} and the tensor product): v1 = C^{o2} p (n floats),
+ * v2 = D^{o2} q (m floats) and W3 = C T D^T (n x m, ldW >= m), all device,
+ * computed exactly as in rfd_gw_loss (L = v1 1^T + 1 v2^T - 2 W3 with the
+ * same roundings). Errors as for rfd_gw_loss. */
+rfd_status rfd_gw_terms(rfd_gw_t gw, const float* T_dev, int64_t ldT, float* v1_dev, float* v2_dev,
+                        float* W3_dev, int64_t ldW, rfd_stream_t stream);
+
+/* Waits for the device and frees the workspace (not the plans). */
+void rfd_gw_destroy(rfd_gw_t gw);
 
 /* ---------------------------------------------------------------- server */
 

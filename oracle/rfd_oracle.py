@@ -377,21 +377,27 @@ def rfd_operator(X, eps: float, lam: float, m: int, seed: int, shape: int = BALL
     return apply
 
 
-def gw_loss(apply_C, apply_D, T):
-    """Loss matrix of the Gromov-Wasserstein iterations for the Euclidean loss
-    (App. "Fast Computation of Tensor Products", Alg. 2): with p = T 1 and
-    q = T^T 1,
-        L = (C^2 p) 1^T + 1 (D^2 q)^T - 2 C T D^T,
+def gw_terms(apply_C, apply_D, T):
+    """The three terms of the Gromov-Wasserstein loss matrix for the Euclidean
+    loss (App. "Fast Computation of Tensor Products", Alg. 2): with p = T 1
+    and q = T^T 1,
+        v1 = C^2 p, v2 = D^2 q, w3 = C T D^T,
     where C^2 p (the Hadamard square of C applied to p) is taken as
-    diag(C (C diag(p))^T) and D likewise, and C T D^T as (D (C T)^T)^T; C and D
-    enter only through their actions (apply_C on n-row, apply_D on m-row
-    blocks)."""
+    diag(C (C diag(p))^T) (the Hadamard-square subsection before Alg. 2) and
+    D likewise, and C T D^T as (D (C T)^T)^T (Alg. 2, step 3); C and D enter
+    only through their actions (apply_C on n-row, apply_D on m-row blocks)."""
     T = np.asarray(T, dtype=np.float64)
     p = T.sum(axis=1)
     q = T.sum(axis=0)
     v1 = np.diag(apply_C(apply_C(np.diag(p)).T)).copy()
     v2 = np.diag(apply_D(apply_D(np.diag(q)).T)).copy()
     w3 = apply_D(apply_C(T).T).T
+    return v1, v2, w3
+
+
+def gw_loss(apply_C, apply_D, T):
+    """L = v1 1^T + 1 v2^T - 2 w3 (Alg. 2, its returned value) from gw_terms."""
+    v1, v2, w3 = gw_terms(apply_C, apply_D, T)
     return v1[:, None] + v2[None, :] - 2.0 * w3
 
 

@@ -1,0 +1,155 @@
+// Loss matrix of the Gromov-Wasserstein iterations with RFD operators in place
+// of the two cost matrices (App. "Fast Computation of Tensor Products",
+// Alg. 2, with the Hadamard-square action of the preceding subsection):
+//
+//   p = T 1, q = T^T 1
+//   v1 = diag(FM_C(FM_C(diag p)^T))      (= C^{o2} p)
+//   v2 = diag(FM_D(FM_D(diag q)^T))      (= D^{o2} q)
+//   w3 = (FM_D(FM_C(T)^T))^T             (= C T D^T)
+//   L  = v1 1^T + 1 v2^T - 2 w3
+//
+// FM_C is the resident integrate of the plan of the source cloud (n points),
+// FM_D that of the target cloud (m points); the matrix-valued fields are
+// integrated 64 channels at a time. Every step runs on the caller's stream.
+#include <new>
+
+#include "rfd_internal.h"
+
+struct rfd_gw_s {
+  rfd_plan_s* pc = nullptr;
+  rfd_plan_s* pd = nullptr;
+  int n = 0, m = 0;
+  float* A = nullptr;   // max(n, m)^2 floats
+  float* B = nullptr;   // max(n, m)^2 floats
+  float* vec = nullptr; // p (n), q (m), v1 (n), v2 (m)
+};
+
+namespace {
+
+#define HIPCK(x)                                  \
+  do {                                            \
+    if ((x) != hipSuccess) return RFD_ERR_DEVICE; \
+  } while (0)
+
+#define RFDCK(x)                     \
+  do {                               \
+    const rfd_status s_ = (x);       \
+    if (s_ != RFD_OK) return s_;     \
+  } while (0)
+
+constexpr int kMaxGwPoints = 32768;  // largest n or m (two n^2 float buffers: 8 GiB)
+
+void free_gw(rfd_gw_s* g) {
+  void* ptrs[] = {g->A, g->B, g->vec};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete g;
+}
+
+// Partial buffer for every 64-channel slice of a d-column field on plan p.
+rfd_status size_partials(rfd_plan_s* p, int d) {
+  const int W = rfd::slice_width(p->dev_m, false);
+  size_t need = 0;
+  for (int c0 = 0; c0 < d; c0 += W) {
+    const size_t f = rfd::partial_floats_needed(p, p->N, d - c0 < W ? d - c0 : W, false);
+    need = f > need ? f : need;
+  }
+  return rfd::ensure_partials(p, need, nullptr);
+}
+
+// v = diag(FM(FM(diag w)^T)) on plan p with k points (Hadamard-square action).
+rfd_status hadamard_square(rfd_plan_s* p, int k, const float* w, float* v, float* A, float* B, hipStream_t st) {
+  HIPCK(rfd::launch_gw_diag_field(w, k, A, k, st));
+  RFDCK(rfd::integrate_enqueue(p, A, k, k, B, k, st, 0, nullptr));
+  HIPCK(rfd::launch_gw_transpose(B, k, k, k, A, k, st));
+  RFDCK(rfd::integrate_enqueue(p, A, k, k, B, k, st, 0, nullptr));
+  HIPCK(rfd::launch_gw_take_diag(B, k, k, v, st));
+  return RFD_OK;
+}
+
+// p, q, v1, v2 into g->vec and w3^T = FM_D(FM_C(T)^T) (m x n) into g->B.
+rfd_status enqueue_terms(rfd_gw_s* g, const float* T, int64_t ldT, hipStream_t st) {
+  if (!T || ldT < g->m) return RFD_ERR_INVALID_ARG;
+  if (g->pc->N != g->n || g->pd->N != g->m) return RFD_ERR_INVALID_ARG;  // a cloud changed size
+  const int n = g->n, m = g->m;
+  float *p = g->vec, *q = p + n, *v1 = q + m, *v2 = v1 + n;
+  RFDCK(rfd::ensure_core(g->pc, st));
+  RFDCK(rfd::ensure_core(g->pd, st));
+  HIPCK(rfd::launch_gw_margins(T, ldT, n, m, p, q, st));
+  RFDCK(hadamard_square(g->pc, n, p, v1, g->A, g->B, st));
+  RFDCK(hadamard_square(g->pd, m, q, v2, g->A, g->B, st));
+  // A = FM_C(T) (n x m), B = A^T (m x n), B <- FM_D(B) in place
+  RFDCK(rfd::integrate_enqueue(g->pc, T, ldT, m, g->A, m, st, 0, nullptr));
+  HIPCK(rfd::launch_gw_transpose(g->A, m, n, m, g->B, n, st));
+  RFDCK(rfd::integrate_enqueue(g->pd, g->B, n, n, g->B, n, st, 0, nullptr));
+  return RFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out) {
+  if (!out) return RFD_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!pc || !pd || pc == pd) return RFD_ERR_INVALID_ARG;
+  if (pc->N < 0 || pd->N < 0) return RFD_ERR_NOT_READY;
+  if (pc->N < 1 || pd->N < 1 || pc->N > kMaxGwPoints || pd->N > kMaxGwPoints) return RFD_ERR_INVALID_ARG;
+  rfd_gw_s* g = new (std::nothrow) rfd_gw_s();
+  if (!g) return RFD_ERR_DEVICE;
+  g->pc = pc;
+  g->pd = pd;
+  g->n = (int)pc->N;
+  g->m = (int)pd->N;
+  const size_t k = (size_t)(g->n > g->m ? g->n : g->m);
+  bool ok = hipMalloc((void**)&g->A, sizeof(float) * k * k) == hipSuccess &&
+            hipMalloc((void**)&g->B, sizeof(float) * k * k) == hipSuccess &&
+            hipMalloc((void**)&g->vec, sizeof(float) * 2 * (size_t)(g->n + g->m)) == hipSuccess;
+  // S and T of both plans, and partial buffers for the widest fields each
+  // plan integrates (n and m columns), so that no call of the loss allocates
+  rfd_status s = ok ? RFD_OK : RFD_ERR_DEVICE;
+  for (rfd_plan_s* p : {pc, pd}) {
+    if (s == RFD_OK && !p->core_ready) {
+      s = hipDeviceSynchronize() == hipSuccess ? rfd::ensure_core(p, nullptr) : RFD_ERR_DEVICE;
+      if (s == RFD_OK && hipDeviceSynchronize() != hipSuccess) s = RFD_ERR_DEVICE;
+    }
+  }
+  if (s == RFD_OK) s = size_partials(pc, g->n > g->m ? g->n : g->m);
+  if (s == RFD_OK) s = size_partials(pd, g->n > g->m ? g->n : g->m);
+  if (s != RFD_OK) {
+    free_gw(g);
+    return s;
+  }
+  *out = g;
+  return RFD_OK;
+}
+
+rfd_status rfd_gw_loss(rfd_gw_t g, const float* T, int64_t ldT, float* L, int64_t ldL, rfd_stream_t stream) {
+  if (!g || !L || ldL < g->m) return RFD_ERR_INVALID_ARG;
+  const hipStream_t st = (hipStream_t)stream;
+  RFDCK(enqueue_terms(g, T, ldT, st));
+  const float *v1 = g->vec + g->n + g->m, *v2 = v1 + g->n;
+  HIPCK(rfd::launch_gw_combine(v1, v2, g->B, g->n, g->n, g->m, L, ldL, st));
+  return RFD_OK;
+}
+
+rfd_status rfd_gw_terms(rfd_gw_t g, const float* T, int64_t ldT, float* v1, float* v2, float* W3, int64_t ldW,
+                        rfd_stream_t stream) {
+  if (!g || !v1 || !v2 || !W3 || ldW < g->m) return RFD_ERR_INVALID_ARG;
+  const hipStream_t st = (hipStream_t)stream;
+  RFDCK(enqueue_terms(g, T, ldT, st));
+  const int n = g->n, m = g->m;
+  const float* dv1 = g->vec + n + m;
+  HIPCK(hipMemcpyAsync(v1, dv1, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+  HIPCK(hipMemcpyAsync(v2, dv1 + n, sizeof(float) * m, hipMemcpyDeviceToDevice, st));
+  HIPCK(rfd::launch_gw_transpose(g->B, n, m, n, W3, ldW, st));
+  return RFD_OK;
+}
+
+void rfd_gw_destroy(rfd_gw_t g) {
+  if (!g) return;
+  (void)hipDeviceSynchronize();
+  free_gw(g);
+}
+
+}  // extern "C"

@@ -145,6 +145,14 @@ hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, co
 hipError_t launch_phi1_batch_dev(int M, int n, const void* dev_args, hipStream_t st);
 void phi1_fill_args(rfd_plan_s* p, void* args_out);  // writes one Phi1Args
 int dblocks(int d);
+// Gromov-Wasserstein loss matrix (k_gw.hip): row-major FP32 matrices.
+hipError_t launch_gw_margins(const float* T, int64_t ldT, int n, int m, float* p, float* q, hipStream_t st);
+hipError_t launch_gw_diag_field(const float* v, int n, float* out, int64_t ld, hipStream_t st);
+hipError_t launch_gw_transpose(const float* in, int64_t ldi, int rows, int cols, float* out, int64_t ldo,
+                               hipStream_t st);
+hipError_t launch_gw_take_diag(const float* Z, int64_t ld, int n, float* v, hipStream_t st);
+hipError_t launch_gw_combine(const float* v1, const float* v2, const float* V, int64_t ldV, int n, int m, float* L,
+                             int64_t ldL, hipStream_t st);
 // Launch-geometry tuning (autotune.cpp): knobs that change speed, never results.
 enum TuneKnob { kTuneExpandTilesPerWave = 0, kTuneBatchExpandTilesPerItem = 1, kTunePhi1Workgroups = 2,
                 kNumTuneKnobs };

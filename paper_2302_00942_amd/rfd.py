@@ -68,6 +68,10 @@ def lib() -> C.CDLL:
             "rfd_loop_create": ([vp, vp, i32, vp, i64, i32, i32, C.POINTER(vp)], i32),
             "rfd_loop_launch": ([vp, vp], i32),
             "rfd_loop_destroy": ([vp], None),
+            "rfd_gw_create": ([vp, vp, C.POINTER(vp)], i32),
+            "rfd_gw_loss": ([vp, vp, i64, vp, i64, vp], i32),
+            "rfd_gw_terms": ([vp, vp, i64, vp, vp, vp, i64, vp], i32),
+            "rfd_gw_destroy": ([vp], None),
             "rfd_plan_check": ([vp, vp], i32),
             "rfd_plan_core": ([vp, vp, vp, vp, vp], i32),
             "rfd_plan_destroy": ([vp], None),
@@ -342,6 +346,60 @@ class Loop:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().rfd_loop_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GW:
+    """Loss matrix of the Gromov-Wasserstein iterations (rfd_gw_*): the source
+    plan pc and target plan pd have their features computed on clouds of n and
+    m points; loss(T) returns L = v1 1^T + 1 v2^T - 2 C T D^T (n x m)."""
+
+    def __init__(self, pc: "Plan", pd: "Plan"):
+        h = C.c_void_p()
+        _check(lib().rfd_gw_create(pc.handle, pd.handle, C.byref(h)), "rfd_gw_create")
+        self._keep = (pc, pd)
+        self._h = h
+        self.n, self.m = pc.N, pd.N
+
+    def _coupling(self, T):
+        _dev_f32(T, "T", self.m)
+        if T.shape[0] != self.n:
+            raise ValueError(f"T must be {self.n} x {self.m}")
+        return T
+
+    def loss(self, T, out=None, stream=None):
+        import torch
+        self._coupling(T)
+        if out is None:
+            out = torch.empty(T.shape, dtype=torch.float32, device=T.device)
+        _dev_f32(out, "out", self.m)
+        if out.shape[0] != self.n:
+            raise ValueError(f"out must be {self.n} x {self.m}")
+        _check(lib().rfd_gw_loss(self._h, T.data_ptr(), T.stride(0), out.data_ptr(), out.stride(0),
+                                 _stream_handle(stream)), "rfd_gw_loss")
+        return out
+
+    def terms(self, T, stream=None):
+        """(v1 = C^(o2) p, v2 = D^(o2) q, W3 = C T D^T) as rfd_gw_terms returns them."""
+        import torch
+        self._coupling(T)
+        n, m = T.shape
+        v1 = torch.empty(n, dtype=torch.float32, device=T.device)
+        v2 = torch.empty(m, dtype=torch.float32, device=T.device)
+        W3 = torch.empty((n, m), dtype=torch.float32, device=T.device)
+        _check(lib().rfd_gw_terms(self._h, T.data_ptr(), T.stride(0), v1.data_ptr(), v2.data_ptr(), W3.data_ptr(),
+                                  W3.stride(0), _stream_handle(stream)), "rfd_gw_terms")
+        return v1, v2, W3
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().rfd_gw_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -175,6 +175,35 @@ def scaling_vectors(n: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     return (g.uniform(0.9, 1.1, n).astype(np.float32), g.uniform(0.9, 1.1, n).astype(np.float32))
 
 
+def box_cloud(n: int, seed: int) -> np.ndarray:
+    """Uniform in the unit cube: a random 3-D distribution of the kind the
+    Gromov-Wasserstein experiments (App. "Ablation Studies for Gromov
+    Wasserstein experiments") run on."""
+    return _rng(seed).uniform(0.0, 1.0, (n, 3)).astype(np.float32)
+
+
+def coupling(n: int, m: int, seed: int) -> np.ndarray:
+    """A dense positive coupling T (n x m) with total mass 1: the product of
+    two random marginals, each entry perturbed by a factor U[0.5, 1.5]."""
+    g = _rng(seed)
+    a = g.uniform(0.5, 1.5, n)
+    b = g.uniform(0.5, 1.5, m)
+    T = np.outer(a, b) * g.uniform(0.5, 1.5, (n, m))
+    return (T / T.sum()).astype(np.float32)
+
+
+def gw_pair(n: int = 3000, m: int = 3000, seed: int = 0, feats: int = 16):
+    """Source and target clouds of a Gromov-Wasserstein problem (uniform in the
+    unit cube and on a sphere of radius 0.5 about the cube's centre) with the
+    RFD parameters of the paper's GW experiments (m = 16 features, eps = 0.3,
+    lambda = -0.2) and a dense coupling T (n x m). The clouds carry no field."""
+    Xc = box_cloud(n, seed)
+    Xd = (0.5 + sphere(m, seed + 1, radius=0.5)).astype(np.float32)
+    c = Cloud(Xc, np.zeros((n, 0), np.float32), eps=0.3, lam=-0.2, m=feats, seed=seed, surface="box")
+    d = Cloud(Xd, np.zeros((m, 0), np.float32), eps=0.3, lam=-0.2, m=feats, seed=seed + 1, surface="sphere")
+    return c, d, coupling(n, m, seed + 2)
+
+
 def poisson_requests(count: int, qps: float, seed: int, lo: int = 2000, hi: int = 200_000,
                      ds=(3, 16, 64), ms=(64, 128, 256)) -> list[dict]:
     """Request stream for the serving loop: exponential inter-arrival gaps at

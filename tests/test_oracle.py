@@ -471,3 +471,15 @@ def test_gw_hadamard_square_action():
     C = aC(np.eye(n))
     p = T.sum(axis=1)
     assert o.relf(np.diag(aC(aC(np.diag(p)).T)), (C * C) @ p) < 1e-13
+
+
+def test_gw_terms_against_explicit_matrices():
+    """The three terms one by one against the explicit operator matrices:
+    v1 = (C o C) p, v2 = (D o D) q, w3 = C T D^T."""
+    aC, aD, T = _gw_case(7, n=33, m=47)
+    C = aC(np.eye(T.shape[0]))
+    D = aD(np.eye(T.shape[1]))
+    v1, v2, w3 = o.gw_terms(aC, aD, T)
+    assert o.relf(v1, (C * C) @ T.sum(axis=1)) < 1e-13
+    assert o.relf(v2, (D * D) @ T.sum(axis=0)) < 1e-13
+    assert o.relf(w3, C @ T @ D.T) < 1e-13
