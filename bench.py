@@ -277,6 +277,60 @@ def bench_resident_wide(torch, rfd, wl, reps: int):
                         "integrate only", "unit": "points*channels/s", **res}
 
 
+def gw_bytes(n: int, m: int) -> float:
+    """Algorithmic HBM bytes of one Gromov-Wasserstein loss matrix (n x m):
+    every action of a k-column field on N points reads X twice and the field
+    twice and writes the result once, N (24 + 12 k); the diagonal fields are
+    written once, each transpose reads and writes its matrix once, the
+    marginals read T once, the final combination reads W3 and writes L."""
+    act = lambda N, k: N * (24 + 12 * k)
+    sq = lambda k: 4 * k * k + 2 * act(k, k) + 8 * k * k
+    return 4 * n * m + sq(n) + sq(m) + act(n, m) + 8 * n * m + act(m, n) + 8 * n * m
+
+
+def bench_gw(torch, rfd, wl, reps: int):
+    """Gromov-Wasserstein loss matrix (Alg. 2 of the tensor-product appendix)
+    with RFD operators for both cost matrices: two clouds of n points (unit
+    cube, sphere), m = 16 features, eps = 0.3, lambda = -0.2, a dense coupling.
+    n = 3000 is the size of the paper's GW ablations; n = 8192 is near the
+    largest size the paper's baselines reach. The oracle's loss at n = 3000
+    (numpy float64) is timed and compared."""
+    from oracle import rfd_oracle as o
+    res = {}
+    for n in (3000, 8192):
+        c, dcl, T = wl.gw_pair(n, n, 0, 16)
+        Td = torch.from_numpy(T).cuda()
+        L = torch.empty_like(Td)
+        ref = None
+        if n == 3000:
+            t0 = time.perf_counter()
+            aC = o.rfd_operator(c.X, c.eps, c.lam, c.m, c.seed)
+            aD = o.rfd_operator(dcl.X, dcl.eps, dcl.lam, dcl.m, dcl.seed)
+            ref = o.gw_loss(aC, aD, T)
+            t_cpu = time.perf_counter() - t0
+        for prec in ("bf16", "fp32"):
+            pc = rfd.Plan(c.m, c.eps, c.lam, c.seed, precision=prec)
+            pd = rfd.Plan(dcl.m, dcl.eps, dcl.lam, dcl.seed, precision=prec)
+            pc.features(torch.from_numpy(c.X).cuda())
+            pd.features(torch.from_numpy(dcl.X).cuda())
+            g = rfd.GW(pc, pd)
+            ms, p50, _ = time_steps(lambda: g.loss(Td, L), reps, 3, torch)
+            gbs = gw_bytes(n, n) / (ms * 1e-3) / 1e9
+            r = {"ms": round(ms, 4), "value": round(n * n / (ms * 1e-3), 1),
+                 "hbm_GBs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / PEAK["hbm_GBs"], 4)}
+            if ref is not None:
+                r["rel_err_vs_oracle"] = float(f"{o.relf(L.cpu().numpy(), ref):.3e}")
+            res[f"n{n}_{prec}"] = r
+            g.close()
+            pc.close()
+            pd.close()
+        if n == 3000:
+            res["cpu_oracle_n3000"] = {"s": round(t_cpu, 3), "value": round(n * n / t_cpu, 1)}
+    return {"workload": "GW loss matrix L (n x n): source cloud uniform in the unit cube, target on a sphere, "
+                        "m=16, eps=0.3, lambda=-0.2, dense coupling; 6 wide-field RFD integrations per loss",
+            "unit": "loss entries/s", "bytes_per_loss_n3000": gw_bytes(3000, 3000), **res}
+
+
 def bench_serving(torch, rfd, wl, count: int, warm: int, pool: int = 64):
     """Serving: a pool of clouds (N log-uniform in [2000, 200000], random
     surface, m in {64, 128, 256}); each request integrates a fresh field of a
@@ -392,10 +446,13 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (and the error check)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched, repeated-application and serving measurements")
+                    help="skip the batched, repeated-application, wide-field, GW and serving measurements")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests of the serving leg")
     ap.add_argument("--n", type=int, default=1_000_000, help=argparse.SUPPRESS)
+    ap.add_argument("--gw-n", type=int, default=3000, help=argparse.SUPPRESS)
     ap.add_argument("--dump-inputs", metavar="DIR", help="write the cloud for paper_2302_00942_amd/rfd_run and exit")
+    ap.add_argument("--gw-only", action="store_true", help="run only the Gromov-Wasserstein stage")
+    ap.add_argument("--dump-gw", metavar="DIR", help="write the GW problem (n=3000 per cloud) for paper_2302_00942_amd/rfd_run and exit")
     args = ap.parse_args()
     if args.dump_inputs:
         from paper_2302_00942_amd import workloads as wl
@@ -405,6 +462,16 @@ def main() -> int:
         c.F.tofile(os.path.join(args.dump_inputs, "F.bin"))
         with open(os.path.join(args.dump_inputs, "meta.txt"), "w") as fh:
             fh.write(f"{c.n} {c.d} {c.m} {c.eps!r} {c.lam!r} {c.seed}\n")
+        return 0
+    if args.dump_gw:
+        from paper_2302_00942_amd import workloads as wl
+        c, dcl, T = wl.gw_pair(args.gw_n, args.gw_n, 0, 16)
+        os.makedirs(args.dump_gw, exist_ok=True)
+        c.X.tofile(os.path.join(args.dump_gw, "Xc.bin"))
+        dcl.X.tofile(os.path.join(args.dump_gw, "Xd.bin"))
+        T.tofile(os.path.join(args.dump_gw, "T.bin"))
+        with open(os.path.join(args.dump_gw, "meta_gw.txt"), "w") as fh:
+            fh.write(f"{c.n} {dcl.n} {c.m} {c.eps!r} {c.lam!r} {c.seed} {dcl.seed}\n")
         return 0
     if args.gpus != 1:
         print("bench.py measures one MI355X: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -416,6 +483,9 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     rfd.lib()
+    if args.gw_only:
+        print(json.dumps({"gromov_wasserstein": bench_gw(torch, rfd, wl, max(5, args.steps))}))
+        return 0
     cloud = wl.large_torus(n=args.n)
     N, m, d = cloud.n, cloud.m, cloud.d
     workload = f"torus N={N} m={m} d={d} eps={cloud.eps} lambda={cloud.lam} one-shot"
@@ -489,6 +559,7 @@ def main() -> int:
         line["batched"] = bench_batch(torch, rfd, wl, max(5, args.steps))
         line["repeated_application"] = bench_loop(torch, rfd, wl, max(5, args.steps // 2))
         line["resident_wide_fields"] = bench_resident_wide(torch, rfd, wl, max(5, args.steps))
+        line["gromov_wasserstein"] = bench_gw(torch, rfd, wl, max(5, args.steps))
         line["serving"] = bench_serving(torch, rfd, wl, args.serve_requests, 500)
         line["tuning_table"] = rfd.tune_export().strip().splitlines()
     if not args.no_cpu_baseline:

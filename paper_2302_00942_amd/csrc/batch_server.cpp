@@ -61,8 +61,8 @@ void free_batch(rfd_batch_s* b) {
 }
 
 rfd_status enqueue(rfd_batch_s* b, hipStream_t st) {
-  HIPCK(rfd::launch_bta_batch(b->M, b->prec, b->DB, b->dcl, b->dwork_bta, b->nwork_bta, st));
-  HIPCK(rfd::launch_reduce_batch(b->M, b->DB, b->dcl, b->n, b->max_parts, st));
+  HIPCK(rfd::launch_bta_batch(b->M, b->prec, b->DB, true, b->dcl, b->dwork_bta, b->nwork_bta, st));
+  HIPCK(rfd::launch_reduce_batch(b->M, b->DB, true, b->dcl, b->n, b->max_parts, st));
   if (b->n_apply > 0) HIPCK(rfd::launch_phi1_apply_batch_dev(b->M, b->n_apply, b->dargs_apply, b->daargs, st));
   if (b->n_full > 0) {
     HIPCK(rfd::launch_phi1_batch_dev(b->M, b->n_full, b->dargs, st));

@@ -8,9 +8,12 @@
 //   w3 = (FM_D(FM_C(T)^T))^T             (= C T D^T)
 //   L  = v1 1^T + 1 v2^T - 2 w3
 //
-// FM_C is the resident integrate of the plan of the source cloud (n points),
-// FM_D that of the target cloud (m points); the matrix-valued fields are
-// integrated 64 channels at a time. Every step runs on the caller's stream.
+// FM_C is a resident integration on the plan of the source cloud (n points),
+// FM_D one on the plan of the target cloud (m points). Each of the six
+// matrix-valued fields is integrated as one wide field (all 64-channel slices
+// in one launch per stage); the second action of each Hadamard-square term
+// forms only the diagonal that the term keeps. Every step runs on the
+// caller's stream.
 #include <new>
 
 #include "rfd_internal.h"
@@ -19,9 +22,13 @@ struct rfd_gw_s {
   rfd_plan_s* pc = nullptr;
   rfd_plan_s* pd = nullptr;
   int n = 0, m = 0;
-  float* A = nullptr;   // max(n, m)^2 floats
-  float* B = nullptr;   // max(n, m)^2 floats
-  float* vec = nullptr; // p (n), q (m), v1 (n), v2 (m)
+  float* A = nullptr;    // max(n, m)^2 floats
+  float* B = nullptr;    // max(n, m)^2 floats
+  float* vec = nullptr;  // p (n), q (m), v1 (n), v2 (m)
+  double* colpart = nullptr;  // column-sum partials of the coupling
+  // wide integrations: C on n-column fields A -> B, D on m-column fields
+  // A -> B, C on T -> A (n x m), D on B -> B (m x n, in place)
+  rfd::WideField c_sq, d_sq, c_t, d_cross;
 };
 
 namespace {
@@ -31,39 +38,30 @@ namespace {
     if ((x) != hipSuccess) return RFD_ERR_DEVICE; \
   } while (0)
 
-#define RFDCK(x)                     \
-  do {                               \
-    const rfd_status s_ = (x);       \
-    if (s_ != RFD_OK) return s_;     \
+#define RFDCK(x)                 \
+  do {                           \
+    const rfd_status s_ = (x);   \
+    if (s_ != RFD_OK) return s_; \
   } while (0)
 
 constexpr int kMaxGwPoints = 32768;  // largest n or m (two n^2 float buffers: 8 GiB)
 
 void free_gw(rfd_gw_s* g) {
-  void* ptrs[] = {g->A, g->B, g->vec};
+  for (rfd::WideField* w : {&g->c_sq, &g->d_sq, &g->c_t, &g->d_cross}) rfd::wide_free(w);
+  void* ptrs[] = {g->A, g->B, g->vec, g->colpart};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete g;
 }
 
-// Partial buffer for every 64-channel slice of a d-column field on plan p.
-rfd_status size_partials(rfd_plan_s* p, int d) {
-  const int W = rfd::slice_width(p->dev_m, false);
-  size_t need = 0;
-  for (int c0 = 0; c0 < d; c0 += W) {
-    const size_t f = rfd::partial_floats_needed(p, p->N, d - c0 < W ? d - c0 : W, false);
-    need = f > need ? f : need;
-  }
-  return rfd::ensure_partials(p, need, nullptr);
-}
-
-// v = diag(FM(FM(diag w)^T)) on plan p with k points (Hadamard-square action).
-rfd_status hadamard_square(rfd_plan_s* p, int k, const float* w, float* v, float* A, float* B, hipStream_t st) {
+// v = diag(FM(FM(diag w)^T)) with the wide integration W (k x k fields A -> B);
+// the second action forms only the diagonal of its result.
+rfd_status hadamard_square(const rfd::WideField& W, int k, const float* w, float* v, float* A, float* B,
+                           hipStream_t st) {
   HIPCK(rfd::launch_gw_diag_field(w, k, A, k, st));
-  RFDCK(rfd::integrate_enqueue(p, A, k, k, B, k, st, 0, nullptr));
+  HIPCK(rfd::wide_enqueue(&W, st));
   HIPCK(rfd::launch_gw_transpose(B, k, k, k, A, k, st));
-  RFDCK(rfd::integrate_enqueue(p, A, k, k, B, k, st, 0, nullptr));
-  HIPCK(rfd::launch_gw_take_diag(B, k, k, v, st));
+  HIPCK(rfd::wide_diag_enqueue(&W, v, st));
   return RFD_OK;
 }
 
@@ -75,13 +73,14 @@ rfd_status enqueue_terms(rfd_gw_s* g, const float* T, int64_t ldT, hipStream_t s
   float *p = g->vec, *q = p + n, *v1 = q + m, *v2 = v1 + n;
   RFDCK(rfd::ensure_core(g->pc, st));
   RFDCK(rfd::ensure_core(g->pd, st));
-  HIPCK(rfd::launch_gw_margins(T, ldT, n, m, p, q, st));
-  RFDCK(hadamard_square(g->pc, n, p, v1, g->A, g->B, st));
-  RFDCK(hadamard_square(g->pd, m, q, v2, g->A, g->B, st));
-  // A = FM_C(T) (n x m), B = A^T (m x n), B <- FM_D(B) in place
-  RFDCK(rfd::integrate_enqueue(g->pc, T, ldT, m, g->A, m, st, 0, nullptr));
+  HIPCK(rfd::launch_gw_margins(T, ldT, n, m, p, q, g->colpart, st));
+  RFDCK(hadamard_square(g->c_sq, n, p, v1, g->A, g->B, st));
+  RFDCK(hadamard_square(g->d_sq, m, q, v2, g->A, g->B, st));
+  // A = FM_C(T) (n x m), B = A^T (m x n), B <- FM_D(B)
+  HIPCK(rfd::wide_set_input(&g->c_t, T, ldT, st));
+  HIPCK(rfd::wide_enqueue(&g->c_t, st));
   HIPCK(rfd::launch_gw_transpose(g->A, m, n, m, g->B, n, st));
-  RFDCK(rfd::integrate_enqueue(g->pd, g->B, n, n, g->B, n, st, 0, nullptr));
+  HIPCK(rfd::wide_enqueue(&g->d_cross, st));
   return RFD_OK;
 }
 
@@ -99,23 +98,26 @@ rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out) {
   if (!g) return RFD_ERR_DEVICE;
   g->pc = pc;
   g->pd = pd;
-  g->n = (int)pc->N;
-  g->m = (int)pd->N;
-  const size_t k = (size_t)(g->n > g->m ? g->n : g->m);
+  const int n = (int)pc->N, m = (int)pd->N;
+  g->n = n;
+  g->m = m;
+  const size_t k = (size_t)(n > m ? n : m);
   bool ok = hipMalloc((void**)&g->A, sizeof(float) * k * k) == hipSuccess &&
             hipMalloc((void**)&g->B, sizeof(float) * k * k) == hipSuccess &&
-            hipMalloc((void**)&g->vec, sizeof(float) * 2 * (size_t)(g->n + g->m)) == hipSuccess;
-  // S and T of both plans, and partial buffers for the widest fields each
-  // plan integrates (n and m columns), so that no call of the loss allocates
+            hipMalloc((void**)&g->vec, sizeof(float) * 2 * (size_t)(n + m)) == hipSuccess &&
+            hipMalloc((void**)&g->colpart, sizeof(double) * rfd::gw_margin_scratch_doubles(n, m)) == hipSuccess;
   rfd_status s = ok ? RFD_OK : RFD_ERR_DEVICE;
+  // S and T of both plans now, so that no call of the loss forms them
   for (rfd_plan_s* p : {pc, pd}) {
     if (s == RFD_OK && !p->core_ready) {
       s = hipDeviceSynchronize() == hipSuccess ? rfd::ensure_core(p, nullptr) : RFD_ERR_DEVICE;
       if (s == RFD_OK && hipDeviceSynchronize() != hipSuccess) s = RFD_ERR_DEVICE;
     }
   }
-  if (s == RFD_OK) s = size_partials(pc, g->n > g->m ? g->n : g->m);
-  if (s == RFD_OK) s = size_partials(pd, g->n > g->m ? g->n : g->m);
+  if (s == RFD_OK) s = rfd::wide_create(pc, n, g->A, n, g->B, n, &g->c_sq);
+  if (s == RFD_OK) s = rfd::wide_create(pd, m, g->A, m, g->B, m, &g->d_sq);
+  if (s == RFD_OK) s = rfd::wide_create(pc, m, nullptr, m, g->A, m, &g->c_t);
+  if (s == RFD_OK) s = rfd::wide_create(pd, n, g->B, n, g->B, n, &g->d_cross);
   if (s != RFD_OK) {
     free_gw(g);
     return s;

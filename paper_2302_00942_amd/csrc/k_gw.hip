@@ -2,9 +2,10 @@
 // (App. "Fast Computation of Tensor Products", Alg. 2). The operator actions
 // themselves are resident RFD integrations; these kernels form the marginals
 // p = T 1 and q = T^T 1, the diagonal field diag(p), the transposes between
-// the actions, the diagonal of C (C diag(p))^T, and the final
+// the actions, and the final
 //   L[i][j] = v1[i] + v2[j] - 2 V[j][i].
-// All matrices are row-major FP32 with explicit row pitches.
+// All matrices are row-major FP32 with explicit row pitches. A last small
+// kernel re-points the slice descriptors of a wide-field integration.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -15,6 +16,20 @@ namespace rfd {
 namespace {
 
 constexpr int kTile = 32;
+constexpr int kXcds = 8;  // workgroups are dealt to the 8 XCDs round-robin by linear id
+
+// Tile of a 2-D grid for this workgroup such that each XCD takes a contiguous
+// run of tiles in row-major order: row-adjacent tiles share the cache lines
+// that straddle their boundary (rows are not line-aligned in general), and
+// on one XCD they share its L2 instead of fetching those lines twice.
+__device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
+  const int gx = gridDim.x, total = gx * gridDim.y;
+  const int b = blockIdx.y * gx + blockIdx.x;
+  const int q = total / kXcds, r = total % kXcds, x = b % kXcds, k = b / kXcds;
+  const int t = x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+  tx = t % gx;
+  ty = t / gx;
+}
 
 // p[i] = sum_j T[i][j]: one workgroup per row, FP64 lane sums over a fixed
 // stride, then a fixed tree over the workgroup.
@@ -33,14 +48,32 @@ __global__ __launch_bounds__(256) void k_gw_row_sums(const float* __restrict__ T
   if (t == 0) p[i] = (float)red[0];
 }
 
-// q[j] = sum_i T[i][j]: one thread per column, rows in order (coalesced).
-__global__ __launch_bounds__(256) void k_gw_col_sums(const float* __restrict__ T, int64_t ldT, int n, int m,
-                                                     float* __restrict__ q) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
+// Column sums in two passes with a fixed order: block b of kColRows rows
+// gives part[b][j] (rows in order, coalesced over j) ...
+constexpr int kColRows = 64;
+__global__ __launch_bounds__(256) void k_gw_col_parts(const float* __restrict__ T, int64_t ldT, int n, int m,
+                                                      double* __restrict__ part) {
+  const int j = blockIdx.x * 256 + threadIdx.x, b = blockIdx.y;
   if (j >= m) return;
+  const int r0 = b * kColRows, r1 = min(n, r0 + kColRows);
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += (double)T[(int64_t)i * ldT + j];
-  q[j] = (float)s;
+  for (int r = r0; r < r1; ++r) s += (double)T[(int64_t)r * ldT + j];
+  part[(size_t)b * m + j] = s;
+}
+
+// ... then q[j] = sum_b part[b][j]: 64 columns per workgroup, four row-block
+// groups per column summed in order, the four group sums added in order.
+__global__ __launch_bounds__(256) void k_gw_col_finish(const double* __restrict__ part, int nb, int m,
+                                                       float* __restrict__ q) {
+  __shared__ double red[4][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6, j = blockIdx.x * 64 + c;
+  const int b0 = (int)(((int64_t)g * nb) / 4), b1 = (int)(((int64_t)(g + 1) * nb) / 4);
+  double s = 0.0;
+  if (j < m)
+    for (int b = b0; b < b1; ++b) s += part[(size_t)b * m + j];
+  red[g][c] = s;
+  __syncthreads();
+  if (g == 0 && j < m) q[j] = (float)(((red[0][c] + red[1][c]) + red[2][c]) + red[3][c]);
 }
 
 // out (n x n) = diag(v).
@@ -56,7 +89,9 @@ __global__ __launch_bounds__(256) void k_gw_diag_field(const float* __restrict__
 __global__ __launch_bounds__(256) void k_gw_transpose(const float* __restrict__ in, int64_t ldi, int rows, int cols,
                                                       float* __restrict__ out, int64_t ldo) {
   __shared__ float tile[kTile][kTile + 1];
-  const int r0 = blockIdx.y * kTile, c0 = blockIdx.x * kTile;
+  int bx, by;
+  xcd_tile(bx, by);
+  const int r0 = by * kTile, c0 = bx * kTile;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
   for (int k = ty; k < kTile; k += 8) {
     const int r = r0 + k, c = c0 + tx;
@@ -69,20 +104,15 @@ __global__ __launch_bounds__(256) void k_gw_transpose(const float* __restrict__ 
   }
 }
 
-// v[i] = Z[i][i].
-__global__ __launch_bounds__(256) void k_gw_take_diag(const float* __restrict__ Z, int64_t ld, int n,
-                                                      float* __restrict__ v) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) v[i] = Z[(int64_t)i * ld + i];
-}
-
 // L[i][j] = v1[i] + v2[j] - 2 V[j][i] for V (m x n), through a padded tile;
 // rounded as fma(-2, V[j][i], v1[i] + v2[j]).
 __global__ __launch_bounds__(256) void k_gw_combine(const float* __restrict__ v1, const float* __restrict__ v2,
                                                     const float* __restrict__ V, int64_t ldV, int n, int m,
                                                     float* __restrict__ L, int64_t ldL) {
   __shared__ float tile[kTile][kTile + 1];
-  const int j0 = blockIdx.y * kTile, i0 = blockIdx.x * kTile;  // V rows j, columns i
+  int bx, by;
+  xcd_tile(bx, by);
+  const int j0 = by * kTile, i0 = bx * kTile;  // V rows j, columns i
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int k = ty; k < kTile; k += 8) {
     const int j = j0 + k, i = i0 + tx;
@@ -95,11 +125,30 @@ __global__ __launch_bounds__(256) void k_gw_combine(const float* __restrict__ v1
   }
 }
 
+// Re-points the slices of a wide field: descriptor i reads F + i W.
+__global__ __launch_bounds__(64) void k_wide_patch(CloudDesc* __restrict__ dcl, int nsl, const float* F, int64_t ldF,
+                                                   int W) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= nsl) return;
+  dcl[i].F = F + (size_t)i * W;
+  dcl[i].ldF = ldF;
+}
+
 }  // namespace
 
-hipError_t launch_gw_margins(const float* T, int64_t ldT, int n, int m, float* p, float* q, hipStream_t st) {
+hipError_t launch_wide_patch(CloudDesc* dcl, int nsl, const float* F, int64_t ldF, int W, hipStream_t st) {
+  hipLaunchKernelGGL(k_wide_patch, dim3((nsl + 63) / 64), dim3(64), 0, st, dcl, nsl, F, ldF, W);
+  return hipGetLastError();
+}
+
+size_t gw_margin_scratch_doubles(int n, int m) { return (size_t)((n + kColRows - 1) / kColRows) * m; }
+
+hipError_t launch_gw_margins(const float* T, int64_t ldT, int n, int m, float* p, float* q, double* scratch,
+                             hipStream_t st) {
+  const int nb = (n + kColRows - 1) / kColRows;
   hipLaunchKernelGGL(k_gw_row_sums, dim3(n), dim3(256), 0, st, T, ldT, m, p);
-  hipLaunchKernelGGL(k_gw_col_sums, dim3((m + 255) / 256), dim3(256), 0, st, T, ldT, n, m, q);
+  hipLaunchKernelGGL(k_gw_col_parts, dim3((m + 255) / 256, nb), dim3(256), 0, st, T, ldT, n, m, scratch);
+  hipLaunchKernelGGL(k_gw_col_finish, dim3((m + 63) / 64), dim3(256), 0, st, scratch, nb, m, q);
   return hipGetLastError();
 }
 
@@ -113,11 +162,6 @@ hipError_t launch_gw_transpose(const float* in, int64_t ldi, int rows, int cols,
                                hipStream_t st) {
   const dim3 grid((cols + kTile - 1) / kTile, (rows + kTile - 1) / kTile);
   hipLaunchKernelGGL(k_gw_transpose, grid, dim3(256), 0, st, in, ldi, rows, cols, out, ldo);
-  return hipGetLastError();
-}
-
-hipError_t launch_gw_take_diag(const float* Z, int64_t ld, int n, float* v, hipStream_t st) {
-  hipLaunchKernelGGL(k_gw_take_diag, dim3((n + 255) / 256), dim3(256), 0, st, Z, ld, n, v);
   return hipGetLastError();
 }
 

@@ -1045,20 +1045,56 @@ hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* 
   return hipErrorInvalidValue;
 }
 
+// Diagonal of a square wide-field integration (d = N, slices of 64 channels):
+// v[i] = F[i][i] + sum_j phi_j(x_i) G'_s[j][c] with s = i / 64, c = i % 64 and
+// G'_s = T H0 of slice s, the features in FP32 as the expansion forms them
+// and the sum in FP64. Only the diagonal is formed: no other element of the
+// result is read or written. One thread per point.
+template <int M>
+__global__ __launch_bounds__(256) void k_wide_diag(const CloudDesc* __restrict__ cl, int64_t N,
+                                                   float* __restrict__ v) {
+  __shared__ float4 oms[M / 2];
+  for (int k = threadIdx.x; k < M / 2; k += 256) oms[k] = gld4((const float*)(cl[0].om + k));
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const CloudDesc& c = cl[i / 64];
+  const int ch = (int)(i % 64);
+  const float x = gldf(c.X + 3 * i), y = gldf(c.X + 3 * i + 1), z = gldf(c.X + 3 * i + 2);
+  double s = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < M / 2; ++k) {
+    float sn, cs;
+    phase_sincos(oms[k], x, y, z, sn, cs);
+    s += (double)cs * gldf(c.G32 + (size_t)(2 * k) * c.d + ch);
+    s += (double)sn * gldf(c.G32 + (size_t)(2 * k + 1) * c.d + ch);
+  }
+  gstf(v + i, (float)((double)gldf(c.F + i * c.ldF + ch) + s));
+}
+
+hipError_t launch_wide_diag(int M, const CloudDesc* dcl, int64_t N, float* v, hipStream_t st) {
+  const dim3 grid((unsigned)((N + 255) / 256));
+  if (M == 64) hipLaunchKernelGGL(k_wide_diag<64>, grid, dim3(256), 0, st, dcl, N, v);
+  else if (M == 128) hipLaunchKernelGGL(k_wide_diag<128>, grid, dim3(256), 0, st, dcl, N, v);
+  else if (M == 256) hipLaunchKernelGGL(k_wide_diag<256>, grid, dim3(256), 0, st, dcl, N, v);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ batched launchers
-template <int M, int PREC>
+template <int M, int PREC, bool GRAM>
 static hipError_t bta_batch_db(int DB, int nwork, const CloudDesc* dcl, const int2* dwork, size_t stride,
                                hipStream_t st) {
   switch (DB) {
     case 1:
-      hipLaunchKernelGGL((k_bta_batch<M, PREC, true, 1>), dim3(nwork), dim3(256), 0, st, dcl, dwork, stride);
+      hipLaunchKernelGGL((k_bta_batch<M, PREC, GRAM, 1>), dim3(nwork), dim3(256), 0, st, dcl, dwork, stride);
       return hipGetLastError();
     case 2:
-      hipLaunchKernelGGL((k_bta_batch<M, PREC, true, 2>), dim3(nwork), dim3(256), 0, st, dcl, dwork, stride);
+      hipLaunchKernelGGL((k_bta_batch<M, PREC, GRAM, 2>), dim3(nwork), dim3(256), 0, st, dcl, dwork, stride);
       return hipGetLastError();
     case 4:
-      if constexpr (M != 256) {
-        hipLaunchKernelGGL((k_bta_batch<M, PREC, true, 4>), dim3(nwork), dim3(256), 0, st, dcl, dwork, stride);
+      if constexpr (M != 256 || !GRAM) {  // the Gram at m = 256 takes at most 32 channels
+        hipLaunchKernelGGL((k_bta_batch<M, PREC, GRAM, 4>), dim3(nwork), dim3(256), 0, st, dcl, dwork, stride);
         return hipGetLastError();
       }
       return hipErrorInvalidValue;
@@ -1067,23 +1103,30 @@ static hipError_t bta_batch_db(int DB, int nwork, const CloudDesc* dcl, const in
   }
 }
 
-hipError_t launch_bta_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork,
+template <int M, int PREC>
+static hipError_t bta_batch_gram(bool gram, int DB, int nwork, const CloudDesc* dcl, const int2* dwork, size_t stride,
+                                 hipStream_t st) {
+  return gram ? bta_batch_db<M, PREC, true>(DB, nwork, dcl, dwork, stride, st)
+              : bta_batch_db<M, PREC, false>(DB, nwork, dcl, dwork, stride, st);
+}
+
+hipError_t launch_bta_batch(int M, int prec, int DB, bool gram, const CloudDesc* dcl, const int2* dwork, int nwork,
                             hipStream_t st) {
-  const size_t stride = bta_partial_floats(M, 16 * DB, true);
+  const size_t stride = bta_partial_floats(M, 16 * DB, gram);
   ProfileScope prof(kKBtaBatch, st);
-  if (M == 64) return prec ? bta_batch_db<64, 1>(DB, nwork, dcl, dwork, stride, st) : bta_batch_db<64, 0>(DB, nwork, dcl, dwork, stride, st);
-  if (M == 128) return prec ? bta_batch_db<128, 1>(DB, nwork, dcl, dwork, stride, st) : bta_batch_db<128, 0>(DB, nwork, dcl, dwork, stride, st);
-  if (M == 256) return prec ? bta_batch_db<256, 1>(DB, nwork, dcl, dwork, stride, st) : bta_batch_db<256, 0>(DB, nwork, dcl, dwork, stride, st);
+  if (M == 64) return prec ? bta_batch_gram<64, 1>(gram, DB, nwork, dcl, dwork, stride, st) : bta_batch_gram<64, 0>(gram, DB, nwork, dcl, dwork, stride, st);
+  if (M == 128) return prec ? bta_batch_gram<128, 1>(gram, DB, nwork, dcl, dwork, stride, st) : bta_batch_gram<128, 0>(gram, DB, nwork, dcl, dwork, stride, st);
+  if (M == 256) return prec ? bta_batch_gram<256, 1>(gram, DB, nwork, dcl, dwork, stride, st) : bta_batch_gram<256, 0>(gram, DB, nwork, dcl, dwork, stride, st);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce_batch(int M, int DB, const CloudDesc* dcl, int ncl, int max_parts, hipStream_t st) {
-  const size_t stride = bta_partial_floats(M, 16 * DB, true);
-  const size_t E = reduce_elems(M, DB, true);
+hipError_t launch_reduce_batch(int M, int DB, bool gram, const CloudDesc* dcl, int ncl, int max_parts, hipStream_t st) {
+  const size_t stride = bta_partial_floats(M, 16 * DB, gram);
+  const size_t E = reduce_elems(M, DB, gram);
   ProfileScope prof(kKReduce, st);
   if (max_parts <= kFusedReduceMaxParts) {
     hipLaunchKernelGGL(k_reduce_fused_batch, dim3((unsigned)((E + 255) / 256), (unsigned)ncl), dim3(256), 0, st, dcl,
-                       stride, E, M, DB, 1);
+                       stride, E, M, DB, gram ? 1 : 0);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_reduce1_batch, dim3((unsigned)((E + 255) / 256), kReduceGroups, (unsigned)ncl), dim3(256), 0, st,
@@ -1091,9 +1134,11 @@ hipError_t launch_reduce_batch(int M, int DB, const CloudDesc* dcl, int ncl, int
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce2_batch, dim3((unsigned)((E + 255) / 256), 1, (unsigned)ncl), dim3(256), 0, st, dcl, E, M,
-                     DB, 1);
+                     DB, gram ? 1 : 0);
   return hipGetLastError();
 }
+
+int fused_reduce_max_parts() { return kFusedReduceMaxParts; }
 
 hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hipStream_t st) {
   ProfileScope prof(kKGcore, st);

@@ -137,8 +137,12 @@ hipError_t launch_gcore(rfd_plan_s* p, int d, hipStream_t st);
 hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF,
                          int d, float* out, int64_t ldO, const float* rowscale, hipStream_t st);
 // Batched stages over device descriptor arrays.
-hipError_t launch_bta_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, hipStream_t st);
-hipError_t launch_reduce_batch(int M, int DB, const CloudDesc* dcl, int ncl, int max_parts, hipStream_t st);
+// gram: the pass also forms the feature Gram (one-shot batches); without it only
+// B^T F of each descriptor's field (resident clouds, slices of a wide field).
+hipError_t launch_bta_batch(int M, int prec, int DB, bool gram, const CloudDesc* dcl, const int2* dwork, int nwork,
+                            hipStream_t st);
+hipError_t launch_reduce_batch(int M, int DB, bool gram, const CloudDesc* dcl, int ncl, int max_parts, hipStream_t st);
+int fused_reduce_max_parts();  // most partials the one-launch reduction takes
 hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hipStream_t st);
 hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, int tpi,
                                hipStream_t st);
@@ -146,13 +150,39 @@ hipError_t launch_phi1_batch_dev(int M, int n, const void* dev_args, hipStream_t
 void phi1_fill_args(rfd_plan_s* p, void* args_out);  // writes one Phi1Args
 int dblocks(int d);
 // Gromov-Wasserstein loss matrix (k_gw.hip): row-major FP32 matrices.
-hipError_t launch_gw_margins(const float* T, int64_t ldT, int n, int m, float* p, float* q, hipStream_t st);
+// p = T 1 and q = T^T 1 (n x m coupling), FP64 sums in a fixed order; scratch
+// holds gw_margin_scratch_doubles(n, m) doubles.
+hipError_t launch_gw_margins(const float* T, int64_t ldT, int n, int m, float* p, float* q, double* scratch,
+                             hipStream_t st);
+size_t gw_margin_scratch_doubles(int n, int m);
 hipError_t launch_gw_diag_field(const float* v, int n, float* out, int64_t ld, hipStream_t st);
 hipError_t launch_gw_transpose(const float* in, int64_t ldi, int rows, int cols, float* out, int64_t ldo,
                                hipStream_t st);
-hipError_t launch_gw_take_diag(const float* Z, int64_t ld, int n, float* v, hipStream_t st);
 hipError_t launch_gw_combine(const float* v1, const float* v2, const float* V, int64_t ldV, int n, int m, float* L,
                              int64_t ldL, hipStream_t st);
+// Resident integration of a wide field on one plan, one launch per stage over
+// its 64-channel slices (wide.cpp). Shapes and buffers are fixed at creation;
+// wide_set_input re-points the field (same width) on the stream.
+struct WideField {
+  rfd_plan_s* p = nullptr;
+  int64_t N = 0;
+  int d = 0, nsl = 0, DB = 4, nparts = 1, tpi = 64;
+  CloudDesc* dcl = nullptr;  // one descriptor per slice (device)
+  int2* dwork_bta = nullptr;
+  int2* dwork_exp = nullptr;
+  int nwork_bta = 0, nwork_exp = 0;
+  void* arena = nullptr;     // per-slice partials, H0, G32, Gt16
+};
+rfd_status wide_create(rfd_plan_s* p, int d, const float* F, int64_t ldF, float* out, int64_t ldO, WideField* w);
+hipError_t wide_set_input(WideField* w, const float* F, int64_t ldF, hipStream_t st);
+hipError_t wide_enqueue(const WideField* w, hipStream_t st);  // needs the plan's S and T (ensure_core)
+// Square fields (d = N) only: v = the diagonal of the integrated field, with
+// no other element formed.
+hipError_t wide_diag_enqueue(const WideField* w, float* v, hipStream_t st);
+hipError_t launch_wide_diag(int M, const CloudDesc* dcl, int64_t N, float* v, hipStream_t st);  // k_stream.hip
+size_t wide_device_bytes(const WideField* w);
+void wide_free(WideField* w);
+hipError_t launch_wide_patch(CloudDesc* dcl, int nsl, const float* F, int64_t ldF, int W, hipStream_t st);  // k_gw.hip
 // Launch-geometry tuning (autotune.cpp): knobs that change speed, never results.
 enum TuneKnob { kTuneExpandTilesPerWave = 0, kTuneBatchExpandTilesPerItem = 1, kTunePhi1Workgroups = 2,
                 kNumTuneKnobs };

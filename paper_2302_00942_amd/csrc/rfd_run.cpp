@@ -1,12 +1,16 @@
 // rfd_run: native driver of the C ABI for profiling runs.
 //
 //   rfd_run DIR STEPS [PREC]
+//   rfd_run gw DIR STEPS [PREC]
 //   rfd_run copy MIB
 //
 // DIR holds X.bin (N x 3 float32), F.bin (N x d float32) and meta.txt
 // ("N d m eps lambda seed"), as written by `bench.py --dump-inputs DIR`.
 // Runs STEPS one-shot integrations (PREC: bf16 or fp32, default bf16) on the
-// default stream and prints the average milliseconds per step. The copy form
+// default stream and prints the average milliseconds per step. The gw form
+// reads Xc.bin (n x 3), Xd.bin (m x 3), T.bin (n x m) and meta_gw.txt
+// ("n m feats eps lambda seed_c seed_d"), as written by `bench.py --dump-gw
+// DIR`, and runs STEPS Gromov-Wasserstein loss matrices. The copy form
 // runs one device-to-device copy of MIB mebibytes (a reference kernel of
 // known traffic for calibrating hardware byte counters).
 #include <hip/hip_runtime.h>
@@ -40,8 +44,81 @@ static int copy_mode(long long mib) {
   return 0;
 }
 
+static float* upload(const std::vector<float>& h) {
+  float* d = nullptr;
+  if (hipMalloc(&d, h.size() * 4) != hipSuccess) return nullptr;
+  if (hipMemcpy(d, h.data(), h.size() * 4, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  return d;
+}
+
+static int gw_mode(const std::string& dir, int steps, int prec) {
+  long long n = 0, m = 0;
+  int feats = 0;
+  double eps = 0, lam = 0;
+  unsigned long long sc = 0, sd = 0;
+  FILE* mf = fopen((dir + "/meta_gw.txt").c_str(), "r");
+  if (!mf || fscanf(mf, "%lld %lld %d %lf %lf %llu %llu", &n, &m, &feats, &eps, &lam, &sc, &sd) != 7) {
+    fprintf(stderr, "cannot read %s/meta_gw.txt\n", dir.c_str());
+    return 1;
+  }
+  fclose(mf);
+  if (n <= 0 || m <= 0 || steps <= 0) return 1;
+  std::vector<float> Xc((size_t)n * 3), Xd((size_t)m * 3), T((size_t)n * m);
+  if (!read_file(dir + "/Xc.bin", Xc.data(), Xc.size() * 4) || !read_file(dir + "/Xd.bin", Xd.data(), Xd.size() * 4) ||
+      !read_file(dir + "/T.bin", T.data(), T.size() * 4)) {
+    fprintf(stderr, "cannot read Xc.bin / Xd.bin / T.bin\n");
+    return 1;
+  }
+  float *dXc = upload(Xc), *dXd = upload(Xd), *dT = upload(T), *dL = nullptr;
+  if (!dXc || !dXd || !dT || hipMalloc(&dL, T.size() * 4) != hipSuccess) return 1;
+  rfd_params p;
+  memset(&p, 0, sizeof(p));
+  p.m = feats;
+  p.shape = RFD_BALL_L2;
+  p.precision = prec;
+  p.eps = eps;
+  p.lambda = lam;
+  rfd_plan_t pc = nullptr, pd = nullptr;
+  rfd_gw_t g = nullptr;
+  p.seed = sc;
+  rfd_status st = rfd_plan_create(&p, &pc);
+  p.seed = sd;
+  if (st == RFD_OK) st = rfd_plan_create(&p, &pd);
+  if (st == RFD_OK) st = rfd_features(pc, dXc, n, nullptr);
+  if (st == RFD_OK) st = rfd_features(pd, dXd, m, nullptr);
+  if (st == RFD_OK) st = rfd_gw_create(pc, pd, &g);
+  if (st == RFD_OK) st = rfd_gw_loss(g, dT, m, dL, m, nullptr);  // untimed
+  if (st == RFD_OK) st = rfd_plan_check(pc, nullptr);
+  if (st != RFD_OK) {
+    fprintf(stderr, "gw set-up: %s\n", rfd_status_string(st));
+    return 1;
+  }
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  (void)hipEventRecord(a, nullptr);
+  for (int i = 0; i < steps && st == RFD_OK; ++i) st = rfd_gw_loss(g, dT, m, dL, m, nullptr);
+  (void)hipEventRecord(b, nullptr);
+  (void)hipEventSynchronize(b);
+  if (st == RFD_OK) st = rfd_plan_check(pc, nullptr);
+  if (st == RFD_OK) st = rfd_plan_check(pd, nullptr);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  printf("rfd_run gw n=%lld m=%lld feats=%d prec=%s steps=%d: %.4f ms/loss (%s)\n", n, m, feats,
+         prec == RFD_BF16 ? "bf16" : "fp32", steps, ms / steps, rfd_status_string(st));
+  fflush(stdout);
+  rfd_gw_destroy(g);
+  rfd_plan_destroy(pc);
+  rfd_plan_destroy(pd);
+  float* bufs[] = {dXc, dXd, dT, dL};
+  for (float* q : bufs) (void)hipFree(q);
+  return st == RFD_OK ? 0 : 1;
+}
+
 int main(int argc, char** argv) {
   if (argc == 3 && strcmp(argv[1], "copy") == 0) return copy_mode(atoll(argv[2]));
+  if (argc >= 4 && strcmp(argv[1], "gw") == 0)
+    return gw_mode(argv[2], atoi(argv[3]), (argc > 4 && strcmp(argv[4], "fp32") == 0) ? RFD_FP32 : RFD_BF16);
   if (argc < 3) {
     fprintf(stderr, "usage: %s DIR STEPS [bf16|fp32]\n", argv[0]);
     return 2;

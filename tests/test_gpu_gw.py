@@ -119,3 +119,31 @@ def test_gw_repeatable_and_rejects_bad_shapes(torch_cuda):
     with pytest.raises(rfd.RfdError) as e:
         rfd.GW(pc, fresh)
     assert e.value.status == rfd.NOT_READY
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_gw_wide_integrations_equal_sliced_integrate(torch_cuda, prec):
+    """Each matrix-valued field is integrated in one launch per stage over its
+    64-channel slices; at these sizes (same partial count per slice) the
+    cross term equals, bitwise, the same chain of public integrations 64
+    channels at a time, W3 = (FM_D(FM_C(T)^T))^T. The second action of a
+    Hadamard-square term forms only the diagonal (FP32 features, FP64 sum),
+    so v1 = diag(FM_C(FM_C(diag p)^T)) agrees with the public chain to the
+    one-action bar. The marginals are exact FP64 sums here, so p is the
+    float32 rounding of the exact row sum."""
+    torch = torch_cuda
+    import math
+    from paper_2302_00942_amd import rfd
+    c, d, T, pc, pd = _problem(torch, 300, 200, 16, prec, seed=11)
+    g = rfd.GW(pc, pd)
+    Td = torch.from_numpy(T).cuda()
+    v1, v2, W3 = (x.cpu().numpy() for x in g.terms(Td))
+    p = np.array([math.fsum(map(float, row)) for row in T], dtype=np.float32)
+    Dp = torch.from_numpy(np.diag(p)).cuda()
+    A1 = pc.integrate(Dp)
+    A2 = pc.integrate(A1.t().contiguous())
+    assert o.relf(v1, np.diag(A2.cpu().numpy())) <= BAR[prec]
+    U = pc.integrate(Td)
+    V = pd.integrate(U.t().contiguous())
+    assert np.array_equal(V.t().cpu().numpy(), W3)
+    g.close()
