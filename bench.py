@@ -278,14 +278,17 @@ def bench_resident_wide(torch, rfd, wl, reps: int):
 
 
 def gw_bytes(n: int, m: int) -> float:
-    """Algorithmic HBM bytes of one Gromov-Wasserstein loss matrix (n x m):
-    every action of a k-column field on N points reads X twice and the field
-    twice and writes the result once, N (24 + 12 k); the diagonal fields are
-    written once, each transpose reads and writes its matrix once, the
-    marginals read T once, the final combination reads W3 and writes L."""
+    """Algorithmic HBM bytes of one Gromov-Wasserstein loss matrix (n x m) as
+    the library computes it: the marginals read T once; each Hadamard-square
+    term integrates diag(p) (X read twice, p read, the k x k result written
+    once) and then forms only the diagonal of the second action (X read
+    twice, its k x k field read once, k values written); each cross-term
+    action of a k-column field on N points reads X twice and the field twice
+    and writes its result once, N (24 + 12 k); the final combination reads
+    W3 and writes L."""
     act = lambda N, k: N * (24 + 12 * k)
-    sq = lambda k: 4 * k * k + 2 * act(k, k) + 8 * k * k
-    return 4 * n * m + sq(n) + sq(m) + act(n, m) + 8 * n * m + act(m, n) + 8 * n * m
+    sq = lambda k: (28 * k + 4 * k * k) + (28 * k + 4 * k * k)
+    return 4 * n * m + sq(n) + sq(m) + act(n, m) + act(m, n) + 8 * n * m
 
 
 def bench_gw(torch, rfd, wl, reps: int):
@@ -327,7 +330,8 @@ def bench_gw(torch, rfd, wl, reps: int):
         if n == 3000:
             res["cpu_oracle_n3000"] = {"s": round(t_cpu, 3), "value": round(n * n / t_cpu, 1)}
     return {"workload": "GW loss matrix L (n x n): source cloud uniform in the unit cube, target on a sphere, "
-                        "m=16, eps=0.3, lambda=-0.2, dense coupling; 6 wide-field RFD integrations per loss",
+                        "m=16, eps=0.3, lambda=-0.2, dense coupling; 6 wide-field RFD integrations per loss "
+                        "(two of them on diagonal fields, two forming only a diagonal)",
             "unit": "loss entries/s", "bytes_per_loss_n3000": gw_bytes(3000, 3000), **res}
 
 

@@ -11,9 +11,10 @@
 // FM_C is a resident integration on the plan of the source cloud (n points),
 // FM_D one on the plan of the target cloud (m points). Each of the six
 // matrix-valued fields is integrated as one wide field (all 64-channel slices
-// in one launch per stage); the second action of each Hadamard-square term
-// forms only the diagonal that the term keeps. Every step runs on the
-// caller's stream.
+// in one launch per stage). An action whose result is transposed next stores
+// it transposed (no transpose pass), and the second action of each
+// Hadamard-square term forms only the diagonal that the term keeps. Every
+// step runs on the caller's stream.
 #include <new>
 
 #include "rfd_internal.h"
@@ -22,13 +23,13 @@ struct rfd_gw_s {
   rfd_plan_s* pc = nullptr;
   rfd_plan_s* pd = nullptr;
   int n = 0, m = 0;
-  float* A = nullptr;    // max(n, m)^2 floats
   float* B = nullptr;    // max(n, m)^2 floats
   float* vec = nullptr;  // p (n), q (m), v1 (n), v2 (m)
   double* colpart = nullptr;  // column-sum partials of the coupling
-  // wide integrations: C on n-column fields A -> B, D on m-column fields
-  // A -> B, C on T -> A (n x m), D on B -> B (m x n, in place)
-  rfd::WideField c_sq, d_sq, c_t, d_cross;
+  // wide integrations: C on diag(p) with the result stored transposed in B,
+  // then C on B forming only the diagonal (likewise D); C on T stored
+  // transposed in B (m x n), D on B in place
+  rfd::WideField c_sq1, c_sq2, d_sq1, d_sq2, c_t, d_cross;
 };
 
 namespace {
@@ -44,24 +45,23 @@ namespace {
     if (s_ != RFD_OK) return s_; \
   } while (0)
 
-constexpr int kMaxGwPoints = 32768;  // largest n or m (two n^2 float buffers: 8 GiB)
+constexpr int kMaxGwPoints = 32768;  // largest n or m (one max(n, m)^2 float buffer: 4 GiB)
 
 void free_gw(rfd_gw_s* g) {
-  for (rfd::WideField* w : {&g->c_sq, &g->d_sq, &g->c_t, &g->d_cross}) rfd::wide_free(w);
-  void* ptrs[] = {g->A, g->B, g->vec, g->colpart};
+  for (rfd::WideField* w : {&g->c_sq1, &g->c_sq2, &g->d_sq1, &g->d_sq2, &g->c_t, &g->d_cross}) rfd::wide_free(w);
+  void* ptrs[] = {g->B, g->vec, g->colpart};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete g;
 }
 
-// v = diag(FM(FM(diag w)^T)) with the wide integration W (k x k fields A -> B);
-// the second action forms only the diagonal of its result.
-rfd_status hadamard_square(const rfd::WideField& W, int k, const float* w, float* v, float* A, float* B,
-                           hipStream_t st) {
-  HIPCK(rfd::launch_gw_diag_field(w, k, A, k, st));
-  HIPCK(rfd::wide_enqueue(&W, st));
-  HIPCK(rfd::launch_gw_transpose(B, k, k, k, A, k, st));
-  HIPCK(rfd::wide_diag_enqueue(&W, v, st));
+// v = diag(FM(FM(diag w)^T)) on k x k fields: W1 integrates diag(w) (never
+// materialised: B^T diag(w) is formed from the features directly and the
+// residual is the diagonal) and stores the result transposed in B, W2
+// integrates B forming only the diagonal of its result.
+rfd_status hadamard_square(const rfd::WideField& W1, const rfd::WideField& W2, float* v, hipStream_t st) {
+  HIPCK(rfd::wide_diag_field_enqueue(&W1, st));
+  HIPCK(rfd::wide_diag_enqueue(&W2, v, st));
   return RFD_OK;
 }
 
@@ -74,12 +74,11 @@ rfd_status enqueue_terms(rfd_gw_s* g, const float* T, int64_t ldT, hipStream_t s
   RFDCK(rfd::ensure_core(g->pc, st));
   RFDCK(rfd::ensure_core(g->pd, st));
   HIPCK(rfd::launch_gw_margins(T, ldT, n, m, p, q, g->colpart, st));
-  RFDCK(hadamard_square(g->c_sq, n, p, v1, g->A, g->B, st));
-  RFDCK(hadamard_square(g->d_sq, m, q, v2, g->A, g->B, st));
-  // A = FM_C(T) (n x m), B = A^T (m x n), B <- FM_D(B)
+  RFDCK(hadamard_square(g->c_sq1, g->c_sq2, v1, st));
+  RFDCK(hadamard_square(g->d_sq1, g->d_sq2, v2, st));
+  // B = FM_C(T)^T (m x n), then B <- FM_D(B)
   HIPCK(rfd::wide_set_input(&g->c_t, T, ldT, st));
   HIPCK(rfd::wide_enqueue(&g->c_t, st));
-  HIPCK(rfd::launch_gw_transpose(g->A, m, n, m, g->B, n, st));
   HIPCK(rfd::wide_enqueue(&g->d_cross, st));
   return RFD_OK;
 }
@@ -102,8 +101,7 @@ rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out) {
   g->n = n;
   g->m = m;
   const size_t k = (size_t)(n > m ? n : m);
-  bool ok = hipMalloc((void**)&g->A, sizeof(float) * k * k) == hipSuccess &&
-            hipMalloc((void**)&g->B, sizeof(float) * k * k) == hipSuccess &&
+  bool ok = hipMalloc((void**)&g->B, sizeof(float) * k * k) == hipSuccess &&
             hipMalloc((void**)&g->vec, sizeof(float) * 2 * (size_t)(n + m)) == hipSuccess &&
             hipMalloc((void**)&g->colpart, sizeof(double) * rfd::gw_margin_scratch_doubles(n, m)) == hipSuccess;
   rfd_status s = ok ? RFD_OK : RFD_ERR_DEVICE;
@@ -114,9 +112,12 @@ rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out) {
       if (s == RFD_OK && hipDeviceSynchronize() != hipSuccess) s = RFD_ERR_DEVICE;
     }
   }
-  if (s == RFD_OK) s = rfd::wide_create(pc, n, g->A, n, g->B, n, &g->c_sq);
-  if (s == RFD_OK) s = rfd::wide_create(pd, m, g->A, m, g->B, m, &g->d_sq);
-  if (s == RFD_OK) s = rfd::wide_create(pc, m, nullptr, m, g->A, m, &g->c_t);
+  float* p = g->vec;  // p (n), then q (m)
+  if (s == RFD_OK) s = rfd::wide_create(pc, n, nullptr, n, g->B, n, &g->c_sq1, true, p);
+  if (s == RFD_OK) s = rfd::wide_create(pc, n, g->B, n, nullptr, n, &g->c_sq2);
+  if (s == RFD_OK) s = rfd::wide_create(pd, m, nullptr, m, g->B, m, &g->d_sq1, true, p + n);
+  if (s == RFD_OK) s = rfd::wide_create(pd, m, g->B, m, nullptr, m, &g->d_sq2);
+  if (s == RFD_OK) s = rfd::wide_create(pc, m, nullptr, m, g->B, n, &g->c_t, true);
   if (s == RFD_OK) s = rfd::wide_create(pd, n, g->B, n, g->B, n, &g->d_cross);
   if (s != RFD_OK) {
     free_gw(g);

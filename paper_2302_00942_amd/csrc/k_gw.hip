@@ -1,9 +1,9 @@
 // Element-wise and transpose kernels of the Gromov-Wasserstein loss matrix
 // (App. "Fast Computation of Tensor Products", Alg. 2). The operator actions
-// themselves are resident RFD integrations; these kernels form the marginals
-// p = T 1 and q = T^T 1, the diagonal field diag(p), the transposes between
-// the actions, and the final
-//   L[i][j] = v1[i] + v2[j] - 2 V[j][i].
+// themselves are wide-field RFD integrations; these kernels form the
+// marginals p = T 1 and q = T^T 1 and the final
+//   L[i][j] = v1[i] + v2[j] - 2 V[j][i],
+// and transpose the cross term for the entry point that returns it.
 // All matrices are row-major FP32 with explicit row pitches. A last small
 // kernel re-points the slice descriptors of a wide-field integration.
 #include <hip/hip_runtime.h>
@@ -76,15 +76,6 @@ __global__ __launch_bounds__(256) void k_gw_col_finish(const double* __restrict_
   if (g == 0 && j < m) q[j] = (float)(((red[0][c] + red[1][c]) + red[2][c]) + red[3][c]);
 }
 
-// out (n x n) = diag(v).
-__global__ __launch_bounds__(256) void k_gw_diag_field(const float* __restrict__ v, int n, float* __restrict__ out,
-                                                       int64_t ld) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)n * n) return;
-  const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
-  out[(int64_t)i * ld + j] = i == j ? v[i] : 0.f;
-}
-
 // out (cols x rows) = in^T (rows x cols), through a padded 32 x 32 LDS tile.
 __global__ __launch_bounds__(256) void k_gw_transpose(const float* __restrict__ in, int64_t ldi, int rows, int cols,
                                                       float* __restrict__ out, int64_t ldo) {
@@ -149,12 +140,6 @@ hipError_t launch_gw_margins(const float* T, int64_t ldT, int n, int m, float* p
   hipLaunchKernelGGL(k_gw_row_sums, dim3(n), dim3(256), 0, st, T, ldT, m, p);
   hipLaunchKernelGGL(k_gw_col_parts, dim3((m + 255) / 256, nb), dim3(256), 0, st, T, ldT, n, m, scratch);
   hipLaunchKernelGGL(k_gw_col_finish, dim3((m + 63) / 64), dim3(256), 0, st, scratch, nb, m, q);
-  return hipGetLastError();
-}
-
-hipError_t launch_gw_diag_field(const float* v, int n, float* out, int64_t ld, hipStream_t st) {
-  const int64_t e = (int64_t)n * n;
-  hipLaunchKernelGGL(k_gw_diag_field, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, v, n, out, ld);
   return hipGetLastError();
 }
 

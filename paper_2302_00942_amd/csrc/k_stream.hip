@@ -722,10 +722,74 @@ __device__ __forceinline__ void load_residual(const float* F, int64_t ldF, int d
   }
 }
 
+// Residual of a diagonal field diag(w) (square, sliced): the slice's channel
+// c is column col0 + c, so point p has w[c] (w already offset by col0) where
+// p == col0 + c and zero elsewhere; same lane layout as load_residual.
 template <int DB>
+__device__ __forceinline__ void diag_residual(const float* w, int64_t col0, int d, int64_t N, int64_t tile, int g,
+                                              int pl, float (&fres)[DB][4]) {
+  if constexpr (kRowPieces<DB>) {
+    const int64_t pr = tile * 16 + pl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * g + q;
+      fres[0][q] = (c < d && pr < N && pr == col0 + c) ? gldf(w + c) : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int cb = 0; cb < DB; ++cb) {
+      const int c = cb * 16 + pl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t pr = tile * 16 + 4 * g + q;
+        fres[cb][q] = (c < d && pr < N && pr == col0 + c) ? gldf(w + c) : 0.f;
+      }
+    }
+  }
+}
+
+// TOUT: the result is stored transposed, out[c * ldO + p] (channel-major),
+// for fields whose transpose is the next operand; the direct layout then
+// writes four consecutive points of one channel per lane.
+template <int DB, bool TOUT>
 __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* __restrict__ rowscale, int d,
                                           int64_t N, int64_t tile, int g, int pl, bool vec,
                                           const float (&fres)[DB][4], const f32x4 (&acc)[DB]) {
+  if constexpr (TOUT) {
+    if constexpr (kRowPieces<DB>) {
+      const int64_t pr = tile * 16 + pl;
+      if (pr >= N) return;
+      const float sc = rowscale ? gldf(rowscale + pr) : 1.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = 4 * g + q;
+        const float v = fres[0][q] + acc[0][q];
+        if (c < d) gstf(out + (int64_t)c * ldO + pr, rowscale ? sc * v : v);
+      }
+    } else {
+      const int64_t p0 = tile * 16 + 4 * g;
+      const bool vt = ((ldO & 3) == 0) && (((uintptr_t)out & 15) == 0) && p0 + 3 < N;
+#pragma unroll
+      for (int cb = 0; cb < DB; ++cb) {
+        const int c = cb * 16 + pl;
+        if (c >= d) continue;
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          v[q] = fres[cb][q] + acc[cb][q];
+          if (rowscale && p0 + q < N) v[q] *= gldf(rowscale + p0 + q);
+        }
+        if (vt) {
+          gst4(out + (int64_t)c * ldO + p0, float4{v[0], v[1], v[2], v[3]});
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (p0 + q < N) gstf(out + (int64_t)c * ldO + p0 + q, v[q]);
+        }
+      }
+    }
+    return;
+  }
   if constexpr (kRowPieces<DB>) {
     const int64_t pr = tile * 16 + pl;
     if (pr >= N) return;
@@ -768,7 +832,10 @@ __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* 
 // over the waves of the grid.
 // Point tiles [t_first + wave, t_end) with stride t_step are processed by the
 // four waves of the workgroup.
-template <int M, int PREC, int DB>
+// DIAG: the field is diag(w) of a square sliced field (see diag_residual):
+// F is the slice's part of w and ldF its first column; nothing of the n x n
+// field is read.
+template <int M, int PREC, int DB, bool TOUT = false, bool DIAG = false>
 __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t N, const float4* __restrict__ om,
                                             const float* __restrict__ G32, const __bf16* __restrict__ Gt16, int d,
                                             const float* F, int64_t ldF, float* out, int64_t ldO,
@@ -820,7 +887,10 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
     const int64_t p = tile * 16 + pl;
     xn = yn = zn = 0.f;
     if (p < N) { xn = gldf(X + p * 3); yn = gldf(X + p * 3 + 1); zn = gldf(X + p * 3 + 2); }
-    load_residual(F, ldF, d, N, tile, g, pl, vec, fn);
+    if constexpr (DIAG)
+      diag_residual(F, ldF, d, N, tile, g, pl, fn);
+    else
+      load_residual(F, ldF, d, N, tile, g, pl, vec, fn);
   };
   if (t_first + (tid >> 6) < ntiles) load_tile(t_first + (tid >> 6));
 
@@ -860,7 +930,7 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
           }
         }
       }
-      store_out(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc);
+      store_out<DB, TOUT>(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc);
     }
   } else {
     for (int64_t tile = t_first + (tid >> 6); tile < ntiles; tile += wstride) {
@@ -893,7 +963,7 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
           }
         }
       }
-      store_out(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc);
+      store_out<DB, TOUT>(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc);
     }
   }
 }
@@ -911,7 +981,7 @@ __global__ __launch_bounds__(256) void k_expand(const float* __restrict__ X, int
 // Batched expansion: one workgroup per (cloud, first tile) work item, each
 // covering `tpi` tiles of 16 points (a launch-geometry choice: any tpi gives
 // the same result).
-template <int M, int PREC, int DB>
+template <int M, int PREC, int DB, bool TOUT, bool DIAG>
 __global__ __launch_bounds__(256) void k_expand_batch(const CloudDesc* __restrict__ cl, const int2* __restrict__ work,
                                                       int tpi) {
   const int2 wi = work[blockIdx.x];
@@ -919,7 +989,8 @@ __global__ __launch_bounds__(256) void k_expand_batch(const CloudDesc* __restric
   const int64_t ntiles = (c.N + 15) / 16;
   int64_t t_end = (int64_t)wi.y + tpi;
   if (t_end > ntiles) t_end = ntiles;
-  expand_body<M, PREC, DB>(c.X, c.N, c.om, c.G32, c.Gt16, c.d, c.F, c.ldF, c.out, c.ldO, nullptr, wi.y, t_end, 4);
+  expand_body<M, PREC, DB, TOUT, DIAG>(c.X, c.N, c.om, c.G32, c.Gt16, c.d, c.F, c.ldF, c.out, c.ldO, nullptr, wi.y,
+                                       t_end, 4);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1072,6 +1143,39 @@ __global__ __launch_bounds__(256) void k_wide_diag(const CloudDesc* __restrict__
   gstf(v + i, (float)((double)gldf(c.F + i * c.ldF + ch) + s));
 }
 
+// B^T diag(w) of a square sliced field, formed directly: slice s's H0 column
+// c is phi(x_i) w_i for i = 64 s + c (unscaled device-order features, the
+// product in FP64). One thread per point; no n x n field is read.
+template <int M>
+__global__ __launch_bounds__(256) void k_wide_diag_h0(const CloudDesc* __restrict__ cl, int64_t N,
+                                                      const float* __restrict__ w) {
+  __shared__ float4 oms[M / 2];
+  for (int k = threadIdx.x; k < M / 2; k += 256) oms[k] = gld4((const float*)(cl[0].om + k));
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const CloudDesc& c = cl[i / 64];
+  const int ch = (int)(i % 64);
+  const float x = gldf(c.X + 3 * i), y = gldf(c.X + 3 * i + 1), z = gldf(c.X + 3 * i + 2);
+  const double wi = (double)gldf(w + i);
+#pragma unroll 4
+  for (int k = 0; k < M / 2; ++k) {
+    float sn, cs;
+    phase_sincos(oms[k], x, y, z, sn, cs);
+    gstd(c.H0 + (size_t)(2 * k) * c.d + ch, (double)cs * wi);
+    gstd(c.H0 + (size_t)(2 * k + 1) * c.d + ch, (double)sn * wi);
+  }
+}
+
+hipError_t launch_wide_diag_h0(int M, const CloudDesc* dcl, int64_t N, const float* w, hipStream_t st) {
+  const dim3 grid((unsigned)((N + 255) / 256));
+  if (M == 64) hipLaunchKernelGGL(k_wide_diag_h0<64>, grid, dim3(256), 0, st, dcl, N, w);
+  else if (M == 128) hipLaunchKernelGGL(k_wide_diag_h0<128>, grid, dim3(256), 0, st, dcl, N, w);
+  else if (M == 256) hipLaunchKernelGGL(k_wide_diag_h0<256>, grid, dim3(256), 0, st, dcl, N, w);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_wide_diag(int M, const CloudDesc* dcl, int64_t N, float* v, hipStream_t st) {
   const dim3 grid((unsigned)((N + 255) / 256));
   if (M == 64) hipLaunchKernelGGL(k_wide_diag<64>, grid, dim3(256), 0, st, dcl, N, v);
@@ -1147,18 +1251,18 @@ hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hi
   return hipGetLastError();
 }
 
-template <int M, int PREC>
+template <int M, int PREC, bool TOUT, bool DIAG>
 static hipError_t expand_batch_db(int DB, int nwork, const CloudDesc* dcl, const int2* dwork, int tpi,
                                   hipStream_t st) {
   switch (DB) {
     case 1:
-      hipLaunchKernelGGL((k_expand_batch<M, PREC, 1>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 1, TOUT, DIAG>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
       break;
     case 2:
-      hipLaunchKernelGGL((k_expand_batch<M, PREC, 2>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 2, TOUT, DIAG>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
       break;
     case 4:
-      hipLaunchKernelGGL((k_expand_batch<M, PREC, 4>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 4, TOUT, DIAG>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1166,12 +1270,21 @@ static hipError_t expand_batch_db(int DB, int nwork, const CloudDesc* dcl, const
   return hipGetLastError();
 }
 
+template <int M, int PREC>
+static hipError_t expand_batch_t(bool tout, bool diag, int DB, int nwork, const CloudDesc* dcl, const int2* dwork,
+                                 int tpi, hipStream_t st) {
+  if (diag)  // diagonal fields are only used with the transposed store
+    return tout ? expand_batch_db<M, PREC, true, true>(DB, nwork, dcl, dwork, tpi, st) : hipErrorInvalidValue;
+  return tout ? expand_batch_db<M, PREC, true, false>(DB, nwork, dcl, dwork, tpi, st)
+              : expand_batch_db<M, PREC, false, false>(DB, nwork, dcl, dwork, tpi, st);
+}
+
 hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, int tpi,
-                               hipStream_t st) {
+                               hipStream_t st, bool tout, bool diag) {
   ProfileScope prof(kKExpandBatch, st);
-  if (M == 64) return prec ? expand_batch_db<64, 1>(DB, nwork, dcl, dwork, tpi, st) : expand_batch_db<64, 0>(DB, nwork, dcl, dwork, tpi, st);
-  if (M == 128) return prec ? expand_batch_db<128, 1>(DB, nwork, dcl, dwork, tpi, st) : expand_batch_db<128, 0>(DB, nwork, dcl, dwork, tpi, st);
-  if (M == 256) return prec ? expand_batch_db<256, 1>(DB, nwork, dcl, dwork, tpi, st) : expand_batch_db<256, 0>(DB, nwork, dcl, dwork, tpi, st);
+  if (M == 64) return prec ? expand_batch_t<64, 1>(tout, diag, DB, nwork, dcl, dwork, tpi, st) : expand_batch_t<64, 0>(tout, diag, DB, nwork, dcl, dwork, tpi, st);
+  if (M == 128) return prec ? expand_batch_t<128, 1>(tout, diag, DB, nwork, dcl, dwork, tpi, st) : expand_batch_t<128, 0>(tout, diag, DB, nwork, dcl, dwork, tpi, st);
+  if (M == 256) return prec ? expand_batch_t<256, 1>(tout, diag, DB, nwork, dcl, dwork, tpi, st) : expand_batch_t<256, 0>(tout, diag, DB, nwork, dcl, dwork, tpi, st);
   return hipErrorInvalidValue;
 }
 

@@ -144,8 +144,11 @@ hipError_t launch_bta_batch(int M, int prec, int DB, bool gram, const CloudDesc*
 hipError_t launch_reduce_batch(int M, int DB, bool gram, const CloudDesc* dcl, int ncl, int max_parts, hipStream_t st);
 int fused_reduce_max_parts();  // most partials the one-launch reduction takes
 hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hipStream_t st);
+// tout: each descriptor's result is stored transposed (out[c * ldO + p]).
+// diag (with tout only): each descriptor's field is a slice of diag(w), F
+// pointing at the slice's part of w and ldF holding its first column.
 hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, int tpi,
-                               hipStream_t st);
+                               hipStream_t st, bool tout = false, bool diag = false);
 hipError_t launch_phi1_batch_dev(int M, int n, const void* dev_args, hipStream_t st);
 void phi1_fill_args(rfd_plan_s* p, void* args_out);  // writes one Phi1Args
 int dblocks(int d);
@@ -155,7 +158,6 @@ int dblocks(int d);
 hipError_t launch_gw_margins(const float* T, int64_t ldT, int n, int m, float* p, float* q, double* scratch,
                              hipStream_t st);
 size_t gw_margin_scratch_doubles(int n, int m);
-hipError_t launch_gw_diag_field(const float* v, int n, float* out, int64_t ld, hipStream_t st);
 hipError_t launch_gw_transpose(const float* in, int64_t ldi, int rows, int cols, float* out, int64_t ldo,
                                hipStream_t st);
 hipError_t launch_gw_combine(const float* v1, const float* v2, const float* V, int64_t ldV, int n, int m, float* L,
@@ -167,19 +169,30 @@ struct WideField {
   rfd_plan_s* p = nullptr;
   int64_t N = 0;
   int d = 0, nsl = 0, DB = 4, nparts = 1, tpi = 64;
+  bool tout = false;         // result stored transposed (d x N)
+  const float* diag = nullptr;  // the field is diag(diag) (square; F unused)
   CloudDesc* dcl = nullptr;  // one descriptor per slice (device)
   int2* dwork_bta = nullptr;
   int2* dwork_exp = nullptr;
   int nwork_bta = 0, nwork_exp = 0;
   void* arena = nullptr;     // per-slice partials, H0, G32, Gt16
 };
-rfd_status wide_create(rfd_plan_s* p, int d, const float* F, int64_t ldF, float* out, int64_t ldO, WideField* w);
+// trans_out: the result is written transposed, out (d x N, leading dimension
+// ldO >= N) = (F + A S B^T F)^T; out must not overlap F.
+// diag_of (square fields, with trans_out): the field is diag(diag_of), never
+// materialised; F and ldF are ignored.
+rfd_status wide_create(rfd_plan_s* p, int d, const float* F, int64_t ldF, float* out, int64_t ldO, WideField* w,
+                       bool trans_out = false, const float* diag_of = nullptr);
 hipError_t wide_set_input(WideField* w, const float* F, int64_t ldF, hipStream_t st);
 hipError_t wide_enqueue(const WideField* w, hipStream_t st);  // needs the plan's S and T (ensure_core)
 // Square fields (d = N) only: v = the diagonal of the integrated field, with
 // no other element formed.
 hipError_t wide_diag_enqueue(const WideField* w, float* v, hipStream_t st);
 hipError_t launch_wide_diag(int M, const CloudDesc* dcl, int64_t N, float* v, hipStream_t st);  // k_stream.hip
+// Square fields diag(w) only (a wide field created with diag_of set): the
+// integration of diag(w), stored transposed, from B^T diag(w) formed directly.
+hipError_t wide_diag_field_enqueue(const WideField* w, hipStream_t st);
+hipError_t launch_wide_diag_h0(int M, const CloudDesc* dcl, int64_t N, const float* w, hipStream_t st);
 size_t wide_device_bytes(const WideField* w);
 void wide_free(WideField* w);
 hipError_t launch_wide_patch(CloudDesc* dcl, int nsl, const float* F, int64_t ldF, int W, hipStream_t st);  // k_gw.hip

@@ -29,9 +29,11 @@ void wide_free(WideField* w) {
   *w = WideField();
 }
 
-rfd_status wide_create(rfd_plan_s* p, int d, const float* F, int64_t ldF, float* out, int64_t ldO, WideField* w) {
+rfd_status wide_create(rfd_plan_s* p, int d, const float* F, int64_t ldF, float* out, int64_t ldO, WideField* w,
+                       bool trans_out, const float* diag_of) {
   *w = WideField();
   if (p->N < 1 || d < 1) return RFD_ERR_INVALID_ARG;
+  if (diag_of && (d != p->N || !trans_out)) return RFD_ERR_INVALID_ARG;
   const int M = p->dev_m, prec = p->params.precision;
   const int64_t N = p->N;
   const int nsl = (d + kWideSlice - 1) / kWideSlice;
@@ -59,9 +61,14 @@ rfd_status wide_create(rfd_plan_s* p, int d, const float* F, int64_t ldF, float*
     c.Xcopy = nullptr;
     c.N = N;
     c.om = p->dev.om;
-    c.F = F ? F + (size_t)s * kWideSlice : nullptr;
-    c.ldF = ldF;
-    c.out = out + (size_t)s * kWideSlice;
+    if (diag_of) {  // the slice's part of the diagonal, and its first column
+      c.F = diag_of + (size_t)s * kWideSlice;
+      c.ldF = (int64_t)s * kWideSlice;
+    } else {
+      c.F = F ? F + (size_t)s * kWideSlice : nullptr;
+      c.ldF = ldF;
+    }
+    c.out = out ? out + (size_t)s * kWideSlice * (trans_out ? (size_t)ldO : 1) : nullptr;
     c.ldO = ldO;
     c.partials = (float*)a;
     c.lvl = nullptr;  // nparts <= fused_reduce_max_parts(): one-launch reduction
@@ -83,6 +90,8 @@ rfd_status wide_create(rfd_plan_s* p, int d, const float* F, int64_t ldF, float*
   w->DB = DB;
   w->nparts = nparts;
   w->tpi = tpi;
+  w->tout = trans_out;
+  w->diag = diag_of;
   w->nwork_bta = (int)wb.size();
   w->nwork_exp = (int)we.size();
   bool ok = hipMalloc((void**)&w->dcl, sizeof(CloudDesc) * nsl) == hipSuccess &&
@@ -123,7 +132,17 @@ static hipError_t wide_core(const WideField* w, hipStream_t st) {
 hipError_t wide_enqueue(const WideField* w, hipStream_t st) {
   hipError_t e = wide_core(w, st);
   if (e == hipSuccess)
-    e = launch_expand_batch(w->p->dev_m, w->p->params.precision, w->DB, w->dcl, w->dwork_exp, w->nwork_exp, w->tpi, st);
+    e = launch_expand_batch(w->p->dev_m, w->p->params.precision, w->DB, w->dcl, w->dwork_exp, w->nwork_exp, w->tpi, st,
+                            w->tout);
+  return e;
+}
+
+hipError_t wide_diag_field_enqueue(const WideField* w, hipStream_t st) {
+  if (!w->diag) return hipErrorInvalidValue;
+  const int M = w->p->dev_m, prec = w->p->params.precision;
+  hipError_t e = launch_wide_diag_h0(M, w->dcl, w->N, w->diag, st);
+  if (e == hipSuccess) e = launch_gcore_batch(M, std::min(w->d, kWideSlice), w->dcl, w->nsl, st);
+  if (e == hipSuccess) e = launch_expand_batch(M, prec, w->DB, w->dcl, w->dwork_exp, w->nwork_exp, w->tpi, st, true, true);
   return e;
 }
 
