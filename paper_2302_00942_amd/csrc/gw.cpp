@@ -28,8 +28,9 @@ struct rfd_gw_s {
   double* colpart = nullptr;  // column-sum partials of the coupling
   // wide integrations: C on diag(p) with the result stored transposed in B,
   // then C on B forming only the diagonal (likewise D); C on T stored
-  // transposed in B (m x n), D on B in place
-  rfd::WideField c_sq1, c_sq2, d_sq1, d_sq2, c_t, d_cross;
+  // transposed in B (m x n); D on B either in place (the terms) or stored
+  // transposed into L with the final combination as its epilogue (the loss)
+  rfd::WideField c_sq1, c_sq2, d_sq1, d_sq2, c_t, d_cross, d_loss;
 };
 
 namespace {
@@ -48,7 +49,8 @@ namespace {
 constexpr int kMaxGwPoints = 32768;  // largest n or m (one max(n, m)^2 float buffer: 4 GiB)
 
 void free_gw(rfd_gw_s* g) {
-  for (rfd::WideField* w : {&g->c_sq1, &g->c_sq2, &g->d_sq1, &g->d_sq2, &g->c_t, &g->d_cross}) rfd::wide_free(w);
+  for (rfd::WideField* w : {&g->c_sq1, &g->c_sq2, &g->d_sq1, &g->d_sq2, &g->c_t, &g->d_cross, &g->d_loss})
+    rfd::wide_free(w);
   void* ptrs[] = {g->B, g->vec, g->colpart};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -65,7 +67,7 @@ rfd_status hadamard_square(const rfd::WideField& W1, const rfd::WideField& W2, f
   return RFD_OK;
 }
 
-// p, q, v1, v2 into g->vec and w3^T = FM_D(FM_C(T)^T) (m x n) into g->B.
+// p, q, v1, v2 into g->vec and FM_C(T)^T (m x n) into g->B.
 rfd_status enqueue_terms(rfd_gw_s* g, const float* T, int64_t ldT, hipStream_t st) {
   if (!T || ldT < g->m) return RFD_ERR_INVALID_ARG;
   if (g->pc->N != g->n || g->pd->N != g->m) return RFD_ERR_INVALID_ARG;  // a cloud changed size
@@ -76,10 +78,9 @@ rfd_status enqueue_terms(rfd_gw_s* g, const float* T, int64_t ldT, hipStream_t s
   HIPCK(rfd::launch_gw_margins(T, ldT, n, m, p, q, g->colpart, st));
   RFDCK(hadamard_square(g->c_sq1, g->c_sq2, v1, st));
   RFDCK(hadamard_square(g->d_sq1, g->d_sq2, v2, st));
-  // B = FM_C(T)^T (m x n), then B <- FM_D(B)
+  // B = FM_C(T)^T (m x n)
   HIPCK(rfd::wide_set_input(&g->c_t, T, ldT, st));
   HIPCK(rfd::wide_enqueue(&g->c_t, st));
-  HIPCK(rfd::wide_enqueue(&g->d_cross, st));
   return RFD_OK;
 }
 
@@ -119,6 +120,7 @@ rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out) {
   if (s == RFD_OK) s = rfd::wide_create(pd, m, g->B, m, nullptr, m, &g->d_sq2);
   if (s == RFD_OK) s = rfd::wide_create(pc, m, nullptr, m, g->B, n, &g->c_t, true);
   if (s == RFD_OK) s = rfd::wide_create(pd, n, g->B, n, g->B, n, &g->d_cross);
+  if (s == RFD_OK) s = rfd::wide_create(pd, n, g->B, n, nullptr, m, &g->d_loss, true);
   if (s != RFD_OK) {
     free_gw(g);
     return s;
@@ -131,8 +133,10 @@ rfd_status rfd_gw_loss(rfd_gw_t g, const float* T, int64_t ldT, float* L, int64_
   if (!g || !L || ldL < g->m) return RFD_ERR_INVALID_ARG;
   const hipStream_t st = (hipStream_t)stream;
   RFDCK(enqueue_terms(g, T, ldT, st));
+  // L = (FM_D(B))^T combined as fma(-2, ., v1[i] + v2[j]) in the store
   const float *v1 = g->vec + g->n + g->m, *v2 = v1 + g->n;
-  HIPCK(rfd::launch_gw_combine(v1, v2, g->B, g->n, g->n, g->m, L, ldL, st));
+  HIPCK(rfd::wide_set_output_epilogue(&g->d_loss, L, ldL, v1, v2, st));
+  HIPCK(rfd::wide_enqueue(&g->d_loss, st));
   return RFD_OK;
 }
 
@@ -141,6 +145,7 @@ rfd_status rfd_gw_terms(rfd_gw_t g, const float* T, int64_t ldT, float* v1, floa
   if (!g || !v1 || !v2 || !W3 || ldW < g->m) return RFD_ERR_INVALID_ARG;
   const hipStream_t st = (hipStream_t)stream;
   RFDCK(enqueue_terms(g, T, ldT, st));
+  HIPCK(rfd::wide_enqueue(&g->d_cross, st));  // B <- FM_D(B) = W3^T
   const int n = g->n, m = g->m;
   const float* dv1 = g->vec + n + m;
   HIPCK(hipMemcpyAsync(v1, dv1, sizeof(float) * n, hipMemcpyDeviceToDevice, st));

@@ -1,11 +1,11 @@
 // Element-wise and transpose kernels of the Gromov-Wasserstein loss matrix
 // (App. "Fast Computation of Tensor Products", Alg. 2). The operator actions
-// themselves are wide-field RFD integrations; these kernels form the
-// marginals p = T 1 and q = T^T 1 and the final
-//   L[i][j] = v1[i] + v2[j] - 2 V[j][i],
-// and transpose the cross term for the entry point that returns it.
-// All matrices are row-major FP32 with explicit row pitches. A last small
-// kernel re-points the slice descriptors of a wide-field integration.
+// themselves are wide-field RFD integrations (the final combination
+// L[i][j] = v1[i] + v2[j] - 2 W3[i][j] is the epilogue of the last one's
+// store); these kernels form the marginals p = T 1 and q = T^T 1 and
+// transpose the cross term for the entry point that returns it.
+// All matrices are row-major FP32 with explicit row pitches. Two small
+// kernels re-point the slice descriptors of a wide-field integration.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -31,38 +31,48 @@ __device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
   ty = t / gx;
 }
 
-// p[i] = sum_j T[i][j]: one workgroup per row, FP64 lane sums over a fixed
-// stride, then a fixed tree over the workgroup.
-__global__ __launch_bounds__(256) void k_gw_row_sums(const float* __restrict__ T, int64_t ldT, int m,
-                                                     float* __restrict__ p) {
-  __shared__ double red[256];
-  const int i = blockIdx.x, t = threadIdx.x;
-  double s = 0.0;
-  for (int j = t; j < m; j += 256) s += (double)T[(int64_t)i * ldT + j];
-  red[t] = s;
-  __syncthreads();
-  for (int o = 128; o >= 1; o >>= 1) {
-    if (t < o) red[t] += red[t + o];
-    __syncthreads();
+// Marginals in one pass over T with a fixed summation order. A workgroup
+// takes a tile of kMargRows rows x 256 columns, one column per thread:
+// colpart[b][j] sums the tile's rows of column j in order, and
+// rowpart[c][i] sums row i over the tile's 256 columns (a butterfly in each
+// wave, read from lane 0, then the four waves in order), all in FP64 ...
+constexpr int kMargRows = 32;
+__global__ __launch_bounds__(256) void k_gw_margin_parts(const float* __restrict__ T, int64_t ldT, int n, int m,
+                                                         double* __restrict__ colpart, double* __restrict__ rowpart) {
+  __shared__ double red[4][kMargRows];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int j = blockIdx.x * 256 + t, r0 = blockIdx.y * kMargRows;
+  float v[kMargRows];
+#pragma unroll
+  for (int r = 0; r < kMargRows; ++r) v[r] = (j < m && r0 + r < n) ? T[(int64_t)(r0 + r) * ldT + j] : 0.f;
+  double cs = 0.0;
+#pragma unroll
+  for (int r = 0; r < kMargRows; ++r) cs += (double)v[r];
+  if (j < m) colpart[(size_t)blockIdx.y * m + j] = cs;
+#pragma unroll
+  for (int r = 0; r < kMargRows; ++r) {
+    double s = (double)v[r];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) red[w][r] = s;
   }
-  if (t == 0) p[i] = (float)red[0];
+  __syncthreads();
+  if (t < kMargRows && r0 + t < n)
+    rowpart[(size_t)blockIdx.x * n + r0 + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
 }
 
-// Column sums in two passes with a fixed order: block b of kColRows rows
-// gives part[b][j] (rows in order, coalesced over j) ...
-constexpr int kColRows = 64;
-__global__ __launch_bounds__(256) void k_gw_col_parts(const float* __restrict__ T, int64_t ldT, int n, int m,
-                                                      double* __restrict__ part) {
-  const int j = blockIdx.x * 256 + threadIdx.x, b = blockIdx.y;
-  if (j >= m) return;
-  const int r0 = b * kColRows, r1 = min(n, r0 + kColRows);
+// ... then p[i] = sum_c rowpart[c][i] in order, one thread per row, and
+// q[j] = sum_b colpart[b][j]: 64 columns per workgroup, four row-block groups
+// per column summed in order, the four group sums added in order.
+__global__ __launch_bounds__(256) void k_gw_row_finish(const double* __restrict__ rowpart, int nc, int n,
+                                                       float* __restrict__ p) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
   double s = 0.0;
-  for (int r = r0; r < r1; ++r) s += (double)T[(int64_t)r * ldT + j];
-  part[(size_t)b * m + j] = s;
+  for (int c = 0; c < nc; ++c) s += rowpart[(size_t)c * n + i];
+  p[i] = (float)s;
 }
 
-// ... then q[j] = sum_b part[b][j]: 64 columns per workgroup, four row-block
-// groups per column summed in order, the four group sums added in order.
 __global__ __launch_bounds__(256) void k_gw_col_finish(const double* __restrict__ part, int nb, int m,
                                                        float* __restrict__ q) {
   __shared__ double red[4][64];
@@ -95,27 +105,6 @@ __global__ __launch_bounds__(256) void k_gw_transpose(const float* __restrict__ 
   }
 }
 
-// L[i][j] = v1[i] + v2[j] - 2 V[j][i] for V (m x n), through a padded tile;
-// rounded as fma(-2, V[j][i], v1[i] + v2[j]).
-__global__ __launch_bounds__(256) void k_gw_combine(const float* __restrict__ v1, const float* __restrict__ v2,
-                                                    const float* __restrict__ V, int64_t ldV, int n, int m,
-                                                    float* __restrict__ L, int64_t ldL) {
-  __shared__ float tile[kTile][kTile + 1];
-  int bx, by;
-  xcd_tile(bx, by);
-  const int j0 = by * kTile, i0 = bx * kTile;  // V rows j, columns i
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int k = ty; k < kTile; k += 8) {
-    const int j = j0 + k, i = i0 + tx;
-    if (j < m && i < n) tile[k][tx] = V[(int64_t)j * ldV + i];
-  }
-  __syncthreads();
-  for (int k = ty; k < kTile; k += 8) {
-    const int i = i0 + k, j = j0 + tx;
-    if (i < n && j < m) L[(int64_t)i * ldL + j] = __builtin_fmaf(-2.f, tile[tx][k], v1[i] + v2[j]);
-  }
-}
-
 // Re-points the slices of a wide field: descriptor i reads F + i W.
 __global__ __launch_bounds__(64) void k_wide_patch(CloudDesc* __restrict__ dcl, int nsl, const float* F, int64_t ldF,
                                                    int W) {
@@ -125,21 +114,43 @@ __global__ __launch_bounds__(64) void k_wide_patch(CloudDesc* __restrict__ dcl, 
   dcl[i].ldF = ldF;
 }
 
+// Re-points the transposed outputs of a wide field and sets its epilogue:
+// descriptor i writes rows [i W, i W + W) of out and reads a + i W, b.
+__global__ __launch_bounds__(64) void k_wide_patch_out(CloudDesc* __restrict__ dcl, int nsl, float* out, int64_t ldO,
+                                                       const float* a, const float* b, int W) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= nsl) return;
+  dcl[i].out = out + (size_t)i * W * ldO;
+  dcl[i].ldO = ldO;
+  dcl[i].epi_a = a + (size_t)i * W;
+  dcl[i].epi_b = b;
+}
+
 }  // namespace
+
+hipError_t launch_wide_patch_out(CloudDesc* dcl, int nsl, float* out, int64_t ldO, const float* a, const float* b,
+                                 int W, hipStream_t st) {
+  hipLaunchKernelGGL(k_wide_patch_out, dim3((nsl + 63) / 64), dim3(64), 0, st, dcl, nsl, out, ldO, a, b, W);
+  return hipGetLastError();
+}
 
 hipError_t launch_wide_patch(CloudDesc* dcl, int nsl, const float* F, int64_t ldF, int W, hipStream_t st) {
   hipLaunchKernelGGL(k_wide_patch, dim3((nsl + 63) / 64), dim3(64), 0, st, dcl, nsl, F, ldF, W);
   return hipGetLastError();
 }
 
-size_t gw_margin_scratch_doubles(int n, int m) { return (size_t)((n + kColRows - 1) / kColRows) * m; }
+size_t gw_margin_scratch_doubles(int n, int m) {
+  return (size_t)((n + kMargRows - 1) / kMargRows) * m + (size_t)((m + 255) / 256) * n;
+}
 
 hipError_t launch_gw_margins(const float* T, int64_t ldT, int n, int m, float* p, float* q, double* scratch,
                              hipStream_t st) {
-  const int nb = (n + kColRows - 1) / kColRows;
-  hipLaunchKernelGGL(k_gw_row_sums, dim3(n), dim3(256), 0, st, T, ldT, m, p);
-  hipLaunchKernelGGL(k_gw_col_parts, dim3((m + 255) / 256, nb), dim3(256), 0, st, T, ldT, n, m, scratch);
-  hipLaunchKernelGGL(k_gw_col_finish, dim3((m + 63) / 64), dim3(256), 0, st, scratch, nb, m, q);
+  const int nb = (n + kMargRows - 1) / kMargRows, nc = (m + 255) / 256;
+  double* colpart = scratch;
+  double* rowpart = scratch + (size_t)nb * m;
+  hipLaunchKernelGGL(k_gw_margin_parts, dim3(nc, nb), dim3(256), 0, st, T, ldT, n, m, colpart, rowpart);
+  hipLaunchKernelGGL(k_gw_row_finish, dim3((n + 255) / 256), dim3(256), 0, st, rowpart, nc, n, p);
+  hipLaunchKernelGGL(k_gw_col_finish, dim3((m + 63) / 64), dim3(256), 0, st, colpart, nb, m, q);
   return hipGetLastError();
 }
 
@@ -147,13 +158,6 @@ hipError_t launch_gw_transpose(const float* in, int64_t ldi, int rows, int cols,
                                hipStream_t st) {
   const dim3 grid((cols + kTile - 1) / kTile, (rows + kTile - 1) / kTile);
   hipLaunchKernelGGL(k_gw_transpose, grid, dim3(256), 0, st, in, ldi, rows, cols, out, ldo);
-  return hipGetLastError();
-}
-
-hipError_t launch_gw_combine(const float* v1, const float* v2, const float* V, int64_t ldV, int n, int m, float* L,
-                             int64_t ldL, hipStream_t st) {
-  const dim3 grid((n + kTile - 1) / kTile, (m + kTile - 1) / kTile);
-  hipLaunchKernelGGL(k_gw_combine, grid, dim3(256), 0, st, v1, v2, V, ldV, n, m, L, ldL);
   return hipGetLastError();
 }
 

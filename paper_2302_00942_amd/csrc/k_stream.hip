@@ -751,10 +751,13 @@ __device__ __forceinline__ void diag_residual(const float* w, int64_t col0, int 
 // TOUT: the result is stored transposed, out[c * ldO + p] (channel-major),
 // for fields whose transpose is the next operand; the direct layout then
 // writes four consecutive points of one channel per lane.
-template <int DB, bool TOUT>
+// EPI (with TOUT): the stored value is fma(-2, result, ea[c] + eb[p]).
+template <int DB, bool TOUT, bool EPI = false>
 __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* __restrict__ rowscale, int d,
                                           int64_t N, int64_t tile, int g, int pl, bool vec,
-                                          const float (&fres)[DB][4], const f32x4 (&acc)[DB]) {
+                                          const float (&fres)[DB][4], const f32x4 (&acc)[DB],
+                                          const float* __restrict__ ea = nullptr,
+                                          const float* __restrict__ eb = nullptr) {
   if constexpr (TOUT) {
     if constexpr (kRowPieces<DB>) {
       const int64_t pr = tile * 16 + pl;
@@ -763,8 +766,11 @@ __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* 
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = 4 * g + q;
-        const float v = fres[0][q] + acc[0][q];
-        if (c < d) gstf(out + (int64_t)c * ldO + pr, rowscale ? sc * v : v);
+        if (c >= d) continue;
+        float v = fres[0][q] + acc[0][q];
+        if (rowscale) v = sc * v;
+        if constexpr (EPI) v = __builtin_fmaf(-2.f, v, gldf(ea + c) + gldf(eb + pr));
+        gstf(out + (int64_t)c * ldO + pr, v);
       }
     } else {
       const int64_t p0 = tile * 16 + 4 * g;
@@ -778,6 +784,8 @@ __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* 
         for (int q = 0; q < 4; ++q) {
           v[q] = fres[cb][q] + acc[cb][q];
           if (rowscale && p0 + q < N) v[q] *= gldf(rowscale + p0 + q);
+          if constexpr (EPI)
+            if (p0 + q < N) v[q] = __builtin_fmaf(-2.f, v[q], gldf(ea + c) + gldf(eb + p0 + q));
         }
         if (vt) {
           gst4(out + (int64_t)c * ldO + p0, float4{v[0], v[1], v[2], v[3]});
@@ -835,12 +843,13 @@ __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* 
 // DIAG: the field is diag(w) of a square sliced field (see diag_residual):
 // F is the slice's part of w and ldF its first column; nothing of the n x n
 // field is read.
-template <int M, int PREC, int DB, bool TOUT = false, bool DIAG = false>
+template <int M, int PREC, int DB, bool TOUT = false, bool DIAG = false, bool EPI = false>
 __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t N, const float4* __restrict__ om,
                                             const float* __restrict__ G32, const __bf16* __restrict__ Gt16, int d,
                                             const float* F, int64_t ldF, float* out, int64_t ldO,
                                             const float* __restrict__ rowscale, int64_t t_first, int64_t t_end,
-                                            int64_t t_step) {
+                                            int64_t t_step, const float* __restrict__ ea = nullptr,
+                                            const float* __restrict__ eb = nullptr) {
   constexpr int FQ = M / 2;
   constexpr int GP = M + 8;  // BF16 row pitch of G'^T in LDS: conflict-free 16-byte reads
   __shared__ float4 oms[FQ];
@@ -930,7 +939,7 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
           }
         }
       }
-      store_out<DB, TOUT>(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc);
+      store_out<DB, TOUT, EPI>(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc, ea, eb);
     }
   } else {
     for (int64_t tile = t_first + (tid >> 6); tile < ntiles; tile += wstride) {
@@ -963,7 +972,7 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
           }
         }
       }
-      store_out<DB, TOUT>(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc);
+      store_out<DB, TOUT, EPI>(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc, ea, eb);
     }
   }
 }
@@ -981,7 +990,7 @@ __global__ __launch_bounds__(256) void k_expand(const float* __restrict__ X, int
 // Batched expansion: one workgroup per (cloud, first tile) work item, each
 // covering `tpi` tiles of 16 points (a launch-geometry choice: any tpi gives
 // the same result).
-template <int M, int PREC, int DB, bool TOUT, bool DIAG>
+template <int M, int PREC, int DB, bool TOUT, bool DIAG, bool EPI>
 __global__ __launch_bounds__(256) void k_expand_batch(const CloudDesc* __restrict__ cl, const int2* __restrict__ work,
                                                       int tpi) {
   const int2 wi = work[blockIdx.x];
@@ -989,8 +998,8 @@ __global__ __launch_bounds__(256) void k_expand_batch(const CloudDesc* __restric
   const int64_t ntiles = (c.N + 15) / 16;
   int64_t t_end = (int64_t)wi.y + tpi;
   if (t_end > ntiles) t_end = ntiles;
-  expand_body<M, PREC, DB, TOUT, DIAG>(c.X, c.N, c.om, c.G32, c.Gt16, c.d, c.F, c.ldF, c.out, c.ldO, nullptr, wi.y,
-                                       t_end, 4);
+  expand_body<M, PREC, DB, TOUT, DIAG, EPI>(c.X, c.N, c.om, c.G32, c.Gt16, c.d, c.F, c.ldF, c.out, c.ldO, nullptr,
+                                            wi.y, t_end, 4, c.epi_a, c.epi_b);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1251,18 +1260,18 @@ hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hi
   return hipGetLastError();
 }
 
-template <int M, int PREC, bool TOUT, bool DIAG>
+template <int M, int PREC, bool TOUT, bool DIAG, bool EPI>
 static hipError_t expand_batch_db(int DB, int nwork, const CloudDesc* dcl, const int2* dwork, int tpi,
                                   hipStream_t st) {
   switch (DB) {
     case 1:
-      hipLaunchKernelGGL((k_expand_batch<M, PREC, 1, TOUT, DIAG>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 1, TOUT, DIAG, EPI>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
       break;
     case 2:
-      hipLaunchKernelGGL((k_expand_batch<M, PREC, 2, TOUT, DIAG>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 2, TOUT, DIAG, EPI>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
       break;
     case 4:
-      hipLaunchKernelGGL((k_expand_batch<M, PREC, 4, TOUT, DIAG>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
+      hipLaunchKernelGGL((k_expand_batch<M, PREC, 4, TOUT, DIAG, EPI>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1270,21 +1279,25 @@ static hipError_t expand_batch_db(int DB, int nwork, const CloudDesc* dcl, const
   return hipGetLastError();
 }
 
+// The combinations in use: plain; transposed; transposed from a diagonal
+// field; transposed with the epilogue.
 template <int M, int PREC>
-static hipError_t expand_batch_t(bool tout, bool diag, int DB, int nwork, const CloudDesc* dcl, const int2* dwork,
-                                 int tpi, hipStream_t st) {
-  if (diag)  // diagonal fields are only used with the transposed store
-    return tout ? expand_batch_db<M, PREC, true, true>(DB, nwork, dcl, dwork, tpi, st) : hipErrorInvalidValue;
-  return tout ? expand_batch_db<M, PREC, true, false>(DB, nwork, dcl, dwork, tpi, st)
-              : expand_batch_db<M, PREC, false, false>(DB, nwork, dcl, dwork, tpi, st);
+static hipError_t expand_batch_t(bool tout, bool diag, bool epi, int DB, int nwork, const CloudDesc* dcl,
+                                 const int2* dwork, int tpi, hipStream_t st) {
+  if ((diag || epi) && !tout) return hipErrorInvalidValue;
+  if (diag && epi) return hipErrorInvalidValue;
+  if (diag) return expand_batch_db<M, PREC, true, true, false>(DB, nwork, dcl, dwork, tpi, st);
+  if (epi) return expand_batch_db<M, PREC, true, false, true>(DB, nwork, dcl, dwork, tpi, st);
+  return tout ? expand_batch_db<M, PREC, true, false, false>(DB, nwork, dcl, dwork, tpi, st)
+              : expand_batch_db<M, PREC, false, false, false>(DB, nwork, dcl, dwork, tpi, st);
 }
 
 hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, int tpi,
-                               hipStream_t st, bool tout, bool diag) {
+                               hipStream_t st, bool tout, bool diag, bool epi) {
   ProfileScope prof(kKExpandBatch, st);
-  if (M == 64) return prec ? expand_batch_t<64, 1>(tout, diag, DB, nwork, dcl, dwork, tpi, st) : expand_batch_t<64, 0>(tout, diag, DB, nwork, dcl, dwork, tpi, st);
-  if (M == 128) return prec ? expand_batch_t<128, 1>(tout, diag, DB, nwork, dcl, dwork, tpi, st) : expand_batch_t<128, 0>(tout, diag, DB, nwork, dcl, dwork, tpi, st);
-  if (M == 256) return prec ? expand_batch_t<256, 1>(tout, diag, DB, nwork, dcl, dwork, tpi, st) : expand_batch_t<256, 0>(tout, diag, DB, nwork, dcl, dwork, tpi, st);
+  if (M == 64) return prec ? expand_batch_t<64, 1>(tout, diag, epi, DB, nwork, dcl, dwork, tpi, st) : expand_batch_t<64, 0>(tout, diag, epi, DB, nwork, dcl, dwork, tpi, st);
+  if (M == 128) return prec ? expand_batch_t<128, 1>(tout, diag, epi, DB, nwork, dcl, dwork, tpi, st) : expand_batch_t<128, 0>(tout, diag, epi, DB, nwork, dcl, dwork, tpi, st);
+  if (M == 256) return prec ? expand_batch_t<256, 1>(tout, diag, epi, DB, nwork, dcl, dwork, tpi, st) : expand_batch_t<256, 0>(tout, diag, epi, DB, nwork, dcl, dwork, tpi, st);
   return hipErrorInvalidValue;
 }
 

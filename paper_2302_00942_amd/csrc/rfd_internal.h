@@ -49,6 +49,10 @@ struct CloudDesc {
   int* flag;
   int d;
   int nparts;
+  // optional epilogue of a transposed store: out = fma(-2, result,
+  // epi_a[c] + epi_b[p]) for channel c, point p (null: plain store)
+  const float* epi_a;
+  const float* epi_b;
 };
 
 // Scratch and resident buffers of one plan.
@@ -147,8 +151,9 @@ hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hi
 // tout: each descriptor's result is stored transposed (out[c * ldO + p]).
 // diag (with tout only): each descriptor's field is a slice of diag(w), F
 // pointing at the slice's part of w and ldF holding its first column.
+// epi (with tout only): the descriptors' epi_a / epi_b epilogue.
 hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, int tpi,
-                               hipStream_t st, bool tout = false, bool diag = false);
+                               hipStream_t st, bool tout = false, bool diag = false, bool epi = false);
 hipError_t launch_phi1_batch_dev(int M, int n, const void* dev_args, hipStream_t st);
 void phi1_fill_args(rfd_plan_s* p, void* args_out);  // writes one Phi1Args
 int dblocks(int d);
@@ -160,8 +165,6 @@ hipError_t launch_gw_margins(const float* T, int64_t ldT, int n, int m, float* p
 size_t gw_margin_scratch_doubles(int n, int m);
 hipError_t launch_gw_transpose(const float* in, int64_t ldi, int rows, int cols, float* out, int64_t ldo,
                                hipStream_t st);
-hipError_t launch_gw_combine(const float* v1, const float* v2, const float* V, int64_t ldV, int n, int m, float* L,
-                             int64_t ldL, hipStream_t st);
 // Resident integration of a wide field on one plan, one launch per stage over
 // its 64-channel slices (wide.cpp). Shapes and buffers are fixed at creation;
 // wide_set_input re-points the field (same width) on the stream.
@@ -171,6 +174,7 @@ struct WideField {
   int d = 0, nsl = 0, DB = 4, nparts = 1, tpi = 64;
   bool tout = false;         // result stored transposed (d x N)
   const float* diag = nullptr;  // the field is diag(diag) (square; F unused)
+  bool epi = false;             // transposed store with the epi_a / epi_b epilogue
   CloudDesc* dcl = nullptr;  // one descriptor per slice (device)
   int2* dwork_bta = nullptr;
   int2* dwork_exp = nullptr;
@@ -184,6 +188,10 @@ struct WideField {
 rfd_status wide_create(rfd_plan_s* p, int d, const float* F, int64_t ldF, float* out, int64_t ldO, WideField* w,
                        bool trans_out = false, const float* diag_of = nullptr);
 hipError_t wide_set_input(WideField* w, const float* F, int64_t ldF, hipStream_t st);
+// Transposed-store fields: re-points the output (d x N, leading dimension ldO)
+// and sets the epilogue out = fma(-2, result, a[c] + b[p]) (a, b non-null).
+hipError_t wide_set_output_epilogue(WideField* w, float* out, int64_t ldO, const float* a, const float* b,
+                                    hipStream_t st);
 hipError_t wide_enqueue(const WideField* w, hipStream_t st);  // needs the plan's S and T (ensure_core)
 // Square fields (d = N) only: v = the diagonal of the integrated field, with
 // no other element formed.
@@ -196,6 +204,8 @@ hipError_t launch_wide_diag_h0(int M, const CloudDesc* dcl, int64_t N, const flo
 size_t wide_device_bytes(const WideField* w);
 void wide_free(WideField* w);
 hipError_t launch_wide_patch(CloudDesc* dcl, int nsl, const float* F, int64_t ldF, int W, hipStream_t st);  // k_gw.hip
+hipError_t launch_wide_patch_out(CloudDesc* dcl, int nsl, float* out, int64_t ldO, const float* a, const float* b,
+                                 int W, hipStream_t st);  // k_gw.hip
 // Launch-geometry tuning (autotune.cpp): knobs that change speed, never results.
 enum TuneKnob { kTuneExpandTilesPerWave = 0, kTuneBatchExpandTilesPerItem = 1, kTunePhi1Workgroups = 2,
                 kNumTuneKnobs };

@@ -120,6 +120,13 @@ hipError_t wide_set_input(WideField* w, const float* F, int64_t ldF, hipStream_t
   return launch_wide_patch(w->dcl, w->nsl, F, ldF, kWideSlice, st);
 }
 
+hipError_t wide_set_output_epilogue(WideField* w, float* out, int64_t ldO, const float* a, const float* b,
+                                    hipStream_t st) {
+  if (!w->tout || !a || !b) return hipErrorInvalidValue;
+  w->epi = true;
+  return launch_wide_patch_out(w->dcl, w->nsl, out, ldO, a, b, kWideSlice, st);
+}
+
 // Split-N B^T F of every slice, the reduction and G' = T H0.
 static hipError_t wide_core(const WideField* w, hipStream_t st) {
   const int M = w->p->dev_m, prec = w->p->params.precision;
@@ -133,7 +140,7 @@ hipError_t wide_enqueue(const WideField* w, hipStream_t st) {
   hipError_t e = wide_core(w, st);
   if (e == hipSuccess)
     e = launch_expand_batch(w->p->dev_m, w->p->params.precision, w->DB, w->dcl, w->dwork_exp, w->nwork_exp, w->tpi, st,
-                            w->tout);
+                            w->tout, false, w->epi);
   return e;
 }
 
