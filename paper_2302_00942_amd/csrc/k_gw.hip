@@ -33,32 +33,35 @@ __device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
 
 // Marginals in one pass over T with a fixed summation order. A workgroup
 // takes a tile of kMargRows rows x 256 columns, one column per thread:
-// colpart[b][j] sums the tile's rows of column j in order, and
-// rowpart[c][i] sums row i over the tile's 256 columns (a butterfly in each
-// wave, read from lane 0, then the four waves in order), all in FP64 ...
+// colpart[b][j] sums the tile's rows of column j in order; the tile is also
+// staged in LDS, where eight threads per row sum 32 columns each (every
+// eighth column, in order) and a three-step butterfly (read from the first
+// of the eight) gives
+// rowpart[c][i], the sum of row i over the tile's columns; all in FP64 ...
 constexpr int kMargRows = 32;
 __global__ __launch_bounds__(256) void k_gw_margin_parts(const float* __restrict__ T, int64_t ldT, int n, int m,
                                                          double* __restrict__ colpart, double* __restrict__ rowpart) {
-  __shared__ double red[4][kMargRows];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  __shared__ float tile[kMargRows][256 + 1];
+  const int t = threadIdx.x;
   const int j = blockIdx.x * 256 + t, r0 = blockIdx.y * kMargRows;
   float v[kMargRows];
 #pragma unroll
   for (int r = 0; r < kMargRows; ++r) v[r] = (j < m && r0 + r < n) ? T[(int64_t)(r0 + r) * ldT + j] : 0.f;
   double cs = 0.0;
 #pragma unroll
-  for (int r = 0; r < kMargRows; ++r) cs += (double)v[r];
-  if (j < m) colpart[(size_t)blockIdx.y * m + j] = cs;
-#pragma unroll
   for (int r = 0; r < kMargRows; ++r) {
-    double s = (double)v[r];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) red[w][r] = s;
+    cs += (double)v[r];
+    tile[r][t] = v[r];
   }
+  if (j < m) colpart[(size_t)blockIdx.y * m + j] = cs;
   __syncthreads();
-  if (t < kMargRows && r0 + t < n)
-    rowpart[(size_t)blockIdx.x * n + r0 + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+  const int r = t >> 3, seg = t & 7;
+  double rs = 0.0;
+#pragma unroll 8
+  for (int k = 0; k < 32; ++k) rs += (double)tile[r][seg + 8 * k];
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) rs += __shfl_xor(rs, o);
+  if (seg == 0 && r0 + r < n) rowpart[(size_t)blockIdx.x * n + r0 + r] = rs;
 }
 
 // ... then p[i] = sum_c rowpart[c][i] in order, one thread per row, and

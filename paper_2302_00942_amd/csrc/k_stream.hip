@@ -763,29 +763,40 @@ __device__ __forceinline__ void store_out(float* out, int64_t ldO, const float* 
       const int64_t pr = tile * 16 + pl;
       if (pr >= N) return;
       const float sc = rowscale ? gldf(rowscale + pr) : 1.f;
+      const float ebp = EPI ? gldf(eb + pr) : 0.f;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = 4 * g + q;
         if (c >= d) continue;
         float v = fres[0][q] + acc[0][q];
         if (rowscale) v = sc * v;
-        if constexpr (EPI) v = __builtin_fmaf(-2.f, v, gldf(ea + c) + gldf(eb + pr));
+        if constexpr (EPI) v = __builtin_fmaf(-2.f, v, gldf(ea + c) + ebp);
         gstf(out + (int64_t)c * ldO + pr, v);
       }
     } else {
       const int64_t p0 = tile * 16 + 4 * g;
       const bool vt = ((ldO & 3) == 0) && (((uintptr_t)out & 15) == 0) && p0 + 3 < N;
+      float ebq[4] = {0.f, 0.f, 0.f, 0.f};  // the epilogue's point terms, loaded once per tile
+      if constexpr (EPI) {
+        if (p0 + 3 < N && ((uintptr_t)(eb + p0) & 15) == 0) {
+          const float4 e4 = gld4(eb + p0);
+          ebq[0] = e4.x; ebq[1] = e4.y; ebq[2] = e4.z; ebq[3] = e4.w;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) ebq[q] = p0 + q < N ? gldf(eb + p0 + q) : 0.f;
+        }
+      }
 #pragma unroll
       for (int cb = 0; cb < DB; ++cb) {
         const int c = cb * 16 + pl;
         if (c >= d) continue;
+        const float eac = EPI ? gldf(ea + c) : 0.f;
         float v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           v[q] = fres[cb][q] + acc[cb][q];
           if (rowscale && p0 + q < N) v[q] *= gldf(rowscale + p0 + q);
-          if constexpr (EPI)
-            if (p0 + q < N) v[q] = __builtin_fmaf(-2.f, v[q], gldf(ea + c) + gldf(eb + p0 + q));
+          if constexpr (EPI) v[q] = __builtin_fmaf(-2.f, v[q], eac + ebq[q]);
         }
         if (vt) {
           gst4(out + (int64_t)c * ldO + p0, float4{v[0], v[1], v[2], v[3]});
