@@ -175,6 +175,10 @@ struct WideField {
   bool tout = false;         // result stored transposed (d x N)
   const float* diag = nullptr;  // the field is diag(diag) (square; F unused)
   bool epi = false;             // transposed store with the epi_a / epi_b epilogue
+  // what the descriptors were last re-pointed to (a repeat call enqueues no patch)
+  const void* cur_in = nullptr;
+  const void* cur_out = nullptr;
+  int64_t cur_ld = -1;
   CloudDesc* dcl = nullptr;  // one descriptor per slice (device)
   int2* dwork_bta = nullptr;
   int2* dwork_exp = nullptr;

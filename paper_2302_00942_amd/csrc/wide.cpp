@@ -117,14 +117,27 @@ size_t wide_device_bytes(const WideField* w) {
 }
 
 hipError_t wide_set_input(WideField* w, const float* F, int64_t ldF, hipStream_t st) {
-  return launch_wide_patch(w->dcl, w->nsl, F, ldF, kWideSlice, st);
+  if (F == w->cur_in && ldF == w->cur_ld) return hipSuccess;  // already points there (stream order)
+  const hipError_t e = launch_wide_patch(w->dcl, w->nsl, F, ldF, kWideSlice, st);
+  if (e == hipSuccess) {
+    w->cur_in = F;
+    w->cur_ld = ldF;
+  }
+  return e;
 }
 
 hipError_t wide_set_output_epilogue(WideField* w, float* out, int64_t ldO, const float* a, const float* b,
                                     hipStream_t st) {
   if (!w->tout || !a || !b) return hipErrorInvalidValue;
   w->epi = true;
-  return launch_wide_patch_out(w->dcl, w->nsl, out, ldO, a, b, kWideSlice, st);
+  if (out == w->cur_out && ldO == w->cur_ld && a == w->cur_in) return hipSuccess;  // already set (stream order)
+  const hipError_t e = launch_wide_patch_out(w->dcl, w->nsl, out, ldO, a, b, kWideSlice, st);
+  if (e == hipSuccess) {
+    w->cur_out = out;
+    w->cur_ld = ldO;
+    w->cur_in = a;
+  }
+  return e;
 }
 
 // Split-N B^T F of every slice, the reduction and G' = T H0.
