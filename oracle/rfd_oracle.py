@@ -401,6 +401,26 @@ def gw_loss(apply_C, apply_D, T):
     return v1[:, None] + v2[None, :] - 2.0 * w3
 
 
+def kernel_spectrum(X, eps: float, lam: float, m: int, seed: int, shape: int = BALL_L2):
+    """All N eigenvalues, ascending, of the RFD kernel matrix exp(lam A B^T)
+    through the low-rank factors, as the classification experiments use them
+    (Sec. 3, point-cloud classification; the graph-classification appendix):
+    det(t I_N - A B^T) = t^(N-m) det(t I_m - B^T A), so A B^T has the m
+    eigenvalues mu_i of B^T A and N - m zeros when N >= m, and for N < m the
+    eigenvalues of B^T A less m - N of its zero ones (those of smallest |mu|);
+    exp(lam A B^T) has exp(lam mu) for each."""
+    om, w = frequencies_and_weights(m, eps, seed, shape)
+    Phi, sg = features(X, om, w)
+    M = Phi.T @ (Phi * sg)  # B^T A
+    mu = np.linalg.eigvals(M).real
+    N = np.asarray(X).shape[0]
+    if N >= m:
+        mu = np.concatenate([mu, np.zeros(N - m)])
+    else:
+        mu = mu[np.argsort(np.abs(mu), kind="stable")[m - N:]]
+    return np.sort(np.exp(lam * mu))
+
+
 def relf(a, b) -> float:
     """Relative Frobenius error ||a - b|| / ||b||."""
     a = np.asarray(a, dtype=np.float64)

@@ -483,3 +483,20 @@ def test_gw_terms_against_explicit_matrices():
     assert o.relf(v1, (C * C) @ T.sum(axis=1)) < 1e-13
     assert o.relf(v2, (D * D) @ T.sum(axis=0)) < 1e-13
     assert o.relf(w3, C @ T @ D.T) < 1e-13
+
+
+@pytest.mark.parametrize("n,m,eps,lam", [(40, 16, 0.4, -0.7), (10, 16, 0.5, -0.3), (64, 64, 0.3, 0.2)])
+def test_kernel_spectrum_matches_dense_eigenvalues(n, m, eps, lam):
+    """The low-rank spectrum equals the eigenvalues of the dense N x N matrix
+    exp(lam A B^T) (SciPy expm, symmetric eigensolver), for N > m, N < m and
+    N = m, with lambda of either sign."""
+    import scipy.linalg as sl
+    X = wl.sphere(n, 7)
+    om, w = o.frequencies_and_weights(m, eps, 11)
+    K = sl.expm(lam * o.what_hat(X, om, w))
+    dense = np.sort(sl.eigvalsh(0.5 * (K + K.T)))
+    got = o.kernel_spectrum(X, eps, lam, m, 11)
+    assert got.shape == (n,)
+    assert np.abs(got - dense).max() <= 1e-12 * max(1.0, np.abs(dense).max())
+    if n > m:
+        assert np.sum(np.abs(got - 1.0) < 1e-12) >= n - m  # the eigenvalue 1 of the null space of A B^T
