@@ -262,6 +262,26 @@ rfd_status rfd_loop_launch(rfd_loop_t loop, rfd_stream_t stream);
 /* Waits for the device and frees the loop (not the plans). */
 void rfd_loop_destroy(rfd_loop_t loop);
 
+/* ----------------------------------------------------- spectrum of the kernel */
+
+/* The k smallest (which = 0, ascending) or k largest (which = 1, descending)
+ * of the N eigenvalues of the kernel matrix exp(lambda A B^T) of the plan's
+ * cloud, written as doubles to out_dev (device, k entries), computed from
+ * the low-rank factors as the classification experiments do (Sec. 3,
+ * point-cloud classification; the graph-classification appendix):
+ * A B^T and the m x m core M = B^T A share their non-zero eigenvalues mu, so
+ * the kernel's eigenvalues are exp(lambda mu) and, for N > m, the eigenvalue
+ * 1 with multiplicity N - m (for N < m, the m - N eigenvalues of M of
+ * smallest |mu| are its extra zeros and are left out). M is symmetric when
+ * every weight is non-negative (the default main-lobe sampling); its
+ * eigenvalues are found by cyclic Jacobi in FP64 in one workgroup on
+ * `stream`, using the plan's M from rfd_features and its phi_1 workspace
+ * (do not overlap with other work on the same plan). Errors: RFD_ERR_NOT_READY
+ * (no features), RFD_ERR_INVALID_ARG (which not 0 or 1, k < 0, k > N, null
+ * out with k > 0, a negative weight); a non-finite M is reported by
+ * rfd_plan_check. k = 0 is a no-op. */
+rfd_status rfd_plan_spectrum(rfd_plan_t plan, int32_t which, int64_t k, double* out_dev, rfd_stream_t stream);
+
 /* ------------------------------------------- Gromov-Wasserstein loss matrix */
 
 typedef struct rfd_gw_s* rfd_gw_t;

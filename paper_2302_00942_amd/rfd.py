@@ -68,6 +68,7 @@ def lib() -> C.CDLL:
             "rfd_loop_create": ([vp, vp, i32, vp, i64, i32, i32, C.POINTER(vp)], i32),
             "rfd_loop_launch": ([vp, vp], i32),
             "rfd_loop_destroy": ([vp], None),
+            "rfd_plan_spectrum": ([vp, i32, i64, vp, vp], i32),
             "rfd_gw_create": ([vp, vp, C.POINTER(vp)], i32),
             "rfd_gw_loss": ([vp, vp, i64, vp, i64, vp], i32),
             "rfd_gw_terms": ([vp, vp, i64, vp, vp, vp, i64, vp], i32),
@@ -239,6 +240,16 @@ class Plan:
     def autotune_phi1(self, reps: int = 5, stream=None) -> None:
         """Tunes the workgroup count of the phi_1 kernel (needs features)."""
         _check(lib().rfd_autotune_phi1(self._h, int(reps), _stream_handle(stream)), "rfd_autotune_phi1")
+
+    def spectrum(self, k: int, which: str = "smallest", stream=None):
+        """The k smallest (ascending) or largest (descending) eigenvalues of
+        exp(lambda A B^T) on the plan's cloud (rfd_plan_spectrum), float64 CUDA."""
+        import torch
+        w = {"smallest": 0, "largest": 1}[which]
+        out = torch.empty(max(int(k), 1), dtype=torch.float64, device="cuda")
+        _check(lib().rfd_plan_spectrum(self._h, w, int(k), out.data_ptr(), _stream_handle(stream)),
+               "rfd_plan_spectrum")
+        return out[: int(k)]
 
     def check(self, stream=None) -> int:
         """Synchronises and returns the device status code (OK, NONFINITE, RANGE, DEVICE)."""

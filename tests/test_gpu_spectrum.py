@@ -1,0 +1,85 @@
+"""GPU: eigenvalues of the RFD kernel matrix exp(lambda A B^T) from the
+low-rank factors (rfd_plan_spectrum) against the oracle's kernel_spectrum.
+
+Tolerance: the device forms M = B^T A from FP32 (or BF16) features with the
+integrator's relative error (FP32 1e-5, BF16 2e-3, the one-action bars); by
+Weyl's inequality each eigenvalue mu moves by at most ||dM||_2 <= ||dM||_F,
+and exp(lambda mu) by |lambda| exp(lambda mu) times that, so the bar on
+every returned eigenvalue is |lambda| max(1, max spectrum) ||M||_F times the
+precision's bar."""
+import numpy as np
+import pytest
+
+from oracle import rfd_oracle as o
+from paper_2302_00942_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+BAR = {"fp32": 1e-5, "bf16": 2e-3}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2302_00942_amd import rfd
+    rfd.lib()
+    return torch
+
+
+def _oracle_M_norm(X, eps, m, seed):
+    om, w = o.frequencies_and_weights(m, eps, seed)
+    Phi, sg = o.features(X, om, w)
+    return float(np.linalg.norm(Phi.T @ (Phi * sg)))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,m,eps,lam", [(2048, 64, 0.1, -0.1), (700, 130, 0.2, -0.5), (100, 256, 0.3, -0.2),
+                                         (300, 16, 0.3, 0.05), (1, 2, 0.1, -0.1), (64, 64, 0.2, -1.0)])
+def test_spectrum_matches_oracle(torch_cuda, n, m, eps, lam, prec):
+    """N > m, N < m, N = m, a single point, lambda of either sign, every
+    padded feature count; the full spectrum both ways and a short head."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    X = wl.surface(("sphere", "torus", "ellipsoid")[n % 3], n, 5)
+    plan = rfd.Plan(m, eps, lam, 3, precision=prec)
+    plan.features(torch.from_numpy(X).cuda())
+    ref = o.kernel_spectrum(X, eps, lam, m, 3)
+    lo = plan.spectrum(n, "smallest").cpu().numpy()
+    hi = plan.spectrum(n, "largest").cpu().numpy()
+    head = plan.spectrum(min(5, n), "smallest").cpu().numpy()
+    assert plan.check() == rfd.OK
+    tol = abs(lam) * max(1.0, float(ref.max())) * _oracle_M_norm(X, eps, m, 3) * BAR[prec]
+    err = max(np.abs(lo - ref).max(), np.abs(hi - ref[::-1]).max())
+    print(f"spectrum N={n} m={m} lam={lam} {prec}: max err {err:.2e} (bar {tol:.2e}), min {ref[0]:.6f}")
+    assert err <= tol
+    assert np.array_equal(head, lo[: len(head)])
+    assert np.all(np.diff(lo) >= 0) and np.all(np.diff(hi) <= 0)
+    if n > m:  # the null space of A B^T: eigenvalue exactly 1, N - m times
+        assert np.sum(lo == 1.0) >= n - m
+
+
+def test_spectrum_repeatable_and_errors(torch_cuda):
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    X = torch.from_numpy(wl.sphere(500, 2)).cuda()
+    plan = rfd.Plan(128, 0.1, -0.3, 1, precision="bf16")
+    with pytest.raises(rfd.RfdError) as e:
+        plan.spectrum(3)
+    assert e.value.status == rfd.NOT_READY
+    plan.features(X)
+    a = plan.spectrum(500).cpu().numpy()
+    b = plan.spectrum(500).cpu().numpy()
+    assert np.array_equal(a, b)
+    for bad in (501, -1):
+        with pytest.raises(rfd.RfdError) as e:
+            plan.spectrum(bad)
+        assert e.value.status == rfd.INVALID_ARG
+    assert plan.spectrum(0).numel() == 0
+    # signed weights (a frequency law wider than the main lobe): B^T A is not symmetric
+    signed = rfd.Plan(64, 0.08, -0.002, 1, sigma=1 / 0.08, radius=3 / 0.08)
+    assert (signed.export()[1] < 0).any()
+    signed.features(X)
+    with pytest.raises(rfd.RfdError) as e:
+        signed.spectrum(3)
+    assert e.value.status == rfd.INVALID_ARG
