@@ -335,6 +335,36 @@ def bench_gw(torch, rfd, wl, reps: int):
             "unit": "loss entries/s", "bytes_per_loss_n3000": gw_bytes(3000, 3000), **res}
 
 
+def bench_spectrum(torch, rfd, wl, reps: int):
+    """Kernel spectrum for classification features (Sec. 3, point-cloud
+    classification: 2048 points per shape, eps = 0.1, lambda = -0.1, the 32
+    smallest eigenvalues of exp(lambda A B^T)): features of the cloud (the
+    Gram pass and phi_1), then rfd_plan_spectrum; the oracle's eigenvalues of
+    B^T A beside it. One workgroup runs the Jacobi sweeps, so the call is
+    latency-bound: its figure is the time per cloud."""
+    from oracle import rfd_oracle as o
+    n, k = 2048, 32
+    res = {}
+    for m in (64, 128, 256):
+        X_np = wl.sphere(n, 21)
+        X = torch.from_numpy(X_np).cuda()
+        p = rfd.Plan(m, 0.1, -0.1, 7, precision="bf16")
+        p.features(X)
+        ref = o.kernel_spectrum(X_np, 0.1, -0.1, m, 7)[:k]
+        sp_ms, _, _ = time_steps(lambda: p.spectrum(k), reps, 2, torch)
+        both_ms, _, _ = time_steps(lambda: (p.features(X), p.spectrum(k)), reps, 2, torch)
+        got = p.spectrum(k).cpu().numpy()
+        t0 = time.perf_counter()
+        o.kernel_spectrum(X_np, 0.1, -0.1, m, 7)
+        t_cpu = time.perf_counter() - t0
+        res[f"m{m}"] = {"spectrum_ms": round(sp_ms, 4), "features_and_spectrum_ms": round(both_ms, 4),
+                        "clouds_per_s": round(1e3 / both_ms, 1), "max_abs_err_vs_oracle": float(f"{np.abs(got - ref).max():.3e}"),
+                        "cpu_oracle_ms": round(t_cpu * 1e3, 2)}
+        p.close()
+    return {"workload": f"sphere N={n}, eps=0.1, lambda=-0.1, BF16 features, {k} smallest eigenvalues of the kernel",
+            "unit": "ms per cloud", **res}
+
+
 def bench_serving(torch, rfd, wl, count: int, warm: int, pool: int = 64):
     """Serving: a pool of clouds (N log-uniform in [2000, 200000], random
     surface, m in {64, 128, 256}); each request integrates a fresh field of a
@@ -454,8 +484,10 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests of the serving leg")
     ap.add_argument("--n", type=int, default=1_000_000, help=argparse.SUPPRESS)
     ap.add_argument("--gw-n", type=int, default=3000, help=argparse.SUPPRESS)
+    ap.add_argument("--dump-spectrum", metavar="DIR",
+                    help="write the spectrum workload (2048-point sphere) for paper_2302_00942_amd/rfd_run and exit")
     ap.add_argument("--dump-inputs", metavar="DIR", help="write the cloud for paper_2302_00942_amd/rfd_run and exit")
-    ap.add_argument("--gw-only", action="store_true", help="run only the Gromov-Wasserstein stage")
+    ap.add_argument("--gw-only", action="store_true", help="run only the Gromov-Wasserstein and spectrum stages")
     ap.add_argument("--dump-gw", metavar="DIR", help="write the GW problem (n=3000 per cloud) for paper_2302_00942_amd/rfd_run and exit")
     args = ap.parse_args()
     if args.dump_inputs:
@@ -477,6 +509,13 @@ def main() -> int:
         with open(os.path.join(args.dump_gw, "meta_gw.txt"), "w") as fh:
             fh.write(f"{c.n} {dcl.n} {c.m} {c.eps!r} {c.lam!r} {c.seed} {dcl.seed}\n")
         return 0
+    if args.dump_spectrum:
+        from paper_2302_00942_amd import workloads as wl
+        os.makedirs(args.dump_spectrum, exist_ok=True)
+        wl.sphere(2048, 21).tofile(os.path.join(args.dump_spectrum, "Xs.bin"))
+        with open(os.path.join(args.dump_spectrum, "meta_spec.txt"), "w") as fh:
+            fh.write("2048 32 0.1 -0.1 7\n")
+        return 0
     if args.gpus != 1:
         print("bench.py measures one MI355X: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         return 2
@@ -488,7 +527,8 @@ def main() -> int:
         return 1
     rfd.lib()
     if args.gw_only:
-        print(json.dumps({"gromov_wasserstein": bench_gw(torch, rfd, wl, max(5, args.steps))}))
+        print(json.dumps({"gromov_wasserstein": bench_gw(torch, rfd, wl, max(5, args.steps)),
+                          "kernel_spectrum": bench_spectrum(torch, rfd, wl, max(5, args.steps))}))
         return 0
     cloud = wl.large_torus(n=args.n)
     N, m, d = cloud.n, cloud.m, cloud.d
@@ -564,6 +604,7 @@ def main() -> int:
         line["repeated_application"] = bench_loop(torch, rfd, wl, max(5, args.steps // 2))
         line["resident_wide_fields"] = bench_resident_wide(torch, rfd, wl, max(5, args.steps))
         line["gromov_wasserstein"] = bench_gw(torch, rfd, wl, max(5, args.steps))
+        line["kernel_spectrum"] = bench_spectrum(torch, rfd, wl, max(5, args.steps))
         line["serving"] = bench_serving(torch, rfd, wl, args.serve_requests, 500)
         line["tuning_table"] = rfd.tune_export().strip().splitlines()
     if not args.no_cpu_baseline:

@@ -2,6 +2,7 @@
 //
 //   rfd_run DIR STEPS [PREC]
 //   rfd_run gw DIR STEPS [PREC]
+//   rfd_run spectrum DIR STEPS M
 //   rfd_run copy MIB
 //
 // DIR holds X.bin (N x 3 float32), F.bin (N x d float32) and meta.txt
@@ -10,7 +11,10 @@
 // default stream and prints the average milliseconds per step. The gw form
 // reads Xc.bin (n x 3), Xd.bin (m x 3), T.bin (n x m) and meta_gw.txt
 // ("n m feats eps lambda seed_c seed_d"), as written by `bench.py --dump-gw
-// DIR`, and runs STEPS Gromov-Wasserstein loss matrices. The copy form
+// DIR`, and runs STEPS Gromov-Wasserstein loss matrices. The spectrum form
+// reads Xs.bin (N x 3) and meta_spec.txt ("N k eps lambda seed"), as written
+// by `bench.py --dump-spectrum DIR`, computes BF16 features with M features
+// and runs STEPS spectrum calls (k smallest eigenvalues). The copy form
 // runs one device-to-device copy of MIB mebibytes (a reference kernel of
 // known traffic for calibrating hardware byte counters).
 #include <hip/hip_runtime.h>
@@ -115,8 +119,61 @@ static int gw_mode(const std::string& dir, int steps, int prec) {
   return st == RFD_OK ? 0 : 1;
 }
 
+static int spectrum_mode(const std::string& dir, int steps, int m) {
+  long long n = 0, k = 0;
+  double eps = 0, lam = 0;
+  unsigned long long seed = 0;
+  FILE* mf = fopen((dir + "/meta_spec.txt").c_str(), "r");
+  if (!mf || fscanf(mf, "%lld %lld %lf %lf %llu", &n, &k, &eps, &lam, &seed) != 5) {
+    fprintf(stderr, "cannot read %s/meta_spec.txt\n", dir.c_str());
+    return 1;
+  }
+  fclose(mf);
+  if (n <= 0 || k <= 0 || k > n || steps <= 0 || m <= 0) return 1;
+  std::vector<float> X((size_t)n * 3);
+  if (!read_file(dir + "/Xs.bin", X.data(), X.size() * 4)) return 1;
+  float* dX = upload(X);
+  double* dOut = nullptr;
+  if (!dX || hipMalloc(&dOut, sizeof(double) * k) != hipSuccess) return 1;
+  rfd_params p;
+  memset(&p, 0, sizeof(p));
+  p.m = m;
+  p.shape = RFD_BALL_L2;
+  p.precision = RFD_BF16;
+  p.eps = eps;
+  p.lambda = lam;
+  p.seed = seed;
+  rfd_plan_t plan = nullptr;
+  rfd_status st = rfd_plan_create(&p, &plan);
+  if (st == RFD_OK) st = rfd_features(plan, dX, n, nullptr);
+  if (st == RFD_OK) st = rfd_plan_spectrum(plan, 0, k, dOut, nullptr);  // untimed
+  if (st == RFD_OK) st = rfd_plan_check(plan, nullptr);
+  if (st != RFD_OK) {
+    fprintf(stderr, "spectrum set-up: %s\n", rfd_status_string(st));
+    return 1;
+  }
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  (void)hipEventRecord(a, nullptr);
+  for (int i = 0; i < steps && st == RFD_OK; ++i) st = rfd_plan_spectrum(plan, 0, k, dOut, nullptr);
+  (void)hipEventRecord(b, nullptr);
+  (void)hipEventSynchronize(b);
+  if (st == RFD_OK) st = rfd_plan_check(plan, nullptr);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  printf("rfd_run spectrum N=%lld m=%d k=%lld steps=%d: %.4f ms/call (%s)\n", n, m, k, steps, ms / steps,
+         rfd_status_string(st));
+  fflush(stdout);
+  rfd_plan_destroy(plan);
+  (void)hipFree(dX);
+  (void)hipFree(dOut);
+  return st == RFD_OK ? 0 : 1;
+}
+
 int main(int argc, char** argv) {
   if (argc == 3 && strcmp(argv[1], "copy") == 0) return copy_mode(atoll(argv[2]));
+  if (argc == 5 && strcmp(argv[1], "spectrum") == 0) return spectrum_mode(argv[2], atoi(argv[3]), atoi(argv[4]));
   if (argc >= 4 && strcmp(argv[1], "gw") == 0)
     return gw_mode(argv[2], atoi(argv[3]), (argc > 4 && strcmp(argv[4], "fp32") == 0) ? RFD_FP32 : RFD_BF16);
   if (argc < 3) {
