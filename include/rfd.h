@@ -274,9 +274,10 @@ void rfd_loop_destroy(rfd_loop_t loop);
  * 1 with multiplicity N - m (for N < m, the m - N eigenvalues of M of
  * smallest |mu| are its extra zeros and are left out). M is symmetric when
  * every weight is non-negative (the default main-lobe sampling); its
- * eigenvalues are found by cyclic Jacobi in FP64 in one workgroup on
- * `stream`, using the plan's M from rfd_features and its phi_1 workspace
- * (do not overlap with other work on the same plan). Errors: RFD_ERR_NOT_READY
+ * eigenvalues are found in FP64 (Householder tridiagonalisation, then
+ * bisection on the Sturm count) by one workgroup on `stream`, using the
+ * plan's M from rfd_features and its phi_1 workspace (do not overlap with
+ * other work on the same plan). Errors: RFD_ERR_NOT_READY
  * (no features), RFD_ERR_INVALID_ARG (which not 0 or 1, k < 0, k > N, null
  * out with k > 0, a negative weight); a non-finite M is reported by
  * rfd_plan_check. k = 0 is a no-op. */

@@ -4,63 +4,64 @@
 // eigenvalues, and A B^T has N - m more zeros when N >= m (for N < m,
 // B^T A has m - N zeros that A B^T lacks). With non-negative weights
 // B^T A = diag(c) Phi_u^T Phi_u diag(c) is symmetric; its eigenvalues mu are
-// found by cyclic Jacobi in FP64, and the kernel's are exp(lambda mu) plus the
-// eigenvalue 1 of the null space.
+// found in FP64 (Householder tridiagonalisation, then bisection), and the
+// kernel's are exp(lambda mu) plus the eigenvalue 1 of the null space.
 //
 // One workgroup does everything: the m x m matrix (from the plan's Mraw and
-// scales) lives in a global workspace; each Jacobi round applies m/2
-// disjoint rotations (a round-robin schedule of pairs, so one sweep of m - 1
-// rounds meets every pair once) as a column update A <- A J and a row update
-// A <- J^T A. Sweeps stop when the off-diagonal sum of squares falls below
-// 1e-30 of the matrix's, or after kMaxSweeps.
+// scales) lives in LDS when it fits (m <= 128), else in a global workspace; m - 2 Householder reflections reduce
+// it to a symmetric tridiagonal T (each a product p = 2 A22 v over the
+// trailing block and the rank-2 update A22 - v q^T - q v^T, with
+// q = p - (v^T p) v), and every thread then finds one eigenvalue of T by
+// bisection on its Sturm count (eigenvalues below x = negative pivots of
+// T - x I), from the Gershgorin interval, until the interval cannot shrink.
 #include "rfd_internal.h"
 
 namespace rfd {
 namespace {
 
-constexpr int kMaxSweeps = 40;
+constexpr int kMaxBisect = 200;  // bisection steps per eigenvalue (about 60-70 reach the limit of FP64)
 
 typedef __attribute__((address_space(1))) double gdouble_t;
 __device__ __forceinline__ double ldg(const double* p) { return *(const gdouble_t*)p; }
 __device__ __forceinline__ void stg(double* p, double v) { *(gdouble_t*)p = v; }
 
-// Pair t of round r over n (even) indices: n - 1 stays, the others rotate.
-__device__ __forceinline__ void round_pair(int r, int t, int n, int& a, int& b) {
-  if (t == 0) {
-    a = r;
-    b = n - 1;
-  } else {
-    a = (r + t) % (n - 1);
-    b = (r - t + n - 1) % (n - 1);
-  }
-}
-
-// Sum over the workgroup (fixed tree); every thread gets the result.
+// Sum over the workgroup in a fixed order (a butterfly in each wave, read
+// from lane 0, then the four wave sums in order); every thread gets the
+// result. Two barriers: the second lets red be reused at once.
 __device__ __forceinline__ double block_sum(double v, double* red) {
   const int t = threadIdx.x;
-  red[t] = v;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  if ((t & 63) == 0) red[t >> 6] = v;
   __syncthreads();
-  for (int o = 128; o >= 1; o >>= 1) {
-    if (t < o) red[t] += red[t + o];
-    __syncthreads();
-  }
-  const double s = red[0];
+  const double s = ((red[0] + red[1]) + red[2]) + red[3];
   __syncthreads();
   return s;
 }
 
+// The matrix lives in LDS (dynamic, m^2 doubles) when it fits, else in the
+// global workspace Ag.
+template <bool LDS>
 __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ Mraw, const double* __restrict__ cvec,
                                                   int Mp, int m, int f, double lambda, int64_t N, int which,
-                                                  int64_t k, double* __restrict__ A, double* __restrict__ out,
+                                                  int64_t k, double* __restrict__ Ag, double* __restrict__ out,
                                                   int* __restrict__ flag) {
-  __shared__ double red[256];
-  __shared__ double rc[kMaxM / 2], rs[kMaxM / 2];
-  __shared__ int ra[kMaxM / 2], rb[kMaxM / 2];
+  extern __shared__ double As[];
+  const auto ld = [&](size_t e) -> double {
+    if constexpr (LDS) return As[e];
+    else return ldg(Ag + e);
+  };
+  const auto st = [&](size_t e, double v) {
+    if constexpr (LDS) As[e] = v;
+    else stg(Ag + e, v);
+  };
+  __shared__ double red[4];
+  __shared__ double vv[kMaxM], qq[kMaxM];
+  __shared__ double dg[kMaxM], od[kMaxM];  // T: diagonal, and od[i] = T[i][i-1]
   __shared__ double mu[kMaxM];
   __shared__ double val[kMaxM];
   __shared__ int keep[kMaxM];
   const int t = threadIdx.x;
-  const int n = m + (m & 1);  // even index count; index m is a dummy when m is odd
   const int fp = Mp / 2;
   // A = diag(c) Mraw diag(c) over the real features (canonical order)
   double fro = 0.0;
@@ -68,73 +69,122 @@ __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ Mra
     const int i = e / m, j = e - i * m;
     const int pi = i < f ? i : fp + (i - f), pj = j < f ? j : fp + (j - f);
     const double v = ldg(cvec + pi) * ldg(Mraw + (size_t)pi * Mp + pj) * ldg(cvec + pj);
-    stg(A + e, v);
+    st(e, v);
     fro += v * v;
   }
   fro = block_sum(fro, red);
-  if (!isfinite(fro)) {
-    if (t == 0) __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    fro = 0.0;  // rotate nothing; the flag reports the input
-  }
-  for (int sweep = 0; sweep < kMaxSweeps && fro > 0.0; ++sweep) {
-    double off = 0.0;
-    for (int e = t; e < m * m; e += 256) {
-      const int i = e / m, j = e - i * m;
-      if (i != j) {
-        const double v = ldg(A + e);
-        off += v * v;
+  if (!isfinite(fro) && t == 0) __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // Householder tridiagonalisation; every branch below is uniform over the
+  // workgroup (it depends on block sums and LDS values only)
+  for (int k = 0; k + 2 < m; ++k) {
+    const int r = m - k - 1;  // order of the trailing block A22 = A[k+1.., k+1..]
+    double tail = 0.0;
+    for (int i = t; i < r; i += 256) {
+      const double x = ld((size_t)(k + 1 + i) * m + k);
+      vv[i] = x;
+      if (i > 0) tail += x * x;
+    }
+    tail = block_sum(tail, red);  // also orders the vv stores before the reads below
+    const double x0 = vv[0];
+    if (t == 0) dg[k] = ld((size_t)k * m + k);
+    if (!(tail > 0.0)) {  // the column is reduced already (or not finite: then nothing is rotated)
+      if (t == 0) od[k + 1] = x0;
+      __syncthreads();
+      continue;
+    }
+    const double sq = x0 * x0 + tail;
+    const double nrm = sqrt(sq);
+    const double alpha = x0 >= 0.0 ? -nrm : nrm;
+    const double vn = sqrt(2.0 * (sq - alpha * x0));  // |x - alpha e1|
+    for (int i = t; i < r; i += 256) vv[i] = (i == 0 ? x0 - alpha : vv[i]) / vn;
+    __syncthreads();
+    // p = 2 A22 v (A22 is symmetric: thread i walks column i, coalesced over i)
+    double vp = 0.0;
+    for (int i = t; i < r; i += 256) {
+      // eight partial sums, so that eight loads are in flight (a fixed order)
+      double ps[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int j = 0;
+      for (; j + 8 <= r; j += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = ld((size_t)(k + 1 + j + u) * m + (k + 1 + i));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ps[u] += x[u] * vv[j + u];
+      }
+      for (; j < r; ++j) ps[j & 7] += ld((size_t)(k + 1 + j) * m + (k + 1 + i)) * vv[j];
+      const double s = ((ps[0] + ps[1]) + (ps[2] + ps[3])) + ((ps[4] + ps[5]) + (ps[6] + ps[7]));
+      qq[i] = 2.0 * s;
+      vp += vv[i] * (2.0 * s);
+    }
+    const double beta = block_sum(vp, red);
+    for (int i = t; i < r; i += 256) qq[i] -= beta * vv[i];
+    __syncthreads();
+    // rank-2 update, eight elements per thread at a time: all loads, then all stores
+    for (int e0 = t; e0 < r * r; e0 += 8 * 256) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256;
+        x[u] = 0.0;
+        if (e < r * r) {
+          const int i = e / r, j = e - i * r;
+          x[u] = ld((size_t)(k + 1 + i) * m + (k + 1 + j));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256;
+        if (e < r * r) {
+          const int i = e / r, j = e - i * r;
+          st((size_t)(k + 1 + i) * m + (k + 1 + j), x[u] - (vv[i] * qq[j] + qq[i] * vv[j]));
+        }
       }
     }
-    off = block_sum(off, red);
-    if (off <= 1e-30 * fro) break;  // uniform: every thread holds the same sums
-    for (int r = 0; r < n - 1; ++r) {
-      if (t < n / 2) {
-        int a, b;
-        round_pair(r, t, n, a, b);
-        double c = 1.0, s = 0.0;
-        if (a < m && b < m) {
-          const double apq = ldg(A + (size_t)a * m + b);
-          if (apq != 0.0) {
-            const double app = ldg(A + (size_t)a * m + a), aqq = ldg(A + (size_t)b * m + b);
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            s = tt * c;
-          }
-        }
-        ra[t] = a;
-        rb[t] = b;
-        rc[t] = c;
-        rs[t] = s;
-      }
-      __syncthreads();
-      // A <- A J: columns a and b of every row
-      for (int e = t; e < (n / 2) * m; e += 256) {
-        const int q = e / m, i = e - q * m;
-        const int a = ra[q], b = rb[q];
-        if (a < m && b < m && rs[q] != 0.0) {
-          const double c = rc[q], s = rs[q];
-          const double x = ldg(A + (size_t)i * m + a), y = ldg(A + (size_t)i * m + b);
-          stg(A + (size_t)i * m + a, c * x - s * y);
-          stg(A + (size_t)i * m + b, s * x + c * y);
-        }
-      }
-      __syncthreads();
-      // A <- J^T A: rows a and b of every column
-      for (int e = t; e < (n / 2) * m; e += 256) {
-        const int q = e / m, j = e - q * m;
-        const int a = ra[q], b = rb[q];
-        if (a < m && b < m && rs[q] != 0.0) {
-          const double c = rc[q], s = rs[q];
-          const double x = ldg(A + (size_t)a * m + j), y = ldg(A + (size_t)b * m + j);
-          stg(A + (size_t)a * m + j, c * x - s * y);
-          stg(A + (size_t)b * m + j, s * x + c * y);
-        }
-      }
-      __syncthreads();
-    }
+    if (t == 0) od[k + 1] = alpha;
+    __syncthreads();
   }
-  for (int i = t; i < m; i += 256) mu[i] = ldg(A + (size_t)i * m + i);
+  if (t == 0) {
+    if (m >= 2) {
+      dg[m - 2] = ld((size_t)(m - 2) * m + (m - 2));
+      dg[m - 1] = ld((size_t)(m - 1) * m + (m - 1));
+      od[m - 1] = ld((size_t)(m - 1) * m + (m - 2));
+    } else {
+      dg[0] = ld(0);
+    }
+    od[0] = 0.0;
+  }
+  __syncthreads();
+  // bisection on the Sturm count, one eigenvalue (the j-th smallest) per thread
+  double emax2 = 1.0, lo = 0.0, hi = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double ei = fabs(od[i]), en = i + 1 < m ? fabs(od[i + 1]) : 0.0;
+    emax2 = fmax(emax2, ei * ei);
+    lo = i == 0 ? dg[i] - ei - en : fmin(lo, dg[i] - ei - en);
+    hi = i == 0 ? dg[i] + ei + en : fmax(hi, dg[i] + ei + en);
+  }
+  const double pivmin = 2.2250738585072014e-308 * emax2;
+  const double tol = 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi));  // absolute accuracy, 2 eps |T|
+  for (int j = t; j < m; j += 256) {
+    double a = lo, b = hi;
+    for (int it = 0; it < kMaxBisect; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (!(mid > a && mid < b) || b - a <= tol) break;
+      int cnt = 0;
+      double q = dg[0] - mid;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0 ? 1 : 0;
+      for (int i = 1; i < m; ++i) {
+        q = dg[i] - mid - od[i] * od[i] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0 ? 1 : 0;
+      }
+      if (cnt > j)
+        b = mid;
+      else
+        a = mid;
+    }
+    mu[j] = 0.5 * (a + b);
+  }
   __syncthreads();
   // for N < m, drop the m - N eigenvalues of smallest |mu| (ties by index)
   const int64_t drop = N < m ? (int64_t)m - N : 0;
@@ -164,15 +214,29 @@ __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ Mra
     if (slot < k) stg(out + slot, val[i]);
   }
   // the ones occupy ascending positions [below, below + ones)
-  const int64_t lo = which == 0 ? below : N - below - ones;
-  for (int64_t p = lo + t; p < lo + ones && p < k; p += 256) stg(out + p, 1.0);
+  const int64_t first_one = which == 0 ? below : N - below - ones;
+  for (int64_t p = first_one + t; p < first_one + ones && p < k; p += 256) stg(out + p, 1.0);
 }
 
 }  // namespace
 
 hipError_t launch_spectrum(rfd_plan_s* p, int which, int64_t k, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_spectrum, dim3(1), dim3(256), 0, st, p->dev.Mraw, p->dev.cvec, p->dev_m, p->m, p->f,
-                     p->params.lambda, p->N, which, k, p->dev.phi_ws, out, p->dev.flag);
+  // the m x m core in LDS when it fits beside the kernel's own 15 KB
+  const size_t bytes = sizeof(double) * (size_t)p->m * p->m;
+  constexpr size_t kLdsLimit = 160 * 1024 - 16 * 1024;
+  static int lds_ok = -1;  // whether the large-LDS attribute was accepted (set once per process)
+  if (lds_ok < 0)
+    lds_ok = hipFuncSetAttribute((const void*)k_spectrum<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kLdsLimit) == hipSuccess
+                 ? 1
+                 : 0;
+  const size_t lds_max = lds_ok ? kLdsLimit : 48 * 1024;
+  if (bytes <= lds_max)
+    hipLaunchKernelGGL(k_spectrum<true>, dim3(1), dim3(256), bytes, st, p->dev.Mraw, p->dev.cvec, p->dev_m, p->m,
+                       p->f, p->params.lambda, p->N, which, k, nullptr, out, p->dev.flag);
+  else
+    hipLaunchKernelGGL(k_spectrum<false>, dim3(1), dim3(256), 0, st, p->dev.Mraw, p->dev.cvec, p->dev_m, p->m,
+                       p->f, p->params.lambda, p->N, which, k, p->dev.phi_ws, out, p->dev.flag);
   return hipGetLastError();
 }
 
