@@ -361,7 +361,18 @@ def bench_spectrum(torch, rfd, wl, reps: int):
                         "clouds_per_s": round(1e3 / both_ms, 1), "max_abs_err_vs_oracle": float(f"{np.abs(got - ref).max():.3e}"),
                         "cpu_oracle_ms": round(t_cpu * 1e3, 2)}
         p.close()
-    return {"workload": f"sphere N={n}, eps=0.1, lambda=-0.1, BF16 features, {k} smallest eigenvalues of the kernel",
+    # many clouds in one launch (one workgroup each): 256 shapes of 2048 points
+    clouds = [torch.from_numpy(wl.surface(wl.SURFACES[i % 3], n, 100 + i)).cuda() for i in range(256)]
+    for m in (64, 128):
+        plans = [rfd.Plan(m, 0.1, -0.1, 7 + i, precision="bf16") for i in range(len(clouds))]
+        for pl, X in zip(plans, clouds):
+            pl.features(X)
+        ms, _, _ = time_steps(lambda: rfd.spectrum_batch(plans, k), max(3, reps // 4), 1, torch)
+        res[f"batch256_m{m}"] = {"ms": round(ms, 3), "clouds_per_s": round(len(plans) / (ms * 1e-3), 1)}
+        for pl in plans:
+            pl.close()
+    return {"workload": f"sphere N={n}, eps=0.1, lambda=-0.1, BF16 features, {k} smallest eigenvalues of the kernel; "
+                        "batch: 256 clouds (sphere / torus / ellipsoid) in one launch",
             "unit": "ms per cloud", **res}
 
 

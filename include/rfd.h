@@ -283,6 +283,16 @@ void rfd_loop_destroy(rfd_loop_t loop);
  * rfd_plan_check. k = 0 is a no-op. */
 rfd_status rfd_plan_spectrum(rfd_plan_t plan, int32_t which, int64_t k, double* out_dev, rfd_stream_t stream);
 
+/* rfd_plan_spectrum for n plans at once (one workgroup per cloud, one
+ * launch): cloud i's k values go to outs[i] (device). Each plan appears once
+ * and meets rfd_plan_spectrum's conditions, with k <= its N; the feature
+ * counts may differ. The call copies n argument records to the device and
+ * synchronises `stream` before returning. Errors: those of
+ * rfd_plan_spectrum, RFD_ERR_INVALID_ARG for n < 0, null arrays or a plan
+ * given twice; n = 0 or k = 0 is a no-op. */
+rfd_status rfd_spectrum_batch(const rfd_plan_t* plans, int32_t n, int32_t which, int64_t k, double* const* outs,
+                              rfd_stream_t stream);
+
 /* ------------------------------------------- Gromov-Wasserstein loss matrix */
 
 typedef struct rfd_gw_s* rfd_gw_t;

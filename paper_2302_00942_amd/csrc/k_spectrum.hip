@@ -40,12 +40,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // The matrix lives in LDS (dynamic, m^2 doubles) when it fits, else in the
-// global workspace Ag.
+// global workspace Ag. One workgroup per cloud.
 template <bool LDS>
-__global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ Mraw, const double* __restrict__ cvec,
-                                                  int Mp, int m, int f, double lambda, int64_t N, int which,
-                                                  int64_t k, double* __restrict__ Ag, double* __restrict__ out,
-                                                  int* __restrict__ flag) {
+__device__ __forceinline__ void spectrum_body(const SpecArgs& sa) {
+  const double* __restrict__ Mraw = sa.Mraw;
+  const double* __restrict__ cvec = sa.cvec;
+  double* __restrict__ Ag = sa.Ag;
+  double* __restrict__ out = sa.out;
+  int* __restrict__ flag = sa.flag;
+  const double lambda = sa.lambda;
+  const int64_t N = sa.N, k = sa.k;
+  const int Mp = sa.Mp, m = sa.m, f = sa.f, which = sa.which;
   extern __shared__ double As[];
   const auto ld = [&](size_t e) -> double {
     if constexpr (LDS) return As[e];
@@ -218,25 +223,66 @@ __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ Mra
   for (int64_t p = first_one + t; p < first_one + ones && p < k; p += 256) stg(out + p, 1.0);
 }
 
+template <bool LDS>
+__global__ __launch_bounds__(256) void k_spectrum(SpecArgs sa) {
+  spectrum_body<LDS>(sa);
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(256) void k_spectrum_batch(const SpecArgs* __restrict__ arr) {
+  const SpecArgs sa = arr[blockIdx.x];
+  spectrum_body<LDS>(sa);
+}
+
 }  // namespace
 
-hipError_t launch_spectrum(rfd_plan_s* p, int which, int64_t k, double* out, hipStream_t st) {
-  // the m x m core in LDS when it fits beside the kernel's own 15 KB
-  const size_t bytes = sizeof(double) * (size_t)p->m * p->m;
+// The m x m core goes to LDS when it fits beside the kernel's own 15 KB.
+static size_t spectrum_lds_max() {
   constexpr size_t kLdsLimit = 160 * 1024 - 16 * 1024;
   static int lds_ok = -1;  // whether the large-LDS attribute was accepted (set once per process)
-  if (lds_ok < 0)
-    lds_ok = hipFuncSetAttribute((const void*)k_spectrum<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)kLdsLimit) == hipSuccess
-                 ? 1
-                 : 0;
-  const size_t lds_max = lds_ok ? kLdsLimit : 48 * 1024;
-  if (bytes <= lds_max)
-    hipLaunchKernelGGL(k_spectrum<true>, dim3(1), dim3(256), bytes, st, p->dev.Mraw, p->dev.cvec, p->dev_m, p->m,
-                       p->f, p->params.lambda, p->N, which, k, nullptr, out, p->dev.flag);
+  if (lds_ok < 0) {
+    const bool a = hipFuncSetAttribute((const void*)k_spectrum<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kLdsLimit) == hipSuccess;
+    const bool b = hipFuncSetAttribute((const void*)k_spectrum_batch<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit) == hipSuccess;
+    lds_ok = a && b ? 1 : 0;
+  }
+  return lds_ok ? kLdsLimit : 48 * 1024;
+}
+
+SpecArgs spectrum_args(rfd_plan_s* p, int which, int64_t k, double* out) {
+  SpecArgs a;
+  a.Mraw = p->dev.Mraw;
+  a.cvec = p->dev.cvec;
+  a.Ag = p->dev.phi_ws;
+  a.out = out;
+  a.flag = p->dev.flag;
+  a.lambda = p->params.lambda;
+  a.N = p->N;
+  a.k = k;
+  a.Mp = p->dev_m;
+  a.m = p->m;
+  a.f = p->f;
+  a.which = which;
+  return a;
+}
+
+hipError_t launch_spectrum(rfd_plan_s* p, int which, int64_t k, double* out, hipStream_t st) {
+  const SpecArgs a = spectrum_args(p, which, k, out);
+  const size_t bytes = sizeof(double) * (size_t)p->m * p->m;
+  if (bytes <= spectrum_lds_max())
+    hipLaunchKernelGGL(k_spectrum<true>, dim3(1), dim3(256), bytes, st, a);
   else
-    hipLaunchKernelGGL(k_spectrum<false>, dim3(1), dim3(256), 0, st, p->dev.Mraw, p->dev.cvec, p->dev_m, p->m,
-                       p->f, p->params.lambda, p->N, which, k, p->dev.phi_ws, out, p->dev.flag);
+    hipLaunchKernelGGL(k_spectrum<false>, dim3(1), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_spectrum_batch(const SpecArgs* dev_args, int n, int max_m, hipStream_t st) {
+  const size_t bytes = sizeof(double) * (size_t)max_m * max_m;
+  if (bytes <= spectrum_lds_max())
+    hipLaunchKernelGGL(k_spectrum_batch<true>, dim3(n), dim3(256), bytes, st, dev_args);
+  else
+    hipLaunchKernelGGL(k_spectrum_batch<false>, dim3(n), dim3(256), 0, st, dev_args);
   return hipGetLastError();
 }
 

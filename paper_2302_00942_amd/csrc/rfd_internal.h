@@ -210,6 +210,22 @@ void wide_free(WideField* w);
 hipError_t launch_wide_patch(CloudDesc* dcl, int nsl, const float* F, int64_t ldF, int W, hipStream_t st);  // k_gw.hip
 hipError_t launch_wide_patch_out(CloudDesc* dcl, int nsl, float* out, int64_t ldO, const float* a, const float* b,
                                  int W, hipStream_t st);  // k_gw.hip
+// Spectrum of the kernel matrix of one cloud (k_spectrum.hip): the plan's core,
+// its phi_1 workspace (global path), the output and the selection.
+struct SpecArgs {
+  const double* Mraw;
+  const double* cvec;
+  double* Ag;
+  double* out;
+  int* flag;
+  double lambda;
+  int64_t N;
+  int64_t k;
+  int Mp, m, f, which;
+};
+SpecArgs spectrum_args(rfd_plan_s* p, int which, int64_t k, double* out);
+hipError_t launch_spectrum(rfd_plan_s* p, int which, int64_t k, double* out, hipStream_t st);
+hipError_t launch_spectrum_batch(const SpecArgs* dev_args, int n, int max_m, hipStream_t st);
 // Launch-geometry tuning (autotune.cpp): knobs that change speed, never results.
 enum TuneKnob { kTuneExpandTilesPerWave = 0, kTuneBatchExpandTilesPerItem = 1, kTunePhi1Workgroups = 2,
                 kNumTuneKnobs };

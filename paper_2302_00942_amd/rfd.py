@@ -69,6 +69,7 @@ def lib() -> C.CDLL:
             "rfd_loop_launch": ([vp, vp], i32),
             "rfd_loop_destroy": ([vp], None),
             "rfd_plan_spectrum": ([vp, i32, i64, vp, vp], i32),
+            "rfd_spectrum_batch": ([vp, i32, i32, i64, vp, vp], i32),
             "rfd_gw_create": ([vp, vp, C.POINTER(vp)], i32),
             "rfd_gw_loss": ([vp, vp, i64, vp, i64, vp], i32),
             "rfd_gw_terms": ([vp, vp, i64, vp, vp, vp, i64, vp], i32),
@@ -364,6 +365,20 @@ class Loop:
             self.close()
         except Exception:
             pass
+
+
+def spectrum_batch(plans, k: int, which: str = "smallest", stream=None):
+    """rfd_spectrum_batch: the k smallest (or largest) kernel eigenvalues of
+    every plan's cloud in one launch; a list of float64 CUDA tensors."""
+    import torch
+    w = {"smallest": 0, "largest": 1}[which]
+    n = len(plans)
+    outs = [torch.empty(max(int(k), 1), dtype=torch.float64, device="cuda") for _ in range(n)]
+    P = C.c_void_p * max(n, 1)
+    hp = P(*[p.handle.value for p in plans])
+    ho = P(*[o.data_ptr() for o in outs])
+    _check(lib().rfd_spectrum_batch(hp, n, w, int(k), ho, _stream_handle(stream)), "rfd_spectrum_batch")
+    return [o[: int(k)] for o in outs]
 
 
 class GW:

@@ -83,3 +83,30 @@ def test_spectrum_repeatable_and_errors(torch_cuda):
     with pytest.raises(rfd.RfdError) as e:
         signed.spectrum(3)
     assert e.value.status == rfd.INVALID_ARG
+
+
+@pytest.mark.parametrize("m", [64, 256])
+def test_spectrum_batch_equals_single_calls(torch_cuda, m):
+    """One launch for many clouds (one workgroup each) gives, cloud by cloud,
+    bitwise the single-call spectrum; mixed feature counts share a launch."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    sizes = [150, 2048, 333, 64, 1000, 77, 512, 129]
+    plans = []
+    for i, n in enumerate(sizes):
+        mm = m if i % 3 else (128 if m == 64 else 64)
+        p = rfd.Plan(mm, 0.1, -0.2, 20 + i, precision="bf16" if i % 2 else "fp32")
+        p.features(torch.from_numpy(wl.surface(("sphere", "torus", "ellipsoid")[i % 3], n, 30 + i)).cuda())
+        plans.append(p)
+    k = min(sizes)
+    for which in ("smallest", "largest"):
+        got = rfd.spectrum_batch(plans, k, which)
+        for p, g in zip(plans, got):
+            assert np.array_equal(g.cpu().numpy(), p.spectrum(k, which).cpu().numpy())
+    with pytest.raises(rfd.RfdError) as e:
+        rfd.spectrum_batch(plans, max(sizes))  # k above some cloud's N
+    assert e.value.status == rfd.INVALID_ARG
+    with pytest.raises(rfd.RfdError) as e:
+        rfd.spectrum_batch([plans[0], plans[0]], 3)
+    assert e.value.status == rfd.INVALID_ARG
+    assert rfd.spectrum_batch([], 3) == []
