@@ -305,12 +305,8 @@ typedef struct rfd_gw_s* rfd_gw_t;
  * C and D enter only through their actions (resident integrations). The
  * identity behind Alg. 2 assumes symmetric costs, which holds for RFD
  * operators whose weights are all positive (the default main-lobe sampling).
- * Allocates n^2 + m^2 + n m floats plus per-slice scratch, two streams of
- * its own (default priority) and three events, and forms both plans' S, so
- * that rfd_gw_loss allocates nothing. rfd_gw_loss forks the two
- * Hadamard-square terms onto those streams after an event on `stream` and
- * makes `stream` wait for them before its final step, so the caller's
- * stream orders the whole call. The plans must outlive
+ * Allocates one max(n, m)^2 float buffer plus per-slice scratch, and forms
+ * both plans' S, so that rfd_gw_loss allocates nothing. The plans must outlive
  * the workspace and keep their cloud sizes. Errors: RFD_ERR_INVALID_ARG (null
  * or identical plans, n or m < 1 or > 32768), RFD_ERR_NOT_READY (no
  * features), RFD_ERR_DEVICE. */

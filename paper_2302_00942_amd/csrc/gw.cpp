@@ -13,9 +13,8 @@
 // matrix-valued fields is integrated as one wide field (all 64-channel slices
 // in one launch per stage). An action whose result is transposed next stores
 // it transposed (no transpose pass), and the second action of each
-// Hadamard-square term forms only the diagonal that the term keeps. The two
-// Hadamard-square terms run on two streams of the workspace beside the cross
-// term on the caller's stream, which waits for both before the final action.
+// Hadamard-square term forms only the diagonal that the term keeps. Every
+// step runs on the caller's stream.
 #include <new>
 
 #include "rfd_internal.h"
@@ -24,20 +23,14 @@ struct rfd_gw_s {
   rfd_plan_s* pc = nullptr;
   rfd_plan_s* pd = nullptr;
   int n = 0, m = 0;
-  float* Bc = nullptr;    // n x n: FM_C(diag p)^T
-  float* Bd = nullptr;    // m x m: FM_D(diag q)^T
-  float* Bx = nullptr;    // m x n: FM_C(T)^T
-  float* vec = nullptr;   // p (n), q (m), v1 (n), v2 (m)
+  float* B = nullptr;    // max(n, m)^2 floats
+  float* vec = nullptr;  // p (n), q (m), v1 (n), v2 (m)
   double* colpart = nullptr;  // column-sum partials of the coupling
-  // wide integrations: C on diag(p) with the result stored transposed in Bc,
-  // then C on Bc forming only the diagonal (likewise D with Bd); C on T
-  // stored transposed in Bx; D on Bx either in place (the terms) or stored
+  // wide integrations: C on diag(p) with the result stored transposed in B,
+  // then C on B forming only the diagonal (likewise D); C on T stored
+  // transposed in B (m x n); D on B either in place (the terms) or stored
   // transposed into L with the final combination as its epilogue (the loss)
   rfd::WideField c_sq1, c_sq2, d_sq1, d_sq2, c_t, d_cross, d_loss;
-  // the two Hadamard-square terms run on their own streams beside the cross
-  // term (fork after the marginals, join before the final action)
-  hipStream_t sc = nullptr, sd = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_c = nullptr, ev_d = nullptr;
 };
 
 namespace {
@@ -53,16 +46,12 @@ namespace {
     if (s_ != RFD_OK) return s_; \
   } while (0)
 
-constexpr int kMaxGwPoints = 32768;  // largest n or m (buffers of n^2 + m^2 + n m floats: up to 12 GiB)
+constexpr int kMaxGwPoints = 32768;  // largest n or m (one max(n, m)^2 float buffer: 4 GiB)
 
 void free_gw(rfd_gw_s* g) {
   for (rfd::WideField* w : {&g->c_sq1, &g->c_sq2, &g->d_sq1, &g->d_sq2, &g->c_t, &g->d_cross, &g->d_loss})
     rfd::wide_free(w);
-  if (g->sc) (void)hipStreamDestroy(g->sc);
-  if (g->sd) (void)hipStreamDestroy(g->sd);
-  for (hipEvent_t e : {g->ev_fork, g->ev_c, g->ev_d})
-    if (e) (void)hipEventDestroy(e);
-  void* ptrs[] = {g->Bc, g->Bd, g->Bx, g->vec, g->colpart};
+  void* ptrs[] = {g->B, g->vec, g->colpart};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete g;
@@ -78,8 +67,7 @@ rfd_status hadamard_square(const rfd::WideField& W1, const rfd::WideField& W2, f
   return RFD_OK;
 }
 
-// p, q, v1, v2 into g->vec and FM_C(T)^T (m x n) into g->Bx; on return
-// `st` is ordered after all of it.
+// p, q, v1, v2 into g->vec and FM_C(T)^T (m x n) into g->B.
 rfd_status enqueue_terms(rfd_gw_s* g, const float* T, int64_t ldT, hipStream_t st) {
   if (!T || ldT < g->m) return RFD_ERR_INVALID_ARG;
   if (g->pc->N != g->n || g->pd->N != g->m) return RFD_ERR_INVALID_ARG;  // a cloud changed size
@@ -88,18 +76,11 @@ rfd_status enqueue_terms(rfd_gw_s* g, const float* T, int64_t ldT, hipStream_t s
   RFDCK(rfd::ensure_core(g->pc, st));
   RFDCK(rfd::ensure_core(g->pd, st));
   HIPCK(rfd::launch_gw_margins(T, ldT, n, m, p, q, g->colpart, st));
-  HIPCK(hipEventRecord(g->ev_fork, st));
-  HIPCK(hipStreamWaitEvent(g->sc, g->ev_fork, 0));
-  HIPCK(hipStreamWaitEvent(g->sd, g->ev_fork, 0));
-  RFDCK(hadamard_square(g->c_sq1, g->c_sq2, v1, g->sc));
-  HIPCK(hipEventRecord(g->ev_c, g->sc));
-  RFDCK(hadamard_square(g->d_sq1, g->d_sq2, v2, g->sd));
-  HIPCK(hipEventRecord(g->ev_d, g->sd));
-  // Bx = FM_C(T)^T (m x n), beside the two terms
+  RFDCK(hadamard_square(g->c_sq1, g->c_sq2, v1, st));
+  RFDCK(hadamard_square(g->d_sq1, g->d_sq2, v2, st));
+  // B = FM_C(T)^T (m x n)
   HIPCK(rfd::wide_set_input(&g->c_t, T, ldT, st));
   HIPCK(rfd::wide_enqueue(&g->c_t, st));
-  HIPCK(hipStreamWaitEvent(st, g->ev_c, 0));
-  HIPCK(hipStreamWaitEvent(st, g->ev_d, 0));
   return RFD_OK;
 }
 
@@ -120,14 +101,8 @@ rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out) {
   const int n = (int)pc->N, m = (int)pd->N;
   g->n = n;
   g->m = m;
-  bool ok = hipMalloc((void**)&g->Bc, sizeof(float) * (size_t)n * n) == hipSuccess &&
-            hipMalloc((void**)&g->Bd, sizeof(float) * (size_t)m * m) == hipSuccess &&
-            hipMalloc((void**)&g->Bx, sizeof(float) * (size_t)m * n) == hipSuccess &&
-            hipStreamCreateWithFlags(&g->sc, hipStreamNonBlocking) == hipSuccess &&
-            hipStreamCreateWithFlags(&g->sd, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&g->ev_c, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&g->ev_d, hipEventDisableTiming) == hipSuccess &&
+  const size_t k = (size_t)(n > m ? n : m);
+  bool ok = hipMalloc((void**)&g->B, sizeof(float) * k * k) == hipSuccess &&
             hipMalloc((void**)&g->vec, sizeof(float) * 2 * (size_t)(n + m)) == hipSuccess &&
             hipMalloc((void**)&g->colpart, sizeof(double) * rfd::gw_margin_scratch_doubles(n, m)) == hipSuccess;
   rfd_status s = ok ? RFD_OK : RFD_ERR_DEVICE;
@@ -139,13 +114,13 @@ rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out) {
     }
   }
   float* p = g->vec;  // p (n), then q (m)
-  if (s == RFD_OK) s = rfd::wide_create(pc, n, nullptr, n, g->Bc, n, &g->c_sq1, true, p);
-  if (s == RFD_OK) s = rfd::wide_create(pc, n, g->Bc, n, nullptr, n, &g->c_sq2);
-  if (s == RFD_OK) s = rfd::wide_create(pd, m, nullptr, m, g->Bd, m, &g->d_sq1, true, p + n);
-  if (s == RFD_OK) s = rfd::wide_create(pd, m, g->Bd, m, nullptr, m, &g->d_sq2);
-  if (s == RFD_OK) s = rfd::wide_create(pc, m, nullptr, m, g->Bx, n, &g->c_t, true);
-  if (s == RFD_OK) s = rfd::wide_create(pd, n, g->Bx, n, g->Bx, n, &g->d_cross);
-  if (s == RFD_OK) s = rfd::wide_create(pd, n, g->Bx, n, nullptr, m, &g->d_loss, true);
+  if (s == RFD_OK) s = rfd::wide_create(pc, n, nullptr, n, g->B, n, &g->c_sq1, true, p);
+  if (s == RFD_OK) s = rfd::wide_create(pc, n, g->B, n, nullptr, n, &g->c_sq2);
+  if (s == RFD_OK) s = rfd::wide_create(pd, m, nullptr, m, g->B, m, &g->d_sq1, true, p + n);
+  if (s == RFD_OK) s = rfd::wide_create(pd, m, g->B, m, nullptr, m, &g->d_sq2);
+  if (s == RFD_OK) s = rfd::wide_create(pc, m, nullptr, m, g->B, n, &g->c_t, true);
+  if (s == RFD_OK) s = rfd::wide_create(pd, n, g->B, n, g->B, n, &g->d_cross);
+  if (s == RFD_OK) s = rfd::wide_create(pd, n, g->B, n, nullptr, m, &g->d_loss, true);
   if (s != RFD_OK) {
     free_gw(g);
     return s;
@@ -170,12 +145,12 @@ rfd_status rfd_gw_terms(rfd_gw_t g, const float* T, int64_t ldT, float* v1, floa
   if (!g || !v1 || !v2 || !W3 || ldW < g->m) return RFD_ERR_INVALID_ARG;
   const hipStream_t st = (hipStream_t)stream;
   RFDCK(enqueue_terms(g, T, ldT, st));
-  HIPCK(rfd::wide_enqueue(&g->d_cross, st));  // Bx <- FM_D(Bx) = W3^T
+  HIPCK(rfd::wide_enqueue(&g->d_cross, st));  // B <- FM_D(B) = W3^T
   const int n = g->n, m = g->m;
   const float* dv1 = g->vec + n + m;
   HIPCK(hipMemcpyAsync(v1, dv1, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
   HIPCK(hipMemcpyAsync(v2, dv1 + n, sizeof(float) * m, hipMemcpyDeviceToDevice, st));
-  HIPCK(rfd::launch_gw_transpose(g->Bx, n, m, n, W3, ldW, st));
+  HIPCK(rfd::launch_gw_transpose(g->B, n, m, n, W3, ldW, st));
   return RFD_OK;
 }
 
