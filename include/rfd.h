@@ -314,7 +314,7 @@ rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out);
 
 /* L = v1 1^T + 1 v2^T - 2 C T D^T for the coupling T (n x m float32,
  * row-major, leading dimension ldT >= m, device), written to L (n x m,
- * ldL >= m, device; must not overlap T), with p = T 1, q = T^T 1,
+ * ldL >= m, device; overlapping T is an error), with p = T 1, q = T^T 1,
  * v1 = diag(C (C diag p)^T) = C^{o2} p and v2 = D^{o2} q, each Hadamard-square
  * action taken as two operator actions (the subsection "Estimating the Action
  * of Hadamard Square of Matrices on Vectors"), and C T D^T as

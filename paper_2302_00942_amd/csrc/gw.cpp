@@ -131,6 +131,11 @@ rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out) {
 
 rfd_status rfd_gw_loss(rfd_gw_t g, const float* T, int64_t ldT, float* L, int64_t ldL, rfd_stream_t stream) {
   if (!g || !L || ldL < g->m) return RFD_ERR_INVALID_ARG;
+  if (T) {  // L and T must not overlap (T is the caller's input and stays intact)
+    const char *t0 = (const char*)T, *t1 = (const char*)(T + ((size_t)(g->n - 1) * ldT + g->m));
+    const char *l0 = (const char*)L, *l1 = (const char*)(L + ((size_t)(g->n - 1) * ldL + g->m));
+    if (t0 < l1 && l0 < t1) return RFD_ERR_INVALID_ARG;
+  }
   const hipStream_t st = (hipStream_t)stream;
   RFDCK(enqueue_terms(g, T, ldT, st));
   // L = (FM_D(B))^T combined as fma(-2, ., v1[i] + v2[j]) in the store

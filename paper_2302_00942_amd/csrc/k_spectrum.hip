@@ -239,14 +239,15 @@ __global__ __launch_bounds__(256) void k_spectrum_batch(const SpecArgs* __restri
 // The m x m core goes to LDS when it fits beside the kernel's own 15 KB.
 static size_t spectrum_lds_max() {
   constexpr size_t kLdsLimit = 160 * 1024 - 16 * 1024;
-  static int lds_ok = -1;  // whether the large-LDS attribute was accepted (set once per process)
-  if (lds_ok < 0) {
+  // whether the large-LDS attribute was accepted: decided once per process
+  // (a function-local static is initialised by exactly one thread)
+  static const bool lds_ok = [] {
     const bool a = hipFuncSetAttribute((const void*)k_spectrum<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)kLdsLimit) == hipSuccess;
     const bool b = hipFuncSetAttribute((const void*)k_spectrum_batch<true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit) == hipSuccess;
-    lds_ok = a && b ? 1 : 0;
-  }
+    return a && b;
+  }();
   return lds_ok ? kLdsLimit : 48 * 1024;
 }
 

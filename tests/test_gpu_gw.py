@@ -103,6 +103,9 @@ def test_gw_repeatable_and_rejects_bad_shapes(torch_cuda):
     assert np.array_equal(a, b)
     with pytest.raises(ValueError):
         g.loss(Td[:, :100].contiguous())
+    with pytest.raises(rfd.RfdError) as e:
+        g.loss(Td, out=Td)  # L may not overlap T
+    assert e.value.status == rfd.INVALID_ARG
     # a changed cloud size invalidates the workspace
     pd.features(torch.from_numpy(wl.box_cloud(151, 1)).cuda())
     with pytest.raises(rfd.RfdError) as e:
