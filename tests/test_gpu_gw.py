@@ -150,3 +150,40 @@ def test_gw_wide_integrations_equal_sliced_integrate(torch_cuda, prec):
     V = pd.integrate(U.t().contiguous())
     assert np.array_equal(V.t().cpu().numpy(), W3)
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_gw_largest_size_sampled(torch_cuda, prec):
+    """The largest source cloud the workspace takes (n = 32768) with a
+    2048-point target: sampled entries of L against the oracle, which forms
+    the needed columns of C and D one by one as operator actions on unit
+    vectors (C and D are symmetric): v1_i = sum_k C_ki^2 p_k,
+    v2_j = sum_l D_lj^2 q_l, W3_ij = C[:, i]^T T D[:, j]."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    n, m = 32768, 2048
+    c, d, T, pc, pd = _problem(torch, n, m, 16, prec, seed=13)
+    g = rfd.GW(pc, pd)
+    L = g.loss(torch.from_numpy(T).cuda()).cpu().numpy()
+    assert pc.check() == rfd.OK and pd.check() == rfd.OK
+    g.close()
+    aC = o.rfd_operator(c.X, c.eps, c.lam, c.m, c.seed)
+    aD = o.rfd_operator(d.X, d.eps, d.lam, d.m, d.seed)
+    T64 = T.astype(np.float64)
+    p, q = T64.sum(axis=1), T64.sum(axis=0)
+    rows = np.random.default_rng(1).choice(n, 6, replace=False)
+    cols = np.random.default_rng(2).choice(m, 6, replace=False)
+    E = np.zeros((n, len(rows)))
+    E[rows, np.arange(len(rows))] = 1.0
+    Ci = aC(E)  # columns i of C
+    F = np.zeros((m, len(cols)))
+    F[cols, np.arange(len(cols))] = 1.0
+    Dj = aD(F)  # columns j of D
+    v1 = (Ci * Ci * p[:, None]).sum(axis=0)
+    v2 = (Dj * Dj * q[:, None]).sum(axis=0)
+    W3 = Ci.T @ (T64 @ Dj)
+    ref = v1[:, None] + v2[None, :] - 2.0 * W3
+    got = L[np.ix_(rows, cols)]
+    e = o.relf(got, ref)
+    print(f"GW n={n} m={m} {prec}: sampled relF={e:.2e}")
+    assert e <= 2 * BAR[prec]
