@@ -416,11 +416,15 @@ rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan) {
     }
   }
   int zero = 0;
+  const std::vector<unsigned> zero_bar(rfd::kBarrierWords, 0u);
   ok = hipMemcpy(d.om, om.data(), sizeof(float4) * fp, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(d.cvec, cv.data(), sizeof(double) * M, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(d.svec, sv.data(), sizeof(double) * M, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(d.flag, &zero, sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(d.sdev, &zero, sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+       hipMemcpy(d.sdev, &zero, sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+       // grid-barrier counters: zeroed once here; every phi_1 launch leaves them zero
+       hipMemcpy(d.barrier, zero_bar.data(), sizeof(unsigned) * rfd::kBarrierWords, hipMemcpyHostToDevice) ==
+           hipSuccess;
   if (!ok) {
     free_dev(d);
     delete p;

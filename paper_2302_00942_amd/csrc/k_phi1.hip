@@ -38,7 +38,7 @@ struct Phi1Args {
   double* S64;         // m x m canonical: lambda phi_1(lambda M)
   double* T64;         // m x m device order: diag(c s) S diag(c)
   int* flag;           // bit 0: non-finite input; bit 1: overflow in phi_1; bit 2: barrier timeout
-  unsigned* barrier;   // grid barrier counter (zeroed before launch)
+  unsigned* barrier;   // grid barrier counters (zero at launch; each launch leaves them zero)
 };
 
 // The action form: G' = diag(c s) S diag(c) H0 for one channel block, without S.
@@ -53,6 +53,7 @@ constexpr int kThinWidth = 32;
 
 struct WgBarrier {
   __device__ __forceinline__ void sync() { __syncthreads(); }
+  __device__ __forceinline__ void finish() {}
 };
 
 // Two-level counter barrier over a cooperative grid. Workgroups arrive on the
@@ -66,7 +67,11 @@ struct WgBarrier {
 // and followed by one acquire fence. On gfx950 that is one L2 write-back
 // before the arrival and one invalidate after the wait. The wait is bounded:
 // on timeout the flag gets bit 2 and the workgroup proceeds, so every wave
-// always exits.
+// always exits. The counters start at zero (the plan zeroes them when it is
+// created) and every launch leaves them at zero: after its last wait each
+// workgroup arrives on an exit counter (word 1), and the last arrival, which
+// knows that no workgroup of the launch reads a counter again, clears them
+// all, so no clearing kernel runs between launches on a stream.
 constexpr int kBarGroup = 16;
 constexpr int kBarStride = 32;        // unsigned words between counters (128 bytes)
 constexpr int kBarWords = kBarStride * (1 + 256 / kBarGroup);
@@ -103,6 +108,17 @@ struct GridBarrier {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
+  }
+  // Called once by every workgroup after its last sync.
+  __device__ __forceinline__ void finish() {
+    if (threadIdx.x != 0) return;
+    const unsigned old = __hip_atomic_fetch_add(ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 != nblocks) return;
+    const unsigned groups = (nblocks + kBarGroup - 1) / kBarGroup;
+    for (unsigned g = 0; g < groups; ++g)
+      __hip_atomic_store(ctr + kBarStride * (1 + g), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(ctr + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 };
 
@@ -711,6 +727,7 @@ __global__ __launch_bounds__(256) void k_phi1_grid(Phi1Args a) {
   extern __shared__ double lds[];
   GridBarrier bar{a.barrier, gridDim.x, 0u, a.flag};
   phi1_body<M, (M < kGridKB ? M : kGridKB), true>(a, (int)blockIdx.x, (int)gridDim.x, lds, bar);
+  bar.finish();
 }
 
 template <int M>
@@ -718,6 +735,7 @@ __global__ __launch_bounds__(256) void k_phi1_apply_grid(Phi1Args a, ApplyArgs a
   extern __shared__ double lds[];
   GridBarrier bar{a.barrier, gridDim.x, 0u, a.flag};
   apply_body<M, (M < kGridKB ? M : kGridKB), true>(a, ap, (int)blockIdx.x, (int)gridDim.x, lds, bar);
+  bar.finish();
 }
 
 template <int M>
@@ -728,11 +746,6 @@ __global__ __launch_bounds__(256) void k_phi1_apply_wg(const Phi1Args* __restric
   const ApplyArgs ap = aargs[blockIdx.x];
   WgBarrier bar;
   apply_body<M, wg_kb<M>(), wg_all<M>()>(a, ap, 0, 1, lds, bar);
-}
-
-__global__ void k_zero_u32(unsigned* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
 }
 
 // LDS bytes of the phi_1 kernels for padded size m.
@@ -767,9 +780,6 @@ static hipError_t launch_phi1_m(Phi1Args& a, hipStream_t st) {
   int nw = tuned(kTunePhi1Workgroups, M, 0, 1, 0, nb * nb);
   if (nw < 1) nw = 1;
   if (nw > nb * nb) nw = nb * nb;
-  hipLaunchKernelGGL(k_zero_u32, dim3((kBarWords + 255) / 256), dim3(256), 0, st, a.barrier, kBarWords);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   void* kargs[] = {&a};
   ProfileScope prof(kKPhi1, st);
   return hipLaunchCooperativeKernel((const void*)k_phi1_grid<M>, dim3(nw), dim3(256), kargs, (unsigned)lds, st);
@@ -794,9 +804,6 @@ static hipError_t launch_apply_m(Phi1Args& a, ApplyArgs& ap, hipStream_t st) {
   if (e != hipSuccess) return e;
   constexpr int nb = M / 32;
   const int nw = nb * nb + nb;  // full tiles plus thin row tiles
-  hipLaunchKernelGGL(k_zero_u32, dim3((kBarWords + 255) / 256), dim3(256), 0, st, a.barrier, kBarWords);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   void* kargs[] = {&a, &ap};
   ProfileScope prof(kKPhi1Apply, st);
   return hipLaunchCooperativeKernel((const void*)k_phi1_apply_grid<M>, dim3(nw), dim3(256), kargs, (unsigned)lds, st);
