@@ -294,6 +294,38 @@ def test_autotune_never_changes_results(torch_cuda):
     rfd.tune_reset()
 
 
+def test_phi1_launches_back_to_back(torch_cuda):
+    """Consecutive phi_1 launches on one plan and one stream with no host
+    synchronisation between them. The cooperative kernels' grid-barrier
+    counters are zeroed once at plan creation and left at zero by every
+    launch, with no clearing kernel in between: the action-form kernel
+    (8 channels) and the full-core kernel (33 channels), interleaved and
+    after the workgroup count is retuned, give the same bits every time and
+    never flag a barrier timeout."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    n = 6000
+    X = torch.from_numpy(wl.torus(n, 41, jitter=0.005)).cuda()
+    F = wl.field(n, 33, 42)
+    Fa = torch.from_numpy(np.ascontiguousarray(F[:, :8])).cuda()
+    Fb = torch.from_numpy(F).cuda()
+    try:
+        for m in (64, 256):
+            plan = rfd.Plan(m, 0.05, -0.6, 9, precision="bf16")
+            a0 = plan.oneshot(X, Fa).cpu().numpy()
+            b0 = plan.oneshot(X, Fb).cpu().numpy()
+            outs = [plan.oneshot(X, Fa if i % 2 == 0 else Fb) for i in range(12)]
+            plan.autotune_phi1(reps=2)
+            outs += [plan.oneshot(X, Fb), plan.oneshot(X, Fa), plan.oneshot(X, Fb)]
+            assert plan.check() == rfd.OK
+            for i, r in enumerate(outs):
+                ref = a0 if r.shape[1] == 8 else b0
+                assert np.array_equal(r.cpu().numpy(), ref), (m, i)
+            plan.close()
+    finally:
+        rfd.tune_reset()
+
+
 @pytest.mark.parametrize("m", [64, 128, 256])
 def test_action_form_matches_full_core(torch_cuda, m):
     """A one-shot call on a field of <= 32 channels takes phi_1 in action form
