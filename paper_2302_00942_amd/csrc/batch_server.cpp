@@ -51,6 +51,22 @@ std::vector<int2> expand_work(const std::vector<int64_t>& Ns, int tpi) {
   return we;
 }
 
+// Reorders fixed-size records (and, with bsz > 0, a parallel record array)
+// by descending N, ties in their original order.
+void longest_first(std::vector<unsigned char>& a, size_t asz, std::vector<unsigned char>& b, size_t bsz,
+                   const std::vector<int64_t>& Ns) {
+  std::vector<int> idx(Ns.size());
+  for (int i = 0; i < (int)idx.size(); ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return Ns[x] > Ns[y]; });
+  std::vector<unsigned char> a2(a.size()), b2(b.size());
+  for (size_t k = 0; k < idx.size(); ++k) {
+    memcpy(a2.data() + k * asz, a.data() + idx[k] * asz, asz);
+    if (bsz) memcpy(b2.data() + k * bsz, b.data() + idx[k] * bsz, bsz);
+  }
+  a.swap(a2);
+  if (bsz) b.swap(b2);
+}
+
 void free_batch(rfd_batch_s* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -126,6 +142,8 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
   std::vector<int2> wb;
   std::vector<unsigned char> args, args_apply, aargs;
   std::vector<rfd::CloudDesc> cl_full;
+  std::vector<int64_t> Ns_apply, Ns_full;
+  std::vector<unsigned char> aargs_none;
   const size_t PA = rfd::phi1_args_bytes(), AA = rfd::phi1_apply_args_bytes();
   for (int i = 0; i < n; ++i) {
     rfd_plan_s* p = plans[i];
@@ -162,12 +180,14 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
     const bool ap = ds[i] <= rfd::phi1_apply_max_width();
     b->applied.push_back(ap);
     if (ap) {
+      Ns_apply.push_back(N);
       args_apply.resize(args_apply.size() + PA);
       aargs.resize(aargs.size() + AA);
       rfd::phi1_fill_args(p, args_apply.data() + args_apply.size() - PA);
       rfd::phi1_fill_apply_args(p, ds[i], aargs.data() + aargs.size() - AA);
       ++b->n_apply;
     } else {
+      Ns_full.push_back(N);
       args.resize(args.size() + PA);
       rfd::phi1_fill_args(p, args.data() + args.size() - PA);
       cl_full.push_back(c);
@@ -175,6 +195,14 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
       ++b->n_full;
     }
   }
+  // phi_1 records largest cloud first. The per-cloud kernels run one
+  // workgroup per cloud and, at m = 128 and 256, one workgroup per CU (LDS),
+  // so the records queue for free CUs; the core's norm, and with it the
+  // number of squarings, grows with N, so dispatching the large clouds first
+  // leaves the short ones to fill the tail. Each record carries its own
+  // pointers: the order changes no result.
+  longest_first(args_apply, PA, aargs, AA, Ns_apply);
+  longest_first(args, PA, aargs_none, 0, Ns_full);
   for (int i = 0; i < n; ++i) {
     b->bound.push_back(plans[i]->dev.X);
     b->bound.push_back(plans[i]->dev.partials);
