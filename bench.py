@@ -499,6 +499,8 @@ def main() -> int:
                     help="write the spectrum workload (2048-point sphere) for paper_2302_00942_amd/rfd_run and exit")
     ap.add_argument("--dump-inputs", metavar="DIR", help="write the cloud for paper_2302_00942_amd/rfd_run and exit")
     ap.add_argument("--gw-only", action="store_true", help="run only the Gromov-Wasserstein and spectrum stages")
+    ap.add_argument("--batch-only", action="store_true", help="run only the 512-cloud batch stage")
+    ap.add_argument("--dump-batch", metavar="DIR", help="write the 512-cloud batch for paper_2302_00942_amd/rfd_run batch and exit")
     ap.add_argument("--dump-gw", metavar="DIR", help="write the GW problem (n=3000 per cloud) for paper_2302_00942_amd/rfd_run and exit")
     args = ap.parse_args()
     if args.dump_inputs:
@@ -520,6 +522,19 @@ def main() -> int:
         with open(os.path.join(args.dump_gw, "meta_gw.txt"), "w") as fh:
             fh.write(f"{c.n} {dcl.n} {c.m} {c.eps!r} {c.lam!r} {c.seed} {dcl.seed}\n")
         return 0
+    if args.dump_batch:
+        from paper_2302_00942_amd import workloads as wl
+        clouds = wl.uneven_batch()
+        os.makedirs(args.dump_batch, exist_ok=True)
+        np.concatenate([c.X for c in clouds]).astype(np.float32).tofile(os.path.join(args.dump_batch, "Xb.bin"))
+        np.concatenate([c.F for c in clouds]).astype(np.float32).tofile(os.path.join(args.dump_batch, "Fb.bin"))
+        c0 = clouds[0]
+        with open(os.path.join(args.dump_batch, "meta_batch.txt"), "w") as fh:
+            fh.write(f"{len(clouds)} {c0.d} {c0.m} {c0.eps!r} {c0.lam!r}\n")
+            for c in clouds:
+                assert (c.d, c.m, c.eps, c.lam) == (c0.d, c0.m, c0.eps, c0.lam)
+                fh.write(f"{c.n} {c.seed}\n")
+        return 0
     if args.dump_spectrum:
         from paper_2302_00942_amd import workloads as wl
         os.makedirs(args.dump_spectrum, exist_ok=True)
@@ -537,6 +552,9 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     rfd.lib()
+    if args.batch_only:
+        print(json.dumps({"batched": bench_batch(torch, rfd, wl, max(5, args.steps))}))
+        return 0
     if args.gw_only:
         print(json.dumps({"gromov_wasserstein": bench_gw(torch, rfd, wl, max(5, args.steps)),
                           "kernel_spectrum": bench_spectrum(torch, rfd, wl, max(5, args.steps))}))

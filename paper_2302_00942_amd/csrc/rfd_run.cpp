@@ -3,6 +3,7 @@
 //   rfd_run DIR STEPS [PREC]
 //   rfd_run gw DIR STEPS [PREC]
 //   rfd_run spectrum DIR STEPS M
+//   rfd_run batch DIR STEPS [PREC]
 //   rfd_run copy MIB
 //
 // DIR holds X.bin (N x 3 float32), F.bin (N x d float32) and meta.txt
@@ -14,7 +15,11 @@
 // DIR`, and runs STEPS Gromov-Wasserstein loss matrices. The spectrum form
 // reads Xs.bin (N x 3) and meta_spec.txt ("N k eps lambda seed"), as written
 // by `bench.py --dump-spectrum DIR`, computes BF16 features with M features
-// and runs STEPS spectrum calls (k smallest eigenvalues). The copy form
+// and runs STEPS spectrum calls (k smallest eigenvalues). The batch form
+// reads Xb.bin and Fb.bin (the clouds' points and fields, concatenated) and
+// meta_batch.txt ("count d m eps lambda", then "N seed" per cloud), as
+// written by `bench.py --dump-batch DIR`, creates one batch over all clouds
+// and times STEPS graph replays of it on a stream of its own. The copy form
 // runs one device-to-device copy of MIB mebibytes (a reference kernel of
 // known traffic for calibrating hardware byte counters).
 #include <hip/hip_runtime.h>
@@ -171,9 +176,103 @@ static int spectrum_mode(const std::string& dir, int steps, int m) {
   return st == RFD_OK ? 0 : 1;
 }
 
+static int batch_mode(const std::string& dir, int steps, int prec) {
+  int count = 0, d = 0, m = 0;
+  double eps = 0, lam = 0;
+  FILE* mf = fopen((dir + "/meta_batch.txt").c_str(), "r");
+  if (!mf || fscanf(mf, "%d %d %d %lf %lf", &count, &d, &m, &eps, &lam) != 5 || count <= 0 || d <= 0 || d > 64 ||
+      steps <= 0) {
+    fprintf(stderr, "cannot read %s/meta_batch.txt\n", dir.c_str());
+    if (mf) fclose(mf);
+    return 1;
+  }
+  std::vector<int64_t> Ns(count);
+  std::vector<unsigned long long> seeds(count);
+  long long total = 0;
+  for (int i = 0; i < count; ++i) {
+    long long n = 0;
+    if (fscanf(mf, "%lld %llu", &n, &seeds[i]) != 2 || n <= 0) {
+      fprintf(stderr, "bad cloud line %d\n", i);
+      fclose(mf);
+      return 1;
+    }
+    Ns[i] = n;
+    total += n;
+  }
+  fclose(mf);
+  std::vector<float> X((size_t)total * 3), F((size_t)total * d);
+  if (!read_file(dir + "/Xb.bin", X.data(), X.size() * 4) || !read_file(dir + "/Fb.bin", F.data(), F.size() * 4)) {
+    fprintf(stderr, "cannot read Xb.bin / Fb.bin\n");
+    return 1;
+  }
+  float* dX = upload(X);
+  float* dF = upload(F);
+  float* dO = nullptr;
+  if (!dX || !dF || hipMalloc(&dO, F.size() * 4) != hipSuccess) {
+    fprintf(stderr, "device buffers failed\n");
+    return 1;
+  }
+  std::vector<rfd_plan_t> plans(count, nullptr);
+  std::vector<const float*> Xs(count), Fs(count);
+  std::vector<float*> outs(count);
+  std::vector<int64_t> lds(count, d);
+  std::vector<int32_t> ds(count, d);
+  size_t off = 0;
+  rfd_status st = RFD_OK;
+  for (int i = 0; i < count && st == RFD_OK; ++i) {
+    rfd_params p;
+    memset(&p, 0, sizeof(p));
+    p.m = m;
+    p.shape = RFD_BALL_L2;
+    p.precision = prec;
+    p.eps = eps;
+    p.lambda = lam;
+    p.seed = seeds[i];
+    st = rfd_plan_create(&p, &plans[i]);
+    Xs[i] = dX + off * 3;
+    Fs[i] = dF + off * d;
+    outs[i] = dO + off * d;
+    off += (size_t)Ns[i];
+  }
+  rfd_batch_t batch = nullptr;
+  if (st == RFD_OK)
+    st = rfd_batch_create(plans.data(), Xs.data(), Ns.data(), Fs.data(), lds.data(), ds.data(), outs.data(),
+                          lds.data(), count, &batch);
+  hipStream_t s = nullptr;
+  if (st == RFD_OK && hipStreamCreate(&s) != hipSuccess) st = RFD_ERR_DEVICE;
+  // an eager launch, then the one that records the graph; the timed ones replay it
+  for (int i = 0; i < 2 && st == RFD_OK; ++i) st = rfd_batch_launch(batch, s);
+  if (st == RFD_OK && hipStreamSynchronize(s) != hipSuccess) st = RFD_ERR_DEVICE;
+  float ms = 0.f;
+  if (st == RFD_OK) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(a, s);
+    for (int i = 0; i < steps && st == RFD_OK; ++i) st = rfd_batch_launch(batch, s);
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    (void)hipEventElapsedTime(&ms, a, b);
+  }
+  for (int i = 0; i < count && st == RFD_OK; ++i) st = rfd_plan_check(plans[i], s);
+  printf("rfd_run batch clouds=%d points=%lld d=%d m=%d prec=%s steps=%d: %.4f ms/batch (%s)\n", count, total, d, m,
+         prec == RFD_BF16 ? "bf16" : "fp32", steps, ms / steps, rfd_status_string(st));
+  fflush(stdout);
+  if (batch) rfd_batch_destroy(batch);
+  for (rfd_plan_t p : plans)
+    if (p) rfd_plan_destroy(p);
+  if (s) (void)hipStreamDestroy(s);
+  (void)hipFree(dX);
+  (void)hipFree(dF);
+  (void)hipFree(dO);
+  return st == RFD_OK ? 0 : 1;
+}
+
 int main(int argc, char** argv) {
   if (argc == 3 && strcmp(argv[1], "copy") == 0) return copy_mode(atoll(argv[2]));
   if (argc == 5 && strcmp(argv[1], "spectrum") == 0) return spectrum_mode(argv[2], atoi(argv[3]), atoi(argv[4]));
+  if (argc >= 4 && strcmp(argv[1], "batch") == 0)
+    return batch_mode(argv[2], atoi(argv[3]), (argc > 4 && strcmp(argv[4], "fp32") == 0) ? RFD_FP32 : RFD_BF16);
   if (argc >= 4 && strcmp(argv[1], "gw") == 0)
     return gw_mode(argv[2], atoi(argv[3]), (argc > 4 && strcmp(argv[4], "fp32") == 0) ? RFD_FP32 : RFD_BF16);
   if (argc < 3) {
