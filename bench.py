@@ -543,7 +543,7 @@ def main() -> int:
             fh.write("2048 32 0.1 -0.1 7\n")
         return 0
     if args.gpus != 1:
-        print("bench.py measures one MI355X: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one MI355X: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         return 2
     import torch
     from paper_2302_00942_amd import rfd, workloads as wl
