@@ -124,6 +124,29 @@ def test_positive_lambda(torch_cuda):
     compare(out, ref, F, "fp32", "lambda>0")
 
 
+@pytest.mark.parametrize("m", [64, 256])
+def test_widest_field(torch_cuda, m):
+    """The widest field one call accepts (1024 channels: the fused first pass
+    takes one slice, the rest runs slice by slice) against the oracle, and
+    1025 channels refused before any launch."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    n, eps, lam, seed = 600, 0.2, -0.4, 13
+    X = wl.sphere(n, 51)
+    F = wl.field(n, 1024, 52)
+    ref = o.rfd_integrate(X, F, eps, lam, m, seed)
+    for prec in ("fp32", "bf16"):
+        out, plan, st = run_oneshot(torch, X, F, eps, lam, m, seed, prec)
+        assert st == rfd.OK
+        compare(out, ref, F, prec, f"d=1024 m={m}")
+        Fd = torch.from_numpy(F).cuda()
+        r = plan.integrate(Fd).cpu().numpy()  # resident plan, same field
+        compare(r, ref, F, prec, f"resident d=1024 m={m}")
+        with pytest.raises(rfd.RfdError) as e:
+            plan.oneshot(torch.from_numpy(X).cuda(), torch.zeros((n, 1025), device="cuda"))
+        assert e.value.status == rfd.INVALID_ARG
+
+
 def test_single_point_closed_form(torch_cuda):
     X = np.array([[0.3, -0.2, 0.9]], dtype=np.float32)
     F = np.array([[1.5, -2.0, 0.25, 4.0]], dtype=np.float32)
