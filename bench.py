@@ -92,7 +92,23 @@ def phi1_apply_flops(m: int, s: int) -> float:
     return (8 + s - 1) * 2.0 * m ** 3 + (8 + s) * 2.0 * m * m * 32
 
 
-def algorithmic(kernel: str, N: int, m: int, d: int, s: int, nparts: int):
+THETA13 = 5.371920351148152  # Pade [13/13] scaling threshold (Higham 2005)
+
+
+def pade_scaling_power(norm1: float) -> int:
+    """s = max(0, ceil(log2(||lambda M||_1 / theta_13))): the squarings a
+    Pade [13/13] scaling-and-squaring evaluation of the core takes."""
+    return max(0, math.ceil(math.log2(norm1 / THETA13))) if norm1 > THETA13 else 0
+
+
+def phi1_counted_flops(m: int, s13: int) -> float:
+    # the fixed count of the phi_1 roof: (32 + 4 s) m^3 FP64 flops for a Pade [13/13]
+    # evaluation of exp and phi_1 of an m x m core with s squarings, whatever scheme
+    # the kernel uses
+    return (32 + 4 * s13) * float(m) ** 3
+
+
+def algorithmic(kernel: str, N: int, m: int, d: int, s: int, nparts: int, s13: int = 0):
     """(bytes, flops, transcendentals) per launch, from the per-point figures:
     pass 1 (Gram + B^T F) reads X (12 B) and F (4d B) and does m^2 + 2md flops
     (Gram halved by symmetry) and m sin/cos; the expansion reads X and F and
@@ -104,17 +120,18 @@ def algorithmic(kernel: str, N: int, m: int, d: int, s: int, nparts: int):
     if kernel == "k_expand":
         return N * (12 + 8 * d), N * 2.0 * m * d, N * m
     if kernel == "k_phi1":
-        return 12 * m * m * 8, phi1_flops(m, s), 0
+        return 12 * m * m * 8, phi1_counted_flops(m, s13), 0
     if kernel == "k_phi1_apply":
-        return 8 * m * m * 8, phi1_apply_flops(m, s), 0
+        return 8 * m * m * 8, phi1_counted_flops(m, s13), 0
     if kernel == "k_reduce":
         floats = m * (m + 1) / 2 + m * d
         return nparts * floats * 4, nparts * floats, 0
     return 0, 0, 0
 
 
-def roofline(kernel: str, avg_ms: float, N: int, m: int, d: int, s: int, nparts: int, prec: str, workload: str):
-    B, Fl, T = algorithmic(kernel, N, m, d, s, nparts)
+def roofline(kernel: str, avg_ms: float, N: int, m: int, d: int, s: int, nparts: int, prec: str, workload: str,
+             s13: int = 0):
+    B, Fl, T = algorithmic(kernel, N, m, d, s, nparts, s13)
     sec = avg_ms * 1e-3
     cands = []
     if B:
@@ -133,6 +150,11 @@ def roofline(kernel: str, avg_ms: float, N: int, m: int, d: int, s: int, nparts:
            "frac": round(ach / peak, 4), "traffic": traffic, "avg_us": round(avg_ms * 1e3, 2),
            "all": {c[0]: round(c[1] / c[2], 4) for c in cands}}
     if kernel in ("k_phi1", "k_phi1_apply"):
+        out["flops_counted"] = f"(32 + 4 s) m^3 with s = {s13} (Pade [13/13] on ||lambda M||_1), m = {m}"
+        # the flops the kernel's own scheme performs (degree-23 Taylor with s_taylor squarings)
+        own = phi1_apply_flops(m, s) if kernel == "k_phi1_apply" else phi1_flops(m, s)
+        out["frac_own_scheme"] = round(own / sec / 1e12 / PEAK["fp64_TFs"], 4)
+        out["s_taylor"] = s
         # grid barriers in one call: set-up, Y^2, (Y^3, Y^4), five Horner steps, s squarings
         phases = 8 + s
         out["dependent_phases"] = phases
@@ -586,11 +608,12 @@ def main() -> int:
             step()
         kern = rfd.profile_read(reset=True)
         rfd.profile_enable(False)
-        _, _, s = plan.core()
+        Mc, _, s = plan.core()
+        s13 = pade_scaling_power(float(np.abs(cloud.lam * Mc).sum(axis=0).max()))
         # resident plan: integrate only (two passes over X and F)
         plan.features(X)
         rms, rp50, rp99 = time_steps(lambda: plan.integrate(F, out=out), args.steps, args.warmup, torch)
-        res[prec] = dict(ms=ms, p50=p50, p99=p99, kern=kern, s=s, resident_ms=rms)
+        res[prec] = dict(ms=ms, p50=p50, p99=p99, kern=kern, s=s, s13=s13, resident_ms=rms)
         plan.close()
 
     line = {
@@ -624,9 +647,10 @@ def main() -> int:
     from paper_2302_00942_amd.rfd import lib  # noqa: F401
     nparts = n_partials(N)
     dom = max(kern.items(), key=lambda kv: kv[1][0])[0]
+    s13 = res["bf16"]["s13"]
     line["roofline"] = roofline(dom, kern[dom][0] / kern[dom][1], N, m, d, res["bf16"]["s"], nparts, "bf16",
-                                workload)
-    line["roofline_all"] = {k: roofline(k, v[0] / v[1], N, m, d, res["bf16"]["s"], nparts, "bf16", workload)
+                                workload, s13)
+    line["roofline_all"] = {k: roofline(k, v[0] / v[1], N, m, d, res["bf16"]["s"], nparts, "bf16", workload, s13)
                             for k, v in kern.items() if k in KERNEL_SOURCES}
     if not args.no_extras:
         line["batched"] = bench_batch(torch, rfd, wl, max(5, args.steps))

@@ -66,7 +66,10 @@ typedef enum {
  * from FP32 phases; accumulation is FP32; phi_1 is FP64). */
 typedef enum {
   RFD_FP32 = 0,  /* FP32 features, FP32 matrix cores (v_mfma_f32_*_f32) */
-  RFD_BF16 = 1   /* features and F rounded to BF16 (RNE) as MFMA operands */
+  RFD_BF16 = 1   /* features rounded to BF16 (RNE) as MFMA operands; the field F
+                    (pass 1) and G (pass 2) enter as a BF16 hi + lo pair
+                    (hi = bf16(x), lo = bf16(x - hi), two MFMAs), so the features
+                    are the only BF16 rounding on the data path */
 } rfd_precision;
 
 typedef struct {
@@ -151,6 +154,22 @@ rfd_status rfd_plan_check(rfd_plan_t plan, rfd_stream_t stream);
  * B^T A in the feature scaling c_k (the same matrix the paper's core uses). */
 rfd_status rfd_plan_core(rfd_plan_t plan, double* M_mxm, double* S_mxm, int32_t* s_out,
                          rfd_stream_t stream);
+
+/* The plan's cloud size (the N of the last rfd_features / one-shot call, -1
+ * before any), its feature count m and the padded count the device uses (64,
+ * 128 or 256). Host only; any pointer may be NULL. Callers that pass F and
+ * out to rfd_integrate check their row counts against N with it. */
+rfd_status rfd_plan_info(rfd_plan_t plan, int64_t* N_out, int32_t* m_out, int32_t* padded_m_out);
+
+/* The field block of the last one-shot call (or batch item) whose phi_1 ran
+ * in action form (fields of <= 32 channels): H = B^T F (m x d, FP64,
+ * row-major, the paper's feature order, Sec. 2.4) as the phi_1 kernel read
+ * it, and G = lambda phi_1(lambda M) H (m x d, FP64) as it computed it, before
+ * G is rounded for the expansion. Synchronises `stream` first. Any pointer
+ * may be NULL; *d_out gets d. Errors: RFD_ERR_NOT_READY if no action-form
+ * call has run on the plan. For checking the FP64 core arithmetic. */
+rfd_status rfd_plan_action(rfd_plan_t plan, double* H_mxd, double* G_mxd, int32_t* d_out,
+                           rfd_stream_t stream);
 
 void rfd_plan_destroy(rfd_plan_t plan);
 
@@ -286,8 +305,10 @@ rfd_status rfd_plan_spectrum(rfd_plan_t plan, int32_t which, int64_t k, double* 
 /* rfd_plan_spectrum for n plans at once (one workgroup per cloud, one
  * launch): cloud i's k values go to outs[i] (device). Each plan appears once
  * and meets rfd_plan_spectrum's conditions, with k <= its N; the feature
- * counts may differ. The call copies n argument records to the device and
- * synchronises `stream` before returning. Errors: those of
+ * counts may differ. The call copies n argument records into a device buffer
+ * the library keeps per device and reuses (it is allocated only when n
+ * exceeds every earlier n on the device; rfd_library_release frees it), and
+ * synchronises `stream` before returning; concurrent calls are serialised. Errors: those of
  * rfd_plan_spectrum, RFD_ERR_INVALID_ARG for n < 0, null arrays or a plan
  * given twice; n = 0 or k = 0 is a no-op. */
 rfd_status rfd_spectrum_batch(const rfd_plan_t* plans, int32_t n, int32_t which, int64_t k, double* const* outs,
@@ -427,6 +448,14 @@ int32_t rfd_profile_read(double* total_ms, int64_t* counts, int32_t n, int32_t r
 
 /* Name of kernel id i (a static string), "?" when out of range. */
 const char* rfd_profile_kernel_name(int32_t id);
+
+/* Destroys the HIP objects the library keeps process-wide (the timing event
+ * pool, with profiling switched off, and the batched spectrum's argument
+ * buffers) after a device-wide wait, so that nothing
+ * of the library's is left for the runtime's exit-time teardown. Objects the
+ * caller created (plans, batches, loops, servers, GW workspaces) are the
+ * caller's to destroy first. Later calls recreate what they need. */
+void rfd_library_release(void);
 
 #ifdef __cplusplus
 }

@@ -362,10 +362,12 @@ def repeated_apply(clouds, v0, scales, lam_list, iters: int, omegas, ws):
     return v
 
 
-def rfd_operator(X, eps: float, lam: float, m: int, seed: int, shape: int = BALL_L2):
-    """x -> exp(lam A B^T) x on the cloud X with the frequencies of `seed`,
-    by the low-rank identity (Sec. 2.4): x + A (lam phi_1(lam B^T A)) (B^T x)."""
-    om, w = frequencies_and_weights(m, eps, seed, shape)
+def rfd_operator(X, eps: float, lam: float, m: int, seed: int, shape: int = BALL_L2,
+                 sigma: float = 0.0, radius: float = 0.0):
+    """x -> exp(lam A B^T) x on the cloud X with the frequencies of `seed`
+    (frequency law as in sample_frequencies), by the low-rank identity
+    (Sec. 2.4): x + A (lam phi_1(lam B^T A)) (B^T x)."""
+    om, w = frequencies_and_weights(m, eps, seed, shape, sigma, radius)
     Phi, sg = features(X, om, w)
     A = Phi * sg
     S = lam * phi1(lam * (Phi.T @ A))

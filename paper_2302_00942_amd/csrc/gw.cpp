@@ -23,6 +23,8 @@ struct rfd_gw_s {
   rfd_plan_s* pc = nullptr;
   rfd_plan_s* pd = nullptr;
   int n = 0, m = 0;
+  const float* xc = nullptr;  // the plans' point copies the wide fields were bound to
+  const float* xd = nullptr;
   float* B = nullptr;    // max(n, m)^2 floats
   float* vec = nullptr;  // p (n), q (m), v1 (n), v2 (m)
   double* colpart = nullptr;  // column-sum partials of the coupling
@@ -71,6 +73,9 @@ rfd_status hadamard_square(const rfd::WideField& W1, const rfd::WideField& W2, f
 rfd_status enqueue_terms(rfd_gw_s* g, const float* T, int64_t ldT, hipStream_t st) {
   if (!T || ldT < g->m) return RFD_ERR_INVALID_ARG;
   if (g->pc->N != g->n || g->pd->N != g->m) return RFD_ERR_INVALID_ARG;  // a cloud changed size
+  // the wide fields read the plans' point copies bound at creation: a larger
+  // call in between reallocates them
+  if (g->pc->dev.X != g->xc || g->pd->dev.X != g->xd) return RFD_ERR_INVALID_ARG;
   const int n = g->n, m = g->m;
   float *p = g->vec, *q = p + n, *v1 = q + m, *v2 = v1 + n;
   RFDCK(rfd::ensure_core(g->pc, st));
@@ -101,6 +106,8 @@ rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out) {
   const int n = (int)pc->N, m = (int)pd->N;
   g->n = n;
   g->m = m;
+  g->xc = pc->dev.X;
+  g->xd = pd->dev.X;
   const size_t k = (size_t)(n > m ? n : m);
   bool ok = hipMalloc((void**)&g->B, sizeof(float) * k * k) == hipSuccess &&
             hipMalloc((void**)&g->vec, sizeof(float) * 2 * (size_t)(n + m)) == hipSuccess &&

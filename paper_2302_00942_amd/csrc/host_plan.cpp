@@ -116,7 +116,7 @@ hipError_t dalloc(T** p, size_t count) {
 }
 
 void free_dev(rfd::PlanDev& d) {
-  void* ptrs[] = {d.om, d.cvec, d.svec, d.X, d.Mraw, d.H0, d.S64, d.T64, d.G32, d.Gt16,
+  void* ptrs[] = {d.om, d.cvec, d.svec, d.X, d.Mraw, d.H0, d.S64, d.T64, d.G32, d.Gt16, d.G64,
                   d.phi_ws, d.sdev, d.barrier, d.flag, d.lvl, d.partials};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -243,7 +243,7 @@ void free_plan_device(rfd_plan_s* p) {
 size_t plan_fixed_bytes(int M) {
   const size_t mm = (size_t)M * M;
   return sizeof(float4) * (M / 2) + 2 * sizeof(double) * M + 3 * sizeof(double) * mm +
-         sizeof(double) * M * 64 + sizeof(float) * M * 64 + 2 * sizeof(__bf16) * M * 64 +
+         sizeof(double) * M * 64 + sizeof(float) * M * 64 + 2 * sizeof(__bf16) * M * 64 + sizeof(double) * M * 32 +
          sizeof(double) * phi1_ws_doubles(M) + 2 * sizeof(int) +
          sizeof(unsigned) * kBarrierWords + sizeof(double) * reduce_scratch_doubles(M);
 }
@@ -394,6 +394,7 @@ rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan) {
             dalloc(&d.Mraw, mm) == hipSuccess && dalloc(&d.H0, (size_t)M * 64) == hipSuccess &&
             dalloc(&d.S64, mm) == hipSuccess && dalloc(&d.T64, mm) == hipSuccess &&
             dalloc(&d.G32, (size_t)M * 64) == hipSuccess && dalloc(&d.Gt16, (size_t)2 * M * 64) == hipSuccess &&
+            dalloc(&d.G64, (size_t)M * 32) == hipSuccess &&
             dalloc(&d.phi_ws, rfd::phi1_ws_doubles(M)) == hipSuccess &&
             dalloc(&d.sdev, 1) == hipSuccess && dalloc(&d.barrier, rfd::kBarrierWords) == hipSuccess && dalloc(&d.flag, 1) == hipSuccess &&
             dalloc(&d.lvl, rfd::reduce_scratch_doubles(M)) == hipSuccess;
@@ -521,6 +522,37 @@ rfd_status rfd_plan_core(rfd_plan_t p, double* M_out, double* S_out, int32_t* s_
     }
   }
   if (s_out) *s_out = sv;
+  return RFD_OK;
+}
+
+rfd_status rfd_plan_info(rfd_plan_t p, int64_t* N_out, int32_t* m_out, int32_t* padded_m_out) {
+  if (!p) return RFD_ERR_INVALID_ARG;
+  if (N_out) *N_out = p->N;
+  if (m_out) *m_out = p->m;
+  if (padded_m_out) *padded_m_out = p->dev_m;
+  return RFD_OK;
+}
+
+rfd_status rfd_plan_action(rfd_plan_t p, double* H_out, double* G_out, int32_t* d_out, rfd_stream_t stream) {
+  if (!p) return RFD_ERR_INVALID_ARG;
+  if (p->N < 0 || p->action_d <= 0) return RFD_ERR_NOT_READY;
+  HIPCK(hipStreamSynchronize((hipStream_t)stream));
+  const int M = p->dev_m, m = p->m, f = p->f, fp = M / 2, d = p->action_d;
+  constexpr int TW = 32;  // row pitch of G64
+  std::vector<double> h0((size_t)M * d), g((size_t)M * TW);
+  HIPCK(hipMemcpy(h0.data(), p->dev.H0, sizeof(double) * h0.size(), hipMemcpyDeviceToHost));
+  HIPCK(hipMemcpy(g.data(), p->dev.G64, sizeof(double) * g.size(), hipMemcpyDeviceToHost));
+  for (int i = 0; i < m; ++i) {
+    const int k = i < f ? i : i - f;                  // frequency of canonical column i
+    const int di = i < f ? 2 * k : 2 * k + 1;         // its device column
+    const int pi = i < f ? i : fp + k;                // its padded canonical index
+    const double c = sqrt(fabs(p->w[k]) / f);
+    for (int j = 0; j < d; ++j) {
+      if (H_out) H_out[(size_t)i * d + j] = c * h0[(size_t)di * d + j];
+      if (G_out) G_out[(size_t)i * d + j] = g[(size_t)pi * TW + j];
+    }
+  }
+  if (d_out) *d_out = d;
   return RFD_OK;
 }
 

@@ -48,6 +48,7 @@ struct ApplyArgs {
   int reserved;
   float* G32;        // m x d, device order
   __bf16* Gt16;      // BF16 hi (d x m), then lo at offset 64 m
+  double* G64;       // m x kThinWidth, canonical: G = lambda phi_1(lambda M) H in FP64
 };
 constexpr int kThinWidth = 32;
 
@@ -693,6 +694,7 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
     const int i = (int)(e / d), c = (int)(e - (size_t)i * d);
     const double sv = a.lambda * Wc[(size_t)i * TW + c];
     if (!isfinite(sv)) __hip_atomic_fetch_or(a.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    gst(ap.G64 + (size_t)i * TW + c, sv);
     const int di = i < f ? 2 * i : 2 * (i - f) + 1;
     const float g = (float)(a.cvec[i] * a.svec[i] * sv);
     const __bf16 hi = (__bf16)g;
@@ -813,7 +815,8 @@ hipError_t launch_phi1_apply(rfd_plan_s* p, int d, hipStream_t st) {
   if (d < 1 || d > kThinWidth) return hipErrorInvalidValue;
   Phi1Args a;
   fill_args(p, a);
-  ApplyArgs ap{p->dev.H0, d, 0, p->dev.G32, p->dev.Gt16};
+  ApplyArgs ap{p->dev.H0, d, 0, p->dev.G32, p->dev.Gt16, p->dev.G64};
+  p->action_d = d;
   switch (a.m) {
     case 64: return launch_apply_m<64>(a, ap, st);
     case 128: return launch_apply_m<128>(a, ap, st);
@@ -825,7 +828,8 @@ hipError_t launch_phi1_apply(rfd_plan_s* p, int d, hipStream_t st) {
 int phi1_apply_max_width() { return kThinWidth; }
 
 void phi1_fill_apply_args(rfd_plan_s* p, int d, void* out) {
-  *(ApplyArgs*)out = ApplyArgs{p->dev.H0, d, 0, p->dev.G32, p->dev.Gt16};
+  *(ApplyArgs*)out = ApplyArgs{p->dev.H0, d, 0, p->dev.G32, p->dev.Gt16, p->dev.G64};
+  p->action_d = d;
 }
 
 size_t phi1_apply_args_bytes() { return sizeof(ApplyArgs); }

@@ -121,6 +121,13 @@ rfd_status rfd_loop_launch(rfd_loop_t L, rfd_stream_t stream) {
   if (!L) return RFD_ERR_INVALID_ARG;
   if (stale(L)) return RFD_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
+  // The recorded launches read each plan's S and T. A one-shot call on a plan
+  // since then (same cloud size, so the same buffers) may have applied phi_1
+  // in action form to a new cloud and left S and T stale: form them first.
+  for (rfd_plan_s* p : L->plans) {
+    const rfd_status cs = rfd::ensure_core(p, st);
+    if (cs != RFD_OK) return cs;
+  }
   if (L->exec) {
     HIPCK(hipGraphLaunch(L->exec, st));
     return RFD_OK;

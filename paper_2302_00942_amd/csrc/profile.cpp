@@ -110,4 +110,19 @@ int32_t rfd_profile_read(double* total_ms, int64_t* counts, int32_t n, int32_t r
 
 const char* rfd_profile_kernel_name(int32_t id) { return rfd::kernel_name(id); }
 
+void rfd_library_release(void) {
+  rfd::Profiler& p = rfd::prof();
+  (void)hipDeviceSynchronize();
+  std::lock_guard<std::mutex> g(p.mu);
+  for (const auto& q : p.pending) {
+    p.pool.push_back(q.a);
+    p.pool.push_back(q.b);
+  }
+  p.pending.clear();
+  for (hipEvent_t e : p.pool) (void)hipEventDestroy(e);
+  p.pool.clear();
+  p.on = false;
+  rfd::release_spectrum_records();
+}
+
 }  // extern "C"

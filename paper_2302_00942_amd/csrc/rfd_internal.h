@@ -68,6 +68,7 @@ struct PlanDev {
   double* T64 = nullptr;      // m x m, device order
   float* G32 = nullptr;       // m x 64, device order: G' = T H0 of one channel slice
   __bf16* Gt16 = nullptr;     // 2 x 64 x m: G'^T as BF16 hi, then BF16 lo
+  double* G64 = nullptr;      // m x 32, canonical: G = S H of the last phi_1 action (FP64)
   double* phi_ws = nullptr;   // phi_1 workspace (phi1_ws_doubles)
   int* sdev = nullptr;        // scaling power s
   unsigned* barrier = nullptr;// grid barrier counter
@@ -89,6 +90,7 @@ struct rfd_plan_s {
   bool any_growth = false;    // lambda * w_k > 0 for some k
   int64_t N = -1;             // cloud size after rfd_features (-1: none)
   bool core_ready = false;    // S and T hold phi_1 of the current cloud's core
+  int action_d = 0;           // channels of the last phi_1 action in G64 (0: none)
   int dev_m = 0;              // padded feature count used on the device: 64, 128 or 256
   int device = 0;
   rfd::PlanDev dev;
@@ -226,6 +228,7 @@ struct SpecArgs {
 SpecArgs spectrum_args(rfd_plan_s* p, int which, int64_t k, double* out);
 hipError_t launch_spectrum(rfd_plan_s* p, int which, int64_t k, double* out, hipStream_t st);
 hipError_t launch_spectrum_batch(const SpecArgs* dev_args, int n, int max_m, hipStream_t st);
+void release_spectrum_records();  // frees the batched spectrum's record buffers (spectrum.cpp)
 // Launch-geometry tuning (autotune.cpp): knobs that change speed, never results.
 enum TuneKnob { kTuneExpandTilesPerWave = 0, kTuneBatchExpandTilesPerItem = 1, kTunePhi1Workgroups = 2,
                 kNumTuneKnobs };

@@ -22,6 +22,7 @@
 // and times STEPS graph replays of it on a stream of its own. The copy form
 // runs one device-to-device copy of MIB mebibytes (a reference kernel of
 // known traffic for calibrating hardware byte counters).
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -113,6 +114,8 @@ static int gw_mode(const std::string& dir, int steps, int prec) {
   if (st == RFD_OK) st = rfd_plan_check(pd, nullptr);
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
   printf("rfd_run gw n=%lld m=%lld feats=%d prec=%s steps=%d: %.4f ms/loss (%s)\n", n, m, feats,
          prec == RFD_BF16 ? "bf16" : "fp32", steps, ms / steps, rfd_status_string(st));
   fflush(stdout);
@@ -167,6 +170,8 @@ static int spectrum_mode(const std::string& dir, int steps, int m) {
   if (st == RFD_OK) st = rfd_plan_check(plan, nullptr);
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
   printf("rfd_run spectrum N=%lld m=%d k=%lld steps=%d: %.4f ms/call (%s)\n", n, m, k, steps, ms / steps,
          rfd_status_string(st));
   fflush(stdout);
@@ -253,6 +258,8 @@ static int batch_mode(const std::string& dir, int steps, int prec) {
     (void)hipEventRecord(b, s);
     (void)hipEventSynchronize(b);
     (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
   }
   for (int i = 0; i < count && st == RFD_OK; ++i) st = rfd_plan_check(plans[i], s);
   printf("rfd_run batch clouds=%d points=%lld d=%d m=%d prec=%s steps=%d: %.4f ms/batch (%s)\n", count, total, d, m,
@@ -268,7 +275,27 @@ static int batch_mode(const std::string& dir, int steps, int prec) {
   return st == RFD_OK ? 0 : 1;
 }
 
+// Where the library and the HIP runtime are mapped, so that frames of a
+// crash report can be attributed to one of them.
+static void print_load_addresses() {
+  Dl_info a{}, b{};
+  if (dladdr((const void*)&rfd_plan_create, &a) && dladdr((const void*)&hipGetDeviceCount, &b))
+    fprintf(stderr, "rfd_run: %s at %p, %s at %p\n", a.dli_fname, a.dli_fbase, b.dli_fname, b.dli_fbase);
+}
+
+static int run(int argc, char** argv);
+
 int main(int argc, char** argv) {
+  print_load_addresses();
+  const int rc = run(argc, argv);
+  // nothing of the library's is left for the exit-time teardown
+  rfd_library_release();
+  fflush(stdout);
+  fflush(stderr);
+  return rc;
+}
+
+static int run(int argc, char** argv) {
   if (argc == 3 && strcmp(argv[1], "copy") == 0) return copy_mode(atoll(argv[2]));
   if (argc == 5 && strcmp(argv[1], "spectrum") == 0) return spectrum_mode(argv[2], atoi(argv[3]), atoi(argv[4]));
   if (argc >= 4 && strcmp(argv[1], "batch") == 0)
@@ -343,6 +370,8 @@ int main(int argc, char** argv) {
   if (st == RFD_OK) st = rfd_plan_check(plan, nullptr);
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
   fflush(stderr);
   printf("rfd_run N=%lld d=%d m=%d prec=%s steps=%d: %.4f ms/step (%s)\n", N, d, m, prec == RFD_BF16 ? "bf16" : "fp32",
          steps, ms / steps, rfd_status_string(st));

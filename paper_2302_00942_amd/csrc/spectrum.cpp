@@ -3,7 +3,46 @@
 // enqueue one kernel with one workgroup per cloud.
 #include "rfd_internal.h"
 
+#include <mutex>
 #include <vector>
+
+namespace {
+
+// Device copies of the batched argument records: one grow-only buffer per
+// device, reused by every call (each call waits for its launch before it
+// returns, and the mutex keeps concurrent calls from sharing it), so a call
+// allocates only when it has more clouds than any earlier call on the device.
+struct RecordCache {
+  std::mutex mu;
+  std::vector<void*> buf;
+  std::vector<size_t> cap;
+};
+
+RecordCache& records() {
+  static RecordCache c;
+  return c;
+}
+
+}  // namespace
+
+namespace rfd {
+
+void release_spectrum_records() {
+  RecordCache& c = records();
+  std::lock_guard<std::mutex> g(c.mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (size_t dev = 0; dev < c.buf.size(); ++dev) {
+    if (!c.buf[dev]) continue;
+    (void)hipSetDevice((int)dev);
+    (void)hipFree(c.buf[dev]);
+    c.buf[dev] = nullptr;
+    c.cap[dev] = 0;
+  }
+  (void)hipSetDevice(cur);
+}
+
+}  // namespace rfd
 
 extern "C" {
 
@@ -37,12 +76,29 @@ rfd_status rfd_spectrum_batch(const rfd_plan_t* plans, int32_t n, int32_t which,
     max_m = p->m > max_m ? p->m : max_m;
   }
   hipStream_t st = (hipStream_t)stream;
-  rfd::SpecArgs* dargs = nullptr;
-  if (hipMalloc((void**)&dargs, sizeof(rfd::SpecArgs) * n) != hipSuccess) return RFD_ERR_DEVICE;
-  hipError_t e = hipMemcpyAsync(dargs, args.data(), sizeof(rfd::SpecArgs) * n, hipMemcpyHostToDevice, st);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return RFD_ERR_DEVICE;
+  RecordCache& c = records();
+  std::lock_guard<std::mutex> g(c.mu);
+  if (c.buf.size() <= (size_t)dev) {
+    c.buf.resize(dev + 1, nullptr);
+    c.cap.resize(dev + 1, 0);
+  }
+  const size_t bytes = sizeof(rfd::SpecArgs) * n;
+  if (c.cap[dev] < bytes) {
+    size_t want = c.cap[dev] ? 2 * c.cap[dev] : sizeof(rfd::SpecArgs) * 64;
+    while (want < bytes) want *= 2;
+    if (c.buf[dev]) (void)hipFree(c.buf[dev]);  // the previous call waited for its launch
+    c.buf[dev] = nullptr;
+    c.cap[dev] = 0;
+    if (hipMalloc(&c.buf[dev], want) != hipSuccess) return RFD_ERR_DEVICE;
+    c.cap[dev] = want;
+  }
+  rfd::SpecArgs* dargs = (rfd::SpecArgs*)c.buf[dev];
+  hipError_t e = hipMemcpyAsync(dargs, args.data(), bytes, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = rfd::launch_spectrum_batch(dargs, n, max_m, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);  // the records (and the host copy) are released below
-  (void)hipFree(dargs);
+  // the records are reused by the next call, and the host copy is released on return
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   return e == hipSuccess ? RFD_OK : RFD_ERR_DEVICE;
 }
 

@@ -76,6 +76,8 @@ def lib() -> C.CDLL:
             "rfd_gw_destroy": ([vp], None),
             "rfd_plan_check": ([vp, vp], i32),
             "rfd_plan_core": ([vp, vp, vp, vp, vp], i32),
+            "rfd_plan_info": ([vp, vp, vp, vp], i32),
+            "rfd_plan_action": ([vp, vp, vp, vp, vp], i32),
             "rfd_plan_destroy": ([vp], None),
             "rfd_integrate_batch": ([vp, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
             "rfd_batch_create": ([vp, vp, vp, vp, vp, vp, vp, vp, i32, C.POINTER(vp)], i32),
@@ -96,6 +98,7 @@ def lib() -> C.CDLL:
             "rfd_profile_enable": ([C.c_int], None),
             "rfd_profile_read": ([vp, vp, i32, i32], i32),
             "rfd_profile_kernel_name": ([i32], C.c_char_p),
+            "rfd_library_release": ([], None),
         }
         for name, (args, res) in sigs.items():
             fn = getattr(L, name)
@@ -166,7 +169,6 @@ class Plan:
         self._h = h
         self.m, self.eps, self.lam, self.seed = m, eps, lam, seed
         self.precision = _PREC[precision]
-        self.N = None
 
     @property
     def handle(self) -> C.c_void_p:
@@ -184,7 +186,22 @@ class Plan:
         if X.stride(0) != 3:
             raise ValueError("X must be contiguous N x 3")
         _check(lib().rfd_features(self._h, X.data_ptr(), X.shape[0], _stream_handle(stream)), "rfd_features")
-        self.N = X.shape[0]
+
+    @property
+    def points(self) -> int:
+        """The plan's cloud size as the library holds it (-1 before any features)."""
+        n = C.c_int64()
+        _check(lib().rfd_plan_info(self._h, C.byref(n), None, None), "rfd_plan_info")
+        return int(n.value)
+
+    def _rows(self, F, out) -> None:
+        # the library reads and writes N rows of F and out: shorter tensors
+        # would be accessed out of bounds, so refuse them before any launch
+        n = self.points
+        if n >= 0 and F.shape[0] != n:
+            raise ValueError(f"F has {F.shape[0]} rows; the plan's cloud has {n} points")
+        if out.shape[0] != F.shape[0]:
+            raise ValueError("out must have as many rows as F")
 
     def integrate(self, F, out=None, stream=None):
         import torch
@@ -192,6 +209,7 @@ class Plan:
         if out is None:
             out = torch.empty_like(F)
         out = _dev_f32(out, "out", F.shape[1])
+        self._rows(F, out)
         _check(lib().rfd_integrate(self._h, F.data_ptr(), F.stride(0), F.shape[1], out.data_ptr(), out.stride(0),
                                    _stream_handle(stream)), "rfd_integrate")
         return out
@@ -203,6 +221,7 @@ class Plan:
         if out is None:
             out = torch.empty_like(F)
         out = _dev_f32(out, "out", F.shape[1])
+        self._rows(F, out)
         sp = 0
         if scale is not None:
             if not (isinstance(scale, torch.Tensor) and scale.is_cuda and scale.dtype == torch.float32
@@ -224,16 +243,18 @@ class Plan:
         if out is None:
             out = torch.empty_like(F)
         out = _dev_f32(out, "out", F.shape[1])
+        if out.shape[0] != F.shape[0]:
+            raise ValueError("out must have as many rows as F")
         _check(lib().rfd_integrate_oneshot(self._h, X.data_ptr(), X.shape[0], F.data_ptr(), F.stride(0), F.shape[1],
                                            out.data_ptr(), out.stride(0), _stream_handle(stream)),
                "rfd_integrate_oneshot")
-        self.N = X.shape[0]
         return out
 
     def autotune(self, F, out, reps: int = 10, stream=None):
         """Tunes the expansion geometry for this cloud and F's width; out gets integrate(F)."""
         F = _dev_f32(F, "F")
         out = _dev_f32(out, "out", F.shape[1])
+        self._rows(F, out)
         _check(lib().rfd_autotune(self._h, F.data_ptr(), F.stride(0), F.shape[1], out.data_ptr(), out.stride(0),
                                   int(reps), _stream_handle(stream)), "rfd_autotune")
         return out
@@ -265,6 +286,17 @@ class Plan:
                "rfd_plan_core")
         return M, S, int(s.value)
 
+    def action(self, stream=None):
+        """(H, G): the FP64 field block H = B^T F (m x d) and G = lambda phi_1(lambda M) H
+        of the last call whose phi_1 ran in action form (rfd_plan_action)."""
+        d = C.c_int32()
+        _check(lib().rfd_plan_action(self._h, None, None, C.byref(d), _stream_handle(stream)), "rfd_plan_action")
+        H = np.zeros((self.m, d.value))
+        G = np.zeros((self.m, d.value))
+        _check(lib().rfd_plan_action(self._h, H.ctypes.data, G.ctypes.data, None, _stream_handle(stream)),
+               "rfd_plan_action")
+        return H, G
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().rfd_plan_destroy(self._h)
@@ -293,6 +325,8 @@ class Batch:
             _dev_f32(o, "out", F.shape[1])
             if X.shape[0] != F.shape[0] or X.stride(0) != 3:
                 raise ValueError("X must be contiguous N x 3 with N = F.shape[0]")
+            if o.shape[0] != F.shape[0]:
+                raise ValueError("each out must have as many rows as its F")
         self._keep = (plans, Xs, Fs, outs)
         P = C.c_void_p * n
         self._arrs = dict(
@@ -343,6 +377,9 @@ class Loop:
             if s is not None and not (isinstance(s, torch.Tensor) and s.is_cuda and s.dtype == torch.float32
                                       and s.is_contiguous() and s.numel() == v.shape[0]):
                 raise ValueError("each scale must be a contiguous float32 CUDA vector with one entry per row")
+        for p in plans:
+            if p.points >= 0 and p.points != v.shape[0]:
+                raise ValueError(f"v has {v.shape[0]} rows; a plan's cloud has {p.points} points")
         self._keep = (plans, scales, v)
         P = C.c_void_p * n
         self._plans = P(*[p.handle.value for p in plans])
@@ -391,7 +428,7 @@ class GW:
         _check(lib().rfd_gw_create(pc.handle, pd.handle, C.byref(h)), "rfd_gw_create")
         self._keep = (pc, pd)
         self._h = h
-        self.n, self.m = pc.N, pd.N
+        self.n, self.m = pc.points, pd.points
 
     def _coupling(self, T):
         _dev_f32(T, "T", self.m)

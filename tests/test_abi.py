@@ -150,3 +150,23 @@ def test_taylor_scaling_threshold():
     (Al-Mohy & Higham's Taylor thresholds for double precision)."""
     assert abs(_taylor_theta(23) - 2.014710780944616) < 1e-9
     assert abs(_taylor_theta(18) - 1.09) < 5e-3
+
+
+def test_plan_row_check_runs_on_the_host():
+    """Plan._rows refuses F and out whose row count differs from the plan's
+    cloud before anything reaches the library (host logic; no GPU)."""
+    class FakePlan(rfd.Plan):
+        points = 500
+
+        def __init__(self):
+            pass
+
+    class T:
+        def __init__(self, rows):
+            self.shape = (rows, 3)
+
+    p = FakePlan()
+    p._rows(T(500), T(500))
+    for F, out in ((T(499), T(499)), (T(500), T(499)), (T(501), T(501))):
+        with pytest.raises(ValueError):
+            p._rows(F, out)

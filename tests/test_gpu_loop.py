@@ -157,3 +157,45 @@ def test_repeated_application_full_size(torch_cuda, prec):
     print(f"repeated application N=1e5 d=32 {prec} x{iters}: relF={e:.3e}")
     assert e <= TOL[prec]
     loop.close()
+
+
+def test_loop_after_same_size_action_form_oneshot(torch_cuda):
+    """A one-shot call of at most 32 channels on a loop's plan, with a new
+    cloud of the same size, applies phi_1 in action form and leaves S and T
+    stale; the next loop launch forms them for the new cloud first, so the
+    loop matches the oracle on the new cloud."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    n, iters = 3000, 6
+    clouds = wl.sinkhorn_pair(n=n, d=4, m=64, seed=11)
+    s0, s1 = wl.scaling_vectors(n, 12)
+    plans = make_plans(torch, clouds, "fp32")
+    sd = [torch.from_numpy(s0).cuda(), torch.from_numpy(s1).cuda()]
+    v0 = torch.from_numpy(clouds[0].F).cuda()
+    v = v0.clone()
+    loop = rfd.Loop(plans, sd, v, iters)
+    loop.launch()
+    torch.cuda.synchronize()
+    Xnew = wl.ellipsoid(n, 13)
+    Fnew = torch.from_numpy(wl.field(n, 8, 14)).cuda()
+    plans[0].oneshot(torch.from_numpy(Xnew).cuda(), Fnew)  # action form (8 <= 32 channels)
+    v.copy_(v0)
+    loop.launch()
+    torch.cuda.synchronize()
+    oms, ws = zip(*[p.export() for p in plans])
+    ref = o.repeated_apply([Xnew, clouds[1].X], clouds[0].F, (s0, s1), [clouds[0].lam, clouds[1].lam], iters, oms,
+                           ws)
+    e = o.relf(v.cpu().numpy(), ref)
+    print(f"loop after an action-form one-shot on a new cloud: relF={e:.3e}")
+    assert e <= TOL["fp32"]
+    assert all(p.check() == rfd.OK for p in plans)
+    loop.close()
+
+
+def test_loop_rows_must_match_the_clouds(torch_cuda):
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    a = rfd.Plan(64, 0.1, -0.5, 0)
+    a.features(torch.from_numpy(wl.sphere(100, 0)).cuda())
+    with pytest.raises(ValueError):
+        rfd.Loop([a], None, torch.zeros((99, 2), device="cuda"), 3)

@@ -259,6 +259,31 @@ def test_not_ready_before_features(torch_cuda):
     assert e.value.status == rfd.NOT_READY
 
 
+def test_row_counts_are_checked_before_any_launch(torch_cuda):
+    """F and out shorter (or longer) than the plan's cloud are refused on the
+    host: the library would read and write N rows of them."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    plan = rfd.Plan(64, 0.1, -0.5, 0)
+    X = torch.from_numpy(wl.sphere(500, 2)).cuda()
+    plan.features(X)
+    assert plan.points == 500
+    good = torch.zeros((500, 3), device="cuda")
+    for F, out in ((torch.zeros((499, 3), device="cuda"), None), (good, torch.zeros((499, 3), device="cuda")),
+                   (torch.zeros((501, 3), device="cuda"), None)):
+        with pytest.raises(ValueError):
+            plan.integrate(F, out)
+        with pytest.raises(ValueError):
+            plan.integrate_scaled(F, None, out)
+    with pytest.raises(ValueError):
+        plan.oneshot(X, good, out=torch.zeros((400, 3), device="cuda"))
+    with pytest.raises(ValueError):
+        rfd.Batch([plan], [X], [good], [torch.zeros((400, 3), device="cuda")])
+    assert plan.points == 500  # nothing ran
+    plan.integrate(good)
+    assert plan.check() == rfd.OK
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_large_torus_full_size(torch_cuda, prec):
     """The 1M-point torus at its full size, m=256, d=16, in the benchmark's

@@ -340,6 +340,52 @@ def test_self_loop_convention_is_a_scalar_factor():
     assert np.linalg.norm(a - math.exp(c.lam) * b) / np.linalg.norm(a) < 1e-13
 
 
+def test_dense_adjacency_box_boundary():
+    """The L-infinity box branch: pairs whose largest coordinate gap is exactly
+    eps (on a face, an edge or a corner of the box) are neighbours, a gap one
+    float32 step above eps is not, and corner pairs that the L2 ball excludes
+    are kept; a random cloud matches a plain double loop over the definition."""
+    up = float(np.nextafter(np.float32(0.25), np.float32(1.0)))
+    X = np.array([[0, 0, 0], [0.25, 0.25, -0.25], [0.25, 0.25, 0.0], [0.5, 0, 0], [0.25, -0.25, 0.25],
+                  [0.0, up, 0.0]], dtype=np.float32)
+    W = o.dense_adjacency(X, 0.25, shape=o.BOX_LINF)
+    ref = [[1, 1, 1, 0, 1, 0],
+           [1, 1, 1, 1, 0, 1],
+           [1, 1, 1, 1, 0, 1],
+           [0, 1, 1, 1, 1, 0],
+           [1, 0, 0, 1, 1, 0],
+           [0, 1, 1, 0, 0, 1]]
+    assert W.tolist() == ref
+    # the L2 ball drops the corner and edge pairs of the origin
+    W2 = o.dense_adjacency(X, 0.25)
+    assert W2[0, 1] == 0 and W2[0, 2] == 0 and W2[0, 4] == 0 and W2[1, 2] == 1
+    Xr = wl.sphere(40, 3)
+    Wr = o.dense_adjacency(Xr, 0.3, shape=o.BOX_LINF, self_loops=False)
+    for i in range(40):
+        for j in range(40):
+            gap = max(abs(float(Xr[i][c]) - float(Xr[j][c])) for c in range(3))
+            assert Wr[i, j] == (1.0 if (i != j and gap <= 0.3) else 0.0)
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_rfd_operator_matches_dense_expm(signed):
+    """rfd_operator(x) = expm(lam W_hat) x with W_hat from the plain-loop
+    estimator and SciPy's expm, for a vector and a block, under the main-lobe
+    law (A = B) and a signed-weight law (A != B, M = B^T A not symmetric)."""
+    X = wl.sphere(90, 21)
+    eps, m, seed = 0.3, 32, 8
+    kw = dict(sigma=1 / eps, radius=3 / eps) if signed else {}
+    lam = -0.01 if signed else -0.4
+    om, w = o.frequencies_and_weights(m, eps, seed, **kw)
+    assert np.any(w < 0) if signed else np.all(w > 0)
+    K = sl.expm(lam * _what_loop(X, om, w))
+    op = o.rfd_operator(X, eps, lam, m, seed, **kw)
+    g = np.random.default_rng(4)
+    for x in (g.standard_normal(90), g.standard_normal((90, 3))):
+        ref = K @ x
+        assert np.linalg.norm(op(x) - ref) / np.linalg.norm(ref) < 1e-12
+
+
 # ---------------------------------------------------------------- estimator law (Lemma 2.5 proof)
 def _gl(R, n=4000):
     x, wq = np.polynomial.legendre.leggauss(n)
