@@ -362,6 +362,61 @@ def repeated_apply(clouds, v0, scales, lam_list, iters: int, omegas, ws):
     return v
 
 
+def wasserstein_barycenter(apply_K, mus, a, alpha, iters: int, floor=None, return_state: bool = False):
+    """Entropic Wasserstein barycenter by the scaling iteration of App. D
+    (Alg. 1, "Fast Computation of Wasserstein Barycenter"), with the kernel
+    entering only through its action apply_K (an FM: here the RFD operator).
+
+    mus: k input distributions (each N,), a: area weights (N,), alpha: k
+    weights. Starting from v^i = w^i = 1, each of `iters` iterations does, for
+    i = 1..k,
+        w^i = mu^i / K(a v^i),   d^i = v^i K(a w^i),   mu = mu * (d^i)^alpha_i,
+    and then v^i = v^i mu / d^i for every i.
+
+    Reading: mu restarts from the all-ones vector at the start of every
+    iteration, so mu = prod_i (d^i)^alpha_i, the weighted geometric mean of
+    the current marginals (the listing initialises mu once; without the
+    restart the update would multiply the barycenter into mu at every
+    iteration and have no fixed point).
+
+    floor (optional safeguard, not in the listing): a factor rho >= 0 by which
+    every output y = K(x) of the two kernel actions is replaced by
+    max(y, rho x) elementwise. With rho = 1 this is the lower bound
+    exp(lambda W) x >= x that the exact kernel satisfies for lambda >= 0 and a
+    non-negative W, which the random-feature estimate can violate (its values
+    can be negative). Returns mu, or (mu, v, d, floored count) with
+    return_state."""
+    mus = [np.asarray(m_, dtype=np.float64) for m_ in mus]
+    a = np.asarray(a, dtype=np.float64)
+    k = len(mus)
+    N = a.shape[0]
+    v = [np.ones(N) for _ in range(k)]
+    d = [np.ones(N) for _ in range(k)]
+    mu = np.ones(N)
+    floored = 0
+
+    def K(x):
+        nonlocal floored
+        y = np.asarray(apply_K(x), dtype=np.float64)
+        if floor is None:
+            return y
+        lo = floor * x
+        floored += int(np.sum(y < lo))
+        return np.maximum(y, lo)
+
+    for _ in range(iters):
+        mu = np.ones(N)
+        for i in range(k):
+            w = mus[i] / K(a * v[i])
+            d[i] = v[i] * K(a * w)
+            mu = mu * d[i] ** alpha[i]
+        for i in range(k):
+            v[i] = v[i] * mu / d[i]
+    if return_state:
+        return mu, v, d, floored
+    return mu
+
+
 def rfd_operator(X, eps: float, lam: float, m: int, seed: int, shape: int = BALL_L2,
                  sigma: float = 0.0, radius: float = 0.0):
     """x -> exp(lam A B^T) x on the cloud X with the frequencies of `seed`

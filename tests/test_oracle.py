@@ -546,3 +546,106 @@ def test_kernel_spectrum_matches_dense_eigenvalues(n, m, eps, lam):
     assert np.abs(got - dense).max() <= 1e-12 * max(1.0, np.abs(dense).max())
     if n > m:
         assert np.sum(np.abs(got - 1.0) < 1e-12) >= n - m  # the eigenvalue 1 of the null space of A B^T
+
+
+# ---------------------------------------------------------------- Wasserstein barycenter (App. D, Alg. 1)
+def _bary_inputs(n=60, k=3, seed=0):
+    g = np.random.default_rng(seed)
+    a = g.uniform(0.5, 1.5, n)
+    mus = [g.uniform(0.1, 2.0, n) for _ in range(k)]
+    return a, mus
+
+
+def test_barycenter_identity_kernel_is_weighted_geometric_mean():
+    """With K = I the marginals d^i equal mu^i after every iteration, so the
+    barycenter is prod_i (mu^i)^alpha_i exactly (the restart of mu each
+    iteration keeps it there)."""
+    a, mus = _bary_inputs()
+    alpha = [0.2, 0.3, 0.5]
+    ref = mus[0] ** 0.2 * mus[1] ** 0.3 * mus[2] ** 0.5
+    for it in (1, 5):
+        assert o.relf(o.wasserstein_barycenter(lambda x: x, mus, a, alpha, it), ref) < 1e-13
+
+
+def _positive_kernel(n=60, seed=1):
+    # exp(0.5 W) of an epsilon graph: entrywise positive (every term of the
+    # series is non-negative) and symmetric
+    X = wl.sphere(n, seed)
+    return sl.expm(0.5 * o.dense_adjacency(X, 0.6))
+
+
+def test_barycenter_single_input_closed_form():
+    """k = 1, alpha = 1: v stays 1, so after any number of iterations
+    mu = K(a (mu^1 / K(a))), with K a dense positive kernel (SciPy expm)."""
+    K = _positive_kernel()
+    a, mus = _bary_inputs(k=1, seed=2)
+    ref = K @ (a * (mus[0] / (K @ a)))
+    for it in (1, 4):
+        assert o.relf(o.wasserstein_barycenter(lambda x: K @ x, mus, a, [1.0], it), ref) < 1e-13
+
+
+def test_barycenter_of_equal_inputs_is_the_single_input_result():
+    K = _positive_kernel(seed=3)
+    a, mus = _bary_inputs(k=1, seed=4)
+    ref = K @ (a * (mus[0] / (K @ a)))
+    got = o.wasserstein_barycenter(lambda x: K @ x, [mus[0]] * 3, a, [1 / 3] * 3, 6)
+    assert o.relf(got, ref) < 1e-12
+
+
+def test_barycenter_marginals_converge_to_it():
+    """At the fixed point every coupling's marginal d^i equals the barycenter
+    mu (the scaling v^i = v^i mu / d^i stops changing): checked after enough
+    iterations on a dense positive kernel with distinct inputs."""
+    K = _positive_kernel(seed=11)
+    a, mus = _bary_inputs(seed=12)
+    mus = [m_ / (a @ m_) for m_ in mus]  # probability vectors for the area weights
+    mu, _, d, _ = o.wasserstein_barycenter(lambda x: K @ x, mus, a, [0.5, 0.3, 0.2], 400, return_state=True)
+    assert max(o.relf(di, mu) for di in d) < 1e-8
+    assert abs(a @ mu - 1.0) < 1e-8  # a probability vector too
+    assert o.relf(mu, mus[0]) > 1e-2  # not one of the inputs
+
+
+def test_barycenter_is_symmetric_in_its_inputs():
+    K = _positive_kernel(seed=5)
+    a, mus = _bary_inputs(seed=6)
+    one = o.wasserstein_barycenter(lambda x: K @ x, mus, a, [1 / 3] * 3, 7)
+    two = o.wasserstein_barycenter(lambda x: K @ x, [mus[2], mus[0], mus[1]], a, [1 / 3] * 3, 7)
+    assert o.relf(two, one) < 1e-12
+    # unequal weights are not symmetric: a different barycenter
+    three = o.wasserstein_barycenter(lambda x: K @ x, mus, a, [0.6, 0.2, 0.2], 7)
+    assert o.relf(three, one) > 1e-3
+
+
+def test_barycenter_floor_safeguard():
+    """floor = 1 replaces every kernel output below its input by the input:
+    an operator returning -x then acts as the identity (geometric mean), and
+    every one of the 2 k N outputs per iteration is counted."""
+    a, mus = _bary_inputs(seed=7)
+    mu, _, _, nfl = o.wasserstein_barycenter(lambda x: -x, mus, a, [1 / 3] * 3, 3, floor=1.0, return_state=True)
+    assert o.relf(mu, (mus[0] * mus[1] * mus[2]) ** (1 / 3)) < 1e-13
+    assert nfl == 2 * 3 * 3 * len(a)
+    # an operator that keeps its input where it is large and negates the
+    # rest: only the negated entries are floored
+    a1, mus1 = _bary_inputs(k=1, seed=8)
+    half = np.arange(len(a1)) % 2 == 0
+    mu1, _, _, n1 = o.wasserstein_barycenter(lambda x: np.where(half, x, -x), mus1, a1, [1.0], 1, floor=1.0,
+                                             return_state=True)
+    assert n1 == 2 * int(half.size - half.sum()) and o.relf(mu1, mus1[0]) < 1e-13
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_barycenter_on_rfd_operator_matches_dense_expm(signed):
+    """The loop on the low-rank operator equals the same loop on the dense
+    matrix expm(lam W_hat) (SciPy, W_hat from the plain-loop estimator), with
+    the floor active (the estimate is not entrywise positive)."""
+    X = wl.sphere(70, 8)
+    eps, m, seed, lam = 0.3, 32, 9, 0.05
+    kw = dict(sigma=1 / eps, radius=3 / eps) if signed else dict(sigma=1.0, radius=3.0)
+    om, w = o.frequencies_and_weights(m, eps, seed, **kw)
+    K = sl.expm(lam * _what_loop(X, om, w))
+    op = o.rfd_operator(X, eps, lam, m, seed, **kw)
+    a, mus = _bary_inputs(n=70, seed=10)
+    got, _, _, n1 = o.wasserstein_barycenter(op, mus, a, [1 / 3] * 3, 4, floor=1.0, return_state=True)
+    ref, _, _, n2 = o.wasserstein_barycenter(lambda x: K @ x, mus, a, [1 / 3] * 3, 4, floor=1.0, return_state=True)
+    assert np.all(np.isfinite(ref)) and n1 == n2
+    assert o.relf(got, ref) < 1e-9
