@@ -273,6 +273,52 @@ def bench_loop(torch, rfd, wl, reps: int):
             "unit": "points*channels/s", **out}
 
 
+def bench_barycenter(torch, rfd, wl, reps: int, iters: int = 10):
+    """Wasserstein barycenter (App. D, Alg. 1) with the paper's settings
+    (eps = 0.01, lambda = 0.5, m = 30, k = 3, alpha = 1/3, frequency law
+    sigma = 1, R = 3, floor safeguard 1) on synthetic surfaces of the paper's
+    mesh sizes, `iters` iterations graph-replayed. Per iteration: two
+    integrations of the N x 3 field and three elementwise kernels."""
+    from oracle import rfd_oracle as o
+    out = {}
+    kinds = ("sphere", "torus", "ellipsoid", "deformed_torus")
+    for n, kind in zip(wl.BARYCENTER_SIZES, kinds):
+        bp = wl.barycenter_problem(n, kind, seed=1)
+        a = torch.from_numpy(bp.a).cuda()
+        mus = torch.from_numpy(bp.mus).cuda()
+        for prec in ("bf16", "fp32"):
+            plan = rfd.Plan(bp.m, bp.eps, bp.lam, bp.seed, precision=prec, sigma=bp.sigma, radius=bp.radius)
+            plan.features(torch.from_numpy(bp.X).cuda())
+            b = rfd.Barycenter(plan, a, mus, list(bp.alpha), iters, 1.0)
+            st = torch.cuda.Stream()
+            ms = replay_ms(lambda s: b.launch(s), reps, torch, st)
+            mu = b.mu.cpu().numpy()
+            it_us = ms * 1e3 / iters
+            # per iteration and integration of the 3-channel field: X twice (24 B), the field
+            # read twice and written once (36 B); the elementwise kernels move a, mu_in, v, F,
+            # K and mu (about 60 B per point)
+            gbs = (2 * (24 + 36) + 60) * n / (it_us * 1e-6) / 1e9
+            entry = {"us_per_iteration": round(it_us, 3), "hbm_GBs_algorithmic": round(gbs, 1),
+                     "hbm_frac": round(gbs / PEAK["hbm_GBs"], 4),
+                     "floored_frac": round(b.floored(st) / (2 * 3 * iters * n), 4),
+                     "mu_finite": bool(np.all(np.isfinite(mu))), "a_dot_mu": float(f"{float(bp.a @ mu):.4g}")}
+            if n == wl.BARYCENTER_SIZES[0]:
+                op = o.rfd_operator(bp.X, bp.eps, bp.lam, bp.m, bp.seed, sigma=bp.sigma, radius=bp.radius)
+                t0 = time.perf_counter()
+                with np.errstate(all="ignore"):
+                    ref = o.wasserstein_barycenter(op, [bp.mus[:, i].astype(np.float64) for i in range(3)],
+                                                   bp.a.astype(np.float64), list(bp.alpha), iters, floor=1.0)
+                entry["cpu_oracle_s"] = round(time.perf_counter() - t0, 3)
+                entry["rel_err_vs_oracle"] = float(f"{o.relf(mu, ref):.3e}")
+            out[f"n{n}_{prec}"] = entry
+            b.close()
+            plan.close()
+    return {"workload": f"{iters} iterations of Alg. 1 on synthetic surfaces of N = "
+                        f"{', '.join(str(n) for n in wl.BARYCENTER_SIZES)} (sphere, torus, ellipsoid, deformed "
+                        "torus), eps=0.01, lambda=0.5, m=30, k=3, alpha=1/3, sigma=1, R=3, floor 1",
+            "unit": "us per iteration", **out}
+
+
 def bench_resident_wide(torch, rfd, wl, reps: int):
     """The HBM-bound regime: resident integrate of wide fields (m = 64 and 128,
     d = 64) on the 1M-point torus. Algorithmic bytes per point: X read twice
@@ -522,6 +568,7 @@ def main() -> int:
     ap.add_argument("--dump-inputs", metavar="DIR", help="write the cloud for paper_2302_00942_amd/rfd_run and exit")
     ap.add_argument("--gw-only", action="store_true", help="run only the Gromov-Wasserstein and spectrum stages")
     ap.add_argument("--batch-only", action="store_true", help="run only the 512-cloud batch stage")
+    ap.add_argument("--bary-only", action="store_true", help="run only the Wasserstein-barycenter stage")
     ap.add_argument("--dump-batch", metavar="DIR", help="write the 512-cloud batch for paper_2302_00942_amd/rfd_run batch and exit")
     ap.add_argument("--dump-gw", metavar="DIR", help="write the GW problem (n=3000 per cloud) for paper_2302_00942_amd/rfd_run and exit")
     args = ap.parse_args()
@@ -576,6 +623,9 @@ def main() -> int:
     rfd.lib()
     if args.batch_only:
         print(json.dumps({"batched": bench_batch(torch, rfd, wl, max(5, args.steps))}))
+        return 0
+    if args.bary_only:
+        print(json.dumps({"barycenter": bench_barycenter(torch, rfd, wl, max(5, args.steps // 2))}))
         return 0
     if args.gw_only:
         print(json.dumps({"gromov_wasserstein": bench_gw(torch, rfd, wl, max(5, args.steps)),
@@ -656,6 +706,7 @@ def main() -> int:
         line["batched"] = bench_batch(torch, rfd, wl, max(5, args.steps))
         line["repeated_application"] = bench_loop(torch, rfd, wl, max(5, args.steps // 2))
         line["resident_wide_fields"] = bench_resident_wide(torch, rfd, wl, max(5, args.steps))
+        line["barycenter"] = bench_barycenter(torch, rfd, wl, max(5, args.steps // 2))
         line["gromov_wasserstein"] = bench_gw(torch, rfd, wl, max(5, args.steps))
         line["kernel_spectrum"] = bench_spectrum(torch, rfd, wl, max(5, args.steps))
         line["serving"] = bench_serving(torch, rfd, wl, args.serve_requests, 500)

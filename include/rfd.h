@@ -100,6 +100,29 @@ typedef void* rfd_stream_t; /* a hipStream_t; NULL = the default stream */
  * uploads the frequencies. Errors: RFD_ERR_INVALID_ARG. */
 rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan);
 
+/* Device bytes of a plan that lives in a caller's arena (rfd_plan_create_in)
+ * sized for clouds of up to N_max points and fields of up to d_max channels:
+ * the plan's fixed buffers (core, phi_1 workspace, reduction groups), the
+ * point copy (12 B per point) and the split-N partials of the widest
+ * one-shot or resident pass. Host only. Errors: those of rfd_plan_create's
+ * parameter checks, RFD_ERR_INVALID_ARG for N_max < 0 or d_max outside
+ * [0, 1024]. */
+rfd_status rfd_plan_workspace_size(const rfd_params* params, int64_t N_max, int32_t d_max, size_t* bytes);
+
+/* rfd_plan_create with every device buffer of the plan carved from the
+ * caller's arena (device memory, 256-byte aligned, `bytes` >=
+ * rfd_plan_workspace_size(params, N_max, d_max)), so the caller (a torch
+ * tensor, a pool) owns all device memory the plan uses (Sec. 1, Eq. 1: the
+ * integrator as a library call inside a larger program). The plan never
+ * allocates or frees device memory: a call that would need more than the
+ * sizing (a cloud of more than N_max points, a field wider than d_max) returns
+ * RFD_ERR_OUT_OF_BUDGET before any launch. The arena must outlive the plan;
+ * rfd_plan_destroy leaves it to the caller. Errors: RFD_ERR_INVALID_ARG (null
+ * or unaligned arena, sizes), RFD_ERR_OUT_OF_BUDGET (bytes too small), those
+ * of rfd_plan_create. */
+rfd_status rfd_plan_create_in(const rfd_params* params, void* arena_dev, size_t bytes, int64_t N_max,
+                              int32_t d_max, rfd_plan_t* out_plan);
+
 /* Host only (no device memory, no GPU needed): the f frequencies and FP64
  * weights that rfd_plan_create would produce for these params, written to
  * caller-owned host arrays of f x 3 floats and f doubles. Errors:
@@ -119,6 +142,13 @@ rfd_status rfd_plan_export(rfd_plan_t plan, float* omega_fx3, double* w_f);
  * bound |lambda| N sum|w|/f exceeds 700. Device-side findings (non-finite X
  * or core) are reported by rfd_plan_check. N = 0 is valid: out = F. */
 rfd_status rfd_features(rfd_plan_t plan, const float* X_dev, int64_t N, rfd_stream_t stream);
+
+/* rfd_features with its status reported synchronously: waits for `stream`
+ * after the enqueue and returns what the device found for the plan (as
+ * rfd_plan_check does: RFD_ERR_NONFINITE for a non-finite point or core,
+ * RFD_ERR_RANGE for an overflowing phi_1), so plan errors surface at this
+ * call. Errors otherwise those of rfd_features. */
+rfd_status rfd_features_sync(rfd_plan_t plan, const float* X_dev, int64_t N, rfd_stream_t stream);
 
 /* out = F + A (S (B^T F)) for the plan's cloud: K4 (split-N B^T F), K5
  * (reduce, G = S H) and K6 (out = F + A G), enqueued on `stream`. out may
@@ -313,6 +343,47 @@ rfd_status rfd_plan_spectrum(rfd_plan_t plan, int32_t which, int64_t k, double* 
  * given twice; n = 0 or k = 0 is a no-op. */
 rfd_status rfd_spectrum_batch(const rfd_plan_t* plans, int32_t n, int32_t which, int64_t k, double* const* outs,
                               rfd_stream_t stream);
+
+/* ------------------------------------------------- Wasserstein barycenter */
+
+typedef struct rfd_bary_s* rfd_bary_t;
+
+/* The scaling iteration for the entropic Wasserstein barycenter of k
+ * distributions on a resident plan's cloud (App. D, Alg. 1, "Fast Computation
+ * of Wasserstein Barycenter"), with the kernel K = exp(lambda A B^T) applied
+ * by the low-rank integrator. From v^i = 1, each iteration computes, for
+ * every i, w^i = mu^i / K(a v^i), d^i = v^i K(a w^i), then
+ * mu = prod_i (d^i)^alpha_i and v^i = v^i mu / d^i; the k distributions are
+ * the channels of one N x k field, so an iteration is two integrations of
+ * width k plus three elementwise kernels. mu restarts from the all-ones
+ * vector every iteration (the listing initialises it once; without the
+ * restart the update has no fixed point). floor >= 0 switches on a safeguard:
+ * every kernel output below floor times its input is raised to that bound
+ * (floor = 1 is the bound exp(lambda W) x >= x of the exact kernel for
+ * lambda >= 0, which the random-feature estimate can violate); floor < 0
+ * applies K as estimated. Arguments: a = area weights (device, N float32),
+ * mus = inputs (device, N x k float32, leading dimension ldmu >= k),
+ * alpha = k host weights, mu_out = result (device, N float32), all kept
+ * alive by the caller while the object exists; 1 <= k <= 16,
+ * iterations >= 1. The plan must have its features (rfd_features). Creation
+ * allocates the N x k work fields; launches do not. Errors:
+ * RFD_ERR_NOT_READY (no features), RFD_ERR_INVALID_ARG (sizes, null
+ * pointers, a negative or non-finite alpha, N = 0), RFD_ERR_DEVICE. */
+rfd_status rfd_bary_create(rfd_plan_t plan, const float* a_dev, const float* mus_dev, int64_t ldmu, int32_t k,
+                           const double* alpha, int32_t iterations, double floor, float* mu_out_dev,
+                           rfd_bary_t* out);
+
+/* Runs all iterations on `stream` (async): the first launch eagerly, the
+ * second records them into a hipGraph, later ones replay it; every launch
+ * starts from v = 1, so each gives the same bits. RFD_ERR_INVALID_ARG if the
+ * plan's buffers or cloud size changed since creation. */
+rfd_status rfd_bary_launch(rfd_bary_t bary, rfd_stream_t stream);
+
+/* Number of kernel outputs the floor raised during the last launch (waits
+ * for `stream`). */
+rfd_status rfd_bary_floored(rfd_bary_t bary, int64_t* count, rfd_stream_t stream);
+
+void rfd_bary_destroy(rfd_bary_t bary);
 
 /* ------------------------------------------- Gromov-Wasserstein loss matrix */
 

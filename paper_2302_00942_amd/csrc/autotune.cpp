@@ -122,6 +122,31 @@ rfd_status rfd_autotune(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, fl
   (void)hipEventDestroy(e1);
   rfd::set_tuned(rfd::kTuneExpandTilesPerWave, M, prec, DB, N, ok && best ? best : prev);
   if (!ok || best == 0) return RFD_ERR_DEVICE;
+  // fields of at most kValuMaxD channels: matrix-core or FMA arithmetic of the
+  // expansion, whichever runs faster (this knob does change the rounding;
+  // both paths are within the precision's bar, and single and batched calls
+  // read the same entry)
+  if (d <= rfd::kValuMaxD) {
+    float path_ms[2] = {1e30f, 1e30f};
+    const int path_prev = rfd::expand_path(M, prec, d);
+    const int paths[2] = {rfd::kExpandMfma, rfd::kExpandValu};
+    e0 = e1 = nullptr;
+    ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    for (int q = 0; ok && q < 2; ++q) {
+      rfd::set_tuned(rfd::kTuneExpandPath, M, prec, 1, (int64_t)1 << d, paths[q]);
+      ok = rfd::launch_expand(p, p->dev.X, N, F, ldF, dc, out, ldO, nullptr, st) == hipSuccess &&
+           hipEventRecord(e0, st) == hipSuccess;
+      for (int r = 0; ok && r < reps; ++r)
+        ok = rfd::launch_expand(p, p->dev.X, N, F, ldF, dc, out, ldO, nullptr, st) == hipSuccess;
+      ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&path_ms[q], e0, e1) == hipSuccess;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    rfd::set_tuned(rfd::kTuneExpandPath, M, prec, 1, (int64_t)1 << d,
+                   ok ? (path_ms[1] < path_ms[0] ? rfd::kExpandValu : rfd::kExpandMfma) : path_prev);
+    if (!ok) return RFD_ERR_DEVICE;
+  }
   // leave the full result in out
   return rfd::integrate_enqueue(p, F, ldF, d, out, ldO, st, 0, nullptr);
 }
@@ -131,7 +156,7 @@ rfd_status rfd_autotune_phi1(rfd_plan_t p, int32_t reps, rfd_stream_t stream) {
   if (p->N < 0) return RFD_ERR_NOT_READY;
   if (p->N == 0) return RFD_OK;
   hipStream_t st = (hipStream_t)stream;
-  const int M = p->dev_m, nt = (M / 32) * (M / 32);
+  const int M = p->dev_m, nt = rfd::phi1_grid_workers_max(p);
   const int prev = rfd::tuned(rfd::kTunePhi1Workgroups, M, 0, 1, 0, nt);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCK(hipEventCreate(&e0));
@@ -143,7 +168,7 @@ rfd_status rfd_autotune_phi1(rfd_plan_t p, int32_t reps, rfd_stream_t stream) {
   float best_ms = 1e30f;
   bool ok = true;
   // phi_1 reads the plan's core and rewrites S and T with the same values
-  for (int nw = nt; ok && nw >= 2 && nw * 4 >= nt; nw /= 2) {
+  for (int nw = nt; ok && nw >= 2 && nw * 4 >= nt; nw = nw * 3 / 4) {
     rfd::set_tuned(rfd::kTunePhi1Workgroups, M, 0, 1, 0, nw);
     ok = rfd::launch_phi1(p, st) == hipSuccess && hipEventRecord(e0, st) == hipSuccess;
     for (int r = 0; ok && r < reps; ++r) ok = rfd::launch_phi1(p, st) == hipSuccess;

@@ -10,6 +10,7 @@
 
 struct rfd_batch_s {
   int n = 0, M = 0, prec = 0, DB = 1, dmax = 0, tpi = 64;
+  int tpi_v = 64;  // tiles per item of the FMA-path expansion list (fixed at creation)
   bool aliased = false;  // some out aliases its F (the batch is then not re-runnable)
   int64_t total_n = 0;
   std::vector<int64_t> Ns;
@@ -26,7 +27,9 @@ struct rfd_batch_s {
   rfd::CloudDesc* dcl = nullptr;
   int2* dwork_bta = nullptr;
   int2* dwork_exp = nullptr;
-  int nwork_bta = 0, nwork_exp = 0;
+  int2* dwork_expv = nullptr;    // expansion items of the clouds on the FMA path (expand_path)
+  std::vector<bool> valu;        // per cloud: expansion on the FMA path
+  int nwork_bta = 0, nwork_exp = 0, nwork_expv = 0;
   void* dargs = nullptr;
   int launches = 0;
   std::vector<const void*> bound;  // per plan: the X copy and partial buffers the work lists point into
@@ -41,10 +44,12 @@ namespace {
     if ((x) != hipSuccess) return RFD_ERR_DEVICE; \
   } while (0)
 
-// Expansion work items: (cloud, first tile) every `tpi` tiles of 16 points.
-std::vector<int2> expand_work(const std::vector<int64_t>& Ns, int tpi) {
+// Expansion work items: (cloud, first tile) every `tpi` tiles of 16 points,
+// for the clouds whose flag in `on_valu` equals `valu`.
+std::vector<int2> expand_work(const std::vector<int64_t>& Ns, int tpi, const std::vector<bool>& on_valu, bool valu) {
   std::vector<int2> we;
   for (int i = 0; i < (int)Ns.size(); ++i) {
+    if (on_valu[i] != valu) continue;
     const int64_t ntiles = (Ns[i] + 15) / 16;
     for (int64_t t0 = 0; t0 < ntiles; t0 += tpi) we.push_back(make_int2(i, (int)t0));
   }
@@ -70,7 +75,8 @@ void longest_first(std::vector<unsigned char>& a, size_t asz, std::vector<unsign
 void free_batch(rfd_batch_s* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  void* ptrs[] = {b->dcl, b->dwork_bta, b->dwork_exp, b->dargs, b->dargs_apply, b->daargs, b->dcl_full};
+  void* ptrs[] = {b->dcl, b->dwork_bta, b->dwork_exp, b->dwork_expv, b->dargs, b->dargs_apply, b->daargs,
+                  b->dcl_full};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete b;
@@ -86,6 +92,8 @@ rfd_status enqueue(rfd_batch_s* b, hipStream_t st) {
   }
   if (b->nwork_exp > 0)
     HIPCK(rfd::launch_expand_batch(b->M, b->prec, b->DB, b->dcl, b->dwork_exp, b->nwork_exp, b->tpi, st));
+  if (b->nwork_expv > 0)
+    HIPCK(rfd::launch_expand_valu_batch(b->M, b->prec, b->dcl, b->dwork_expv, b->nwork_expv, b->tpi_v, st));
   return RFD_OK;
 }
 
@@ -207,12 +215,19 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
     b->bound.push_back(plans[i]->dev.X);
     b->bound.push_back(plans[i]->dev.partials);
   }
-  const std::vector<int2> we = expand_work(b->Ns, b->tpi);
+  // the expansion path of each cloud follows the single-cloud entry points
+  // (expand_path of its field width), so every cloud keeps its bits
+  for (int i = 0; i < n; ++i) b->valu.push_back(rfd::expand_path(M, prec, ds[i]) == rfd::kExpandValu);
+  const std::vector<int2> we = expand_work(b->Ns, b->tpi, b->valu, false);
+  b->tpi_v = b->tpi;
+  const std::vector<int2> wv = expand_work(b->Ns, b->tpi_v, b->valu, true);
   b->nwork_bta = (int)wb.size();
   b->nwork_exp = (int)we.size();
+  b->nwork_expv = (int)wv.size();
   b->exp_cap = b->nwork_exp;
   bool ok = upload(&b->dcl, cl) == hipSuccess &&
             upload(&b->dwork_bta, wb) == hipSuccess && upload(&b->dwork_exp, we) == hipSuccess &&
+            upload(&b->dwork_expv, wv) == hipSuccess &&
             upload((unsigned char**)&b->dargs, args) == hipSuccess &&
             upload((unsigned char**)&b->dargs_apply, args_apply) == hipSuccess &&
             upload((unsigned char**)&b->daargs, aargs) == hipSuccess && upload(&b->dcl_full, cl_full) == hipSuccess;
@@ -272,7 +287,7 @@ rfd_status rfd_batch_tune(rfd_batch_t b, int32_t reps, rfd_stream_t stream) {
   for (int i = 0; i < b->n; ++i) b->plans[i]->core_ready = !b->applied[i];
   if (s != RFD_OK || b->nwork_exp == 0) return s;
   static const int cands[] = {8, 16, 32, 64, 128, 256};
-  const std::vector<int2> most = expand_work(b->Ns, cands[0]);
+  const std::vector<int2> most = expand_work(b->Ns, cands[0], b->valu, false);
   int2* dw = nullptr;
   HIPCK(hipMalloc((void**)&dw, sizeof(int2) * most.size()));
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -280,7 +295,7 @@ rfd_status rfd_batch_tune(rfd_batch_t b, int32_t reps, rfd_stream_t stream) {
   float best_ms = 1e30f;
   bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
   for (int c = 0; ok && c < (int)(sizeof(cands) / sizeof(cands[0])); ++c) {
-    const std::vector<int2> we = expand_work(b->Ns, cands[c]);
+    const std::vector<int2> we = expand_work(b->Ns, cands[c], b->valu, false);
     // (the previous candidate's launches have finished: its end event was waited on)
     ok = hipMemcpyAsync(dw, we.data(), sizeof(int2) * we.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
          hipStreamSynchronize(st) == hipSuccess &&
@@ -303,7 +318,7 @@ rfd_status rfd_batch_tune(rfd_batch_t b, int32_t reps, rfd_stream_t stream) {
   if (!ok) return RFD_ERR_DEVICE;
   rfd::set_tuned(rfd::kTuneBatchExpandTilesPerItem, b->M, b->prec, b->DB, b->total_n, best);
   if (best != b->tpi) {
-    const std::vector<int2> we = expand_work(b->Ns, best);
+    const std::vector<int2> we = expand_work(b->Ns, best, b->valu, false);
     if ((int)we.size() > b->exp_cap) {
       (void)hipFree(b->dwork_exp);
       b->dwork_exp = nullptr;

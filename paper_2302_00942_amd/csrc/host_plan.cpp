@@ -115,12 +115,70 @@ hipError_t dalloc(T** p, size_t count) {
   return hipMalloc((void**)p, count * sizeof(T));
 }
 
+// Where a plan's buffers come from at creation: hipMalloc, or 256-byte
+// aligned pieces of a caller's arena (base != nullptr; with base == nullptr
+// and carving on, only the bytes are counted).
+struct Source {
+  bool carve = false;
+  unsigned char* base = nullptr;
+  size_t off = 0, cap = 0;
+  template <class T>
+  hipError_t get(T** p, size_t count) {
+    if (!carve) return dalloc(p, count);
+    *p = nullptr;
+    const size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    if (base && off + bytes > cap) return hipErrorOutOfMemory;
+    if (base && count) *p = (T*)(base + off);
+    off += bytes;
+    return hipSuccess;
+  }
+};
+
 void free_dev(rfd::PlanDev& d) {
-  void* ptrs[] = {d.om, d.cvec, d.svec, d.X, d.Mraw, d.H0, d.S64, d.T64, d.G32, d.Gt16, d.G64,
-                  d.phi_ws, d.sdev, d.barrier, d.flag, d.lvl, d.partials};
-  for (void* q : ptrs)
-    if (q) (void)hipFree(q);
+  if (!d.external) {
+    void* ptrs[] = {d.om, d.cvec, d.svec, d.X, d.Mraw, d.H0, d.S64, d.T64, d.G32, d.Gt16, d.G64,
+                    d.phi_ws, d.sdev, d.barrier, d.flag, d.lvl, d.partials};
+    for (void* q : ptrs)
+      if (q) (void)hipFree(q);
+  }
   d = rfd::PlanDev{};
+}
+
+// Takes every fixed buffer of a plan with padded size M from `src`, and with
+// an arena also the point copy and the partials for clouds of up to N_max
+// points and fields of up to d_max channels (one-shot and resident passes).
+hipError_t take_buffers(Source& src, rfd::PlanDev& d, int M, int prec, int64_t N_max, int d_max) {
+  const int fp = M / 2;
+  const size_t mm = (size_t)M * M;
+  hipError_t e = hipSuccess;
+  const auto ok = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  ok(src.get(&d.om, fp));
+  ok(src.get(&d.cvec, M));
+  ok(src.get(&d.svec, M));
+  ok(src.get(&d.Mraw, mm));
+  ok(src.get(&d.H0, (size_t)M * 64));
+  ok(src.get(&d.S64, mm));
+  ok(src.get(&d.T64, mm));
+  ok(src.get(&d.G32, (size_t)M * 64));
+  ok(src.get(&d.Gt16, (size_t)2 * M * 64));
+  ok(src.get(&d.G64, (size_t)M * 32));
+  ok(src.get(&d.phi_ws, rfd::phi1_ws_doubles(M)));
+  ok(src.get(&d.sdev, 1));
+  ok(src.get(&d.barrier, rfd::kBarrierWords));
+  ok(src.get(&d.flag, 1));
+  ok(src.get(&d.lvl, rfd::reduce_scratch_doubles(M)));
+  if (src.carve) {
+    const size_t pf = std::max(rfd::request_partial_floats(M, prec, N_max, d_max, true),
+                               rfd::request_partial_floats(M, prec, N_max, d_max, false));
+    ok(src.get(&d.X, (size_t)N_max * 3));
+    ok(src.get(&d.partials, pf));
+    d.Xcap = N_max;
+    d.partials_cap = pf;
+    d.external = true;
+  }
+  return e;
 }
 
 // Frequencies (sampled from the seed, or taken from params->omega) and the
@@ -177,6 +235,7 @@ namespace rfd {
 
 rfd_status ensure_partials(rfd_plan_s* p, size_t floats, hipStream_t st) {
   if (floats <= p->dev.partials_cap) return RFD_OK;
+  if (p->dev.external) return RFD_ERR_OUT_OF_BUDGET;  // beyond the arena's sizing: never allocate
   if (p->dev.partials) {
     HIPCK(hipStreamSynchronize(st));
     HIPCK(hipFree(p->dev.partials));
@@ -190,6 +249,7 @@ rfd_status ensure_partials(rfd_plan_s* p, size_t floats, hipStream_t st) {
 
 rfd_status ensure_x(rfd_plan_s* p, int64_t N, hipStream_t st) {
   if (N <= p->dev.Xcap) return RFD_OK;
+  if (p->dev.external) return RFD_ERR_OUT_OF_BUDGET;
   if (p->dev.X) {
     HIPCK(hipStreamSynchronize(st));
     HIPCK(hipFree(p->dev.X));
@@ -360,7 +420,11 @@ const char* rfd_status_string(rfd_status s) {
   return "unknown status";
 }
 
-rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan) {
+}  // extern "C"
+
+namespace {
+
+rfd_status create_plan(const rfd_params* params, Source& src, int64_t N_max, int d_max, rfd_plan_t* out_plan) {
   if (!out_plan) return RFD_ERR_INVALID_ARG;
   *out_plan = nullptr;
   rfd_status st = check_params(params);
@@ -389,20 +453,13 @@ rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan) {
   const int fp = M / 2;
   (void)hipGetDevice(&p->device);
   rfd::PlanDev& d = p->dev;
-  const size_t mm = (size_t)M * M;
-  bool ok = dalloc(&d.om, fp) == hipSuccess && dalloc(&d.cvec, M) == hipSuccess && dalloc(&d.svec, M) == hipSuccess &&
-            dalloc(&d.Mraw, mm) == hipSuccess && dalloc(&d.H0, (size_t)M * 64) == hipSuccess &&
-            dalloc(&d.S64, mm) == hipSuccess && dalloc(&d.T64, mm) == hipSuccess &&
-            dalloc(&d.G32, (size_t)M * 64) == hipSuccess && dalloc(&d.Gt16, (size_t)2 * M * 64) == hipSuccess &&
-            dalloc(&d.G64, (size_t)M * 32) == hipSuccess &&
-            dalloc(&d.phi_ws, rfd::phi1_ws_doubles(M)) == hipSuccess &&
-            dalloc(&d.sdev, 1) == hipSuccess && dalloc(&d.barrier, rfd::kBarrierWords) == hipSuccess && dalloc(&d.flag, 1) == hipSuccess &&
-            dalloc(&d.lvl, rfd::reduce_scratch_doubles(M)) == hipSuccess;
-  if (!ok) {
+  const hipError_t te = take_buffers(src, d, M, params->precision, N_max, d_max);
+  if (te != hipSuccess) {
     free_dev(d);
     delete p;
-    return RFD_ERR_DEVICE;
+    return te == hipErrorOutOfMemory && src.carve ? RFD_ERR_OUT_OF_BUDGET : RFD_ERR_DEVICE;
   }
+  bool ok = true;
   std::vector<float4> om(fp);
   std::vector<double> cv(M, 0.0), sv(M, 1.0);
   for (int k = 0; k < fp; ++k) {
@@ -435,6 +492,42 @@ rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan) {
   return RFD_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan) {
+  Source src;
+  return create_plan(params, src, 0, 0, out_plan);
+}
+
+rfd_status rfd_plan_workspace_size(const rfd_params* params, int64_t N_max, int32_t d_max, size_t* bytes) {
+  if (!bytes) return RFD_ERR_INVALID_ARG;
+  *bytes = 0;
+  rfd_status st = check_params(params);
+  if (st != RFD_OK) return st;
+  if (N_max < 0 || d_max < 0 || d_max > rfd::kMaxD) return RFD_ERR_INVALID_ARG;
+  Source src;
+  src.carve = true;
+  rfd::PlanDev d;
+  (void)take_buffers(src, d, rfd::padded_m(params->m), params->precision, N_max, d_max < 1 ? 1 : d_max);
+  *bytes = src.off;
+  return RFD_OK;
+}
+
+rfd_status rfd_plan_create_in(const rfd_params* params, void* arena_dev, size_t bytes, int64_t N_max, int32_t d_max,
+                              rfd_plan_t* out_plan) {
+  if (!out_plan) return RFD_ERR_INVALID_ARG;
+  *out_plan = nullptr;
+  if (!arena_dev || ((uintptr_t)arena_dev & 255) || N_max < 0 || d_max < 0 || d_max > rfd::kMaxD)
+    return RFD_ERR_INVALID_ARG;
+  Source src;
+  src.carve = true;
+  src.base = (unsigned char*)arena_dev;
+  src.cap = bytes;
+  return create_plan(params, src, N_max, d_max < 1 ? 1 : d_max, out_plan);
+}
+
 rfd_status rfd_params_frequencies(const rfd_params* params, float* omega_fx3, double* w_f) {
   rfd_status st = check_params(params);
   if (st != RFD_OK) return st;
@@ -459,6 +552,13 @@ rfd_status rfd_plan_export(rfd_plan_t p, float* omega_fx3, double* w_f) {
 rfd_status rfd_features(rfd_plan_t p, const float* X_dev, int64_t N, rfd_stream_t stream) {
   if (!p) return RFD_ERR_INVALID_ARG;
   return rfd::features_enqueue(p, X_dev, N, (hipStream_t)stream, nullptr);
+}
+
+rfd_status rfd_features_sync(rfd_plan_t p, const float* X_dev, int64_t N, rfd_stream_t stream) {
+  if (!p) return RFD_ERR_INVALID_ARG;
+  const rfd_status s = rfd::features_enqueue(p, X_dev, N, (hipStream_t)stream, nullptr);
+  if (s != RFD_OK) return s;
+  return rfd_plan_check(p, stream);
 }
 
 rfd_status rfd_integrate(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, float* out, int64_t ldO,

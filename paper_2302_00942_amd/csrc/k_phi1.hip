@@ -28,7 +28,7 @@ namespace rfd {
 
 struct Phi1Args {
   int m;               // padded size, a multiple of 64, <= 256
-  int reserved;
+  int sym;             // 1: every weight is >= 0, so lambda M and every matrix of both chains is symmetric
   double lambda;
   const double* Mraw;  // m x m, canonical order (symmetric)
   const double* cvec;  // m, canonical order
@@ -52,8 +52,14 @@ struct ApplyArgs {
 };
 constexpr int kThinWidth = 32;
 
+// One workgroup per cloud: the phases' global stores are waited for before
+// the workgroup barrier, so every wave's next loads see them (the barrier
+// alone does not wait for outstanding stores).
 struct WgBarrier {
-  __device__ __forceinline__ void sync() { __syncthreads(); }
+  __device__ __forceinline__ void sync() {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  }
   __device__ __forceinline__ void finish() {}
 };
 
@@ -61,40 +67,54 @@ struct WgBarrier {
 // counter of their group of kBarGroup (128-byte apart lines); the last arrival
 // of a group (seen from the returned count) bumps the top counter, which every
 // workgroup polls. Counters only grow: round r waits for r * groups top
-// arrivals. Ordering comes from fences around relaxed counter operations:
-// each arrival is preceded by an agent-scope release fence; the last arrival
-// of a group takes an acquire-release fence before it bumps the top counter
-// (so the group's writes reach every poller through it); the poll is relaxed
-// and followed by one acquire fence. On gfx950 that is one L2 write-back
-// before the arrival and one invalidate after the wait. The wait is bounded:
-// on timeout the flag gets bit 2 and the workgroup proceeds, so every wave
-// always exits. The counters start at zero (the plan zeroes them when it is
-// created) and every launch leaves them at zero: after its last wait each
-// workgroup arrives on an exit counter (word 1), and the last arrival, which
-// knows that no workgroup of the launch reads a counter again, clears them
-// all, so no clearing kernel runs between launches on a stream.
+// arrivals. The wait is bounded: on timeout the flag gets bit 2 and the
+// workgroup proceeds, so every wave always exits. The counters start at zero
+// (the plan zeroes them when it is created) and every launch leaves them at
+// zero: after its last wait each workgroup arrives on an exit counter (word 1),
+// and the last arrival, which knows that no workgroup of the launch reads a
+// counter again, clears them all, so no clearing kernel runs between launches.
+//
+// Visibility of the phase data. Every wave waits for its own stores to be
+// acknowledged before the workgroup arrives, and every wave drops its L1
+// lines after the wait (the L1 is write-through, so stores sit in the L2 of
+// the writer's XCD). When all workers run on one XCD they share that L2, and
+// this is all the ordering the phases need: no L2 write-back or invalidate.
+// The workers publish the XCD they run on before the first wait; the first
+// wait also takes an agent-scope release fence before the arrival and an
+// acquire fence after the wait (one L2 write-back and one invalidate), after
+// which every worker compares the published ids. Only if they all agree do
+// the later waits drop the two fences; otherwise every wait keeps them.
 constexpr int kBarGroup = 16;
 constexpr int kBarStride = 32;        // unsigned words between counters (128 bytes)
 constexpr int kBarWords = kBarStride * (1 + 256 / kBarGroup);
-static_assert(kBarWords <= kBarrierWords, "barrier counters exceed the plan's buffer");
+constexpr int kXccWords = kBarWords;  // then one word per worker: the XCD it runs on
+static_assert(kXccWords + 256 <= kBarrierWords, "barrier counters exceed the plan's buffer");
+// XCC_ID hardware register, bits [15:0]
+constexpr int kXccIdReg = 20 | (0 << 6) | ((16 - 1) << 11);
 
 struct GridBarrier {
   unsigned* ctr;
   unsigned nblocks;
+  unsigned worker;
   unsigned round;
   int* flag;
+  bool local;  // thread 0 only: every worker is on one XCD
+  __device__ __forceinline__ void publish_xcd() {
+    if (threadIdx.x == 0) ctr[kXccWords + worker] = (unsigned)__builtin_amdgcn_s_getreg(kXccIdReg);
+  }
   __device__ __forceinline__ void sync() {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are in L2
     __syncthreads();
     if (threadIdx.x == 0) {
       ++round;
-      const unsigned g = blockIdx.x / kBarGroup;
+      const unsigned g = worker / kBarGroup;
       const unsigned groups = (nblocks + kBarGroup - 1) / kBarGroup;
       const unsigned gsz = (g + 1 < groups) ? kBarGroup : nblocks - g * kBarGroup;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned old =
           __hip_atomic_fetch_add(ctr + kBarStride * (1 + g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (old + 1 == round * gsz) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
         __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       const unsigned target = round * groups;
@@ -106,9 +126,17 @@ struct GridBarrier {
           break;
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (round == 1) {
+        const unsigned mine = ctr[kXccWords + worker];
+        bool same = true;
+        for (unsigned w = 0; w < nblocks; ++w)
+          same = same && __hip_atomic_load(ctr + kXccWords + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == mine;
+        local = same;
+      }
     }
     __syncthreads();
+    asm volatile("buffer_inv sc0" ::: "memory");  // drop this CU's L1 lines
   }
   // Called once by every workgroup after its last sync.
   __device__ __forceinline__ void finish() {
@@ -266,7 +294,10 @@ __device__ __forceinline__ void gemm_range(int first, int end, int step, MAP map
       for (int c = 0; c < 4; ++c) acc[p][c] = f64x4{0.0, 0.0, 0.0, 0.0};
   };
   // f64 16x16x4 output layout: register r holds row 4 r + l/16, column l%16
+  // an off-diagonal tile of a symmetric product is stored at (i, j) and (j, i):
+  // the side matrices the epilogue reads are then symmetric too
   const auto epilogue = [&](int i0, int j0, const f64x4 (&acc)[NP][4], const Side<NS> (&side)[4]) {
+    const bool mir = map.mirror(i0, j0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = i0 * 32 + qi * 16 + 4 * r + (l >> 4);
@@ -276,6 +307,7 @@ __device__ __forceinline__ void gemm_range(int first, int end, int step, MAP map
           NP == 2 ? alpha2 * ((acc[NP - 1][0][r] + acc[NP - 1][1][r]) + (acc[NP - 1][2][r] + acc[NP - 1][3][r]))
                   : 0.0;
       epi(i, j, v1, v2, side[r]);
+      if (mir) epi(j, i, v1, v2, side[r]);
     }
   };
   if constexpr (ALL && NB_K == 1) {
@@ -341,12 +373,28 @@ __device__ __forceinline__ void gemm_range(int first, int end, int step, MAP map
 // (tile (t / nb, t % nb) of an m x m product) come first, then the thin row
 // blocks t = nt .. nt + nthin - 1 (tile (t - nt, 0)), as in the loop
 // for (t = worker; t < nt + nthin; t += nw).
+// A symmetric product (sym) is formed from its upper block triangle only:
+// tile t runs over the nb (nb + 1) / 2 tiles (i, j), i <= j, row by row, and
+// an off-diagonal tile is also stored at its mirror position (j, i); a
+// diagonal tile computes each of its elements itself.
 struct FullTileMap {
   int nb;
+  bool sym;
   __device__ void operator()(int t, int& ti, int& tj) const {
-    ti = t / nb;
-    tj = t - ti * nb;
+    if (!sym) {
+      ti = t / nb;
+      tj = t - ti * nb;
+      return;
+    }
+    int i = 0;
+    while (t >= nb - i) {
+      t -= nb - i;
+      ++i;
+    }
+    ti = i;
+    tj = i + t;
   }
+  __device__ bool mirror(int ti, int tj) const { return sym && ti != tj; }
 };
 struct ThinTileMap {
   int nt;
@@ -354,14 +402,16 @@ struct ThinTileMap {
     ti = t - nt;
     tj = 0;
   }
+  __device__ bool mirror(int, int) const { return false; }
 };
+__host__ __device__ constexpr int full_tiles(int nb, bool sym) { return sym ? nb * (nb + 1) / 2 : nb * nb; }
 struct PhaseTiles {
   int first_full, end_full, first_thin, end_thin, step;
   FullTileMap full;
   ThinTileMap thin;
-  __device__ PhaseTiles(int worker, int nw, int nb, int nthin)
-      : first_full(worker), end_full(nb * nb), step(nw), full{nb}, thin{nb * nb} {
-    const int nt = nb * nb;
+  __device__ PhaseTiles(int worker, int nw, int nb, int nthin, bool sym)
+      : first_full(worker), end_full(full_tiles(nb, sym)), step(nw), full{nb, sym}, thin{full_tiles(nb, sym)} {
+    const int nt = end_full;
     first_thin = worker >= nt ? worker : worker + ((nt - worker + nw - 1) / nw) * nw;
     end_thin = nt + nthin;
   }
@@ -430,6 +480,7 @@ struct TaylorWs {
   double* Y4;
   double* R[2][2];   // [chain][ping-pong]
   double sc1;        // 2^-s
+  bool sym;          // symmetric chain (see FullTileMap)
 };
 
 // Horner step J (J = 4 ... 0): R_chain <- Y4 R_chain + B_J, both chains (one
@@ -439,7 +490,7 @@ __device__ __forceinline__ void horner_phase(const TaylorWs& w, int worker, int 
   constexpr int nb = m / 32, nt = nb * nb;
   constexpr int src = (J + 1) & 1, dst = J & 1;
   {
-    const PhaseTiles pt(worker, nw, nb, 0);
+    const PhaseTiles pt(worker, nw, nb, 0, w.sym);
     gemm_range<m, KB, ALL, 2, kShareA, 3>(
         pt.first_full, pt.end_full, pt.step, pt.full, w.Y4, w.R[0][src], w.Y4, w.R[1][src], 1.0, 1.0, lds,
         [&](int i, int j, double v0, double v1, const Side<3>& sd) {
@@ -484,7 +535,7 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
 
   // ---- P1: Y2 = X0 X0 / 4^s
   {
-    const PhaseTiles pt(worker, nw, nb, 0);
+    const PhaseTiles pt(worker, nw, nb, 0, a.sym != 0);
     gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, pt.full, X0, X0, X0, X0, sc2, 0.0, lds,
                                        [&](int i, int j, double v, double, const Side<0>&) {
                                          gst(Y2 + (size_t)i * m + j, v);
@@ -493,7 +544,7 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   bar.sync();
   // ---- P2: Y3 = Y2 X0 / 2^s (its epilogue also forms B_5 of both chains) and Y4 = Y2 Y2
   {
-    const PhaseTiles pt(worker, nw, nb, 0);
+    const PhaseTiles pt(worker, nw, nb, 0, a.sym != 0);
     gemm_range<m, KB, ALL, 2, kShareA, 2>(
         pt.first_full, pt.end_full, pt.step, pt.full, Y2, X0, Y2, Y2, sc1, 1.0, lds,
         [&](int i, int j, double y3, double y4, const Side<2>& sd) {
@@ -508,7 +559,7 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   }
   bar.sync();
   // ---- P3..P7: Horner steps J = 4 ... 0 (J odd reads buffer 0, writes 1 ... ends in buffer 0)
-  const TaylorWs w{X0, Y2, Y3, Y4, {{R00, R01}, {R10, R11}}, sc1};
+  const TaylorWs w{X0, Y2, Y3, Y4, {{R00, R01}, {R10, R11}}, sc1, a.sym != 0};
   horner_phase<m, KB, ALL, 4>(w, worker, nw, lds, bar);
   horner_phase<m, KB, ALL, 3>(w, worker, nw, lds, bar);
   horner_phase<m, KB, ALL, 2>(w, worker, nw, lds, bar);
@@ -521,7 +572,7 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   double* En = R11;
   for (int it = 0; it < s; ++it) {
     {
-      const PhaseTiles pt(worker, nw, nb, 0);
+      const PhaseTiles pt(worker, nw, nb, 0, a.sym != 0);
       gemm_range<m, KB, ALL, 2, kShareB, 1>(
           pt.first_full, pt.end_full, pt.step, pt.full, Ec, Ec, Pc, Ec, 1.0, 0.5, lds,
           [&](int i, int j, double e2, double pe, const Side<1>& sd) {
@@ -567,7 +618,7 @@ __device__ __forceinline__ void apply_horner(const TaylorWs& w, double* const (&
   constexpr int nb = m / 32, nt = nb * nb, TW = kThinWidth;
   constexpr int src = (J + 1) & 1, dst = J & 1;
   {
-    const PhaseTiles pt(worker, nw, nb, nb);
+    const PhaseTiles pt(worker, nw, nb, nb, w.sym);
     gemm_range<m, KB, ALL, 1, kShareA, 3>(
         pt.first_full, pt.end_full, pt.step, pt.full, w.Y4, E[src], w.Y4, E[src], 1.0, 0.0, lds,
         [&](int i, int j, double v, double, const Side<3>& sd) {
@@ -623,7 +674,7 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
 
   // ---- P1: Y2 = X0 X0 / 4^s; U1 = Y v
   {
-    const PhaseTiles pt(worker, nw, nb, nb);
+    const PhaseTiles pt(worker, nw, nb, nb, a.sym != 0);
     gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, pt.full, X0, X0, X0, X0, sc2, 0.0, lds,
                                        [&](int i, int j, double v, double, const Side<0>&) {
                                          gst(Y2 + (size_t)i * m + j, v);
@@ -636,7 +687,7 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
   bar.sync();
   // ---- P2: Y3 = Y2 Y, Y4 = Y2 Y2 (with B_5 of the exp chain); U2 = Y2 v, U3 = Y2 U1 (with B_5 v)
   {
-    const PhaseTiles pt(worker, nw, nb, nb);
+    const PhaseTiles pt(worker, nw, nb, nb, a.sym != 0);
     gemm_range<m, KB, ALL, 2, kShareA, 2>(
         pt.first_full, pt.end_full, pt.step, pt.full, Y2, X0, Y2, Y2, sc1, 1.0, lds,
         [&](int i, int j, double y3, double y4, const Side<2>& sd) {
@@ -659,7 +710,7 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
   }
   bar.sync();
   // ---- Horner steps J = 4 ... 0 (results in E0 and W0)
-  const TaylorWs w{X0, Y2, Y3, Y4, {{nullptr, nullptr}, {nullptr, nullptr}}, sc1};
+  const TaylorWs w{X0, Y2, Y3, Y4, {{nullptr, nullptr}, {nullptr, nullptr}}, sc1, a.sym != 0};
   double* const E[2] = {E0, E1};
   double* const W[2] = {W0, W1};
   apply_horner<m, KB, ALL, 4>(w, E, V, U1, U2, U3, W, worker, nw, lds, bar);
@@ -674,7 +725,7 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
   double* Wn = W1;
   for (int it = 0; it < s; ++it) {
     {
-      const PhaseTiles pt(worker, nw, nb, nb);
+      const PhaseTiles pt(worker, nw, nb, nb, a.sym != 0);
       if (it + 1 < s)
         gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, pt.full, Ec, Ec, Ec, Ec, 1.0, 0.0,
                                            lds, [&](int i, int j, double v, double, const Side<0>&) {
@@ -724,19 +775,32 @@ __global__ __launch_bounds__(256) void k_phi1_wg(const Phi1Args* __restrict__ ar
   phi1_body<M, wg_kb<M>(), wg_all<M>()>(a, 0, 1, lds, bar);
 }
 
+// The cooperative kernels are launched with kXcds workgroups per worker;
+// workgroups are dealt to the XCDs in turn, so every kXcds-th one (the
+// workers) runs on one XCD and the others leave at once. The barrier checks
+// that placement (see GridBarrier) and keeps its fences if it does not hold.
+constexpr int kXcds = 8;
+constexpr int kMaxWorkers = 32;  // CUs of one XCD: one worker each (its LDS allows no second)
+
 template <int M>
 __global__ __launch_bounds__(256) void k_phi1_grid(Phi1Args a) {
   extern __shared__ double lds[];
-  GridBarrier bar{a.barrier, gridDim.x, 0u, a.flag};
-  phi1_body<M, (M < kGridKB ? M : kGridKB), true>(a, (int)blockIdx.x, (int)gridDim.x, lds, bar);
+  if (blockIdx.x % kXcds != 0) return;
+  const unsigned worker = blockIdx.x / kXcds, nw = gridDim.x / kXcds;
+  GridBarrier bar{a.barrier, nw, worker, 0u, a.flag, false};
+  bar.publish_xcd();
+  phi1_body<M, (M < kGridKB ? M : kGridKB), true>(a, (int)worker, (int)nw, lds, bar);
   bar.finish();
 }
 
 template <int M>
 __global__ __launch_bounds__(256) void k_phi1_apply_grid(Phi1Args a, ApplyArgs ap) {
   extern __shared__ double lds[];
-  GridBarrier bar{a.barrier, gridDim.x, 0u, a.flag};
-  apply_body<M, (M < kGridKB ? M : kGridKB), true>(a, ap, (int)blockIdx.x, (int)gridDim.x, lds, bar);
+  if (blockIdx.x % kXcds != 0) return;
+  const unsigned worker = blockIdx.x / kXcds, nw = gridDim.x / kXcds;
+  GridBarrier bar{a.barrier, nw, worker, 0u, a.flag, false};
+  bar.publish_xcd();
+  apply_body<M, (M < kGridKB ? M : kGridKB), true>(a, ap, (int)worker, (int)nw, lds, bar);
   bar.finish();
 }
 
@@ -757,7 +821,9 @@ size_t phi1_ws_doubles(int m) { return 8 * (size_t)m * m + m + 6 * (size_t)m * k
 
 static void fill_args(rfd_plan_s* p, Phi1Args& a) {
   a.m = p->dev_m;
-  a.reserved = 0;
+  a.sym = 1;
+  for (double w : p->w)
+    if (w < 0.0) a.sym = 0;
   a.lambda = p->params.lambda;
   a.Mraw = p->dev.Mraw;
   a.cvec = p->dev.cvec;
@@ -776,15 +842,19 @@ static hipError_t launch_phi1_m(Phi1Args& a, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)k_phi1_grid<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   constexpr int nb = M / 32;
-  // workgroups: every phase has nb^2 tiles (pairs of products); fewer
-  // workgroups make the barrier cheaper and give each more tiles (the count
-  // never changes results: each tile is computed the same way)
-  int nw = tuned(kTunePhi1Workgroups, M, 0, 1, 0, nb * nb);
+  // workers: every phase has full_tiles(nb, sym) tiles (pairs of products);
+  // fewer workers make the barrier cheaper and give each more tiles (the count
+  // never changes results: each tile is computed the same way). All of them
+  // run on one XCD, at most one per CU there (kMaxWorkers).
+  const int tiles = full_tiles(nb, a.sym != 0);
+  int nw = tuned(kTunePhi1Workgroups, M, 0, 1, 0, tiles < kMaxWorkers ? tiles : kMaxWorkers);
   if (nw < 1) nw = 1;
-  if (nw > nb * nb) nw = nb * nb;
+  if (nw > tiles) nw = tiles;
+  if (nw > kMaxWorkers) nw = kMaxWorkers;
   void* kargs[] = {&a};
   ProfileScope prof(kKPhi1, st);
-  return hipLaunchCooperativeKernel((const void*)k_phi1_grid<M>, dim3(nw), dim3(256), kargs, (unsigned)lds, st);
+  return hipLaunchCooperativeKernel((const void*)k_phi1_grid<M>, dim3(kXcds * nw), dim3(256), kargs, (unsigned)lds,
+                                    st);
 }
 
 hipError_t launch_phi1(rfd_plan_s* p, hipStream_t st) {
@@ -805,10 +875,12 @@ static hipError_t launch_apply_m(Phi1Args& a, ApplyArgs& ap, hipStream_t st) {
       hipFuncSetAttribute((const void*)k_phi1_apply_grid<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   constexpr int nb = M / 32;
-  const int nw = nb * nb + nb;  // full tiles plus thin row tiles
+  const int units = full_tiles(nb, a.sym != 0) + nb;  // full tiles plus thin row tiles
+  const int nw = units < kMaxWorkers ? units : kMaxWorkers;
   void* kargs[] = {&a, &ap};
   ProfileScope prof(kKPhi1Apply, st);
-  return hipLaunchCooperativeKernel((const void*)k_phi1_apply_grid<M>, dim3(nw), dim3(256), kargs, (unsigned)lds, st);
+  return hipLaunchCooperativeKernel((const void*)k_phi1_apply_grid<M>, dim3(kXcds * nw), dim3(256), kargs,
+                                    (unsigned)lds, st);
 }
 
 hipError_t launch_phi1_apply(rfd_plan_s* p, int d, hipStream_t st) {
@@ -826,6 +898,13 @@ hipError_t launch_phi1_apply(rfd_plan_s* p, int d, hipStream_t st) {
 }
 
 int phi1_apply_max_width() { return kThinWidth; }
+
+int phi1_grid_workers_max(rfd_plan_s* p) {
+  Phi1Args a;
+  fill_args(p, a);
+  const int tiles = full_tiles(a.m / 32, a.sym != 0);
+  return tiles < kMaxWorkers ? tiles : kMaxWorkers;
+}
 
 void phi1_fill_apply_args(rfd_plan_s* p, int d, void* out) {
   *(ApplyArgs*)out = ApplyArgs{p->dev.H0, d, 0, p->dev.G32, p->dev.Gt16, p->dev.G64};

@@ -988,6 +988,81 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
   }
 }
 
+// The expansion without the matrix cores, for fields of DV <= 4 channels
+// (the A (G) step with m d small): one thread per point evaluates its
+// features in turn (rounded to BF16 in BF16 mode, as the matrix-core path
+// feeds them) and accumulates the d channels of Phi_i G' with FP32 FMAs, G'
+// in FP32 from LDS (every lane reads the same word: a broadcast).
+template <int M, int PREC, int DV>
+__device__ __forceinline__ void expand_valu_body(const float* __restrict__ X, int64_t N,
+                                                 const float4* __restrict__ om, const float* __restrict__ G32, int d,
+                                                 const float* __restrict__ F, int64_t ldF, float* __restrict__ out,
+                                                 int64_t ldO, const float* __restrict__ rowscale, int64_t p_first,
+                                                 int64_t p_end, int64_t p_step) {
+  constexpr int FQ = M / 2;
+  __shared__ float4 oms[FQ];
+  __shared__ float gs[M * DV];
+  const int tid = threadIdx.x;
+  for (int k = tid; k < FQ; k += 256) oms[k] = gld4((const float*)(om + k));
+  for (int idx = tid; idx < M * DV; idx += 256) {
+    const int j = idx / DV, c = idx - j * DV;
+    gs[idx] = c < d ? gldf(G32 + (size_t)j * d + c) : 0.f;
+  }
+  __syncthreads();
+  for (int64_t p = p_first + tid; p < p_end; p += p_step) {
+    const float x = gldf(X + p * 3), y = gldf(X + p * 3 + 1), z = gldf(X + p * 3 + 2);
+    float acc[DV];
+#pragma unroll
+    for (int c = 0; c < DV; ++c) acc[c] = 0.f;
+#pragma unroll 4
+    for (int k = 0; k < FQ; ++k) {
+      float sn, cs;
+      phase_sincos(oms[k], x, y, z, sn, cs);
+      if constexpr (PREC) {
+        cs = (float)(__bf16)cs;
+        sn = (float)(__bf16)sn;
+      }
+#pragma unroll
+      for (int c = 0; c < DV; ++c) {
+        acc[c] = fmaf(cs, gs[(2 * k) * DV + c], acc[c]);
+        acc[c] = fmaf(sn, gs[(2 * k + 1) * DV + c], acc[c]);
+      }
+    }
+    const float sc = rowscale ? gldf(rowscale + p) : 1.f;
+#pragma unroll
+    for (int c = 0; c < DV; ++c) {
+      if (c < d) {
+        const float v = gldf(F + p * ldF + c) + acc[c];
+        gstf(out + p * ldO + c, rowscale ? sc * v : v);
+      }
+    }
+  }
+}
+
+template <int M, int PREC, int DV>
+__global__ __launch_bounds__(256) void k_expand_valu(const float* __restrict__ X, int64_t N,
+                                                     const float4* __restrict__ om, const float* __restrict__ G32,
+                                                     int d, const float* F, int64_t ldF, float* out, int64_t ldO,
+                                                     const float* __restrict__ rowscale) {
+  expand_valu_body<M, PREC, DV>(X, N, om, G32, d, F, ldF, out, ldO, rowscale, (int64_t)blockIdx.x * 256, N,
+                                (int64_t)gridDim.x * 256);
+}
+
+// Batched: work item (cloud, first tile) covers the points of tpi tiles of 16.
+// Every cloud takes the kValuMaxD-channel body with its own d; channels past
+// d carry zero G' rows, and each kept channel sees the same FMAs in the same
+// order as in the single-cloud kernel of its exact width, so the bits agree.
+template <int M, int PREC>
+__global__ __launch_bounds__(256) void k_expand_valu_batch(const CloudDesc* __restrict__ cl,
+                                                           const int2* __restrict__ work, int tpi) {
+  const int2 wi = work[blockIdx.x];
+  const CloudDesc& c = cl[wi.x];
+  const int64_t p0 = (int64_t)wi.y * 16;
+  int64_t p1 = p0 + (int64_t)tpi * 16;
+  if (p1 > c.N) p1 = c.N;
+  expand_valu_body<M, PREC, kValuMaxD>(c.X, c.N, c.om, c.G32, c.d, c.F, c.ldF, c.out, c.ldO, nullptr, p0, p1, 256);
+}
+
 template <int M, int PREC, int DB>
 __global__ __launch_bounds__(256) void k_expand(const float* __restrict__ X, int64_t N,
                                                 const float4* __restrict__ om, const float* __restrict__ G32,
@@ -1111,9 +1186,65 @@ static hipError_t expand_dispatch(int DB, dim3 grid, const float* X, int64_t N, 
   return hipGetLastError();
 }
 
+template <int M, int PREC>
+static hipError_t expand_valu_dispatch(int64_t N, const float* X, const float4* om, const float* G32, int d,
+                                       const float* F, int64_t ldF, float* out, int64_t ldO, const float* rowscale,
+                                       hipStream_t st) {
+  int64_t nwg = (N + 255) / 256;
+  if (nwg > 4096) nwg = 4096;
+  if (nwg < 1) nwg = 1;
+  const dim3 grid((unsigned)nwg);
+  switch (d) {
+    case 1:
+      hipLaunchKernelGGL((k_expand_valu<M, PREC, 1>), grid, dim3(256), 0, st, X, N, om, G32, d, F, ldF, out, ldO,
+                         rowscale);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_expand_valu<M, PREC, 2>), grid, dim3(256), 0, st, X, N, om, G32, d, F, ldF, out, ldO,
+                         rowscale);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_expand_valu<M, PREC, 3>), grid, dim3(256), 0, st, X, N, om, G32, d, F, ldF, out, ldO,
+                         rowscale);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_expand_valu<M, PREC, 4>), grid, dim3(256), 0, st, X, N, om, G32, d, F, ldF, out, ldO,
+                         rowscale);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Default from measurements on MI355X (resident integrate, 1M and 100k
+// points, m = 64 and 128): in FP32 the FMA path takes 0.43-0.58 of the
+// FP32-matrix-core expansion's time for d <= 3; in BF16 it is 4-8% faster at
+// d = 1 and up to 19% slower at d = 3.
+int expand_path(int M, int prec, int d) {
+  if (d < 1 || d > kValuMaxD) return kExpandMfma;
+  const int rule = (prec == 0 || d == 1) ? kExpandValu : kExpandMfma;
+  (void)M;
+  return tuned(kTuneExpandPath, M, prec, 1, (int64_t)1 << d, rule);
+}
+
 hipError_t launch_expand(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF, int d, float* out,
                          int64_t ldO, const float* rowscale, hipStream_t st) {
   const int M = p->dev_m, prec = p->params.precision;
+  if (expand_path(M, prec, d) == kExpandValu) {
+    const float4* om = p->dev.om;
+    ProfileScope prof(kKExpand, st);
+#define RFD_EXPV(MM, PP) \
+  if (M == MM && prec == PP) return expand_valu_dispatch<MM, PP>(N, X, om, p->dev.G32, d, F, ldF, out, ldO, rowscale, st);
+    RFD_EXPV(64, 0)
+    RFD_EXPV(64, 1)
+    RFD_EXPV(128, 0)
+    RFD_EXPV(128, 1)
+    RFD_EXPV(256, 0)
+    RFD_EXPV(256, 1)
+#undef RFD_EXPV
+    return hipErrorInvalidValue;
+  }
   const int DB = dblocks(d);
   const int64_t ntiles = (N + 15) / 16;
   // tiles of 16 points per wave: launch geometry only (results do not depend on it)
@@ -1301,6 +1432,25 @@ static hipError_t expand_batch_t(bool tout, bool diag, bool epi, int DB, int nwo
   if (epi) return expand_batch_db<M, PREC, true, false, true>(DB, nwork, dcl, dwork, tpi, st);
   return tout ? expand_batch_db<M, PREC, true, false, false>(DB, nwork, dcl, dwork, tpi, st)
               : expand_batch_db<M, PREC, false, false, false>(DB, nwork, dcl, dwork, tpi, st);
+}
+
+hipError_t launch_expand_valu_batch(int M, int prec, const CloudDesc* dcl, const int2* dwork, int nwork, int tpi,
+                                    hipStream_t st) {
+  if (nwork <= 0) return hipSuccess;
+  ProfileScope prof(kKExpandBatch, st);
+#define RFD_EXPVB(MM, PP)                                                                                    \
+  if (M == MM && prec == PP) {                                                                               \
+    hipLaunchKernelGGL((k_expand_valu_batch<MM, PP>), dim3(nwork), dim3(256), 0, st, dcl, dwork, tpi);     \
+    return hipGetLastError();                                                                                \
+  }
+  RFD_EXPVB(64, 0)
+  RFD_EXPVB(64, 1)
+  RFD_EXPVB(128, 0)
+  RFD_EXPVB(128, 1)
+  RFD_EXPVB(256, 0)
+  RFD_EXPVB(256, 1)
+#undef RFD_EXPVB
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_expand_batch(int M, int prec, int DB, const CloudDesc* dcl, const int2* dwork, int nwork, int tpi,

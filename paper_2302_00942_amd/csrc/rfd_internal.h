@@ -76,6 +76,7 @@ struct PlanDev {
   double* lvl = nullptr;      // level-1 sums of the partial reduction
   float* partials = nullptr;  // split-N partial sums
   size_t partials_cap = 0;    // in floats
+  bool external = false;      // every buffer is a piece of a caller's arena (never freed, never grown)
 };
 
 }  // namespace rfd
@@ -131,6 +132,8 @@ hipError_t launch_phi1_batch(rfd_plan_s** plans, int n, void* dev_args, hipStrea
 // without forming S (the plan's S and T are then stale: see ensure_core).
 hipError_t launch_phi1_apply(rfd_plan_s* p, int d, hipStream_t st);
 int phi1_apply_max_width();
+// Most workers the cooperative phi_1 kernel of this plan uses (its tiles per phase, at most one XCD's CUs).
+int phi1_grid_workers_max(rfd_plan_s* p);
 // Batched action form: one workgroup per cloud over Phi1Args / apply records.
 hipError_t launch_phi1_apply_batch_dev(int M, int n, const void* dev_args, const void* dev_aargs, hipStream_t st);
 void phi1_fill_apply_args(rfd_plan_s* p, int d, void* out);  // writes one apply record
@@ -229,9 +232,30 @@ SpecArgs spectrum_args(rfd_plan_s* p, int which, int64_t k, double* out);
 hipError_t launch_spectrum(rfd_plan_s* p, int which, int64_t k, double* out, hipStream_t st);
 hipError_t launch_spectrum_batch(const SpecArgs* dev_args, int n, int max_m, hipStream_t st);
 void release_spectrum_records();  // frees the batched spectrum's record buffers (spectrum.cpp)
+// Elementwise steps of the Wasserstein-barycenter iteration (k_bary.hip);
+// fields N x k row-major, rho < 0: no floor.
+constexpr int kMaxBaryInputs = 16;
+hipError_t launch_bary_init(const float* a, int64_t N, int k, float* v, float* F, unsigned long long* ctr,
+                            hipStream_t st);
+hipError_t launch_bary_ratio(const float* a, const float* mus, int64_t ldmu, int64_t N, int k, float rho,
+                             const float* K, float* F, unsigned long long* ctr, hipStream_t st);
+hipError_t launch_bary_update(const float* a, int64_t N, int k, const float* alpha, float rho, const float* K,
+                              float* v, float* F, float* mu, unsigned long long* ctr, hipStream_t st);
 // Launch-geometry tuning (autotune.cpp): knobs that change speed, never results.
 enum TuneKnob { kTuneExpandTilesPerWave = 0, kTuneBatchExpandTilesPerItem = 1, kTunePhi1Workgroups = 2,
-                kNumTuneKnobs };
+                kTuneExpandPath = 3, kNumTuneKnobs };
+// Arithmetic of the expansion out = F + A G' for fields of at most
+// kValuMaxD channels: the matrix cores or FP32 FMAs (k_expand_valu). Unlike
+// the geometry knobs this one selects different (equally valid) roundings;
+// its table entry is keyed by (m, precision, d) and read by every expansion
+// of such a field, single or batched.
+constexpr int kValuMaxD = 4;
+constexpr int kExpandMfma = 1, kExpandValu = 2;
+int expand_path(int M, int prec, int d);
+// Batched FMA-path expansion over (cloud, first tile) items of clouds whose
+// expand_path is kExpandValu.
+hipError_t launch_expand_valu_batch(int M, int prec, const CloudDesc* dcl, const int2* dwork, int nwork, int tpi,
+                                    hipStream_t st);
 int tuned(int knob, int M, int prec, int DB, int64_t N, int fallback);
 void set_tuned(int knob, int M, int prec, int DB, int64_t N, int value);
 int default_expand_tiles_per_wave(int64_t N, int prec);

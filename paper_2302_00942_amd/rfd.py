@@ -77,6 +77,13 @@ def lib() -> C.CDLL:
             "rfd_plan_check": ([vp, vp], i32),
             "rfd_plan_core": ([vp, vp, vp, vp, vp], i32),
             "rfd_plan_info": ([vp, vp, vp, vp], i32),
+            "rfd_features_sync": ([vp, vp, i64, vp], i32),
+            "rfd_plan_workspace_size": ([vp, i64, i32, vp], i32),
+            "rfd_plan_create_in": ([vp, vp, C.c_size_t, i64, i32, C.POINTER(vp)], i32),
+            "rfd_bary_create": ([vp, vp, vp, i64, i32, vp, i32, dbl, vp, C.POINTER(vp)], i32),
+            "rfd_bary_launch": ([vp, vp], i32),
+            "rfd_bary_floored": ([vp, vp, vp], i32),
+            "rfd_bary_destroy": ([vp], None),
             "rfd_plan_action": ([vp, vp, vp, vp, vp], i32),
             "rfd_plan_destroy": ([vp], None),
             "rfd_integrate_batch": ([vp, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
@@ -131,6 +138,15 @@ def make_params(m: int, eps: float, lam: float, seed: int = 0, shape="ball", pre
     return p, keep
 
 
+def workspace_size(m: int, eps: float, N_max: int, d_max: int, seed: int = 0, shape="ball", precision="fp32",
+                   sigma: float = 0.0, radius: float = 0.0) -> int:
+    """Device bytes of a plan in a caller's arena (rfd_plan_workspace_size; host only)."""
+    p, _ = make_params(m, eps, 0.0, seed, shape, precision, sigma, radius)
+    n = C.c_size_t()
+    _check(lib().rfd_plan_workspace_size(C.byref(p), int(N_max), int(d_max), C.byref(n)), "rfd_plan_workspace_size")
+    return int(n.value)
+
+
 def frequencies(m: int, eps: float, seed: int = 0, shape="ball", sigma: float = 0.0, radius: float = 0.0):
     """(omega f x 3 float32, w f float64) as the library samples them (host only)."""
     p, _ = make_params(m, eps, 0.0, seed, shape, "fp32", sigma, radius)
@@ -170,6 +186,26 @@ class Plan:
         self.m, self.eps, self.lam, self.seed = m, eps, lam, seed
         self.precision = _PREC[precision]
 
+    @classmethod
+    def in_arena(cls, m: int, eps: float, lam: float, N_max: int, d_max: int, seed: int = 0, shape="ball",
+                 precision="fp32", sigma: float = 0.0, radius: float = 0.0, omega: Optional[np.ndarray] = None):
+        """A plan whose device memory is one torch tensor (rfd_plan_create_in),
+        sized for clouds of up to N_max points and fields of up to d_max channels."""
+        import torch
+        p, keep = make_params(m, eps, lam, seed, shape, precision, sigma, radius, omega)
+        nbytes = workspace_size(m, eps, N_max, d_max, seed, shape, precision, sigma, radius)
+        arena = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = (arena.data_ptr() + 255) & ~255
+        self = cls.__new__(cls)
+        h = C.c_void_p()
+        _check(lib().rfd_plan_create_in(C.byref(p), base, nbytes, int(N_max), int(d_max), C.byref(h)),
+               "rfd_plan_create_in")
+        self._h = h
+        self._arena = arena
+        self.m, self.eps, self.lam, self.seed = m, eps, lam, seed
+        self.precision = _PREC[precision]
+        return self
+
     @property
     def handle(self) -> C.c_void_p:
         return self._h
@@ -181,11 +217,15 @@ class Plan:
         _check(lib().rfd_plan_export(self._h, om.ctypes.data, w.ctypes.data), "rfd_plan_export")
         return om, w
 
-    def features(self, X, stream=None) -> None:
+    def features(self, X, stream=None, sync: bool = False) -> None:
+        """rfd_features (async), or with sync=True rfd_features_sync: waits and
+        raises on what the device found (non-finite points or core)."""
         X = _dev_f32(X, "X", 3)
         if X.stride(0) != 3:
             raise ValueError("X must be contiguous N x 3")
-        _check(lib().rfd_features(self._h, X.data_ptr(), X.shape[0], _stream_handle(stream)), "rfd_features")
+        fn = lib().rfd_features_sync if sync else lib().rfd_features
+        _check(fn(self._h, X.data_ptr(), X.shape[0], _stream_handle(stream)),
+               "rfd_features_sync" if sync else "rfd_features")
 
     @property
     def points(self) -> int:
@@ -395,6 +435,54 @@ class Loop:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().rfd_loop_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Barycenter:
+    """Wasserstein barycenter of k distributions on a resident plan's cloud
+    (rfd_bary_*; App. D, Alg. 1). a: area weights (N float32 CUDA vector),
+    mus: N x k float32 CUDA tensor (one distribution per column), alpha: k
+    weights, floor: the safeguard factor (None: no floor). launch() runs the
+    iterations and returns mu (N float32, the tensor the object owns)."""
+
+    def __init__(self, plan: "Plan", a, mus, alpha, iterations: int, floor: Optional[float] = 1.0):
+        import torch
+        _dev_f32(mus, "mus")
+        n, k = mus.shape
+        if plan.points >= 0 and plan.points != n:
+            raise ValueError(f"mus has {n} rows; the plan's cloud has {plan.points} points")
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float32 and a.is_contiguous()
+                and a.numel() == n):
+            raise ValueError("a must be a contiguous float32 CUDA vector with one entry per point")
+        if len(alpha) != k:
+            raise ValueError("one weight per distribution")
+        self.mu = torch.empty(n, dtype=torch.float32, device=mus.device)
+        self._keep = (plan, a, mus)
+        al = (C.c_double * k)(*[float(x) for x in alpha])
+        h = C.c_void_p()
+        _check(lib().rfd_bary_create(plan.handle, a.data_ptr(), mus.data_ptr(), mus.stride(0), k, al, int(iterations),
+                                     -1.0 if floor is None else float(floor), self.mu.data_ptr(), C.byref(h)),
+               "rfd_bary_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().rfd_bary_launch(self._h, _stream_handle(stream)), "rfd_bary_launch")
+        return self.mu
+
+    def floored(self, stream=None) -> int:
+        c = C.c_int64()
+        _check(lib().rfd_bary_floored(self._h, C.byref(c), _stream_handle(stream)), "rfd_bary_floored")
+        return int(c.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().rfd_bary_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -217,3 +217,42 @@ def poisson_requests(count: int, qps: float, seed: int, lo: int = 2000, hi: int 
         out.append(dict(t=t, n=n, surface=SURFACES[int(g.integers(0, 3))], d=int(g.choice(ds)),
                         m=int(g.choice(ms)), seed=int(g.integers(0, 2**31 - 1))))
     return out
+
+
+# Mesh sizes of the paper's barycenter table (Table 2: alien, duck, land, octocat).
+BARYCENTER_SIZES = (5212, 9862, 14738, 18944)
+
+
+@dataclass
+class BaryProblem:
+    """k input distributions on a cloud for the Wasserstein-barycenter loop,
+    with the paper's settings (App. D, "Details on Hyper-parameters"):
+    eps = 0.01, lambda = 0.5, m = 30 features, k = 3, alpha = 1/3; the
+    frequency law is the truncated Gaussian sigma = 1, R = 3."""
+    X: np.ndarray        # n x 3 float32
+    a: np.ndarray        # n float32: area weights (area-uniform samples: 1/n each)
+    mus: np.ndarray      # n x k float32: distribution i in column i, a . mu_i = 1
+    eps: float = 0.01
+    lam: float = 0.5
+    m: int = 30
+    seed: int = 3
+    sigma: float = 1.0
+    radius: float = 3.0
+    alpha: tuple = (1 / 3, 1 / 3, 1 / 3)
+
+
+def barycenter_problem(n: int, surface_kind: str = "sphere", seed: int = 0, k: int = 3,
+                       width: float = 0.3, background: float = 1e-2) -> BaryProblem:
+    """Each input has its mass around a distinct centre point of the cloud (a
+    Gaussian bump of the given width in 3-D distance) over a small uniform
+    background (so every entry is positive), normalised to a . mu = 1."""
+    X = surface(surface_kind, n, seed)
+    g = _rng(seed + 1000)
+    centres = X[g.choice(n, k, replace=False)].astype(np.float64)
+    a = np.full(n, 1.0 / n)
+    cols = []
+    for c in centres:
+        b = np.exp(-np.sum((X.astype(np.float64) - c) ** 2, axis=1) / (2.0 * width * width))
+        b = b + background * b.max()
+        cols.append(b / (a @ b))
+    return BaryProblem(X=X, a=a.astype(np.float32), mus=np.stack(cols, axis=1).astype(np.float32))

@@ -170,3 +170,18 @@ def test_plan_row_check_runs_on_the_host():
     for F, out in ((T(499), T(499)), (T(500), T(499)), (T(501), T(501))):
         with pytest.raises(ValueError):
             p._rows(F, out)
+
+
+def test_workspace_size_query_is_host_only_and_monotone():
+    """rfd_plan_workspace_size needs no device: the bytes grow with the cloud
+    and the field width, and invalid sizes are refused."""
+    small = rfd.workspace_size(256, 0.02, 1000, 16)
+    assert small > 0 and small % 256 == 0
+    assert rfd.workspace_size(256, 0.02, 1_000_000, 16) > small
+    assert rfd.workspace_size(256, 0.02, 1000, 64) >= small
+    assert rfd.workspace_size(64, 0.02, 1000, 16) < small
+    # the point copy alone is 12 bytes per point
+    assert rfd.workspace_size(64, 0.1, 200_000, 3) - rfd.workspace_size(64, 0.1, 100_000, 3) >= 12 * 100_000
+    for bad in ((-1, 16), (10, -1), (10, 1025)):
+        with pytest.raises(rfd.RfdError):
+            rfd.workspace_size(64, 0.1, *bad)

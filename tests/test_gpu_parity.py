@@ -236,6 +236,22 @@ def test_nonfinite_input_is_reported(torch_cuda):
     assert st == rfd.NONFINITE
 
 
+def test_features_sync_reports_device_findings(torch_cuda):
+    """rfd_features_sync returns what the device found at the call: a NaN
+    coordinate gives RFD_ERR_NONFINITE there, a finite cloud RFD_OK."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    X = wl.sphere(700, 3)
+    plan = rfd.Plan(64, 0.1, -0.5, 0)
+    plan.features(torch.from_numpy(X).cuda(), sync=True)
+    Xb = X.copy()
+    Xb[123, 2] = np.nan
+    with pytest.raises(rfd.RfdError) as e:
+        plan.features(torch.from_numpy(Xb).cuda(), sync=True)
+    assert e.value.status == rfd.NONFINITE
+    assert plan.check() == rfd.OK  # the flag was read (and cleared) by the call
+
+
 def test_empty_and_zero_width(torch_cuda):
     torch = torch_cuda
     from paper_2302_00942_amd import rfd
