@@ -56,7 +56,7 @@ def build(verbose: bool = False) -> str:
     # native driver of the C ABI (profiling runs), linked against librfd.so
     drv = os.path.join(HERE, "rfd_run")
     cmd = [hipcc(), "-O2", "-std=c++17", f"--offload-arch={ARCH}", "-I", INCLUDE, os.path.join(CSRC, "rfd_run.cpp"),
-           "-L", HERE, "-lrfd", "-Wl,-rpath,$ORIGIN", "-o", drv + ".tmp"]
+           "-L", HERE, "-lrfd", "-ldl", "-Wl,-rpath,$ORIGIN", "-o", drv + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"driver build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -67,54 +67,43 @@ struct WgBarrier {
 // counter of their group of kBarGroup (128-byte apart lines); the last arrival
 // of a group (seen from the returned count) bumps the top counter, which every
 // workgroup polls. Counters only grow: round r waits for r * groups top
-// arrivals. The wait is bounded: on timeout the flag gets bit 2 and the
+// arrivals. Ordering comes from fences around relaxed counter operations:
+// each arrival is preceded by an agent-scope release fence; the last arrival
+// of a group takes an acquire-release fence before it bumps the top counter
+// (so the group's writes reach every poller through it); the poll is relaxed
+// and followed by one acquire fence. On gfx950 that is one L2 write-back
+// before the arrival and one invalidate after the wait. Every wave also waits
+// for its own stores before the workgroup arrives and drops its L1 lines after
+// the wait. The wait is bounded: on timeout the flag gets bit 2 and the
 // workgroup proceeds, so every wave always exits. The counters start at zero
 // (the plan zeroes them when it is created) and every launch leaves them at
 // zero: after its last wait each workgroup arrives on an exit counter (word 1),
 // and the last arrival, which knows that no workgroup of the launch reads a
-// counter again, clears them all, so no clearing kernel runs between launches.
-//
-// Visibility of the phase data. Every wave waits for its own stores to be
-// acknowledged before the workgroup arrives, and every wave drops its L1
-// lines after the wait (the L1 is write-through, so stores sit in the L2 of
-// the writer's XCD). When all workers run on one XCD they share that L2, and
-// this is all the ordering the phases need: no L2 write-back or invalidate.
-// The workers publish the XCD they run on before the first wait; the first
-// wait also takes an agent-scope release fence before the arrival and an
-// acquire fence after the wait (one L2 write-back and one invalidate), after
-// which every worker compares the published ids. Only if they all agree do
-// the later waits drop the two fences; otherwise every wait keeps them.
+// counter again, clears them all, so no clearing kernel runs between launches
+// on a stream.
 constexpr int kBarGroup = 16;
 constexpr int kBarStride = 32;        // unsigned words between counters (128 bytes)
 constexpr int kBarWords = kBarStride * (1 + 256 / kBarGroup);
-constexpr int kXccWords = kBarWords;  // then one word per worker: the XCD it runs on
-static_assert(kXccWords + 256 <= kBarrierWords, "barrier counters exceed the plan's buffer");
-// XCC_ID hardware register, bits [15:0]
-constexpr int kXccIdReg = 20 | (0 << 6) | ((16 - 1) << 11);
+static_assert(kBarWords <= kBarrierWords, "barrier counters exceed the plan's buffer");
 
 struct GridBarrier {
   unsigned* ctr;
   unsigned nblocks;
-  unsigned worker;
   unsigned round;
   int* flag;
-  bool local;  // thread 0 only: every worker is on one XCD
-  __device__ __forceinline__ void publish_xcd() {
-    if (threadIdx.x == 0) ctr[kXccWords + worker] = (unsigned)__builtin_amdgcn_s_getreg(kXccIdReg);
-  }
   __device__ __forceinline__ void sync() {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are in L2
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are acknowledged
     __syncthreads();
     if (threadIdx.x == 0) {
       ++round;
-      const unsigned g = worker / kBarGroup;
+      const unsigned g = blockIdx.x / kBarGroup;
       const unsigned groups = (nblocks + kBarGroup - 1) / kBarGroup;
       const unsigned gsz = (g + 1 < groups) ? kBarGroup : nblocks - g * kBarGroup;
-      if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned old =
           __hip_atomic_fetch_add(ctr + kBarStride * (1 + g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (old + 1 == round * gsz) {
-        if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
         __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       const unsigned target = round * groups;
@@ -126,14 +115,7 @@ struct GridBarrier {
           break;
         }
       }
-      if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      if (round == 1) {
-        const unsigned mine = ctr[kXccWords + worker];
-        bool same = true;
-        for (unsigned w = 0; w < nblocks; ++w)
-          same = same && __hip_atomic_load(ctr + kXccWords + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == mine;
-        local = same;
-      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     asm volatile("buffer_inv sc0" ::: "memory");  // drop this CU's L1 lines
@@ -775,32 +757,21 @@ __global__ __launch_bounds__(256) void k_phi1_wg(const Phi1Args* __restrict__ ar
   phi1_body<M, wg_kb<M>(), wg_all<M>()>(a, 0, 1, lds, bar);
 }
 
-// The cooperative kernels are launched with kXcds workgroups per worker;
-// workgroups are dealt to the XCDs in turn, so every kXcds-th one (the
-// workers) runs on one XCD and the others leave at once. The barrier checks
-// that placement (see GridBarrier) and keeps its fences if it does not hold.
-constexpr int kXcds = 8;
-constexpr int kMaxWorkers = 32;  // CUs of one XCD: one worker each (its LDS allows no second)
+constexpr int kMaxWorkers = 256;  // one workgroup per CU (a workgroup's LDS allows no second)
 
 template <int M>
 __global__ __launch_bounds__(256) void k_phi1_grid(Phi1Args a) {
   extern __shared__ double lds[];
-  if (blockIdx.x % kXcds != 0) return;
-  const unsigned worker = blockIdx.x / kXcds, nw = gridDim.x / kXcds;
-  GridBarrier bar{a.barrier, nw, worker, 0u, a.flag, false};
-  bar.publish_xcd();
-  phi1_body<M, (M < kGridKB ? M : kGridKB), true>(a, (int)worker, (int)nw, lds, bar);
+  GridBarrier bar{a.barrier, gridDim.x, 0u, a.flag};
+  phi1_body<M, (M < kGridKB ? M : kGridKB), true>(a, (int)blockIdx.x, (int)gridDim.x, lds, bar);
   bar.finish();
 }
 
 template <int M>
 __global__ __launch_bounds__(256) void k_phi1_apply_grid(Phi1Args a, ApplyArgs ap) {
   extern __shared__ double lds[];
-  if (blockIdx.x % kXcds != 0) return;
-  const unsigned worker = blockIdx.x / kXcds, nw = gridDim.x / kXcds;
-  GridBarrier bar{a.barrier, nw, worker, 0u, a.flag, false};
-  bar.publish_xcd();
-  apply_body<M, (M < kGridKB ? M : kGridKB), true>(a, ap, (int)worker, (int)nw, lds, bar);
+  GridBarrier bar{a.barrier, gridDim.x, 0u, a.flag};
+  apply_body<M, (M < kGridKB ? M : kGridKB), true>(a, ap, (int)blockIdx.x, (int)gridDim.x, lds, bar);
   bar.finish();
 }
 
@@ -842,10 +813,9 @@ static hipError_t launch_phi1_m(Phi1Args& a, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)k_phi1_grid<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   constexpr int nb = M / 32;
-  // workers: every phase has full_tiles(nb, sym) tiles (pairs of products);
-  // fewer workers make the barrier cheaper and give each more tiles (the count
-  // never changes results: each tile is computed the same way). All of them
-  // run on one XCD, at most one per CU there (kMaxWorkers).
+  // workgroups: every phase has full_tiles(nb, sym) tiles (pairs of products);
+  // fewer workgroups make the barrier cheaper and give each more tiles (the
+  // count never changes results: each tile is computed the same way)
   const int tiles = full_tiles(nb, a.sym != 0);
   int nw = tuned(kTunePhi1Workgroups, M, 0, 1, 0, tiles < kMaxWorkers ? tiles : kMaxWorkers);
   if (nw < 1) nw = 1;
@@ -853,8 +823,7 @@ static hipError_t launch_phi1_m(Phi1Args& a, hipStream_t st) {
   if (nw > kMaxWorkers) nw = kMaxWorkers;
   void* kargs[] = {&a};
   ProfileScope prof(kKPhi1, st);
-  return hipLaunchCooperativeKernel((const void*)k_phi1_grid<M>, dim3(kXcds * nw), dim3(256), kargs, (unsigned)lds,
-                                    st);
+  return hipLaunchCooperativeKernel((const void*)k_phi1_grid<M>, dim3(nw), dim3(256), kargs, (unsigned)lds, st);
 }
 
 hipError_t launch_phi1(rfd_plan_s* p, hipStream_t st) {
@@ -879,8 +848,8 @@ static hipError_t launch_apply_m(Phi1Args& a, ApplyArgs& ap, hipStream_t st) {
   const int nw = units < kMaxWorkers ? units : kMaxWorkers;
   void* kargs[] = {&a, &ap};
   ProfileScope prof(kKPhi1Apply, st);
-  return hipLaunchCooperativeKernel((const void*)k_phi1_apply_grid<M>, dim3(kXcds * nw), dim3(256), kargs,
-                                    (unsigned)lds, st);
+  return hipLaunchCooperativeKernel((const void*)k_phi1_apply_grid<M>, dim3(nw), dim3(256), kargs, (unsigned)lds,
+                                    st);
 }
 
 hipError_t launch_phi1_apply(rfd_plan_s* p, int d, hipStream_t st) {

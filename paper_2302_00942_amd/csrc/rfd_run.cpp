@@ -276,11 +276,18 @@ static int batch_mode(const std::string& dir, int steps, int prec) {
 }
 
 // Where the library and the HIP runtime are mapped, so that frames of a
-// crash report can be attributed to one of them.
+// crash report can be attributed to one of them (the symbols are looked up in
+// the loaded libraries, not through this program's own call stubs).
 static void print_load_addresses() {
-  Dl_info a{}, b{};
-  if (dladdr((const void*)&rfd_plan_create, &a) && dladdr((const void*)&hipGetDeviceCount, &b))
-    fprintf(stderr, "rfd_run: %s at %p, %s at %p\n", a.dli_fname, a.dli_fbase, b.dli_fname, b.dli_fbase);
+  const char* libs[2][2] = {{"librfd.so", "rfd_plan_create"}, {"libamdhip64.so", "hipGetDeviceCount"}};
+  for (auto& l : libs) {
+    void* h = dlopen(l[0], RTLD_LAZY | RTLD_NOLOAD);
+    void* sym = h ? dlsym(h, l[1]) : nullptr;
+    Dl_info info{};
+    if (sym && dladdr(sym, &info))
+      fprintf(stderr, "rfd_run: %s mapped at %p\n", info.dli_fname, info.dli_fbase);
+    if (h) dlclose(h);
+  }
 }
 
 static int run(int argc, char** argv);
