@@ -174,6 +174,28 @@ rfd_status rfd_integrate_oneshot(rfd_plan_t plan, const float* X_dev, int64_t N,
                                  const float* F_dev, int64_t ldF, int32_t d,
                                  float* out_dev, int64_t ldO, rfd_stream_t stream);
 
+/* rfd_integrate_oneshot for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it makes no hipMalloc, hipFree or other allocating call. The
+ * buffers its kernels need besides X, F and out (split-N partials, the core
+ * and field block, the phi_1 workspace, G', barrier counters, a status flag)
+ * live in one fixed 20 MiB device array of the library, which every device it
+ * runs on holds until the process ends. Limits: N <= 65536 points and
+ * d <= 32 channels for m > 128 (d <= 64 for m <= 128), so the whole field
+ * goes through the one fused pass; larger requests get RFD_ERR_OUT_OF_BUDGET
+ * before any launch. The kernels and the split of the cloud are those of
+ * rfd_integrate_oneshot, so out is bitwise the same. Points are read from
+ * X_dev in both passes (X must stay valid until the stream completes) and the
+ * plan's resident cloud, core and buffers are left as they were; device
+ * findings (non-finite values) are added to the plan's flag for
+ * rfd_plan_check. All calls on one GPU share the array: calls that overlap on
+ * one GPU (two streams, two threads) race and give wrong results; serialise
+ * them. The current device must be the plan's (else RFD_ERR_INVALID_ARG).
+ * Other errors: those of rfd_integrate_oneshot. */
+rfd_status rfd_integrate_oneshot_noalloc(rfd_plan_t plan, const float* X_dev, int64_t N,
+                                         const float* F_dev, int64_t ldF, int32_t d,
+                                         float* out_dev, int64_t ldO, rfd_stream_t stream);
+
 /* Waits for `stream` and reports what the device found for this plan since
  * the last check: RFD_OK or RFD_ERR_NONFINITE (clears the flag). */
 rfd_status rfd_plan_check(rfd_plan_t plan, rfd_stream_t stream);

@@ -24,7 +24,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # the host sampler must evaluate float64 expressions exactly as written
 HOST_EXTRA = {"host_plan.cpp": ["-ffp-contract=off"]}
-SOURCES = ["k_stream.hip", "k_phi1.hip", "host_plan.cpp", "batch_server.cpp", "loop.cpp", "wide.cpp", "gw.cpp", "k_gw.hip", "spectrum.cpp", "k_spectrum.hip", "server.cpp", "autotune.cpp", "profile.cpp", "bary.cpp", "k_bary.hip"]
+SOURCES = ["k_stream.hip", "k_phi1.hip", "host_plan.cpp", "batch_server.cpp", "loop.cpp", "wide.cpp", "gw.cpp", "k_gw.hip", "spectrum.cpp", "k_spectrum.hip", "server.cpp", "autotune.cpp", "profile.cpp", "noalloc.hip", "bary.cpp", "k_bary.hip"]
 
 
 def hipcc() -> str:

@@ -84,6 +84,7 @@ def lib() -> C.CDLL:
             "rfd_bary_launch": ([vp, vp], i32),
             "rfd_bary_floored": ([vp, vp, vp], i32),
             "rfd_bary_destroy": ([vp], None),
+            "rfd_integrate_oneshot_noalloc": ([vp, vp, i64, vp, i64, i32, vp, i64, vp], i32),
             "rfd_plan_action": ([vp, vp, vp, vp, vp], i32),
             "rfd_plan_destroy": ([vp], None),
             "rfd_integrate_batch": ([vp, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
@@ -288,6 +289,26 @@ class Plan:
         _check(lib().rfd_integrate_oneshot(self._h, X.data_ptr(), X.shape[0], F.data_ptr(), F.stride(0), F.shape[1],
                                            out.data_ptr(), out.stride(0), _stream_handle(stream)),
                "rfd_integrate_oneshot")
+        return out
+
+    def oneshot_noalloc(self, X, F, out=None, stream=None):
+        """rfd_integrate_oneshot_noalloc: the one-shot integration with no device
+        allocation by the library (its buffers live in a fixed device array)."""
+        import torch
+        X = _dev_f32(X, "X", 3)
+        if X.stride(0) != 3:
+            raise ValueError("X must be contiguous N x 3")
+        F = _dev_f32(F, "F")
+        if F.shape[0] != X.shape[0]:
+            raise ValueError("X and F must have the same number of rows")
+        if out is None:
+            out = torch.empty_like(F)
+        out = _dev_f32(out, "out", F.shape[1])
+        if out.shape[0] != F.shape[0]:
+            raise ValueError("out must have as many rows as F")
+        _check(lib().rfd_integrate_oneshot_noalloc(self._h, X.data_ptr(), X.shape[0], F.data_ptr(), F.stride(0),
+                                                   F.shape[1], out.data_ptr(), out.stride(0), _stream_handle(stream)),
+               "rfd_integrate_oneshot_noalloc")
         return out
 
     def autotune(self, F, out, reps: int = 10, stream=None):
