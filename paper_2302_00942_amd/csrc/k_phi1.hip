@@ -469,7 +469,7 @@ struct TaylorWs {
 // workgroup per tile, the Y4 row panel shared by the two products).
 template <int m, int KB, bool ALL, int J, class BAR>
 __device__ __forceinline__ void horner_phase(const TaylorWs& w, int worker, int nw, double* lds, BAR& bar) {
-  constexpr int nb = m / 32, nt = nb * nb;
+  constexpr int nb = m / 32;
   constexpr int src = (J + 1) & 1, dst = J & 1;
   {
     const PhaseTiles pt(worker, nw, nb, 0, w.sym);
@@ -488,7 +488,7 @@ __device__ __forceinline__ void horner_phase(const TaylorWs& w, int worker, int 
 
 template <int m, int KB, bool ALL, class BAR>
 __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw, double* lds, BAR& bar) {
-  constexpr int nb = m / 32, nt = nb * nb;
+  constexpr int nb = m / 32;
   const size_t mm = (size_t)m * m;
   double* X0 = a.ws;        // lambda M
   double* Y2 = X0 + mm;
@@ -597,7 +597,7 @@ template <int m, int KB, bool ALL, int J, class BAR>
 __device__ __forceinline__ void apply_horner(const TaylorWs& w, double* const (&E)[2], const double* V,
                                              const double* U1, const double* U2, const double* U3,
                                              double* const (&W)[2], int worker, int nw, double* lds, BAR& bar) {
-  constexpr int nb = m / 32, nt = nb * nb, TW = kThinWidth;
+  constexpr int nb = m / 32, TW = kThinWidth;
   constexpr int src = (J + 1) & 1, dst = J & 1;
   {
     const PhaseTiles pt(worker, nw, nb, nb, w.sym);
@@ -621,7 +621,7 @@ __device__ __forceinline__ void apply_horner(const TaylorWs& w, double* const (&
 template <int m, int KB, bool ALL, class BAR>
 __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& ap, int worker, int nw, double* lds,
                                            BAR& bar) {
-  constexpr int nb = m / 32, nt = nb * nb, TW = kThinWidth;
+  constexpr int nb = m / 32, TW = kThinWidth;
   const size_t mm = (size_t)m * m, mt = (size_t)m * TW;
   double* X0 = a.ws;
   double* Y2 = X0 + mm;
@@ -739,18 +739,20 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
 
 // K blocks: the cooperative kernel (one workgroup per CU) issues all of a
 // tile's loads at once and stages 128-wide blocks, one memory round trip per
-// tile. The one-workgroup-per-cloud kernel takes a whole tile as one block
-// when m <= 128 and streams its tiles (the next tile's loads fly during the
-// current tile's products); at m = 256 it pipelines 32-wide blocks, which
-// keeps its LDS small.
+// tile. The one-workgroup-per-cloud kernels pipeline 32-wide blocks through
+// two LDS buffers (50 KB) and are held to 256 registers per lane, so two
+// clouds share a CU (two waves per SIMD hide each other's LDS and memory
+// waits); a whole tile as one block would take 101 KB of LDS and 512
+// registers, one cloud per CU. The k order of every MFMA chain is the same
+// for any block width, so both kernels give the same bits.
 constexpr int kWgKB = 32, kGridKB = 128;
 template <int M>
-constexpr int wg_kb() { return M <= kGridKB ? M : kWgKB; }
+constexpr int wg_kb() { return kWgKB; }
 template <int M>
-constexpr bool wg_all() { return M <= kGridKB; }
+constexpr bool wg_all() { return false; }
 
 template <int M>
-__global__ __launch_bounds__(256) void k_phi1_wg(const Phi1Args* __restrict__ args) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_phi1_wg(const Phi1Args* __restrict__ args) {
   extern __shared__ double lds[];
   const Phi1Args a = args[blockIdx.x];
   WgBarrier bar;
@@ -776,7 +778,7 @@ __global__ __launch_bounds__(256) void k_phi1_apply_grid(Phi1Args a, ApplyArgs a
 }
 
 template <int M>
-__global__ __launch_bounds__(256) void k_phi1_apply_wg(const Phi1Args* __restrict__ args,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_phi1_apply_wg(const Phi1Args* __restrict__ args,
                                                       const ApplyArgs* __restrict__ aargs) {
   extern __shared__ double lds[];
   const Phi1Args a = args[blockIdx.x];
