@@ -157,11 +157,14 @@ __device__ __forceinline__ void gst(double* p, double v) { *(gdouble*)p = v; }
 // front (one memory round trip per tile) and staged through one LDS buffer;
 // otherwise two LDS buffers alternate and the next block's panels are loaded
 // while the current block is multiplied. Each wave computes one 16 x 16
-// quadrant of each tile with four MFMA chains over the k steps (k = 4c mod 16
-// in chain c, increasing k within a chain), summed in a fixed order. The NS
-// side matrices the epilogue reads elementwise are loaded with the panels
-// (ALL) or after the products; the epilogue gets (i, j, c1, c2, side values at (i, j)) for the four
-// values each lane holds.
+// quadrant of each tile as one MFMA chain over the k steps in increasing
+// order (k = 4 t .. 4 t + 3 in step t, lane (r, q) holding k = 4 t + q), then
+// scales it by alpha: every kernel that forms these products uses this chain,
+// so they give the same bits (dependent FP64 MFMAs issue back to back on
+// gfx950: splitting the chain bought no speed). The NS side matrices the
+// epilogue reads elementwise are loaded with the panels (ALL) or after the
+// products; the epilogue gets (i, j, c1, c2, side values at (i, j)) for the
+// four values each lane holds.
 constexpr int kShareA = 0, kShareB = 1;
 // doubles per LDS panel: A panels are 32 x KB (row pitch KB + 1), B panels
 // KB x 32 (row pitch 33)
@@ -252,42 +255,35 @@ __device__ __forceinline__ void gemm_range(int first, int end, int step, MAP map
 #pragma unroll
       for (int q = 0; q < NS; ++q) side[r].v[q] = gld(sp[q] + out_index(ti, tj, r));
   };
-  const auto multiply = [&](const double* buf, f64x4 (&acc)[NP][4]) {
+  const auto multiply = [&](const double* buf, f64x4 (&acc)[NP]) {
     const int ao = (qi * 16 + (l & 15)) * AP + (l >> 4);
     const int bo = (l >> 4) * 33 + qj * 16 + (l & 15);
 #pragma unroll
-    for (int s = 0; s < KB / 4; s += 4) {
+    for (int t = 0; t < KB / 4; ++t) {
+      const int k = 4 * t;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int k = 4 * (s + c);
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          const int pa = (NA == 2) ? p : 0, pb = (NBP == 2) ? p : 0;
-          acc[p][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(buf[pa * PD + ao + k], buf[(NA + pb) * PD + bo + k * 33],
-                                                           acc[p][c], 0, 0, 0);
-        }
+      for (int p = 0; p < NP; ++p) {
+        const int pa = (NA == 2) ? p : 0, pb = (NBP == 2) ? p : 0;
+        acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(buf[pa * PD + ao + k], buf[(NA + pb) * PD + bo + k * 33], acc[p],
+                                                      0, 0, 0);
       }
     }
   };
-  const auto zero = [&](f64x4 (&acc)[NP][4]) {
+  const auto zero = [&](f64x4 (&acc)[NP]) {
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[p][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int p = 0; p < NP; ++p) acc[p] = f64x4{0.0, 0.0, 0.0, 0.0};
   };
   // f64 16x16x4 output layout: register r holds row 4 r + l/16, column l%16
   // an off-diagonal tile of a symmetric product is stored at (i, j) and (j, i):
   // the side matrices the epilogue reads are then symmetric too
-  const auto epilogue = [&](int i0, int j0, const f64x4 (&acc)[NP][4], const Side<NS> (&side)[4]) {
+  const auto epilogue = [&](int i0, int j0, const f64x4 (&acc)[NP], const Side<NS> (&side)[4]) {
     const bool mir = map.mirror(i0, j0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = i0 * 32 + qi * 16 + 4 * r + (l >> 4);
       const int j = j0 * 32 + qj * 16 + (l & 15);
-      const double v1 = alpha1 * ((acc[0][0][r] + acc[0][1][r]) + (acc[0][2][r] + acc[0][3][r]));
-      const double v2 =
-          NP == 2 ? alpha2 * ((acc[NP - 1][0][r] + acc[NP - 1][1][r]) + (acc[NP - 1][2][r] + acc[NP - 1][3][r]))
-                  : 0.0;
+      const double v1 = alpha1 * acc[0][r];
+      const double v2 = NP == 2 ? alpha2 * acc[NP - 1][r] : 0.0;
       epi(i, j, v1, v2, side[r]);
       if (mir) epi(j, i, v1, v2, side[r]);
     }
@@ -310,7 +306,7 @@ __device__ __forceinline__ void gemm_range(int first, int end, int step, MAP map
         load_side(side);
       }
       __syncthreads();
-      f64x4 acc[NP][4];
+      f64x4 acc[NP];
       zero(acc);
       multiply(lds, acc);
       epilogue(ci, cj, acc, cur);
@@ -319,7 +315,7 @@ __device__ __forceinline__ void gemm_range(int first, int end, int step, MAP map
     for (int idx = first; idx < end; idx += step) {
       map(idx, ti, tj);
       Side<NS> side[4];
-      f64x4 acc[NP][4];
+      f64x4 acc[NP];
       zero(acc);
       if constexpr (ALL) {
 #pragma unroll
@@ -377,6 +373,8 @@ struct FullTileMap {
     tj = i + t;
   }
   __device__ bool mirror(int ti, int tj) const { return sym && ti != tj; }
+  __device__ bool symmetric() const { return sym; }
+  static constexpr bool kThin = false;
 };
 struct ThinTileMap {
   int nt;
@@ -385,6 +383,8 @@ struct ThinTileMap {
     tj = 0;
   }
   __device__ bool mirror(int, int) const { return false; }
+  __device__ bool symmetric() const { return false; }
+  static constexpr bool kThin = true;
 };
 __host__ __device__ constexpr int full_tiles(int nb, bool sym) { return sym ? nb * (nb + 1) / 2 : nb * nb; }
 struct PhaseTiles {
@@ -399,6 +399,298 @@ struct PhaseTiles {
   }
 };
 
+// One product group of a phase for the streaming gemm and gemm_pair: the
+// tiles first .. end - 1 (by step) of `map`, the B operands (B2 for the
+// second product when NP = 2), the scales, the epilogue and its side matrices.
+template <int NP_, int NS_, int LDB_, int LDC_, class MAP, class EPI>
+struct Part {
+  static constexpr int NP = NP_, NS = NS_, LDB = LDB_, LDC = LDC_;
+  int first, end, step;
+  MAP map;
+  const double* B1;
+  const double* B2;
+  double alpha1, alpha2;
+  EPI epi;
+  const double* S[4];
+};
+template <int NP, int NS, int LDB, int LDC, class MAP, class EPI>
+__device__ __forceinline__ Part<NP, NS, LDB, LDC, MAP, EPI> part(int first, int end, int step, MAP map,
+                                                                 const double* B1, const double* B2, double alpha1,
+                                                                 double alpha2, EPI epi, const double* S0 = nullptr,
+                                                                 const double* S1 = nullptr,
+                                                                 const double* S2 = nullptr,
+                                                                 const double* S3 = nullptr) {
+  return Part<NP, NS, LDB, LDC, MAP, EPI>{first, end, step, map, B1, B2, alpha1, alpha2, epi, {S0, S1, S2, S3}};
+}
+// No thin part.
+struct NoThinEpi {
+  __device__ void operator()(int, int, double, double, const Side<0>&) const {}
+};
+using NoPart = Part<1, 0, kThinWidth, kThinWidth, ThinTileMap, NoThinEpi>;
+
+// Register-resident output for the one-workgroup-per-cloud kernels (m <=
+// 128). A phase's full product group (the tiles of a FullTileMap: nb x nb
+// tiles of 32 x 32, the upper block triangle when symmetric) and, optionally,
+// its thin group (nb x 1 tiles of a ThinTileMap, B of width kThinWidth, the
+// same A and the same number of products) are formed in one sweep over K.
+// Wave w computes quadrant (w / 2, w % 2) of every tile, as in gemm_range, and
+// keeps them all in registers (one 16 x 16 MFMA accumulator per tile and
+// product) while K streams through LDS in slabs of 16 (four k steps),
+// double-buffered, the next slab's loads in flight during the current slab's
+// products; per k step a wave reads one A fragment per tile row and one B
+// fragment per tile column. Each quadrant is one MFMA chain over the k steps
+// in increasing order, scaled by alpha at the end: the arithmetic of
+// gemm_range, so the results are its bits. A is read once per product and
+// the B operands once per pass (two passes of half the tile rows for two
+// products), against a 32-row and a 32-column panel per tile. With SHARE ==
+// kShareB (no thin group) the two products have their own A (A1, A2) and
+// one B.
+constexpr int kStreamPA = 18;  // A slab row pitch (rows x 16 slab): conflict-free fragment reads
+constexpr int stream_pb(int ldb) { return ldb + 16; }  // B slab row pitch (16 x ldb slab)
+constexpr int stream_rows(int m, int np) { return np == 1 ? m : m / 2; }  // A rows per pass
+constexpr int stream_buf_doubles(int m, int na, int nbp, int ldb, int np, int nthin) {
+  return na * stream_rows(m, np) * kStreamPA + nbp * 16 * stream_pb(ldb) + nthin * 16 * stream_pb(kThinWidth);
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// LDS doubles of the streaming gemm over every phase shape (two buffers)
+constexpr int stream_lds_doubles(int m) {
+  return 2 * cmax(cmax(stream_buf_doubles(m, 1, 1, m, 1, 1), stream_buf_doubles(m, 1, 2, m, 2, 2)),
+                  stream_buf_doubles(m, 2, 1, m, 2, 0));
+}
+
+template <int m, int SHARE, class FP, class TP>
+__device__ __attribute__((noinline)) void gemm_stream(const double* __restrict__ A1, const double* __restrict__ A2,
+                                                     FP f, TP t, bool do_full, double* lds) {
+  constexpr bool TH = !std::is_same<TP, NoPart>::value;
+  constexpr int NP = FP::NP;
+  static_assert(!TH || (TP::NP == NP && SHARE == kShareA), "a thin group shares A and the product count");
+  constexpr int NA = (NP == 2 && SHARE == kShareB) ? 2 : 1;
+  constexpr int NBP = (NP == 2 && SHARE == kShareA) ? 2 : 1;
+  constexpr int NT = TH ? NBP : 0;            // thin B slabs
+  constexpr int NB = m / 32;                  // tile rows (and full tile columns)
+  constexpr int R = stream_rows(m, NP) / 32;  // tile rows per pass
+  constexpr int LDB = FP::LDB, TW = kThinWidth;
+  constexpr int PA = kStreamPA, PB = stream_pb(LDB), PT = stream_pb(TW);
+  constexpr int ASL = 32 * R * PA, BSL = 16 * PB, TSL = 16 * PT;  // slab sizes (doubles)
+  constexpr int BUF = NA * ASL + NBP * BSL + NT * TSL;
+  constexpr int NKB = m / 16;              // slabs
+  constexpr int AQ = 32 * R * 8 / 256;     // double2 per thread per A slab
+  constexpr int BH = LDB / 2, TH2 = TW / 2;  // double2 per B slab row
+  constexpr int BQ = 16 * BH / 256;        // double2 per thread per B slab
+  constexpr int TQ = 16 * TH2 / 256;       // double2 per thread per thin B slab
+  static_assert(AQ >= 1 && BQ >= 1 && TQ >= 1 && 2 * BUF <= stream_lds_doubles(m), "slab shape");
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, qi = w >> 1, qj = w & 1;
+  const bool sym = f.map.symmetric();
+  const double* Ag[2] = {A1, A2};
+  const double* Bg[2] = {f.B1, f.B2};
+  const double* Tg[2] = {t.B1, t.B2};
+  for (int r0 = 0; r0 < NB; r0 += R) {
+    double2 ra[NA][AQ], rb[NBP][BQ], rt[NT > 0 ? NT : 1][TQ];
+    // A slab element e = tid + 256 q: row e / 8 of the pass, double2 column
+    // e % 8; B slab element e: row e / BH, double2 column e % BH
+    const auto load = [&](int kb) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) {
+          const int e = tid + 256 * q, r = e >> 3, c2 = e & 7;
+          ra[a][q] = gld2(Ag[a] + (size_t)(r0 * 32 + r) * m + kb * 16 + 2 * c2);
+        }
+      if (do_full) {
+#pragma unroll
+        for (int b = 0; b < NBP; ++b)
+#pragma unroll
+          for (int q = 0; q < BQ; ++q) {
+            const int e = tid + 256 * q, r = e / BH, c2 = e % BH;
+            rb[b][q] = gld2(Bg[b] + (size_t)(kb * 16 + r) * LDB + 2 * c2);
+          }
+      }
+#pragma unroll
+      for (int b = 0; b < NT; ++b)
+#pragma unroll
+        for (int q = 0; q < TQ; ++q) {
+          const int e = tid + 256 * q, r = e / TH2, c2 = e % TH2;
+          rt[b][q] = gld2(Tg[b] + (size_t)(kb * 16 + r) * TW + 2 * c2);
+        }
+    };
+    const auto store = [&](double* buf) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) {
+          const int e = tid + 256 * q, r = e >> 3, c2 = e & 7;
+          *(double2*)(buf + a * ASL + r * PA + 2 * c2) = ra[a][q];
+        }
+      if (do_full) {
+#pragma unroll
+        for (int b = 0; b < NBP; ++b)
+#pragma unroll
+          for (int q = 0; q < BQ; ++q) {
+            const int e = tid + 256 * q, r = e / BH, c2 = e % BH;
+            *(double2*)(buf + NA * ASL + b * BSL + r * PB + 2 * c2) = rb[b][q];
+          }
+      }
+#pragma unroll
+      for (int b = 0; b < NT; ++b)
+#pragma unroll
+        for (int q = 0; q < TQ; ++q) {
+          const int e = tid + 256 * q, r = e / TH2, c2 = e % TH2;
+          *(double2*)(buf + NA * ASL + NBP * BSL + b * TSL + r * PT + 2 * c2) = rt[b][q];
+        }
+    };
+    f64x4 acc[R][NB][NP], act[R][NP];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j][p] = f64x4{0.0, 0.0, 0.0, 0.0};
+        act[i][p] = f64x4{0.0, 0.0, 0.0, 0.0};
+      }
+    __syncthreads();  // the buffers' previous readers are done
+    load(0);
+    store(lds);
+    __syncthreads();
+    const int ao = (qi * 16 + (l & 15)) * PA + (l >> 4);
+    const int bo = (l >> 4) * PB + qj * 16 + (l & 15);
+    const int to = (l >> 4) * PT + qj * 16 + (l & 15);
+#pragma unroll 1
+    for (int kb = 0; kb < NKB; ++kb) {
+      if (kb + 1 < NKB) load(kb + 1);  // in flight during this slab's products
+      const double* buf = lds + (kb & 1) * BUF;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {  // the slab's four k steps, in order
+        double af[NA][R];
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+          for (int i = 0; i < R; ++i) af[a][i] = buf[a * ASL + ao + i * 32 * PA + 4 * c];
+        if (do_full) {
+          double bf[NBP][NB];
+#pragma unroll
+          for (int b = 0; b < NBP; ++b)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) bf[b][j] = buf[NA * ASL + b * BSL + bo + 4 * c * PB + j * 32];
+#pragma unroll
+          for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+              if (!sym || r0 + i <= j) {
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                  acc[i][j][p] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[NA == 2 ? p : 0][i],
+                                                                      bf[NBP == 2 ? p : 0][j], acc[i][j][p], 0, 0, 0);
+              }
+        }
+        if constexpr (TH) {
+          double bt[NT];
+#pragma unroll
+          for (int b = 0; b < NT; ++b) bt[b] = buf[NA * ASL + NBP * BSL + b * TSL + to + 4 * c * PT];
+#pragma unroll
+          for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+              act[i][p] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[0][i], bt[NT == 2 ? p : 0], act[i][p], 0, 0, 0);
+        }
+      }
+      if (kb + 1 < NKB) store(lds + ((kb + 1) & 1) * BUF);
+      __syncthreads();
+    }
+    // Epilogues, one tile row at a time: the side values of a whole row are
+    // loaded together (with one product, the next row's while this row is
+    // stored), since the epilogue's stores keep later loads from moving above
+    // them. f64 16x16x4 output layout: register r holds row 4 r + l/16,
+    // column l%16.
+    if (do_full) {
+      constexpr int NS = FP::NS, LDC = FP::LDC;
+      constexpr int SB = NP == 1 ? 2 : 1;  // side buffers
+      Side<NS> sd[SB][NB][4];
+      const auto load_row = [&](int i, Side<NS> (&dst)[NB][4]) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (!(sym && r0 + i > j)) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int ii = (r0 + i) * 32 + qi * 16 + 4 * r + (l >> 4);
+              const int jj = j * 32 + qj * 16 + (l & 15);
+#pragma unroll
+              for (int u = 0; u < NS; ++u) dst[j][r].v[u] = gld(f.S[u] + (size_t)ii * LDC + jj);
+            }
+          }
+      };
+      if constexpr (NS > 0 && SB == 2) load_row(0, sd[0]);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        if constexpr (NS > 0 && SB == 2) {
+          if (i + 1 < R) load_row(i + 1, sd[(i + 1) & 1]);
+        } else if constexpr (NS > 0) {
+          load_row(i, sd[0]);
+        }
+        const int ti = r0 + i;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          if (sym && ti > j) continue;
+          const bool mir = sym && ti != j;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int ii = ti * 32 + qi * 16 + 4 * r + (l >> 4);
+            const int jj = j * 32 + qj * 16 + (l & 15);
+            const double v1 = f.alpha1 * acc[i][j][0][r];
+            const double v2 = NP == 2 ? f.alpha2 * acc[i][j][NP - 1][r] : 0.0;
+            f.epi(ii, jj, v1, v2, sd[i % SB][j][r]);
+            if (mir) f.epi(jj, ii, v1, v2, sd[i % SB][j][r]);
+          }
+        }
+      }
+    }
+    if constexpr (TH) {
+      constexpr int NS = TP::NS;
+      Side<NS> sd[R][4];
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ii = (r0 + i) * 32 + qi * 16 + 4 * r + (l >> 4);
+          const int jj = qj * 16 + (l & 15);
+#pragma unroll
+          for (int u = 0; u < NS; ++u) sd[i][r].v[u] = gld(t.S[u] + (size_t)ii * TW + jj);
+        }
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ii = (r0 + i) * 32 + qi * 16 + 4 * r + (l >> 4);
+          const int jj = qj * 16 + (l & 15);
+          const double v1 = t.alpha1 * act[i][0][r];
+          const double v2 = NP == 2 ? t.alpha2 * act[i][NP - 1][r] : 0.0;
+          t.epi(ii, jj, v1, v2, sd[i][r]);
+        }
+    }
+  }
+}
+
+// A phase's full product group and thin group with one A (A1, and A2 for the
+// second full product with SHARE == kShareB): one streaming sweep for the
+// per-cloud kernels (KB = 0), two gemm_range calls otherwise. The full group
+// is skipped when do_full is false.
+template <int m, int KB, bool ALL, int SHARE, class FP, class TP>
+__device__ __forceinline__ void gemm_pair(const double* A1, const double* A2, const FP& f, const TP& t, bool do_full,
+                                          double* lds) {
+  constexpr bool TH = !std::is_same<TP, NoPart>::value;
+  if constexpr (KB == 0) {
+    gemm_stream<m, SHARE>(A1, A2, f, t, do_full, lds);
+  } else {
+    if (do_full)
+      gemm_range<m, KB, ALL, FP::NP, SHARE, FP::NS, FP::LDB, FP::LDC>(f.first, f.end, f.step, f.map, A1, f.B1,
+                                                                      A2, f.B2, f.alpha1, f.alpha2, lds, f.epi,
+                                                                      f.S[0], f.S[1], f.S[2], f.S[3]);
+    if constexpr (TH)
+      gemm_range<m, KB, ALL, TP::NP, kShareA, TP::NS, TP::LDB, TP::LDC>(t.first, t.end, t.step, t.map, A1, t.B1,
+                                                                        A1, t.B2, t.alpha1, t.alpha2, lds, t.epi,
+                                                                        t.S[0], t.S[1], t.S[2], t.S[3]);
+  }
+}
+
 // ------------------------------------------------------------------ body
 constexpr double kTheta23 = 2.014710780944616;
 
@@ -407,14 +699,53 @@ constexpr double kTheta23 = 2.014710780944616;
 // sum is |lambda| c_j sum_i c_i |M_ij|, read along row j of the symmetric M.
 // One wave per column: lane l adds rows l, l + 64, ... in order, then a fixed
 // butterfly combines the lanes and lane 0 keeps the total.
+// Columns go in groups of kEwGroup per wave, every load of a group issued
+// before its stores (a store in between would keep the next column's loads
+// from being issued early).
+constexpr int kEwGroup = 8;
 template <int m>
 __device__ __forceinline__ void column_abs_sums(const Phi1Args& a, int worker, int nw, double* colsum) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int j = worker * 4 + w; j < m; j += nw * 4) {
-    double v = 0.0;
-    for (int i = l; i < m; i += 64) v += a.cvec[i] * fabs(a.Mraw[(size_t)j * m + i]);
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    if (l == 0) colsum[j] = fabs(a.lambda) * a.cvec[j] * v;
+  for (int j0 = worker * 4 + w; j0 < m; j0 += kEwGroup * nw * 4) {
+    double v[kEwGroup];
+#pragma unroll
+    for (int u = 0; u < kEwGroup; ++u) {
+      const int j = j0 + u * nw * 4;
+      double acc = 0.0;
+      if (j < m) {
+#pragma unroll
+        for (int i = l; i < m; i += 64) acc += a.cvec[i] * fabs(a.Mraw[(size_t)j * m + i]);
+      }
+      v[u] = acc;
+    }
+#pragma unroll
+    for (int u = 0; u < kEwGroup; ++u) {
+      for (int o = 32; o >= 1; o >>= 1) v[u] += __shfl_xor(v[u], o);
+      const int j = j0 + u * nw * 4;
+      if (l == 0 && j < m) colsum[j] = fabs(a.lambda) * a.cvec[j] * v[u];
+    }
+  }
+}
+
+// An elementwise pass over e = first, first + step, ... < n in groups of
+// kEwGroup per thread: ld(e) reads and computes element e's value, st(e, v)
+// stores it; every load of a group is issued before its stores (the compiler
+// cannot move a load above a store that may alias it).
+template <class LD, class ST>
+__device__ __forceinline__ void ew_pass(size_t first, size_t step, size_t n, LD ld, ST st) {
+  using V = decltype(ld(first));
+  for (size_t e0 = first; e0 < n; e0 += kEwGroup * step) {
+    V v[kEwGroup];
+#pragma unroll
+    for (int u = 0; u < kEwGroup; ++u) {
+      const size_t e = e0 + u * step;
+      if (e < n) v[u] = ld(e);
+    }
+#pragma unroll
+    for (int u = 0; u < kEwGroup; ++u) {
+      const size_t e = e0 + u * step;
+      if (e < n) st(e, v[u]);
+    }
   }
 }
 
@@ -473,15 +804,17 @@ __device__ __forceinline__ void horner_phase(const TaylorWs& w, int worker, int 
   constexpr int src = (J + 1) & 1, dst = J & 1;
   {
     const PhaseTiles pt(worker, nw, nb, 0, w.sym);
-    gemm_range<m, KB, ALL, 2, kShareA, 3>(
-        pt.first_full, pt.end_full, pt.step, pt.full, w.Y4, w.R[0][src], w.Y4, w.R[1][src], 1.0, 1.0, lds,
-        [&](int i, int j, double v0, double v1, const Side<3>& sd) {
-          const size_t e = (size_t)i * m + j;
-          const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * w.sc1, y2 = sd.v[1], y3 = sd.v[2];
-          gst(w.R[0][dst] + e, v0 + coef_block<J, 0>(id, y, y2, y3));
-          gst(w.R[1][dst] + e, v1 + coef_block<J, 1>(id, y, y2, y3));
-        },
-        w.X0, w.Y2, w.Y3);
+    gemm_pair<m, KB, ALL, kShareA>(
+        w.Y4, w.Y4,
+        part<2, 3, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, w.R[0][src], w.R[1][src], 1.0, 1.0,
+                         [&](int i, int j, double v0, double v1, const Side<3>& sd) {
+                           const size_t e = (size_t)i * m + j;
+                           const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * w.sc1, y2 = sd.v[1], y3 = sd.v[2];
+                           gst(w.R[0][dst] + e, v0 + coef_block<J, 0>(id, y, y2, y3));
+                           gst(w.R[1][dst] + e, v1 + coef_block<J, 1>(id, y, y2, y3));
+                         },
+                         w.X0, w.Y2, w.Y3),
+        NoPart{}, true, lds);
   }
   bar.sync();
 }
@@ -503,10 +836,12 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
 
   // ---- P0: X0 = lambda M, and column sums of |X0| (M is symmetric, so the
   // column sum of |X0| over rows is a row sum of |Mraw| scaled by c)
-  for (size_t e = (size_t)worker * 256 + t; e < mm; e += (size_t)nw * 256) {
-    const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
-    X0[e] = a.lambda * a.cvec[i] * a.Mraw[e] * a.cvec[j] * a.svec[j];
-  }
+  ew_pass((size_t)worker * 256 + t, (size_t)nw * 256, mm,
+          [&](size_t e) {
+            const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
+            return a.lambda * a.cvec[i] * a.Mraw[e] * a.cvec[j] * a.svec[j];
+          },
+          [&](size_t e, double v) { X0[e] = v; });
   column_abs_sums<m>(a, worker, nw, colsum);
   bar.sync();
 
@@ -518,26 +853,30 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   // ---- P1: Y2 = X0 X0 / 4^s
   {
     const PhaseTiles pt(worker, nw, nb, 0, a.sym != 0);
-    gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, pt.full, X0, X0, X0, X0, sc2, 0.0, lds,
-                                       [&](int i, int j, double v, double, const Side<0>&) {
-                                         gst(Y2 + (size_t)i * m + j, v);
-                                       });
+    gemm_pair<m, KB, ALL, kShareA>(X0, X0,
+                                   part<1, 0, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, X0, X0, sc2, 0.0,
+                                                    [&](int i, int j, double v, double, const Side<0>&) {
+                                                      gst(Y2 + (size_t)i * m + j, v);
+                                                    }),
+                                   NoPart{}, true, lds);
   }
   bar.sync();
   // ---- P2: Y3 = Y2 X0 / 2^s (its epilogue also forms B_5 of both chains) and Y4 = Y2 Y2
   {
     const PhaseTiles pt(worker, nw, nb, 0, a.sym != 0);
-    gemm_range<m, KB, ALL, 2, kShareA, 2>(
-        pt.first_full, pt.end_full, pt.step, pt.full, Y2, X0, Y2, Y2, sc1, 1.0, lds,
-        [&](int i, int j, double y3, double y4, const Side<2>& sd) {
-          const size_t e = (size_t)i * m + j;
-          const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * sc1, y2 = sd.v[1];
-          gst(Y3 + e, y3);
-          gst(Y4 + e, y4);
-          gst(R01 + e, coef_block<5, 0>(id, y, y2, y3));
-          gst(R11 + e, coef_block<5, 1>(id, y, y2, y3));
-        },
-        X0, Y2);
+    gemm_pair<m, KB, ALL, kShareA>(
+        Y2, Y2,
+        part<2, 2, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, X0, Y2, sc1, 1.0,
+                         [&](int i, int j, double y3, double y4, const Side<2>& sd) {
+                           const size_t e = (size_t)i * m + j;
+                           const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * sc1, y2 = sd.v[1];
+                           gst(Y3 + e, y3);
+                           gst(Y4 + e, y4);
+                           gst(R01 + e, coef_block<5, 0>(id, y, y2, y3));
+                           gst(R11 + e, coef_block<5, 1>(id, y, y2, y3));
+                         },
+                         X0, Y2),
+        NoPart{}, true, lds);
   }
   bar.sync();
   // ---- P3..P7: Horner steps J = 4 ... 0 (J odd reads buffer 0, writes 1 ... ends in buffer 0)
@@ -555,14 +894,15 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   for (int it = 0; it < s; ++it) {
     {
       const PhaseTiles pt(worker, nw, nb, 0, a.sym != 0);
-      gemm_range<m, KB, ALL, 2, kShareB, 1>(
-          pt.first_full, pt.end_full, pt.step, pt.full, Ec, Ec, Pc, Ec, 1.0, 0.5, lds,
-          [&](int i, int j, double e2, double pe, const Side<1>& sd) {
-            const size_t e = (size_t)i * m + j;
-            gst(En + e, e2);
-            gst(Pn + e, pe + 0.5 * sd.v[0]);
-          },
-          Pc);
+      gemm_pair<m, KB, ALL, kShareB>(Ec, Pc,
+                                     part<2, 1, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, Ec, Ec, 1.0, 0.5,
+                                                      [&](int i, int j, double e2, double pe, const Side<1>& sd) {
+                                                        const size_t e = (size_t)i * m + j;
+                                                        gst(En + e, e2);
+                                                        gst(Pn + e, pe + 0.5 * sd.v[0]);
+                                                      },
+                                                      Pc),
+                                     NoPart{}, true, lds);
     }
     bar.sync();
     double* x = Ec; Ec = En; En = x;
@@ -570,15 +910,20 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
   }
   // ---- S = lambda P (canonical), T = diag(c s) S diag(c) in device order
   const int fq = m / 2;
-  for (size_t e = (size_t)worker * 256 + t; e < mm; e += (size_t)nw * 256) {
-    const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
-    const double sv = a.lambda * Pc[e];
-    if (!isfinite(sv)) __hip_atomic_fetch_or(a.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a.S64[e] = sv;
-    const int di = i < fq ? 2 * i : 2 * (i - fq) + 1;
-    const int dj = j < fq ? 2 * j : 2 * (j - fq) + 1;
-    a.T64[(size_t)di * m + dj] = a.cvec[i] * a.svec[i] * sv * a.cvec[j];
-  }
+  ew_pass((size_t)worker * 256 + t, (size_t)nw * 256, mm,
+          [&](size_t e) {
+            const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
+            const double sv = a.lambda * Pc[e];
+            return make_double2(sv, a.cvec[i] * a.svec[i] * sv * a.cvec[j]);
+          },
+          [&](size_t e, double2 v) {
+            const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
+            if (!isfinite(v.x)) __hip_atomic_fetch_or(a.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            a.S64[e] = v.x;
+            const int di = i < fq ? 2 * i : 2 * (i - fq) + 1;
+            const int dj = j < fq ? 2 * j : 2 * (j - fq) + 1;
+            a.T64[(size_t)di * m + dj] = v.y;
+          });
 }
 
 // ------------------------------------------------------------------ action form
@@ -601,19 +946,22 @@ __device__ __forceinline__ void apply_horner(const TaylorWs& w, double* const (&
   constexpr int src = (J + 1) & 1, dst = J & 1;
   {
     const PhaseTiles pt(worker, nw, nb, nb, w.sym);
-    gemm_range<m, KB, ALL, 1, kShareA, 3>(
-        pt.first_full, pt.end_full, pt.step, pt.full, w.Y4, E[src], w.Y4, E[src], 1.0, 0.0, lds,
-        [&](int i, int j, double v, double, const Side<3>& sd) {
-          const double id = i == j ? 1.0 : 0.0;
-          gst(E[dst] + (size_t)i * m + j, v + coef_block<J, 1>(id, sd.v[0] * w.sc1, sd.v[1], sd.v[2]));
-        },
-        w.X0, w.Y2, w.Y3);
-    gemm_range<m, KB, ALL, 1, kShareA, 4, TW, TW>(
-        pt.first_thin, pt.end_thin, pt.step, pt.thin, w.Y4, W[src], w.Y4, W[src], 1.0, 0.0, lds,
-        [&](int i, int j, double v, double, const Side<4>& sd) {
-          gst(W[dst] + (size_t)i * TW + j, v + coef_block<J, 0>(sd.v[0], sd.v[1], sd.v[2], sd.v[3]));
-        },
-        V, U1, U2, U3);
+    gemm_pair<m, KB, ALL, kShareA>(
+        w.Y4, w.Y4,
+        part<1, 3, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, E[src], E[src], 1.0, 0.0,
+                         [&](int i, int j, double v, double, const Side<3>& sd) {
+                           const double id = i == j ? 1.0 : 0.0;
+                           gst(E[dst] + (size_t)i * m + j,
+                               v + coef_block<J, 1>(id, sd.v[0] * w.sc1, sd.v[1], sd.v[2]));
+                         },
+                         w.X0, w.Y2, w.Y3),
+        part<1, 4, TW, TW>(pt.first_thin, pt.end_thin, pt.step, pt.thin, W[src], W[src], 1.0, 0.0,
+                           [&](int i, int j, double v, double, const Side<4>& sd) {
+                             gst(W[dst] + (size_t)i * TW + j,
+                                 v + coef_block<J, 0>(sd.v[0], sd.v[1], sd.v[2], sd.v[3]));
+                           },
+                           V, U1, U2, U3),
+        true, lds);
   }
   bar.sync();
 }
@@ -639,15 +987,19 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
   const int t = threadIdx.x, f = m / 2, d = ap.d;
 
   // ---- P0: X0 = lambda M, column sums of |X0|, and v = diag(c) H0 (canonical, zero past d)
-  for (size_t e = (size_t)worker * 256 + t; e < mm; e += (size_t)nw * 256) {
-    const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
-    X0[e] = a.lambda * a.cvec[i] * a.Mraw[e] * a.cvec[j] * a.svec[j];
-  }
-  for (size_t e = (size_t)worker * 256 + t; e < mt; e += (size_t)nw * 256) {
-    const int i = (int)(e / TW), c = (int)(e - (size_t)i * TW);
-    const int di = i < f ? 2 * i : 2 * (i - f) + 1;
-    V[e] = c < d ? a.cvec[i] * ap.H0[(size_t)di * d + c] : 0.0;
-  }
+  ew_pass((size_t)worker * 256 + t, (size_t)nw * 256, mm,
+          [&](size_t e) {
+            const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
+            return a.lambda * a.cvec[i] * a.Mraw[e] * a.cvec[j] * a.svec[j];
+          },
+          [&](size_t e, double v) { X0[e] = v; });
+  ew_pass((size_t)worker * 256 + t, (size_t)nw * 256, mt,
+          [&](size_t e) {
+            const int i = (int)(e / TW), c = (int)(e - (size_t)i * TW);
+            const int di = i < f ? 2 * i : 2 * (i - f) + 1;
+            return c < d ? a.cvec[i] * ap.H0[(size_t)di * d + c] : 0.0;
+          },
+          [&](size_t e, double v) { V[e] = v; });
   column_abs_sums<m>(a, worker, nw, colsum);
   bar.sync();
   const int s = scaling_power<m>(colsum, lds);
@@ -657,38 +1009,41 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
   // ---- P1: Y2 = X0 X0 / 4^s; U1 = Y v
   {
     const PhaseTiles pt(worker, nw, nb, nb, a.sym != 0);
-    gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, pt.full, X0, X0, X0, X0, sc2, 0.0, lds,
-                                       [&](int i, int j, double v, double, const Side<0>&) {
-                                         gst(Y2 + (size_t)i * m + j, v);
-                                       });
-    gemm_range<m, KB, ALL, 1, kShareA, 0, TW, TW>(pt.first_thin, pt.end_thin, pt.step, pt.thin, X0, V, X0, V, sc1,
-                                                  0.0, lds, [&](int i, int j, double v, double, const Side<0>&) {
-                                                    gst(U1 + (size_t)i * TW + j, v);
-                                                  });
+    gemm_pair<m, KB, ALL, kShareA>(X0, X0,
+                                   part<1, 0, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, X0, X0, sc2, 0.0,
+                                                    [&](int i, int j, double v, double, const Side<0>&) {
+                                                      gst(Y2 + (size_t)i * m + j, v);
+                                                    }),
+                                   part<1, 0, TW, TW>(pt.first_thin, pt.end_thin, pt.step, pt.thin, V, V, sc1, 0.0,
+                                                      [&](int i, int j, double v, double, const Side<0>&) {
+                                                        gst(U1 + (size_t)i * TW + j, v);
+                                                      }),
+                                   true, lds);
   }
   bar.sync();
   // ---- P2: Y3 = Y2 Y, Y4 = Y2 Y2 (with B_5 of the exp chain); U2 = Y2 v, U3 = Y2 U1 (with B_5 v)
   {
     const PhaseTiles pt(worker, nw, nb, nb, a.sym != 0);
-    gemm_range<m, KB, ALL, 2, kShareA, 2>(
-        pt.first_full, pt.end_full, pt.step, pt.full, Y2, X0, Y2, Y2, sc1, 1.0, lds,
-        [&](int i, int j, double y3, double y4, const Side<2>& sd) {
-          const size_t e = (size_t)i * m + j;
-          const double id = i == j ? 1.0 : 0.0;
-          gst(Y3 + e, y3);
-          gst(Y4 + e, y4);
-          gst(E1 + e, coef_block<5, 1>(id, sd.v[0] * sc1, sd.v[1], y3));
-        },
-        X0, Y2);
-    gemm_range<m, KB, ALL, 2, kShareA, 2, TW, TW>(
-        pt.first_thin, pt.end_thin, pt.step, pt.thin, Y2, V, Y2, U1, 1.0, 1.0, lds,
-        [&](int i, int j, double u2, double u3, const Side<2>& sd) {
-          const size_t e = (size_t)i * TW + j;
-          gst(U2 + e, u2);
-          gst(U3 + e, u3);
-          gst(W1 + e, coef_block<5, 0>(sd.v[0], sd.v[1], u2, u3));
-        },
-        V, U1);
+    gemm_pair<m, KB, ALL, kShareA>(
+        Y2, Y2,
+        part<2, 2, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, X0, Y2, sc1, 1.0,
+                         [&](int i, int j, double y3, double y4, const Side<2>& sd) {
+                           const size_t e = (size_t)i * m + j;
+                           const double id = i == j ? 1.0 : 0.0;
+                           gst(Y3 + e, y3);
+                           gst(Y4 + e, y4);
+                           gst(E1 + e, coef_block<5, 1>(id, sd.v[0] * sc1, sd.v[1], y3));
+                         },
+                         X0, Y2),
+        part<2, 2, TW, TW>(pt.first_thin, pt.end_thin, pt.step, pt.thin, V, U1, 1.0, 1.0,
+                           [&](int i, int j, double u2, double u3, const Side<2>& sd) {
+                             const size_t e = (size_t)i * TW + j;
+                             gst(U2 + e, u2);
+                             gst(U3 + e, u3);
+                             gst(W1 + e, coef_block<5, 0>(sd.v[0], sd.v[1], u2, u3));
+                           },
+                           V, U1),
+        true, lds);
   }
   bar.sync();
   // ---- Horner steps J = 4 ... 0 (results in E0 and W0)
@@ -708,33 +1063,39 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
   for (int it = 0; it < s; ++it) {
     {
       const PhaseTiles pt(worker, nw, nb, nb, a.sym != 0);
-      if (it + 1 < s)
-        gemm_range<m, KB, ALL, 1, kShareA>(pt.first_full, pt.end_full, pt.step, pt.full, Ec, Ec, Ec, Ec, 1.0, 0.0,
-                                           lds, [&](int i, int j, double v, double, const Side<0>&) {
-                                             gst(En + (size_t)i * m + j, v);
-                                           });
-      gemm_range<m, KB, ALL, 1, kShareA, 1, TW, TW>(
-          pt.first_thin, pt.end_thin, pt.step, pt.thin, Ec, Wc, Ec, Wc, 0.5, 0.0, lds,
-          [&](int i, int j, double v, double, const Side<1>& sd) { gst(Wn + (size_t)i * TW + j, v + 0.5 * sd.v[0]); },
-          Wc);
+      gemm_pair<m, KB, ALL, kShareA>(
+          Ec, Ec,
+          part<1, 0, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, Ec, Ec, 1.0, 0.0,
+                           [&](int i, int j, double v, double, const Side<0>&) { gst(En + (size_t)i * m + j, v); }),
+          part<1, 1, TW, TW>(pt.first_thin, pt.end_thin, pt.step, pt.thin, Wc, Wc, 0.5, 0.0,
+                             [&](int i, int j, double v, double, const Side<1>& sd) {
+                               gst(Wn + (size_t)i * TW + j, v + 0.5 * sd.v[0]);
+                             },
+                             Wc),
+          it + 1 < s, lds);
     }
     bar.sync();
     double* x = Ec; Ec = En; En = x;
     x = Wc; Wc = Wn; Wn = x;
   }
   // ---- G' = diag(c s) lambda w in device order, as FP32 and a BF16 hi + lo pair
-  for (size_t e = (size_t)worker * 256 + t; e < (size_t)m * d; e += (size_t)nw * 256) {
-    const int i = (int)(e / d), c = (int)(e - (size_t)i * d);
-    const double sv = a.lambda * Wc[(size_t)i * TW + c];
-    if (!isfinite(sv)) __hip_atomic_fetch_or(a.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    gst(ap.G64 + (size_t)i * TW + c, sv);
-    const int di = i < f ? 2 * i : 2 * (i - f) + 1;
-    const float g = (float)(a.cvec[i] * a.svec[i] * sv);
-    const __bf16 hi = (__bf16)g;
-    ap.G32[(size_t)di * d + c] = g;
-    ap.Gt16[(size_t)c * m + di] = hi;
-    ap.Gt16[(size_t)kMaxDBlocks * kDBlock * m + (size_t)c * m + di] = (__bf16)(g - (float)hi);
-  }
+  ew_pass((size_t)worker * 256 + t, (size_t)nw * 256, (size_t)m * d,
+          [&](size_t e) {
+            const int i = (int)(e / d), c = (int)(e - (size_t)i * d);
+            const double sv = a.lambda * Wc[(size_t)i * TW + c];
+            return make_double2(sv, a.cvec[i] * a.svec[i] * sv);
+          },
+          [&](size_t e, double2 v) {
+            const int i = (int)(e / d), c = (int)(e - (size_t)i * d);
+            if (!isfinite(v.x)) __hip_atomic_fetch_or(a.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            gst(ap.G64 + (size_t)i * TW + c, v.x);
+            const int di = i < f ? 2 * i : 2 * (i - f) + 1;
+            const float g = (float)v.y;
+            const __bf16 hi = (__bf16)g;
+            ap.G32[(size_t)di * d + c] = g;
+            ap.Gt16[(size_t)c * m + di] = hi;
+            ap.Gt16[(size_t)kMaxDBlocks * kDBlock * m + (size_t)c * m + di] = (__bf16)(g - (float)hi);
+          });
 }
 
 // K blocks: the cooperative kernel (one workgroup per CU) issues all of a
@@ -747,12 +1108,16 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
 // for any block width, so both kernels give the same bits.
 constexpr int kWgKB = 32, kGridKB = 128;
 template <int M>
-constexpr int wg_kb() { return kWgKB; }
+constexpr int wg_kb() { return M <= 128 ? 0 : kWgKB; }
 template <int M>
 constexpr bool wg_all() { return false; }
+// waves per SIMD the per-cloud kernels are compiled for: one with the
+// register-resident output (m <= 128), two otherwise
+template <int M>
+constexpr int wg_waves() { return M <= 128 ? 1 : 2; }
 
 template <int M>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_phi1_wg(const Phi1Args* __restrict__ args) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(wg_waves<M>()))) void k_phi1_wg(const Phi1Args* __restrict__ args) {
   extern __shared__ double lds[];
   const Phi1Args a = args[blockIdx.x];
   WgBarrier bar;
@@ -778,7 +1143,7 @@ __global__ __launch_bounds__(256) void k_phi1_apply_grid(Phi1Args a, ApplyArgs a
 }
 
 template <int M>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_phi1_apply_wg(const Phi1Args* __restrict__ args,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(wg_waves<M>()))) void k_phi1_apply_wg(const Phi1Args* __restrict__ args,
                                                       const ApplyArgs* __restrict__ aargs) {
   extern __shared__ double lds[];
   const Phi1Args a = args[blockIdx.x];
@@ -789,6 +1154,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 // LDS bytes of the phi_1 kernels for padded size m.
 static size_t phi1_lds_bytes(int KB, bool all) { return (size_t)gemm_lds_doubles(KB, all) * sizeof(double); }
+// LDS bytes of the per-cloud kernels
+template <int M>
+static size_t wg_lds_bytes() {
+  return wg_kb<M>() == 0 ? sizeof(double) * (size_t)stream_lds_doubles(M) : phi1_lds_bytes(wg_kb<M>(), wg_all<M>());
+}
 
 size_t phi1_ws_doubles(int m) { return 8 * (size_t)m * m + m + 6 * (size_t)m * kThinWidth; }
 
@@ -886,7 +1256,7 @@ size_t phi1_apply_args_bytes() { return sizeof(ApplyArgs); }
 
 template <int M>
 static hipError_t launch_apply_batch_m(int n, const void* dev_args, const void* dev_aargs, hipStream_t st) {
-  const size_t lds = phi1_lds_bytes(wg_kb<M>(), wg_all<M>());
+  const size_t lds = wg_lds_bytes<M>();
   hipError_t e =
       hipFuncSetAttribute((const void*)k_phi1_apply_wg<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -910,7 +1280,7 @@ void phi1_fill_args(rfd_plan_s* p, void* args_out) { fill_args(p, *(Phi1Args*)ar
 
 template <int M>
 static hipError_t launch_phi1_batch_m(int n, const void* dev_args, hipStream_t st) {
-  const size_t lds = phi1_lds_bytes(wg_kb<M>(), wg_all<M>());
+  const size_t lds = wg_lds_bytes<M>();
   hipError_t e = hipFuncSetAttribute((const void*)k_phi1_wg<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   ProfileScope prof(kKPhi1Batch, st);
