@@ -36,6 +36,13 @@ in the design notes of the repository):
 * tau of the L2 ball indicator in 3-D is the spherical-Bessel form
   (sin u - u cos u) / (2 pi^2 r^3), u = 2 pi eps r; the paper's L1 formula is
   read as the transform of the L-infinity box, prod_i sin(2 pi eps w_i)/(pi w_i).
+* Points in D dimensions (the graph-classification appendix: node features as
+  vectors in R^D): tau of the D-ball is eps^(D/2) J_{D/2}(2 pi eps r) / r^(D/2)
+  (Sec. 2.4: a Bessel function of order tied to the dimension), the box
+  transform is the same product over D coordinates, P is N(0, sigma^2 I_D)
+  truncated to the D-ball (chi_D mass, the regularised incomplete gamma
+  function) or D-box, and the main-lobe ball radius is the first zero of
+  J_{D/2} over 2 pi eps. D = 3 keeps the closed forms above.
 * Self-loops: W_ii = 1 (f(0) = 1).
 * Random stream: SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) from the seed,
   53-bit uniforms, Box-Muller with both outputs used in order, 3 normals per
@@ -50,6 +57,8 @@ import math
 from fractions import Fraction
 
 import numpy as np
+from scipy import optimize as _opt
+from scipy import special as _sp
 
 # First positive root of tan(u) = u, i.e. of sin(u) - u cos(u): the first zero
 # of the 3-D ball transform's numerator. r0 = U0 / (2 pi) is that zero in
@@ -100,36 +109,60 @@ def gaussian_stream(seed: int):
         yield r * math.sin(t)
 
 
-def preset(eps: float, shape: int = BALL_L2, sigma: float = 0.0, radius: float = 0.0):
+def bessel_first_zero(nu: float) -> float:
+    """First positive zero j_{nu,1} of the Bessel function J_nu (nu >= 1/2):
+    bracketed between nu and nu + 2 sqrt(nu + 1) + 3 (the zero lies above nu)
+    and found by Brent's method on scipy's J_nu."""
+    a = max(nu, 1e-3)
+    b = nu + 2.0 * math.sqrt(nu + 1.0) + 3.0
+    # step up from a until J_nu changes sign (its first sign change is j_{nu,1})
+    xs = np.linspace(a, b, 400)
+    v = _sp.jv(nu, xs)
+    i = int(np.nonzero(np.sign(v[1:]) != np.sign(v[:-1]))[0][0])
+    return float(_opt.brentq(lambda x: _sp.jv(nu, x), xs[i], xs[i + 1], xtol=1e-15, rtol=8.9e-16, maxiter=200))
+
+
+def ball_radius_unit(dim: int) -> float:
+    """r0 of the D-ball: the first zero of its transform in units of 1/eps,
+    j_{D/2,1} / (2 pi); the 3-D constant R0 for D = 3."""
+    return R0 if dim == 3 else bessel_first_zero(0.5 * dim) / (2.0 * math.pi)
+
+
+def preset(eps: float, shape: int = BALL_L2, sigma: float = 0.0, radius: float = 0.0, dim: int = 3):
     """(sigma, R) of the truncated Gaussian. sigma = R = 0 selects the
     main-lobe preset: ball R = r0/eps, box R = 1/(2 eps); sigma = R/3."""
     if sigma > 0.0 and radius > 0.0:
         return float(sigma), float(radius)
     if sigma != 0.0 or radius != 0.0:
         raise ValueError("sigma and radius must both be set or both be 0")
-    R = (R0 / eps) if shape == BALL_L2 else (0.5 / eps)
+    R = (ball_radius_unit(dim) / eps) if shape == BALL_L2 else (0.5 / eps)
     return R / 3.0, R
 
 
 def sample_frequencies(f: int, eps: float, seed: int, shape: int = BALL_L2,
-                       sigma: float = 0.0, radius: float = 0.0) -> np.ndarray:
-    """f frequencies omega_k ~ N(0, sigma^2 I3) truncated to ||omega|| <= R
-    (L2 for the ball, L-infinity for the box) by rejection, as float32 (f x 3).
-    Sec. 2.4: omega_1..omega_m i.i.d. from P, P a truncated Gaussian."""
-    sig, R = preset(eps, shape, sigma, radius)
+                       sigma: float = 0.0, radius: float = 0.0, dim: int = 3) -> np.ndarray:
+    """f frequencies omega_k ~ N(0, sigma^2 I_D) truncated to ||omega|| <= R
+    (L2 for the ball, L-infinity for the box) by rejection, as float32
+    (f x D). Sec. 2.4: omega_1..omega_m i.i.d. from P, P a truncated Gaussian.
+    A candidate takes the next D normals of the stream in order; the squared
+    norm is summed left to right."""
+    if dim < 1:
+        raise ValueError("dim must be >= 1")
+    sig, R = preset(eps, shape, sigma, radius, dim)
     g = gaussian_stream(seed)
-    out = np.empty((f, 3), dtype=np.float32)
+    out = np.empty((f, dim), dtype=np.float32)
     k = 0
     while k < f:
-        w0 = sig * next(g)
-        w1 = sig * next(g)
-        w2 = sig * next(g)
+        cand = [sig * next(g) for _ in range(dim)]
         if shape == BALL_L2:
-            ok = (w0 * w0 + w1 * w1) + w2 * w2 <= R * R
+            r2 = cand[0] * cand[0]
+            for c in cand[1:]:
+                r2 = r2 + c * c
+            ok = r2 <= R * R
         else:
-            ok = max(abs(w0), abs(w1), abs(w2)) <= R
+            ok = max(abs(c) for c in cand) <= R
         if ok:
-            out[k] = (w0, w1, w2)
+            out[k] = cand
             k += 1
     return out
 
@@ -154,6 +187,26 @@ def tau_ball(omega: np.ndarray, eps: float) -> np.ndarray:
     return out
 
 
+def tau_ball_nd(omega: np.ndarray, eps: float) -> np.ndarray:
+    """Fourier transform of 1[||z||_2 <= eps] in D = omega.shape[-1]
+    dimensions, same convention: eps^(D/2) J_{D/2}(2 pi eps r) / r^(D/2);
+    at r = 0 the ball's volume pi^(D/2) eps^D / Gamma(D/2 + 1) (the limit of
+    J_nu(u) ~ (u/2)^nu / Gamma(nu + 1)), and its two-term series for small u."""
+    om = np.asarray(omega, dtype=np.float64)
+    D = om.shape[-1]
+    nu = 0.5 * D
+    r = np.sqrt(np.sum(om * om, axis=-1))
+    u = 2.0 * math.pi * eps * r
+    vol = math.pi ** nu * eps ** D / math.gamma(nu + 1.0)
+    small = u < 1e-4
+    out = np.empty_like(r)
+    us = u[small]
+    out[small] = vol * (1.0 - us * us / (4.0 * (nu + 1.0)))
+    ub, rb = u[~small], r[~small]
+    out[~small] = eps ** nu * _sp.jv(nu, ub) / rb ** nu
+    return out
+
+
 def tau_box(omega: np.ndarray, eps: float) -> np.ndarray:
     """Fourier transform of prod_i 1[|z_i| <= eps]: prod_i sin(2 pi eps w_i)/(pi w_i)
     = prod_i 2 eps sinc(2 eps w_i) with sinc(t) = sin(pi t)/(pi t)."""
@@ -161,28 +214,37 @@ def tau_box(omega: np.ndarray, eps: float) -> np.ndarray:
     return np.prod(2.0 * eps * np.sinc(2.0 * eps * om), axis=-1)
 
 
-def truncation_mass(t: float, shape: int = BALL_L2) -> float:
-    """P(N(0, I3) lies in the ball of radius t): the chi_3 CDF
-    erf(t/sqrt2) - sqrt(2/pi) t exp(-t^2/2); for the box, erf(t/sqrt2)^3."""
+def truncation_mass(t: float, shape: int = BALL_L2, dim: int = 3) -> float:
+    """P(N(0, I_D) lies in the ball of radius t): the chi_D CDF, the
+    regularised lower incomplete gamma P(D/2, t^2/2); for D = 3 the closed form
+    erf(t/sqrt2) - sqrt(2/pi) t exp(-t^2/2). For the box, erf(t/sqrt2)^D."""
     if shape == BALL_L2:
-        return math.erf(t / math.sqrt(2.0)) - math.sqrt(2.0 / math.pi) * t * math.exp(-t * t / 2.0)
-    return math.erf(t / math.sqrt(2.0)) ** 3
+        if dim == 3:
+            return math.erf(t / math.sqrt(2.0)) - math.sqrt(2.0 / math.pi) * t * math.exp(-t * t / 2.0)
+        return float(_sp.gammainc(0.5 * dim, 0.5 * t * t))
+    return math.erf(t / math.sqrt(2.0)) ** dim
 
 
 def pdf(omega: np.ndarray, sigma: float, R: float, shape: int = BALL_L2) -> np.ndarray:
-    """Density of N(0, sigma^2 I3) truncated to the radius-R ball (or box)."""
+    """Density of N(0, sigma^2 I_D) truncated to the radius-R ball (or box),
+    D = omega.shape[-1]."""
     om = np.asarray(omega, dtype=np.float64)
+    D = om.shape[-1]
     r2 = np.sum(om * om, axis=-1)
-    C = truncation_mass(R / sigma, shape)
-    return (2.0 * math.pi * sigma * sigma) ** -1.5 * np.exp(-r2 / (2.0 * sigma * sigma)) / C
+    C = truncation_mass(R / sigma, shape, D)
+    return (2.0 * math.pi * sigma * sigma) ** (-0.5 * D) * np.exp(-r2 / (2.0 * sigma * sigma)) / C
 
 
 def weights(omega: np.ndarray, eps: float, shape: int = BALL_L2, sigma: float = 0.0,
             radius: float = 0.0) -> np.ndarray:
     """w_k = tau(omega_k) / p(omega_k) at the float32 frequencies (Sec. 2.4:
-    nu_k^2 = tau/p)."""
-    sig, R = preset(eps, shape, sigma, radius)
-    tau = tau_ball(omega, eps) if shape == BALL_L2 else tau_box(omega, eps)
+    nu_k^2 = tau/p); the dimension is that of the frequencies."""
+    D = np.asarray(omega).shape[-1]
+    sig, R = preset(eps, shape, sigma, radius, D)
+    if shape == BALL_L2:
+        tau = tau_ball(omega, eps) if D == 3 else tau_ball_nd(omega, eps)
+    else:
+        tau = tau_box(omega, eps)
     return tau / pdf(omega, sig, R, shape)
 
 
@@ -298,11 +360,11 @@ def lowrank_apply(A: np.ndarray, B: np.ndarray, F: np.ndarray, lam: float):
 
 
 def frequencies_and_weights(m: int, eps: float, seed: int, shape: int = BALL_L2,
-                            sigma: float = 0.0, radius: float = 0.0):
+                            sigma: float = 0.0, radius: float = 0.0, dim: int = 3):
     if m <= 0 or m % 2:
         raise ValueError("m must be a positive even number")
     f = m // 2
-    om = sample_frequencies(f, eps, seed, shape, sigma, radius)
+    om = sample_frequencies(f, eps, seed, shape, sigma, radius, dim)
     return om, weights(om, eps, shape, sigma, radius)
 
 
@@ -458,15 +520,18 @@ def gw_loss(apply_C, apply_D, T):
     return v1[:, None] + v2[None, :] - 2.0 * w3
 
 
-def kernel_spectrum(X, eps: float, lam: float, m: int, seed: int, shape: int = BALL_L2):
+def kernel_spectrum(X, eps: float, lam: float, m: int, seed: int, shape: int = BALL_L2,
+                    sigma: float = 0.0, radius: float = 0.0):
     """All N eigenvalues, ascending, of the RFD kernel matrix exp(lam A B^T)
     through the low-rank factors, as the classification experiments use them
     (Sec. 3, point-cloud classification; the graph-classification appendix):
     det(t I_N - A B^T) = t^(N-m) det(t I_m - B^T A), so A B^T has the m
     eigenvalues mu_i of B^T A and N - m zeros when N >= m, and for N < m the
     eigenvalues of B^T A less m - N of its zero ones (those of smallest |mu|);
-    exp(lam A B^T) has exp(lam mu) for each."""
-    om, w = frequencies_and_weights(m, eps, seed, shape)
+    exp(lam A B^T) has exp(lam mu) for each. Points may have any dimension D
+    (the frequencies take the points' dimension)."""
+    D = np.asarray(X).shape[1]
+    om, w = frequencies_and_weights(m, eps, seed, shape, sigma, radius, D)
     Phi, sg = features(X, om, w)
     M = Phi.T @ (Phi * sg)  # B^T A
     mu = np.linalg.eigvals(M).real

@@ -144,6 +144,173 @@ def test_main_lobe_weights_positive_and_origin_value():
         assert np.all(w > 0)
 
 
+# ---------------------------------------------------------------- points in D dimensions
+def test_bessel_first_zero_known_values():
+    """j_{nu,1}: pi for nu = 1/2 (J_{1/2} ~ sin x / sqrt x), the root of
+    tan u = u for nu = 3/2, the root of tan x = 3x / (3 - x^2) for nu = 5/2
+    (spherical j_2), and SciPy's jn_zeros (its own algorithm) at integer
+    orders."""
+    import scipy.special as sp
+    assert o.bessel_first_zero(0.5) == pytest.approx(math.pi, rel=1e-15)
+    u0 = so.brentq(lambda u: math.sin(u) - u * math.cos(u), math.pi, 1.5 * math.pi, xtol=1e-15)
+    assert o.bessel_first_zero(1.5) == pytest.approx(u0, rel=1e-14)
+    x2 = so.brentq(lambda x: (3 - x * x) * math.sin(x) - 3 * x * math.cos(x), 4.6, 6.0, xtol=1e-15)
+    assert o.bessel_first_zero(2.5) == pytest.approx(x2, rel=1e-14)
+    for n in (1, 2, 4, 8, 32):
+        assert o.bessel_first_zero(float(n)) == pytest.approx(sp.jn_zeros(n, 1)[0], rel=1e-14)
+    assert o.ball_radius_unit(3) == o.R0
+
+
+def test_tau_ball_nd_closed_forms():
+    """D = 3 is the spherical-Bessel form, D = 1 the interval transform
+    sin(2 pi eps w) / (pi w), and tau(0) the D-ball volume; the small-u series
+    meets the Bessel branch at its switch point."""
+    eps = 0.07
+    for u in [1e-6, 5e-5, 9.9e-5, 1.01e-4, 0.3, 1.0, 4.4, 9.0]:
+        r = u / (2 * math.pi * eps)
+        om3 = np.array([[r / math.sqrt(3)] * 3])
+        assert o.tau_ball_nd(om3, eps)[0] == pytest.approx(o.tau_ball(om3, eps)[0], rel=1e-12, abs=1e-15)
+        om1 = np.array([[r]])
+        ref1 = math.sin(2 * math.pi * eps * r) / (math.pi * r)
+        assert o.tau_ball_nd(om1, eps)[0] == pytest.approx(ref1, rel=1e-12, abs=1e-15)
+        assert o.tau_ball_nd(om1, eps)[0] == pytest.approx(o.tau_box(om1, eps)[0], rel=1e-12, abs=1e-15)
+    for D in range(1, 9):
+        vol = math.pi ** (D / 2) * eps ** D / math.gamma(D / 2 + 1)
+        assert o.tau_ball_nd(np.zeros((1, D)), eps)[0] == pytest.approx(vol, rel=1e-15)
+        u = 1e-4  # either side of the switch
+        lo = o.tau_ball_nd(np.array([[u * 0.999 / (2 * math.pi * eps)] + [0.0] * (D - 1)]), eps)[0]
+        hi = o.tau_ball_nd(np.array([[u * 1.001 / (2 * math.pi * eps)] + [0.0] * (D - 1)]), eps)[0]
+        assert abs(lo - hi) < 1e-9 * vol
+
+
+def _tau_ball_hankel(r, eps, D):
+    # radial Fourier transform in R^D: 2 pi r^(1 - D/2) int_0^eps rho^(D/2) J_{D/2-1}(2 pi r rho) d rho
+    import scipy.special as sp
+    nu = D / 2 - 1
+    val, _ = si.quad(lambda rho: rho ** (D / 2) * sp.jv(nu, 2 * math.pi * r * rho), 0.0, eps, epsabs=0,
+                     epsrel=1e-13, limit=200)
+    return 2 * math.pi * r ** (1 - D / 2) * val
+
+
+@pytest.mark.parametrize("D", [2, 4, 5, 7, 10])
+def test_tau_ball_nd_matches_radial_quadrature(D):
+    eps = 0.09
+    vol = math.pi ** (D / 2) * eps ** D / math.gamma(D / 2 + 1)
+    rng = np.random.default_rng(D)
+    for u in [3e-3, 0.5, 2.0, 4.0, 7.5, 12.0]:
+        r = u / (2 * math.pi * eps)
+        direction = rng.normal(size=D)
+        om = (r * direction / np.linalg.norm(direction))[None]
+        got = o.tau_ball_nd(om, eps)[0]
+        ref = _tau_ball_hankel(r, eps, D)
+        assert abs(got - ref) <= 1e-11 * vol, (D, u, got, ref)
+
+
+def test_truncation_mass_nd():
+    for t in [0.4, 1.0, 2.5, 6.0]:
+        assert o.truncation_mass(t, o.BALL_L2, 1) == pytest.approx(math.erf(t / math.sqrt(2)), rel=1e-13)
+        assert o.truncation_mass(t, o.BALL_L2, 2) == pytest.approx(-math.expm1(-t * t / 2), rel=1e-13)
+        for D in (4, 5, 10, 64):
+            assert o.truncation_mass(t, o.BALL_L2, D) == pytest.approx(ss.chi(D).cdf(t), rel=1e-12, abs=1e-300)
+            assert o.truncation_mass(t, o.BOX_LINF, D) == pytest.approx((2 * ss.norm.cdf(t) - 1) ** D, rel=1e-12)
+
+
+def test_pdf_normalisation_nd():
+    sig, R = 0.7, 1.6
+    # D = 2 ball: 2 pi r dr; D = 5 ball: surface 8 pi^2 / 3 r^4
+    tot2, _ = si.quad(lambda r: o.pdf(np.array([[r, 0.0]]), sig, R)[0] * 2 * math.pi * r, 0, R, epsabs=0,
+                      epsrel=1e-13)
+    tot5, _ = si.quad(lambda r: o.pdf(np.array([[r, 0, 0, 0, 0.0]]), sig, R)[0] * 8 * math.pi ** 2 / 3 * r ** 4,
+                      0, R, epsabs=0, epsrel=1e-13)
+    box2, _ = si.dblquad(lambda y, x: o.pdf(np.array([[x, y]]), sig, R, o.BOX_LINF)[0], -R, R, -R, R,
+                         epsabs=0, epsrel=1e-11)
+    assert tot2 == pytest.approx(1.0, abs=1e-12)
+    assert tot5 == pytest.approx(1.0, abs=1e-12)
+    assert box2 == pytest.approx(1.0, abs=1e-9)
+
+
+@pytest.mark.parametrize("D", [1, 2, 5, 8])
+def test_nd_main_lobe_preset(D):
+    """The preset ball radius is the transform's first zero, and every
+    sampled weight is positive (the main lobe only); the box radius is
+    1/(2 eps) in any dimension."""
+    eps = 0.1
+    sig, R = o.preset(eps, dim=D)
+    assert sig == pytest.approx(R / 3)
+    e1 = np.zeros((1, D))
+    e1[0, 0] = R
+    assert abs(o.tau_ball_nd(e1, eps)[0]) < 1e-12 * o.tau_ball_nd(np.zeros((1, D)), eps)[0]
+    om, w = o.frequencies_and_weights(512, eps, seed=3, dim=D)
+    assert om.shape == (256, D) and np.all(w > 0)
+    assert o.preset(eps, o.BOX_LINF, dim=D)[1] == pytest.approx(0.5 / eps)
+
+
+def test_nd_sampler_is_truncated_gaussian():
+    """D = 5: inside the ball, with the truncated chi^2 mean of |omega|^2:
+    sigma^2 D P(D/2 + 1, t^2/2) / P(D/2, t^2/2), t = R/sigma; the D = 3 draw
+    is the default sampler's."""
+    import scipy.special as sp
+    D, eps = 5, 0.1
+    sig, R = o.preset(eps, dim=D)
+    om = o.sample_frequencies(4000, eps, seed=9, dim=D).astype(np.float64)
+    r2 = np.sum(om * om, axis=1)
+    assert np.all(r2 <= R * R * (1 + 1e-6))
+    t2 = (R / sig) ** 2 / 2
+    mean_ref = sig * sig * D * sp.gammainc(D / 2 + 1, t2) / sp.gammainc(D / 2, t2)
+    se = r2.std(ddof=1) / math.sqrt(len(r2))
+    assert abs(r2.mean() - mean_ref) < 5 * se
+    assert np.array_equal(o.sample_frequencies(40, 0.2, seed=4, dim=3), o.sample_frequencies(40, 0.2, seed=4))
+    box = o.sample_frequencies(500, eps, seed=2, shape=o.BOX_LINF, dim=D)
+    assert box.shape == (500, D) and np.abs(box).max() <= 0.5 / eps
+
+
+def _f_tilde_nd(rho, eps, R, D):
+    # E[W_hat(z)] = int_{|w| <= R} cos(2 pi w.z) tau(w) dw in R^D, by the radial transform
+    import scipy.special as sp
+    tau = lambda r: o.tau_ball_nd(np.array([[r] + [0.0] * (D - 1)]), eps)[0]
+    if rho == 0.0:
+        area = 2 * math.pi ** (D / 2) / math.gamma(D / 2)
+        val, _ = si.quad(lambda r: tau(r) * area * r ** (D - 1), 0, R, epsabs=0, epsrel=1e-11, limit=200)
+        return val
+    nu = D / 2 - 1
+    val, _ = si.quad(lambda r: tau(r) * sp.jv(nu, 2 * math.pi * r * rho) * r ** (D / 2), 0, R, epsabs=0,
+                     epsrel=1e-11, limit=200)
+    return 2 * math.pi * rho ** (1 - D / 2) * val
+
+
+@pytest.mark.parametrize("D", [2, 5])
+def test_nd_estimator_mean_converges(D):
+    """Sec. 2.4's estimator in D dimensions: over independent seeds, the mean
+    of W_hat(x0, x_j) is the truncated transform integral (within 5 standard
+    errors), which approaches the eps-ball indicator."""
+    eps, f = 0.1, 128
+    sig, R = o.preset(eps, dim=D)
+    rhos = [0.0, 0.5 * eps, 1.5 * eps]
+    X = np.zeros((len(rhos), D), dtype=np.float32)
+    for j, r in enumerate(rhos):
+        X[j, 0] = r
+    draws = np.array([o.what_hat(X, *o.frequencies_and_weights(2 * f, eps, seed=500 + s, dim=D))[0]
+                      for s in range(200)])
+    for j, rho in enumerate(rhos):
+        ref = _f_tilde_nd(float(X[j, 0]), eps, R, D)
+        se = draws[:, j].std(ddof=1) / math.sqrt(len(draws))
+        assert abs(draws[:, j].mean() - ref) < 5 * se + 1e-12, (D, rho, draws[:, j].mean(), ref)
+    assert _f_tilde_nd(0.0, eps, R, D) > 0.8 and abs(_f_tilde_nd(1.5 * eps, eps, R, D)) < 0.2
+
+
+@pytest.mark.parametrize("D,shape", [(5, 0), (2, 0), (7, 1)])
+def test_kernel_spectrum_nd_matches_dense(D, shape):
+    import scipy.linalg as sl
+    g = np.random.default_rng(D)
+    X = g.uniform(0, 1, (30, D)).astype(np.float32)
+    eps, lam, m = 0.5, -0.4, 16
+    om, w = o.frequencies_and_weights(m, eps, 5, shape, dim=D)
+    K = sl.expm(lam * o.what_hat(X, om, w))
+    dense = np.sort(sl.eigvalsh(0.5 * (K + K.T)))
+    got = o.kernel_spectrum(X, eps, lam, m, 5, shape)
+    assert np.abs(got - dense).max() <= 1e-12 * max(1.0, np.abs(dense).max())
+
+
 # ---------------------------------------------------------------- expm, phi1
 def test_pade13_coefficients_satisfy_the_pade_conditions():
     # [13/13] Pade of e^x: q(x) e^x - p(x) = O(x^27), checked in exact rational
