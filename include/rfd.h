@@ -76,7 +76,15 @@ typedef struct {
   int32_t m;          /* real feature columns, even, 2 <= m <= 256 (f = m/2 frequencies) */
   int32_t shape;      /* rfd_shape */
   int32_t precision;  /* rfd_precision */
-  int32_t reserved;   /* must be 0 */
+  int32_t dim;        /* coordinate dimension D of the points, 1 <= D <= 64; 0 means 3. Points in D
+                         dimensions (the graph-classification appendix: node features as vectors
+                         in R^D) are taken by rfd_features, rfd_features_sync, rfd_plan_core and the
+                         spectrum calls; every entry point that applies the kernel to a field needs
+                         D = 3 and returns RFD_ERR_INVALID_ARG otherwise. For D != 3 the ball's
+                         transform is tau = eps^(D/2) J_{D/2}(2 pi eps r) / r^(D/2), its preset
+                         radius the first zero of J_{D/2} over 2 pi eps, the preset sigma
+                         R / sqrt(D + 6) (R/3 at D = 3), and the frequency law N(0, sigma^2 I_D)
+                         truncated to the D-ball or D-box (Sec. 2.4). */
   double eps;         /* neighbourhood radius, > 0 */
   double lambda;      /* diffusion strength in exp(lambda W); any sign */
   double sigma;       /* Gaussian scale of the frequency law; 0 with radius 0 = preset */
@@ -84,7 +92,7 @@ typedef struct {
                          ball R = 0.7151483/eps (first zero of tau), box R = 1/(2 eps);
                          sigma = R/3. The preset keeps every weight >= 0. */
   uint64_t seed;      /* SplitMix64 seed of the frequency stream */
-  const float* omega; /* optional HOST array of f x 3 frequencies (row-major); NULL = sample */
+  const float* omega; /* optional HOST array of f x D frequencies (row-major); NULL = sample */
 } rfd_params;
 
 typedef struct rfd_plan_s* rfd_plan_t;
@@ -94,8 +102,9 @@ typedef void* rfd_stream_t; /* a hipStream_t; NULL = the default stream */
 /* ---------------------------------------------------------------- plans */
 
 /* Validates params, samples the f frequencies on the host (SplitMix64 ->
- * 53-bit uniforms -> Box-Muller, both outputs in order -> times sigma ->
- * rejected outside the ball/box of radius R, in FP64 -> rounded to FP32) or
+ * 53-bit uniforms -> Box-Muller, both outputs in order, D per candidate ->
+ * times sigma -> rejected outside the ball/box of radius R, the squared norm
+ * summed in coordinate order, in FP64 -> rounded to FP32) or
  * takes them from params->omega, computes the weights w = tau/p in FP64 and
  * uploads the frequencies. Errors: RFD_ERR_INVALID_ARG. */
 rfd_status rfd_plan_create(const rfd_params* params, rfd_plan_t* out_plan);
@@ -125,17 +134,19 @@ rfd_status rfd_plan_create_in(const rfd_params* params, void* arena_dev, size_t 
 
 /* Host only (no device memory, no GPU needed): the f frequencies and FP64
  * weights that rfd_plan_create would produce for these params, written to
- * caller-owned host arrays of f x 3 floats and f doubles. Errors:
+ * caller-owned host arrays of f x D floats and f doubles. Errors:
  * RFD_ERR_INVALID_ARG as for rfd_plan_create. */
 rfd_status rfd_params_frequencies(const rfd_params* params, float* omega_fx3, double* w_f);
 
-/* Copies the plan's FP32 frequencies (f x 3, row-major) and FP64 weights (f)
+/* Copies the plan's FP32 frequencies (f x D, row-major) and FP64 weights (f)
  * to host arrays; either pointer may be NULL. */
 rfd_status rfd_plan_export(rfd_plan_t plan, float* omega_fx3, double* w_f);
 
 /* Features of a cloud: copies X (N x 3 float32, device, row-major) into the
  * plan, computes M = B^T A (split over N, fixed-order reduction, FP64 result)
  * and S = lambda phi_1(lambda M) in FP64 (Taylor 23, scaling and squaring).
+ * For a plan of dimension D != 3, X is N x D and is not kept (the plan then
+ * serves rfd_plan_core and the spectrum calls only).
  * Enqueued on `stream`; returns once enqueued. Errors found on the host are
  * returned at once: RFD_ERR_INVALID_ARG (N < 0), RFD_ERR_RANGE when lambda
  * and the weights allow growth (lambda * w > 0 for some k) and the exact

@@ -74,6 +74,11 @@ THETA13 = 5.371920351148152
 BALL_L2 = 0
 BOX_LINF = 1
 
+# Rejection sampling gives up after this many candidates (per frequency, plus
+# a fixed allowance): a law whose truncation keeps almost no mass is refused.
+MAX_CANDIDATES_PER_FREQUENCY = 10000
+MAX_CANDIDATES_EXTRA = 1000000
+
 _MASK64 = (1 << 64) - 1
 
 
@@ -130,13 +135,15 @@ def ball_radius_unit(dim: int) -> float:
 
 def preset(eps: float, shape: int = BALL_L2, sigma: float = 0.0, radius: float = 0.0, dim: int = 3):
     """(sigma, R) of the truncated Gaussian. sigma = R = 0 selects the
-    main-lobe preset: ball R = r0/eps, box R = 1/(2 eps); sigma = R/3."""
+    main-lobe preset: ball R = r0/eps, box R = 1/(2 eps); sigma = R/3 in 3-D,
+    R / sqrt(D + 6) in D dimensions (the same for D = 3; the D-dimensional
+    Gaussian's mass sits near radius sigma sqrt(D), which stays inside R)."""
     if sigma > 0.0 and radius > 0.0:
         return float(sigma), float(radius)
     if sigma != 0.0 or radius != 0.0:
         raise ValueError("sigma and radius must both be set or both be 0")
     R = (ball_radius_unit(dim) / eps) if shape == BALL_L2 else (0.5 / eps)
-    return R / 3.0, R
+    return (R / 3.0 if dim == 3 else R / math.sqrt(dim + 6.0)), R
 
 
 def sample_frequencies(f: int, eps: float, seed: int, shape: int = BALL_L2,
@@ -152,7 +159,11 @@ def sample_frequencies(f: int, eps: float, seed: int, shape: int = BALL_L2,
     g = gaussian_stream(seed)
     out = np.empty((f, dim), dtype=np.float32)
     k = 0
+    tries = 0
     while k < f:
+        tries += 1
+        if tries > MAX_CANDIDATES_PER_FREQUENCY * f + MAX_CANDIDATES_EXTRA:
+            raise ValueError("the truncated frequency law accepts too few candidates")
         cand = [sig * next(g) for _ in range(dim)]
         if shape == BALL_L2:
             r2 = cand[0] * cand[0]

@@ -74,7 +74,7 @@ extern "C" {
 
 rfd_status rfd_autotune(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, float* out, int64_t ldO, int32_t reps,
                         rfd_stream_t stream) {
-  if (!p || reps < 1) return RFD_ERR_INVALID_ARG;
+  if (!p || reps < 1 || !rfd::plan_is_3d(p)) return RFD_ERR_INVALID_ARG;
   if (p->N < 0) return RFD_ERR_NOT_READY;
   rfd_status s = rfd::check_field_args(p->N, F, ldF, d, out, ldO);
   if (s != RFD_OK) return s;

@@ -71,7 +71,8 @@ rfd_status rfd_bary_create(rfd_plan_t p, const float* a, const float* mus, int64
                            const double* alpha, int32_t iterations, double floor, float* mu_out, rfd_bary_t* out) {
   if (!out) return RFD_ERR_INVALID_ARG;
   *out = nullptr;
-  if (!p || !a || !mus || !alpha || !mu_out || k < 1 || k > rfd::kMaxBaryInputs || ldmu < k || iterations < 1)
+  if (!p || !a || !mus || !alpha || !mu_out || k < 1 || k > rfd::kMaxBaryInputs || ldmu < k || iterations < 1 ||
+      !rfd::plan_is_3d(p))
     return RFD_ERR_INVALID_ARG;
   for (int i = 0; i < k; ++i)
     if (!(alpha[i] >= 0.0) || !isfinite(alpha[i])) return RFD_ERR_INVALID_ARG;

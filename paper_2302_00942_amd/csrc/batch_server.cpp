@@ -120,7 +120,7 @@ rfd_status rfd_batch_create(const rfd_plan_t* plans, const float* const* Xs, con
   int dmax = 0;
   for (int i = 0; i < n; ++i) {
     rfd_plan_s* p = plans[i];
-    if (!p || p->dev_m != M || p->params.precision != prec) return RFD_ERR_INVALID_ARG;
+    if (!p || p->dev_m != M || p->params.precision != prec || !rfd::plan_is_3d(p)) return RFD_ERR_INVALID_ARG;
     if (Ns[i] < 0 || ds[i] < 1 || ldFs[i] < ds[i] || ldOs[i] < ds[i]) return RFD_ERR_INVALID_ARG;
     if (Ns[i] > 0 && (!Xs[i] || !Fs[i] || !outs[i])) return RFD_ERR_INVALID_ARG;
     for (int j = 0; j < i; ++j)

@@ -96,7 +96,7 @@ extern "C" {
 rfd_status rfd_gw_create(rfd_plan_t pc, rfd_plan_t pd, rfd_gw_t* out) {
   if (!out) return RFD_ERR_INVALID_ARG;
   *out = nullptr;
-  if (!pc || !pd || pc == pd) return RFD_ERR_INVALID_ARG;
+  if (!pc || !pd || pc == pd || !rfd::plan_is_3d(pc) || !rfd::plan_is_3d(pd)) return RFD_ERR_INVALID_ARG;
   if (pc->N < 0 || pd->N < 0) return RFD_ERR_NOT_READY;
   if (pc->N < 1 || pd->N < 1 || pc->N > kMaxGwPoints || pd->N > kMaxGwPoints) return RFD_ERR_INVALID_ARG;
   rfd_gw_s* g = new (std::nothrow) rfd_gw_s();

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <vector>
 
@@ -18,6 +19,9 @@ constexpr double kPi = 3.14159265358979323846;
 // First positive root of sin(u) - u cos(u): where the 3-D ball transform first
 // changes sign. Main-lobe truncation radius = kU0 / (2 pi eps).
 constexpr double kU0 = 4.493409457909064;
+// Rejection sampling gives up after this many candidates (per frequency, plus
+// a fixed allowance): a law whose truncation keeps almost no mass is refused.
+constexpr int64_t kMaxCandidatesPerFrequency = 10000, kMaxCandidatesExtra = 1000000;
 
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): Weyl sequence with
 // increment 0x9E3779B97F4A7C15, then the variant-13 mixer.
@@ -54,15 +58,39 @@ struct Gaussian {
   }
 };
 
+// First positive zero of the Bessel function J_nu (nu >= 1/2): J_nu is
+// positive on (0, j_{nu,1}) and j_{nu,1} > nu, so scan upward from nu in
+// steps of 1/16 to the first sign change, then bisect it to the last bit.
+double bessel_first_zero(double nu) {
+  double a = nu, fa = std::cyl_bessel_j(nu, a);
+  double b = a + 0.0625;
+  while (std::cyl_bessel_j(nu, b) > 0.0) {
+    a = b;
+    b += 0.0625;
+  }
+  (void)fa;
+  for (int i = 0; i < 200; ++i) {
+    const double c = 0.5 * (a + b);
+    if (c <= a || c >= b) break;
+    if (std::cyl_bessel_j(nu, c) > 0.0) a = c;
+    else b = c;
+  }
+  return 0.5 * (a + b);
+}
+
 void preset(const rfd_params& p, double* sigma, double* R) {
   if (p.sigma > 0.0 && p.radius > 0.0) {
     *sigma = p.sigma;
     *R = p.radius;
     return;
   }
-  const double r0 = kU0 / (2.0 * kPi);
+  const int D = rfd::plan_dim(p);
+  // main lobe of the ball: the first zero of its transform, j_{D/2,1} / (2 pi eps)
+  const double r0 = (D == 3 ? kU0 : bessel_first_zero(0.5 * D)) / (2.0 * kPi);
   *R = (p.shape == RFD_BALL_L2) ? (r0 / p.eps) : (0.5 / p.eps);
-  *sigma = *R / 3.0;
+  // R/3 in 3-D; R/sqrt(D + 6) in D dimensions (equal for D = 3), so that the
+  // Gaussian's bulk, near radius sigma sqrt(D), stays inside R
+  *sigma = D == 3 ? *R / 3.0 : *R / sqrt(D + 6.0);
 }
 
 // Fourier transform of the ball indicator 1[||z|| <= eps] in R^3 under
@@ -93,6 +121,66 @@ double trunc_mass(double t, int shape) {
   return e * e * e;
 }
 
+// Regularised lower incomplete gamma P(a, x) = gamma(a, x) / Gamma(a):
+// for x < a + 1 its power series x^a e^-x / Gamma(a + 1) sum_n x^n / ((a+1)..(a+n));
+// otherwise 1 - Q(a, x) with Q from Legendre's continued fraction
+// e^-x x^a / Gamma(a) * 1/(x + 1 - a - 1(1 - a)/(x + 3 - a - 2(2 - a)/(x + 5 - a - ...))),
+// evaluated by the modified Lentz method.
+double gamma_p(double a, double x) {
+  if (x <= 0.0) return 0.0;
+  const double lead = -x + a * log(x) - lgamma(a);
+  if (x < a + 1.0) {
+    double term = 1.0 / a, sum = term;
+    for (int n = 1; n < 1000; ++n) {
+      term *= x / (a + n);
+      sum += term;
+      if (fabs(term) < fabs(sum) * 1e-17) break;
+    }
+    return sum * exp(lead);
+  }
+  const double tiny = 1e-300;
+  double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
+  for (int i = 1; i < 1000; ++i) {
+    const double an = -i * (i - a);
+    b += 2.0;
+    d = an * d + b;
+    if (fabs(d) < tiny) d = tiny;
+    c = b + an / c;
+    if (fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    h *= del;
+    if (fabs(del - 1.0) < 1e-16) break;
+  }
+  return 1.0 - exp(lead) * h;
+}
+
+// Points in D dimensions. Transform of the D-ball indicator:
+// eps^(D/2) J_{D/2}(2 pi eps r) / r^(D/2), the ball's volume
+// pi^(D/2) eps^D / Gamma(D/2 + 1) at r = 0 and its two-term series for small u.
+double tau_ball_nd(const double* w, int D, double eps) {
+  double r2 = w[0] * w[0];
+  for (int k = 1; k < D; ++k) r2 = r2 + w[k] * w[k];
+  const double r = sqrt(r2), nu = 0.5 * D;
+  const double u = 2.0 * kPi * eps * r;
+  const double vol = pow(kPi, nu) * pow(eps, D) / tgamma(nu + 1.0);
+  if (u < 1e-4) return vol * (1.0 - u * u / (4.0 * (nu + 1.0)));
+  return pow(eps, nu) * std::cyl_bessel_j(nu, u) / pow(r, nu);
+}
+double tau_box_nd(const double* w, int D, double eps) {
+  double t = 1.0;
+  for (int k = 0; k < D; ++k) {
+    const double a = 2.0 * kPi * eps * w[k];
+    t *= fabs(a) < 1e-4 ? 2.0 * eps * (1.0 - a * a / 6.0) : sin(a) / (kPi * w[k]);
+  }
+  return t;
+}
+// P(N(0, I_D) in the radius-t ball): the chi_D CDF P(D/2, t^2/2); box: erf^D.
+double trunc_mass_nd(double t, int shape, int D) {
+  if (shape == RFD_BALL_L2) return gamma_p(0.5 * D, 0.5 * t * t);
+  return pow(erf(t / sqrt(2.0)), D);
+}
+
 rfd_status check_params(const rfd_params* p) {
   if (!p) return RFD_ERR_INVALID_ARG;
   if (p->m < 2 || p->m > rfd::kMaxM || (p->m & 1)) return RFD_ERR_INVALID_ARG;
@@ -100,7 +188,7 @@ rfd_status check_params(const rfd_params* p) {
   if (!isfinite(p->lambda)) return RFD_ERR_INVALID_ARG;
   if (p->shape != RFD_BALL_L2 && p->shape != RFD_BOX_LINF) return RFD_ERR_INVALID_ARG;
   if (p->precision != RFD_FP32 && p->precision != RFD_BF16) return RFD_ERR_INVALID_ARG;
-  if (p->reserved != 0) return RFD_ERR_INVALID_ARG;
+  if (p->dim < 0 || p->dim > rfd::kMaxDim) return RFD_ERR_INVALID_ARG;
   const bool zs = p->sigma == 0.0, zr = p->radius == 0.0;
   if (zs != zr) return RFD_ERR_INVALID_ARG;
   if (!zs && !(p->sigma > 0.0 && p->radius > 0.0 && isfinite(p->sigma) && isfinite(p->radius)))
@@ -136,7 +224,7 @@ struct Source {
 
 void free_dev(rfd::PlanDev& d) {
   if (!d.external) {
-    void* ptrs[] = {d.om, d.cvec, d.svec, d.X, d.Mraw, d.H0, d.S64, d.T64, d.G32, d.Gt16, d.G64,
+    void* ptrs[] = {d.om, d.omD, d.cvec, d.svec, d.X, d.Mraw, d.H0, d.S64, d.T64, d.G32, d.Gt16, d.G64,
                     d.phi_ws, d.sdev, d.barrier, d.flag, d.lvl, d.partials};
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
@@ -147,7 +235,7 @@ void free_dev(rfd::PlanDev& d) {
 // Takes every fixed buffer of a plan with padded size M from `src`, and with
 // an arena also the point copy and the partials for clouds of up to N_max
 // points and fields of up to d_max channels (one-shot and resident passes).
-hipError_t take_buffers(Source& src, rfd::PlanDev& d, int M, int prec, int64_t N_max, int d_max) {
+hipError_t take_buffers(Source& src, rfd::PlanDev& d, int M, int prec, int64_t N_max, int d_max, int dim) {
   const int fp = M / 2;
   const size_t mm = (size_t)M * M;
   hipError_t e = hipSuccess;
@@ -155,6 +243,7 @@ hipError_t take_buffers(Source& src, rfd::PlanDev& d, int M, int prec, int64_t N
     if (e == hipSuccess) e = r;
   };
   ok(src.get(&d.om, fp));
+  if (dim != 3) ok(src.get(&d.omD, (size_t)fp * dim));
   ok(src.get(&d.cvec, M));
   ok(src.get(&d.svec, M));
   ok(src.get(&d.Mraw, mm));
@@ -172,7 +261,7 @@ hipError_t take_buffers(Source& src, rfd::PlanDev& d, int M, int prec, int64_t N
   if (src.carve) {
     const size_t pf = std::max(rfd::request_partial_floats(M, prec, N_max, d_max, true),
                                rfd::request_partial_floats(M, prec, N_max, d_max, false));
-    ok(src.get(&d.X, (size_t)N_max * 3));
+    if (dim == 3) ok(src.get(&d.X, (size_t)N_max * 3));  // no point copy in D != 3
     ok(src.get(&d.partials, pf));
     d.Xcap = N_max;
     d.partials_cap = pf;
@@ -186,17 +275,44 @@ hipError_t take_buffers(Source& src, rfd::PlanDev& d, int M, int prec, int64_t N
 rfd_status sample_features(const rfd_params& prm, double sigma, double radius, std::vector<float>& omega,
                            std::vector<double>& w) {
   const int f = prm.m / 2;
-  omega.resize((size_t)f * 3);
+  const int D = rfd::plan_dim(prm);
+  omega.resize((size_t)f * D);
   if (prm.omega) {
-    for (int i = 0; i < 3 * f; ++i) {
+    for (int i = 0; i < D * f; ++i) {
       if (!isfinite(prm.omega[i])) return RFD_ERR_INVALID_ARG;
       omega[i] = prm.omega[i];
+    }
+  } else if (D != 3) {
+    // D normals per candidate, in stream order; squared norm summed in order
+    Gaussian g{SplitMix64{prm.seed}};
+    std::vector<double> cand(D);
+    int k = 0;
+    int64_t tries = 0;
+    while (k < f) {
+      if (++tries > kMaxCandidatesPerFrequency * f + kMaxCandidatesExtra) return RFD_ERR_INVALID_ARG;
+      for (int i = 0; i < D; ++i) cand[i] = sigma * g.next();
+      bool ok;
+      if (prm.shape == RFD_BALL_L2) {
+        double r2 = cand[0] * cand[0];
+        for (int i = 1; i < D; ++i) r2 = r2 + cand[i] * cand[i];
+        ok = r2 <= radius * radius;
+      } else {
+        double mx = 0.0;
+        for (int i = 0; i < D; ++i) mx = std::max(mx, fabs(cand[i]));
+        ok = mx <= radius;
+      }
+      if (ok) {
+        for (int i = 0; i < D; ++i) omega[(size_t)k * D + i] = (float)cand[i];
+        ++k;
+      }
     }
   } else {
     Gaussian g{SplitMix64{prm.seed}};
     const double R = radius, sig = sigma;
     int k = 0;
+    int64_t tries = 0;
     while (k < f) {
+      if (++tries > kMaxCandidatesPerFrequency * f + kMaxCandidatesExtra) return RFD_ERR_INVALID_ARG;
       const double w0 = sig * g.next();
       const double w1 = sig * g.next();
       const double w2 = sig * g.next();
@@ -212,6 +328,21 @@ rfd_status sample_features(const rfd_params& prm, double sigma, double radius, s
     }
   }
   w.resize(f);
+  if (D != 3) {
+    const double C = trunc_mass_nd(radius / sigma, prm.shape, D);
+    const double norm = pow(2.0 * kPi * sigma * sigma, -0.5 * D) / C;
+    std::vector<double> wk(D);
+    for (int k = 0; k < f; ++k) {
+      double r2 = 0.0;
+      for (int i = 0; i < D; ++i) {
+        wk[i] = omega[(size_t)k * D + i];
+        r2 += wk[i] * wk[i];
+      }
+      const double tau = prm.shape == RFD_BALL_L2 ? tau_ball_nd(wk.data(), D, prm.eps) : tau_box_nd(wk.data(), D, prm.eps);
+      w[k] = tau / (norm * exp(-r2 / (2.0 * sigma * sigma)));
+    }
+    return RFD_OK;
+  }
   const double C = trunc_mass(radius / sigma, prm.shape);
   const double norm = pow(2.0 * kPi * sigma * sigma, -1.5) / C;
   for (int k = 0; k < f; ++k) {
@@ -339,6 +470,14 @@ rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_
   if (range_exceeded(p, N)) return RFD_ERR_RANGE;
   p->N = N;
   if (N == 0) return RFD_OK;
+  if (!plan_is_3d(p)) {
+    // D-dimensional points: the Gram pass only (no point copy), then M and S
+    rfd_status s = ensure_partials(p, partial_floats_needed(p, N, 0, true), st);
+    if (s != RFD_OK) return s;
+    HIPCK(launch_gram_nd(p, X, N, st));
+    HIPCK(launch_reduce(p, N, 0, true, st));
+    return enqueue_phi1(p, st, lane);
+  }
   rfd_status s = ensure_x(p, N, st);
   if (s != RFD_OK) return s;
   s = ensure_partials(p, partial_floats_needed(p, N, 0, true), st);
@@ -350,6 +489,7 @@ rfd_status features_enqueue(rfd_plan_s* p, const float* X, int64_t N, hipStream_
 
 rfd_status integrate_enqueue(rfd_plan_s* p, const float* F, int64_t ldF, int d, float* out, int64_t ldO,
                              hipStream_t st, int first_channel_done, const float* rowscale) {
+  if (!plan_is_3d(p)) return RFD_ERR_INVALID_ARG;
   const int M = p->dev_m;
   const int64_t N = p->N;
   const int W = slice_width(M, false);
@@ -367,6 +507,7 @@ rfd_status integrate_enqueue(rfd_plan_s* p, const float* F, int64_t ldF, int d, 
 
 rfd_status oneshot_enqueue(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF, int d,
                            float* out, int64_t ldO, hipStream_t st, const PhiLane* lane) {
+  if (!plan_is_3d(p)) return RFD_ERR_INVALID_ARG;
   if (N < 0 || (N > 0 && !X)) return RFD_ERR_INVALID_ARG;
   rfd_status s = check_field_args(N, F, ldF, d, out, ldO);
   if (s != RFD_OK) return s;
@@ -453,7 +594,8 @@ rfd_status create_plan(const rfd_params* params, Source& src, int64_t N_max, int
   const int fp = M / 2;
   (void)hipGetDevice(&p->device);
   rfd::PlanDev& d = p->dev;
-  const hipError_t te = take_buffers(src, d, M, params->precision, N_max, d_max);
+  const int D = rfd::plan_dim(*params);
+  const hipError_t te = take_buffers(src, d, M, params->precision, N_max, d_max, D);
   if (te != hipSuccess) {
     free_dev(d);
     delete p;
@@ -461,9 +603,17 @@ rfd_status create_plan(const rfd_params* params, Source& src, int64_t N_max, int
   }
   bool ok = true;
   std::vector<float4> om(fp);
+  std::vector<float> omD(D == 3 ? 0 : (size_t)fp * D, 0.f);  // padding rows stay zero
   std::vector<double> cv(M, 0.0), sv(M, 1.0);
   for (int k = 0; k < fp; ++k) {
-    if (k < f) {
+    if (k < f && D != 3) {
+      om[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int i = 0; i < D; ++i) omD[(size_t)k * D + i] = p->omega[(size_t)k * D + i];
+      const double c = sqrt(fabs(p->w[k]) / f);
+      cv[k] = c;
+      cv[fp + k] = c;
+      sv[k] = sv[fp + k] = p->w[k] < 0.0 ? -1.0 : 1.0;
+    } else if (k < f) {
       om[k] = make_float4(p->omega[3 * k], p->omega[3 * k + 1], p->omega[3 * k + 2], 0.f);
       const double c = sqrt(fabs(p->w[k]) / f);
       cv[k] = c;
@@ -476,6 +626,7 @@ rfd_status create_plan(const rfd_params* params, Source& src, int64_t N_max, int
   int zero = 0;
   const std::vector<unsigned> zero_bar(rfd::kBarrierWords, 0u);
   ok = hipMemcpy(d.om, om.data(), sizeof(float4) * fp, hipMemcpyHostToDevice) == hipSuccess &&
+       (D == 3 || hipMemcpy(d.omD, omD.data(), sizeof(float) * omD.size(), hipMemcpyHostToDevice) == hipSuccess) &&
        hipMemcpy(d.cvec, cv.data(), sizeof(double) * M, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(d.svec, sv.data(), sizeof(double) * M, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(d.flag, &zero, sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
@@ -510,7 +661,8 @@ rfd_status rfd_plan_workspace_size(const rfd_params* params, int64_t N_max, int3
   Source src;
   src.carve = true;
   rfd::PlanDev d;
-  (void)take_buffers(src, d, rfd::padded_m(params->m), params->precision, N_max, d_max < 1 ? 1 : d_max);
+  (void)take_buffers(src, d, rfd::padded_m(params->m), params->precision, N_max, d_max < 1 ? 1 : d_max,
+                     rfd::plan_dim(*params));
   *bytes = src.off;
   return RFD_OK;
 }
@@ -568,7 +720,7 @@ rfd_status rfd_integrate(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, f
 
 rfd_status rfd_integrate_scaled(rfd_plan_t p, const float* F, int64_t ldF, int32_t d, float* out, int64_t ldO,
                                 const float* scale, rfd_stream_t stream) {
-  if (!p) return RFD_ERR_INVALID_ARG;
+  if (!p || !rfd::plan_is_3d(p)) return RFD_ERR_INVALID_ARG;
   if (p->N < 0) return RFD_ERR_NOT_READY;
   rfd_status s = rfd::check_field_args(p->N, F, ldF, d, out, ldO);
   if (s != RFD_OK || d == 0 || p->N == 0) return s;
@@ -579,7 +731,7 @@ rfd_status rfd_integrate_scaled(rfd_plan_t p, const float* F, int64_t ldF, int32
 
 rfd_status rfd_integrate_oneshot(rfd_plan_t p, const float* X, int64_t N, const float* F, int64_t ldF, int32_t d,
                                  float* out, int64_t ldO, rfd_stream_t stream) {
-  if (!p) return RFD_ERR_INVALID_ARG;
+  if (!p || !rfd::plan_is_3d(p)) return RFD_ERR_INVALID_ARG;
   return rfd::oneshot_enqueue(p, X, N, F, ldF, d, out, ldO, (hipStream_t)stream, nullptr);
 }
 
@@ -634,7 +786,7 @@ rfd_status rfd_plan_info(rfd_plan_t p, int64_t* N_out, int32_t* m_out, int32_t* 
 }
 
 rfd_status rfd_plan_action(rfd_plan_t p, double* H_out, double* G_out, int32_t* d_out, rfd_stream_t stream) {
-  if (!p) return RFD_ERR_INVALID_ARG;
+  if (!p || !rfd::plan_is_3d(p)) return RFD_ERR_INVALID_ARG;
   if (p->N < 0 || p->action_d <= 0) return RFD_ERR_NOT_READY;
   HIPCK(hipStreamSynchronize((hipStream_t)stream));
   const int M = p->dev_m, m = p->m, f = p->f, fp = M / 2, d = p->action_d;

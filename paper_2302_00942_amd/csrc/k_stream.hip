@@ -21,11 +21,14 @@
 namespace rfd {
 
 // ------------------------------------------------------------------ helpers
-__device__ __forceinline__ void phase_sincos(float4 w, float x, float y, float z, float& s, float& c) {
-  float th = fmaf(w.z, z, fmaf(w.y, y, w.x * x));
+// sin and cos of 2 pi th for a phase th in revolutions
+__device__ __forceinline__ void rev_sincos(float th, float& s, float& c) {
   float t = __builtin_amdgcn_fractf(th);  // exact: th - floor(th) in [0, 1)
   s = __builtin_amdgcn_sinf(t);           // sin(2 pi t)
   c = __builtin_amdgcn_cosf(t);           // cos(2 pi t)
+}
+__device__ __forceinline__ void phase_sincos(float4 w, float x, float y, float z, float& s, float& c) {
+  rev_sincos(fmaf(w.z, z, fmaf(w.y, y, w.x * x)), s, c);
 }
 
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
@@ -475,6 +478,87 @@ __global__ __launch_bounds__(256) void k_bta_batch(const CloudDesc* __restrict__
   const CloudDesc& c = cl[wi.x];
   bta_body<M, PREC, GRAM, DB>(c.X, c.Xcopy, c.N, c.om, c.F, c.ldF, c.d, wi.y, c.nparts,
                               c.partials + (size_t)wi.y * part_stride);
+}
+
+// ------------------------------------------------------------------ k_gram_nd
+// The Gram pass over points in D dimensions, D != 3 (node features as points
+// of R^D, for the kernel's spectrum): one workgroup per partial with
+// k_bta's chunk split, MFMA schedule and partial layout (its Gram pass
+// without a field: one all-zero channel block). A chunk's points and the
+// f x D frequencies sit in LDS; a feature's phase is the FP32 sum
+// w_0 x_0 + ... + w_{D-1} x_{D-1} accumulated in coordinate order with fused
+// multiply-adds (the 3-D pass's own order when D = 3).
+constexpr int kGramNdPitch = kMaxDim + 1;  // LDS row pitch of a chunk's points (floats)
+template <int M, int PREC>
+__global__ __launch_bounds__(256) void k_gram_nd(const float* __restrict__ X, int64_t N, int D,
+                                                 const float* __restrict__ omD, float* __restrict__ partials,
+                                                 size_t part_stride) {
+  using S = BtaShape<M, PREC>;
+  using E = typename S::elem;
+  constexpr int P = S::PITCH;
+  constexpr int FQ = M / 2;
+  __shared__ float oms[FQ * kMaxDim];
+  __shared__ float xs[kChunk * kGramNdPitch];
+  __shared__ __attribute__((aligned(16))) E phi[M * P];
+  __shared__ __attribute__((aligned(16))) E fs[16 * P];
+  __shared__ __attribute__((aligned(16))) E fsl[PREC ? 16 * P : 1];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int e = tid; e < FQ * D; e += 256) oms[e] = gldf(omD + e);
+  for (int e = tid; e < 16 * P; e += 256) fs[e] = (E)0.f;
+  if constexpr (PREC)
+    for (int e = tid; e < 16 * P; e += 256) fsl[e] = (E)0.f;
+  f32x16 acc[S::SLOTS];
+  f32x4 hacc[S::RPW][1];
+#pragma unroll
+  for (int i = 0; i < S::SLOTS; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+#pragma unroll
+  for (int i = 0; i < S::RPW; ++i) hacc[i][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int b = blockIdx.x, nparts = gridDim.x;
+  const int64_t nchunks = (N + kChunk - 1) / kChunk;
+  const int64_t c0 = ((int64_t)b * nchunks) / nparts;
+  const int64_t c1 = ((int64_t)(b + 1) * nchunks) / nparts;
+  const int pp = tid & 31;  // point pair within the chunk
+  const int kq = tid >> 5;  // frequency phase 0..7
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    const int64_t base = ch * kChunk;
+    __syncthreads();  // the previous chunk's reads of xs and phi are done
+    for (int e = tid; e < kChunk * D; e += 256) {
+      const int q = e / D, c = e - q * D;
+      xs[q * kGramNdPitch + c] = base + q < N ? gldf(X + (base + q) * D + c) : 0.f;
+    }
+    __syncthreads();
+    const bool va = base + 2 * pp < N, vb = base + 2 * pp + 1 < N;
+    const float* xa = xs + (2 * pp) * kGramNdPitch;
+    const float* xb = xa + kGramNdPitch;
+    for (int k = kq; k < FQ; k += 8) {
+      const float* w = oms + k * D;
+      float tha = w[0] * xa[0], thb = w[0] * xb[0];
+      for (int c = 1; c < D; ++c) {
+        tha = fmaf(w[c], xa[c], tha);
+        thb = fmaf(w[c], xb[c], thb);
+      }
+      float sa, ca, sb, cb;
+      rev_sincos(tha, sa, ca);
+      rev_sincos(thb, sb, cb);
+      if (!va) sa = ca = 0.f;  // points past N: zero features
+      if (!vb) sb = cb = 0.f;
+      if constexpr (PREC) {
+        *(unsigned*)(phi + (2 * k) * P + 2 * pp) = pack_bf16x2(ca, cb);
+        *(unsigned*)(phi + (2 * k + 1) * P + 2 * pp) = pack_bf16x2(sa, sb);
+      } else {
+        phi[(2 * k) * P + 2 * pp] = ca;
+        phi[(2 * k) * P + 2 * pp + 1] = cb;
+        phi[(2 * k + 1) * P + 2 * pp] = sa;
+        phi[(2 * k + 1) * P + 2 * pp + 1] = sb;
+      }
+    }
+    __syncthreads();
+    bta_mma<M, PREC, true, 1>(phi, fs, fsl, acc, hacc, lane, wave);
+  }
+  bta_store<M, PREC, true, 1>(partials + (size_t)b * part_stride, acc, hacc, lane, wave);
 }
 
 // ------------------------------------------------------------------ k_reduce
@@ -1132,6 +1216,28 @@ hipError_t launch_bta(rfd_plan_s* p, const float* X, int64_t N, const float* F, 
   RFD_BTA(256, 0)
   RFD_BTA(256, 1)
 #undef RFD_BTA
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gram_nd(rfd_plan_s* p, const float* X, int64_t N, hipStream_t st) {
+  const int M = p->dev_m, prec = p->params.precision, D = plan_dim(p->params);
+  if (D < 1 || D > kMaxDim || !p->dev.omD) return hipErrorInvalidValue;
+  const int nparts = bta_partials(N, M, 0, true, prec);
+  const size_t stride = bta_partial_floats(M, 0, true);
+  ProfileScope prof(kKGram, st);
+#define RFD_GND(MM, PP)                                                                                    \
+  if (M == MM && prec == PP) {                                                                             \
+    hipLaunchKernelGGL((k_gram_nd<MM, PP>), dim3(nparts), dim3(256), 0, st, X, N, D, p->dev.omD,          \
+                       p->dev.partials, stride);                                                           \
+    return hipGetLastError();                                                                              \
+  }
+  RFD_GND(64, 0)
+  RFD_GND(64, 1)
+  RFD_GND(128, 0)
+  RFD_GND(128, 1)
+  RFD_GND(256, 0)
+  RFD_GND(256, 1)
+#undef RFD_GND
   return hipErrorInvalidValue;
 }
 

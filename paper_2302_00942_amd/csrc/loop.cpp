@@ -69,7 +69,7 @@ rfd_status rfd_loop_create(const rfd_plan_t* plans, const float* const* scales, 
     return RFD_ERR_INVALID_ARG;
   const int64_t N = plans[0] ? plans[0]->N : -1;
   for (int i = 0; i < nplans; ++i) {
-    if (!plans[i]) return RFD_ERR_INVALID_ARG;
+    if (!plans[i] || !rfd::plan_is_3d(plans[i])) return RFD_ERR_INVALID_ARG;
     if (plans[i]->N < 0) return RFD_ERR_NOT_READY;
     if (plans[i]->N != N) return RFD_ERR_INVALID_ARG;  // one vector block shared by every operator
   }

@@ -90,7 +90,7 @@ extern "C" {
 
 rfd_status rfd_integrate_oneshot_noalloc(rfd_plan_t p, const float* X, int64_t N, const float* F, int64_t ldF,
                                          int32_t d, float* out, int64_t ldO, rfd_stream_t stream) {
-  if (!p) return RFD_ERR_INVALID_ARG;
+  if (!p || !rfd::plan_is_3d(p)) return RFD_ERR_INVALID_ARG;
   if (N < 0 || (N > 0 && !X)) return RFD_ERR_INVALID_ARG;
   rfd_status s = rfd::check_field_args(N, F, ldF, d, out, ldO);
   if (s != RFD_OK) return s;

@@ -17,6 +17,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMaxM = 256;        // largest supported number of feature columns
+constexpr int kMaxDim = 64;       // largest coordinate dimension of the points
 constexpr int kMaxD = 1024;       // largest field width per call
 constexpr int kChunk = 64;        // points per chunk of the split-N passes
 constexpr int kDBlock = 16;       // channels per MFMA block of the field
@@ -58,6 +59,7 @@ struct CloudDesc {
 // Scratch and resident buffers of one plan.
 struct PlanDev {
   float4* om = nullptr;       // f x float4
+  float* omD = nullptr;       // f x D frequencies of a plan of dimension D != 3 (zero rows past f)
   double* cvec = nullptr;     // m: c_j in canonical order
   double* svec = nullptr;     // m: sign_j in canonical order
   float* X = nullptr;         // copy of the cloud
@@ -85,7 +87,7 @@ struct rfd_plan_s {
   rfd_params params{};
   int m = 0, f = 0;
   double sigma = 0, radius = 0;
-  std::vector<float> omega;   // f x 3
+  std::vector<float> omega;   // f x D
   std::vector<double> w;      // f
   double wsum_abs = 0;        // sum |w_k|
   bool any_growth = false;    // lambda * w_k > 0 for some k
@@ -98,6 +100,11 @@ struct rfd_plan_s {
 };
 
 namespace rfd {
+
+// Coordinate dimension of a plan's points (params.dim, 0 meaning 3).
+inline int plan_dim(const rfd_params& p) { return p.dim == 0 ? 3 : p.dim; }
+// Entry points that apply the kernel to a field run on 3-D points only.
+inline bool plan_is_3d(const rfd_plan_s* p) { return plan_dim(p->params) == 3; }
 
 // Kernel ids of the optional per-launch timing (profile.cpp).
 enum KernelId {
@@ -126,6 +133,9 @@ const char* kernel_name(int id);
 hipError_t launch_bta(rfd_plan_s* p, const float* X, int64_t N, const float* F, int64_t ldF,
                       int d, bool gram, hipStream_t st, float* xcopy = nullptr);
 hipError_t launch_reduce(rfd_plan_s* p, int64_t N, int d, bool gram, hipStream_t st);
+// The Gram pass of a plan of dimension D != 3 over N x D points (partials as
+// launch_bta's Gram pass without a field, for launch_reduce(p, N, 0, true)).
+hipError_t launch_gram_nd(rfd_plan_s* p, const float* X, int64_t N, hipStream_t st);
 hipError_t launch_phi1(rfd_plan_s* p, hipStream_t st);
 hipError_t launch_phi1_batch(rfd_plan_s** plans, int n, void* dev_args, hipStream_t st);
 // G' of one block of d <= phi1_apply_max_width() channels straight from H0,

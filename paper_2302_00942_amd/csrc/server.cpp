@@ -328,7 +328,7 @@ rfd_status rfd_submit(rfd_server_t S, const rfd_request* r, uint64_t* ticket) {
   *ticket = 0;
   rfd_status s = rfd::check_params(&r->params);
   if (s != RFD_OK) return s;
-  if (r->params.omega || r->N < 0 || (r->N > 0 && !r->X)) return RFD_ERR_INVALID_ARG;
+  if (r->params.omega || rfd::plan_dim(r->params) != 3 || r->N < 0 || (r->N > 0 && !r->X)) return RFD_ERR_INVALID_ARG;
   s = rfd::check_field_args(r->N, r->F, r->ldF, r->d, r->out, r->ldO);
   if (s != RFD_OK) return s;
   const int M = rfd::padded_m(r->params.m);

@@ -29,7 +29,7 @@ class RfdError(RuntimeError):
 
 
 class Params(C.Structure):
-    _fields_ = [("m", C.c_int32), ("shape", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("m", C.c_int32), ("shape", C.c_int32), ("precision", C.c_int32), ("dim", C.c_int32),
                 ("eps", C.c_double), ("lam", C.c_double), ("sigma", C.c_double), ("radius", C.c_double),
                 ("seed", C.c_uint64), ("omega", C.POINTER(C.c_float))]
 
@@ -126,9 +126,9 @@ def _check(s: int, what: str) -> None:
 
 
 def make_params(m: int, eps: float, lam: float, seed: int = 0, shape="ball", precision="fp32",
-                sigma: float = 0.0, radius: float = 0.0, omega: Optional[np.ndarray] = None):
+                sigma: float = 0.0, radius: float = 0.0, omega: Optional[np.ndarray] = None, dim: int = 3):
     p = Params()
-    p.m, p.shape, p.precision, p.reserved = int(m), _SHAPE[shape], _PREC[precision], 0
+    p.m, p.shape, p.precision, p.dim = int(m), _SHAPE[shape], _PREC[precision], int(dim)
     p.eps, p.lam, p.sigma, p.radius, p.seed = float(eps), float(lam), float(sigma), float(radius), int(seed)
     keep = None
     if omega is not None:
@@ -140,19 +140,20 @@ def make_params(m: int, eps: float, lam: float, seed: int = 0, shape="ball", pre
 
 
 def workspace_size(m: int, eps: float, N_max: int, d_max: int, seed: int = 0, shape="ball", precision="fp32",
-                   sigma: float = 0.0, radius: float = 0.0) -> int:
+                   sigma: float = 0.0, radius: float = 0.0, dim: int = 3) -> int:
     """Device bytes of a plan in a caller's arena (rfd_plan_workspace_size; host only)."""
-    p, _ = make_params(m, eps, 0.0, seed, shape, precision, sigma, radius)
+    p, _ = make_params(m, eps, 0.0, seed, shape, precision, sigma, radius, dim=dim)
     n = C.c_size_t()
     _check(lib().rfd_plan_workspace_size(C.byref(p), int(N_max), int(d_max), C.byref(n)), "rfd_plan_workspace_size")
     return int(n.value)
 
 
-def frequencies(m: int, eps: float, seed: int = 0, shape="ball", sigma: float = 0.0, radius: float = 0.0):
-    """(omega f x 3 float32, w f float64) as the library samples them (host only)."""
-    p, _ = make_params(m, eps, 0.0, seed, shape, "fp32", sigma, radius)
+def frequencies(m: int, eps: float, seed: int = 0, shape="ball", sigma: float = 0.0, radius: float = 0.0,
+                dim: int = 3):
+    """(omega f x D float32, w f float64) as the library samples them (host only)."""
+    p, _ = make_params(m, eps, 0.0, seed, shape, "fp32", sigma, radius, dim=dim)
     f = m // 2
-    om = np.zeros((f, 3), dtype=np.float32)
+    om = np.zeros((f, dim if dim else 3), dtype=np.float32)
     w = np.zeros(f, dtype=np.float64)
     _check(lib().rfd_params_frequencies(C.byref(p), om.ctypes.data, w.ctypes.data), "rfd_params_frequencies")
     return om, w
@@ -179,12 +180,13 @@ class Plan:
     """An RFD plan: frequencies, weights and (after features) the m x m core."""
 
     def __init__(self, m: int, eps: float, lam: float, seed: int = 0, shape="ball", precision="fp32",
-                 sigma: float = 0.0, radius: float = 0.0, omega: Optional[np.ndarray] = None):
-        p, keep = make_params(m, eps, lam, seed, shape, precision, sigma, radius, omega)
+                 sigma: float = 0.0, radius: float = 0.0, omega: Optional[np.ndarray] = None, dim: int = 3):
+        p, keep = make_params(m, eps, lam, seed, shape, precision, sigma, radius, omega, dim)
         h = C.c_void_p()
         _check(lib().rfd_plan_create(C.byref(p), C.byref(h)), "rfd_plan_create")
         self._h = h
         self.m, self.eps, self.lam, self.seed = m, eps, lam, seed
+        self.dim = int(dim) if dim else 3
         self.precision = _PREC[precision]
 
     @classmethod
@@ -204,6 +206,7 @@ class Plan:
         self._h = h
         self._arena = arena
         self.m, self.eps, self.lam, self.seed = m, eps, lam, seed
+        self.dim = 3
         self.precision = _PREC[precision]
         return self
 
@@ -213,7 +216,7 @@ class Plan:
 
     def export(self):
         f = self.m // 2
-        om = np.zeros((f, 3), dtype=np.float32)
+        om = np.zeros((f, self.dim), dtype=np.float32)
         w = np.zeros(f, dtype=np.float64)
         _check(lib().rfd_plan_export(self._h, om.ctypes.data, w.ctypes.data), "rfd_plan_export")
         return om, w
@@ -221,9 +224,9 @@ class Plan:
     def features(self, X, stream=None, sync: bool = False) -> None:
         """rfd_features (async), or with sync=True rfd_features_sync: waits and
         raises on what the device found (non-finite points or core)."""
-        X = _dev_f32(X, "X", 3)
-        if X.stride(0) != 3:
-            raise ValueError("X must be contiguous N x 3")
+        X = _dev_f32(X, "X", self.dim)
+        if X.stride(0) != self.dim:
+            raise ValueError(f"X must be contiguous N x {self.dim}")
         fn = lib().rfd_features_sync if sync else lib().rfd_features
         _check(fn(self._h, X.data_ptr(), X.shape[0], _stream_handle(stream)),
                "rfd_features_sync" if sync else "rfd_features")

@@ -256,3 +256,24 @@ def barycenter_problem(n: int, surface_kind: str = "sphere", seed: int = 0, k: i
         b = b + background * b.max()
         cols.append(b / (a @ b))
     return BaryProblem(X=X, a=a.astype(np.float32), mus=np.stack(cols, axis=1).astype(np.float32))
+
+
+# ------------------------------------------------------------------ node features in D dimensions
+def node_features(n: int, dim: int, seed: int, clusters: int = 4, spread: float = 0.15) -> np.ndarray:
+    """n points of R^dim standing in for a graph's node-feature vectors (the
+    graph-classification appendix treats them as a point set): a few cluster
+    centres uniform in the unit cube (node kinds) and Gaussian spread around
+    them, float32 n x dim."""
+    g = _rng(seed)
+    centres = g.uniform(0.0, 1.0, (clusters, dim))
+    which = g.integers(0, clusters, n)
+    return (centres[which] + spread * g.normal(size=(n, dim))).astype(np.float32)
+
+
+def graph_batch(count: int = 1024, dim: int = 16, seed: int = 0, lo: int = 10, hi: int = 300):
+    """Synthetic stand-in for a graph-classification set: `count` graphs with
+    node counts log-uniform in [lo, hi] (the appendix's datasets average 14 to
+    284 nodes) and node features in R^dim, each a node_features cloud."""
+    g = _rng(seed)
+    sizes = np.floor(np.exp(g.uniform(math.log(lo), math.log(hi + 1), count))).astype(np.int64)
+    return [node_features(int(n), dim, seed * 100003 + i) for i, n in enumerate(sizes)]

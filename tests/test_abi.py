@@ -41,6 +41,48 @@ def test_custom_sigma_radius_signed_weights_match_oracle():
     assert np.allclose(w, w_ref, rtol=1e-11, atol=1e-14 * np.abs(w_ref).max())
 
 
+@pytest.mark.parametrize("D", [1, 2, 4, 5, 8, 17, 64])
+@pytest.mark.parametrize("shape", ["ball", "box"])
+def test_sampler_in_d_dimensions_matches_oracle(D, shape):
+    """Points in D dimensions: the host sampler draws the oracle's frequencies
+    bit for bit (D normals per candidate, the squared norm summed in order, its
+    own first Bessel zero for the preset radius) and its weights (its own
+    Bessel function and incomplete gamma) agree to rounding."""
+    sh = o.BALL_L2 if shape == "ball" else o.BOX_LINF
+    om, w = rfd.frequencies(96, 0.2, 21, shape=shape, dim=D)
+    om_ref, w_ref = o.frequencies_and_weights(96, 0.2, 21, sh, dim=D)
+    assert om.shape == (48, D) and np.array_equal(om, om_ref)
+    assert np.all(w_ref > 0)  # the preset keeps every weight positive
+    assert np.allclose(w, w_ref, rtol=1e-11, atol=0)
+    # explicit law reaching past the main lobe (signed weights), scaled with D
+    R = 2.5 * o.preset(0.2, sh, dim=D)[1]
+    sig = R / np.sqrt(D + 6.0)
+    om, w = rfd.frequencies(64, 0.2, 4, shape=shape, sigma=sig, radius=R, dim=D)
+    om_ref, w_ref = o.frequencies_and_weights(64, 0.2, 4, sh, sigma=sig, radius=R, dim=D)
+    assert np.array_equal(om, om_ref)
+    assert np.allclose(w, w_ref, rtol=1e-9, atol=1e-12 * np.abs(w_ref).max())
+
+
+def test_sampler_refuses_a_law_that_accepts_nothing():
+    """A truncation that keeps almost no mass (64-D Gaussian cut at 3 sigma):
+    both samplers give up instead of looping."""
+    p, _ = rfd.make_params(32, 0.2, -0.5, 1, sigma=4.0, radius=12.0, dim=64)
+    om = np.zeros((16, 64), dtype=np.float32)
+    w = np.zeros(16)
+    assert rfd.lib().rfd_params_frequencies(C.byref(p), om.ctypes.data, w.ctypes.data) == rfd.INVALID_ARG
+
+
+def test_dim_zero_means_three_and_bad_dims_are_rejected():
+    om0, w0 = rfd.frequencies(32, 0.1, 2, dim=0)
+    om3, w3 = rfd.frequencies(32, 0.1, 2, dim=3)
+    assert np.array_equal(om0, om3) and np.array_equal(w0, w3)
+    for D in (-1, 65, 1000):
+        p, _ = rfd.make_params(32, 0.1, -0.5, 2, dim=D)
+        om = np.zeros((16, 1000), dtype=np.float32)
+        w = np.zeros(16)
+        assert rfd.lib().rfd_params_frequencies(C.byref(p), om.ctypes.data, w.ctypes.data) == rfd.INVALID_ARG
+
+
 @pytest.mark.parametrize("kw", [dict(m=63), dict(m=0), dict(m=258), dict(eps=0.0), dict(eps=-1.0),
                                 dict(lam=float("nan")), dict(sigma=1.0), dict(radius=2.0), dict(shape=5),
                                 dict(precision=7)])

@@ -233,10 +233,11 @@ def test_pdf_normalisation_nd():
 def test_nd_main_lobe_preset(D):
     """The preset ball radius is the transform's first zero, and every
     sampled weight is positive (the main lobe only); the box radius is
-    1/(2 eps) in any dimension."""
+    1/(2 eps) in any dimension; sigma = R / sqrt(D + 6), which is R/3 at
+    D = 3 and keeps the D-dimensional Gaussian's bulk inside R."""
     eps = 0.1
     sig, R = o.preset(eps, dim=D)
-    assert sig == pytest.approx(R / 3)
+    assert sig == pytest.approx(R / math.sqrt(D + 6))  # R/3 at D = 3
     e1 = np.zeros((1, D))
     e1[0, 0] = R
     assert abs(o.tau_ball_nd(e1, eps)[0]) < 1e-12 * o.tau_ball_nd(np.zeros((1, D)), eps)[0]
