@@ -204,6 +204,48 @@ def replay_ms(launch, reps: int, torch, st):
     return a.elapsed_time(b) / reps
 
 
+def _oracle_threads():
+    from threadpoolctl import threadpool_info
+    return max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+
+
+def bench_plain(torch, rfd, wl, reps: int):
+    """The small configuration (2,000 points on the unit sphere, eps = 0.1,
+    lambda = -0.5, m = 64, d = 3): the FP32 one-shot on the GPU, the oracle
+    and the dense brute force exp(lambda W_eps) F on the host, and the errors
+    of both low-rank results against the brute force and of the GPU against
+    the oracle."""
+    import scipy.linalg as sl
+    from oracle import rfd_oracle as o
+    c = wl.plain_sphere()
+    X = torch.from_numpy(c.X).cuda()
+    F = torch.from_numpy(c.F).cuda()
+    res = {}
+    for prec in ("fp32", "bf16"):
+        plan = rfd.Plan(c.m, c.eps, c.lam, c.seed, precision=prec)
+        out = torch.empty_like(F)
+        st = torch.cuda.Stream()
+        ms = replay_ms(lambda s_: plan.oneshot(X, F, out=out, stream=s_), reps, torch, st)
+        res[prec] = {"ms": round(ms, 4), "value": round(c.n * c.d / (ms * 1e-3), 1), "out": out.cpu().numpy()}
+        plan.close()
+    t0 = time.perf_counter()
+    ref = o.rfd_integrate(c.X, c.F, c.eps, c.lam, c.m, c.seed)
+    t_or = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dense = sl.expm(c.lam * o.dense_adjacency(c.X, c.eps)) @ c.F.astype(np.float64)
+    t_dense = time.perf_counter() - t0
+    for prec in res:
+        g = res[prec].pop("out")
+        res[prec]["rel_err_vs_oracle"] = float(f"{o.relf(g, ref):.3e}")
+        res[prec]["rel_err_vs_dense"] = float(f"{o.relf(g, dense):.3e}")
+    return {"workload": f"sphere N={c.n} eps={c.eps} lambda={c.lam} m={c.m} d={c.d} one-shot",
+            "unit": "points*channels/s", **res,
+            "cpu_oracle": {"ms": round(t_or * 1e3, 2), "value": round(c.n * c.d / t_or, 1), "kind": "oracle",
+                           "cores": _oracle_threads()},
+            "cpu_dense_brute_force": {"ms": round(t_dense * 1e3, 2), "rel_err_lowrank_vs_dense":
+                                      float(f"{o.relf(ref, dense):.3e}")}}
+
+
 def bench_batch(torch, rfd, wl, reps: int):
     """The 512 uneven clouds (N log-uniform in [1000, 65536], m = 128, d = 3,
     BF16) as one batch replayed from its hipGraph, against the plain path: one
@@ -234,6 +276,17 @@ def bench_batch(torch, rfd, wl, reps: int):
         batch.close()
         for p in plans:
             p.close()
+    # the oracle on a stated subset of the batch (its first 8 clouds), scaled to points*channels/s
+    from oracle import rfd_oracle as o
+    sub = clouds[:8]
+    t0 = time.perf_counter()
+    for c in sub:
+        o.rfd_integrate(c.X, c.F, c.eps, c.lam, c.m, c.seed)
+    t_or = time.perf_counter() - t0
+    pc_sub = sum(c.n * c.d for c in sub)
+    res["cpu_oracle"] = {"value": round(pc_sub / t_or, 1), "unit": "points*channels/s", "kind": "oracle",
+                         "cores": _oracle_threads(), "s": round(t_or, 3),
+                         "sample": "clouds 0-7 of the batch (sum N = %d), one one-shot each" % sum(c.n for c in sub)}
     return {"workload": "512 clouds, N log-uniform in [1000, 65536] (sum %d), sphere/torus/ellipsoid, "
                         "eps=0.05, lambda=-0.5, m=128, d=3; one-shot, graph replay" % sum(c.n for c in clouds),
             "unit": "points*channels/s", **res}
@@ -268,6 +321,16 @@ def bench_loop(torch, rfd, wl, reps: int):
             loop.close()
             for p in plans:
                 p.close()
+        if d == 32:  # the oracle's loop, two iterations (its operators formed once, outside the timing)
+            from oracle import rfd_oracle as o
+            fw = [o.frequencies_and_weights(c.m, c.eps, c.seed) for c in clouds]
+            t0 = time.perf_counter()
+            o.repeated_apply([c.X for c in clouds], clouds[0].F, [s0, s1], [c.lam for c in clouds], 2,
+                             [a for a, _ in fw], [b for _, b in fw])
+            t_or = time.perf_counter() - t0
+            out["cpu_oracle_d32"] = {"s": round(t_or, 3), "kind": "oracle", "cores": _oracle_threads(),
+                                     "sample": "2 iterations (operators built inside, so an upper bound per "
+                                               "iteration)", "value": round(n * d * 2 / t_or, 1)}
     return {"workload": "sphere + deformed torus, N=100000 each, eps=0.05, lambda=-0.5, m=128, "
                         "100 alternating scaled applications in one hipGraph",
             "unit": "points*channels/s", **out}
@@ -703,6 +766,7 @@ def main() -> int:
     line["roofline_all"] = {k: roofline(k, v[0] / v[1], N, m, d, res["bf16"]["s"], nparts, "bf16", workload, s13)
                             for k, v in kern.items() if k in KERNEL_SOURCES}
     if not args.no_extras:
+        line["plain_small"] = bench_plain(torch, rfd, wl, max(5, args.steps))
         line["batched"] = bench_batch(torch, rfd, wl, max(5, args.steps))
         line["repeated_application"] = bench_loop(torch, rfd, wl, max(5, args.steps // 2))
         line["resident_wide_fields"] = bench_resident_wide(torch, rfd, wl, max(5, args.steps))

@@ -14,7 +14,10 @@
 // allocation) or a new one is created, and the one-shot path runs. Work on one
 // plan stays on one stream, so requests that share a plan are ordered. The
 // phi_1 launches (cooperative grids) of all requests go through one lane
-// stream, so two such grids never compete for residency.
+// stream, so two such grids never compete for residency. The request streams
+// and the lane together stay within the four hardware queues a process gets
+// by default: more streams than queues share queues and serialise behind
+// each other's barriers.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -28,7 +31,7 @@
 namespace {
 
 constexpr int kMaxInflight = 64;
-constexpr int kMaxStreams = 8;
+constexpr int kMaxStreams = 3;  // request streams; with the phi_1 lane, four hardware queues
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -36,7 +39,7 @@ double now_s() {
 
 bool same_params(const rfd_params& a, const rfd_params& b) {
   return a.m == b.m && a.shape == b.shape && a.precision == b.precision && a.eps == b.eps && a.lambda == b.lambda &&
-         a.sigma == b.sigma && a.radius == b.radius && a.seed == b.seed;
+         a.sigma == b.sigma && a.radius == b.radius && a.seed == b.seed && rfd::plan_dim(a) == rfd::plan_dim(b);
 }
 
 struct Entry {
