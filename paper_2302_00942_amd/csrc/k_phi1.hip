@@ -52,6 +52,26 @@ struct ApplyArgs {
 };
 constexpr int kThinWidth = 32;
 
+// Global-typed accesses. The per-cloud kernels read their pointers from
+// argument records in device memory, which the compiler cannot place in an
+// address space, so plain accesses become flat ones; flat accesses also
+// count against the LDS wait counter, so every LDS wait before a barrier
+// would drain the loads in flight as well. All these buffers are global.
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) f64x2_t gf64x2;
+__device__ __forceinline__ double gld(const double* p) { return *(const gdouble*)p; }
+__device__ __forceinline__ double2 gld2(const double* p) {
+  const f64x2_t v = *(const gf64x2*)p;
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(double* p, double v) { *(gdouble*)p = v; }
+// A relaxed agent-scope store (global_store ... sc1 on gfx950): coherent at
+// device scope once acknowledged, with no L2 write-back.
+__device__ __forceinline__ void gst_agent(double* p, double v) {
+  __hip_atomic_store((gdouble*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // One workgroup per cloud: the phases' global stores are waited for before
 // the workgroup barrier, so every wave's next loads see them (the barrier
 // alone does not wait for outstanding stores).
@@ -60,6 +80,8 @@ struct WgBarrier {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
   }
+  // a phase output (read by the same workgroup after sync)
+  __device__ __forceinline__ void st(double* p, double v) const { gst(p, v); }
   __device__ __forceinline__ void finish() {}
 };
 
@@ -67,14 +89,16 @@ struct WgBarrier {
 // counter of their group of kBarGroup (128-byte apart lines); the last arrival
 // of a group (seen from the returned count) bumps the top counter, which every
 // workgroup polls. Counters only grow: round r waits for r * groups top
-// arrivals. Ordering comes from fences around relaxed counter operations:
-// each arrival is preceded by an agent-scope release fence; the last arrival
-// of a group takes an acquire-release fence before it bumps the top counter
-// (so the group's writes reach every poller through it); the poll is relaxed
-// and followed by one acquire fence. On gfx950 that is one L2 write-back
-// before the arrival and one invalidate after the wait. Every wave also waits
-// for its own stores before the workgroup arrives and drops its L1 lines after
-// the wait. The wait is bounded: on timeout the flag gets bit 2 and the
+// arrivals. Visibility of the phase outputs: every one of them is written
+// with a relaxed agent-scope store (`st`, global_store ... sc1), which is
+// coherent at device scope once acknowledged, and every wave waits for its
+// own stores before the workgroup arrives, so an arrival is counted only
+// after its workgroup's outputs are visible to every XCD: no L2 write-back
+// fence is needed (with plain stores, the agent-scope release fence's L2
+// write-back at every arrival cost about 31 us of a 180 us call at m = 256).
+// The poll is relaxed and followed by an agent-scope acquire fence (the L2
+// and L1 invalidates that drop lines older than the phase), and every wave
+// drops its L1 lines after the wait. The wait is bounded: on timeout the flag gets bit 2 and the
 // workgroup proceeds, so every wave always exits. The counters start at zero
 // (the plan zeroes them when it is created) and every launch leaves them at
 // zero: after its last wait each workgroup arrives on an exit counter (word 1),
@@ -99,13 +123,9 @@ struct GridBarrier {
       const unsigned g = blockIdx.x / kBarGroup;
       const unsigned groups = (nblocks + kBarGroup - 1) / kBarGroup;
       const unsigned gsz = (g + 1 < groups) ? kBarGroup : nblocks - g * kBarGroup;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned old =
           __hip_atomic_fetch_add(ctr + kBarStride * (1 + g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (old + 1 == round * gsz) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      if (old + 1 == round * gsz) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const unsigned target = round * groups;
       unsigned spins = 0;
       while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -120,6 +140,8 @@ struct GridBarrier {
     __syncthreads();
     asm volatile("buffer_inv sc0" ::: "memory");  // drop this CU's L1 lines
   }
+  // a phase output read by other workgroups after sync
+  __device__ __forceinline__ void st(double* p, double v) const { gst_agent(p, v); }
   // Called once by every workgroup after its last sync.
   __device__ __forceinline__ void finish() {
     if (threadIdx.x != 0) return;
@@ -133,20 +155,7 @@ struct GridBarrier {
   }
 };
 
-// Global-typed accesses. The per-cloud kernels read their pointers from
-// argument records in device memory, which the compiler cannot place in an
-// address space, so plain accesses become flat ones; flat accesses also
-// count against the LDS wait counter, so every LDS wait before a barrier
-// would drain the loads in flight as well. All these buffers are global.
-typedef double f64x2_t __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(1))) double gdouble;
-typedef __attribute__((address_space(1))) f64x2_t gf64x2;
-__device__ __forceinline__ double gld(const double* p) { return *(const gdouble*)p; }
-__device__ __forceinline__ double2 gld2(const double* p) {
-  const f64x2_t v = *(const gf64x2*)p;
-  return make_double2(v.x, v.y);
-}
-__device__ __forceinline__ void gst(double* p, double v) { *(gdouble*)p = v; }
+
 
 // ------------------------------------------------------------------ GEMM tiles
 // One workgroup computes the 32 x 32 tile (ti, tj) of C1 = alpha1 A1 B1 and,
@@ -703,8 +712,8 @@ constexpr double kTheta23 = 2.014710780944616;
 // before its stores (a store in between would keep the next column's loads
 // from being issued early).
 constexpr int kEwGroup = 8;
-template <int m>
-__device__ __forceinline__ void column_abs_sums(const Phi1Args& a, int worker, int nw, double* colsum) {
+template <int m, class BAR>
+__device__ __forceinline__ void column_abs_sums(const Phi1Args& a, int worker, int nw, double* colsum, BAR& bar) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   for (int j0 = worker * 4 + w; j0 < m; j0 += kEwGroup * nw * 4) {
     double v[kEwGroup];
@@ -722,7 +731,7 @@ __device__ __forceinline__ void column_abs_sums(const Phi1Args& a, int worker, i
     for (int u = 0; u < kEwGroup; ++u) {
       for (int o = 32; o >= 1; o >>= 1) v[u] += __shfl_xor(v[u], o);
       const int j = j0 + u * nw * 4;
-      if (l == 0 && j < m) colsum[j] = fabs(a.lambda) * a.cvec[j] * v[u];
+      if (l == 0 && j < m) bar.st(colsum + j, fabs(a.lambda) * a.cvec[j] * v[u]);
     }
   }
 }
@@ -810,8 +819,8 @@ __device__ __forceinline__ void horner_phase(const TaylorWs& w, int worker, int 
                          [&](int i, int j, double v0, double v1, const Side<3>& sd) {
                            const size_t e = (size_t)i * m + j;
                            const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * w.sc1, y2 = sd.v[1], y3 = sd.v[2];
-                           gst(w.R[0][dst] + e, v0 + coef_block<J, 0>(id, y, y2, y3));
-                           gst(w.R[1][dst] + e, v1 + coef_block<J, 1>(id, y, y2, y3));
+                           bar.st(w.R[0][dst] + e, v0 + coef_block<J, 0>(id, y, y2, y3));
+                           bar.st(w.R[1][dst] + e, v1 + coef_block<J, 1>(id, y, y2, y3));
                          },
                          w.X0, w.Y2, w.Y3),
         NoPart{}, true, lds);
@@ -841,8 +850,8 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
             const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
             return a.lambda * a.cvec[i] * a.Mraw[e] * a.cvec[j] * a.svec[j];
           },
-          [&](size_t e, double v) { X0[e] = v; });
-  column_abs_sums<m>(a, worker, nw, colsum);
+          [&](size_t e, double v) { bar.st(X0 + e, v); });
+  column_abs_sums<m>(a, worker, nw, colsum, bar);
   bar.sync();
 
   // ---- s from the 1-norm (every worker, same value)
@@ -856,7 +865,7 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
     gemm_pair<m, KB, ALL, kShareA>(X0, X0,
                                    part<1, 0, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, X0, X0, sc2, 0.0,
                                                     [&](int i, int j, double v, double, const Side<0>&) {
-                                                      gst(Y2 + (size_t)i * m + j, v);
+                                                      bar.st(Y2 + (size_t)i * m + j, v);
                                                     }),
                                    NoPart{}, true, lds);
   }
@@ -870,10 +879,10 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
                          [&](int i, int j, double y3, double y4, const Side<2>& sd) {
                            const size_t e = (size_t)i * m + j;
                            const double id = i == j ? 1.0 : 0.0, y = sd.v[0] * sc1, y2 = sd.v[1];
-                           gst(Y3 + e, y3);
-                           gst(Y4 + e, y4);
-                           gst(R01 + e, coef_block<5, 0>(id, y, y2, y3));
-                           gst(R11 + e, coef_block<5, 1>(id, y, y2, y3));
+                           bar.st(Y3 + e, y3);
+                           bar.st(Y4 + e, y4);
+                           bar.st(R01 + e, coef_block<5, 0>(id, y, y2, y3));
+                           bar.st(R11 + e, coef_block<5, 1>(id, y, y2, y3));
                          },
                          X0, Y2),
         NoPart{}, true, lds);
@@ -898,8 +907,8 @@ __device__ __forceinline__ void phi1_body(const Phi1Args& a, int worker, int nw,
                                      part<2, 1, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, Ec, Ec, 1.0, 0.5,
                                                       [&](int i, int j, double e2, double pe, const Side<1>& sd) {
                                                         const size_t e = (size_t)i * m + j;
-                                                        gst(En + e, e2);
-                                                        gst(Pn + e, pe + 0.5 * sd.v[0]);
+                                                        bar.st(En + e, e2);
+                                                        bar.st(Pn + e, pe + 0.5 * sd.v[0]);
                                                       },
                                                       Pc),
                                      NoPart{}, true, lds);
@@ -951,13 +960,13 @@ __device__ __forceinline__ void apply_horner(const TaylorWs& w, double* const (&
         part<1, 3, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, E[src], E[src], 1.0, 0.0,
                          [&](int i, int j, double v, double, const Side<3>& sd) {
                            const double id = i == j ? 1.0 : 0.0;
-                           gst(E[dst] + (size_t)i * m + j,
+                           bar.st(E[dst] + (size_t)i * m + j,
                                v + coef_block<J, 1>(id, sd.v[0] * w.sc1, sd.v[1], sd.v[2]));
                          },
                          w.X0, w.Y2, w.Y3),
         part<1, 4, TW, TW>(pt.first_thin, pt.end_thin, pt.step, pt.thin, W[src], W[src], 1.0, 0.0,
                            [&](int i, int j, double v, double, const Side<4>& sd) {
-                             gst(W[dst] + (size_t)i * TW + j,
+                             bar.st(W[dst] + (size_t)i * TW + j,
                                  v + coef_block<J, 0>(sd.v[0], sd.v[1], sd.v[2], sd.v[3]));
                            },
                            V, U1, U2, U3),
@@ -992,15 +1001,15 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
             const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
             return a.lambda * a.cvec[i] * a.Mraw[e] * a.cvec[j] * a.svec[j];
           },
-          [&](size_t e, double v) { X0[e] = v; });
+          [&](size_t e, double v) { bar.st(X0 + e, v); });
   ew_pass((size_t)worker * 256 + t, (size_t)nw * 256, mt,
           [&](size_t e) {
             const int i = (int)(e / TW), c = (int)(e - (size_t)i * TW);
             const int di = i < f ? 2 * i : 2 * (i - f) + 1;
             return c < d ? a.cvec[i] * ap.H0[(size_t)di * d + c] : 0.0;
           },
-          [&](size_t e, double v) { V[e] = v; });
-  column_abs_sums<m>(a, worker, nw, colsum);
+          [&](size_t e, double v) { bar.st(V + e, v); });
+  column_abs_sums<m>(a, worker, nw, colsum, bar);
   bar.sync();
   const int s = scaling_power<m>(colsum, lds);
   if (worker == 0 && t == 0) *a.sdev = s;
@@ -1012,11 +1021,11 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
     gemm_pair<m, KB, ALL, kShareA>(X0, X0,
                                    part<1, 0, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, X0, X0, sc2, 0.0,
                                                     [&](int i, int j, double v, double, const Side<0>&) {
-                                                      gst(Y2 + (size_t)i * m + j, v);
+                                                      bar.st(Y2 + (size_t)i * m + j, v);
                                                     }),
                                    part<1, 0, TW, TW>(pt.first_thin, pt.end_thin, pt.step, pt.thin, V, V, sc1, 0.0,
                                                       [&](int i, int j, double v, double, const Side<0>&) {
-                                                        gst(U1 + (size_t)i * TW + j, v);
+                                                        bar.st(U1 + (size_t)i * TW + j, v);
                                                       }),
                                    true, lds);
   }
@@ -1030,17 +1039,17 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
                          [&](int i, int j, double y3, double y4, const Side<2>& sd) {
                            const size_t e = (size_t)i * m + j;
                            const double id = i == j ? 1.0 : 0.0;
-                           gst(Y3 + e, y3);
-                           gst(Y4 + e, y4);
-                           gst(E1 + e, coef_block<5, 1>(id, sd.v[0] * sc1, sd.v[1], y3));
+                           bar.st(Y3 + e, y3);
+                           bar.st(Y4 + e, y4);
+                           bar.st(E1 + e, coef_block<5, 1>(id, sd.v[0] * sc1, sd.v[1], y3));
                          },
                          X0, Y2),
         part<2, 2, TW, TW>(pt.first_thin, pt.end_thin, pt.step, pt.thin, V, U1, 1.0, 1.0,
                            [&](int i, int j, double u2, double u3, const Side<2>& sd) {
                              const size_t e = (size_t)i * TW + j;
-                             gst(U2 + e, u2);
-                             gst(U3 + e, u3);
-                             gst(W1 + e, coef_block<5, 0>(sd.v[0], sd.v[1], u2, u3));
+                             bar.st(U2 + e, u2);
+                             bar.st(U3 + e, u3);
+                             bar.st(W1 + e, coef_block<5, 0>(sd.v[0], sd.v[1], u2, u3));
                            },
                            V, U1),
         true, lds);
@@ -1066,10 +1075,10 @@ __device__ __forceinline__ void apply_body(const Phi1Args& a, const ApplyArgs& a
       gemm_pair<m, KB, ALL, kShareA>(
           Ec, Ec,
           part<1, 0, m, m>(pt.first_full, pt.end_full, pt.step, pt.full, Ec, Ec, 1.0, 0.0,
-                           [&](int i, int j, double v, double, const Side<0>&) { gst(En + (size_t)i * m + j, v); }),
+                           [&](int i, int j, double v, double, const Side<0>&) { bar.st(En + (size_t)i * m + j, v); }),
           part<1, 1, TW, TW>(pt.first_thin, pt.end_thin, pt.step, pt.thin, Wc, Wc, 0.5, 0.0,
                              [&](int i, int j, double v, double, const Side<1>& sd) {
-                               gst(Wn + (size_t)i * TW + j, v + 0.5 * sd.v[0]);
+                               bar.st(Wn + (size_t)i * TW + j, v + 0.5 * sd.v[0]);
                              },
                              Wc),
           it + 1 < s, lds);
