@@ -60,6 +60,8 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& sa) {
     if constexpr (LDS) As[e] = v;
     else stg(Ag + e, v);
   };
+  // loads in flight per thread in the two passes over A22
+  constexpr int GL = 16;
   __shared__ double red[4];
   __shared__ double vv[kMaxM], qq[kMaxM];
   __shared__ double dg[kMaxM], od[kMaxM];  // T: diagonal, and od[i] = T[i][i-1]
@@ -106,9 +108,19 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& sa) {
     // p = 2 A22 v (A22 is symmetric: thread i walks column i, coalesced over i)
     double vp = 0.0;
     for (int i = t; i < r; i += 256) {
-      // eight partial sums, so that eight loads are in flight (a fixed order)
+      // eight partial sums (ps[u] adds the j = u mod 8 terms in increasing j),
+      // GL loads in flight
       double ps[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       int j = 0;
+      for (; j + GL <= r; j += GL) {
+        double x[GL];
+#pragma unroll
+        for (int u = 0; u < GL; ++u) x[u] = ld((size_t)(k + 1 + j + u) * m + (k + 1 + i));
+#pragma unroll
+        for (int g = 0; g < GL / 8; ++g)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) ps[u] += x[8 * g + u] * vv[j + 8 * g + u];
+      }
       for (; j + 8 <= r; j += 8) {
         double x[8];
 #pragma unroll
@@ -124,26 +136,21 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& sa) {
     const double beta = block_sum(vp, red);
     for (int i = t; i < r; i += 256) qq[i] -= beta * vv[i];
     __syncthreads();
-    // rank-2 update, eight elements per thread at a time: all loads, then all stores
-    for (int e0 = t; e0 < r * r; e0 += 8 * 256) {
-      double x[8];
+    // rank-2 update: thread j walks column j of A22 (coalesced over j), GL
+    // rows at a time: all loads, then all stores
+    for (int j = t; j < r; j += 256) {
+      const double vj = vv[j], qj = qq[j];
+      int i = 0;
+      for (; i + GL <= r; i += GL) {
+        double x[GL];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256;
-        x[u] = 0.0;
-        if (e < r * r) {
-          const int i = e / r, j = e - i * r;
-          x[u] = ld((size_t)(k + 1 + i) * m + (k + 1 + j));
-        }
-      }
+        for (int u = 0; u < GL; ++u) x[u] = ld((size_t)(k + 1 + i + u) * m + (k + 1 + j));
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256;
-        if (e < r * r) {
-          const int i = e / r, j = e - i * r;
-          st((size_t)(k + 1 + i) * m + (k + 1 + j), x[u] - (vv[i] * qq[j] + qq[i] * vv[j]));
-        }
+        for (int u = 0; u < GL; ++u)
+          st((size_t)(k + 1 + i + u) * m + (k + 1 + j), x[u] - (vv[i + u] * qj + qq[i + u] * vj));
       }
+      for (; i < r; ++i)
+        st((size_t)(k + 1 + i) * m + (k + 1 + j), ld((size_t)(k + 1 + i) * m + (k + 1 + j)) - (vv[i] * qj + qq[i] * vj));
     }
     if (t == 0) od[k + 1] = alpha;
     __syncthreads();
