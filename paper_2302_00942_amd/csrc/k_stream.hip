@@ -650,6 +650,7 @@ __device__ __forceinline__ void reduce2_body(const double* __restrict__ lvl, siz
 // Both levels in one thread: the same group sums, added in the same order,
 // so the result is bitwise that of reduce1 + reduce2 (for few partials).
 constexpr int kFusedReduceMaxParts = 64;
+constexpr int kFusedInFlight = 8;  // loads in flight per thread in the one-launch reduction
 __device__ __forceinline__ void reduce_fused_body(const float* __restrict__ partials, size_t stride, int nparts,
                                                   size_t E, int m, int d, int DB, int gram, double* __restrict__ Mraw,
                                                   double* __restrict__ H0, int* __restrict__ flag, size_t e) {
@@ -659,13 +660,34 @@ __device__ __forceinline__ void reduce_fused_body(const float* __restrict__ part
   if (e >= E) return;
   int I = 0, J = 0;
   if (!reduce_slot(e, ng, NB, slots, I, J)) return;
-  double s = 0.0;
-  for (int g = 0; g < kReduceGroups; ++g) {
-    const int b0 = (int)(((int64_t)g * nparts) / kReduceGroups);
-    const int b1 = (int)(((int64_t)(g + 1) * nparts) / kReduceGroups);
-    double sg = 0.0;
-    for (int b = b0; b < b1; ++b) sg += (double)gldf(partials + (size_t)b * stride + e);
+  // The partials stream in blocks of kFusedInFlight loads (a load per round
+  // trip would leave the thread waiting on each); the sums are the group loop
+  // s = sum_g (sum_{b in g} P_b), every group's sum (zero for an empty group)
+  // added to s in group order.
+  double s = 0.0, sg = 0.0;
+  int g = 0;
+  int gend = (int)((int64_t)nparts / kReduceGroups);  // end of group 0
+  const auto add = [&](int b, float v) {
+    while (b >= gend) {  // close the groups that end before partial b
+      s += sg;
+      sg = 0.0;
+      ++g;
+      gend = (int)(((int64_t)(g + 1) * nparts) / kReduceGroups);
+    }
+    sg += (double)v;
+  };
+  int b0 = 0;
+  for (; b0 + kFusedInFlight <= nparts; b0 += kFusedInFlight) {
+    float v[kFusedInFlight];
+#pragma unroll
+    for (int u = 0; u < kFusedInFlight; ++u) v[u] = gldf(partials + (size_t)(b0 + u) * stride + e);
+#pragma unroll
+    for (int u = 0; u < kFusedInFlight; ++u) add(b0 + u, v[u]);
+  }
+  for (; b0 < nparts; ++b0) add(b0, gldf(partials + (size_t)b0 * stride + e));
+  for (; g < kReduceGroups; ++g) {  // the last group with partials, then any empty ones
     s += sg;
+    sg = 0.0;
   }
   reduce_scatter(s, e, ng, I, J, m, d, DB, Mraw, H0, flag);
 }
