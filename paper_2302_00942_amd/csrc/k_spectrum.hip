@@ -14,6 +14,7 @@
 // q = p - (v^T p) v), and every thread then finds one eigenvalue of T by
 // bisection on its Sturm count (eigenvalues below x = negative pivots of
 // T - x I), from the Gershgorin interval, until the interval cannot shrink.
+#include "grid_barrier.h"
 #include "rfd_internal.h"
 
 namespace rfd {
@@ -39,6 +40,80 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Eigenvalues of the tridiagonal T (diagonal dg, od[i] = T[i][i-1], od[0] = 0)
+// and the selection of the k requested kernel eigenvalues; mu, val and keep
+// are workgroup scratch of m entries. Every thread of the workgroup calls it.
+__device__ __forceinline__ void spectrum_finish(const SpecArgs& sa, const double* dg, const double* od, double* mu,
+                                                double* val, int* keep) {
+  double* __restrict__ out = sa.out;
+  const double lambda = sa.lambda;
+  const int64_t N = sa.N, k = sa.k;
+  const int m = sa.m, which = sa.which;
+  const int t = threadIdx.x;
+  // bisection on the Sturm count, one eigenvalue (the j-th smallest) per thread
+  double emax2 = 1.0, lo = 0.0, hi = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double ei = fabs(od[i]), en = i + 1 < m ? fabs(od[i + 1]) : 0.0;
+    emax2 = fmax(emax2, ei * ei);
+    lo = i == 0 ? dg[i] - ei - en : fmin(lo, dg[i] - ei - en);
+    hi = i == 0 ? dg[i] + ei + en : fmax(hi, dg[i] + ei + en);
+  }
+  const double pivmin = 2.2250738585072014e-308 * emax2;
+  const double tol = 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi));  // absolute accuracy, 2 eps |T|
+  for (int j = t; j < m; j += 256) {
+    double a = lo, b = hi;
+    for (int it = 0; it < kMaxBisect; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (!(mid > a && mid < b) || b - a <= tol) break;
+      int cnt = 0;
+      double q = dg[0] - mid;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0 ? 1 : 0;
+      for (int i = 1; i < m; ++i) {
+        q = dg[i] - mid - od[i] * od[i] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0 ? 1 : 0;
+      }
+      if (cnt > j)
+        b = mid;
+      else
+        a = mid;
+    }
+    mu[j] = 0.5 * (a + b);
+  }
+  __syncthreads();
+  // for N < m, drop the m - N eigenvalues of smallest |mu| (ties by index)
+  const int64_t drop = N < m ? (int64_t)m - N : 0;
+  for (int i = t; i < m; i += 256) {
+    int rank = 0;
+    const double ai = fabs(mu[i]);
+    for (int j = 0; j < m; ++j) {
+      const double aj = fabs(mu[j]);
+      rank += (aj < ai || (aj == ai && j < i)) ? 1 : 0;
+    }
+    keep[i] = rank >= drop ? 1 : 0;
+    val[i] = exp(lambda * mu[i]);
+  }
+  __syncthreads();
+  // ascending position of each kept value among all N: kept values below 1
+  // first, then the N - m ones of the null space, then the rest
+  const int64_t ones = N > m ? N - m : 0;
+  int below = 0;
+  for (int j = 0; j < m; ++j) below += (keep[j] && val[j] < 1.0) ? 1 : 0;
+  for (int i = t; i < m; i += 256) {
+    if (!keep[i]) continue;
+    int64_t pos = 0;
+    for (int j = 0; j < m; ++j)
+      pos += (keep[j] && (val[j] < val[i] || (val[j] == val[i] && j < i))) ? 1 : 0;
+    if (val[i] >= 1.0) pos += ones;
+    const int64_t slot = which == 0 ? pos : N - 1 - pos;
+    if (slot < k) stg(out + slot, val[i]);
+  }
+  // the ones occupy ascending positions [below, below + ones)
+  const int64_t first_one = which == 0 ? below : N - below - ones;
+  for (int64_t p = first_one + t; p < first_one + ones && p < k; p += 256) stg(out + p, 1.0);
+}
+
 // The matrix lives in LDS (dynamic, m^2 doubles) when it fits, else in the
 // global workspace Ag. One workgroup per cloud.
 template <bool LDS>
@@ -46,11 +121,8 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& sa) {
   const double* __restrict__ Mraw = sa.Mraw;
   const double* __restrict__ cvec = sa.cvec;
   double* __restrict__ Ag = sa.Ag;
-  double* __restrict__ out = sa.out;
   int* __restrict__ flag = sa.flag;
-  const double lambda = sa.lambda;
-  const int64_t N = sa.N, k = sa.k;
-  const int Mp = sa.Mp, m = sa.m, f = sa.f, which = sa.which;
+  const int Mp = sa.Mp, m = sa.m, f = sa.f;
   extern __shared__ double As[];
   const auto ld = [&](size_t e) -> double {
     if constexpr (LDS) return As[e];
@@ -166,68 +238,7 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& sa) {
     od[0] = 0.0;
   }
   __syncthreads();
-  // bisection on the Sturm count, one eigenvalue (the j-th smallest) per thread
-  double emax2 = 1.0, lo = 0.0, hi = 0.0;
-  for (int i = 0; i < m; ++i) {
-    const double ei = fabs(od[i]), en = i + 1 < m ? fabs(od[i + 1]) : 0.0;
-    emax2 = fmax(emax2, ei * ei);
-    lo = i == 0 ? dg[i] - ei - en : fmin(lo, dg[i] - ei - en);
-    hi = i == 0 ? dg[i] + ei + en : fmax(hi, dg[i] + ei + en);
-  }
-  const double pivmin = 2.2250738585072014e-308 * emax2;
-  const double tol = 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi));  // absolute accuracy, 2 eps |T|
-  for (int j = t; j < m; j += 256) {
-    double a = lo, b = hi;
-    for (int it = 0; it < kMaxBisect; ++it) {
-      const double mid = 0.5 * (a + b);
-      if (!(mid > a && mid < b) || b - a <= tol) break;
-      int cnt = 0;
-      double q = dg[0] - mid;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0 ? 1 : 0;
-      for (int i = 1; i < m; ++i) {
-        q = dg[i] - mid - od[i] * od[i] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0 ? 1 : 0;
-      }
-      if (cnt > j)
-        b = mid;
-      else
-        a = mid;
-    }
-    mu[j] = 0.5 * (a + b);
-  }
-  __syncthreads();
-  // for N < m, drop the m - N eigenvalues of smallest |mu| (ties by index)
-  const int64_t drop = N < m ? (int64_t)m - N : 0;
-  for (int i = t; i < m; i += 256) {
-    int rank = 0;
-    const double ai = fabs(mu[i]);
-    for (int j = 0; j < m; ++j) {
-      const double aj = fabs(mu[j]);
-      rank += (aj < ai || (aj == ai && j < i)) ? 1 : 0;
-    }
-    keep[i] = rank >= drop ? 1 : 0;
-    val[i] = exp(lambda * mu[i]);
-  }
-  __syncthreads();
-  // ascending position of each kept value among all N: kept values below 1
-  // first, then the N - m ones of the null space, then the rest
-  const int64_t ones = N > m ? N - m : 0;
-  int below = 0;
-  for (int j = 0; j < m; ++j) below += (keep[j] && val[j] < 1.0) ? 1 : 0;
-  for (int i = t; i < m; i += 256) {
-    if (!keep[i]) continue;
-    int64_t pos = 0;
-    for (int j = 0; j < m; ++j)
-      pos += (keep[j] && (val[j] < val[i] || (val[j] == val[i] && j < i))) ? 1 : 0;
-    if (val[i] >= 1.0) pos += ones;
-    const int64_t slot = which == 0 ? pos : N - 1 - pos;
-    if (slot < k) stg(out + slot, val[i]);
-  }
-  // the ones occupy ascending positions [below, below + ones)
-  const int64_t first_one = which == 0 ? below : N - below - ones;
-  for (int64_t p = first_one + t; p < first_one + ones && p < k; p += 256) stg(out + p, 1.0);
+  spectrum_finish(sa, dg, od, mu, val, keep);
 }
 
 template <bool LDS>
@@ -239,6 +250,161 @@ template <bool LDS>
 __global__ __launch_bounds__(256) void k_spectrum_batch(const SpecArgs* __restrict__ arr) {
   const SpecArgs sa = arr[blockIdx.x];
   spectrum_body<LDS>(sa);
+}
+
+// ------------------------------------------------------------------ cooperative
+// A single call with m > 128 runs on W = ceil(m / 32) workgroups of a
+// cooperative grid: column j of the matrix lives in the LDS of workgroup
+// j % W (local column j / W), so the passes over the trailing block read LDS
+// on W CUs instead of streaming the block through one CU's L2 port at every
+// step. Step k: the owner of column k forms v from its column and publishes
+// it (barrier); each workgroup forms p over its columns and publishes it
+// (barrier); each workgroup then takes beta and q from the whole of v and p
+// and updates its columns. Every value is formed as in spectrum_body — p as
+// eight strided partial sums in increasing row order, combined in the same
+// tree; beta by the same workgroup sum over the same lanes; the same update —
+// so the eigenvalues are its bits, and WG 0 finishes as it does. v and the
+// step's skip flag alternate between two slots, so the owner of step k + 1
+// never overwrites what a workgroup may still read of step k. Published
+// values are agent-scope stores (coherent once acknowledged, see GridBarrier).
+constexpr int kCoopCols = 32;  // columns per workgroup
+// column pitch m + 8 doubles: the eight columns a wave reads in the product
+// fall on different banks
+constexpr int kCoopPad = 8;
+constexpr int kMaxCoopSpectrumGroups = (kMaxM + kCoopCols - 1) / kCoopCols;
+static_assert(kMaxCoopSpectrumGroups <= 256, "more workgroups than the grid barrier counts");
+
+__global__ __launch_bounds__(256) void k_spectrum_coop(SpecArgs sa, unsigned* bar_ctr, double* gws) {
+  GridBarrier bar{bar_ctr, gridDim.x, 0u, sa.flag};
+  extern __shared__ double cols[];  // [local column][row], column pitch CP
+  const double* __restrict__ Mraw = sa.Mraw;
+  const double* __restrict__ cvec = sa.cvec;
+  const int W = (int)gridDim.x, w = (int)blockIdx.x, t = threadIdx.x;
+  const int Mp = sa.Mp, m = sa.m, f = sa.f, fp = Mp / 2;
+  double* const gv = gws;             // v, two slots of m
+  double* const gflag = gv + 2 * m;   // step kept (1) or skipped (0), two slots
+  double* const gp = gflag + 2;       // p, m
+  double* const gdg = gp + m;         // T: diagonal
+  double* const god = gdg + m;        // T: od[i] = T[i][i-1]
+  double* const gfro = god + m;       // per workgroup: sum of squares of its entries
+  __shared__ double red[4];
+  __shared__ double vv[kMaxM], qq[kMaxM];
+  __shared__ double dg[kMaxM], od[kMaxM];
+  __shared__ double mu[kMaxM];
+  __shared__ double val[kMaxM];
+  __shared__ int keep[kMaxM];
+  const int ncol = (m - w + W - 1) / W;  // columns w, w + W, ...
+  const int CP = m + kCoopPad;
+  // A = diag(c) Mraw diag(c) over the real features (canonical order), own columns
+  double fro = 0.0;
+  for (int e = t; e < ncol * m; e += 256) {
+    const int lc = e / m, i = e - lc * m, j = lc * W + w;
+    const int pi = i < f ? i : fp + (i - f), pj = j < f ? j : fp + (j - f);
+    const double v = ldg(cvec + pi) * ldg(Mraw + (size_t)pi * Mp + pj) * ldg(cvec + pj);
+    cols[lc * CP + i] = v;
+    fro += v * v;
+  }
+  fro = block_sum(fro, red);
+  if (t == 0) gst_agent(gfro + w, fro);
+  for (int k = 0; k + 2 < m; ++k) {
+    const int r = m - k - 1, slot = k & 1;
+    if (w == k % W) {  // the owner of column k
+      const double* col = cols + (k / W) * CP;
+      double tail = 0.0;
+      for (int i = t; i < r; i += 256) {
+        const double x = col[k + 1 + i];
+        vv[i] = x;
+        if (i > 0) tail += x * x;
+      }
+      tail = block_sum(tail, red);
+      const double x0 = vv[0];
+      if (t == 0) gst_agent(gdg + k, col[k]);
+      if (!(tail > 0.0)) {
+        if (t == 0) {
+          gst_agent(god + k + 1, x0);
+          gst_agent(gflag + slot, 0.0);
+        }
+      } else {
+        const double sq = x0 * x0 + tail;
+        const double nrm = sqrt(sq);
+        const double alpha = x0 >= 0.0 ? -nrm : nrm;
+        const double vn = sqrt(2.0 * (sq - alpha * x0));
+        for (int i = t; i < r; i += 256) gst_agent(gv + slot * m + i, (i == 0 ? x0 - alpha : vv[i]) / vn);
+        if (t == 0) {
+          gst_agent(god + k + 1, alpha);
+          gst_agent(gflag + slot, 1.0);
+        }
+      }
+    }
+    bar.sync();
+    if (!(ldg(gflag + slot) != 0.0)) continue;  // the column was reduced already: no rotation
+    for (int i = t; i < r; i += 256) vv[i] = ldg(gv + slot * m + i);
+    __syncthreads();
+    // p over this workgroup's columns c > k: eight threads per column, lane u
+    // adding the rows j = u (mod 8) of the trailing block in increasing order
+    {
+      const int lc0 = k + 1 > w ? (k + 1 - w + W - 1) / W : 0;
+      const int u = t & 7;
+      for (int lc = lc0 + (t >> 3); lc < ncol; lc += 256 / 8) {
+        const double* col = cols + lc * CP + (k + 1);
+        double ps = 0.0;
+        for (int j = u; j < r; j += 8) ps += col[j] * vv[j];
+        const double a = ps + __shfl_xor(ps, 1);  // ps0 + ps1, ps2 + ps3, ...
+        const double b = a + __shfl_xor(a, 2);    // (ps0 + ps1) + (ps2 + ps3), ...
+        const double sum = b + __shfl_xor(b, 4);
+        if (u == 0) gst_agent(gp + (lc * W + w - (k + 1)), 2.0 * sum);
+      }
+    }
+    bar.sync();
+    double vp = 0.0;
+    for (int i = t; i < r; i += 256) {
+      const double pi = ldg(gp + i);
+      qq[i] = pi;
+      vp += vv[i] * pi;
+    }
+    const double beta = block_sum(vp, red);
+    for (int i = t; i < r; i += 256) qq[i] -= beta * vv[i];
+    __syncthreads();
+    // rank-2 update of this workgroup's columns c > k: a wave per column, a
+    // lane per row
+    {
+      const int lc0 = k + 1 > w ? (k + 1 - w + W - 1) / W : 0;
+      for (int lc = lc0 + (t >> 6); lc < ncol; lc += 4) {
+        const int jc = lc * W + w - (k + 1);
+        const double vj = vv[jc], qj = qq[jc];
+        double* col = cols + lc * CP + (k + 1);
+        for (int i = t & 63; i < r; i += 64) col[i] = col[i] - (vv[i] * qj + qq[i] * vj);
+      }
+    }
+    __syncthreads();
+  }
+  // the last 2 x 2 block of T
+  if (t == 0) {
+    if (m >= 2) {
+      if (w == (m - 2) % W) {
+        const double* col = cols + ((m - 2) / W) * CP;
+        gst_agent(gdg + m - 2, col[m - 2]);
+        gst_agent(god + m - 1, col[m - 1]);
+      }
+      if (w == (m - 1) % W) gst_agent(gdg + m - 1, cols[((m - 1) / W) * CP + m - 1]);
+    } else if (w == 0) {
+      gst_agent(gdg, cols[0]);
+    }
+  }
+  bar.sync();
+  bar.finish();
+  if (w != 0) return;
+  for (int i = t; i < m; i += 256) {
+    dg[i] = ldg(gdg + i);
+    od[i] = i == 0 ? 0.0 : ldg(god + i);
+  }
+  if (t == 0) {
+    double tot = 0.0;
+    for (int v = 0; v < W; ++v) tot += ldg(gfro + v);
+    if (!isfinite(tot)) __hip_atomic_fetch_or(sa.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  spectrum_finish(sa, dg, od, mu, val, keep);
 }
 
 }  // namespace
@@ -276,13 +442,23 @@ SpecArgs spectrum_args(rfd_plan_s* p, int which, int64_t k, double* out) {
 }
 
 hipError_t launch_spectrum(rfd_plan_s* p, int which, int64_t k, double* out, hipStream_t st) {
-  const SpecArgs a = spectrum_args(p, which, k, out);
+  SpecArgs a = spectrum_args(p, which, k, out);
   const size_t bytes = sizeof(double) * (size_t)p->m * p->m;
-  if (bytes <= spectrum_lds_max())
+  if (bytes <= spectrum_lds_max()) {
     hipLaunchKernelGGL(k_spectrum<true>, dim3(1), dim3(256), bytes, st, a);
-  else
-    hipLaunchKernelGGL(k_spectrum<false>, dim3(1), dim3(256), 0, st, a);
-  return hipGetLastError();
+    return hipGetLastError();
+  }
+  // the matrix does not fit one CU's LDS: its columns spread over W workgroups
+  const int W = (p->m + kCoopCols - 1) / kCoopCols;
+  const size_t lds = sizeof(double) * (size_t)kCoopCols * (p->m + kCoopPad);
+  static const bool attr_ok = hipFuncSetAttribute((const void*)k_spectrum_coop,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)(sizeof(double) * kCoopCols * (kMaxM + kCoopPad))) == hipSuccess;
+  if (!attr_ok || W > kMaxCoopSpectrumGroups) return hipErrorInvalidValue;
+  unsigned* ctr = p->dev.barrier + kSpecBarrierOffset;
+  double* gws = p->dev.phi_ws;  // v (2 m), flags (2), p, dg, od (m each), W sums: within the phi_1 workspace
+  void* kargs[] = {&a, &ctr, &gws};
+  return hipLaunchCooperativeKernel((const void*)k_spectrum_coop, dim3(W), dim3(256), kargs, (unsigned)lds, st);
 }
 
 hipError_t launch_spectrum_batch(const SpecArgs* dev_args, int n, int max_m, hipStream_t st) {

@@ -22,7 +22,8 @@ constexpr int kMaxD = 1024;       // largest field width per call
 constexpr int kChunk = 64;        // points per chunk of the split-N passes
 constexpr int kDBlock = 16;       // channels per MFMA block of the field
 constexpr int kMaxDBlocks = 4;    // channel blocks handled by one pass (64 channels)
-constexpr int kBarrierWords = 1024; // words of the grid-barrier counters of a plan
+constexpr int kBarrierWords = 2048; // words of the grid-barrier counters of a plan
+constexpr int kSpecBarrierOffset = 1024;  // the cooperative spectrum's counters (phi_1 uses the words below)
 
 // Device feature order: column 2k holds cos(2 pi omega_k . x), column 2k+1
 // holds sin(2 pi omega_k . x), both unscaled. The paper's order
