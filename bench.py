@@ -43,19 +43,25 @@ PEAK = {  # MI355X published peaks
     # 157.3 TFLOP/s (256 CUs x 4 SIMDs x 32 lanes x 2 flops x 2.4 GHz)
     "trans_Tops": 256 * 4 * 32 / 4 * 2.4e9 / 1e12,
 }
+_STREAM = ("paper_2302_00942_amd/csrc/k_stream.hip",)
+_PHI1 = ("paper_2302_00942_amd/csrc/k_phi1.hip", "paper_2302_00942_amd/csrc/grid_barrier.h")
 KERNEL_SOURCES = {
-    "k_bta_gram": "paper_2302_00942_amd/csrc/k_stream.hip",
-    "k_bta": "paper_2302_00942_amd/csrc/k_stream.hip",
-    "k_expand": "paper_2302_00942_amd/csrc/k_stream.hip",
-    "k_reduce": "paper_2302_00942_amd/csrc/k_stream.hip",
-    "k_phi1": "paper_2302_00942_amd/csrc/k_phi1.hip",
-    "k_phi1_apply": "paper_2302_00942_amd/csrc/k_phi1.hip",
+    "k_bta_gram": _STREAM,
+    "k_bta": _STREAM,
+    "k_expand": _STREAM,
+    "k_reduce": _STREAM,
+    "k_phi1": _PHI1,
+    "k_phi1_apply": _PHI1,
 }
 
 
-def source_hash(path: str) -> str:
-    with open(os.path.join(ROOT, path), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def source_hash(paths) -> str:
+    """First 16 hex digits of the sha256 of the kernel's source files, concatenated in order."""
+    h = hashlib.sha256()
+    for path in paths:
+        with open(os.path.join(ROOT, path), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(kernel: str, workload: str):
@@ -65,7 +71,9 @@ def read_traffic(kernel: str, workload: str):
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
-    want = source_hash(KERNEL_SOURCES.get(kernel, ""))
+    if kernel not in KERNEL_SOURCES:
+        return None
+    want = source_hash(KERNEL_SOURCES[kernel])
     with open(path) as fh:
         for line in fh:
             if line.startswith("#") or not line.strip():
