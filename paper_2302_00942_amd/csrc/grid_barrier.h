@@ -34,7 +34,7 @@ __device__ __forceinline__ void gst_agent(double* p, double v) {
 // and the last arrival, which knows that no workgroup of the launch reads a
 // counter again, clears them all, so no clearing kernel runs between launches
 // on a stream.
-constexpr int kBarGroup = 16;
+constexpr int kBarGroup = 32;
 constexpr int kBarStride = 32;        // unsigned words between counters (128 bytes)
 constexpr int kBarWords = kBarStride * (1 + 256 / kBarGroup);
 static_assert(kBarWords <= kBarrierWords, "barrier counters exceed the plan's buffer");
