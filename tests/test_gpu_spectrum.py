@@ -110,3 +110,26 @@ def test_spectrum_batch_equals_single_calls(torch_cuda, m):
         rfd.spectrum_batch([plans[0], plans[0]], 3)
     assert e.value.status == rfd.INVALID_ARG
     assert rfd.spectrum_batch([], 3) == []
+
+
+def test_spectrum_cooperative_repeatable(torch_cuda):
+    """A single call with m > 128 runs on a cooperative grid (columns over
+    ceil(m / 32) workgroups): back-to-back calls give the same bits, leave no
+    barrier timeout in the status flag, and interleave with the batched path
+    and with integrations on the same plan."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    X = torch.from_numpy(wl.torus(900, 4)).cuda()
+    F = torch.from_numpy(wl.field(900, 3, 4)).cuda()
+    plan = rfd.Plan(200, 0.15, -0.4, 9, precision="bf16")
+    plan.features(X)
+    a = plan.spectrum(900, "largest").cpu().numpy()
+    plan.integrate(F)
+    b = plan.spectrum(900, "largest").cpu().numpy()
+    c = rfd.spectrum_batch([plan], 900, "largest")[0].cpu().numpy()
+    d = plan.spectrum(900, "largest").cpu().numpy()
+    assert plan.check() == rfd.OK
+    assert np.array_equal(a, b) and np.array_equal(a, c) and np.array_equal(a, d)
+    ref = o.kernel_spectrum(wl.torus(900, 4), 0.15, -0.4, 200, 9)[::-1]
+    tol = 0.4 * max(1.0, float(ref.max())) * _oracle_M_norm(wl.torus(900, 4), 0.15, 200, 9) * BAR["bf16"]
+    assert np.abs(a - ref).max() <= tol
