@@ -320,14 +320,26 @@ struct ThinTileMap {
   static constexpr bool kThin = true;
 };
 __host__ __device__ constexpr int full_tiles(int nb, bool sym) { return sym ? nb * (nb + 1) / 2 : nb * nb; }
+// XCD-aware unit order for the symmetric m = 256 action form (36 full and 8
+// thin units on 44 workgroups, the hardware dealing workgroup w to XCD w % 8):
+// the units of one XCD share row and column panels (40 distinct panels per
+// phase over the eight XCDs' L2s, against 83 in the plain order). Any order
+// gives the same results: every unit is computed the same way.
+__constant__ int kUnitOrder44[44] = {41, 5,  31, 40, 17, 0,  1,  16, 37, 11, 18, 33, 38, 6,  3,  15, 35, 4,  19, 42, 36, 13,
+                                     8,  25, 14, 12, 30, 29, 39, 2,  10, 20, 32, 27, 24, 28, 22, 9,  7,  21, 43, 26, 23, 34};
+__device__ __forceinline__ int phase_unit(int worker, int nw, int nb, bool sym) {
+  return (nw == 44 && nb == 8 && sym) ? kUnitOrder44[worker] : worker;
+}
 struct PhaseTiles {
   int first_full, end_full, first_thin, end_thin, step;
   FullTileMap full;
   ThinTileMap thin;
   __device__ PhaseTiles(int worker, int nw, int nb, int nthin, bool sym)
-      : first_full(worker), end_full(full_tiles(nb, sym)), step(nw), full{nb, sym}, thin{full_tiles(nb, sym)} {
+      : end_full(full_tiles(nb, sym)), step(nw), full{nb, sym}, thin{full_tiles(nb, sym)} {
+    const int u = phase_unit(worker, nw, nb, sym);
     const int nt = end_full;
-    first_thin = worker >= nt ? worker : worker + ((nt - worker + nw - 1) / nw) * nw;
+    first_full = u;
+    first_thin = u >= nt ? u : u + ((nt - u + nw - 1) / nw) * nw;
     end_thin = nt + nthin;
   }
 };
