@@ -17,23 +17,28 @@ __device__ __forceinline__ void gst_agent(double* p, double v) {
 // Two-level counter barrier over a cooperative grid. Workgroups arrive on the
 // counter of their group of kBarGroup (128-byte apart lines); the last arrival
 // of a group (seen from the returned count) bumps the top counter, which every
-// workgroup polls (a grid of one group polls its group counter instead). Counters only grow: round r waits for r * groups top
-// arrivals. Visibility of the phase outputs: every one of them is written
-// with a relaxed agent-scope store (`st`, global_store ... sc1), which is
-// coherent at device scope once acknowledged, and every wave waits for its
-// own stores before the workgroup arrives, so an arrival is counted only
-// after its workgroup's outputs are visible to every XCD: no L2 write-back
-// fence is needed (with plain stores, the agent-scope release fence's L2
-// write-back at every arrival cost about 31 us of a 180 us call at m = 256).
-// The poll is relaxed and followed by an agent-scope acquire fence (the L2
-// and L1 invalidates that drop lines older than the phase), and every wave
-// drops its L1 lines after the wait. The wait is bounded: on timeout the flag gets bit 2 and the
-// workgroup proceeds, so every wave always exits. The counters start at zero
-// (the plan zeroes them when it is created) and every launch leaves them at
-// zero: after its last wait each workgroup arrives on an exit counter (word 1),
-// and the last arrival, which knows that no workgroup of the launch reads a
-// counter again, clears them all, so no clearing kernel runs between launches
-// on a stream.
+// workgroup polls; a grid of one group polls its group counter instead.
+// Counters only grow: round r waits for r * groups top arrivals (r * nblocks
+// group arrivals for one group).
+//
+// Visibility of the phase outputs: every one of them is written with a
+// relaxed agent-scope store (`st`, global_store ... sc1), which is coherent at
+// device scope once acknowledged, and every wave waits for its own stores
+// before the workgroup arrives, so an arrival is counted only after its
+// workgroup's outputs are visible to every XCD: no L2 write-back fence is
+// needed (with plain stores, the agent-scope release fence's L2 write-back at
+// every arrival cost about 31 us of a 180 us phi_1 call at m = 256). The poll
+// is relaxed and followed by an agent-scope acquire fence (the L2 and L1
+// invalidates that drop lines older than the phase), and every wave drops its
+// L1 lines after the wait.
+//
+// The wait is bounded: on timeout the flag gets bit 2 and the workgroup
+// proceeds, so every wave always exits. The counters start at zero (the plan
+// zeroes them when it is created) and every launch leaves them at zero: after
+// its last wait each workgroup arrives on an exit counter (word 1), and the
+// last arrival, which knows that no workgroup of the launch reads a counter
+// again, clears them all, so no clearing kernel runs between launches on a
+// stream.
 constexpr int kBarGroup = 32;
 constexpr int kBarStride = 32;        // unsigned words between counters (128 bytes)
 constexpr int kBarWords = kBarStride * (1 + 256 / kBarGroup);
