@@ -365,20 +365,10 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __r
     if (base + kChunk <= N) {
       xa = gldf(X + pa * 3); ya = gldf(X + pa * 3 + 1); za = gldf(X + pa * 3 + 2);
       xb = gldf(X + pb * 3); yb = gldf(X + pb * 3 + 1); zb = gldf(X + pb * 3 + 2);
-      if (Xcopy && kq == 0) {
-        gstf(Xcopy + pa * 3, xa); gstf(Xcopy + pa * 3 + 1, ya); gstf(Xcopy + pa * 3 + 2, za);
-        gstf(Xcopy + pb * 3, xb); gstf(Xcopy + pb * 3 + 1, yb); gstf(Xcopy + pb * 3 + 2, zb);
-      }
     } else {
       xa = ya = za = xb = yb = zb = 0.f;
-      if (pa < N) {
-        xa = gldf(X + pa * 3); ya = gldf(X + pa * 3 + 1); za = gldf(X + pa * 3 + 2);
-        if (Xcopy && kq == 0) { gstf(Xcopy + pa * 3, xa); gstf(Xcopy + pa * 3 + 1, ya); gstf(Xcopy + pa * 3 + 2, za); }
-      }
-      if (pb < N) {
-        xb = gldf(X + pb * 3); yb = gldf(X + pb * 3 + 1); zb = gldf(X + pb * 3 + 2);
-        if (Xcopy && kq == 0) { gstf(Xcopy + pb * 3, xb); gstf(Xcopy + pb * 3 + 1, yb); gstf(Xcopy + pb * 3 + 2, zb); }
-      }
+      if (pa < N) { xa = gldf(X + pa * 3); ya = gldf(X + pa * 3 + 1); za = gldf(X + pa * 3 + 2); }
+      if (pb < N) { xb = gldf(X + pb * 3); yb = gldf(X + pb * 3 + 1); zb = gldf(X + pb * 3 + 2); }
     }
     if constexpr (PREC) {
       // lane: channel tid % 16 of a 16-channel block, point pair (tid / 16) % 4
@@ -430,6 +420,12 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __r
     const int64_t base = ch * kChunk;
     __syncthreads();  // previous chunk's MFMA reads are done (and oms is visible)
     const int64_t pa = base + 2 * pp;
+    // the plan's copy of the chunk's points, written where they are first
+    // used (a store right after the prefetch would wait for its loads)
+    if (Xcopy && kq == 0) {
+      if (pa < N) { gstf(Xcopy + pa * 3, xa); gstf(Xcopy + pa * 3 + 1, ya); gstf(Xcopy + pa * 3 + 2, za); }
+      if (pa + 1 < N) { gstf(Xcopy + pa * 3 + 3, xb); gstf(Xcopy + pa * 3 + 4, yb); gstf(Xcopy + pa * 3 + 5, zb); }
+    }
     if (base + kChunk <= N)  // full chunk (uniform branch): no masking
       features(pa, true, true, std::false_type{});
     else
