@@ -192,7 +192,9 @@ __device__ __forceinline__ void bta_mma(const typename BtaShape<M, PREC>::elem* 
   if constexpr (PREC) {
     // BF16: Gram with 32x32x16, B^T F with 16x16x32.
     if constexpr (GRAM) {
-#pragma unroll 1
+      // the four K steps unrolled: a step's LDS operand reads can be issued
+      // during the previous step's MFMAs
+#pragma unroll
       for (int ks = 0; ks < kChunk / 16; ++ks) {
         const __bf16* base = phi + (lane & 31) * P + ks * 16 + 8 * (lane >> 5);
         int s0 = 0;
@@ -1017,15 +1019,7 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
   if (t_first + (tid >> 6) < ntiles) load_tile(t_first + (tid >> 6));
 
   if constexpr (PREC) {
-    for (int64_t tile = t_first + (tid >> 6); tile < ntiles; tile += wstride) {
-      const float x = xn, y = yn, z = zn;
-      float fres[DB][4];
-#pragma unroll
-      for (int cb = 0; cb < DB; ++cb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) fres[cb][q] = fn[cb][q];
-      if (tile + wstride < ntiles) load_tile(tile + wstride);
-      f32x4 acc[DB];
+    const auto products = [&](float x, float y, float z, f32x4 (&acc)[DB]) {
 #pragma unroll
       for (int cb = 0; cb < DB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
@@ -1052,6 +1046,43 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
           }
         }
       }
+    };
+    int64_t tile = t_first + (tid >> 6);
+    if constexpr (kRowPieces<DB> && !TOUT && !DIAG && !EPI) {
+      // interior tiles of a full 16-channel field without row scaling: every
+      // load and store unconditional, so no wait for the prefetch also waits
+      // for the previous tile's stores
+      const int64_t nfull = N / 16;  // tiles whose 16 points all lie below N
+      if (vec && d == 16 && rowscale == nullptr && tile + wstride < nfull) {
+        // the first tile's loads arrive here, so no wait inside the loop
+        // covers them (such a wait would also cover the previous tile's store)
+        asm volatile("" ::"v"(xn), "v"(yn), "v"(zn), "v"(fn[0][0]), "v"(fn[0][1]), "v"(fn[0][2]), "v"(fn[0][3]));
+        for (; tile + wstride < nfull; tile += wstride) {
+          const float x = xn, y = yn, z = zn;
+          const float r0 = fn[0][0], r1 = fn[0][1], r2 = fn[0][2], r3 = fn[0][3];
+          {
+            const int64_t p = (tile + wstride) * 16 + pl;
+            xn = gldf(X + p * 3); yn = gldf(X + p * 3 + 1); zn = gldf(X + p * 3 + 2);
+            const float4 v = gld4(F + p * ldF + 4 * g);
+            fn[0][0] = v.x; fn[0][1] = v.y; fn[0][2] = v.z; fn[0][3] = v.w;
+          }
+          f32x4 acc[DB];
+          products(x, y, z, acc);
+          const int64_t pr = tile * 16 + pl;
+          gst4(out + pr * ldO + 4 * g, float4{r0 + acc[0][0], r1 + acc[0][1], r2 + acc[0][2], r3 + acc[0][3]});
+        }
+      }
+    }
+    for (; tile < ntiles; tile += wstride) {
+      const float x = xn, y = yn, z = zn;
+      float fres[DB][4];
+#pragma unroll
+      for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fres[cb][q] = fn[cb][q];
+      if (tile + wstride < ntiles) load_tile(tile + wstride);
+      f32x4 acc[DB];
+      products(x, y, z, acc);
       store_out<DB, TOUT, EPI>(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc, ea, eb);
     }
   } else {
