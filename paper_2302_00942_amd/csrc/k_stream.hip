@@ -1048,28 +1048,53 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
       }
     };
     int64_t tile = t_first + (tid >> 6);
-    if constexpr (kRowPieces<DB> && !TOUT && !DIAG && !EPI) {
-      // interior tiles of a full 16-channel field without row scaling: every
-      // load and store unconditional, so no wait for the prefetch also waits
-      // for the previous tile's stores
-      const int64_t nfull = N / 16;  // tiles whose 16 points all lie below N
-      if (vec && d == 16 && rowscale == nullptr && tile + wstride < nfull) {
+    if constexpr (!TOUT && !DIAG && !EPI) {
+      // interior tiles of a field of full 16-channel blocks without row
+      // scaling: every load and store unconditional, so no wait for the
+      // prefetch also waits for the previous tile's stores
+      // the wave's interior tiles: all 16 points below N and, like the tile
+      // it prefetches, inside this call's range [t_first, t_end)
+      const int64_t nfull = N / 16 < ntiles ? N / 16 : ntiles;
+      const bool full = kRowPieces<DB> ? (vec && d == 16) : d == DB * 16;
+      if (full && rowscale == nullptr && tile + wstride < nfull) {
         // the first tile's loads arrive here, so no wait inside the loop
         // covers them (such a wait would also cover the previous tile's store)
-        asm volatile("" ::"v"(xn), "v"(yn), "v"(zn), "v"(fn[0][0]), "v"(fn[0][1]), "v"(fn[0][2]), "v"(fn[0][3]));
+        asm volatile("" ::"v"(xn), "v"(yn), "v"(zn));
+#pragma unroll
+        for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) asm volatile("" ::"v"(fn[cb][q]));
         for (; tile + wstride < nfull; tile += wstride) {
           const float x = xn, y = yn, z = zn;
-          const float r0 = fn[0][0], r1 = fn[0][1], r2 = fn[0][2], r3 = fn[0][3];
-          {
-            const int64_t p = (tile + wstride) * 16 + pl;
-            xn = gldf(X + p * 3); yn = gldf(X + p * 3 + 1); zn = gldf(X + p * 3 + 2);
+          float fres[DB][4];
+#pragma unroll
+          for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) fres[cb][q] = fn[cb][q];
+          const int64_t nt = tile + wstride;
+          const int64_t p = nt * 16 + pl;
+          xn = gldf(X + p * 3); yn = gldf(X + p * 3 + 1); zn = gldf(X + p * 3 + 2);
+          if constexpr (kRowPieces<DB>) {
             const float4 v = gld4(F + p * ldF + 4 * g);
             fn[0][0] = v.x; fn[0][1] = v.y; fn[0][2] = v.z; fn[0][3] = v.w;
+          } else {
+#pragma unroll
+            for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) fn[cb][q] = gldf(F + (nt * 16 + 4 * g + q) * ldF + cb * 16 + pl);
           }
           f32x4 acc[DB];
           products(x, y, z, acc);
-          const int64_t pr = tile * 16 + pl;
-          gst4(out + pr * ldO + 4 * g, float4{r0 + acc[0][0], r1 + acc[0][1], r2 + acc[0][2], r3 + acc[0][3]});
+          if constexpr (kRowPieces<DB>) {
+            gst4(out + (tile * 16 + pl) * ldO + 4 * g, float4{fres[0][0] + acc[0][0], fres[0][1] + acc[0][1],
+                                                              fres[0][2] + acc[0][2], fres[0][3] + acc[0][3]});
+          } else {
+#pragma unroll
+            for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                gstf(out + (tile * 16 + 4 * g + q) * ldO + cb * 16 + pl, fres[cb][q] + acc[cb][q]);
+          }
         }
       }
     }
