@@ -228,3 +228,28 @@ def test_batch_schedules_bitwise_equal_alone(torch_cuda, m):
         c, F = clouds[1], Fs_np[1]
         e = o.relf(outs[1].cpu().numpy(), o.rfd_integrate(c.X, F, c.eps, c.lam, c.m, c.seed))
         assert e <= {"fp32": 1e-5, "bf16": 2e-3}[prec], e
+
+
+@pytest.mark.parametrize("d", [16, 32, 64])
+def test_batch_in_place_equals_per_cloud(torch_cuda, d):
+    """out may be F itself. Each cloud spans several expansion work items (64
+    tiles of 16 points each) and ends in a ragged tile; a tile handled by two
+    work items would, in place, carry the correction twice. Full 16-channel
+    blocks (d = 16, 32, 64) take the expansion's interior-tile loop."""
+    torch = torch_cuda
+    from paper_2302_00942_amd import rfd
+    clouds = _clouds(6, d, 128, 11, lo=3000, hi=9000)
+    assert all(c.n % 16 for c in clouds) and all(c.n > 2 * 64 * 16 for c in clouds)
+    plans = [rfd.Plan(c.m, c.eps, c.lam, c.seed, precision="bf16") for c in clouds]
+    Xs = [torch.from_numpy(c.X).cuda() for c in clouds]
+    Fs = [torch.from_numpy(c.F).cuda() for c in clouds]
+    b = rfd.Batch(plans, Xs, Fs, Fs)
+    b.launch()
+    torch.cuda.synchronize()
+    for p in plans:
+        assert p.check() == rfd.OK
+    for i, c in enumerate(clouds):
+        got = Fs[i].cpu().numpy()
+        ref = _single(torch, c, "bf16")
+        assert np.array_equal(got, ref), (i, c.n, np.abs(got - ref).max())
+    b.close()
