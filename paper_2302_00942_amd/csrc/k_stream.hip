@@ -1018,8 +1018,9 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
   };
   if (t_first + (tid >> 6) < ntiles) load_tile(t_first + (tid >> 6));
 
-  if constexpr (PREC) {
-    const auto products = [&](float x, float y, float z, f32x4 (&acc)[DB]) {
+  // the products of one tile: acc = (Phi G')^T (one channel block) or Phi G'
+  const auto products = [&](float x, float y, float z, f32x4 (&acc)[DB]) {
+    if constexpr (PREC) {
 #pragma unroll
       for (int cb = 0; cb < DB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
@@ -1046,80 +1047,7 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
           }
         }
       }
-    };
-    int64_t tile = t_first + (tid >> 6);
-    if constexpr (!TOUT && !DIAG && !EPI) {
-      // interior tiles of a field of full 16-channel blocks without row
-      // scaling: every load and store unconditional, so no wait for the
-      // prefetch also waits for the previous tile's stores
-      // the wave's interior tiles: all 16 points below N and, like the tile
-      // it prefetches, inside this call's range [t_first, t_end)
-      const int64_t nfull = N / 16 < ntiles ? N / 16 : ntiles;
-      const bool full = kRowPieces<DB> ? (vec && d == 16) : d == DB * 16;
-      if (full && rowscale == nullptr && tile + wstride < nfull) {
-        // the first tile's loads arrive here, so no wait inside the loop
-        // covers them (such a wait would also cover the previous tile's store)
-        asm volatile("" ::"v"(xn), "v"(yn), "v"(zn));
-#pragma unroll
-        for (int cb = 0; cb < DB; ++cb)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) asm volatile("" ::"v"(fn[cb][q]));
-        for (; tile + wstride < nfull; tile += wstride) {
-          const float x = xn, y = yn, z = zn;
-          float fres[DB][4];
-#pragma unroll
-          for (int cb = 0; cb < DB; ++cb)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) fres[cb][q] = fn[cb][q];
-          const int64_t nt = tile + wstride;
-          const int64_t p = nt * 16 + pl;
-          xn = gldf(X + p * 3); yn = gldf(X + p * 3 + 1); zn = gldf(X + p * 3 + 2);
-          if constexpr (kRowPieces<DB>) {
-            const float4 v = gld4(F + p * ldF + 4 * g);
-            fn[0][0] = v.x; fn[0][1] = v.y; fn[0][2] = v.z; fn[0][3] = v.w;
-          } else {
-#pragma unroll
-            for (int cb = 0; cb < DB; ++cb)
-#pragma unroll
-              for (int q = 0; q < 4; ++q) fn[cb][q] = gldf(F + (nt * 16 + 4 * g + q) * ldF + cb * 16 + pl);
-          }
-          f32x4 acc[DB];
-          products(x, y, z, acc);
-          if constexpr (kRowPieces<DB>) {
-            gst4(out + (tile * 16 + pl) * ldO + 4 * g, float4{fres[0][0] + acc[0][0], fres[0][1] + acc[0][1],
-                                                              fres[0][2] + acc[0][2], fres[0][3] + acc[0][3]});
-          } else {
-#pragma unroll
-            for (int cb = 0; cb < DB; ++cb)
-#pragma unroll
-              for (int q = 0; q < 4; ++q)
-                gstf(out + (tile * 16 + 4 * g + q) * ldO + cb * 16 + pl, fres[cb][q] + acc[cb][q]);
-          }
-        }
-      }
-    }
-    for (; tile < ntiles; tile += wstride) {
-      const float x = xn, y = yn, z = zn;
-      float fres[DB][4];
-#pragma unroll
-      for (int cb = 0; cb < DB; ++cb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) fres[cb][q] = fn[cb][q];
-      if (tile + wstride < ntiles) load_tile(tile + wstride);
-      f32x4 acc[DB];
-      products(x, y, z, acc);
-      store_out<DB, TOUT, EPI>(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc, ea, eb);
-    }
-  } else {
-    for (int64_t tile = t_first + (tid >> 6); tile < ntiles; tile += wstride) {
-      const float x = xn, y = yn, z = zn;
-      float fres[DB][4];
-#pragma unroll
-      for (int cb = 0; cb < DB; ++cb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) fres[cb][q] = fn[cb][q];
-      if (tile + wstride < ntiles) load_tile(tile + wstride);
-      f32x4 acc[DB];
+    } else {
 #pragma unroll
       for (int cb = 0; cb < DB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
       // K steps in pairs: lane group g uses frequency k = 4t + g, cos then sin.
@@ -1141,8 +1069,70 @@ __device__ __forceinline__ void expand_body(const float* __restrict__ X, int64_t
           }
         }
       }
-      store_out<DB, TOUT, EPI>(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc, ea, eb);
     }
+  };
+  int64_t tile = t_first + (tid >> 6);
+  if constexpr (!TOUT && !DIAG && !EPI) {
+    // Interior tiles of a field of full 16-channel blocks without row
+    // scaling: all 16 points below N and, like the tile each prefetches,
+    // inside this call's range [t_first, t_end). Every load and store there
+    // is unconditional, so no wait for the prefetch also waits for the
+    // previous tile's stores.
+    const int64_t nfull = N / 16 < ntiles ? N / 16 : ntiles;
+    const bool full = kRowPieces<DB> ? (vec && d == 16) : d == DB * 16;
+    if (full && rowscale == nullptr && tile + wstride < nfull) {
+      // the first tile's loads arrive here, so no wait inside the loop
+      // covers them (such a wait would also cover the previous tile's store)
+      asm volatile("" ::"v"(xn), "v"(yn), "v"(zn));
+#pragma unroll
+      for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) asm volatile("" ::"v"(fn[cb][q]));
+      for (; tile + wstride < nfull; tile += wstride) {
+        const float x = xn, y = yn, z = zn;
+        float fres[DB][4];
+#pragma unroll
+        for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) fres[cb][q] = fn[cb][q];
+        const int64_t nt = tile + wstride;
+        const int64_t p = nt * 16 + pl;
+        xn = gldf(X + p * 3); yn = gldf(X + p * 3 + 1); zn = gldf(X + p * 3 + 2);
+        if constexpr (kRowPieces<DB>) {
+          const float4 v = gld4(F + p * ldF + 4 * g);
+          fn[0][0] = v.x; fn[0][1] = v.y; fn[0][2] = v.z; fn[0][3] = v.w;
+        } else {
+#pragma unroll
+          for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) fn[cb][q] = gldf(F + (nt * 16 + 4 * g + q) * ldF + cb * 16 + pl);
+        }
+        f32x4 acc[DB];
+        products(x, y, z, acc);
+        if constexpr (kRowPieces<DB>) {
+          gst4(out + (tile * 16 + pl) * ldO + 4 * g, float4{fres[0][0] + acc[0][0], fres[0][1] + acc[0][1],
+                                                            fres[0][2] + acc[0][2], fres[0][3] + acc[0][3]});
+        } else {
+#pragma unroll
+          for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              gstf(out + (tile * 16 + 4 * g + q) * ldO + cb * 16 + pl, fres[cb][q] + acc[cb][q]);
+        }
+      }
+    }
+  }
+  for (; tile < ntiles; tile += wstride) {
+    const float x = xn, y = yn, z = zn;
+    float fres[DB][4];
+#pragma unroll
+    for (int cb = 0; cb < DB; ++cb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fres[cb][q] = fn[cb][q];
+    if (tile + wstride < ntiles) load_tile(tile + wstride);
+    f32x4 acc[DB];
+    products(x, y, z, acc);
+    store_out<DB, TOUT, EPI>(out, ldO, rowscale, d, N, tile, g, pl, vec, fres, acc, ea, eb);
   }
 }
 
