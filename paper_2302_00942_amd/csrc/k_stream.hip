@@ -422,12 +422,6 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __r
     const int64_t base = ch * kChunk;
     __syncthreads();  // previous chunk's MFMA reads are done (and oms is visible)
     const int64_t pa = base + 2 * pp;
-    // the plan's copy of the chunk's points, written where they are first
-    // used (a store right after the prefetch would wait for its loads)
-    if (Xcopy && kq == 0) {
-      if (pa < N) { gstf(Xcopy + pa * 3, xa); gstf(Xcopy + pa * 3 + 1, ya); gstf(Xcopy + pa * 3 + 2, za); }
-      if (pa + 1 < N) { gstf(Xcopy + pa * 3 + 3, xb); gstf(Xcopy + pa * 3 + 4, yb); gstf(Xcopy + pa * 3 + 5, zb); }
-    }
     if (base + kChunk <= N)  // full chunk (uniform branch): no masking
       features(pa, true, true, std::false_type{});
     else
@@ -451,6 +445,13 @@ __device__ __forceinline__ void bta_body(const float* __restrict__ X, float* __r
         const int p = idx / DC, c = idx - p * DC;
         fs[c * P + p] = fv[q];
       }
+    }
+    // The plan's copy of the chunk's points, written after their features
+    // and the field staging: a store right after the prefetch would wait for
+    // its loads, and one before the features would be waited for with them.
+    if (Xcopy && kq == 0) {
+      if (pa < N) { gstf(Xcopy + pa * 3, xa); gstf(Xcopy + pa * 3 + 1, ya); gstf(Xcopy + pa * 3 + 2, za); }
+      if (pa + 1 < N) { gstf(Xcopy + pa * 3 + 3, xb); gstf(Xcopy + pa * 3 + 4, yb); gstf(Xcopy + pa * 3 + 5, zb); }
     }
     if (ch + 1 < c1) load_chunk(base + kChunk);  // in flight during the products below
     __syncthreads();
