@@ -162,17 +162,23 @@ size_t bta_partial_floats(int m, int d, bool gram) {
 
 // Number of partials (= workgroups) of a split-N pass over N points: at
 // least 16 chunks per partial when the pass carries the Gram (its partials
-// are m(m+1)/2 floats, so fewer of them), 2 otherwise; at most 512 partials.
-// A function of N and the pass kind only, so a cloud gets the same partition
+// are m(m+1)/2 floats, so fewer of them), 2 otherwise; at most 512 partials
+// (two workgroups per CU), or 768 for a field pass of one channel block over
+// at least 8 chunks per partial, whose registers and LDS leave room for three
+// workgroups per CU (all but the FP32 pass at m = 256, whose feature tile
+// alone takes 66 KB of LDS); with fewer chunks the extra partials cost more
+// in the reduction than they gain. A function of N, m, the precision, the
+// pass kind and the channel blocks only, so a cloud gets the same partition
 // alone and in a batch.
 constexpr int kMinChunksPerPartGram = 16;
 constexpr int kMinChunksPerPart = 2;
 int bta_partials(int64_t N, int m, int d, bool gram, int prec) {
-  (void)m; (void)d; (void)prec;
   const int64_t chunks = (N + kChunk - 1) / kChunk;
   const int per = gram ? kMinChunksPerPartGram : kMinChunksPerPart;
   int64_t parts = (chunks + per - 1) / per;
-  if (parts > 512) parts = 512;
+  const bool three_per_cu = !gram && dblocks(d) == 1 && !(prec == 0 && m > 128) && chunks >= 768 * 8;
+  const int cap = three_per_cu ? 768 : 512;
+  if (parts > cap) parts = cap;
   if (parts < 1) parts = 1;
   return (int)parts;
 }
