@@ -737,44 +737,50 @@ __global__ __launch_bounds__(256) void k_reduce_fused_batch(const CloudDesc* __r
 
 // ------------------------------------------------------------------ k_gcore
 // G'[j][c] = sum_i T[j][i] H0[i][c] (device order), FP64, one workgroup per
-// 16 rows x 16 channels with both operands staged in LDS; stored as FP32
+// kGcoreRows rows x 16 channels with both operands staged in LDS; each sum is
+// split over four threads (terms i = 4s + q in part q, the parts added as
+// (p0 + p1) + (p2 + p3)), so its dependent chain is m/4 long. Stored as FP32
 // [j][c] and as a BF16 hi + lo pair, transposed [c][j] (lo at offset 64 m).
+constexpr int kGcoreRows = 4;
 __device__ __forceinline__ void gcore_body(const double* __restrict__ T, const double* __restrict__ H0, int m, int d,
                                            float* __restrict__ G32, __bf16* __restrict__ Gt16, int j0, int c0) {
-  __shared__ double ts[16 * (kMaxM + 1)];
+  __shared__ double ts[kGcoreRows * kMaxM];
   __shared__ double hs[kMaxM * 16];
   const int t = threadIdx.x;
-  // every load of the two operand tiles in flight at once (16 m elements
-  // each, m <= 256: at most 16 per thread), then staged into LDS
-  constexpr int Q = 16 * kMaxM / 256;
-  double tv[Q], hv[Q];
+  // every load of the two operand tiles in flight at once (m <= 256: at most
+  // 4 + 16 per thread), then staged into LDS
+  constexpr int QT = kGcoreRows * kMaxM / 256;
+  constexpr int QH = 16 * kMaxM / 256;
+  double tv[QT], hv[QH];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = t + 256 * q;
-    tv[q] = 0.0;
-    hv[q] = 0.0;
-    if (e < 16 * m) {
-      const int r = e / m, i = e - r * m;
-      tv[q] = gldd(T + (size_t)(j0 + r) * m + i);
-      const int ih = e >> 4, c = e & 15;
-      if (c0 + c < d) hv[q] = gldd(H0 + (size_t)ih * d + c0 + c);
-    }
+  for (int q = 0; q < QT; ++q) {
+    const int e = t + 256 * q;  // the rows j0 .. j0 + kGcoreRows - 1 are contiguous in T
+    tv[q] = e < kGcoreRows * m ? gldd(T + (size_t)j0 * m + e) : 0.0;
   }
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
+  for (int q = 0; q < QH; ++q) {
     const int e = t + 256 * q;
-    if (e < 16 * m) {
-      const int r = e / m, i = e - r * m;
-      ts[r * (kMaxM + 1) + i] = tv[q];
-      hs[e] = hv[q];
-    }
+    const int ih = e >> 4, c = e & 15;
+    hv[q] = (e < 16 * m && c0 + c < d) ? gldd(H0 + (size_t)ih * d + c0 + c) : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < QT; ++q) {
+    const int e = t + 256 * q;
+    if (e < kGcoreRows * m) ts[(e / m) * kMaxM + e % m] = tv[q];
+  }
+#pragma unroll
+  for (int q = 0; q < QH; ++q) {
+    const int e = t + 256 * q;
+    if (e < 16 * m) hs[e] = hv[q];
   }
   __syncthreads();
-  const int r = t >> 4, c = t & 15;
+  const int part = t & 3, c = (t >> 2) & 15, r = t >> 6;
   double s = 0.0;
-  for (int i = 0; i < m; ++i) s += ts[r * (kMaxM + 1) + i] * hs[i * 16 + c];
+  for (int i = part; i < m; i += 4) s += ts[r * kMaxM + i] * hs[i * 16 + c];
+  s += __shfl_xor(s, 1);  // p0 + p1 (and p2 + p3)
+  s += __shfl_xor(s, 2);  // (p0 + p1) + (p2 + p3): addition commutes, so every part holds the same sum
   const int j = j0 + r, ch = c0 + c;
-  if (ch >= d) return;
+  if (part != 0 || ch >= d) return;
   const float g = (float)s;
   const __bf16 hi = (__bf16)g;
   gstf(G32 + (size_t)j * d + ch, g);
@@ -784,13 +790,13 @@ __device__ __forceinline__ void gcore_body(const double* __restrict__ T, const d
 
 __global__ __launch_bounds__(256) void k_gcore(const double* __restrict__ T, const double* __restrict__ H0, int m,
                                                int d, float* __restrict__ G32, __bf16* __restrict__ Gt16) {
-  gcore_body(T, H0, m, d, G32, Gt16, blockIdx.x * 16, blockIdx.y * 16);
+  gcore_body(T, H0, m, d, G32, Gt16, blockIdx.x * kGcoreRows, blockIdx.y * 16);
 }
 
 __global__ __launch_bounds__(256) void k_gcore_batch(const CloudDesc* __restrict__ cl, int m) {
   const CloudDesc& c = cl[blockIdx.z];
   if ((int)blockIdx.y * 16 >= c.d) return;
-  gcore_body(c.T64, c.H0, m, c.d, c.G32, c.Gt16, blockIdx.x * 16, blockIdx.y * 16);
+  gcore_body(c.T64, c.H0, m, c.d, c.G32, c.Gt16, blockIdx.x * kGcoreRows, blockIdx.y * 16);
 }
 
 // ------------------------------------------------------------------ k_expand
@@ -1337,7 +1343,7 @@ size_t reduce_scratch_doubles(int m) { return (size_t)kReduceGroups * reduce_ele
 
 hipError_t launch_gcore(rfd_plan_s* p, int d, hipStream_t st) {
   const int M = p->dev_m;
-  dim3 grid((unsigned)(M / 16), (unsigned)((d + 15) / 16));
+  dim3 grid((unsigned)(M / kGcoreRows), (unsigned)((d + 15) / 16));
   ProfileScope prof(kKGcore, st);
   hipLaunchKernelGGL(k_gcore, grid, dim3(256), 0, st, p->dev.T64, p->dev.H0, M, d, p->dev.G32, p->dev.Gt16);
   return hipGetLastError();
@@ -1574,7 +1580,7 @@ int fused_reduce_max_parts() { return kFusedReduceMaxParts; }
 
 hipError_t launch_gcore_batch(int M, int dmax, const CloudDesc* dcl, int ncl, hipStream_t st) {
   ProfileScope prof(kKGcore, st);
-  hipLaunchKernelGGL(k_gcore_batch, dim3((unsigned)(M / 16), (unsigned)((dmax + 15) / 16), (unsigned)ncl), dim3(256),
+  hipLaunchKernelGGL(k_gcore_batch, dim3((unsigned)(M / kGcoreRows), (unsigned)((dmax + 15) / 16), (unsigned)ncl), dim3(256),
                      0, st, dcl, M);
   return hipGetLastError();
 }
